@@ -1,0 +1,193 @@
+"""Named synthetic workloads (inputs only).
+
+Each workload fixes a model grid, the sponge width, dt, nt, a Ricker source
+and an acquisition geometry.  Positions are produced in metres, (x, y, z)
+order, from integer node indices: x = ox + i * dx (§2.2.2: coordinates in
+metres, one (x, y, z) triple per source / receiver).
+
+Workloads
+---------
+c1        64^3 constant velocity 2000 m/s, 8-cell sponge, 200 steps, 15 Hz,
+          64 receivers on a line at depth index 4 (plain forward, constant
+          density).
+c1_long   c1 with 400 steps (the direct wave peak reaches the receivers
+          after 0.2 s).
+c2        512^3 layered model with +/-5 % smooth perturbation, Gardner
+          density, 32-cell sponge, dt from Courant 0.4 at 4500 m/s, 2000
+          steps, 10 Hz, 256 x 256 receiver grid (plain forward, variable
+          density).
+c2_small  the same generator on a small ragged grid (93 x 77 x 61, 16-cell
+          sponge, 300 steps) for element-wise parity.
+c4        200 x 200 x 160 smooth layered background + six +/-10 % blobs,
+          20-cell sponge, 1200 steps, 8 shots, 2500 receivers (FWI gradient).
+c4_fd     32^3 layered model, 8-cell sponge, 300 steps, one shot, 64
+          receivers, plus a smooth 1 % velocity perturbation direction for
+          finite-difference gradient checks.
+example   the paper's illustrative 25^3 setup (§3): h = 10 m, border 25,
+          500 steps, dt = 1 ms, 10 Hz Ricker with amplitude 1e5, Gaussian
+          velocity blob.
+"""
+
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+from typing import Callable, Dict, List, Optional
+
+import numpy as np
+
+from .models import layered_model, gardner_density, blob_anomalies, smooth_noise
+from .wavelet import ricker
+
+
+@dataclass
+class Workload:
+    name: str
+    nx: int
+    ny: int
+    nz: int
+    dx: float
+    dy: float
+    dz: float
+    ox: float
+    oy: float
+    oz: float
+    border: int
+    dt: float
+    nt: int
+    vel: np.ndarray                      # float32 [nz][ny][nx]
+    rho: Optional[np.ndarray]            # float32 [nz][ny][nx] or None
+    wavelet: np.ndarray                  # float32 [nt]
+    sources: np.ndarray                  # float64 [nshot][3] metres (x, y, z)
+    receivers: np.ndarray                # float64 [nrec][3] metres (x, y, z)
+    extra: Dict[str, np.ndarray] = field(default_factory=dict)
+
+    @property
+    def padded_shape(self):
+        """(Nz, Ny, Nx) of the grid with the sponge added on every face."""
+        b = 2 * self.border
+        return (self.nz + b, self.ny + b, self.nx + b)
+
+    @property
+    def padded_points(self) -> int:
+        nz, ny, nx = self.padded_shape
+        return nz * ny * nx
+
+    def grid_kwargs(self) -> dict:
+        return dict(nx=self.nx, ny=self.ny, nz=self.nz, dx=self.dx, dy=self.dy,
+                    dz=self.dz, ox=self.ox, oy=self.oy, oz=self.oz,
+                    border=self.border, dt=self.dt, nt=self.nt)
+
+    def nodes_to_metres(self, nodes) -> np.ndarray:
+        nodes = np.asarray(nodes, dtype=np.float64).reshape(-1, 3)
+        o = np.array([self.ox, self.oy, self.oz])
+        h = np.array([self.dx, self.dy, self.dz])
+        return o + nodes * h
+
+
+def _metres(nodes, h, o=(0.0, 0.0, 0.0)) -> np.ndarray:
+    nodes = np.asarray(nodes, dtype=np.float64).reshape(-1, 3)
+    return np.asarray(o, dtype=np.float64) + nodes * np.asarray(h, dtype=np.float64)
+
+
+def _surface_grid(i0, di, ni, j0, dj, nj, z) -> np.ndarray:
+    ii, jj = np.meshgrid(i0 + di * np.arange(ni), j0 + dj * np.arange(nj), indexing="xy")
+    return np.stack([ii.ravel(), jj.ravel(), np.full(ii.size, z)], axis=1)
+
+
+def _c1(nt: int = 200) -> Workload:
+    n, h = 64, 10.0
+    vel = np.full((n, n, n), 2000.0, dtype=np.float32)
+    rec_nodes = np.stack([np.arange(64), np.full(64, 32), np.full(64, 4)], axis=1)
+    return Workload("c1" if nt == 200 else f"c1_nt{nt}", n, n, n, h, h, h, 0.0, 0.0, 0.0,
+                    8, 1.0e-3, nt, vel, None,
+                    ricker(nt, 1.0e-3, 15.0, 1.0 / 15.0),
+                    _metres([[32, 32, 32]], (h, h, h)), _metres(rec_nodes, (h, h, h)))
+
+
+def _c2(nx=512, ny=512, nz=512, border=32, nt=2000, seed=2502, name="c2",
+        src=None, rec=None) -> Workload:
+    h = 10.0
+    vel = layered_model(seed, (nx, ny, nz), 0.05)
+    rho = gardner_density(vel)
+    dt = 0.4 * h / 4500.0
+    if src is None:
+        src = [[nx // 2, ny // 2, 8]]
+    if rec is None:
+        rec = _surface_grid(1, 2, nx // 2, 1, 2, ny // 2, 4)
+    return Workload(name, nx, ny, nz, h, h, h, 0.0, 0.0, 0.0, border, dt, nt, vel, rho,
+                    ricker(nt, dt, 10.0, 0.1), _metres(src, (h, h, h)), _metres(rec, (h, h, h)))
+
+
+def _c2_small() -> Workload:
+    return _c2(nx=93, ny=77, nz=61, border=16, nt=300, name="c2_small",
+               src=[[46, 38, 8]])
+
+
+def _c4(variant: str = "true") -> Workload:
+    nx, ny, nz, h = 200, 200, 160, 10.0
+    bg = layered_model(4, (nx, ny, nz), 0.0)
+    true = blob_anomalies(bg, seed=40, n_blobs=6, amp=0.10)
+    dt = 0.4 * h / float(np.max(true))
+    nt = 1200
+    shots = [[x, y, 4] for y in (67, 133) for x in (25, 75, 125, 175)]
+    rec = _surface_grid(2, 4, 50, 2, 4, 50, 4)
+    vel = true if variant == "true" else bg
+    w = Workload("c4" if variant == "true" else "c4_start", nx, ny, nz, h, h, h, 0.0, 0.0, 0.0,
+                 20, dt, nt, vel, None, ricker(nt, dt, 10.0, 0.1),
+                 _metres(shots, (h, h, h)), _metres(rec, (h, h, h)))
+    w.extra["v_true"] = true
+    w.extra["v_start"] = bg
+    return w
+
+
+def _c4_fd(variable_density: bool = False, nt: int = 300) -> Workload:
+    n, h = 32, 10.0
+    vel = layered_model(44, n, 0.05)
+    rho = gardner_density(vel) if variable_density else None
+    dt = 0.4 * h / float(np.max(vel))
+    rec = _surface_grid(2, 4, 8, 2, 4, 8, 4)
+    w = Workload("c4_fd_vd" if variable_density else "c4_fd", n, n, n, h, h, h, 0.0, 0.0, 0.0,
+                 8, dt, nt, vel, rho, ricker(nt, dt, 15.0),
+                 _metres([[16, 16, 4]], (h, h, h)), _metres(rec, (h, h, h)))
+    dv = smooth_noise(n, 4401, sigma=3.0, max_abs=1.0)
+    w.extra["dv"] = (0.01 * dv * vel).astype(np.float32)
+    return w
+
+
+def _example() -> Workload:
+    """Paper §3: 25^3 cells of 10 m, border 25, 500 steps of 1 ms, 10 Hz Ricker,
+    amplitude 1e5; sources every 100 m from 20 m to 220 m, receivers every
+    50 m from 10 m to 210 m.  The printed velocity formula is ambiguous; it is
+    read as a 2500 m/s background with a +1000 m/s Gaussian blob of 5 cells."""
+    n, h = 25, 10.0
+    i = np.arange(n, dtype=np.float64)
+    r2 = ((i[:, None, None] - n / 2) ** 2 + (i[None, :, None] - n / 2) ** 2
+          + (i[None, None, :] - n / 2) ** 2)
+    vel = (2500.0 + 1.0e3 * np.exp(-0.5 * r2 / 5.0 ** 2)).astype(np.float32)
+    s = np.array([20.0, 120.0, 220.0])
+    src = np.array([[x, y, z] for z in s for y in s for x in s])
+    r = np.arange(10.0, 211.0, 50.0)
+    rec = np.array([[x, y, 10.0] for y in r for x in r])
+    return Workload("example", n, n, n, h, h, h, 0.0, 0.0, 0.0, 25, 1.0e-3, 500, vel, None,
+                    ricker(500, 1.0e-3, 10.0, amplitude=1.0e5), src, rec)
+
+
+WORKLOADS: Dict[str, Callable[[], Workload]] = {
+    "c1": _c1,
+    "c1_long": lambda: _c1(400),
+    "c2": _c2,
+    "c2_small": _c2_small,
+    "c4": _c4,
+    "c4_start": lambda: _c4("start"),
+    "c4_fd": _c4_fd,
+    "c4_fd_vd": lambda: _c4_fd(True),
+    "example": _example,
+}
+
+
+def workload(name: str) -> Workload:
+    """Build a named workload (deterministic; seeds are fixed per workload)."""
+    try:
+        return WORKLOADS[name]()
+    except KeyError:
+        raise KeyError(f"unknown workload {name!r}; known: {sorted(WORKLOADS)}") from None
