@@ -1,0 +1,206 @@
+/*
+ * wfd.h — C ABI of the MI355X acoustic finite-difference library.
+ *
+ * The library time-steps the 3-D acoustic wave equation (arXiv 2502.12350,
+ * §2.1, Eq. 1): constant density p_tt = c^2 lap(p) + S, or variable density
+ * q_tt = c^2 (lap(q) - m^2 q) + S / sqrt(rho) with q = p / sqrt(rho) and
+ * m^2 = lap(sqrt(rho)) / sqrt(rho), S = f(t) delta(x - x_S).  The scheme is
+ * second order in time (leapfrog) and eighth order in space (§2.1), with a
+ * damping sponge of `border` cells (§2.1 absorbing boundaries; §2.2.1
+ * parameter table).  It serves forward modeling (Alg. 1) and the per-shot
+ * body of the FWI gradient (Alg. 3): forward sweep with receiver recording
+ * and wavefield saving, misfit, backward (adjoint) sweep with the
+ * cross-correlation imaging condition, and the chain rule to the velocity
+ * gradient.  Forward-wavefield management follows the paper's two in-memory
+ * options (§2.1): keep every state, or optimal checkpointing with
+ * recomputation.
+ *
+ * Conventions (§2.2.2, data format)
+ *   - volumes are C-order [z][y][x], x fastest, FP32;
+ *   - positions are metres, (x, y, z) order, FP64, host memory; a position
+ *     maps to the nearest node, i = floor((x - o) / h + 1/2); a position
+ *     outside the model is an error (WFD_E_RANGE);
+ *   - seismograms are trace-major [nrec][nt] FP32: sample n of a trace is
+ *     the recorded pressure at time (n + 1) dt, wavelet sample n is the
+ *     source value at time n dt;
+ *   - the sponge is added outside the model on all six faces; the padded
+ *     grid is Nd = nd + 2 border, with the model's edge values replicated
+ *     into the sponge.
+ *
+ * Ownership and ordering
+ *   - the caller owns every device buffer (model buffer, workspace, inputs,
+ *     outputs); the library owns only the opaque context.  All device
+ *     pointers must belong to the context's device.  The library never
+ *     calls hipMalloc.
+ *   - every call that launches work is stream-ordered on the context's
+ *     stream and returns without synchronising, except wfd_set_model (it
+ *     waits for its CFL reduction) and wfd_kernel_stats.
+ *   - outputs named "accumulated" are added to (+=), so several shots sum,
+ *     as the paper's all-reduce over shots does (Alg. 3).
+ *
+ * Errors: every call returns a wfd_status; nothing aborts or throws across
+ * the ABI.  wfd_last_error() returns a thread-local description of the last
+ * failure on the calling thread.
+ */
+#ifndef WFD_H
+#define WFD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  WFD_OK = 0,
+  WFD_E_ARG = -1,    /* bad size, null required pointer, inconsistent arguments   */
+  WFD_E_CFL = -2,    /* dt violates the stability bound (ValidConditions, §2.2)    */
+  WFD_E_RANGE = -3,  /* a source / receiver position lies outside the model        */
+  WFD_E_NOMEM = -4,  /* caller buffer smaller than the size the library asked for  */
+  WFD_E_HIP = -5,    /* a HIP runtime call failed                                   */
+  WFD_E_STATE = -6   /* call out of order (e.g. forward before set_model)          */
+} wfd_status;
+
+/* Model grid, sponge and time axis (§2.2.1: nx ny nz, dx dy dz, ox oy oz,
+ * border, dt, ns).  nt is the number of time steps = samples per trace. */
+typedef struct {
+  int32_t nx, ny, nz; /* model points per axis (>= 1)                          */
+  double dx, dy, dz;  /* spacing, m (> 0)                                      */
+  double ox, oy, oz;  /* position of model node (0,0,0), m                      */
+  int32_t border;     /* sponge cells on every face (>= 0; 0 = no sponge)      */
+  double dt;          /* time step, s (> 0)                                    */
+  int32_t nt;         /* number of time steps (>= 1)                           */
+} wfd_grid;
+
+/* Forward-wavefield management for the gradient (§2.1 "three options"; the
+ * disk option is not provided). */
+enum {
+  WFD_CKPT_FULL = 0,    /* keep w^1 .. w^nt in the workspace                   */
+  WFD_CKPT_REVOLVE = 1  /* keep n_snapshots leapfrog pairs, recompute the rest */
+};
+typedef struct {
+  int32_t mode;         /* WFD_CKPT_FULL or WFD_CKPT_REVOLVE                    */
+  int32_t n_snapshots;  /* REVOLVE: pairs kept (>= 1); 0 = derive from
+                           mem_fraction of the device's free memory            */
+  double mem_fraction;  /* (0, 1]; like the paper's check_mem (default 0.8)    */
+} wfd_ckpt;
+
+typedef struct wfd_ctx wfd_ctx;
+
+/* Create a context on HIP device `device` that launches on `hip_stream`
+ * (a hipStream_t; NULL = the legacy default stream). */
+wfd_status wfd_create(wfd_ctx **ctx, int32_t device, void *hip_stream);
+
+/* Change the stream later calls launch on. */
+wfd_status wfd_set_stream(wfd_ctx *ctx, void *hip_stream);
+
+/* Release the context (not the caller's buffers).  NULL is accepted. */
+wfd_status wfd_destroy(wfd_ctx *ctx);
+
+/* Bytes of the caller-owned device buffer that holds the precomputed model
+ * (coefficient volumes and sponge tables) for this grid.  Host only. */
+wfd_status wfd_model_bytes(const wfd_grid *grid, int32_t variable_density, size_t *bytes);
+
+/* Prepare a model (Eq. 1 coefficients, ValidConditions):
+ *   k = dt^2 v^2 on the padded grid (edge-replicated v),
+ *   VD only: m^2 = L8(sqrt(rho)) / sqrt(rho) in FP64 (sqrt(rho) replicated
+ *   past the padded grid as well), sqrt(rho) kept for source/receiver scales,
+ *   1-D sponge tables g[i] = exp(-(0.4 delta_i / border)^2),
+ * and check dt^2 vmax^2 (Lambda_max + max(m^2, 0)) < 4 with Lambda_max =
+ * (2048/315) sum_d 1/h_d^2 (returns WFD_E_CFL otherwise).
+ *   vel_dev           [nz][ny][nx] FP32 velocity, m/s (> 0), device;
+ *   rho_dev_or_null   [nz][ny][nx] FP32 density (> 0) or NULL = constant density;
+ *   model_dev, bytes  caller buffer of at least wfd_model_bytes(); it must stay
+ *                     allocated and unmodified while the context uses the model.
+ * vel and rho are read during this call only.  Waits on the stream once. */
+wfd_status wfd_set_model(wfd_ctx *ctx, const wfd_grid *grid, const float *vel_dev,
+                         const float *rho_dev_or_null, void *model_dev, size_t model_bytes);
+
+/* Workspace bytes for one shot with nrec receivers: ckpt_or_null == NULL for
+ * wfd_forward, else for wfd_gradient with that checkpoint policy. */
+wfd_status wfd_workspace_bytes(const wfd_ctx *ctx, int32_t nrec, const wfd_ckpt *ckpt_or_null,
+                               size_t *bytes);
+
+/* Forward modeling of one shot (Alg. 1 body; ModelingStep + ReadReceiver).
+ *   wavelet_dev   [nt] FP32 source signature f(n dt), device;
+ *   src_xyz       host [3] source position, m;
+ *   nrec, rec_xyz host [nrec][3] receiver positions, m (nrec >= 0);
+ *   seis_dev      [nrec][nt] FP32 output pressure traces, device (may be NULL
+ *                 when nrec == 0);
+ *   final_dev_or_null  [2][Nz][Ny][Nx] FP32 output: w^nt then w^(nt-1) on the
+ *                 padded grid (q for variable density), device, or NULL;
+ *   work_dev, work_bytes  workspace of at least wfd_workspace_bytes(NULL). */
+wfd_status wfd_forward(wfd_ctx *ctx, const float *wavelet_dev, const double src_xyz[3],
+                       int32_t nrec, const double *rec_xyz, float *seis_dev,
+                       float *final_dev_or_null, void *work_dev, size_t work_bytes);
+
+/* Misfit and velocity gradient of one shot (Alg. 3 body for one shot):
+ * forward sweep with recording and wavefield saving, res = d - d_obs,
+ * J = 1/2 sum res^2, discrete adjoint sweep (exact transpose of the forward
+ * recursion) with the zero-lag cross-correlation imaging condition, then
+ * dJ/dv = 2 g / v with the sponge cells folded into the model-edge cells
+ * they replicate.
+ *   dobs_dev          [nrec][nt] FP32 observed traces, device;
+ *   ckpt              forward-wavefield policy (non-NULL);
+ *   seis_dev_or_null  [nrec][nt] FP32 output synthetic traces, or NULL;
+ *   misfit_dev        device FP64 scalar, accumulated (+= J);
+ *   grad_dev          [nz][ny][nx] FP32 device, accumulated (+= dJ/dv);
+ *   illum_dev_or_null [nz][ny][nx] FP32 device, accumulated (+= sum_{n=1..nt}
+ *                     (w^n)^2 on the model grid), or NULL. */
+wfd_status wfd_gradient(wfd_ctx *ctx, const float *wavelet_dev, const double src_xyz[3],
+                        int32_t nrec, const double *rec_xyz, const float *dobs_dev,
+                        const wfd_ckpt *ckpt, float *seis_dev_or_null, double *misfit_dev,
+                        float *grad_dev, float *illum_dev_or_null, void *work_dev,
+                        size_t work_bytes);
+
+/* ZeroesNearSurface (Alg. 3; zeroes_nplanes_gradient in §3): set the top
+ * `zero_top_planes` z-planes of grad_dev [nz][ny][nx] to zero. */
+wfd_status wfd_gradient_finish(wfd_ctx *ctx, float *grad_dev, int32_t zero_top_planes);
+
+/* ---- host-only helpers (no GPU needed) --------------------------------- */
+
+/* Padded-grid node (ix, iy, iz) of a position in metres (rule above). */
+wfd_status wfd_map_position(const wfd_grid *grid, const double xyz[3], int32_t ijk[3]);
+
+/* Stability ratio dt^2 vmax^2 (Lambda_max + max(m2max, 0)) / 4; the scheme is
+ * stable when the ratio is below 1 (ValidConditions, §2.2). */
+wfd_status wfd_cfl_ratio(const wfd_grid *grid, double vmax, double m2max, double *ratio);
+
+/* Checkpoint schedule for reversing nt steps with n_snapshots stored pairs
+ * (plus the zero initial state, which needs no storage).  Actions are
+ * written as int32 triples (op, a, b):
+ *   op 0 ADVANCE  a = from state, b = to state    (b - a forward steps)
+ *   op 1 STORE    a = state,      b = slot
+ *   op 2 VISIT    a = state (the backward sweep consumes w^a)
+ *   op 3 FREE     a = state,      b = slot
+ * Visits run a = nt down to 1.  The forward-step count is minimal
+ * (Griewank & Walther binomial bound).  actions may be NULL to query sizes. */
+wfd_status wfd_checkpoint_plan(int32_t nt, int32_t n_snapshots, int32_t *actions,
+                               int64_t capacity, int64_t *n_actions, int64_t *n_forward_steps);
+
+/* ---- measurement ---------------------------------------------------------- */
+
+enum {
+  WFD_K_FORWARD = 0,   /* forward step (fd_step, incl. source + receivers)     */
+  WFD_K_ADJOINT = 1,   /* adjoint step fused with imaging                       */
+  WFD_K_OTHER = 2,     /* setup, misfit, copies, gradient finish                */
+  WFD_K_COUNT = 3
+};
+
+/* Enable (1) or disable (0) per-launch HIP-event timing on the context's
+ * stream; enabling clears the counters. */
+wfd_status wfd_set_profiling(wfd_ctx *ctx, int32_t enable);
+
+/* Launch count and summed kernel time (ms) of one kernel class since
+ * profiling was enabled.  Waits for the stream. */
+wfd_status wfd_kernel_stats(wfd_ctx *ctx, int32_t kernel_class, int64_t *launches, double *total_ms);
+
+/* Thread-local text of the last error ("" if none). */
+const char *wfd_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* WFD_H */

@@ -1,0 +1,90 @@
+"""ctypes declarations of include/wfd.h (argument marshalling only).
+
+Loading fails loudly when the in-tree library has not been built: there is
+no CPU fallback anywhere in the package.
+"""
+
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libwfd.so")
+
+WFD_OK = 0
+STATUS_NAMES = {0: "WFD_OK", -1: "WFD_E_ARG", -2: "WFD_E_CFL", -3: "WFD_E_RANGE",
+                -4: "WFD_E_NOMEM", -5: "WFD_E_HIP", -6: "WFD_E_STATE"}
+CKPT_FULL = 0
+CKPT_REVOLVE = 1
+K_FORWARD, K_ADJOINT, K_OTHER = 0, 1, 2
+
+
+class wfd_grid(C.Structure):
+    _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32),
+                ("dx", C.c_double), ("dy", C.c_double), ("dz", C.c_double),
+                ("ox", C.c_double), ("oy", C.c_double), ("oz", C.c_double),
+                ("border", C.c_int32), ("dt", C.c_double), ("nt", C.c_int32)]
+
+
+class wfd_ckpt(C.Structure):
+    _fields_ = [("mode", C.c_int32), ("n_snapshots", C.c_int32), ("mem_fraction", C.c_double)]
+
+
+class WfdError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        self.status = status
+        self.name = STATUS_NAMES.get(status, str(status))
+        super().__init__(f"{self.name}: {message}")
+
+
+_P = C.c_void_p
+_D3 = C.POINTER(C.c_double)
+_SIGS = {
+    "wfd_create": (C.c_int, [C.POINTER(C.c_void_p), C.c_int32, _P]),
+    "wfd_set_stream": (C.c_int, [_P, _P]),
+    "wfd_destroy": (C.c_int, [_P]),
+    "wfd_model_bytes": (C.c_int, [C.POINTER(wfd_grid), C.c_int32, C.POINTER(C.c_size_t)]),
+    "wfd_set_model": (C.c_int, [_P, C.POINTER(wfd_grid), _P, _P, _P, C.c_size_t]),
+    "wfd_workspace_bytes": (C.c_int, [_P, C.c_int32, C.POINTER(wfd_ckpt), C.POINTER(C.c_size_t)]),
+    "wfd_forward": (C.c_int, [_P, _P, _D3, C.c_int32, _D3, _P, _P, _P, C.c_size_t]),
+    "wfd_gradient": (C.c_int, [_P, _P, _D3, C.c_int32, _D3, _P, C.POINTER(wfd_ckpt), _P, _P,
+                               _P, _P, _P, C.c_size_t]),
+    "wfd_gradient_finish": (C.c_int, [_P, _P, C.c_int32]),
+    "wfd_map_position": (C.c_int, [C.POINTER(wfd_grid), _D3, C.POINTER(C.c_int32)]),
+    "wfd_cfl_ratio": (C.c_int, [C.POINTER(wfd_grid), C.c_double, C.c_double, _D3]),
+    "wfd_checkpoint_plan": (C.c_int, [C.c_int32, C.c_int32, C.POINTER(C.c_int32), C.c_int64,
+                                      C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
+    "wfd_set_profiling": (C.c_int, [_P, C.c_int32]),
+    "wfd_kernel_stats": (C.c_int, [_P, C.c_int32, C.POINTER(C.c_int64), C.POINTER(C.c_double)]),
+    "wfd_last_error": (C.c_char_p, []),
+}
+
+_lib = None
+
+
+def lib() -> C.CDLL:
+    """The loaded library (raises if it was never built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(
+                f"{LIB_PATH} is missing: build the HIP library first "
+                "(python -m paper_2502_12350_amd.build or __graft_entry__.build())")
+        L = C.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def exported_symbols():
+    return list(_SIGS)
+
+
+def check(status: int) -> None:
+    if status != WFD_OK:
+        msg = lib().wfd_last_error()
+        raise WfdError(status, msg.decode() if msg else "")

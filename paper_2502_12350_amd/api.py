@@ -1,0 +1,276 @@
+"""Python face of the C ABI: torch supplies device memory and the stream.
+
+Every numerical step runs in the HIP library; this module only checks
+dtypes / shapes / devices, allocates buffers through torch and passes raw
+pointers.
+"""
+
+from __future__ import annotations
+
+import ctypes as C
+from dataclasses import dataclass
+from typing import Optional, Sequence, Tuple
+
+import numpy as np
+
+from . import _lib
+from ._lib import check, wfd_ckpt, wfd_grid
+
+
+@dataclass
+class GridSpec:
+    """Model grid, sponge and time axis (mirrors wfd_grid)."""
+    nx: int
+    ny: int
+    nz: int
+    dx: float
+    dy: float
+    dz: float
+    ox: float = 0.0
+    oy: float = 0.0
+    oz: float = 0.0
+    border: int = 0
+    dt: float = 1.0e-3
+    nt: int = 1
+
+    def c(self) -> wfd_grid:
+        return wfd_grid(int(self.nx), int(self.ny), int(self.nz), float(self.dx), float(self.dy),
+                        float(self.dz), float(self.ox), float(self.oy), float(self.oz),
+                        int(self.border), float(self.dt), int(self.nt))
+
+    @property
+    def padded_shape(self) -> Tuple[int, int, int]:
+        b = 2 * self.border
+        return (self.nz + b, self.ny + b, self.nx + b)
+
+
+def _grid(g) -> GridSpec:
+    if isinstance(g, GridSpec):
+        return g
+    if isinstance(g, dict):
+        return GridSpec(**g)
+    return GridSpec(**{k: getattr(g, k) for k in GridSpec.__dataclass_fields__})
+
+
+def _xyz(a) -> np.ndarray:
+    return np.ascontiguousarray(np.asarray(a, dtype=np.float64).reshape(-1, 3))
+
+
+def _dptr(a: np.ndarray):
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def _ptr(t) -> Optional[int]:
+    return None if t is None else t.data_ptr()
+
+
+def _ckpt(ckpt) -> wfd_ckpt:
+    """'full' | ('revolve', n_snapshots) | ('revolve', 0, mem_fraction) | wfd_ckpt."""
+    if isinstance(ckpt, wfd_ckpt):
+        return ckpt
+    if ckpt in (None, "full"):
+        return wfd_ckpt(_lib.CKPT_FULL, 0, 0.8)
+    if isinstance(ckpt, tuple) and ckpt[0] == "revolve":
+        n = int(ckpt[1]) if len(ckpt) > 1 else 0
+        frac = float(ckpt[2]) if len(ckpt) > 2 else 0.8
+        return wfd_ckpt(_lib.CKPT_REVOLVE, n, frac)
+    raise ValueError(f"bad checkpoint policy {ckpt!r}")
+
+
+# ---------------------------------------------------------------------------
+# host-only helpers (no GPU needed)
+# ---------------------------------------------------------------------------
+def map_position(grid, xyz) -> Tuple[int, int, int]:
+    """Padded-grid node (ix, iy, iz) of a position in metres."""
+    g = _grid(grid).c()
+    p = _xyz(xyz)[0]
+    out = (C.c_int32 * 3)()
+    check(_lib.lib().wfd_map_position(C.byref(g), _dptr(p), out))
+    return (out[0], out[1], out[2])
+
+
+def cfl_ratio(grid, vmax: float, m2max: float = 0.0) -> float:
+    g = _grid(grid).c()
+    r = C.c_double()
+    check(_lib.lib().wfd_cfl_ratio(C.byref(g), float(vmax), float(m2max), C.byref(r)))
+    return r.value
+
+
+def checkpoint_plan(nt: int, n_snapshots: int):
+    """(actions [n][3] int32, forward step count) of the library's schedule."""
+    L = _lib.lib()
+    na, ns = C.c_int64(), C.c_int64()
+    check(L.wfd_checkpoint_plan(int(nt), int(n_snapshots), None, 0, C.byref(na), C.byref(ns)))
+    buf = np.zeros((na.value, 3), dtype=np.int32)
+    check(L.wfd_checkpoint_plan(int(nt), int(n_snapshots),
+                                buf.ctypes.data_as(C.POINTER(C.c_int32)), na.value,
+                                C.byref(na), C.byref(ns)))
+    return buf, ns.value
+
+
+def model_bytes(grid, variable_density: bool) -> int:
+    g = _grid(grid).c()
+    n = C.c_size_t()
+    check(_lib.lib().wfd_model_bytes(C.byref(g), int(bool(variable_density)), C.byref(n)))
+    return n.value
+
+
+# ---------------------------------------------------------------------------
+# device API
+# ---------------------------------------------------------------------------
+class Propagator:
+    """One context on one GPU; all work goes to torch's current stream."""
+
+    def __init__(self, device: int = 0):
+        import torch
+        self.torch = torch
+        self.device = torch.device("cuda", device)
+        self.L = _lib.lib()
+        self._ctx = C.c_void_p()
+        check(self.L.wfd_create(C.byref(self._ctx), int(device), self._stream()))
+        self.grid: Optional[GridSpec] = None
+        self._model = None
+        self._work = None
+
+    def _stream(self):
+        return C.c_void_p(self.torch.cuda.current_stream(self.device).cuda_stream)
+
+    def _sync_stream(self):
+        check(self.L.wfd_set_stream(self._ctx, self._stream()))
+
+    def close(self):
+        if self._ctx:
+            check(self.L.wfd_destroy(self._ctx))
+            self._ctx = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _dev(self, t, name, shape=None, dtype=None):
+        torch = self.torch
+        if t is None:
+            raise ValueError(f"{name} is required")
+        if not (t.is_cuda and t.device == self.device):
+            raise ValueError(f"{name} must live on {self.device}")
+        if dtype is not None and t.dtype != dtype:
+            raise ValueError(f"{name} must be {dtype}, got {t.dtype}")
+        if shape is not None and tuple(t.shape) != tuple(shape):
+            raise ValueError(f"{name} must have shape {tuple(shape)}, got {tuple(t.shape)}")
+        if not t.is_contiguous():
+            raise ValueError(f"{name} must be contiguous")
+        return t
+
+    def _buffer(self, nbytes: int):
+        torch = self.torch
+        buf = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        off = (-buf.data_ptr()) % 256
+        return buf, buf.data_ptr() + off
+
+    def set_model(self, grid, vel, rho=None):
+        """Precompute coefficients and check stability (waits on the stream once)."""
+        torch = self.torch
+        g = _grid(grid)
+        shape = (g.nz, g.ny, g.nx)
+        vel = self._dev(vel, "vel", shape, torch.float32)
+        if rho is not None:
+            rho = self._dev(rho, "rho", shape, torch.float32)
+        nbytes = model_bytes(g, rho is not None)
+        buf, ptr = self._buffer(nbytes)
+        self._sync_stream()
+        gc = g.c()
+        check(self.L.wfd_set_model(self._ctx, C.byref(gc), _ptr(vel), _ptr(rho), ptr, nbytes))
+        self.grid = g
+        self._model = buf
+        return self
+
+    def workspace_bytes(self, nrec: int, ckpt=None) -> int:
+        n = C.c_size_t()
+        ck = None if ckpt is None else _ckpt(ckpt)
+        check(self.L.wfd_workspace_bytes(self._ctx, int(nrec), None if ck is None else C.byref(ck),
+                                         C.byref(n)))
+        return n.value
+
+    def _workspace(self, nbytes: int):
+        if self._work is None or self._work[2] < nbytes:
+            self._work = None
+            buf, ptr = self._buffer(nbytes)
+            self._work = (buf, ptr, nbytes)
+        return self._work[1], self._work[2]
+
+    def release_workspace(self):
+        self._work = None
+
+    def forward(self, wavelet, src_xyz, rec_xyz, *, final: bool = False, seis=None):
+        """Seismograms [nrec][nt] (and, if final, [2][Nz][Ny][Nx] = w^nt, w^(nt-1))."""
+        torch = self.torch
+        g = self.grid
+        if g is None:
+            raise RuntimeError("set_model first")
+        wavelet = self._dev(wavelet, "wavelet", (g.nt,), torch.float32)
+        src = _xyz(src_xyz)
+        rec = _xyz(rec_xyz) if rec_xyz is not None and len(rec_xyz) else np.zeros((0, 3))
+        nrec = rec.shape[0]
+        if seis is None:
+            seis = torch.empty((nrec, g.nt), dtype=torch.float32, device=self.device)
+        else:
+            self._dev(seis, "seis", (nrec, g.nt), torch.float32)
+        fin = (torch.empty((2,) + g.padded_shape, dtype=torch.float32, device=self.device)
+               if final else None)
+        wptr, wbytes = self._workspace(self.workspace_bytes(nrec))
+        self._sync_stream()
+        check(self.L.wfd_forward(self._ctx, _ptr(wavelet), _dptr(src), nrec,
+                                 _dptr(rec) if nrec else None, _ptr(seis) if nrec else None,
+                                 _ptr(fin), wptr, wbytes))
+        return (seis, fin) if final else seis
+
+    def gradient(self, wavelet, src_xyz, rec_xyz, dobs, *, ckpt="full", grad=None, misfit=None,
+                 illum=None, seis: bool = False):
+        """Accumulate one shot's misfit and dJ/dv; returns (misfit, grad[, seis])."""
+        torch = self.torch
+        g = self.grid
+        if g is None:
+            raise RuntimeError("set_model first")
+        wavelet = self._dev(wavelet, "wavelet", (g.nt,), torch.float32)
+        src = _xyz(src_xyz)
+        rec = _xyz(rec_xyz)
+        nrec = rec.shape[0]
+        dobs = self._dev(dobs, "dobs", (nrec, g.nt), torch.float32)
+        if grad is None:
+            grad = torch.zeros((g.nz, g.ny, g.nx), dtype=torch.float32, device=self.device)
+        else:
+            self._dev(grad, "grad", (g.nz, g.ny, g.nx), torch.float32)
+        if misfit is None:
+            misfit = torch.zeros((), dtype=torch.float64, device=self.device)
+        else:
+            self._dev(misfit, "misfit", (), torch.float64)
+        if illum is not None:
+            self._dev(illum, "illum", (g.nz, g.ny, g.nx), torch.float32)
+        out_seis = (torch.empty((nrec, g.nt), dtype=torch.float32, device=self.device)
+                    if seis else None)
+        ck = _ckpt(ckpt)
+        wptr, wbytes = self._workspace(self.workspace_bytes(nrec, ck))
+        self._sync_stream()
+        check(self.L.wfd_gradient(self._ctx, _ptr(wavelet), _dptr(src), nrec, _dptr(rec),
+                                  _ptr(dobs), C.byref(ck), _ptr(out_seis), _ptr(misfit),
+                                  _ptr(grad), _ptr(illum), wptr, wbytes))
+        return (misfit, grad, out_seis) if seis else (misfit, grad)
+
+    def gradient_finish(self, grad, zero_top_planes: int):
+        torch = self.torch
+        g = self.grid
+        self._dev(grad, "grad", (g.nz, g.ny, g.nx), torch.float32)
+        self._sync_stream()
+        check(self.L.wfd_gradient_finish(self._ctx, _ptr(grad), int(zero_top_planes)))
+        return grad
+
+    # measurement -------------------------------------------------------------
+    def set_profiling(self, on: bool):
+        check(self.L.wfd_set_profiling(self._ctx, int(bool(on))))
+
+    def kernel_stats(self, kernel_class: int) -> Tuple[int, float]:
+        n, ms = C.c_int64(), C.c_double()
+        check(self.L.wfd_kernel_stats(self._ctx, int(kernel_class), C.byref(n), C.byref(ms)))
+        return n.value, ms.value

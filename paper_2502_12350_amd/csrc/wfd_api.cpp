@@ -1,0 +1,839 @@
+// C ABI of the library (declared in include/wfd.h): argument validation,
+// model preparation, workspace carving, and the stream-ordered time loops of
+// forward modeling (Alg. 1) and the one-shot gradient (Alg. 3).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "wfd.h"
+#include "wfd_internal.h"
+#include "wfd_plan.h"
+
+namespace {
+
+thread_local std::string g_last_error;
+
+wfd_status fail(wfd_status s, const char *fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+  return s;
+}
+
+#define HIP_TRY(expr)                                                                   \
+  do {                                                                                  \
+    hipError_t e_ = (expr);                                                             \
+    if (e_ != hipSuccess)                                                               \
+      return fail(WFD_E_HIP, "%s failed: %s (%s:%d)", #expr, hipGetErrorString(e_),    \
+                  __FILE__, __LINE__);                                                  \
+  } while (0)
+
+constexpr size_t kAlign = 256;
+inline size_t align_up(size_t v, size_t a = kAlign) { return (v + a - 1) / a * a; }
+
+// Bump allocator over a caller buffer (or a null base for sizing).
+struct Carve {
+  char *base;
+  size_t off = 0;
+  explicit Carve(void *b) : base((char *)b) {}
+  template <class T>
+  T *take(size_t count) {
+    off = align_up(off);
+    T *p = base ? (T *)(base + off) : nullptr;
+    off += count * sizeof(T);
+    return p;
+  }
+};
+
+constexpr int kReducePartials = 1024;
+
+}  // namespace
+
+struct wfd_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+
+  // model
+  bool has_model = false;
+  wfd_grid grid{};
+  int Nx = 0, Ny = 0, Nz = 0, pitch = 0;
+  int64_t plane = 0, vol = 0;  // floats
+  bool vd = false;
+  float *k = nullptr, *m2 = nullptr, *sqrt_rho = nullptr;
+  float *gx = nullptr, *gy = nullptr, *gz = nullptr;
+
+  // host staging of the receiver tables (kept alive until the upload ends)
+  std::vector<char> stage;
+  hipEvent_t upload_done = nullptr;
+  bool upload_pending = false;
+
+  // profiling
+  bool prof = false;
+  std::vector<hipEvent_t> pool;
+  size_t pool_used = 0;
+  std::vector<int> rec_class;  // class of event pair i (pool[2i], pool[2i+1])
+  int64_t launches[WFD_K_COUNT] = {0, 0, 0};
+  double ms[WFD_K_COUNT] = {0, 0, 0};
+};
+
+namespace {
+
+struct ScopedDevice {
+  int prev = -1;
+  explicit ScopedDevice(int dev) {
+    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+    if (prev != dev) (void)hipSetDevice(dev);
+  }
+  ~ScopedDevice() {
+    int cur = -1;
+    if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+  }
+};
+
+// Per-launch HIP-event timing (only when profiling is on).
+struct Timed {
+  wfd_ctx *c;
+  int cls;
+  size_t idx = 0;
+  bool on;
+  Timed(wfd_ctx *ctx, int klass) : c(ctx), cls(klass), on(ctx->prof) {
+    if (!on) return;
+    if (c->pool_used + 2 > c->pool.size()) {
+      for (int i = 0; i < 256; ++i) {
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess) {
+          on = false;
+          return;
+        }
+        c->pool.push_back(e);
+      }
+    }
+    idx = c->pool_used;
+    c->pool_used += 2;
+    c->rec_class.push_back(cls);
+    (void)hipEventRecord(c->pool[idx], c->stream);
+  }
+  ~Timed() {
+    if (on) (void)hipEventRecord(c->pool[idx + 1], c->stream);
+  }
+};
+
+wfd_status drain_profile(wfd_ctx *c) {
+  if (c->pool_used == 0) return WFD_OK;
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  for (size_t i = 0; i + 1 < c->pool_used; i += 2) {
+    float t = 0.0f;
+    HIP_TRY(hipEventElapsedTime(&t, c->pool[i], c->pool[i + 1]));
+    const int cls = c->rec_class[i / 2];
+    c->launches[cls] += 1;
+    c->ms[cls] += t;
+  }
+  c->pool_used = 0;
+  c->rec_class.clear();
+  return WFD_OK;
+}
+
+wfd_status check_grid(const wfd_grid *g) {
+  if (!g) return fail(WFD_E_ARG, "grid is NULL");
+  if (g->nx < 1 || g->ny < 1 || g->nz < 1)
+    return fail(WFD_E_ARG, "model size must be >= 1 per axis (got %d %d %d)", g->nx, g->ny, g->nz);
+  if (!(g->dx > 0) || !(g->dy > 0) || !(g->dz > 0) || !std::isfinite(g->dx) ||
+      !std::isfinite(g->dy) || !std::isfinite(g->dz))
+    return fail(WFD_E_ARG, "grid spacing must be finite and > 0");
+  if (!std::isfinite(g->ox) || !std::isfinite(g->oy) || !std::isfinite(g->oz))
+    return fail(WFD_E_ARG, "origin must be finite");
+  if (g->border < 0) return fail(WFD_E_ARG, "border must be >= 0 (got %d)", g->border);
+  if (!(g->dt > 0) || !std::isfinite(g->dt)) return fail(WFD_E_ARG, "dt must be finite and > 0");
+  if (g->nt < 1) return fail(WFD_E_ARG, "nt must be >= 1 (got %d)", g->nt);
+  const int64_t Nx = (int64_t)g->nx + 2 * g->border, Ny = (int64_t)g->ny + 2 * g->border,
+                Nz = (int64_t)g->nz + 2 * g->border;
+  if (Nx > (1 << 24) || Ny > (1 << 24) || Nz > (1 << 24) || Nx * Ny > (int64_t(1) << 30))
+    return fail(WFD_E_ARG, "padded grid too large");
+  return WFD_OK;
+}
+
+int pitch_of(int Nx) { return (Nx + 63) / 64 * 64; }
+
+// Model buffer layout (shared by wfd_model_bytes and wfd_set_model).
+struct ModelLayout {
+  float *k, *m2, *sqrt_rho, *gx, *gy, *gz, *part_v, *part_m;
+  size_t bytes;
+};
+ModelLayout model_layout(const wfd_grid &g, bool vd, void *base) {
+  const int Nx = g.nx + 2 * g.border, Ny = g.ny + 2 * g.border, Nz = g.nz + 2 * g.border;
+  const size_t vol = (size_t)pitch_of(Nx) * Ny * Nz;
+  Carve cv(base);
+  ModelLayout L{};
+  L.k = cv.take<float>(vol);
+  L.m2 = vd ? cv.take<float>(vol) : nullptr;
+  L.sqrt_rho = vd ? cv.take<float>((size_t)g.nx * g.ny * g.nz) : nullptr;
+  L.gx = cv.take<float>(Nx);
+  L.gy = cv.take<float>(Ny);
+  L.gz = cv.take<float>(Nz);
+  L.part_v = cv.take<float>(kReducePartials);
+  L.part_m = cv.take<float>(kReducePartials);
+  L.bytes = align_up(cv.off);
+  return L;
+}
+
+std::vector<float> sponge_table(int n, int border) {
+  std::vector<float> t(n + 2 * border, 1.0f);
+  if (border == 0) return t;
+  for (int i = 0; i < n + 2 * border; ++i) {
+    int d = std::max(std::max(border - i, 0), i - (border + n - 1));
+    const double r = 0.4 * (double)d / (double)border;
+    t[i] = (float)std::exp(-r * r);
+  }
+  return t;
+}
+
+// Workspace layout for one shot.
+struct Work {
+  // receiver tables (uploaded)
+  int *col_start, *ent_z, *ent_rp, *perm, *rec_model_idx;
+  int64_t *rec_idx;
+  // device-computed scalars / scales
+  float *sigma, *rec_scale, *rec_adj;
+  float *seis_tm;
+  float *W1, *W2;
+  // gradient only
+  float *res_tm, *P1, *P2, *g, *store;
+  double *partial;
+  int64_t n_store_vols;
+  size_t bytes;
+};
+
+int64_t snapshots_for(const wfd_ctx *c, const wfd_ckpt *ck) {
+  if (ck->mode == WFD_CKPT_FULL) return c->grid.nt;
+  if (ck->n_snapshots > 0) return ck->n_snapshots;
+  size_t free_b = 0, total_b = 0;
+  if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) return 0;
+  const double frac = (ck->mem_fraction > 0 && ck->mem_fraction <= 1.0) ? ck->mem_fraction : 0.8;
+  const double pair = 2.0 * (double)c->vol * sizeof(float);
+  int64_t s = (int64_t)(frac * (double)free_b / pair);
+  return std::max<int64_t>(1, std::min<int64_t>(s, c->grid.nt));
+}
+
+Work work_layout(const wfd_ctx *c, int nrec, const wfd_ckpt *ck, int64_t nsnap, void *base) {
+  Carve cv(base);
+  Work w{};
+  const int ncol = c->Nx * c->Ny;
+  w.col_start = cv.take<int>((size_t)ncol + 1);
+  w.ent_z = cv.take<int>((size_t)std::max(nrec, 1));
+  w.ent_rp = cv.take<int>((size_t)nrec + 1);
+  w.perm = cv.take<int>((size_t)std::max(nrec, 1));
+  w.rec_model_idx = cv.take<int>((size_t)std::max(nrec, 1));
+  w.rec_idx = cv.take<int64_t>((size_t)std::max(nrec, 1));
+  w.sigma = cv.take<float>(1);
+  w.rec_scale = cv.take<float>((size_t)std::max(nrec, 1));
+  w.rec_adj = cv.take<float>((size_t)std::max(nrec, 1));
+  w.seis_tm = cv.take<float>((size_t)c->grid.nt * std::max(nrec, 1));
+  w.W1 = cv.take<float>((size_t)c->vol);
+  w.W2 = cv.take<float>((size_t)c->vol);
+  if (ck) {
+    w.res_tm = cv.take<float>((size_t)c->grid.nt * std::max(nrec, 1));
+    w.partial = cv.take<double>((size_t)std::max(1, wfd::residual_partial_count(nrec, c->grid.nt)));
+    w.P1 = cv.take<float>((size_t)c->vol);
+    w.P2 = cv.take<float>((size_t)c->vol);
+    w.g = cv.take<float>((size_t)c->vol);
+    w.n_store_vols = ck->mode == WFD_CKPT_FULL ? (int64_t)c->grid.nt : 2 * nsnap;
+    w.store = cv.take<float>((size_t)w.n_store_vols * (size_t)c->vol);
+  }
+  w.bytes = align_up(cv.off);
+  return w;
+}
+
+wfd::StepGrid step_grid(const wfd_ctx *c) {
+  wfd::StepGrid g;
+  g.nx = c->Nx;
+  g.ny = c->Ny;
+  g.nz = c->Nz;
+  g.pitch = c->pitch;
+  g.plane = c->plane;
+  g.cx = (float)(1.0 / (c->grid.dx * c->grid.dx));
+  g.cy = (float)(1.0 / (c->grid.dy * c->grid.dy));
+  g.cz = (float)(1.0 / (c->grid.dz * c->grid.dz));
+  g.gx = c->gx;
+  g.gy = c->gy;
+  g.gz = c->gz;
+  g.k = c->k;
+  g.m2 = c->vd ? c->m2 : nullptr;
+  return g;
+}
+
+int64_t lin(const wfd_ctx *c, const int32_t ijk[3]) {
+  return (int64_t)ijk[2] * c->plane + (int64_t)ijk[1] * c->pitch + ijk[0];
+}
+
+// Map positions, group receivers by column, upload tables, launch shot setup.
+wfd_status prepare_shot(wfd_ctx *c, const double src_xyz[3], int nrec, const double *rec_xyz,
+                        const Work &w, int64_t &src_idx) {
+  const wfd_grid &g = c->grid;
+  int32_t s[3];
+  if (!wfd::map_position(g, src_xyz, s))
+    return fail(WFD_E_RANGE, "source (%g, %g, %g) is outside the model", src_xyz[0], src_xyz[1],
+                src_xyz[2]);
+  src_idx = lin(c, s);
+  const int src_model =
+      ((s[2] - g.border) * g.ny + (s[1] - g.border)) * g.nx + (s[0] - g.border);
+
+  struct R {
+    int col, z, id;
+    int64_t idx;
+    int model;
+  };
+  std::vector<R> recs((size_t)nrec);
+  for (int r = 0; r < nrec; ++r) {
+    int32_t ijk[3];
+    if (!wfd::map_position(g, rec_xyz + 3 * (size_t)r, ijk))
+      return fail(WFD_E_RANGE, "receiver %d (%g, %g, %g) is outside the model", r,
+                  rec_xyz[3 * r], rec_xyz[3 * r + 1], rec_xyz[3 * r + 2]);
+    recs[r] = R{ijk[1] * c->Nx + ijk[0], ijk[2], r, lin(c, ijk),
+                ((ijk[2] - g.border) * g.ny + (ijk[1] - g.border)) * g.nx + (ijk[0] - g.border)};
+  }
+  std::vector<R> sorted = recs;
+  std::stable_sort(sorted.begin(), sorted.end(), [](const R &a, const R &b) {
+    return a.col != b.col ? a.col < b.col : a.z < b.z;
+  });
+  const int ncol = c->Nx * c->Ny;
+  std::vector<int> col_start((size_t)ncol + 1, 0), ent_z, ent_rp, perm;
+  ent_rp.push_back(0);
+  std::vector<int> ent_col;
+  for (size_t i = 0; i < sorted.size(); ++i) {
+    if (i == 0 || sorted[i].col != sorted[i - 1].col || sorted[i].z != sorted[i - 1].z) {
+      if (i > 0) ent_rp.push_back((int)i);
+      ent_z.push_back(sorted[i].z);
+      ent_col.push_back(sorted[i].col);
+    }
+    perm.push_back(sorted[i].id);
+  }
+  if (!sorted.empty()) ent_rp.push_back((int)sorted.size());
+  // col_start: first entry of each column
+  {
+    size_t e = 0;
+    for (int col = 0; col <= ncol; ++col) {
+      while (e < ent_col.size() && ent_col[e] < col) ++e;
+      col_start[col] = (int)e;
+    }
+  }
+  // staging blob: ints then int64
+  if (c->upload_pending) {
+    HIP_TRY(hipEventSynchronize(c->upload_done));
+    c->upload_pending = false;
+  }
+  const size_t n_ent = ent_z.size();
+  const size_t sz_col = (size_t)(ncol + 1) * sizeof(int);
+  const size_t total = sz_col + (n_ent + (n_ent + 1) + 2 * (size_t)nrec) * sizeof(int) +
+                       (size_t)nrec * sizeof(int64_t) + 64;
+  c->stage.resize(total);
+  char *p = c->stage.data();
+  std::memcpy(p, col_start.data(), sz_col);
+  HIP_TRY(hipMemcpyAsync(w.col_start, p, sz_col, hipMemcpyHostToDevice, c->stream));
+  p += sz_col;
+  auto up = [&](void *dst, const void *src, size_t bytes) -> hipError_t {
+    if (bytes == 0) return hipSuccess;
+    std::memcpy(p, src, bytes);
+    hipError_t e = hipMemcpyAsync(dst, p, bytes, hipMemcpyHostToDevice, c->stream);
+    p += bytes;
+    return e;
+  };
+  std::vector<int> rmodel((size_t)nrec);
+  std::vector<int64_t> ridx((size_t)nrec);
+  for (int r = 0; r < nrec; ++r) {
+    rmodel[r] = recs[r].model;
+    ridx[r] = recs[r].idx;
+  }
+  HIP_TRY(up(w.ent_z, ent_z.data(), n_ent * sizeof(int)));
+  HIP_TRY(up(w.ent_rp, ent_rp.data(), ent_rp.size() * sizeof(int)));
+  HIP_TRY(up(w.perm, perm.data(), perm.size() * sizeof(int)));
+  HIP_TRY(up(w.rec_model_idx, rmodel.data(), rmodel.size() * sizeof(int)));
+  HIP_TRY(up(w.rec_idx, ridx.data(), ridx.size() * sizeof(int64_t)));
+  HIP_TRY(hipEventRecord(c->upload_done, c->stream));
+  c->upload_pending = true;
+
+  const double dt2_over_h3 = g.dt * g.dt / (g.dx * g.dy * g.dz);
+  {
+    Timed t(c, WFD_K_OTHER);
+    HIP_TRY(wfd::launch_shot_setup(c->k, c->vd ? c->sqrt_rho : nullptr, g.border, g.nx, g.ny,
+                                   src_idx, src_model, dt2_over_h3, w.rec_idx, w.rec_model_idx,
+                                   nrec, w.sigma, w.rec_scale, w.rec_adj, c->stream));
+  }
+  return WFD_OK;
+}
+
+wfd::RecTable rec_table(const Work &w, int nrec) {
+  wfd::RecTable t;
+  t.col_start = w.col_start;
+  t.ent_z = w.ent_z;
+  t.ent_rp = w.ent_rp;
+  t.perm = w.perm;
+  t.nrec = nrec;
+  return t;
+}
+
+wfd_status zero(wfd_ctx *c, float *p, int64_t n) {
+  Timed t(c, WFD_K_OTHER);
+  HIP_TRY(wfd::launch_fill_zero(p, n, c->stream));
+  return WFD_OK;
+}
+
+wfd_status common_checks(wfd_ctx *c, const float *wavelet, const double *src, int nrec,
+                         const double *rec) {
+  if (!c) return fail(WFD_E_ARG, "ctx is NULL");
+  if (!c->has_model) return fail(WFD_E_STATE, "no model: call wfd_set_model first");
+  if (!wavelet) return fail(WFD_E_ARG, "wavelet is NULL");
+  if (!src) return fail(WFD_E_ARG, "source position is NULL");
+  if (nrec < 0) return fail(WFD_E_ARG, "nrec must be >= 0");
+  if (nrec > 0 && !rec) return fail(WFD_E_ARG, "receiver positions are NULL");
+  return WFD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *wfd_last_error(void) { return g_last_error.c_str(); }
+
+wfd_status wfd_create(wfd_ctx **out, int32_t device, void *hip_stream) {
+  if (!out) return fail(WFD_E_ARG, "ctx pointer is NULL");
+  *out = nullptr;
+  int n = 0;
+  HIP_TRY(hipGetDeviceCount(&n));
+  if (device < 0 || device >= n) return fail(WFD_E_ARG, "device %d out of range (%d)", device, n);
+  wfd_ctx *c = new (std::nothrow) wfd_ctx();
+  if (!c) return fail(WFD_E_NOMEM, "out of host memory");
+  c->device = device;
+  c->stream = (hipStream_t)hip_stream;
+  ScopedDevice sd(device);
+  if (hipEventCreateWithFlags(&c->upload_done, hipEventDisableTiming) != hipSuccess) {
+    delete c;
+    return fail(WFD_E_HIP, "hipEventCreate failed");
+  }
+  *out = c;
+  return WFD_OK;
+}
+
+wfd_status wfd_set_stream(wfd_ctx *c, void *hip_stream) {
+  if (!c) return fail(WFD_E_ARG, "ctx is NULL");
+  c->stream = (hipStream_t)hip_stream;
+  return WFD_OK;
+}
+
+wfd_status wfd_destroy(wfd_ctx *c) {
+  if (!c) return WFD_OK;
+  ScopedDevice sd(c->device);
+  if (c->upload_pending) (void)hipEventSynchronize(c->upload_done);
+  if (c->upload_done) (void)hipEventDestroy(c->upload_done);
+  for (hipEvent_t e : c->pool) (void)hipEventDestroy(e);
+  delete c;
+  return WFD_OK;
+}
+
+wfd_status wfd_model_bytes(const wfd_grid *grid, int32_t variable_density, size_t *bytes) {
+  if (!bytes) return fail(WFD_E_ARG, "bytes is NULL");
+  wfd_status s = check_grid(grid);
+  if (s != WFD_OK) return s;
+  *bytes = model_layout(*grid, variable_density != 0, nullptr).bytes;
+  return WFD_OK;
+}
+
+wfd_status wfd_set_model(wfd_ctx *c, const wfd_grid *grid, const float *vel,
+                         const float *rho, void *model, size_t model_bytes) {
+  if (!c) return fail(WFD_E_ARG, "ctx is NULL");
+  wfd_status s = check_grid(grid);
+  if (s != WFD_OK) return s;
+  if (!vel) return fail(WFD_E_ARG, "velocity is NULL");
+  if (!model) return fail(WFD_E_ARG, "model buffer is NULL");
+  const bool vd = rho != nullptr;
+  ModelLayout L = model_layout(*grid, vd, model);
+  if (model_bytes < L.bytes)
+    return fail(WFD_E_NOMEM, "model buffer has %zu bytes, %zu needed", model_bytes, L.bytes);
+  if ((uintptr_t)model % kAlign) return fail(WFD_E_ARG, "model buffer must be 256-byte aligned");
+  ScopedDevice sd(c->device);
+  c->has_model = false;
+  c->grid = *grid;
+  c->Nx = grid->nx + 2 * grid->border;
+  c->Ny = grid->ny + 2 * grid->border;
+  c->Nz = grid->nz + 2 * grid->border;
+  c->pitch = pitch_of(c->Nx);
+  c->plane = (int64_t)c->pitch * c->Ny;
+  c->vol = c->plane * c->Nz;
+  c->vd = vd;
+  c->k = L.k;
+  c->m2 = L.m2;
+  c->sqrt_rho = L.sqrt_rho;
+  c->gx = L.gx;
+  c->gy = L.gy;
+  c->gz = L.gz;
+
+  // pitch padding of the coefficient volumes is never read by the kernels
+  // but is cleared so the buffer holds no stale values
+  {
+    Timed t(c, WFD_K_OTHER);
+    HIP_TRY(wfd::launch_fill_zero(c->k, c->vol, c->stream));
+  }
+  if (vd) {
+    Timed t(c, WFD_K_OTHER);
+    HIP_TRY(wfd::launch_fill_zero(c->m2, c->vol, c->stream));
+  }
+  std::vector<float> tx = sponge_table(grid->nx, grid->border);
+  std::vector<float> ty = sponge_table(grid->ny, grid->border);
+  std::vector<float> tz = sponge_table(grid->nz, grid->border);
+  HIP_TRY(hipMemcpyAsync(c->gx, tx.data(), tx.size() * 4, hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(hipMemcpyAsync(c->gy, ty.data(), ty.size() * 4, hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(hipMemcpyAsync(c->gz, tz.data(), tz.size() * 4, hipMemcpyHostToDevice, c->stream));
+  {
+    Timed t(c, WFD_K_OTHER);
+    HIP_TRY(wfd::launch_precompute_k(vel, grid->nx, grid->ny, grid->nz, grid->border, grid->dt,
+                                     c->k, c->pitch, c->Ny, c->Nz, L.part_v, kReducePartials,
+                                     c->stream));
+  }
+  if (vd) {
+    Timed t(c, WFD_K_OTHER);
+    HIP_TRY(wfd::launch_precompute_m2(rho, grid->nx, grid->ny, grid->nz, grid->border,
+                                      1.0 / (grid->dx * grid->dx), 1.0 / (grid->dy * grid->dy),
+                                      1.0 / (grid->dz * grid->dz), c->m2, c->pitch, c->Ny, c->Nz,
+                                      c->sqrt_rho, L.part_m, kReducePartials, c->stream));
+  }
+  std::vector<float> pv(kReducePartials), pm(kReducePartials, 0.0f);
+  HIP_TRY(hipMemcpyAsync(pv.data(), L.part_v, kReducePartials * 4, hipMemcpyDeviceToHost,
+                         c->stream));
+  if (vd)
+    HIP_TRY(hipMemcpyAsync(pm.data(), L.part_m, kReducePartials * 4, hipMemcpyDeviceToHost,
+                           c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  const double vmax = *std::max_element(pv.begin(), pv.end());
+  const double m2max = vd ? *std::max_element(pm.begin(), pm.end()) : 0.0;
+  if (!(vmax > 0) || !std::isfinite(vmax))
+    return fail(WFD_E_ARG, "velocity must be finite and > 0 (max %g)", vmax);
+  const double ratio = wfd::cfl_ratio(*grid, vmax, m2max);
+  if (!(ratio < 1.0))
+    return fail(WFD_E_CFL,
+                "unstable: dt^2 vmax^2 (Lambda + m2max) / 4 = %g >= 1 (vmax %g, dt %g); "
+                "reduce dt below %g",
+                ratio, vmax, grid->dt, grid->dt / std::sqrt(ratio));
+  c->has_model = true;
+  return WFD_OK;
+}
+
+wfd_status wfd_workspace_bytes(const wfd_ctx *c, int32_t nrec, const wfd_ckpt *ck, size_t *bytes) {
+  if (!c || !bytes) return fail(WFD_E_ARG, "NULL argument");
+  if (!c->has_model) return fail(WFD_E_STATE, "no model: call wfd_set_model first");
+  if (nrec < 0) return fail(WFD_E_ARG, "nrec must be >= 0");
+  int64_t nsnap = 0;
+  if (ck) {
+    if (ck->mode != WFD_CKPT_FULL && ck->mode != WFD_CKPT_REVOLVE)
+      return fail(WFD_E_ARG, "unknown checkpoint mode %d", ck->mode);
+    if (ck->mode == WFD_CKPT_REVOLVE && ck->n_snapshots < 0)
+      return fail(WFD_E_ARG, "n_snapshots must be >= 0");
+    ScopedDevice sd(c->device);
+    nsnap = snapshots_for(c, ck);
+  }
+  *bytes = work_layout(c, nrec, ck, nsnap, nullptr).bytes;
+  return WFD_OK;
+}
+
+wfd_status wfd_forward(wfd_ctx *c, const float *wavelet, const double src_xyz[3], int32_t nrec,
+                       const double *rec_xyz, float *seis, float *final_dev, void *work,
+                       size_t work_bytes) {
+  wfd_status s = common_checks(c, wavelet, src_xyz, nrec, rec_xyz);
+  if (s != WFD_OK) return s;
+  if (nrec > 0 && !seis) return fail(WFD_E_ARG, "seismogram output is NULL");
+  if (!work) return fail(WFD_E_ARG, "workspace is NULL");
+  if ((uintptr_t)work % kAlign) return fail(WFD_E_ARG, "workspace must be 256-byte aligned");
+  Work w = work_layout(c, nrec, nullptr, 0, work);
+  if (work_bytes < w.bytes)
+    return fail(WFD_E_NOMEM, "workspace has %zu bytes, %zu needed", work_bytes, w.bytes);
+  ScopedDevice sd(c->device);
+  int64_t src_idx = 0;
+  s = prepare_shot(c, src_xyz, nrec, rec_xyz, w, src_idx);
+  if (s != WFD_OK) return s;
+  if ((s = zero(c, w.W1, c->vol)) != WFD_OK) return s;
+  if ((s = zero(c, w.W2, c->vol)) != WFD_OK) return s;
+  const wfd::StepGrid g = step_grid(c);
+  const wfd::RecTable rt = rec_table(w, nrec);
+  const wfd::Source src{src_idx, w.sigma, wavelet};
+  float *cur = w.W1, *prev = w.W2;
+  for (int n = 0; n < c->grid.nt; ++n) {
+    {
+      Timed t(c, WFD_K_FORWARD);
+      HIP_TRY(wfd::launch_forward_step(g, cur, prev, prev, src, n, nrec > 0 ? &rt : nullptr,
+                                       w.rec_scale, w.seis_tm, c->stream));
+    }
+    std::swap(cur, prev);
+  }
+  if (nrec > 0) {
+    Timed t(c, WFD_K_OTHER);
+    HIP_TRY(wfd::launch_transpose(w.seis_tm, seis, nrec, c->grid.nt, c->stream));
+  }
+  if (final_dev) {
+    const size_t row = (size_t)c->Nx * sizeof(float);
+    const size_t dense = (size_t)c->Nx * c->Ny * c->Nz;
+    HIP_TRY(hipMemcpy2DAsync(final_dev, row, cur, (size_t)c->pitch * 4, row,
+                             (size_t)c->Ny * c->Nz, hipMemcpyDeviceToDevice, c->stream));
+    HIP_TRY(hipMemcpy2DAsync(final_dev + dense, row, prev, (size_t)c->pitch * 4, row,
+                             (size_t)c->Ny * c->Nz, hipMemcpyDeviceToDevice, c->stream));
+  }
+  return WFD_OK;
+}
+
+wfd_status wfd_gradient(wfd_ctx *c, const float *wavelet, const double src_xyz[3], int32_t nrec,
+                        const double *rec_xyz, const float *dobs, const wfd_ckpt *ck,
+                        float *seis, double *misfit, float *grad, float *illum, void *work,
+                        size_t work_bytes) {
+  wfd_status s = common_checks(c, wavelet, src_xyz, nrec, rec_xyz);
+  if (s != WFD_OK) return s;
+  if (!ck) return fail(WFD_E_ARG, "checkpoint policy is NULL");
+  if (ck->mode != WFD_CKPT_FULL && ck->mode != WFD_CKPT_REVOLVE)
+    return fail(WFD_E_ARG, "unknown checkpoint mode %d", ck->mode);
+  if (ck->mode == WFD_CKPT_REVOLVE && ck->n_snapshots < 0)
+    return fail(WFD_E_ARG, "n_snapshots must be >= 0");
+  if (nrec > 0 && !dobs) return fail(WFD_E_ARG, "observed data is NULL");
+  if (!misfit || !grad) return fail(WFD_E_ARG, "misfit / gradient output is NULL");
+  if (!work) return fail(WFD_E_ARG, "workspace is NULL");
+  if ((uintptr_t)work % kAlign) return fail(WFD_E_ARG, "workspace must be 256-byte aligned");
+  ScopedDevice sd(c->device);
+  int64_t nsnap = 0;
+  if (ck->mode == WFD_CKPT_FULL) {
+    nsnap = c->grid.nt;
+  } else if (ck->n_snapshots > 0) {
+    nsnap = ck->n_snapshots;
+  } else {
+    // derived count: as many pairs as the given workspace holds
+    const size_t base = work_layout(c, nrec, ck, 0, nullptr).bytes;
+    const size_t pair = align_up((size_t)c->vol * sizeof(float)) * 2;
+    nsnap = work_bytes > base ? (int64_t)((work_bytes - base) / pair) : 0;
+    nsnap = std::min<int64_t>(nsnap, c->grid.nt);
+    if (nsnap < 1) return fail(WFD_E_NOMEM, "workspace holds no checkpoint pair");
+    while (nsnap > 1 && work_layout(c, nrec, ck, nsnap, nullptr).bytes > work_bytes) --nsnap;
+  }
+  Work w = work_layout(c, nrec, ck, nsnap, work);
+  if (work_bytes < w.bytes)
+    return fail(WFD_E_NOMEM, "workspace has %zu bytes, %zu needed", work_bytes, w.bytes);
+  int64_t src_idx = 0;
+  s = prepare_shot(c, src_xyz, nrec, rec_xyz, w, src_idx);
+  if (s != WFD_OK) return s;
+  const int nt = c->grid.nt;
+  const wfd::StepGrid g = step_grid(c);
+  const wfd::RecTable rt = rec_table(w, nrec);
+  const wfd::Source src{src_idx, w.sigma, wavelet};
+  for (float *p : {w.W1, w.W2, w.P1, w.P2, w.g})
+    if ((s = zero(c, p, c->vol)) != WFD_OK) return s;
+
+  // adjoint state: psi^{m+1} = A1, psi^{m+2} = A2 (psi^m overwrites A2)
+  float *A1 = w.P1, *A2 = w.P2;
+  bool residual_done = false;
+  auto residual = [&]() -> wfd_status {
+    if (residual_done) return WFD_OK;
+    residual_done = true;
+    if (nrec == 0) return WFD_OK;
+    int np = 0;
+    {
+      Timed t(c, WFD_K_OTHER);
+      HIP_TRY(wfd::launch_residual(w.seis_tm, dobs, w.rec_adj, nrec, nt, w.res_tm, w.partial, &np,
+                                   c->stream));
+    }
+    {
+      Timed t(c, WFD_K_OTHER);
+      HIP_TRY(wfd::launch_sum_partials(w.partial, np, misfit, c->stream));
+    }
+    if (seis) {
+      Timed t(c, WFD_K_OTHER);
+      HIP_TRY(wfd::launch_transpose(w.seis_tm, seis, nrec, nt, c->stream));
+    }
+    return WFD_OK;
+  };
+  auto adjoint = [&](int m, const float *wm) -> wfd_status {
+    {
+      Timed t(c, WFD_K_ADJOINT);
+      HIP_TRY(wfd::launch_adjoint_step(g, A1, A2, A2, rt, w.res_tm, m, wm, w.g, illum,
+                                       c->grid.border, c->grid.nx, c->grid.ny, c->grid.nz,
+                                       c->stream));
+    }
+    std::swap(A1, A2);
+    return WFD_OK;
+  };
+  auto fwd = [&](const float *cur, const float *prev, float *out, int n, bool rec) -> wfd_status {
+    Timed t(c, WFD_K_FORWARD);
+    HIP_TRY(wfd::launch_forward_step(g, cur, prev, out, src, n,
+                                     (rec && nrec > 0) ? &rt : nullptr, w.rec_scale, w.seis_tm,
+                                     c->stream));
+    return WFD_OK;
+  };
+
+  if (ck->mode == WFD_CKPT_FULL) {
+    // slot m holds w^m (m = 1..nt); w^0 = W1 and w^-1 = W2 are zero
+    auto S = [&](int m) -> float * {
+      if (m == 0) return w.W1;
+      if (m < 0) return w.W2;
+      return w.store + (size_t)(m - 1) * (size_t)c->vol;
+    };
+    for (int n = 0; n < nt; ++n)
+      if ((s = fwd(S(n), S(n - 1), S(n + 1), n, true)) != WFD_OK) return s;
+    if ((s = residual()) != WFD_OK) return s;
+    for (int m = nt; m >= 1; --m)
+      if ((s = adjoint(m, S(m))) != WFD_OK) return s;
+  } else {
+    std::vector<int32_t> plan;
+    int64_t nsteps = 0;
+    wfd::build_checkpoint_plan(nt, (int32_t)nsnap, plan, nsteps);
+    struct Slot {
+      int state = -1;
+      float *a = nullptr, *b = nullptr;
+    };
+    std::vector<Slot> slots((size_t)nsnap);
+    for (int64_t i = 0; i < nsnap; ++i) {
+      slots[i].a = w.store + (size_t)(2 * i) * (size_t)c->vol;
+      slots[i].b = w.store + (size_t)(2 * i + 1) * (size_t)c->vol;
+    }
+    int cur_state = 0;  // W1/W2 hold x_0 = 0
+    float *cur = w.W1, *prev = w.W2;
+    int reached = 0;    // steps whose data has been recorded
+    auto slot_of = [&](int state) -> Slot * {
+      for (auto &sl : slots)
+        if (sl.state == state) return &sl;
+      return nullptr;
+    };
+    for (size_t i = 0; i + 3 <= plan.size(); i += 3) {
+      const int op = plan[i], a = plan[i + 1], b = plan[i + 2];
+      if (op == wfd::kAdvance) {
+        if (cur_state != a) {
+          if (a == 0) {
+            if ((s = zero(c, w.W1, c->vol)) != WFD_OK) return s;
+            if ((s = zero(c, w.W2, c->vol)) != WFD_OK) return s;
+            cur = w.W1;
+            prev = w.W2;
+          } else {
+            Slot *sl = slot_of(a);
+            if (!sl) return fail(WFD_E_STATE, "checkpoint plan: state %d not stored", a);
+            cur = sl->a;
+            prev = sl->b;
+          }
+        }
+        for (int n = a; n < b; ++n) {
+          float *out;
+          if (prev == w.W1 || prev == w.W2)
+            out = prev;
+          else
+            out = (cur == w.W1) ? w.W2 : w.W1;
+          if ((s = fwd(cur, prev, out, n, n >= reached)) != WFD_OK) return s;
+          if (n >= reached) reached = n + 1;
+          prev = cur;
+          cur = out;
+        }
+        cur_state = b;
+      } else if (op == wfd::kStore) {
+        if (cur_state != a) return fail(WFD_E_STATE, "checkpoint plan: store of non-current state");
+        Slot &sl = slots[(size_t)b];
+        const size_t bytes = (size_t)c->vol * sizeof(float);
+        Timed t(c, WFD_K_OTHER);
+        HIP_TRY(hipMemcpyAsync(sl.a, cur, bytes, hipMemcpyDeviceToDevice, c->stream));
+        HIP_TRY(hipMemcpyAsync(sl.b, prev, bytes, hipMemcpyDeviceToDevice, c->stream));
+        sl.state = a;
+      } else if (op == wfd::kVisit) {
+        if ((s = residual()) != WFD_OK) return s;
+        const float *wm = nullptr;
+        if (cur_state == a)
+          wm = cur;
+        else if (Slot *sl = slot_of(a))
+          wm = sl->a;
+        else if (cur_state == a + 1)
+          wm = prev;
+        if (!wm) return fail(WFD_E_STATE, "checkpoint plan: state %d unavailable", a);
+        if ((s = adjoint(a, wm)) != WFD_OK) return s;
+      } else if (op == wfd::kFree) {
+        slots[(size_t)b].state = -1;
+      }
+    }
+  }
+  {
+    Timed t(c, WFD_K_OTHER);
+    HIP_TRY(wfd::launch_grad_fold(w.g, c->k, c->pitch, c->Ny, c->grid.border, c->grid.nx,
+                                  c->grid.ny, c->grid.nz, c->grid.dt, grad, c->stream));
+  }
+  return WFD_OK;
+}
+
+wfd_status wfd_gradient_finish(wfd_ctx *c, float *grad, int32_t zero_top_planes) {
+  if (!c) return fail(WFD_E_ARG, "ctx is NULL");
+  if (!c->has_model) return fail(WFD_E_STATE, "no model: call wfd_set_model first");
+  if (!grad) return fail(WFD_E_ARG, "gradient is NULL");
+  if (zero_top_planes < 0 || zero_top_planes > c->grid.nz)
+    return fail(WFD_E_ARG, "zero_top_planes must be in [0, nz]");
+  if (zero_top_planes == 0) return WFD_OK;
+  ScopedDevice sd(c->device);
+  return zero(c, grad, (int64_t)zero_top_planes * c->grid.ny * c->grid.nx);
+}
+
+wfd_status wfd_map_position(const wfd_grid *grid, const double xyz[3], int32_t ijk[3]) {
+  wfd_status s = check_grid(grid);
+  if (s != WFD_OK) return s;
+  if (!xyz || !ijk) return fail(WFD_E_ARG, "NULL argument");
+  if (!wfd::map_position(*grid, xyz, ijk))
+    return fail(WFD_E_RANGE, "position (%g, %g, %g) is outside the model", xyz[0], xyz[1], xyz[2]);
+  return WFD_OK;
+}
+
+wfd_status wfd_cfl_ratio(const wfd_grid *grid, double vmax, double m2max, double *ratio) {
+  wfd_status s = check_grid(grid);
+  if (s != WFD_OK) return s;
+  if (!ratio) return fail(WFD_E_ARG, "ratio is NULL");
+  *ratio = wfd::cfl_ratio(*grid, vmax, m2max);
+  return WFD_OK;
+}
+
+wfd_status wfd_checkpoint_plan(int32_t nt, int32_t n_snapshots, int32_t *actions,
+                               int64_t capacity, int64_t *n_actions, int64_t *n_forward_steps) {
+  if (nt < 1) return fail(WFD_E_ARG, "nt must be >= 1");
+  if (n_snapshots < 1) return fail(WFD_E_ARG, "n_snapshots must be >= 1");
+  if (!n_actions || !n_forward_steps) return fail(WFD_E_ARG, "NULL argument");
+  std::vector<int32_t> plan;
+  int64_t steps = 0;
+  wfd::build_checkpoint_plan(nt, n_snapshots, plan, steps);
+  *n_actions = (int64_t)plan.size() / 3;
+  *n_forward_steps = steps;
+  if (actions) {
+    if (capacity < *n_actions) return fail(WFD_E_NOMEM, "action buffer too small");
+    std::memcpy(actions, plan.data(), plan.size() * sizeof(int32_t));
+  }
+  return WFD_OK;
+}
+
+wfd_status wfd_set_profiling(wfd_ctx *c, int32_t enable) {
+  if (!c) return fail(WFD_E_ARG, "ctx is NULL");
+  ScopedDevice sd(c->device);
+  if (enable) {
+    wfd_status s = drain_profile(c);
+    if (s != WFD_OK) return s;
+    for (int i = 0; i < WFD_K_COUNT; ++i) {
+      c->launches[i] = 0;
+      c->ms[i] = 0.0;
+    }
+  }
+  c->prof = enable != 0;
+  return WFD_OK;
+}
+
+wfd_status wfd_kernel_stats(wfd_ctx *c, int32_t kernel_class, int64_t *launches, double *total_ms) {
+  if (!c || !launches || !total_ms) return fail(WFD_E_ARG, "NULL argument");
+  if (kernel_class < 0 || kernel_class >= WFD_K_COUNT)
+    return fail(WFD_E_ARG, "unknown kernel class %d", kernel_class);
+  ScopedDevice sd(c->device);
+  wfd_status s = drain_profile(c);
+  if (s != WFD_OK) return s;
+  *launches = c->launches[kernel_class];
+  *total_ms = c->ms[kernel_class];
+  return WFD_OK;
+}
+
+}  // extern "C"

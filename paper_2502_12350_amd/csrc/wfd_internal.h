@@ -1,0 +1,84 @@
+// Internal interfaces between the host orchestrator (wfd_api.cpp) and the
+// HIP kernels (wfd_kernels.hip).  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace wfd {
+
+// Padded-grid geometry and coefficient volumes seen by every step kernel.
+// Volumes are [Nz][Ny][pitch] FP32 with pitch >= Nx (rows 256-byte aligned).
+struct StepGrid {
+  int nx, ny, nz;        // padded extents Nx, Ny, Nz
+  int pitch;             // floats per row
+  int64_t plane;         // pitch * Ny
+  float cx, cy, cz;      // 1 / h^2 per axis
+  const float *gx, *gy, *gz;  // 1-D sponge tables
+  const float *k;        // dt^2 v^2
+  const float *m2;       // mass term (variable density) or nullptr
+};
+
+// Receivers grouped by (y, x) column of the padded grid.  Entry e is one
+// distinct receiver node at depth ent_z[e]; the receivers sharing it are
+// perm[ent_rp[e] .. ent_rp[e+1]).  col_start has Ny*Nx + 1 entries.
+struct RecTable {
+  const int *col_start;
+  const int *ent_z;
+  const int *ent_rp;
+  const int *perm;
+  int nrec;
+};
+
+// Source: padded node (linear index into a pitched volume), device scalar
+// sigma = dt^2 / (hx hy hz sqrt(rho_src)) and the wavelet.
+struct Source {
+  int64_t idx;
+  const float *sigma;
+  const float *wavelet;
+};
+
+// Kernel launchers; all enqueue on `stream` and return the launch status.
+hipError_t launch_forward_step(const StepGrid &g, const float *cur, const float *prev, float *out,
+                               const Source &src, int n, const RecTable *rec,
+                               const float *rec_scale, float *seis_tm, hipStream_t stream);
+
+hipError_t launch_adjoint_step(const StepGrid &g, const float *cur, const float *prev, float *out,
+                               const RecTable &rec, const float *res_tm, int m,
+                               const float *wm, float *grad, float *illum, int border, int mnx,
+                               int mny, int mnz, hipStream_t stream);
+
+// Model preparation.
+hipError_t launch_precompute_k(const float *vel, int mnx, int mny, int mnz, int border, double dt,
+                               float *k, int pitch, int ny, int nz, float *partial_max,
+                               int n_partial, hipStream_t stream);
+hipError_t launch_precompute_m2(const float *rho, int mnx, int mny, int mnz, int border,
+                                double idx2, double idy2, double idz2, float *m2, int pitch,
+                                int ny, int nz, float *sqrt_rho, float *partial_max,
+                                int n_partial, hipStream_t stream);
+
+// Per-shot scalars: sigma and per-receiver forward / adjoint scales.
+hipError_t launch_shot_setup(const float *k, const float *sqrt_rho, int border, int mnx, int mny,
+                             int64_t src_idx, int src_model_idx, double dt2_over_h3,
+                             const int64_t *rec_idx, const int *rec_model_idx, int nrec,
+                             float *sigma, float *rec_scale, float *rec_adj, hipStream_t stream);
+
+// Residual + misfit: res_tm[n][r] = adj[r] * (seis_tm[n][r] - dobs[r][n]),
+// partial[b] = 1/2 sum res^2 (FP64) per block; then misfit += sum partial.
+hipError_t launch_residual(const float *seis_tm, const float *dobs, const float *rec_adj, int nrec,
+                           int nt, float *res_tm, double *partial, int *n_partial,
+                           hipStream_t stream);
+int residual_partial_count(int nrec, int nt);
+hipError_t launch_sum_partials(const double *partial, int n, double *misfit, hipStream_t stream);
+
+// [nt][nrec] -> [nrec][nt]
+hipError_t launch_transpose(const float *src_tm, float *dst_rm, int nrec, int nt,
+                            hipStream_t stream);
+
+// grad[m] += 2 / v * sum of g over the padded cells that replicate model cell m.
+hipError_t launch_grad_fold(const float *g, const float *k, int pitch, int pny, int border,
+                            int mnx, int mny, int mnz, double dt, float *grad, hipStream_t stream);
+
+hipError_t launch_fill_zero(float *p, int64_t n, hipStream_t stream);
+
+}  // namespace wfd

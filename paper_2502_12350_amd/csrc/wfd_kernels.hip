@@ -1,0 +1,436 @@
+// HIP kernels for gfx950 (MI355X): the acoustic leapfrog step with the
+// eighth-order 25-point star (arXiv 2502.12350, §2.1), fused source
+// injection / receiver recording, the adjoint step fused with the
+// cross-correlation imaging condition (Alg. 3), model preparation, misfit
+// and gradient finishing.
+//
+// Step kernels march in z: each thread owns RY points of one (x, y) column
+// of a 64 x (BY*RY) tile, keeps the nine z-neighbours of each in a register
+// queue, and stages the current plane (plus a 4-cell x/y halo) in LDS so
+// that the x and y neighbours are read from LDS.  Every field is read once
+// and written once per step from HBM (x-fastest, 256-byte rows).
+#include "wfd_internal.h"
+
+namespace wfd {
+namespace {
+
+// Eighth-order central weights of d^2/dx^2.
+constexpr float W0 = -205.0f / 72.0f;
+constexpr float W1 = 8.0f / 5.0f;
+constexpr float W2 = -1.0f / 5.0f;
+constexpr float W3 = 8.0f / 315.0f;
+constexpr float W4 = -1.0f / 560.0f;
+
+__device__ __forceinline__ float ld_or_zero(const float *f, const StepGrid &g, int x, int y,
+                                            int z) {
+  if (x < 0 || x >= g.nx || y < 0 || y >= g.ny || z < 0 || z >= g.nz) return 0.0f;
+  return f[(int64_t)z * g.plane + (int64_t)y * g.pitch + x];
+}
+
+// 25-point Laplacian with zero cells outside the padded grid.
+__device__ __forceinline__ float lap_point(const float *f, const StepGrid &g, int x, int y, int z,
+                                           float c) {
+  float lx = W0 * c + W1 * (ld_or_zero(f, g, x + 1, y, z) + ld_or_zero(f, g, x - 1, y, z)) +
+             W2 * (ld_or_zero(f, g, x + 2, y, z) + ld_or_zero(f, g, x - 2, y, z)) +
+             W3 * (ld_or_zero(f, g, x + 3, y, z) + ld_or_zero(f, g, x - 3, y, z)) +
+             W4 * (ld_or_zero(f, g, x + 4, y, z) + ld_or_zero(f, g, x - 4, y, z));
+  float ly = W0 * c + W1 * (ld_or_zero(f, g, x, y + 1, z) + ld_or_zero(f, g, x, y - 1, z)) +
+             W2 * (ld_or_zero(f, g, x, y + 2, z) + ld_or_zero(f, g, x, y - 2, z)) +
+             W3 * (ld_or_zero(f, g, x, y + 3, z) + ld_or_zero(f, g, x, y - 3, z)) +
+             W4 * (ld_or_zero(f, g, x, y + 4, z) + ld_or_zero(f, g, x, y - 4, z));
+  float lz = W0 * c + W1 * (ld_or_zero(f, g, x, y, z + 1) + ld_or_zero(f, g, x, y, z - 1)) +
+             W2 * (ld_or_zero(f, g, x, y, z + 2) + ld_or_zero(f, g, x, y, z - 2)) +
+             W3 * (ld_or_zero(f, g, x, y, z + 3) + ld_or_zero(f, g, x, y, z - 3)) +
+             W4 * (ld_or_zero(f, g, x, y, z + 4) + ld_or_zero(f, g, x, y, z - 4));
+  return g.cx * lx + g.cy * ly + g.cz * lz;
+}
+
+template <bool VD, bool GATHER>
+__global__ void __launch_bounds__(256)
+    k_forward_naive(StepGrid g, const float *__restrict__ cur, const float *prev, float *out,
+                    Source src, int n, RecTable rec, const float *__restrict__ rec_scale,
+                    float *__restrict__ seis_tm) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  const int y = blockIdx.y * blockDim.y + threadIdx.y;
+  const int z = blockIdx.z;
+  if (x >= g.nx || y >= g.ny) return;
+  const int64_t p = (int64_t)z * g.plane + (int64_t)y * g.pitch + x;
+  const float c = cur[p];
+  const float lap = lap_point(cur, g, x, y, z, c);
+  const float kk = g.k[p];
+  float acc = VD ? 2.0f * c + kk * (lap - g.m2[p] * c) : 2.0f * c + kk * lap;
+  if (p == src.idx) acc += src.sigma[0] * src.wavelet[n];
+  const float G = g.gx[x] * g.gy[y] * g.gz[z];
+  const float o = G * (acc - G * prev[p]);
+  out[p] = o;
+  if (GATHER) {
+    const int col = y * g.nx + x;
+    for (int e = rec.col_start[col]; e < rec.col_start[col + 1]; ++e) {
+      if (rec.ent_z[e] != z) continue;
+      for (int q = rec.ent_rp[e]; q < rec.ent_rp[e + 1]; ++q) {
+        const int r = rec.perm[q];
+        seis_tm[(int64_t)n * rec.nrec + r] = rec_scale[r] * o;
+      }
+    }
+  }
+}
+
+template <bool VD, bool ILLUM>
+__global__ void __launch_bounds__(256)
+    k_adjoint_naive(StepGrid g, const float *__restrict__ cur, const float *prev, float *out,
+                    RecTable rec, const float *__restrict__ res_tm, int m,
+                    const float *__restrict__ wm, float *__restrict__ grad,
+                    float *__restrict__ illum, int border, int mnx, int mny, int mnz) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  const int y = blockIdx.y * blockDim.y + threadIdx.y;
+  const int z = blockIdx.z;
+  if (x >= g.nx || y >= g.ny) return;
+  const int64_t p = (int64_t)z * g.plane + (int64_t)y * g.pitch + x;
+  const float c = cur[p];
+  const float lap = lap_point(cur, g, x, y, z, c);
+  const float kk = g.k[p];
+  const float mm = VD ? g.m2[p] : 0.0f;
+  float acc = VD ? 2.0f * c + kk * (lap - mm * c) : 2.0f * c + kk * lap;
+  const int col = y * g.nx + x;
+  for (int e = rec.col_start[col]; e < rec.col_start[col + 1]; ++e) {
+    if (rec.ent_z[e] != z) continue;
+    float s = 0.0f;
+    for (int q = rec.ent_rp[e]; q < rec.ent_rp[e + 1]; ++q)
+      s += res_tm[(int64_t)(m - 1) * rec.nrec + rec.perm[q]];
+    acc += s;
+  }
+  const float G = g.gx[x] * g.gy[y] * g.gz[z];
+  out[p] = G * (acc - G * prev[p]);
+  // imaging: g += psi^{m+1} (L w^m - m^2 w^m)
+  const float w = wm[p];
+  const float lw = lap_point(wm, g, x, y, z, w);
+  grad[p] += c * (VD ? lw - mm * w : lw);
+  if (ILLUM) {
+    const int ix = x - border, iy = y - border, iz = z - border;
+    if (ix >= 0 && ix < mnx && iy >= 0 && iy < mny && iz >= 0 && iz < mnz)
+      illum[((int64_t)iz * mny + iy) * mnx + ix] += w * w;
+  }
+}
+
+__device__ __forceinline__ int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
+
+// k = dt^2 v^2 over the padded grid (v edge-replicated); per-block max of v.
+__global__ void __launch_bounds__(256)
+    k_precompute_k(const float *__restrict__ vel, int mnx, int mny, int mnz, int border, double dt,
+                   float *__restrict__ k, int pitch, int ny, int nz, float *__restrict__ part) {
+  const int nx = mnx + 2 * border;
+  const int64_t total = (int64_t)nx * ny * nz;
+  float vmax = 0.0f;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int x = (int)(i % nx);
+    const int y = (int)((i / nx) % ny);
+    const int z = (int)(i / ((int64_t)nx * ny));
+    const int mx = clampi(x - border, 0, mnx - 1);
+    const int my = clampi(y - border, 0, mny - 1);
+    const int mz = clampi(z - border, 0, mnz - 1);
+    const double v = vel[((int64_t)mz * mny + my) * mnx + mx];
+    k[(int64_t)z * pitch * ny + (int64_t)y * pitch + x] = (float)(dt * dt * v * v);
+    vmax = fmaxf(vmax, (float)v);
+  }
+  __shared__ float red[256];
+  red[threadIdx.x] = vmax;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (threadIdx.x < s) red[threadIdx.x] = fmaxf(red[threadIdx.x], red[threadIdx.x + s]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+__device__ __forceinline__ double sqrt_rho_at(const float *rho, int mnx, int mny, int mnz,
+                                              int x, int y, int z) {
+  const int mx = clampi(x, 0, mnx - 1), my = clampi(y, 0, mny - 1), mz = clampi(z, 0, mnz - 1);
+  return sqrt((double)rho[((int64_t)mz * mny + my) * mnx + mx]);
+}
+
+// m^2 = L8(s) / s with s = sqrt(rho) edge-replicated beyond the model (FP64);
+// also s on the model grid for source / receiver scales; per-block max m^2.
+__global__ void __launch_bounds__(256)
+    k_precompute_m2(const float *__restrict__ rho, int mnx, int mny, int mnz, int border,
+                    double idx2, double idy2, double idz2, float *__restrict__ m2, int pitch,
+                    int ny, int nz, float *__restrict__ sqrt_rho, float *__restrict__ part) {
+  const int nx = mnx + 2 * border;
+  const int64_t total = (int64_t)nx * ny * nz;
+  const double w[5] = {-205.0 / 72.0, 8.0 / 5.0, -1.0 / 5.0, 8.0 / 315.0, -1.0 / 560.0};
+  float mmax = -3.0e38f;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int x = (int)(i % nx);
+    const int y = (int)((i / nx) % ny);
+    const int z = (int)(i / ((int64_t)nx * ny));
+    const int mx = x - border, my = y - border, mz = z - border;
+    const double s = sqrt_rho_at(rho, mnx, mny, mnz, mx, my, mz);
+    double lx = w[0] * s, ly = w[0] * s, lz = w[0] * s;
+    for (int j = 1; j <= 4; ++j) {
+      lx += w[j] * (sqrt_rho_at(rho, mnx, mny, mnz, mx + j, my, mz) +
+                    sqrt_rho_at(rho, mnx, mny, mnz, mx - j, my, mz));
+      ly += w[j] * (sqrt_rho_at(rho, mnx, mny, mnz, mx, my + j, mz) +
+                    sqrt_rho_at(rho, mnx, mny, mnz, mx, my - j, mz));
+      lz += w[j] * (sqrt_rho_at(rho, mnx, mny, mnz, mx, my, mz + j) +
+                    sqrt_rho_at(rho, mnx, mny, mnz, mx, my, mz - j));
+    }
+    const double val = (lx * idx2 + ly * idy2 + lz * idz2) / s;
+    m2[(int64_t)z * pitch * ny + (int64_t)y * pitch + x] = (float)val;
+    mmax = fmaxf(mmax, (float)val);
+    if (mx >= 0 && mx < mnx && my >= 0 && my < mny && mz >= 0 && mz < mnz)
+      sqrt_rho[((int64_t)mz * mny + my) * mnx + mx] = (float)s;
+  }
+  __shared__ float red[256];
+  red[threadIdx.x] = mmax;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (threadIdx.x < s) red[threadIdx.x] = fmaxf(red[threadIdx.x], red[threadIdx.x + s]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+__global__ void __launch_bounds__(256)
+    k_shot_setup(const float *__restrict__ k, const float *__restrict__ sqrt_rho, int64_t src_idx,
+                 int src_model_idx, double dt2_over_h3, const int64_t *__restrict__ rec_idx,
+                 const int *__restrict__ rec_model_idx, int nrec, float *__restrict__ sigma,
+                 float *__restrict__ rec_scale, float *__restrict__ rec_adj) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i == 0) {
+    const double s = sqrt_rho ? (double)sqrt_rho[src_model_idx] : 1.0;
+    sigma[0] = (float)(dt2_over_h3 / s);
+  }
+  if (i < nrec) {
+    const float s = sqrt_rho ? sqrt_rho[rec_model_idx[i]] : 1.0f;
+    rec_scale[i] = s;
+    rec_adj[i] = k[rec_idx[i]] * s;
+  }
+}
+
+constexpr int TT = 32;  // transpose tile
+
+// res_tm[n][r] = adj[r] (seis_tm[n][r] - dobs[r][n]); per-block 1/2 sum res^2.
+__global__ void __launch_bounds__(256)
+    k_residual(const float *__restrict__ seis_tm, const float *__restrict__ dobs,
+               const float *__restrict__ adj, int nrec, int nt, float *__restrict__ res_tm,
+               double *__restrict__ partial) {
+  __shared__ float tile[TT][TT + 1];
+  __shared__ double red[256];
+  const int r0 = blockIdx.y * TT, n0 = blockIdx.x * TT;
+  const int tx = threadIdx.x, ty = threadIdx.y;  // 32 x 8
+  for (int j = ty; j < TT; j += 8) {
+    const int r = r0 + j, n = n0 + tx;
+    tile[j][tx] = (r < nrec && n < nt) ? dobs[(int64_t)r * nt + n] : 0.0f;
+  }
+  __syncthreads();
+  double acc = 0.0;
+  for (int j = ty; j < TT; j += 8) {
+    const int n = n0 + j, r = r0 + tx;
+    if (r < nrec && n < nt) {
+      const float res = seis_tm[(int64_t)n * nrec + r] - tile[tx][j];
+      res_tm[(int64_t)n * nrec + r] = adj[r] * res;
+      acc += 0.5 * (double)res * (double)res;
+    }
+  }
+  const int t = ty * TT + tx;
+  red[t] = acc;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (t < s) red[t] += red[t + s];
+    __syncthreads();
+  }
+  if (t == 0) partial[(int64_t)blockIdx.y * gridDim.x + blockIdx.x] = red[0];
+}
+
+__global__ void __launch_bounds__(256)
+    k_sum_partials(const double *__restrict__ partial, int n, double *misfit) {
+  __shared__ double red[256];
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < n; i += 256) acc += partial[i];
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) misfit[0] += red[0];
+}
+
+__global__ void __launch_bounds__(256)
+    k_transpose(const float *__restrict__ src_tm, float *__restrict__ dst_rm, int nrec, int nt) {
+  __shared__ float tile[TT][TT + 1];
+  const int r0 = blockIdx.x * TT, n0 = blockIdx.y * TT;
+  const int tx = threadIdx.x, ty = threadIdx.y;
+  for (int j = ty; j < TT; j += 8) {
+    const int n = n0 + j, r = r0 + tx;
+    tile[j][tx] = (r < nrec && n < nt) ? src_tm[(int64_t)n * nrec + r] : 0.0f;
+  }
+  __syncthreads();
+  for (int j = ty; j < TT; j += 8) {
+    const int r = r0 + j, n = n0 + tx;
+    if (r < nrec && n < nt) dst_rm[(int64_t)r * nt + n] = tile[tx][j];
+  }
+}
+
+// Padded range that folds into model index i along an axis of n cells.
+__device__ __forceinline__ void fold_range(int i, int n, int border, int &lo, int &hi) {
+  lo = (i == 0) ? 0 : i + border;
+  hi = (i == n - 1) ? n - 1 + 2 * border : i + border;
+}
+
+__global__ void __launch_bounds__(256)
+    k_grad_fold(const float *__restrict__ g, const float *__restrict__ k, int pitch, int pny,
+                int border, int mnx, int mny, int mnz, double dt, float *__restrict__ grad) {
+  const int64_t total = (int64_t)mnx * mny * mnz;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= total) return;
+  const int ix = (int)(i % mnx);
+  const int iy = (int)((i / mnx) % mny);
+  const int iz = (int)(i / ((int64_t)mnx * mny));
+  int x0, x1, y0, y1, z0, z1;
+  fold_range(ix, mnx, border, x0, x1);
+  fold_range(iy, mny, border, y0, y1);
+  fold_range(iz, mnz, border, z0, z1);
+  const int64_t plane = (int64_t)pitch * pny;
+  double s = 0.0;
+  for (int z = z0; z <= z1; ++z)
+    for (int y = y0; y <= y1; ++y)
+      for (int x = x0; x <= x1; ++x) s += g[(int64_t)z * plane + (int64_t)y * pitch + x];
+  const float kc = k[(int64_t)(iz + border) * plane + (int64_t)(iy + border) * pitch + ix + border];
+  const double v = sqrt((double)kc) / dt;
+  grad[i] += (float)(2.0 * s / v);
+}
+
+__global__ void __launch_bounds__(256) k_fill_zero(float *p, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = 0.0f;
+}
+
+}  // namespace
+
+hipError_t launch_forward_step(const StepGrid &g, const float *cur, const float *prev, float *out,
+                               const Source &src, int n, const RecTable *rec,
+                               const float *rec_scale, float *seis_tm, hipStream_t stream) {
+  dim3 block(64, 4, 1);
+  dim3 grid((g.nx + 63) / 64, (g.ny + 3) / 4, g.nz);
+  const bool vd = g.m2 != nullptr;
+  RecTable none{};
+  if (rec) {
+    if (vd)
+      hipLaunchKernelGGL((k_forward_naive<true, true>), grid, block, 0, stream, g, cur, prev, out,
+                         src, n, *rec, rec_scale, seis_tm);
+    else
+      hipLaunchKernelGGL((k_forward_naive<false, true>), grid, block, 0, stream, g, cur, prev, out,
+                         src, n, *rec, rec_scale, seis_tm);
+  } else {
+    if (vd)
+      hipLaunchKernelGGL((k_forward_naive<true, false>), grid, block, 0, stream, g, cur, prev,
+                         out, src, n, none, rec_scale, seis_tm);
+    else
+      hipLaunchKernelGGL((k_forward_naive<false, false>), grid, block, 0, stream, g, cur, prev,
+                         out, src, n, none, rec_scale, seis_tm);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_adjoint_step(const StepGrid &g, const float *cur, const float *prev, float *out,
+                               const RecTable &rec, const float *res_tm, int m,
+                               const float *wm, float *grad, float *illum, int border, int mnx,
+                               int mny, int mnz, hipStream_t stream) {
+  dim3 block(64, 4, 1);
+  dim3 grid((g.nx + 63) / 64, (g.ny + 3) / 4, g.nz);
+  const bool vd = g.m2 != nullptr;
+  if (vd) {
+    if (illum)
+      hipLaunchKernelGGL((k_adjoint_naive<true, true>), grid, block, 0, stream, g, cur, prev, out,
+                         rec, res_tm, m, wm, grad, illum, border, mnx, mny, mnz);
+    else
+      hipLaunchKernelGGL((k_adjoint_naive<true, false>), grid, block, 0, stream, g, cur, prev,
+                         out, rec, res_tm, m, wm, grad, illum, border, mnx, mny, mnz);
+  } else {
+    if (illum)
+      hipLaunchKernelGGL((k_adjoint_naive<false, true>), grid, block, 0, stream, g, cur, prev,
+                         out, rec, res_tm, m, wm, grad, illum, border, mnx, mny, mnz);
+    else
+      hipLaunchKernelGGL((k_adjoint_naive<false, false>), grid, block, 0, stream, g, cur, prev,
+                         out, rec, res_tm, m, wm, grad, illum, border, mnx, mny, mnz);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_precompute_k(const float *vel, int mnx, int mny, int mnz, int border, double dt,
+                               float *k, int pitch, int ny, int nz, float *partial_max,
+                               int n_partial, hipStream_t stream) {
+  hipLaunchKernelGGL(k_precompute_k, dim3(n_partial), dim3(256), 0, stream, vel, mnx, mny, mnz,
+                     border, dt, k, pitch, ny, nz, partial_max);
+  return hipGetLastError();
+}
+
+hipError_t launch_precompute_m2(const float *rho, int mnx, int mny, int mnz, int border,
+                                double idx2, double idy2, double idz2, float *m2, int pitch,
+                                int ny, int nz, float *sqrt_rho, float *partial_max,
+                                int n_partial, hipStream_t stream) {
+  hipLaunchKernelGGL(k_precompute_m2, dim3(n_partial), dim3(256), 0, stream, rho, mnx, mny, mnz,
+                     border, idx2, idy2, idz2, m2, pitch, ny, nz, sqrt_rho, partial_max);
+  return hipGetLastError();
+}
+
+hipError_t launch_shot_setup(const float *k, const float *sqrt_rho, int border, int mnx, int mny,
+                             int64_t src_idx, int src_model_idx, double dt2_over_h3,
+                             const int64_t *rec_idx, const int *rec_model_idx, int nrec,
+                             float *sigma, float *rec_scale, float *rec_adj, hipStream_t stream) {
+  (void)border;
+  (void)mnx;
+  (void)mny;
+  const int n = nrec > 1 ? nrec : 1;
+  hipLaunchKernelGGL(k_shot_setup, dim3((n + 255) / 256), dim3(256), 0, stream, k, sqrt_rho,
+                     src_idx, src_model_idx, dt2_over_h3, rec_idx, rec_model_idx, nrec, sigma,
+                     rec_scale, rec_adj);
+  return hipGetLastError();
+}
+
+int residual_partial_count(int nrec, int nt) {
+  return ((nt + TT - 1) / TT) * ((nrec + TT - 1) / TT);
+}
+
+hipError_t launch_residual(const float *seis_tm, const float *dobs, const float *rec_adj, int nrec,
+                           int nt, float *res_tm, double *partial, int *n_partial,
+                           hipStream_t stream) {
+  dim3 grid((nt + TT - 1) / TT, (nrec + TT - 1) / TT);
+  *n_partial = (int)(grid.x * grid.y);
+  hipLaunchKernelGGL(k_residual, grid, dim3(TT, 8), 0, stream, seis_tm, dobs, rec_adj, nrec, nt,
+                     res_tm, partial);
+  return hipGetLastError();
+}
+
+hipError_t launch_sum_partials(const double *partial, int n, double *misfit, hipStream_t stream) {
+  hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(256), 0, stream, partial, n, misfit);
+  return hipGetLastError();
+}
+
+hipError_t launch_transpose(const float *src_tm, float *dst_rm, int nrec, int nt,
+                            hipStream_t stream) {
+  dim3 grid((nrec + TT - 1) / TT, (nt + TT - 1) / TT);
+  hipLaunchKernelGGL(k_transpose, grid, dim3(TT, 8), 0, stream, src_tm, dst_rm, nrec, nt);
+  return hipGetLastError();
+}
+
+hipError_t launch_grad_fold(const float *g, const float *k, int pitch, int pny, int border,
+                            int mnx, int mny, int mnz, double dt, float *grad, hipStream_t stream) {
+  const int64_t total = (int64_t)mnx * mny * mnz;
+  hipLaunchKernelGGL(k_grad_fold, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, stream, g,
+                     k, pitch, pny, border, mnx, mny, mnz, dt, grad);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_zero(float *p, int64_t n, hipStream_t stream) {
+  if (n <= 0) return hipSuccess;
+  int64_t blocks = (n + 255) / 256;
+  if (blocks > 65536) blocks = 65536;
+  hipLaunchKernelGGL(k_fill_zero, dim3((unsigned)blocks), dim3(256), 0, stream, p, n);
+  return hipGetLastError();
+}
+
+}  // namespace wfd

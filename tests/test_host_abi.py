@@ -1,0 +1,142 @@
+"""Host-side logic of the C ABI, runnable without a GPU.
+
+* the library loads and exports every function that include/wfd.h declares;
+* position mapping and the stability ratio agree with the oracle;
+* the checkpoint schedule is valid and reaches the closed-form optimum.
+"""
+
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2502_12350_amd import _lib
+from paper_2502_12350_amd import api
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _header_functions():
+    text = open(os.path.join(ROOT, "include", "wfd.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(wfd_[a-z_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_function():
+    names = _header_functions()
+    assert len(names) >= 15
+    L = _lib.lib()
+    for n in names:
+        assert hasattr(L, n), f"{n} declared in wfd.h but not exported"
+    assert sorted(_lib.exported_symbols()) == names
+
+
+def test_error_paths_report_status_and_message():
+    with pytest.raises(_lib.WfdError) as e:
+        api.model_bytes(api.GridSpec(0, 4, 4, 10, 10, 10), False)
+    assert e.value.name == "WFD_E_ARG" and "model size" in str(e.value)
+    with pytest.raises(_lib.WfdError) as e:
+        api.model_bytes(api.GridSpec(4, 4, 4, 10, 10, 10, border=-1), False)
+    assert e.value.name == "WFD_E_ARG"
+    with pytest.raises(_lib.WfdError) as e:
+        api.checkpoint_plan(10, 0)
+    assert e.value.name == "WFD_E_ARG"
+    with pytest.raises(_lib.WfdError) as e:
+        api.map_position(api.GridSpec(4, 4, 4, 10, 10, 10), [45.0, 0.0, 0.0])
+    assert e.value.name == "WFD_E_RANGE"
+    with pytest.raises(_lib.WfdError) as e:
+        api.model_bytes(api.GridSpec(4, 4, 4, 10, 10, 10, dt=0.0), False)
+    assert e.value.name == "WFD_E_ARG"
+
+
+def test_model_bytes_scales_with_density_option():
+    g = api.GridSpec(30, 20, 10, 10, 10, 10, border=4)
+    cd = api.model_bytes(g, False)
+    vd = api.model_bytes(g, True)
+    Nz, Ny, Nx = g.padded_shape
+    vol = 64 * Ny * Nz * 4
+    assert cd >= vol and vd >= 2 * vol + 30 * 20 * 10 * 4
+
+
+def test_map_position_matches_oracle():
+    rng = np.random.default_rng(1)
+    g = api.GridSpec(37, 23, 19, 7.5, 10.0, 4.0, ox=-30.0, oy=100.0, oz=5.0, border=6)
+    og = oracle.Grid(**g.__dict__)
+    for _ in range(400):
+        xyz = [rng.uniform(-40, 250), rng.uniform(90, 330), rng.uniform(0, 85)]
+        # also exact half-way points
+        if rng.random() < 0.3:
+            xyz[0] = -30.0 + 7.5 * (rng.integers(0, 37) + 0.5)
+        try:
+            iz, iy, ix = oracle.node_index(og, xyz)
+            ok = True
+        except ValueError:
+            ok = False
+        if ok:
+            assert api.map_position(g, xyz) == (ix, iy, iz)
+        else:
+            with pytest.raises(_lib.WfdError):
+                api.map_position(g, xyz)
+
+
+def test_cfl_ratio_matches_oracle():
+    for h, dt, v, m2 in [((10, 10, 10), 1e-3, 2000, 0.0), ((5, 7, 9), 4e-4, 4500, 1e-3),
+                         ((10, 10, 10), 8.889e-4, 4500, -2e-3)]:
+        g = api.GridSpec(8, 8, 8, *h, dt=dt)
+        og = oracle.Grid(8, 8, 8, *h, dt=dt)
+        assert abs(api.cfl_ratio(g, v, m2) - oracle.cfl_ratio(og, v, m2)) <= 1e-14
+
+
+def _simulate(actions, nt, S):
+    cur = 0
+    slots = {}
+    visits = []
+    steps = 0
+    first_visit_seen = False
+    chain_end = 0
+    for op, a, b in actions:
+        stored = set(slots.values()) | {0}
+        if op == 0:
+            assert a == cur or a in stored, (op, a, b)
+            assert b > a
+            steps += b - a
+            if not first_visit_seen:
+                assert a == chain_end, "first sweep must be one contiguous chain"
+                chain_end = b
+            cur = b
+        elif op == 1:
+            assert a == cur and 0 <= b < S and b not in slots
+            slots[b] = a
+        elif op == 2:
+            assert a == cur or a in stored or a + 1 == cur
+            if not first_visit_seen:
+                assert chain_end == nt, "all data must be recorded before the first visit"
+            first_visit_seen = True
+            visits.append(a)
+        elif op == 3:
+            assert slots.get(b) == a
+            del slots[b]
+        else:
+            raise AssertionError(op)
+    assert visits == list(range(nt, 0, -1))
+    return steps
+
+
+@pytest.mark.parametrize("nt,S", [(1, 1), (2, 1), (7, 1), (10, 3), (50, 4), (200, 6),
+                                  (300, 299), (64, 64), (1200, 20), (2000, 130)])
+def test_checkpoint_plan_valid_and_optimal(nt, S):
+    actions, nsteps = api.checkpoint_plan(nt, S)
+    steps = _simulate(actions, nt, S)
+    assert steps == nsteps
+    # x_0 needs no slot, so S stored pairs reverse nt+1 states with S+1 snapshots
+    assert nsteps == oracle.forward_steps_closed_form(nt + 1, S + 1)
+
+
+def test_checkpoint_plan_counts_for_the_gradient_workload():
+    # 1200 steps with 20 stored pairs: 3327 forward steps instead of 1200
+    _, n = api.checkpoint_plan(1200, 20)
+    assert n == 3327
+    _, n_full = api.checkpoint_plan(1200, 1200)
+    assert n_full == 1200
