@@ -1,0 +1,247 @@
+#!/usr/bin/env python3
+"""Throughput of the acoustic FD hot path on one MI355X.
+
+One bench step = one full pass of the hot path for one shot on the
+variable-density 512^3 model with a 32-cell sponge (576^3 = 191,102,976
+padded points), 2000 time steps, 65,536 receivers:
+  model prep is done once (untimed); each step runs the forward sweep with
+  source injection and receiver recording, the misfit, the reverse sweep
+  (adjoint step fused with the imaging condition) with binomial
+  checkpointing of the forward states, and the gradient fold.
+
+value = padded points x (nt forward + nt adjoint updates) / step time, in
+Gpt/s (recomputation of checkpointed states is overhead, not counted).
+Per-kernel averages come from HIP events recorded around every launch on
+the library's stream during the timed region.
+
+Usage: python bench.py [--steps K] [--warmup W] [--gpus 1]
+"""
+
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import re
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+KERNEL_SRC = os.path.join(ROOT, "paper_2502_12350_amd", "csrc", "wfd_step.hip")
+
+
+def kernel_hash() -> str:
+    return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
+
+
+def committed_traffic(kernel: str):
+    """HBM bytes per launch of `kernel` from the committed counter summary, if it
+    was taken on the current kernel source."""
+    path = os.path.join(ROOT, "profiles", "hbm_traffic.md")
+    if not os.path.exists(path):
+        return None
+    pat = re.compile(r"^TRAFFIC kernel=(\S+) source=(\S+) bytes_per_launch=(\d+)")
+    for line in open(path):
+        m = pat.match(line.strip())
+        if m and m.group(1) == kernel and m.group(2) == kernel_hash():
+            return int(m.group(3))
+    return None
+
+
+def cpu_baseline(w, n_steps: int = 2):
+    """The FP64 oracle on a bounded sample of the same workload: forward and
+    adjoint(+imaging) steps on a 32-plane model crop with the same 32-cell
+    sponge (576 x 576 x 96 padded points), one process."""
+    import numpy as np
+    import oracle
+
+    z0 = w.nz // 2 - 16
+    crop = dict(w.grid_kwargs())
+    crop["nz"] = 32
+    g = oracle.Grid(**crop)
+    vel = w.vel[z0:z0 + 32].astype(np.float64)
+    rho = None if w.rho is None else w.rho[z0:z0 + 32].astype(np.float64)
+    c = oracle.coefficients(g, vel, rho)
+    rng = np.random.default_rng(0)
+    shape = g.padded_shape
+    f = [rng.standard_normal(shape) * 1e-6 for _ in range(4)]
+    gacc = np.zeros(shape)
+    t_f = t_a = 0.0
+    for _ in range(n_steps):
+        t0 = time.perf_counter()
+        f[1] = oracle.step(c, g, f[0], f[1])
+        t1 = time.perf_counter()
+        f[3] = oracle.step(c, g, f[2], f[3])
+        gacc += f[2] * (oracle.laplacian(f[0], g.h) - c.m2 * f[0])
+        t2 = time.perf_counter()
+        t_f += t1 - t0
+        t_a += t2 - t1
+        f = [f[1], f[0], f[3], f[2]]
+    pts = shape[0] * shape[1] * shape[2]
+    gpts = 2 * n_steps * pts / (t_f + t_a) / 1e9
+    return {"value": gpts, "unit": "Gpt/s", "cores": 1, "kind": "oracle",
+            "sample": f"{n_steps} forward + {n_steps} adjoint/imaging FP64 numpy steps on a "
+                      f"{shape[2]}x{shape[1]}x{shape[0]} padded slab (32-plane model crop, same "
+                      f"32-cell sponge), single process",
+            "host_cpus": os.cpu_count(),
+            "seconds": round(t_f + t_a, 2)}
+
+
+def copy_probe(gib: float = 4.0, reps: int = 5):
+    """A plain device copy of known size (counter calibration)."""
+    import torch
+    n = int(gib * (1 << 30)) // 4
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(reps):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / reps
+    print(json.dumps({"copy_bytes_read": 4 * n, "copy_bytes_written": 4 * n,
+                      "copy_GBps": 8 * n / dt / 1e9}), flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="c2")
+    ap.add_argument("--nt", type=int, default=0, help="override the number of time steps")
+    ap.add_argument("--snapshots", type=int, default=96)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus > 1 or world > 1:
+        print("bench.py: this build measures one GPU only (one shot per GPU; the multi-GPU "
+              "design shards shots and all-reduces the gradient, see DESIGN.md) -- "
+              f"--gpus {args.gpus} is not supported", file=sys.stderr, flush=True)
+        sys.exit(2)
+    if args.copy_probe:
+        copy_probe()
+        return
+
+    import numpy as np
+    import torch
+    import seisgen
+    from paper_2502_12350_amd import GridSpec, Propagator, K_FORWARD, K_ADJOINT, K_OTHER
+
+    t_setup = time.perf_counter()
+    w = seisgen.workload(args.workload)
+    if args.nt:
+        w.nt = args.nt
+        w.wavelet = w.wavelet[:args.nt]
+    grid = GridSpec(**w.grid_kwargs())
+    dev = torch.device("cuda", 0)
+    vel = torch.from_numpy(w.vel).to(dev)
+    rho = None if w.rho is None else torch.from_numpy(w.rho).to(dev)
+    wav = torch.from_numpy(w.wavelet).to(dev)
+    nrec = len(w.receivers)
+    print(f"[bench] workload {w.name}: model {w.nx}x{w.ny}x{w.nz}, padded "
+          f"{w.padded_shape[2]}x{w.padded_shape[1]}x{w.padded_shape[0]}, nt {w.nt}, "
+          f"nrec {nrec}, density {'variable' if rho is not None else 'constant'}",
+          file=sys.stderr, flush=True)
+
+    # observed data: forward on a perturbed ("true") model
+    true = seisgen.blob_anomalies(w.vel, seed=2503, n_blobs=8, amp=0.05, sigma_cells=(10, 30),
+                                  centre_lo=(64, 64, 64), centre_hi=(w.nx - 64, w.ny - 64,
+                                                                      w.nz - 64))
+    P = Propagator(0)
+    P.set_model(grid, torch.from_numpy(true).to(dev), rho)
+    dobs = P.forward(wav, w.sources[0], w.receivers)
+    torch.cuda.synchronize()
+    P.release_workspace()
+    P.set_model(grid, vel, rho)
+    del true
+    ckpt = ("revolve", min(args.snapshots, w.nt))
+    grad = torch.zeros((w.nz, w.ny, w.nx), dtype=torch.float32, device=dev)
+    misfit = torch.zeros((), dtype=torch.float64, device=dev)
+    print(f"[bench] setup {time.perf_counter() - t_setup:.1f}s; workspace "
+          f"{P.workspace_bytes(nrec, ckpt) / 2**30:.1f} GiB", file=sys.stderr, flush=True)
+
+    for i in range(args.warmup):
+        P.gradient(wav, w.sources[0], w.receivers, dobs, ckpt=ckpt, grad=grad, misfit=misfit)
+        torch.cuda.synchronize()
+        print(f"[bench] warmup {i + 1}/{args.warmup} done", file=sys.stderr, flush=True)
+
+    P.set_profiling(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        P.gradient(wav, w.sources[0], w.receivers, dobs, ckpt=ckpt, grad=grad, misfit=misfit)
+        torch.cuda.synchronize()
+        print(f"[bench] step {i + 1}/{args.steps} done", file=sys.stderr, flush=True)
+    t1 = time.perf_counter()
+    nf, msf = P.kernel_stats(K_FORWARD)
+    na, msa = P.kernel_stats(K_ADJOINT)
+    no, mso = P.kernel_stats(K_OTHER)
+    P.set_profiling(False)
+
+    pts = w.padded_points
+    vd = rho is not None
+    ms_step = (t1 - t0) * 1e3 / args.steps
+    value = pts * 2.0 * w.nt / (ms_step * 1e-3) / 1e9
+    kern = {
+        "fd_step": {"launches": nf, "avg_us": 1e3 * msf / max(nf, 1),
+                    "bytes_per_point": 20 if vd else 16, "share": msf / (msf + msa + mso)},
+        "adjoint_imaging": {"launches": na, "avg_us": 1e3 * msa / max(na, 1),
+                            "bytes_per_point": 32 if vd else 28,
+                            "share": msa / (msf + msa + mso)},
+    }
+    for k in kern.values():
+        k["gpts"] = pts / (k["avg_us"] * 1e-6) / 1e9
+        k["GBps"] = k["gpts"] * k["bytes_per_point"]
+        k["hbm_frac"] = k["GBps"] / HBM_PEAK_GBS
+    dom_name = max(kern, key=lambda n: kern[n]["share"])
+    dom = kern[dom_name]
+    lib_kernel = {"fd_step": "k_forward", "adjoint_imaging": "k_adjoint"}[dom_name]
+    traffic = committed_traffic(lib_kernel)
+    out = {
+        "metric": "Gpt/s & %HBM peak (fwd/adjoint 8th-order stencil); FWI misfit cut per GPU-s",
+        "value": round(value, 3),
+        "unit": "Gpt/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"one-shot forward + adjoint gradient pass, variable density, "
+                               f"{w.nx}x{w.ny}x{w.nz} model + {w.border}-cell sponge, "
+                               f"{w.nt} steps, {nrec} receivers",
+                   "padded_points": pts, "nt": w.nt, "nrec": nrec,
+                   "checkpoint": f"binomial, {ckpt[1]} stored pairs",
+                   "parallelism": "1 GPU, one shot"},
+        "roofline": {"bound": "hbm", "achieved": round(dom["GBps"], 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(dom["hbm_frac"], 4),
+                     "traffic": traffic, "kernel": dom_name,
+                     "algorithmic_bytes_per_launch": dom["bytes_per_point"] * pts},
+        "kernels": {n: {k: (round(v, 4) if isinstance(v, float) else v) for k, v in d.items()}
+                    for n, d in kern.items()},
+        "other_ms_per_step": round(mso / args.steps, 3),
+        "misfit": float(misfit.item()) / (args.warmup + args.steps),
+        "kernel_source": kernel_hash(),
+    }
+    if not args.no_cpu_baseline:
+        print("[bench] timing the CPU oracle sample", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(w)
+    else:
+        out["cpu_baseline"] = None
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

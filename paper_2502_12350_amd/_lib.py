@@ -10,7 +10,8 @@ import ctypes as C
 import os
 
 _PKG = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_PKG, "libwfd.so")
+# WFD_LIB may name another build of the same library (used to compare builds)
+LIB_PATH = os.environ.get("WFD_LIB") or os.path.join(_PKG, "libwfd.so")
 
 WFD_OK = 0
 STATUS_NAMES = {0: "WFD_OK", -1: "WFD_E_ARG", -2: "WFD_E_CFL", -3: "WFD_E_RANGE",

@@ -687,32 +687,41 @@ wfd_status wfd_gradient(wfd_ctx *c, const float *wavelet, const double src_xyz[3
     std::vector<int32_t> plan;
     int64_t nsteps = 0;
     wfd::build_checkpoint_plan(nt, (int32_t)nsnap, plan, nsteps);
+    // Zero-copy checkpointing: W1, W2 and the 2*nsnap store volumes form one
+    // pool.  Storing a state pins the two buffers the current state already
+    // holds; advancing from a pinned state writes into free buffers, and a
+    // step updates in place only over a buffer nobody has pinned.
+    std::vector<float *> buf;
+    buf.push_back(w.W1);
+    buf.push_back(w.W2);
+    for (int64_t i = 0; i < 2 * nsnap; ++i) buf.push_back(w.store + (size_t)i * (size_t)c->vol);
+    std::vector<int> pins(buf.size(), 0);
     struct Slot {
-      int state = -1;
-      float *a = nullptr, *b = nullptr;
+      int state = -1, a = -1, b = -1;  // state index, buffers of w^state and w^(state-1)
     };
     std::vector<Slot> slots((size_t)nsnap);
-    for (int64_t i = 0; i < nsnap; ++i) {
-      slots[i].a = w.store + (size_t)(2 * i) * (size_t)c->vol;
-      slots[i].b = w.store + (size_t)(2 * i + 1) * (size_t)c->vol;
-    }
-    int cur_state = 0;  // W1/W2 hold x_0 = 0
-    float *cur = w.W1, *prev = w.W2;
-    int reached = 0;    // steps whose data has been recorded
+    int cur_state = -1, cur = -1, prev = -1;  // working state and its buffers
+    int reached = 0;                         // steps whose data has been recorded
     auto slot_of = [&](int state) -> Slot * {
       for (auto &sl : slots)
         if (sl.state == state) return &sl;
       return nullptr;
     };
+    auto free_buffer = [&](int not1, int not2) -> int {
+      for (size_t i = 0; i < buf.size(); ++i)
+        if (pins[i] == 0 && (int)i != not1 && (int)i != not2) return (int)i;
+      return -1;
+    };
     for (size_t i = 0; i + 3 <= plan.size(); i += 3) {
       const int op = plan[i], a = plan[i + 1], b = plan[i + 2];
       if (op == wfd::kAdvance) {
         if (cur_state != a) {
-          if (a == 0) {
-            if ((s = zero(c, w.W1, c->vol)) != WFD_OK) return s;
-            if ((s = zero(c, w.W2, c->vol)) != WFD_OK) return s;
-            cur = w.W1;
-            prev = w.W2;
+          if (a == 0) {  // the zero initial state, in two scratch buffers
+            cur = free_buffer(-1, -1);
+            prev = free_buffer(cur, -1);
+            if (cur < 0 || prev < 0) return fail(WFD_E_STATE, "checkpoint pool exhausted");
+            if ((s = zero(c, buf[cur], c->vol)) != WFD_OK) return s;
+            if ((s = zero(c, buf[prev], c->vol)) != WFD_OK) return s;
           } else {
             Slot *sl = slot_of(a);
             if (!sl) return fail(WFD_E_STATE, "checkpoint plan: state %d not stored", a);
@@ -721,12 +730,9 @@ wfd_status wfd_gradient(wfd_ctx *c, const float *wavelet, const double src_xyz[3
           }
         }
         for (int n = a; n < b; ++n) {
-          float *out;
-          if (prev == w.W1 || prev == w.W2)
-            out = prev;
-          else
-            out = (cur == w.W1) ? w.W2 : w.W1;
-          if ((s = fwd(cur, prev, out, n, n >= reached)) != WFD_OK) return s;
+          int out = pins[prev] == 0 ? prev : free_buffer(cur, prev);
+          if (out < 0) return fail(WFD_E_STATE, "checkpoint pool exhausted");
+          if ((s = fwd(buf[cur], buf[prev], buf[out], n, n >= reached)) != WFD_OK) return s;
           if (n >= reached) reached = n + 1;
           prev = cur;
           cur = out;
@@ -735,24 +741,27 @@ wfd_status wfd_gradient(wfd_ctx *c, const float *wavelet, const double src_xyz[3
       } else if (op == wfd::kStore) {
         if (cur_state != a) return fail(WFD_E_STATE, "checkpoint plan: store of non-current state");
         Slot &sl = slots[(size_t)b];
-        const size_t bytes = (size_t)c->vol * sizeof(float);
-        Timed t(c, WFD_K_OTHER);
-        HIP_TRY(hipMemcpyAsync(sl.a, cur, bytes, hipMemcpyDeviceToDevice, c->stream));
-        HIP_TRY(hipMemcpyAsync(sl.b, prev, bytes, hipMemcpyDeviceToDevice, c->stream));
         sl.state = a;
+        sl.a = cur;
+        sl.b = prev;
+        ++pins[cur];
+        ++pins[prev];
       } else if (op == wfd::kVisit) {
         if ((s = residual()) != WFD_OK) return s;
         const float *wm = nullptr;
         if (cur_state == a)
-          wm = cur;
+          wm = buf[cur];
         else if (Slot *sl = slot_of(a))
-          wm = sl->a;
+          wm = buf[sl->a];
         else if (cur_state == a + 1)
-          wm = prev;
+          wm = buf[prev];
         if (!wm) return fail(WFD_E_STATE, "checkpoint plan: state %d unavailable", a);
         if ((s = adjoint(a, wm)) != WFD_OK) return s;
       } else if (op == wfd::kFree) {
-        slots[(size_t)b].state = -1;
+        Slot &sl = slots[(size_t)b];
+        --pins[sl.a];
+        --pins[sl.b];
+        sl = Slot{};
       }
     }
   }

@@ -1,116 +1,12 @@
-// HIP kernels for gfx950 (MI355X): the acoustic leapfrog step with the
-// eighth-order 25-point star (arXiv 2502.12350, §2.1), fused source
-// injection / receiver recording, the adjoint step fused with the
-// cross-correlation imaging condition (Alg. 3), model preparation, misfit
-// and gradient finishing.
-//
-// Step kernels march in z: each thread owns RY points of one (x, y) column
-// of a 64 x (BY*RY) tile, keeps the nine z-neighbours of each in a register
-// queue, and stages the current plane (plus a 4-cell x/y halo) in LDS so
-// that the x and y neighbours are read from LDS.  Every field is read once
-// and written once per step from HBM (x-fastest, 256-byte rows).
+// HIP kernels for gfx950 (MI355X) around the step kernels (wfd_step.hip):
+// model preparation (Eq. 1 coefficients, in FP64 where it matters), per-shot
+// source / receiver scales, the misfit with a deterministic FP64 reduction
+// (Alg. 3, SeismicData::Misfit), seismogram transposes and the gradient
+// finish (chain rule to dJ/dv with the sponge fold).
 #include "wfd_internal.h"
 
 namespace wfd {
 namespace {
-
-// Eighth-order central weights of d^2/dx^2.
-constexpr float W0 = -205.0f / 72.0f;
-constexpr float W1 = 8.0f / 5.0f;
-constexpr float W2 = -1.0f / 5.0f;
-constexpr float W3 = 8.0f / 315.0f;
-constexpr float W4 = -1.0f / 560.0f;
-
-__device__ __forceinline__ float ld_or_zero(const float *f, const StepGrid &g, int x, int y,
-                                            int z) {
-  if (x < 0 || x >= g.nx || y < 0 || y >= g.ny || z < 0 || z >= g.nz) return 0.0f;
-  return f[(int64_t)z * g.plane + (int64_t)y * g.pitch + x];
-}
-
-// 25-point Laplacian with zero cells outside the padded grid.
-__device__ __forceinline__ float lap_point(const float *f, const StepGrid &g, int x, int y, int z,
-                                           float c) {
-  float lx = W0 * c + W1 * (ld_or_zero(f, g, x + 1, y, z) + ld_or_zero(f, g, x - 1, y, z)) +
-             W2 * (ld_or_zero(f, g, x + 2, y, z) + ld_or_zero(f, g, x - 2, y, z)) +
-             W3 * (ld_or_zero(f, g, x + 3, y, z) + ld_or_zero(f, g, x - 3, y, z)) +
-             W4 * (ld_or_zero(f, g, x + 4, y, z) + ld_or_zero(f, g, x - 4, y, z));
-  float ly = W0 * c + W1 * (ld_or_zero(f, g, x, y + 1, z) + ld_or_zero(f, g, x, y - 1, z)) +
-             W2 * (ld_or_zero(f, g, x, y + 2, z) + ld_or_zero(f, g, x, y - 2, z)) +
-             W3 * (ld_or_zero(f, g, x, y + 3, z) + ld_or_zero(f, g, x, y - 3, z)) +
-             W4 * (ld_or_zero(f, g, x, y + 4, z) + ld_or_zero(f, g, x, y - 4, z));
-  float lz = W0 * c + W1 * (ld_or_zero(f, g, x, y, z + 1) + ld_or_zero(f, g, x, y, z - 1)) +
-             W2 * (ld_or_zero(f, g, x, y, z + 2) + ld_or_zero(f, g, x, y, z - 2)) +
-             W3 * (ld_or_zero(f, g, x, y, z + 3) + ld_or_zero(f, g, x, y, z - 3)) +
-             W4 * (ld_or_zero(f, g, x, y, z + 4) + ld_or_zero(f, g, x, y, z - 4));
-  return g.cx * lx + g.cy * ly + g.cz * lz;
-}
-
-template <bool VD, bool GATHER>
-__global__ void __launch_bounds__(256)
-    k_forward_naive(StepGrid g, const float *__restrict__ cur, const float *prev, float *out,
-                    Source src, int n, RecTable rec, const float *__restrict__ rec_scale,
-                    float *__restrict__ seis_tm) {
-  const int x = blockIdx.x * blockDim.x + threadIdx.x;
-  const int y = blockIdx.y * blockDim.y + threadIdx.y;
-  const int z = blockIdx.z;
-  if (x >= g.nx || y >= g.ny) return;
-  const int64_t p = (int64_t)z * g.plane + (int64_t)y * g.pitch + x;
-  const float c = cur[p];
-  const float lap = lap_point(cur, g, x, y, z, c);
-  const float kk = g.k[p];
-  float acc = VD ? 2.0f * c + kk * (lap - g.m2[p] * c) : 2.0f * c + kk * lap;
-  if (p == src.idx) acc += src.sigma[0] * src.wavelet[n];
-  const float G = g.gx[x] * g.gy[y] * g.gz[z];
-  const float o = G * (acc - G * prev[p]);
-  out[p] = o;
-  if (GATHER) {
-    const int col = y * g.nx + x;
-    for (int e = rec.col_start[col]; e < rec.col_start[col + 1]; ++e) {
-      if (rec.ent_z[e] != z) continue;
-      for (int q = rec.ent_rp[e]; q < rec.ent_rp[e + 1]; ++q) {
-        const int r = rec.perm[q];
-        seis_tm[(int64_t)n * rec.nrec + r] = rec_scale[r] * o;
-      }
-    }
-  }
-}
-
-template <bool VD, bool ILLUM>
-__global__ void __launch_bounds__(256)
-    k_adjoint_naive(StepGrid g, const float *__restrict__ cur, const float *prev, float *out,
-                    RecTable rec, const float *__restrict__ res_tm, int m,
-                    const float *__restrict__ wm, float *__restrict__ grad,
-                    float *__restrict__ illum, int border, int mnx, int mny, int mnz) {
-  const int x = blockIdx.x * blockDim.x + threadIdx.x;
-  const int y = blockIdx.y * blockDim.y + threadIdx.y;
-  const int z = blockIdx.z;
-  if (x >= g.nx || y >= g.ny) return;
-  const int64_t p = (int64_t)z * g.plane + (int64_t)y * g.pitch + x;
-  const float c = cur[p];
-  const float lap = lap_point(cur, g, x, y, z, c);
-  const float kk = g.k[p];
-  const float mm = VD ? g.m2[p] : 0.0f;
-  float acc = VD ? 2.0f * c + kk * (lap - mm * c) : 2.0f * c + kk * lap;
-  const int col = y * g.nx + x;
-  for (int e = rec.col_start[col]; e < rec.col_start[col + 1]; ++e) {
-    if (rec.ent_z[e] != z) continue;
-    float s = 0.0f;
-    for (int q = rec.ent_rp[e]; q < rec.ent_rp[e + 1]; ++q)
-      s += res_tm[(int64_t)(m - 1) * rec.nrec + rec.perm[q]];
-    acc += s;
-  }
-  const float G = g.gx[x] * g.gy[y] * g.gz[z];
-  out[p] = G * (acc - G * prev[p]);
-  // imaging: g += psi^{m+1} (L w^m - m^2 w^m)
-  const float w = wm[p];
-  const float lw = lap_point(wm, g, x, y, z, w);
-  grad[p] += c * (VD ? lw - mm * w : lw);
-  if (ILLUM) {
-    const int ix = x - border, iy = y - border, iz = z - border;
-    if (ix >= 0 && ix < mnx && iy >= 0 && iy < mny && iz >= 0 && iz < mnz)
-      illum[((int64_t)iz * mny + iy) * mnx + ix] += w * w;
-  }
-}
 
 __device__ __forceinline__ int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
 
@@ -309,56 +205,6 @@ __global__ void __launch_bounds__(256) k_fill_zero(float *p, int64_t n) {
 }
 
 }  // namespace
-
-hipError_t launch_forward_step(const StepGrid &g, const float *cur, const float *prev, float *out,
-                               const Source &src, int n, const RecTable *rec,
-                               const float *rec_scale, float *seis_tm, hipStream_t stream) {
-  dim3 block(64, 4, 1);
-  dim3 grid((g.nx + 63) / 64, (g.ny + 3) / 4, g.nz);
-  const bool vd = g.m2 != nullptr;
-  RecTable none{};
-  if (rec) {
-    if (vd)
-      hipLaunchKernelGGL((k_forward_naive<true, true>), grid, block, 0, stream, g, cur, prev, out,
-                         src, n, *rec, rec_scale, seis_tm);
-    else
-      hipLaunchKernelGGL((k_forward_naive<false, true>), grid, block, 0, stream, g, cur, prev, out,
-                         src, n, *rec, rec_scale, seis_tm);
-  } else {
-    if (vd)
-      hipLaunchKernelGGL((k_forward_naive<true, false>), grid, block, 0, stream, g, cur, prev,
-                         out, src, n, none, rec_scale, seis_tm);
-    else
-      hipLaunchKernelGGL((k_forward_naive<false, false>), grid, block, 0, stream, g, cur, prev,
-                         out, src, n, none, rec_scale, seis_tm);
-  }
-  return hipGetLastError();
-}
-
-hipError_t launch_adjoint_step(const StepGrid &g, const float *cur, const float *prev, float *out,
-                               const RecTable &rec, const float *res_tm, int m,
-                               const float *wm, float *grad, float *illum, int border, int mnx,
-                               int mny, int mnz, hipStream_t stream) {
-  dim3 block(64, 4, 1);
-  dim3 grid((g.nx + 63) / 64, (g.ny + 3) / 4, g.nz);
-  const bool vd = g.m2 != nullptr;
-  if (vd) {
-    if (illum)
-      hipLaunchKernelGGL((k_adjoint_naive<true, true>), grid, block, 0, stream, g, cur, prev, out,
-                         rec, res_tm, m, wm, grad, illum, border, mnx, mny, mnz);
-    else
-      hipLaunchKernelGGL((k_adjoint_naive<true, false>), grid, block, 0, stream, g, cur, prev,
-                         out, rec, res_tm, m, wm, grad, illum, border, mnx, mny, mnz);
-  } else {
-    if (illum)
-      hipLaunchKernelGGL((k_adjoint_naive<false, true>), grid, block, 0, stream, g, cur, prev,
-                         out, rec, res_tm, m, wm, grad, illum, border, mnx, mny, mnz);
-    else
-      hipLaunchKernelGGL((k_adjoint_naive<false, false>), grid, block, 0, stream, g, cur, prev,
-                         out, rec, res_tm, m, wm, grad, illum, border, mnx, mny, mnz);
-  }
-  return hipGetLastError();
-}
 
 hipError_t launch_precompute_k(const float *vel, int mnx, int mny, int mnz, int border, double dt,
                                float *k, int pitch, int ny, int nz, float *partial_max,

@@ -1,0 +1,526 @@
+// Leapfrog step kernels for gfx950 (MI355X): the eighth-order 25-point star
+// (arXiv 2502.12350, §2.1) in a z-marching, LDS-tiled form.
+//
+// A block of 4 wavefronts owns a 64 x TY column tile (TY = 4 * RY) of the
+// padded grid and a chunk of z planes.  Lane = x, so every global access is
+// a 256-byte row per wavefront.  Each thread keeps, for each of its RY rows,
+// the nine z-neighbours of the current point in a register queue; the
+// current plane with a 4-cell x/y halo is staged in LDS (double-buffered:
+// one barrier per plane).  The next plane's queue entries and halo values
+// are fetched one iteration ahead.  Blocks are mapped XCD-aware: the
+// dispatcher places block b on XCD b mod 8, so each XCD receives a
+// contiguous range of tiles and neighbouring tiles share halos in one L2.
+//
+// HBM traffic per point: forward 16 B (constant density) / 20 B (variable
+// density); adjoint + imaging 28 B / 32 B (+ 8 B with illumination).
+#include <climits>
+#include <cstdlib>
+
+#include "wfd_internal.h"
+
+namespace wfd {
+namespace {
+
+constexpr float W0 = -205.0f / 72.0f;
+constexpr float W1 = 8.0f / 5.0f;
+constexpr float W2 = -1.0f / 5.0f;
+constexpr float W3 = 8.0f / 315.0f;
+constexpr float W4 = -1.0f / 560.0f;
+
+constexpr int TX = 64;     // tile width = one wavefront
+constexpr int NWAVE = 4;   // wavefronts per block
+constexpr int NTHREADS = TX * NWAVE;
+
+struct TileMap {
+  int tiles_x, tiles_y, nchunks, zc, nblocks;
+};
+
+template <int RY>
+struct Tile {
+  static constexpr int TY = NWAVE * RY;
+  static constexpr int LX = TX + 8;
+  static constexpr int LY = TY + 8;
+  static constexpr int NHALO = 8 * TX + 8 * TY;  // y-halo rows + x-halo columns
+  static constexpr int HPT = (NHALO + NTHREADS - 1) / NTHREADS;
+};
+
+// Block -> (tile x, tile y, z chunk).  Logical tiles are numbered x fastest,
+// then y, then z chunk; XCD k (= blockIdx mod 8) gets one contiguous range.
+__device__ __forceinline__ void tile_of(const TileMap &m, int &tx, int &ty, int &tz) {
+  const int b = blockIdx.x, nb = m.nblocks;
+  const int per = nb / 8, rem = nb % 8;
+  const int xcd = b % 8, slot = b / 8;
+  const int logical =
+      xcd < rem ? xcd * (per + 1) + slot : rem * (per + 1) + (xcd - rem) * per + slot;
+  tx = logical % m.tiles_x;
+  const int r = logical / m.tiles_x;
+  ty = r % m.tiles_y;
+  tz = r / m.tiles_y;
+}
+
+// Halo element h of a tile plane: global (gx, gy) and its LDS row / column.
+template <int RY>
+__device__ __forceinline__ void halo_slot(int h, int x0, int y0, int &gx, int &gy, int &lrow,
+                                          int &lcol) {
+  constexpr int TY = Tile<RY>::TY;
+  if (h < 8 * TX) {  // four rows above and four below the tile
+    const int r = h / TX, col = h % TX;
+    gx = x0 + col;
+    lcol = 4 + col;
+    if (r < 4) {
+      gy = y0 - 4 + r;
+      lrow = r;
+    } else {
+      gy = y0 + TY + (r - 4);
+      lrow = TY + r;
+    }
+  } else {  // four columns left and four right of each tile row
+    const int hh = h - 8 * TX;
+    const int row = hh / 8, c = hh % 8;
+    gy = y0 + row;
+    lrow = 4 + row;
+    if (c < 4) {
+      gx = x0 - 4 + c;
+      lcol = c;
+    } else {
+      gx = x0 + TX + (c - 4);
+      lcol = TX + c;
+    }
+  }
+}
+
+// Single-use streams (previous state, coefficients, gradient) bypass the
+// cache's normal retention so that L2 keeps the stenciled planes.
+__device__ __forceinline__ float ld_stream(const float *f, const StepGrid &g, int z, uint32_t o,
+                                           bool ok) {
+  return ok ? __builtin_nontemporal_load(f + (int64_t)z * g.plane + o) : 0.0f;
+}
+__device__ __forceinline__ void st_stream(float *f, int64_t p, float v) {
+  __builtin_nontemporal_store(v, f + p);
+}
+
+// Per-thread view of one stenciled field: register queue + halo staging.
+template <int RY>
+struct Marcher {
+  using T = Tile<RY>;
+  float q[RY][9];   // planes z-4 .. z+4 of the thread's RY points
+  float nxt[RY];    // plane z+5 (in flight)
+  float hv[T::HPT]; // halo of the plane written to LDS next
+
+  __device__ __forceinline__ static float ld(const float *f, const StepGrid &g, int z, uint32_t o,
+                                             bool ok) {
+    return (ok && z >= 0 && z < g.nz) ? f[(int64_t)z * g.plane + o] : 0.0f;
+  }
+  __device__ __forceinline__ void prime(const float *f, const StepGrid &g, int z0,
+                                        const uint32_t *off, const bool *in,
+                                        const uint32_t *hoff, const bool *hin) {
+#pragma unroll
+    for (int j = 0; j < RY; ++j)
+#pragma unroll
+      for (int i = 0; i < 9; ++i) q[j][i] = ld(f, g, z0 - 4 + i, off[j], in[j]);
+#pragma unroll
+    for (int i = 0; i < T::HPT; ++i) hv[i] = ld(f, g, z0, hoff[i], hin[i]);
+  }
+  __device__ __forceinline__ void stage(float (*s)[T::LX], int wave, int lane,
+                                        const int *hslot) {
+#pragma unroll
+    for (int j = 0; j < RY; ++j) s[4 + wave * RY + j][4 + lane] = q[j][4];
+#pragma unroll
+    for (int i = 0; i < T::HPT; ++i)
+      if (hslot[i] >= 0) (&s[0][0])[hslot[i]] = hv[i];
+  }
+  __device__ __forceinline__ void fetch(const float *f, const StepGrid &g, int z,
+                                        const uint32_t *off, const bool *in,
+                                        const uint32_t *hoff, const bool *hin) {
+#pragma unroll
+    for (int j = 0; j < RY; ++j) nxt[j] = ld(f, g, z + 5, off[j], in[j]);
+#pragma unroll
+    for (int i = 0; i < T::HPT; ++i) hv[i] = ld(f, g, z + 1, hoff[i], hin[i]);
+  }
+  __device__ __forceinline__ void shift() {
+#pragma unroll
+    for (int j = 0; j < RY; ++j) {
+#pragma unroll
+      for (int i = 0; i < 8; ++i) q[j][i] = q[j][i + 1];
+      q[j][8] = nxt[j];
+    }
+  }
+  // Sum of the x, y and z second differences (before 1/h^2 weights) of row j.
+  template <int J>
+  __device__ __forceinline__ void diffs(const float (*s)[T::LX], int wave, int lane, float &sx,
+                                        float &sy, float &sz) const {
+    const int ly = 4 + wave * RY + J, lx = 4 + lane;
+    const float *row = s[ly];
+    sx = W1 * (row[lx - 1] + row[lx + 1]) + W2 * (row[lx - 2] + row[lx + 2]) +
+         W3 * (row[lx - 3] + row[lx + 3]) + W4 * (row[lx - 4] + row[lx + 4]);
+    float up[4], dn[4];
+#pragma unroll
+    for (int k = 1; k <= 4; ++k) {
+      up[k - 1] = (J - k >= 0) ? q[(J - k >= 0) ? J - k : 0][4] : s[ly - k][lx];
+      dn[k - 1] = (J + k < RY) ? q[(J + k < RY) ? J + k : 0][4] : s[ly + k][lx];
+    }
+    sy = W1 * (up[0] + dn[0]) + W2 * (up[1] + dn[1]) + W3 * (up[2] + dn[2]) +
+         W4 * (up[3] + dn[3]);
+    sz = W1 * (q[J][3] + q[J][5]) + W2 * (q[J][2] + q[J][6]) + W3 * (q[J][1] + q[J][7]) +
+         W4 * (q[J][0] + q[J][8]);
+  }
+};
+
+// Common per-thread tile geometry.
+template <int RY>
+struct Geo {
+  using T = Tile<RY>;
+  int lane, wave, x0, y0, x, z0, z1;
+  bool in[RY];
+  uint32_t off[RY];
+  int yv[RY];
+  uint32_t hoff[T::HPT];
+  bool hin[T::HPT];
+  int hslot[T::HPT];
+
+  __device__ __forceinline__ bool init(const StepGrid &g, const TileMap &map) {
+    int tx, ty, tz;
+    tile_of(map, tx, ty, tz);
+    z0 = tz * map.zc;
+    z1 = min(z0 + map.zc, g.nz);
+    lane = threadIdx.x % TX;
+    wave = threadIdx.x / TX;
+    x0 = tx * TX;
+    y0 = ty * T::TY;
+    x = x0 + lane;
+#pragma unroll
+    for (int j = 0; j < RY; ++j) {
+      yv[j] = y0 + wave * RY + j;
+      in[j] = x < g.nx && yv[j] < g.ny;
+      off[j] = in[j] ? (uint32_t)yv[j] * (uint32_t)g.pitch + (uint32_t)x : 0u;
+    }
+#pragma unroll
+    for (int i = 0; i < T::HPT; ++i) {
+      const int h = threadIdx.x + i * NTHREADS;
+      if (h < T::NHALO) {
+        int gx, gy, lrow, lcol;
+        halo_slot<RY>(h, x0, y0, gx, gy, lrow, lcol);
+        hin[i] = gx >= 0 && gx < g.nx && gy >= 0 && gy < g.ny;
+        hoff[i] = hin[i] ? (uint32_t)gy * (uint32_t)g.pitch + (uint32_t)gx : 0u;
+        hslot[i] = lrow * T::LX + lcol;
+      } else {
+        hin[i] = false;
+        hoff[i] = 0u;
+        hslot[i] = -1;
+      }
+    }
+    return z0 < g.nz;
+  }
+};
+
+// Receiver entries of one column, walked in z order.
+struct ColCursor {
+  int e, ee, ez;
+  __device__ __forceinline__ void init(const RecTable &rec, int col, int z0, bool ok) {
+    e = ee = 0;
+    ez = INT_MAX;
+    if (!ok) return;
+    e = rec.col_start[col];
+    ee = rec.col_start[col + 1];
+    while (e < ee && rec.ent_z[e] < z0) ++e;
+    ez = e < ee ? rec.ent_z[e] : INT_MAX;
+  }
+  __device__ __forceinline__ void advance(const RecTable &rec) {
+    ++e;
+    ez = e < ee ? rec.ent_z[e] : INT_MAX;
+  }
+};
+
+template <int RY, bool VD, bool GATHER>
+__global__ void __launch_bounds__(NTHREADS)
+    k_forward(StepGrid g, const float *__restrict__ cur, const float *prev, float *out,
+              Source src, int n, RecTable rec, const float *__restrict__ rec_scale,
+              float *__restrict__ seis_tm, TileMap map) {
+  using T = Tile<RY>;
+  __shared__ float sm[2][T::LY][T::LX];
+  Geo<RY> geo;
+  if (!geo.init(g, map)) return;
+  Marcher<RY> f;
+  f.prime(cur, g, geo.z0, geo.off, geo.in, geo.hoff, geo.hin);
+  const float gxv = geo.x < g.nx ? g.gx[geo.x] : 0.0f;
+  float gyv[RY];
+  ColCursor cc[RY];
+#pragma unroll
+  for (int j = 0; j < RY; ++j) {
+    gyv[j] = geo.in[j] ? g.gy[geo.yv[j]] : 0.0f;
+    cc[j].ez = INT_MAX;
+    if (GATHER) cc[j].init(rec, geo.yv[j] * g.nx + geo.x, geo.z0, geo.in[j]);
+  }
+  const float c0 = W0 * (g.cx + g.cy + g.cz);
+  float pv[RY], kv[RY], mv[RY];  // pointwise streams of the current plane
+#pragma unroll
+  for (int j = 0; j < RY; ++j) {
+    pv[j] = ld_stream(prev, g, geo.z0, geo.off[j], geo.in[j]);
+    kv[j] = ld_stream(g.k, g, geo.z0, geo.off[j], geo.in[j]);
+    mv[j] = VD ? ld_stream(g.m2, g, geo.z0, geo.off[j], geo.in[j]) : 0.0f;
+  }
+  for (int z = geo.z0; z < geo.z1; ++z) {
+    float(*s)[T::LX] = sm[z & 1];
+    f.stage(s, geo.wave, geo.lane, geo.hslot);
+    f.fetch(cur, g, z, geo.off, geo.in, geo.hoff, geo.hin);
+    const bool more = z + 1 < geo.z1;
+    float pn[RY], kn[RY], mn[RY];  // next plane, in flight during this one
+#pragma unroll
+    for (int j = 0; j < RY; ++j) {
+      pn[j] = ld_stream(prev, g, z + 1, geo.off[j], geo.in[j] && more);
+      kn[j] = ld_stream(g.k, g, z + 1, geo.off[j], geo.in[j] && more);
+      mn[j] = VD ? ld_stream(g.m2, g, z + 1, geo.off[j], geo.in[j] && more) : 0.0f;
+    }
+    __syncthreads();
+    const float gzv = g.gz[z];
+    const int64_t zoff = (int64_t)z * g.plane;
+#pragma unroll
+    for (int j = 0; j < RY; ++j) {
+      float sx, sy, sz;
+      switch (j) {  // compile-time row index for the register / LDS choice
+        case 0: f.template diffs<0>(s, geo.wave, geo.lane, sx, sy, sz); break;
+        case 1: f.template diffs<(RY > 1 ? 1 : 0)>(s, geo.wave, geo.lane, sx, sy, sz); break;
+        case 2: f.template diffs<(RY > 2 ? 2 : 0)>(s, geo.wave, geo.lane, sx, sy, sz); break;
+        default: f.template diffs<(RY > 3 ? 3 : 0)>(s, geo.wave, geo.lane, sx, sy, sz); break;
+      }
+      const float c = f.q[j][4];
+      const float lap = c0 * c + g.cx * sx + g.cy * sy + g.cz * sz;
+      float acc = VD ? 2.0f * c + kv[j] * (lap - mv[j] * c) : 2.0f * c + kv[j] * lap;
+      const int64_t p = zoff + geo.off[j];
+      if (geo.in[j] && p == src.idx) acc += src.sigma[0] * src.wavelet[n];
+      const float G = gxv * gyv[j] * gzv;
+      const float o = G * (acc - G * pv[j]);
+      if (geo.in[j]) st_stream(out, p, o);
+      if (GATHER && cc[j].ez == z) {
+        for (int r = rec.ent_rp[cc[j].e]; r < rec.ent_rp[cc[j].e + 1]; ++r) {
+          const int id = rec.perm[r];
+          seis_tm[(int64_t)n * rec.nrec + id] = rec_scale[id] * o;
+        }
+        cc[j].advance(rec);
+      }
+    }
+    f.shift();
+#pragma unroll
+    for (int j = 0; j < RY; ++j) {
+      pv[j] = pn[j];
+      kv[j] = kn[j];
+      mv[j] = mn[j];
+    }
+  }
+}
+
+template <int RY, bool VD, bool ILLUM>
+__global__ void __launch_bounds__(NTHREADS)
+    k_adjoint(StepGrid g, const float *__restrict__ cur, const float *prev, float *out,
+              RecTable rec, const float *__restrict__ res_tm, int m,
+              const float *__restrict__ wm, float *__restrict__ grad,
+              float *__restrict__ illum, int border, int mnx, int mny, int mnz, TileMap map) {
+  using T = Tile<RY>;
+  __shared__ float sm[2][2][T::LY][T::LX];  // [field][buffer]
+  Geo<RY> geo;
+  if (!geo.init(g, map)) return;
+  Marcher<RY> fa, fw;  // adjoint state psi^{m+1} and forward state w^m
+  fa.prime(cur, g, geo.z0, geo.off, geo.in, geo.hoff, geo.hin);
+  fw.prime(wm, g, geo.z0, geo.off, geo.in, geo.hoff, geo.hin);
+  const float gxv = geo.x < g.nx ? g.gx[geo.x] : 0.0f;
+  float gyv[RY];
+  ColCursor cc[RY];
+#pragma unroll
+  for (int j = 0; j < RY; ++j) {
+    gyv[j] = geo.in[j] ? g.gy[geo.yv[j]] : 0.0f;
+    cc[j].init(rec, geo.yv[j] * g.nx + geo.x, geo.z0, geo.in[j]);
+  }
+  const float c0 = W0 * (g.cx + g.cy + g.cz);
+  const float *res_row = res_tm + (int64_t)(m - 1) * rec.nrec;
+  float pv[RY], kv[RY], mv[RY], gv[RY];
+#pragma unroll
+  for (int j = 0; j < RY; ++j) {
+    pv[j] = ld_stream(prev, g, geo.z0, geo.off[j], geo.in[j]);
+    kv[j] = ld_stream(g.k, g, geo.z0, geo.off[j], geo.in[j]);
+    mv[j] = VD ? ld_stream(g.m2, g, geo.z0, geo.off[j], geo.in[j]) : 0.0f;
+    gv[j] = ld_stream(grad, g, geo.z0, geo.off[j], geo.in[j]);
+  }
+  for (int z = geo.z0; z < geo.z1; ++z) {
+    float(*sa)[T::LX] = sm[0][z & 1];
+    float(*sw)[T::LX] = sm[1][z & 1];
+    fa.stage(sa, geo.wave, geo.lane, geo.hslot);
+    fw.stage(sw, geo.wave, geo.lane, geo.hslot);
+    fa.fetch(cur, g, z, geo.off, geo.in, geo.hoff, geo.hin);
+    fw.fetch(wm, g, z, geo.off, geo.in, geo.hoff, geo.hin);
+    const bool more = z + 1 < geo.z1;
+    float pn[RY], kn[RY], mn[RY], gn[RY];
+#pragma unroll
+    for (int j = 0; j < RY; ++j) {
+      pn[j] = ld_stream(prev, g, z + 1, geo.off[j], geo.in[j] && more);
+      kn[j] = ld_stream(g.k, g, z + 1, geo.off[j], geo.in[j] && more);
+      mn[j] = VD ? ld_stream(g.m2, g, z + 1, geo.off[j], geo.in[j] && more) : 0.0f;
+      gn[j] = ld_stream(grad, g, z + 1, geo.off[j], geo.in[j] && more);
+    }
+    __syncthreads();
+    const float gzv = g.gz[z];
+    const int64_t zoff = (int64_t)z * g.plane;
+#pragma unroll
+    for (int j = 0; j < RY; ++j) {
+      float ax, ay, az, wx, wy, wz;
+      switch (j) {
+        case 0:
+          fa.template diffs<0>(sa, geo.wave, geo.lane, ax, ay, az);
+          fw.template diffs<0>(sw, geo.wave, geo.lane, wx, wy, wz);
+          break;
+        case 1:
+          fa.template diffs<(RY > 1 ? 1 : 0)>(sa, geo.wave, geo.lane, ax, ay, az);
+          fw.template diffs<(RY > 1 ? 1 : 0)>(sw, geo.wave, geo.lane, wx, wy, wz);
+          break;
+        case 2:
+          fa.template diffs<(RY > 2 ? 2 : 0)>(sa, geo.wave, geo.lane, ax, ay, az);
+          fw.template diffs<(RY > 2 ? 2 : 0)>(sw, geo.wave, geo.lane, wx, wy, wz);
+          break;
+        default:
+          fa.template diffs<(RY > 3 ? 3 : 0)>(sa, geo.wave, geo.lane, ax, ay, az);
+          fw.template diffs<(RY > 3 ? 3 : 0)>(sw, geo.wave, geo.lane, wx, wy, wz);
+          break;
+      }
+      const float ca = fa.q[j][4], cw = fw.q[j][4];
+      const float lap_a = c0 * ca + g.cx * ax + g.cy * ay + g.cz * az;
+      const float lap_w = c0 * cw + g.cx * wx + g.cy * wy + g.cz * wz;
+      float acc = VD ? 2.0f * ca + kv[j] * (lap_a - mv[j] * ca) : 2.0f * ca + kv[j] * lap_a;
+      if (cc[j].ez == z) {  // receiver residuals injected at this node
+        float sum = 0.0f;
+        for (int r = rec.ent_rp[cc[j].e]; r < rec.ent_rp[cc[j].e + 1]; ++r)
+          sum += res_row[rec.perm[r]];
+        acc += sum;
+        cc[j].advance(rec);
+      }
+      const float G = gxv * gyv[j] * gzv;
+      const int64_t p = zoff + geo.off[j];
+      if (geo.in[j]) {
+        st_stream(out, p, G * (acc - G * pv[j]));
+        st_stream(grad, p, gv[j] + ca * (VD ? lap_w - mv[j] * cw : lap_w));
+        if (ILLUM) {
+          const int ix = geo.x - border, iy = geo.yv[j] - border, iz = z - border;
+          if (ix >= 0 && ix < mnx && iy >= 0 && iy < mny && iz >= 0 && iz < mnz)
+            illum[((int64_t)iz * mny + iy) * mnx + ix] += cw * cw;
+        }
+      }
+    }
+    fa.shift();
+    fw.shift();
+#pragma unroll
+    for (int j = 0; j < RY; ++j) {
+      pv[j] = pn[j];
+      kv[j] = kn[j];
+      mv[j] = mn[j];
+      gv[j] = gn[j];
+    }
+  }
+}
+
+constexpr int RY_FWD = 4;
+constexpr int RY_ADJ = 2;
+
+int env_int(const char *name, int dflt) {
+  const char *v = std::getenv(name);
+  if (!v || !*v) return dflt;
+  return std::atoi(v);
+}
+
+int device_cus() {
+  static const int cus = [] {
+    int dev = 0, n = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        n <= 0)
+      n = 256;
+    return n;
+  }();
+  return cus;
+}
+
+template <class K>
+int blocks_per_cu(K kernel) {
+  int per_cu = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, NTHREADS, 0) != hipSuccess ||
+      per_cu <= 0)
+    per_cu = 4;
+  return per_cu;
+}
+
+// Tile map: z chunks so that about four rounds of resident blocks cover the
+// grid (measured at 576^3: full-depth columns leave slots idle, and very
+// short chunks re-read the 8-plane z halo too often).
+TileMap make_map(const StepGrid &g, int ty, int per_cu, const char *env_name) {
+  TileMap m;
+  m.tiles_x = (g.nx + TX - 1) / TX;
+  m.tiles_y = (g.ny + ty - 1) / ty;
+  const int tiles = m.tiles_x * m.tiles_y;
+  const int slots = per_cu * device_cus();
+  static const int env_nch = env_int(env_name, 0);
+  int nch = env_nch;
+  if (nch <= 0) nch = (4 * slots + tiles / 2) / tiles;
+  nch = std::max(1, std::min(nch, (g.nz + 15) / 16));
+  m.zc = (g.nz + nch - 1) / nch;
+  m.nchunks = (g.nz + m.zc - 1) / m.zc;
+  m.nblocks = tiles * m.nchunks;
+  return m;
+}
+
+template <int RY, bool VD, bool GATHER>
+hipError_t fwd_launch(const StepGrid &g, const float *cur, const float *prev, float *out,
+                      const Source &src, int n, const RecTable &rec, const float *rec_scale,
+                      float *seis_tm, hipStream_t stream) {
+  static const int per_cu = blocks_per_cu(k_forward<RY, VD, GATHER>);
+  const TileMap map = make_map(g, Tile<RY>::TY, per_cu, "WFD_ZCHUNKS_FWD");
+  hipLaunchKernelGGL((k_forward<RY, VD, GATHER>), dim3(map.nblocks), dim3(NTHREADS), 0, stream,
+                     g, cur, prev, out, src, n, rec, rec_scale, seis_tm, map);
+  return hipGetLastError();
+}
+
+template <int RY, bool VD, bool ILLUM>
+hipError_t adj_launch(const StepGrid &g, const float *cur, const float *prev, float *out,
+                      const RecTable &rec, const float *res_tm, int m, const float *wm,
+                      float *grad, float *illum, int border, int mnx, int mny, int mnz,
+                      hipStream_t stream) {
+  static const int per_cu = blocks_per_cu(k_adjoint<RY, VD, ILLUM>);
+  const TileMap map = make_map(g, Tile<RY>::TY, per_cu, "WFD_ZCHUNKS_ADJ");
+  hipLaunchKernelGGL((k_adjoint<RY, VD, ILLUM>), dim3(map.nblocks), dim3(NTHREADS), 0, stream,
+                     g, cur, prev, out, rec, res_tm, m, wm, grad, illum, border, mnx, mny, mnz,
+                     map);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_forward_step(const StepGrid &g, const float *cur, const float *prev, float *out,
+                               const Source &src, int n, const RecTable *rec,
+                               const float *rec_scale, float *seis_tm, hipStream_t stream) {
+  const bool vd = g.m2 != nullptr;
+  RecTable none{};
+  if (rec) {
+    return vd ? fwd_launch<RY_FWD, true, true>(g, cur, prev, out, src, n, *rec, rec_scale,
+                                               seis_tm, stream)
+              : fwd_launch<RY_FWD, false, true>(g, cur, prev, out, src, n, *rec, rec_scale,
+                                                seis_tm, stream);
+  }
+  return vd ? fwd_launch<RY_FWD, true, false>(g, cur, prev, out, src, n, none, rec_scale, seis_tm,
+                                              stream)
+            : fwd_launch<RY_FWD, false, false>(g, cur, prev, out, src, n, none, rec_scale,
+                                               seis_tm, stream);
+}
+
+hipError_t launch_adjoint_step(const StepGrid &g, const float *cur, const float *prev, float *out,
+                               const RecTable &rec, const float *res_tm, int m,
+                               const float *wm, float *grad, float *illum, int border, int mnx,
+                               int mny, int mnz, hipStream_t stream) {
+  const bool vd = g.m2 != nullptr;
+  if (vd)
+    return illum ? adj_launch<RY_ADJ, true, true>(g, cur, prev, out, rec, res_tm, m, wm, grad,
+                                                  illum, border, mnx, mny, mnz, stream)
+                 : adj_launch<RY_ADJ, true, false>(g, cur, prev, out, rec, res_tm, m, wm, grad,
+                                                   illum, border, mnx, mny, mnz, stream);
+  return illum ? adj_launch<RY_ADJ, false, true>(g, cur, prev, out, rec, res_tm, m, wm, grad,
+                                                 illum, border, mnx, mny, mnz, stream)
+               : adj_launch<RY_ADJ, false, false>(g, cur, prev, out, rec, res_tm, m, wm, grad,
+                                                  illum, border, mnx, mny, mnz, stream);
+}
+
+}  // namespace wfd
