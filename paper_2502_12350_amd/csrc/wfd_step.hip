@@ -27,17 +27,17 @@ constexpr float W2 = -1.0f / 5.0f;
 constexpr float W3 = 8.0f / 315.0f;
 constexpr float W4 = -1.0f / 560.0f;
 
-constexpr int TX = 64;     // tile width = one wavefront
-constexpr int NWAVE = 4;   // wavefronts per block
-constexpr int NTHREADS = TX * NWAVE;
+constexpr int TX = 64;  // tile width = one wavefront
 
 struct TileMap {
   int tiles_x, tiles_y, nchunks, zc, nblocks;
 };
 
-template <int RY>
+// A tile is NW wavefronts, each owning RY consecutive rows of 64 points.
+template <int RY, int NW>
 struct Tile {
-  static constexpr int TY = NWAVE * RY;
+  static constexpr int NTHREADS = TX * NW;
+  static constexpr int TY = NW * RY;
   static constexpr int LX = TX + 8;
   static constexpr int LY = TY + 8;
   static constexpr int NHALO = 8 * TX + 8 * TY;  // y-halo rows + x-halo columns
@@ -59,10 +59,10 @@ __device__ __forceinline__ void tile_of(const TileMap &m, int &tx, int &ty, int 
 }
 
 // Halo element h of a tile plane: global (gx, gy) and its LDS row / column.
-template <int RY>
+template <int RY, int NW>
 __device__ __forceinline__ void halo_slot(int h, int x0, int y0, int &gx, int &gy, int &lrow,
                                           int &lcol) {
-  constexpr int TY = Tile<RY>::TY;
+  constexpr int TY = Tile<RY, NW>::TY;
   if (h < 8 * TX) {  // four rows above and four below the tile
     const int r = h / TX, col = h % TX;
     gx = x0 + col;
@@ -100,9 +100,9 @@ __device__ __forceinline__ void st_stream(float *f, int64_t p, float v) {
 }
 
 // Per-thread view of one stenciled field: register queue + halo staging.
-template <int RY>
+template <int RY, int NW>
 struct Marcher {
-  using T = Tile<RY>;
+  using T = Tile<RY, NW>;
   float q[RY][9];   // planes z-4 .. z+4 of the thread's RY points
   float nxt[RY];    // plane z+5 (in flight)
   float hv[T::HPT]; // halo of the plane written to LDS next
@@ -167,9 +167,9 @@ struct Marcher {
 };
 
 // Common per-thread tile geometry.
-template <int RY>
+template <int RY, int NW>
 struct Geo {
-  using T = Tile<RY>;
+  using T = Tile<RY, NW>;
   int lane, wave, x0, y0, x, z0, z1;
   bool in[RY];
   uint32_t off[RY];
@@ -196,10 +196,10 @@ struct Geo {
     }
 #pragma unroll
     for (int i = 0; i < T::HPT; ++i) {
-      const int h = threadIdx.x + i * NTHREADS;
+      const int h = threadIdx.x + i * T::NTHREADS;
       if (h < T::NHALO) {
         int gx, gy, lrow, lcol;
-        halo_slot<RY>(h, x0, y0, gx, gy, lrow, lcol);
+        halo_slot<RY, NW>(h, x0, y0, gx, gy, lrow, lcol);
         hin[i] = gx >= 0 && gx < g.nx && gy >= 0 && gy < g.ny;
         hoff[i] = hin[i] ? (uint32_t)gy * (uint32_t)g.pitch + (uint32_t)gx : 0u;
         hslot[i] = lrow * T::LX + lcol;
@@ -231,16 +231,18 @@ struct ColCursor {
   }
 };
 
-template <int RY, bool VD, bool GATHER>
-__global__ void __launch_bounds__(NTHREADS)
+// One leapfrog step; records the receivers of step n when seis_tm is set
+// (recomputation sweeps pass none).
+template <int RY, int NW, bool VD>
+__global__ void __launch_bounds__(TX * NW)
     k_forward(StepGrid g, const float *__restrict__ cur, const float *prev, float *out,
               Source src, int n, RecTable rec, const float *__restrict__ rec_scale,
               float *__restrict__ seis_tm, TileMap map) {
-  using T = Tile<RY>;
+  using T = Tile<RY, NW>;
   __shared__ float sm[2][T::LY][T::LX];
-  Geo<RY> geo;
+  Geo<RY, NW> geo;
   if (!geo.init(g, map)) return;
-  Marcher<RY> f;
+  Marcher<RY, NW> f;
   f.prime(cur, g, geo.z0, geo.off, geo.in, geo.hoff, geo.hin);
   const float gxv = geo.x < g.nx ? g.gx[geo.x] : 0.0f;
   float gyv[RY];
@@ -248,8 +250,7 @@ __global__ void __launch_bounds__(NTHREADS)
 #pragma unroll
   for (int j = 0; j < RY; ++j) {
     gyv[j] = geo.in[j] ? g.gy[geo.yv[j]] : 0.0f;
-    cc[j].ez = INT_MAX;
-    if (GATHER) cc[j].init(rec, geo.yv[j] * g.nx + geo.x, geo.z0, geo.in[j]);
+    cc[j].init(rec, geo.yv[j] * g.nx + geo.x, geo.z0, geo.in[j] && seis_tm != nullptr);
   }
   const float c0 = W0 * (g.cx + g.cy + g.cz);
   float pv[RY], kv[RY], mv[RY];  // pointwise streams of the current plane
@@ -291,7 +292,7 @@ __global__ void __launch_bounds__(NTHREADS)
       const float G = gxv * gyv[j] * gzv;
       const float o = G * (acc - G * pv[j]);
       if (geo.in[j]) st_stream(out, p, o);
-      if (GATHER && cc[j].ez == z) {
+      if (cc[j].ez == z) {
         for (int r = rec.ent_rp[cc[j].e]; r < rec.ent_rp[cc[j].e + 1]; ++r) {
           const int id = rec.perm[r];
           seis_tm[(int64_t)n * rec.nrec + id] = rec_scale[id] * o;
@@ -309,17 +310,17 @@ __global__ void __launch_bounds__(NTHREADS)
   }
 }
 
-template <int RY, bool VD, bool ILLUM>
-__global__ void __launch_bounds__(NTHREADS)
+template <int RY, int NW, bool VD, bool ILLUM>
+__global__ void __launch_bounds__(TX * NW)
     k_adjoint(StepGrid g, const float *__restrict__ cur, const float *prev, float *out,
               RecTable rec, const float *__restrict__ res_tm, int m,
               const float *__restrict__ wm, float *__restrict__ grad,
               float *__restrict__ illum, int border, int mnx, int mny, int mnz, TileMap map) {
-  using T = Tile<RY>;
+  using T = Tile<RY, NW>;
   __shared__ float sm[2][2][T::LY][T::LX];  // [field][buffer]
-  Geo<RY> geo;
+  Geo<RY, NW> geo;
   if (!geo.init(g, map)) return;
-  Marcher<RY> fa, fw;  // adjoint state psi^{m+1} and forward state w^m
+  Marcher<RY, NW> fa, fw;  // adjoint state psi^{m+1} and forward state w^m
   fa.prime(cur, g, geo.z0, geo.off, geo.in, geo.hoff, geo.hin);
   fw.prime(wm, g, geo.z0, geo.off, geo.in, geo.hoff, geo.hin);
   const float gxv = geo.x < g.nx ? g.gx[geo.x] : 0.0f;
@@ -415,8 +416,9 @@ __global__ void __launch_bounds__(NTHREADS)
   }
 }
 
-constexpr int RY_FWD = 4;
-constexpr int RY_ADJ = 2;
+// Rows per thread and wavefronts per block of the two step kernels.
+constexpr int RY_FWD = 4, NW_FWD = 4;  // 64 x 16 tiles
+constexpr int RY_ADJ = 2, NW_ADJ = 4;  // 64 x 8 tiles
 
 int env_int(const char *name, int dflt) {
   const char *v = std::getenv(name);
@@ -437,9 +439,9 @@ int device_cus() {
 }
 
 template <class K>
-int blocks_per_cu(K kernel) {
+int blocks_per_cu(K kernel, int threads) {
   int per_cu = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, NTHREADS, 0) != hipSuccess ||
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, threads, 0) != hipSuccess ||
       per_cu <= 0)
     per_cu = 4;
   return per_cu;
@@ -464,27 +466,29 @@ TileMap make_map(const StepGrid &g, int ty, int per_cu, const char *env_name) {
   return m;
 }
 
-template <int RY, bool VD, bool GATHER>
+template <int RY, int NW, bool VD>
 hipError_t fwd_launch(const StepGrid &g, const float *cur, const float *prev, float *out,
                       const Source &src, int n, const RecTable &rec, const float *rec_scale,
                       float *seis_tm, hipStream_t stream) {
-  static const int per_cu = blocks_per_cu(k_forward<RY, VD, GATHER>);
-  const TileMap map = make_map(g, Tile<RY>::TY, per_cu, "WFD_ZCHUNKS_FWD");
-  hipLaunchKernelGGL((k_forward<RY, VD, GATHER>), dim3(map.nblocks), dim3(NTHREADS), 0, stream,
-                     g, cur, prev, out, src, n, rec, rec_scale, seis_tm, map);
+  using T = Tile<RY, NW>;
+  static const int per_cu = blocks_per_cu(k_forward<RY, NW, VD>, T::NTHREADS);
+  const TileMap map = make_map(g, T::TY, per_cu, "WFD_ZCHUNKS_FWD");
+  hipLaunchKernelGGL((k_forward<RY, NW, VD>), dim3(map.nblocks), dim3(T::NTHREADS), 0,
+                     stream, g, cur, prev, out, src, n, rec, rec_scale, seis_tm, map);
   return hipGetLastError();
 }
 
-template <int RY, bool VD, bool ILLUM>
+template <int RY, int NW, bool VD, bool ILLUM>
 hipError_t adj_launch(const StepGrid &g, const float *cur, const float *prev, float *out,
                       const RecTable &rec, const float *res_tm, int m, const float *wm,
                       float *grad, float *illum, int border, int mnx, int mny, int mnz,
                       hipStream_t stream) {
-  static const int per_cu = blocks_per_cu(k_adjoint<RY, VD, ILLUM>);
-  const TileMap map = make_map(g, Tile<RY>::TY, per_cu, "WFD_ZCHUNKS_ADJ");
-  hipLaunchKernelGGL((k_adjoint<RY, VD, ILLUM>), dim3(map.nblocks), dim3(NTHREADS), 0, stream,
-                     g, cur, prev, out, rec, res_tm, m, wm, grad, illum, border, mnx, mny, mnz,
-                     map);
+  using T = Tile<RY, NW>;
+  static const int per_cu = blocks_per_cu(k_adjoint<RY, NW, VD, ILLUM>, T::NTHREADS);
+  const TileMap map = make_map(g, T::TY, per_cu, "WFD_ZCHUNKS_ADJ");
+  hipLaunchKernelGGL((k_adjoint<RY, NW, VD, ILLUM>), dim3(map.nblocks), dim3(T::NTHREADS), 0,
+                     stream, g, cur, prev, out, rec, res_tm, m, wm, grad, illum, border, mnx, mny,
+                     mnz, map);
   return hipGetLastError();
 }
 
@@ -494,17 +498,13 @@ hipError_t launch_forward_step(const StepGrid &g, const float *cur, const float 
                                const Source &src, int n, const RecTable *rec,
                                const float *rec_scale, float *seis_tm, hipStream_t stream) {
   const bool vd = g.m2 != nullptr;
-  RecTable none{};
-  if (rec) {
-    return vd ? fwd_launch<RY_FWD, true, true>(g, cur, prev, out, src, n, *rec, rec_scale,
-                                               seis_tm, stream)
-              : fwd_launch<RY_FWD, false, true>(g, cur, prev, out, src, n, *rec, rec_scale,
-                                                seis_tm, stream);
-  }
-  return vd ? fwd_launch<RY_FWD, true, false>(g, cur, prev, out, src, n, none, rec_scale, seis_tm,
-                                              stream)
-            : fwd_launch<RY_FWD, false, false>(g, cur, prev, out, src, n, none, rec_scale,
-                                               seis_tm, stream);
+  const RecTable none{};
+  const RecTable &r = rec ? *rec : none;
+  float *rec_out = rec ? seis_tm : nullptr;
+  return vd ? fwd_launch<RY_FWD, NW_FWD, true>(g, cur, prev, out, src, n, r, rec_scale, rec_out,
+                                               stream)
+            : fwd_launch<RY_FWD, NW_FWD, false>(g, cur, prev, out, src, n, r, rec_scale, rec_out,
+                                                stream);
 }
 
 hipError_t launch_adjoint_step(const StepGrid &g, const float *cur, const float *prev, float *out,
@@ -513,13 +513,13 @@ hipError_t launch_adjoint_step(const StepGrid &g, const float *cur, const float 
                                int mny, int mnz, hipStream_t stream) {
   const bool vd = g.m2 != nullptr;
   if (vd)
-    return illum ? adj_launch<RY_ADJ, true, true>(g, cur, prev, out, rec, res_tm, m, wm, grad,
+    return illum ? adj_launch<RY_ADJ, NW_ADJ, true, true>(g, cur, prev, out, rec, res_tm, m, wm, grad,
                                                   illum, border, mnx, mny, mnz, stream)
-                 : adj_launch<RY_ADJ, true, false>(g, cur, prev, out, rec, res_tm, m, wm, grad,
+                 : adj_launch<RY_ADJ, NW_ADJ, true, false>(g, cur, prev, out, rec, res_tm, m, wm, grad,
                                                    illum, border, mnx, mny, mnz, stream);
-  return illum ? adj_launch<RY_ADJ, false, true>(g, cur, prev, out, rec, res_tm, m, wm, grad,
+  return illum ? adj_launch<RY_ADJ, NW_ADJ, false, true>(g, cur, prev, out, rec, res_tm, m, wm, grad,
                                                  illum, border, mnx, mny, mnz, stream)
-               : adj_launch<RY_ADJ, false, false>(g, cur, prev, out, rec, res_tm, m, wm, grad,
+               : adj_launch<RY_ADJ, NW_ADJ, false, false>(g, cur, prev, out, rec, res_tm, m, wm, grad,
                                                   illum, border, mnx, mny, mnz, stream);
 }
 
