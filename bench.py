@@ -91,22 +91,31 @@ def cpu_baseline(w, n_steps: int = 2):
             "seconds": round(t_f + t_a, 2)}
 
 
-def copy_probe(gib: float = 4.0, reps: int = 5):
-    """A plain device copy of known size (counter calibration)."""
+def copy_probe(gib: float = 4.0, reps: int = 10):
+    """Streaming references of known size: a plain device copy (also the
+    counter calibration) and a 3-read / 1-write elementwise kernel."""
     import torch
     n = int(gib * (1 << 30)) // 4
     a = torch.ones(n, dtype=torch.float32, device="cuda")
     b = torch.empty_like(a)
-    for _ in range(reps):
-        b.copy_(a)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(reps):
-        b.copy_(a)
-    torch.cuda.synchronize()
-    dt = (time.perf_counter() - t0) / reps
+    c = torch.ones_like(a)
+    d = torch.ones_like(a)
+
+    def timed(fn):
+        for _ in range(3):
+            fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / reps
+
+    t_copy = timed(lambda: b.copy_(a))
+    t_r3w1 = timed(lambda: torch.addcmul(a, c, d, out=b))
     print(json.dumps({"copy_bytes_read": 4 * n, "copy_bytes_written": 4 * n,
-                      "copy_GBps": 8 * n / dt / 1e9}), flush=True)
+                      "copy_GBps": round(8 * n / t_copy / 1e9, 1),
+                      "addcmul_r3w1_GBps": round(16 * n / t_r3w1 / 1e9, 1)}), flush=True)
 
 
 def main():
