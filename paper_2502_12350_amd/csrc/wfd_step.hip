@@ -450,14 +450,13 @@ int blocks_per_cu(K kernel, int threads) {
 // Tile map: z chunks so that about four rounds of resident blocks cover the
 // grid (measured at 576^3: full-depth columns leave slots idle, and very
 // short chunks re-read the 8-plane z halo too often).
-TileMap make_map(const StepGrid &g, int ty, int per_cu, const char *env_name) {
+TileMap make_map(const StepGrid &g, int ty, int per_cu, int nch_override) {
   TileMap m;
   m.tiles_x = (g.nx + TX - 1) / TX;
   m.tiles_y = (g.ny + ty - 1) / ty;
   const int tiles = m.tiles_x * m.tiles_y;
   const int slots = per_cu * device_cus();
-  static const int env_nch = env_int(env_name, 0);
-  int nch = env_nch;
+  int nch = nch_override;
   if (nch <= 0) nch = (4 * slots + tiles / 2) / tiles;
   nch = std::max(1, std::min(nch, (g.nz + 15) / 16));
   m.zc = (g.nz + nch - 1) / nch;
@@ -472,7 +471,8 @@ hipError_t fwd_launch(const StepGrid &g, const float *cur, const float *prev, fl
                       float *seis_tm, hipStream_t stream) {
   using T = Tile<RY, NW>;
   static const int per_cu = blocks_per_cu(k_forward<RY, NW, VD>, T::NTHREADS);
-  const TileMap map = make_map(g, T::TY, per_cu, "WFD_ZCHUNKS_FWD");
+  static const int nch = env_int("WFD_ZCHUNKS_FWD", 0);  // 0 = automatic
+  const TileMap map = make_map(g, T::TY, per_cu, nch);
   hipLaunchKernelGGL((k_forward<RY, NW, VD>), dim3(map.nblocks), dim3(T::NTHREADS), 0,
                      stream, g, cur, prev, out, src, n, rec, rec_scale, seis_tm, map);
   return hipGetLastError();
@@ -485,7 +485,8 @@ hipError_t adj_launch(const StepGrid &g, const float *cur, const float *prev, fl
                       hipStream_t stream) {
   using T = Tile<RY, NW>;
   static const int per_cu = blocks_per_cu(k_adjoint<RY, NW, VD, ILLUM>, T::NTHREADS);
-  const TileMap map = make_map(g, T::TY, per_cu, "WFD_ZCHUNKS_ADJ");
+  static const int nch = env_int("WFD_ZCHUNKS_ADJ", 0);  // 0 = automatic
+  const TileMap map = make_map(g, T::TY, per_cu, nch);
   hipLaunchKernelGGL((k_adjoint<RY, NW, VD, ILLUM>), dim3(map.nblocks), dim3(T::NTHREADS), 0,
                      stream, g, cur, prev, out, rec, res_tm, m, wm, grad, illum, border, mnx, mny,
                      mnz, map);
