@@ -118,6 +118,79 @@ def copy_probe(gib: float = 4.0, reps: int = 10):
                       "addcmul_r3w1_GBps": round(16 * n / t_r3w1 / 1e9, 1)}), flush=True)
 
 
+def fwi_bench(n_iter: int):
+    """FWI on the gradient workload: 200x200x160 model + 20-cell sponge, 1200
+    steps, 8 shots x 2500 receivers, true model = smooth background + six
+    +/-10 % blobs, start = background, constant density.  Observed data come
+    from the library's forward modeling on the true model.  Reports misfit
+    versus GPU-seconds for steepest descent on the illumination-compensated
+    gradient and for projected L-BFGS, and one shot's gradient with full
+    storage versus 20 stored pairs."""
+    import numpy as np
+    import torch
+    import seisgen
+    from paper_2502_12350_amd import GridSpec, Propagator, checkpoint_plan
+    from paper_2502_12350_amd.fwi import Shots, fwi
+
+    w = seisgen.workload("c4_start")
+    g = GridSpec(**w.grid_kwargs())
+    dev = torch.device("cuda", 0)
+    P = Propagator(0)
+    P.set_model(g, torch.from_numpy(w.extra["v_true"]).to(dev))
+    wav = torch.from_numpy(w.wavelet).to(dev)
+    dobs = [P.forward(wav, s, w.receivers).clone() for s in w.sources]
+    torch.cuda.synchronize()
+    P.release_workspace()
+    shots = Shots(wav, np.asarray(w.sources), [w.receivers] * len(w.sources), dobs)
+    v0 = torch.from_numpy(w.vel).to(dev)
+    vt = w.extra["v_true"]
+    out = {"metric": "FWI misfit cut per GPU-s", "unit": "1/GPU-s", "higher_is_better": True,
+           "n_gpus": 1, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": "FWI, 200x200x160 model + 20-cell sponge, 1200 steps, 8 shots, "
+                                  "2500 receivers, smooth background + six +/-10 % blobs",
+                      "iterations": n_iter, "bounds_m_s": [1500.0, 4500.0],
+                      "zero_top_planes": 24,
+                      "preconditioner": "g / (I + 1e-3 max I), I = source illumination"},
+           "methods": {}}
+    for method in ("sd", "lbfgs"):
+        print(f"[bench-fwi] {method}", file=sys.stderr, flush=True)
+        # sources and receivers sit at depth index 4 and the anomalies start at 40:
+        # the acquisition footprint in the top 24 gradient planes is zeroed
+        # (ZeroesNearSurface of Alg. 3)
+        v, tr = fwi(P, g, v0, None, shots, n_iter=n_iter, method=method, bounds=(1500.0, 4500.0),
+                    zero_top_planes=24)
+        out["methods"][method] = {
+            "misfit": [float(x) for x in tr.misfit],
+            "gpu_seconds": [round(t, 3) for t in tr.gpu_seconds],
+            "misfit_cut_per_gpu_s": tr.misfit_cut_per_gpu_s(),
+            "gpu_s_to_half_misfit": tr.time_to_reach(0.5),
+            "gradients": tr.n_gradients, "forward_misfits": tr.n_misfits,
+            "model_error_rel": float(np.linalg.norm(v.cpu().numpy() - vt) / np.linalg.norm(w.vel - vt)),
+        }
+    out["value"] = out["methods"]["lbfgs"]["misfit_cut_per_gpu_s"]
+    # one shot: full storage vs binomial checkpointing with 20 stored pairs
+    P.set_model(g, v0)
+    ck_out = {}
+    for ck in ("full", ("revolve", 20)):
+        P._workspace(P.workspace_bytes(len(w.receivers), ck))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        J, grad = P.gradient(wav, w.sources[0], w.receivers, dobs[0], ckpt=ck)
+        torch.cuda.synchronize()
+        ck_out[str(ck[0] if isinstance(ck, tuple) else ck)] = {
+            "seconds": round(time.perf_counter() - t0, 4),
+            "workspace_GiB": round(P.workspace_bytes(len(w.receivers), ck) / 2**30, 2),
+            "grad": grad.clone()}
+        P.release_workspace()
+    _, steps = checkpoint_plan(w.nt, 20)
+    out["checkpointing_one_shot"] = {
+        "full": {k: v for k, v in ck_out["full"].items() if k != "grad"},
+        "revolve_20_pairs": {**{k: v for k, v in ck_out["revolve"].items() if k != "grad"},
+                             "forward_steps": steps},
+        "bitwise_equal": bool(torch.equal(ck_out["full"]["grad"], ck_out["revolve"]["grad"]))}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -128,6 +201,8 @@ def main():
     ap.add_argument("--snapshots", type=int, default=96)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe", action="store_true")
+    ap.add_argument("--fwi", type=int, default=0, metavar="ITERS",
+                    help="run the FWI benchmark with this many iterations per method instead")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -138,6 +213,9 @@ def main():
         sys.exit(2)
     if args.copy_probe:
         copy_probe()
+        return
+    if args.fwi:
+        fwi_bench(args.fwi)
         return
 
     import numpy as np

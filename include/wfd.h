@@ -135,6 +135,20 @@ wfd_status wfd_forward(wfd_ctx *ctx, const float *wavelet_dev, const double src_
                        int32_t nrec, const double *rec_xyz, float *seis_dev,
                        float *final_dev_or_null, void *work_dev, size_t work_bytes);
 
+/* Forward sweep of one shot and its misfit only (SeismicData::Misfit of
+ * Alg. 3 without the backward sweep; line searches of the FWI loop need it):
+ *   dobs_dev          [nrec][nt] FP32 observed traces, device;
+ *   seis_or_null      [nrec][nt] FP32 output synthetic traces, or NULL;
+ *   misfit_dev        device FP64 scalar, accumulated (+= 1/2 sum (d - d_obs)^2);
+ *   work_dev, work_bytes  workspace of at least wfd_misfit_workspace_bytes(). */
+wfd_status wfd_forward_misfit(wfd_ctx *ctx, const float *wavelet_dev, const double src_xyz[3],
+                              int32_t nrec, const double *rec_xyz, const float *dobs_dev,
+                              float *seis_or_null, double *misfit_dev, void *work_dev,
+                              size_t work_bytes);
+
+/* Workspace bytes of wfd_forward_misfit for nrec receivers. */
+wfd_status wfd_misfit_workspace_bytes(const wfd_ctx *ctx, int32_t nrec, size_t *bytes);
+
 /* Misfit and velocity gradient of one shot (Alg. 3 body for one shot):
  * forward sweep with recording and wavefield saving, res = d - d_obs,
  * J = 1/2 sum res^2, discrete adjoint sweep (exact transpose of the forward

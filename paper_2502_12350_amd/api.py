@@ -226,6 +226,31 @@ class Propagator:
                                  _ptr(fin), wptr, wbytes))
         return (seis, fin) if final else seis
 
+    def forward_misfit(self, wavelet, src_xyz, rec_xyz, dobs, *, misfit=None, seis: bool = False):
+        """Accumulate one shot's misfit from a forward sweep only; returns misfit[, seis]."""
+        torch = self.torch
+        g = self.grid
+        if g is None:
+            raise RuntimeError("set_model first")
+        wavelet = self._dev(wavelet, "wavelet", (g.nt,), torch.float32)
+        src = _xyz(src_xyz)
+        rec = _xyz(rec_xyz)
+        nrec = rec.shape[0]
+        dobs = self._dev(dobs, "dobs", (nrec, g.nt), torch.float32)
+        if misfit is None:
+            misfit = torch.zeros((), dtype=torch.float64, device=self.device)
+        else:
+            self._dev(misfit, "misfit", (), torch.float64)
+        out_seis = (torch.empty((nrec, g.nt), dtype=torch.float32, device=self.device)
+                    if seis else None)
+        n = C.c_size_t()
+        check(self.L.wfd_misfit_workspace_bytes(self._ctx, nrec, C.byref(n)))
+        wptr, wbytes = self._workspace(n.value)
+        self._sync_stream()
+        check(self.L.wfd_forward_misfit(self._ctx, _ptr(wavelet), _dptr(src), nrec, _dptr(rec),
+                                        _ptr(dobs), _ptr(out_seis), _ptr(misfit), wptr, wbytes))
+        return (misfit, out_seis) if seis else misfit
+
     def gradient(self, wavelet, src_xyz, rec_xyz, dobs, *, ckpt="full", grad=None, misfit=None,
                  illum=None, seis: bool = False):
         """Accumulate one shot's misfit and dJ/dv; returns (misfit, grad[, seis])."""

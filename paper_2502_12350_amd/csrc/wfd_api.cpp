@@ -224,7 +224,12 @@ int64_t snapshots_for(const wfd_ctx *c, const wfd_ckpt *ck) {
   return std::max<int64_t>(1, std::min<int64_t>(s, c->grid.nt));
 }
 
-Work work_layout(const wfd_ctx *c, int nrec, const wfd_ckpt *ck, int64_t nsnap, void *base) {
+enum class WorkKind { Forward, Misfit, Gradient };
+
+// Workspace layout of one shot.  Forward: tables, traces, two fields; Misfit
+// adds the residual; Gradient adds the adjoint pair, g and the stored states.
+Work work_layout(const wfd_ctx *c, int nrec, WorkKind kind, const wfd_ckpt *ck, int64_t nsnap,
+                 void *base) {
   Carve cv(base);
   Work w{};
   const int ncol = c->Nx * c->Ny;
@@ -240,9 +245,11 @@ Work work_layout(const wfd_ctx *c, int nrec, const wfd_ckpt *ck, int64_t nsnap, 
   w.seis_tm = cv.take<float>((size_t)c->grid.nt * std::max(nrec, 1));
   w.W1 = cv.take<float>((size_t)c->vol);
   w.W2 = cv.take<float>((size_t)c->vol);
-  if (ck) {
+  if (kind != WorkKind::Forward) {
     w.res_tm = cv.take<float>((size_t)c->grid.nt * std::max(nrec, 1));
     w.partial = cv.take<double>((size_t)std::max(1, wfd::residual_partial_count(nrec, c->grid.nt)));
+  }
+  if (kind == WorkKind::Gradient) {
     w.P1 = cv.take<float>((size_t)c->vol);
     w.P2 = cv.take<float>((size_t)c->vol);
     w.g = cv.take<float>((size_t)c->vol);
@@ -526,6 +533,14 @@ wfd_status wfd_set_model(wfd_ctx *c, const wfd_grid *grid, const float *vel,
   return WFD_OK;
 }
 
+wfd_status wfd_misfit_workspace_bytes(const wfd_ctx *c, int32_t nrec, size_t *bytes) {
+  if (!c || !bytes) return fail(WFD_E_ARG, "NULL argument");
+  if (!c->has_model) return fail(WFD_E_STATE, "no model: call wfd_set_model first");
+  if (nrec < 0) return fail(WFD_E_ARG, "nrec must be >= 0");
+  *bytes = work_layout(c, nrec, WorkKind::Misfit, nullptr, 0, nullptr).bytes;
+  return WFD_OK;
+}
+
 wfd_status wfd_workspace_bytes(const wfd_ctx *c, int32_t nrec, const wfd_ckpt *ck, size_t *bytes) {
   if (!c || !bytes) return fail(WFD_E_ARG, "NULL argument");
   if (!c->has_model) return fail(WFD_E_STATE, "no model: call wfd_set_model first");
@@ -539,19 +554,24 @@ wfd_status wfd_workspace_bytes(const wfd_ctx *c, int32_t nrec, const wfd_ckpt *c
     ScopedDevice sd(c->device);
     nsnap = snapshots_for(c, ck);
   }
-  *bytes = work_layout(c, nrec, ck, nsnap, nullptr).bytes;
+  *bytes = work_layout(c, nrec, ck ? WorkKind::Gradient : WorkKind::Forward, ck, nsnap, nullptr)
+               .bytes;
   return WFD_OK;
 }
 
-wfd_status wfd_forward(wfd_ctx *c, const float *wavelet, const double src_xyz[3], int32_t nrec,
-                       const double *rec_xyz, float *seis, float *final_dev, void *work,
-                       size_t work_bytes) {
+namespace {
+
+// Forward sweep of one shot; optionally the trace output, the final states and
+// the misfit against observed data (then the workspace also holds the residual).
+wfd_status forward_core(wfd_ctx *c, const float *wavelet, const double src_xyz[3], int32_t nrec,
+                        const double *rec_xyz, float *seis, float *final_dev, const float *dobs,
+                        double *misfit, void *work, size_t work_bytes, bool with_misfit) {
   wfd_status s = common_checks(c, wavelet, src_xyz, nrec, rec_xyz);
   if (s != WFD_OK) return s;
-  if (nrec > 0 && !seis) return fail(WFD_E_ARG, "seismogram output is NULL");
   if (!work) return fail(WFD_E_ARG, "workspace is NULL");
   if ((uintptr_t)work % kAlign) return fail(WFD_E_ARG, "workspace must be 256-byte aligned");
-  Work w = work_layout(c, nrec, nullptr, 0, work);
+  Work w = work_layout(c, nrec, with_misfit ? WorkKind::Misfit : WorkKind::Forward, nullptr, 0,
+                       work);
   if (work_bytes < w.bytes)
     return fail(WFD_E_NOMEM, "workspace has %zu bytes, %zu needed", work_bytes, w.bytes);
   ScopedDevice sd(c->device);
@@ -572,9 +592,19 @@ wfd_status wfd_forward(wfd_ctx *c, const float *wavelet, const double src_xyz[3]
     }
     std::swap(cur, prev);
   }
-  if (nrec > 0) {
+  if (nrec > 0 && seis) {
     Timed t(c, WFD_K_OTHER);
     HIP_TRY(wfd::launch_transpose(w.seis_tm, seis, nrec, c->grid.nt, c->stream));
+  }
+  if (with_misfit && nrec > 0) {
+    int np = 0;
+    {
+      Timed t(c, WFD_K_OTHER);
+      HIP_TRY(wfd::launch_residual(w.seis_tm, dobs, w.rec_adj, nrec, c->grid.nt, w.res_tm,
+                                   w.partial, &np, c->stream));
+    }
+    Timed t(c, WFD_K_OTHER);
+    HIP_TRY(wfd::launch_sum_partials(w.partial, np, misfit, c->stream));
   }
   if (final_dev) {
     const size_t row = (size_t)c->Nx * sizeof(float);
@@ -585,6 +615,26 @@ wfd_status wfd_forward(wfd_ctx *c, const float *wavelet, const double src_xyz[3]
                              (size_t)c->Ny * c->Nz, hipMemcpyDeviceToDevice, c->stream));
   }
   return WFD_OK;
+}
+
+}  // namespace
+
+wfd_status wfd_forward(wfd_ctx *c, const float *wavelet, const double src_xyz[3], int32_t nrec,
+                       const double *rec_xyz, float *seis, float *final_dev, void *work,
+                       size_t work_bytes) {
+  if (c && nrec > 0 && !seis) return fail(WFD_E_ARG, "seismogram output is NULL");
+  return forward_core(c, wavelet, src_xyz, nrec, rec_xyz, seis, final_dev, nullptr, nullptr,
+                      work, work_bytes, false);
+}
+
+wfd_status wfd_forward_misfit(wfd_ctx *c, const float *wavelet, const double src_xyz[3],
+                              int32_t nrec, const double *rec_xyz, const float *dobs,
+                              float *seis_or_null, double *misfit, void *work,
+                              size_t work_bytes) {
+  if (c && nrec > 0 && !dobs) return fail(WFD_E_ARG, "observed data is NULL");
+  if (c && !misfit) return fail(WFD_E_ARG, "misfit output is NULL");
+  return forward_core(c, wavelet, src_xyz, nrec, rec_xyz, seis_or_null, nullptr, dobs, misfit,
+                      work, work_bytes, true);
 }
 
 wfd_status wfd_gradient(wfd_ctx *c, const float *wavelet, const double src_xyz[3], int32_t nrec,
@@ -610,14 +660,15 @@ wfd_status wfd_gradient(wfd_ctx *c, const float *wavelet, const double src_xyz[3
     nsnap = ck->n_snapshots;
   } else {
     // derived count: as many pairs as the given workspace holds
-    const size_t base = work_layout(c, nrec, ck, 0, nullptr).bytes;
+    const size_t base = work_layout(c, nrec, WorkKind::Gradient, ck, 0, nullptr).bytes;
     const size_t pair = align_up((size_t)c->vol * sizeof(float)) * 2;
     nsnap = work_bytes > base ? (int64_t)((work_bytes - base) / pair) : 0;
     nsnap = std::min<int64_t>(nsnap, c->grid.nt);
     if (nsnap < 1) return fail(WFD_E_NOMEM, "workspace holds no checkpoint pair");
-    while (nsnap > 1 && work_layout(c, nrec, ck, nsnap, nullptr).bytes > work_bytes) --nsnap;
+    while (nsnap > 1 && work_layout(c, nrec, WorkKind::Gradient, ck, nsnap, nullptr).bytes > work_bytes)
+      --nsnap;
   }
-  Work w = work_layout(c, nrec, ck, nsnap, work);
+  Work w = work_layout(c, nrec, WorkKind::Gradient, ck, nsnap, work);
   if (work_bytes < w.bytes)
     return fail(WFD_E_NOMEM, "workspace has %zu bytes, %zu needed", work_bytes, w.bytes);
   int64_t src_idx = 0;

@@ -1,0 +1,270 @@
+"""Full waveform inversion on top of the library (paper Alg. 2, FWI::run).
+
+* ``WaveFn`` — a ``torch.autograd.Function`` from a velocity volume to the
+  total misfit of a set of shots.  Its forward pass runs the library's
+  one-shot gradient for every shot (forward sweep, misfit, adjoint sweep and
+  imaging, Alg. 3) and keeps the accumulated dJ/dv for the backward pass, so
+  ``loss.backward()`` costs nothing more.
+* ``fwi`` — the outer loop of Alg. 2 with two model-update rules:
+  steepest descent on the illumination-compensated gradient
+  g / (I + eps max I) with a quadratic line search (exact slope plus one
+  trial misfit), and a projected L-BFGS
+  (velocity bounds as in the paper's example, which bounds velocity between
+  2000 and 3500 m/s) with the same preconditioner as its initial inverse
+  Hessian and an Armijo backtracking line search.  Trial misfits use the
+  library's forward-only misfit; every accepted point gets one gradient.
+
+All wave-equation arithmetic runs in the HIP library; this module only
+composes calls and does the O(model size) optimizer algebra in torch.
+"""
+
+from __future__ import annotations
+
+import time
+from dataclasses import dataclass, field
+from typing import List, Optional, Sequence, Tuple
+
+import numpy as np
+
+from .api import GridSpec, Propagator
+
+
+@dataclass
+class Shots:
+    """Acquisition: one wavelet, per-shot source positions, receivers and data."""
+    wavelet: "object"                  # torch float32 [nt] on the device
+    sources: np.ndarray                # [nshot][3] metres
+    receivers: Sequence[np.ndarray]    # per shot [nrec][3] metres
+    dobs: Sequence["object"]           # per shot torch float32 [nrec][nt] on the device
+
+    def __len__(self):
+        return len(self.sources)
+
+
+def auto_checkpoint(prop: Propagator, nrec: int, fraction: float = 0.8):
+    """Full storage when it fits in `fraction` of the free device memory,
+    else binomial checkpointing sized to that memory (the paper's check_mem)."""
+    import torch
+    free, _ = torch.cuda.mem_get_info(prop.device)
+    if prop.workspace_bytes(nrec, "full") <= fraction * free:
+        return "full"
+    return ("revolve", 0, fraction)
+
+
+class WaveFn:
+    """Velocity -> total misfit over shots, differentiable through the library."""
+
+    @staticmethod
+    def apply(vel, prop: Propagator, grid: GridSpec, rho, shots: Shots, ckpt="auto",
+              illum=None):
+        import torch
+
+        class _Fn(torch.autograd.Function):
+            @staticmethod
+            def forward(ctx, v):
+                J, g = evaluate(prop, grid, v.detach(), rho, shots, ckpt=ckpt, illum=illum)
+                ctx.save_for_backward(g)
+                return J
+
+            @staticmethod
+            def backward(ctx, gout):
+                (g,) = ctx.saved_tensors
+                return gout.to(g.dtype) * g
+
+        return _Fn.apply(vel)
+
+
+def evaluate(prop: Propagator, grid: GridSpec, vel, rho, shots: Shots, ckpt="auto",
+             illum=None, zero_top_planes: int = 0):
+    """(misfit, dJ/dv) summed over shots; illum (if given) accumulates sum (w^n)^2."""
+    import torch
+    prop.set_model(grid, vel.contiguous(), rho)
+    misfit = torch.zeros((), dtype=torch.float64, device=prop.device)
+    grad = torch.zeros_like(vel)
+    for s in range(len(shots)):
+        rec = shots.receivers[s]
+        ck = auto_checkpoint(prop, len(rec)) if ckpt == "auto" else ckpt
+        prop.gradient(shots.wavelet, shots.sources[s], rec, shots.dobs[s], ckpt=ck, grad=grad,
+                      misfit=misfit, illum=illum)
+    if zero_top_planes:
+        prop.gradient_finish(grad, zero_top_planes)
+    return misfit, grad
+
+
+def misfit_only(prop: Propagator, grid: GridSpec, vel, rho, shots: Shots):
+    """Total misfit from forward sweeps only."""
+    import torch
+    prop.set_model(grid, vel.contiguous(), rho)
+    misfit = torch.zeros((), dtype=torch.float64, device=prop.device)
+    for s in range(len(shots)):
+        prop.forward_misfit(shots.wavelet, shots.sources[s], shots.receivers[s], shots.dobs[s],
+                            misfit=misfit)
+    return misfit
+
+
+def illumination_compensate(grad, illum, eps: float = 1.0e-3):
+    """g / (I + eps * max I): the plain illumination-compensated gradient."""
+    return grad / (illum + eps * illum.max())
+
+
+@dataclass
+class FwiTrace:
+    method: str
+    gpu_seconds: List[float] = field(default_factory=list)
+    misfit: List[float] = field(default_factory=list)
+    n_gradients: int = 0
+    n_misfits: int = 0
+
+    def record(self, t: float, J: float):
+        self.gpu_seconds.append(t)
+        self.misfit.append(J)
+
+    def misfit_cut_per_gpu_s(self) -> float:
+        """Relative misfit reduction per GPU-second over the whole run."""
+        if len(self.misfit) < 2 or self.gpu_seconds[-1] <= 0:
+            return 0.0
+        return (1.0 - self.misfit[-1] / self.misfit[0]) / self.gpu_seconds[-1]
+
+    def time_to_reach(self, rel_misfit: float) -> Optional[float]:
+        """GPU-seconds until misfit <= rel_misfit * initial misfit."""
+        for t, J in zip(self.gpu_seconds, self.misfit):
+            if J <= rel_misfit * self.misfit[0]:
+                return t
+        return None
+
+
+def _dot(a, b) -> float:
+    """Inner product in FP64 (gradients of the misfit are ~1e-20 and smaller)."""
+    import torch
+    return float(torch.sum(a.double() * b.double()))
+
+
+def _quadratic_step(J_at, v, d, J0, gd, a1, bounds):
+    """Step length along d from the quadratic J(a) ~ J0 + gd a + c a^2 fixed by
+    the exact slope gd = <g, d> and one trial J(a1) (backtracking first if the
+    trial does not lower J); returns the better of the evaluated steps, or None."""
+    J1 = J_at(_project(v + a1 * d, bounds))
+    for _ in range(6):
+        if J1 < J0:
+            break
+        a1 *= 0.25
+        J1 = J_at(_project(v + a1 * d, bounds))
+    best = (J1, a1)
+    c = (J1 - J0 - gd * a1) / (a1 * a1)
+    if c > 0:
+        a_star = min(-gd / (2.0 * c), 50.0 * a1)
+        if abs(a_star - a1) > 0.05 * a1:
+            best = min(best, (J_at(_project(v + a_star * d, bounds)), a_star))
+    elif J1 < J0:  # no positive curvature seen: try a longer step
+        best = min(best, (J_at(_project(v + 4.0 * a1 * d, bounds)), 4.0 * a1))
+    return best[1] if best[0] < J0 else None
+
+
+def _project(v, bounds):
+    if bounds is None:
+        return v
+    return v.clamp(bounds[0], bounds[1])
+
+
+def fwi(prop: Propagator, grid: GridSpec, v0, rho, shots: Shots, *, n_iter: int = 10,
+        method: str = "sd", bounds: Optional[Tuple[float, float]] = None,
+        max_rel_step: float = 0.02, eps_illum: float = 1.0e-3, memory: int = 5,
+        ckpt="auto", zero_top_planes: int = 0):
+    """Alg. 2: repeat {gradient, model update} for n_iter iterations.
+
+    Returns (final velocity, FwiTrace).  GPU-seconds are wall time of the
+    synchronised GPU work (the device runs nothing else meanwhile).
+    """
+    import torch
+    trace = FwiTrace(method)
+    clock = [0.0]
+
+    def timed(fn, *a, **k):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        out = fn(*a, **k)
+        torch.cuda.synchronize()
+        clock[0] += time.perf_counter() - t0
+        return out
+
+    v = _project(v0.clone(), bounds)
+    illum = torch.zeros_like(v)
+
+    def grad_at(vv):
+        illum.zero_()
+        J, g = timed(evaluate, prop, grid, vv, rho, shots, ckpt=ckpt, illum=illum,
+                     zero_top_planes=zero_top_planes)
+        trace.n_gradients += 1
+        return float(J.item()), g
+
+    def J_at(vv):
+        trace.n_misfits += 1
+        return float(timed(misfit_only, prop, grid, vv, rho, shots).item())
+
+    J, g = grad_at(v)
+    trace.record(clock[0], J)
+    S, Y = [], []
+    for it in range(n_iter):
+        P = 1.0 / (illum + eps_illum * illum.max())      # preconditioner (diagonal)
+        if method == "lbfgs" and S:
+            # two-loop recursion with H0 = gamma * P
+            q = g.clone()
+            alphas = []
+            for s_, y_ in reversed(list(zip(S, Y))):
+                rho_k = 1.0 / _dot(y_, s_)
+                a = rho_k * _dot(s_, q)
+                alphas.append((a, rho_k, s_, y_))
+                q -= a * y_
+            sy, yPy = _dot(S[-1], Y[-1]), _dot(Y[-1] * P, Y[-1])
+            r = (sy / yPy) * P * q
+            for a, rho_k, s_, y_ in reversed(alphas):
+                b = rho_k * _dot(y_, r)
+                r += (a - b) * s_
+            d = -r
+            alpha0 = 1.0
+        else:
+            d = -P * g
+            alpha0 = max_rel_step * float(v.abs().max()) / float(d.abs().max())
+        gd = _dot(g, d)
+        if gd >= 0:  # not a descent direction: restart from the preconditioned gradient
+            S, Y = [], []
+            d = -P * g
+            alpha0 = max_rel_step * float(v.abs().max()) / float(d.abs().max())
+            gd = _dot(g, d)
+        if method == "lbfgs" and not S:
+            # no curvature pairs yet: same quadratic step as steepest descent
+            alpha = _quadratic_step(J_at, v, d, J, gd, alpha0, bounds)
+            if alpha is None:
+                trace.record(clock[0], J)
+                continue
+        elif method == "lbfgs":
+            # Armijo backtracking; no acceptable step leaves the model unchanged
+            alpha, ok = alpha0, False
+            for _ in range(10):
+                Jt = J_at(_project(v + alpha * d, bounds))
+                if Jt <= J + 1e-4 * alpha * gd:
+                    ok = True
+                    break
+                alpha *= 0.5
+            if not ok:
+                S, Y = [], []
+                trace.record(clock[0], J)
+                continue
+        else:
+            alpha = _quadratic_step(J_at, v, d, J, gd, alpha0, bounds)
+            if alpha is None:  # no decrease found: stop updating
+                trace.record(clock[0], J)
+                continue
+        v_new = _project(v + alpha * d, bounds)
+        J_new, g_new = grad_at(v_new)
+        if method == "lbfgs":
+            s_, y_ = v_new - v, g_new - g
+            if _dot(s_, y_) > 0:
+                S.append(s_)
+                Y.append(y_)
+                if len(S) > memory:
+                    S.pop(0)
+                    Y.pop(0)
+        v, J, g = v_new, J_new, g_new
+        trace.record(clock[0], J)
+    return v, trace
