@@ -191,6 +191,72 @@ def fwi_bench(n_iter: int):
     print(json.dumps(out), flush=True)
 
 
+def batch_bench(steps: int, warmup: int, autotune: bool):
+    """Batched multi-shot forward: 24 shots on the 400x400x256 variable-density
+    model, each on its own aperture window (sides 160-320 cells, clipped),
+    32-cell sponge, 1500 steps.  Compares one wfd_forward per shot with one
+    launch per step over all windows, eager and replayed as a HIP graph."""
+    import torch
+    import seisgen
+    from paper_2502_12350_amd import GridSpec, Propagator, ShotBatch
+
+    w = seisgen.workload("c3")
+    shots = [seisgen.shot_window(w, i) for i in range(len(w.sources))]
+    dev = torch.device("cuda", 0)
+    stream = torch.cuda.Stream()
+    props = []
+    for s in shots:
+        P = Propagator(0)
+        P.set_model(GridSpec(**s.grid_kwargs()), torch.from_numpy(s.vel).to(dev),
+                    torch.from_numpy(s.rho).to(dev))
+        props.append(P)
+    wav = torch.from_numpy(w.wavelet).to(dev)
+    pts = sum(s.padded_points for s in shots)
+    print(f"[bench-batch] {len(shots)} windows, {pts / 1e6:.1f} M padded points, nt {w.nt}",
+          file=sys.stderr, flush=True)
+    tuned = None
+    if autotune:
+        tuned = [P.autotune(steps=10) for P in props]
+        print(f"[bench-batch] autotuned {tuned}", file=sys.stderr, flush=True)
+    with torch.cuda.stream(stream):
+        batch = ShotBatch(props, wav, [s.sources[0] for s in shots], [s.receivers for s in shots],
+                          stream=stream)
+
+        def per_shot():
+            for s, P in zip(shots, props):
+                P.forward(wav, s.sources[0], s.receivers)
+
+        modes = {"per_shot": per_shot, "batched_eager": lambda: batch.run(use_graph=False),
+                 "batched_graph": lambda: batch.run(use_graph=True)}
+        res = {}
+        for name, fn in modes.items():
+            for _ in range(warmup):
+                fn()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for i in range(steps):
+                fn()
+                torch.cuda.synchronize()
+                print(f"[bench-batch] {name} step {i + 1}/{steps} done", file=sys.stderr,
+                      flush=True)
+            dt = (time.perf_counter() - t0) / steps
+            res[name] = {"ms_per_pass": round(dt * 1e3, 2), "gpts": round(pts * w.nt / dt / 1e9, 2)}
+    out = {"metric": "batched multi-shot forward throughput", "unit": "Gpt/s",
+           "value": res["batched_graph"]["gpts"], "higher_is_better": True, "n_gpus": 1,
+           "steps": steps, "warmup": warmup, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": "24 shots, 400x400x256 variable-density model, per-shot "
+                                  "aperture windows of side 160-320 cells (clipped), 32-cell "
+                                  "sponge, 1500 steps",
+                      "padded_points_all_windows": pts,
+                      "tile_variant": props[0].tuning()[0],
+                      "autotuned": tuned},
+           "modes": res,
+           "speedup_graph_vs_per_shot": round(res["batched_graph"]["gpts"] /
+                                              res["per_shot"]["gpts"], 3)}
+    batch.close()
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -203,6 +269,10 @@ def main():
     ap.add_argument("--copy-probe", action="store_true")
     ap.add_argument("--fwi", type=int, default=0, metavar="ITERS",
                     help="run the FWI benchmark with this many iterations per method instead")
+    ap.add_argument("--batch", action="store_true",
+                    help="run the batched multi-shot forward benchmark instead")
+    ap.add_argument("--autotune", action="store_true",
+                    help="with --batch: autotune each window's launch shape first")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -216,6 +286,9 @@ def main():
         return
     if args.fwi:
         fwi_bench(args.fwi)
+        return
+    if args.batch:
+        batch_bench(max(args.steps, 1), args.warmup, args.autotune)
         return
 
     import numpy as np

@@ -172,6 +172,67 @@ wfd_status wfd_gradient(wfd_ctx *ctx, const float *wavelet_dev, const double src
  * `zero_top_planes` z-planes of grad_dev [nz][ny][nx] to zero. */
 wfd_status wfd_gradient_finish(wfd_ctx *ctx, float *grad_dev, int32_t zero_top_planes);
 
+/* ---- launch tuning and batched shots ------------------------------------ */
+
+/* Forward-kernel launch shape of the context (the paper's per-architecture
+ * CUDA_BLOCK_SIZE choice, re-done for CDNA4 tiles):
+ *   variant 0: 64 x 16 tiles (4 rows per thread, 4 wavefronts)  [default]
+ *           1: 64 x 8 tiles  (2 rows per thread, 4 wavefronts)
+ *           2: 64 x 32 tiles (4 rows per thread, 8 wavefronts)
+ *   rounds     z-chunking aims at this many rounds of resident blocks per
+ *              launch (0 = default 4; at most 64).
+ * Every shape computes bitwise the same result; only speed differs. */
+wfd_status wfd_set_tuning(wfd_ctx *ctx, int32_t variant, int32_t rounds);
+wfd_status wfd_get_tuning(const wfd_ctx *ctx, int32_t *variant, int32_t *rounds);
+
+/* Time `steps` forward steps (no source, no receivers) for each variant in
+ * {0, 1, 2} x rounds in {2, 4, 8} on the context's model with HIP events,
+ * keep the fastest in the context and return it (any output may be NULL).
+ *   work_dev, work_bytes  workspace of at least wfd_workspace_bytes(nrec=0,
+ *                         NULL); its two field volumes are overwritten.
+ * Waits on the stream. */
+wfd_status wfd_autotune(wfd_ctx *ctx, int32_t steps, void *work_dev, size_t work_bytes,
+                        int32_t *variant, int32_t *rounds, double *us_per_step);
+
+/* A batch of shots whose forward sweeps (Alg. 1) run together: each time
+ * step is ONE kernel launch over the tiles of every shot, so small grids
+ * (windowed shots, a sub-volume per source) fill the device.  Each shot has
+ * its own context (model on its own grid, e.g. the window around its source)
+ * and its own workspace; results are bitwise those of wfd_forward on each
+ * context.
+ *   nshot            1..64;
+ *   ctxs[i]          contexts with a model, all on one device and stream,
+ *                    with equal nt and the same density mode (all constant
+ *                    or all variable), each used once;
+ *   wavelet_dev      [nt] FP32 source signature shared by all shots, device;
+ *   src_xyz          host [nshot][3] source positions (in shot i's grid);
+ *   nrec, rec_xyz    host per-shot receiver counts and [nrec[i]][3] arrays;
+ *   seis_dev         per-shot [nrec[i]][nt] FP32 output traces, device;
+ *   work_dev[i], work_bytes[i]  per-shot workspace of at least
+ *                    wfd_workspace_bytes(ctxs[i], nrec[i], NULL), 256-byte
+ *                    aligned; shot 0's also holds the batch's step
+ *                    descriptors.
+ * Receiver tables are built and uploaded here, so a run repeats the same
+ * acquisition.  Contexts, models, wavelet, workspaces and outputs must stay
+ * allocated until wfd_batch_destroy; the contexts' tuning variant at creation
+ * time (shot 0's) is used for every shot. */
+typedef struct wfd_batch wfd_batch;
+wfd_status wfd_batch_create(wfd_batch **batch, int32_t nshot, wfd_ctx *const *ctxs,
+                            const float *wavelet_dev, const double *src_xyz,
+                            const int32_t *nrec, const double *const *rec_xyz,
+                            float *const *seis_dev, void *const *work_dev,
+                            const size_t *work_bytes);
+
+/* Enqueue the whole batch (clear states, nt steps, trace transposes) on the
+ * stream.  use_graph != 0: the first call captures the sequence into a HIP
+ * graph (the stream must not be the legacy NULL stream and profiling must be
+ * off); every call launches that graph.  Asynchronous. */
+wfd_status wfd_batch_run(wfd_batch *batch, int32_t use_graph);
+
+/* Wait for the stream if a graph exists, release the batch (not the
+ * caller's buffers).  NULL is accepted. */
+wfd_status wfd_batch_destroy(wfd_batch *batch);
+
 /* ---- host-only helpers (no GPU needed) --------------------------------- */
 
 /* Padded-grid node (ix, iy, iz) of a position in metres (rule above). */

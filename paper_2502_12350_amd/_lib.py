@@ -54,6 +54,16 @@ _SIGS = {
     "wfd_gradient": (C.c_int, [_P, _P, _D3, C.c_int32, _D3, _P, C.POINTER(wfd_ckpt), _P, _P,
                                _P, _P, _P, C.c_size_t]),
     "wfd_gradient_finish": (C.c_int, [_P, _P, C.c_int32]),
+    "wfd_set_tuning": (C.c_int, [_P, C.c_int32, C.c_int32]),
+    "wfd_get_tuning": (C.c_int, [_P, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
+    "wfd_autotune": (C.c_int, [_P, C.c_int32, _P, C.c_size_t, C.POINTER(C.c_int32),
+                               C.POINTER(C.c_int32), C.POINTER(C.c_double)]),
+    "wfd_batch_create": (C.c_int, [C.POINTER(C.c_void_p), C.c_int32, C.POINTER(C.c_void_p), _P,
+                                   _D3, C.POINTER(C.c_int32), C.POINTER(_D3),
+                                   C.POINTER(C.c_void_p), C.POINTER(C.c_void_p),
+                                   C.POINTER(C.c_size_t)]),
+    "wfd_batch_run": (C.c_int, [_P, C.c_int32]),
+    "wfd_batch_destroy": (C.c_int, [_P]),
     "wfd_map_position": (C.c_int, [C.POINTER(wfd_grid), _D3, C.POINTER(C.c_int32)]),
     "wfd_cfl_ratio": (C.c_int, [C.POINTER(wfd_grid), C.c_double, C.c_double, _D3]),
     "wfd_checkpoint_plan": (C.c_int, [C.c_int32, C.c_int32, C.POINTER(C.c_int32), C.c_int64,

@@ -291,6 +291,28 @@ class Propagator:
         check(self.L.wfd_gradient_finish(self._ctx, _ptr(grad), int(zero_top_planes)))
         return grad
 
+    # launch tuning -----------------------------------------------------------
+    def set_tuning(self, variant: int, rounds: int = 0):
+        """Forward tile shape (0: 64x16, 1: 64x8, 2: 64x32) and z-chunk rounds."""
+        check(self.L.wfd_set_tuning(self._ctx, int(variant), int(rounds)))
+
+    def tuning(self) -> Tuple[int, int]:
+        v, r = C.c_int32(), C.c_int32()
+        check(self.L.wfd_get_tuning(self._ctx, C.byref(v), C.byref(r)))
+        return v.value, r.value
+
+    def autotune(self, steps: int = 20) -> Tuple[int, int, float]:
+        """Time every launch shape on the current model, keep the fastest;
+        returns (variant, rounds, microseconds per step)."""
+        if self.grid is None:
+            raise RuntimeError("set_model first")
+        wptr, wbytes = self._workspace(self.workspace_bytes(0))
+        self._sync_stream()
+        v, r, us = C.c_int32(), C.c_int32(), C.c_double()
+        check(self.L.wfd_autotune(self._ctx, int(steps), wptr, wbytes, C.byref(v), C.byref(r),
+                                  C.byref(us)))
+        return v.value, r.value, us.value
+
     # measurement -------------------------------------------------------------
     def set_profiling(self, on: bool):
         check(self.L.wfd_set_profiling(self._ctx, int(bool(on))))
@@ -299,3 +321,70 @@ class Propagator:
         n, ms = C.c_int64(), C.c_double()
         check(self.L.wfd_kernel_stats(self._ctx, int(kernel_class), C.byref(n), C.byref(ms)))
         return n.value, ms.value
+
+
+class ShotBatch:
+    """Forward sweeps of several shots advanced together (one launch per step
+    over all shots' tiles), optionally replayed as one HIP graph.
+
+    Each shot has its own Propagator (its own model, typically the window
+    around its source) on one device; all of them launch on `stream` (torch's
+    current stream if None; graph replay needs a non-default stream).
+    """
+
+    def __init__(self, props: Sequence[Propagator], wavelet, src_xyz, rec_xyz, stream=None):
+        if not props:
+            raise ValueError("no shots")
+        torch = props[0].torch
+        p0 = props[0]
+        self.torch = torch
+        self.props = list(props)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(p0.device)
+        nt = p0.grid.nt if p0.grid is not None else 0
+        self.wavelet = p0._dev(wavelet, "wavelet", (nt,), torch.float32)
+        n = len(self.props)
+        if len(src_xyz) != n or len(rec_xyz) != n:
+            raise ValueError("one source and one receiver array per shot")
+        self._src = np.ascontiguousarray(np.concatenate([_xyz(s) for s in src_xyz]),
+                                         dtype=np.float64)
+        self._rec = [_xyz(r) if r is not None and len(r) else np.zeros((0, 3)) for r in rec_xyz]
+        nrec = [r.shape[0] for r in self._rec]
+        self.seis = [torch.empty((k, nt), dtype=torch.float32, device=p0.device) for k in nrec]
+        self._work = []
+        ctxs = (C.c_void_p * n)()
+        works = (C.c_void_p * n)()
+        wbytes = (C.c_size_t * n)()
+        seisp = (C.c_void_p * n)()
+        recp = (_lib._D3 * n)()
+        for i, p in enumerate(self.props):
+            if p.grid is None:
+                raise RuntimeError(f"shot {i}: set_model first")
+            check(p.L.wfd_set_stream(p._ctx, C.c_void_p(self.stream.cuda_stream)))
+            nb = p.workspace_bytes(nrec[i])
+            buf, ptr = p._buffer(nb)
+            self._work.append(buf)
+            ctxs[i], works[i], wbytes[i] = p._ctx.value, ptr, nb
+            seisp[i] = _ptr(self.seis[i]) if nrec[i] else None
+            if nrec[i]:
+                recp[i] = _dptr(self._rec[i])
+        nr = (C.c_int32 * n)(*nrec)
+        self._b = C.c_void_p()
+        check(p0.L.wfd_batch_create(C.byref(self._b), n, ctxs, _ptr(self.wavelet),
+                                    _dptr(self._src), nr, recp, seisp, works, wbytes))
+        self.L = p0.L
+
+    def run(self, use_graph: bool = False):
+        """Enqueue all shots on the batch stream; returns the per-shot traces."""
+        check(self.L.wfd_batch_run(self._b, int(bool(use_graph))))
+        return self.seis
+
+    def close(self):
+        if getattr(self, "_b", None):
+            check(self.L.wfd_batch_destroy(self._b))
+            self._b = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -56,6 +56,7 @@ struct Carve {
 };
 
 constexpr int kReducePartials = 1024;
+constexpr int kMaxBatch = 64;  // shots per wfd_batch
 
 }  // namespace
 
@@ -77,6 +78,8 @@ struct wfd_ctx {
   hipEvent_t upload_done = nullptr;
   bool upload_pending = false;
 
+  wfd::Tuning tuning;  // forward tile shape / z chunking (wfd_set_tuning, wfd_autotune)
+
   // profiling
   bool prof = false;
   std::vector<hipEvent_t> pool;
@@ -84,6 +87,22 @@ struct wfd_ctx {
   std::vector<int> rec_class;  // class of event pair i (pool[2i], pool[2i+1])
   int64_t launches[WFD_K_COUNT] = {0, 0, 0};
   double ms[WFD_K_COUNT] = {0, 0, 0};
+};
+
+// A set of shots advanced together: one launch per time step covers every
+// shot's window (its own context, model and workspace); the time loop can be
+// captured once into a HIP graph and replayed.
+struct wfd_batch {
+  std::vector<wfd_ctx *> ctxs;
+  std::vector<float *> W1, W2, seis_tm, seis_out;
+  std::vector<int> nrec;
+  wfd::WindowStep *d_wins[2] = {nullptr, nullptr};  // device descriptors per step parity
+  std::vector<wfd::WindowStep> h_wins[2];
+  int nblocks = 0, variant = 0, nt = 0;
+  bool vd = false;
+  hipStream_t stream = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
 };
 
 namespace {
@@ -206,6 +225,7 @@ struct Work {
   float *sigma, *rec_scale, *rec_adj;
   float *seis_tm;
   float *W1, *W2;
+  wfd::WindowStep *wins;  // batch step descriptors (two parities x kMaxBatch)
   // gradient only
   float *res_tm, *P1, *P2, *g, *store;
   double *partial;
@@ -245,6 +265,7 @@ Work work_layout(const wfd_ctx *c, int nrec, WorkKind kind, const wfd_ckpt *ck, 
   w.seis_tm = cv.take<float>((size_t)c->grid.nt * std::max(nrec, 1));
   w.W1 = cv.take<float>((size_t)c->vol);
   w.W2 = cv.take<float>((size_t)c->vol);
+  w.wins = kind == WorkKind::Forward ? cv.take<wfd::WindowStep>(2 * kMaxBatch) : nullptr;
   if (kind != WorkKind::Forward) {
     w.res_tm = cv.take<float>((size_t)c->grid.nt * std::max(nrec, 1));
     w.partial = cv.take<double>((size_t)std::max(1, wfd::residual_partial_count(nrec, c->grid.nt)));
@@ -588,7 +609,7 @@ wfd_status forward_core(wfd_ctx *c, const float *wavelet, const double src_xyz[3
     {
       Timed t(c, WFD_K_FORWARD);
       HIP_TRY(wfd::launch_forward_step(g, cur, prev, prev, src, n, nrec > 0 ? &rt : nullptr,
-                                       w.rec_scale, w.seis_tm, c->stream));
+                                       w.rec_scale, w.seis_tm, c->tuning, c->stream));
     }
     std::swap(cur, prev);
   }
@@ -718,7 +739,7 @@ wfd_status wfd_gradient(wfd_ctx *c, const float *wavelet, const double src_xyz[3
     Timed t(c, WFD_K_FORWARD);
     HIP_TRY(wfd::launch_forward_step(g, cur, prev, out, src, n,
                                      (rec && nrec > 0) ? &rt : nullptr, w.rec_scale, w.seis_tm,
-                                     c->stream));
+                                     c->tuning, c->stream));
     return WFD_OK;
   };
 
@@ -833,6 +854,239 @@ wfd_status wfd_gradient_finish(wfd_ctx *c, float *grad, int32_t zero_top_planes)
   if (zero_top_planes == 0) return WFD_OK;
   ScopedDevice sd(c->device);
   return zero(c, grad, (int64_t)zero_top_planes * c->grid.ny * c->grid.nx);
+}
+
+wfd_status wfd_set_tuning(wfd_ctx *c, int32_t variant, int32_t rounds) {
+  if (!c) return fail(WFD_E_ARG, "ctx is NULL");
+  if (variant < 0 || variant > 2) return fail(WFD_E_ARG, "tile variant must be 0, 1 or 2");
+  if (rounds < 0 || rounds > 64) return fail(WFD_E_ARG, "rounds must be in [0, 64]");
+  c->tuning.variant = variant;
+  c->tuning.rounds = rounds;
+  return WFD_OK;
+}
+
+wfd_status wfd_get_tuning(const wfd_ctx *c, int32_t *variant, int32_t *rounds) {
+  if (!c || !variant || !rounds) return fail(WFD_E_ARG, "NULL argument");
+  *variant = c->tuning.variant;
+  *rounds = c->tuning.rounds;
+  return WFD_OK;
+}
+
+wfd_status wfd_autotune(wfd_ctx *c, int32_t steps, void *work, size_t work_bytes,
+                        int32_t *variant, int32_t *rounds, double *us_per_step) {
+  if (!c) return fail(WFD_E_ARG, "ctx is NULL");
+  if (!c->has_model) return fail(WFD_E_STATE, "no model: call wfd_set_model first");
+  if (steps < 1) return fail(WFD_E_ARG, "steps must be >= 1");
+  if (!work) return fail(WFD_E_ARG, "workspace is NULL");
+  if ((uintptr_t)work % kAlign) return fail(WFD_E_ARG, "workspace must be 256-byte aligned");
+  Work w = work_layout(c, 0, WorkKind::Forward, nullptr, 0, work);
+  if (work_bytes < w.bytes)
+    return fail(WFD_E_NOMEM, "workspace has %zu bytes, %zu needed", work_bytes, w.bytes);
+  ScopedDevice sd(c->device);
+  wfd_status s;
+  if ((s = zero(c, w.W1, c->vol)) != WFD_OK) return s;
+  if ((s = zero(c, w.W2, c->vol)) != WFD_OK) return s;
+  const wfd::StepGrid g = step_grid(c);
+  // index -1 matches no point: nothing is injected (the pointers stay valid)
+  const wfd::Source none_src{-1, w.sigma, w.sigma};
+  hipEvent_t e0, e1;
+  HIP_TRY(hipEventCreate(&e0));
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return fail(WFD_E_HIP, "hipEventCreate failed");
+  }
+  const int rounds_opts[] = {2, 4, 8};
+  float best = 3.0e38f;
+  wfd::Tuning best_t{0, 4};
+  hipError_t err = hipSuccess;
+  for (int v = 0; v < 3 && err == hipSuccess; ++v) {
+    for (int r : rounds_opts) {
+      const wfd::Tuning tu{v, r};
+      float *cur = w.W1, *prev = w.W2;
+      err = wfd::launch_forward_step(g, cur, prev, prev, none_src, 0, nullptr, nullptr, nullptr,
+                                     tu, c->stream);  // warm-up
+      std::swap(cur, prev);
+      if (err == hipSuccess) err = hipEventRecord(e0, c->stream);
+      for (int n = 0; n < steps && err == hipSuccess; ++n) {
+        err = wfd::launch_forward_step(g, cur, prev, prev, none_src, 0, nullptr, nullptr,
+                                       nullptr, tu, c->stream);
+        std::swap(cur, prev);
+      }
+      if (err == hipSuccess) err = hipEventRecord(e1, c->stream);
+      if (err == hipSuccess) err = hipEventSynchronize(e1);
+      float ms = 0.0f;
+      if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
+      if (err != hipSuccess) break;
+      if (ms < best) {
+        best = ms;
+        best_t = tu;
+      }
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (err != hipSuccess) return fail(WFD_E_HIP, "autotune: %s", hipGetErrorString(err));
+  c->tuning = best_t;
+  if (variant) *variant = best_t.variant;
+  if (rounds) *rounds = best_t.rounds;
+  if (us_per_step) *us_per_step = 1e3 * (double)best / steps;
+  return WFD_OK;
+}
+
+wfd_status wfd_batch_create(wfd_batch **out, int32_t nshot, wfd_ctx *const *ctxs,
+                            const float *wavelet, const double *src_xyz, const int32_t *nrec,
+                            const double *const *rec_xyz, float *const *seis,
+                            void *const *work, const size_t *work_bytes) {
+  if (!out) return fail(WFD_E_ARG, "batch pointer is NULL");
+  *out = nullptr;
+  if (nshot < 1 || nshot > kMaxBatch)
+    return fail(WFD_E_ARG, "batch size must be in [1, %d] (got %d)", kMaxBatch, nshot);
+  if (!ctxs || !src_xyz || !nrec || !work || !work_bytes || !wavelet)
+    return fail(WFD_E_ARG, "NULL argument");
+  wfd_ctx *c0 = ctxs[0];
+  for (int i = 0; i < nshot; ++i) {
+    wfd_ctx *c = ctxs[i];
+    if (!c || !c->has_model) return fail(WFD_E_STATE, "shot %d: context without a model", i);
+    if (c->device != c0->device) return fail(WFD_E_ARG, "shot %d: other device", i);
+    if (c->stream != c0->stream) return fail(WFD_E_ARG, "shot %d: contexts must share one stream", i);
+    if (c->grid.nt != c0->grid.nt) return fail(WFD_E_ARG, "shot %d: nt differs", i);
+    if (c->vd != c0->vd) return fail(WFD_E_ARG, "shot %d: density mode differs", i);
+    if (nrec[i] < 0 || (nrec[i] > 0 && (!rec_xyz || !rec_xyz[i] || !seis || !seis[i])))
+      return fail(WFD_E_ARG, "shot %d: receivers / output missing", i);
+    if (!work[i] || (uintptr_t)work[i] % kAlign)
+      return fail(WFD_E_ARG, "shot %d: workspace NULL or not 256-byte aligned", i);
+    for (int j = 0; j < i; ++j)
+      if (ctxs[j] == c) return fail(WFD_E_ARG, "shot %d: context used twice", i);
+  }
+  ScopedDevice sd(c0->device);
+  wfd_batch *b = new (std::nothrow) wfd_batch();
+  if (!b) return fail(WFD_E_NOMEM, "out of host memory");
+  b->stream = c0->stream;
+  b->nt = c0->grid.nt;
+  b->vd = c0->vd;
+  b->variant = c0->tuning.variant;
+  b->h_wins[0].resize(nshot);
+  b->h_wins[1].resize(nshot);
+  int offset = 0;
+  for (int i = 0; i < nshot; ++i) {
+    wfd_ctx *c = ctxs[i];
+    Work w = work_layout(c, nrec[i], WorkKind::Forward, nullptr, 0, work[i]);
+    if (work_bytes[i] < w.bytes) {
+      delete b;
+      return fail(WFD_E_NOMEM, "shot %d: workspace has %zu bytes, %zu needed", i, work_bytes[i],
+                  w.bytes);
+    }
+    int64_t src_idx = 0;
+    wfd_status s = prepare_shot(c, src_xyz + 3 * (size_t)i, nrec[i],
+                                nrec[i] > 0 ? rec_xyz[i] : nullptr, w, src_idx);
+    if (s != WFD_OK) {
+      delete b;
+      return s;
+    }
+    if (i == 0) {
+      b->d_wins[0] = w.wins;
+      b->d_wins[1] = w.wins + kMaxBatch;
+    }
+    // Each window keeps the tile map of its own launch (z chunks sized for the
+    // whole device); one launch then has a single tail instead of one per
+    // shot.  Measured on 24 windows of 173-300 cells: sizing the chunks for a
+    // 1/nshot share of the device instead makes full-depth columns, whose
+    // last round leaves the device idle longer.
+    wfd::Tuning tu = c->tuning;
+    tu.variant = b->variant;  // one tile shape per launch
+    wfd::WindowStep d{};
+    d.g = step_grid(c);
+    const int nb = wfd::forward_tile_map(d.g, tu, &d.map);
+    d.src = wfd::Source{src_idx, w.sigma, wavelet};
+    d.rec = rec_table(w, nrec[i]);
+    d.rec_scale = w.rec_scale;
+    d.seis_tm = nrec[i] > 0 ? w.seis_tm : nullptr;
+    d.block_begin = offset;
+    d.block_end = offset + nb;
+    offset += (nb + 7) / 8 * 8;
+    for (int p = 0; p < 2; ++p) {
+      wfd::WindowStep e = d;
+      e.cur = p == 0 ? w.W1 : w.W2;
+      e.prev = p == 0 ? w.W2 : w.W1;
+      e.out = const_cast<float *>(e.prev);
+      b->h_wins[p][i] = e;
+    }
+    b->ctxs.push_back(c);
+    b->W1.push_back(w.W1);
+    b->W2.push_back(w.W2);
+    b->seis_tm.push_back(w.seis_tm);
+    b->seis_out.push_back(nrec[i] > 0 ? seis[i] : nullptr);
+    b->nrec.push_back(nrec[i]);
+  }
+  b->nblocks = offset;
+  for (int p = 0; p < 2; ++p) {
+    if (hipMemcpyAsync(b->d_wins[p], b->h_wins[p].data(), nshot * sizeof(wfd::WindowStep),
+                       hipMemcpyHostToDevice, b->stream) != hipSuccess) {
+      delete b;
+      return fail(WFD_E_HIP, "descriptor upload failed");
+    }
+  }
+  if (hipStreamSynchronize(b->stream) != hipSuccess) {  // host descriptors may go now
+    delete b;
+    return fail(WFD_E_HIP, "hipStreamSynchronize failed");
+  }
+  *out = b;
+  return WFD_OK;
+}
+
+namespace {
+
+wfd_status batch_enqueue(wfd_batch *b) {
+  wfd_ctx *c0 = b->ctxs[0];
+  const int nwin = (int)b->ctxs.size();
+  for (int i = 0; i < nwin; ++i) {
+    HIP_TRY(wfd::launch_fill_zero(b->W1[i], b->ctxs[i]->vol, b->stream));
+    HIP_TRY(wfd::launch_fill_zero(b->W2[i], b->ctxs[i]->vol, b->stream));
+  }
+  for (int n = 0; n < b->nt; ++n) {
+    Timed t(c0, WFD_K_FORWARD);
+    HIP_TRY(wfd::launch_forward_multi(b->d_wins[n & 1], nwin, b->nblocks, n, b->variant, b->vd,
+                                      b->stream));
+  }
+  for (int i = 0; i < nwin; ++i)
+    if (b->nrec[i] > 0)
+      HIP_TRY(wfd::launch_transpose(b->seis_tm[i], b->seis_out[i], b->nrec[i], b->nt, b->stream));
+  return WFD_OK;
+}
+
+}  // namespace
+
+wfd_status wfd_batch_run(wfd_batch *b, int32_t use_graph) {
+  if (!b) return fail(WFD_E_ARG, "batch is NULL");
+  ScopedDevice sd(b->ctxs[0]->device);
+  if (!use_graph) return batch_enqueue(b);
+  if (!b->stream) return fail(WFD_E_ARG, "graph capture needs a non-default stream");
+  if (b->ctxs[0]->prof) return fail(WFD_E_STATE, "profiling events cannot be captured");
+  if (!b->exec) {
+    HIP_TRY(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
+    wfd_status s = batch_enqueue(b);
+    hipGraph_t graph = nullptr;
+    const hipError_t e = hipStreamEndCapture(b->stream, &graph);
+    if (s != WFD_OK) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return s;
+    }
+    if (e != hipSuccess) return fail(WFD_E_HIP, "hipStreamEndCapture: %s", hipGetErrorString(e));
+    b->graph = graph;
+    HIP_TRY(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
+  }
+  HIP_TRY(hipGraphLaunch(b->exec, b->stream));
+  return WFD_OK;
+}
+
+wfd_status wfd_batch_destroy(wfd_batch *b) {
+  if (!b) return WFD_OK;
+  ScopedDevice sd(b->ctxs[0]->device);
+  if (b->exec || b->graph) (void)hipStreamSynchronize(b->stream);
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  delete b;
+  return WFD_OK;
 }
 
 wfd_status wfd_map_position(const wfd_grid *grid, const double xyz[3], int32_t ijk[3]) {

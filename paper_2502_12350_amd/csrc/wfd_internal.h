@@ -38,10 +38,46 @@ struct Source {
   const float *wavelet;
 };
 
+// How a step kernel's blocks cover a grid: 64-wide tiles of `ty` rows,
+// z split into nchunks chunks of zc planes.
+struct TileMap {
+  int tiles_x, tiles_y, nchunks, zc, nblocks;
+};
+
+// Forward-kernel tuning: tile shape variant (0: 64x16 tiles of 4 rows per
+// thread, 1: 64x8 of 2 rows, 2: 64x32 of 4 rows in 8-wave blocks) and the
+// number of rounds of resident blocks the z chunking aims for (0 = 4).
+struct Tuning {
+  int variant = 0;
+  int rounds = 0;
+};
+
+// One shot's forward step inside a multi-window launch.
+struct WindowStep {
+  StepGrid g;
+  TileMap map;
+  const float *cur;
+  const float *prev;
+  float *out;
+  Source src;
+  RecTable rec;
+  const float *rec_scale;
+  float *seis_tm;
+  int block_begin, block_end;
+};
+
 // Kernel launchers; all enqueue on `stream` and return the launch status.
 hipError_t launch_forward_step(const StepGrid &g, const float *cur, const float *prev, float *out,
                                const Source &src, int n, const RecTable *rec,
-                               const float *rec_scale, float *seis_tm, hipStream_t stream);
+                               const float *rec_scale, float *seis_tm, const Tuning &tu,
+                               hipStream_t stream);
+
+// Blocks of one forward launch over g with tuning tu (and its tile map).
+int forward_tile_map(const StepGrid &g, const Tuning &tu, TileMap *map);
+
+// One step of every window in wins[0..nwin) (device array), nblocks blocks.
+hipError_t launch_forward_multi(const WindowStep *wins, int nwin, int nblocks, int n, int variant,
+                                bool vd, hipStream_t stream);
 
 hipError_t launch_adjoint_step(const StepGrid &g, const float *cur, const float *prev, float *out,
                                const RecTable &rec, const float *res_tm, int m,

@@ -29,10 +29,6 @@ constexpr float W4 = -1.0f / 560.0f;
 
 constexpr int TX = 64;  // tile width = one wavefront
 
-struct TileMap {
-  int tiles_x, tiles_y, nchunks, zc, nblocks;
-};
-
 // A tile is NW wavefronts, each owning RY consecutive rows of 64 points.
 template <int RY, int NW>
 struct Tile {
@@ -46,8 +42,8 @@ struct Tile {
 
 // Block -> (tile x, tile y, z chunk).  Logical tiles are numbered x fastest,
 // then y, then z chunk; XCD k (= blockIdx mod 8) gets one contiguous range.
-__device__ __forceinline__ void tile_of(const TileMap &m, int &tx, int &ty, int &tz) {
-  const int b = blockIdx.x, nb = m.nblocks;
+__device__ __forceinline__ void tile_of(const TileMap &m, int b, int &tx, int &ty, int &tz) {
+  const int nb = m.nblocks;
   const int per = nb / 8, rem = nb % 8;
   const int xcd = b % 8, slot = b / 8;
   const int logical =
@@ -178,9 +174,9 @@ struct Geo {
   bool hin[T::HPT];
   int hslot[T::HPT];
 
-  __device__ __forceinline__ bool init(const StepGrid &g, const TileMap &map) {
+  __device__ __forceinline__ bool init(const StepGrid &g, const TileMap &map, int b) {
     int tx, ty, tz;
-    tile_of(map, tx, ty, tz);
+    tile_of(map, b, tx, ty, tz);
     z0 = tz * map.zc;
     z1 = min(z0 + map.zc, g.nz);
     lane = threadIdx.x % TX;
@@ -231,17 +227,21 @@ struct ColCursor {
   }
 };
 
-// One leapfrog step; records the receivers of step n when seis_tm is set
-// (recomputation sweeps pass none).
+// One LDS plane of a tile with its halo.
+template <int RY, int NW>
+using LdsPlane = float[Tile<RY, NW>::LY][Tile<RY, NW>::LX];
+
+// One leapfrog step over tile block b of a grid; records the receivers of
+// step n when seis_tm is set (recomputation sweeps pass none).
 template <int RY, int NW, bool VD>
-__global__ void __launch_bounds__(TX * NW)
-    k_forward(StepGrid g, const float *__restrict__ cur, const float *prev, float *out,
-              Source src, int n, RecTable rec, const float *__restrict__ rec_scale,
-              float *__restrict__ seis_tm, TileMap map) {
+__device__ __forceinline__ void forward_tile(
+    LdsPlane<RY, NW> *sm, const StepGrid &g,
+    const float *__restrict__ cur, const float *prev, float *out, const Source &src, int n,
+    const RecTable &rec, const float *__restrict__ rec_scale, float *__restrict__ seis_tm,
+    const TileMap &map, int b) {
   using T = Tile<RY, NW>;
-  __shared__ float sm[2][T::LY][T::LX];
   Geo<RY, NW> geo;
-  if (!geo.init(g, map)) return;
+  if (!geo.init(g, map, b)) return;
   Marcher<RY, NW> f;
   f.prime(cur, g, geo.z0, geo.off, geo.in, geo.hoff, geo.hin);
   const float gxv = geo.x < g.nx ? g.gx[geo.x] : 0.0f;
@@ -310,6 +310,34 @@ __global__ void __launch_bounds__(TX * NW)
   }
 }
 
+template <int RY, int NW, bool VD>
+__global__ void __launch_bounds__(TX * NW)
+    k_forward(StepGrid g, const float *__restrict__ cur, const float *prev, float *out,
+              Source src, int n, RecTable rec, const float *__restrict__ rec_scale,
+              float *__restrict__ seis_tm, TileMap map) {
+  using T = Tile<RY, NW>;
+  __shared__ float sm[2][T::LY][T::LX];
+  forward_tile<RY, NW, VD>(sm, g, cur, prev, out, src, n, rec, rec_scale, seis_tm, map,
+                           blockIdx.x);
+}
+
+// Several grids (one per shot) advanced by one launch: block b belongs to the
+// window whose [block_begin, block_end) contains it.  Window ranges start at
+// multiples of 8 so that each window keeps the XCD-aware tile order.
+template <int RY, int NW, bool VD>
+__global__ void __launch_bounds__(TX * NW)
+    k_forward_multi(const WindowStep *__restrict__ wins, int nwin, int n) {
+  using T = Tile<RY, NW>;
+  __shared__ float sm[2][T::LY][T::LX];
+  const int b = blockIdx.x;
+  int w = 0;
+  while (w + 1 < nwin && b >= wins[w + 1].block_begin) ++w;
+  const WindowStep &d = wins[w];
+  if (b >= d.block_end) return;
+  forward_tile<RY, NW, VD>(sm, d.g, d.cur, d.prev, d.out, d.src, n, d.rec, d.rec_scale,
+                           d.seis_tm, d.map, b - d.block_begin);
+}
+
 template <int RY, int NW, bool VD, bool ILLUM>
 __global__ void __launch_bounds__(TX * NW)
     k_adjoint(StepGrid g, const float *__restrict__ cur, const float *prev, float *out,
@@ -319,7 +347,7 @@ __global__ void __launch_bounds__(TX * NW)
   using T = Tile<RY, NW>;
   __shared__ float sm[2][2][T::LY][T::LX];  // [field][buffer]
   Geo<RY, NW> geo;
-  if (!geo.init(g, map)) return;
+  if (!geo.init(g, map, blockIdx.x)) return;
   Marcher<RY, NW> fa, fw;  // adjoint state psi^{m+1} and forward state w^m
   fa.prime(cur, g, geo.z0, geo.off, geo.in, geo.hoff, geo.hin);
   fw.prime(wm, g, geo.z0, geo.off, geo.in, geo.hoff, geo.hin);
@@ -416,8 +444,7 @@ __global__ void __launch_bounds__(TX * NW)
   }
 }
 
-// Rows per thread and wavefronts per block of the two step kernels.
-constexpr int RY_FWD = 4, NW_FWD = 4;  // 64 x 16 tiles
+// Rows per thread and wavefronts per block of the adjoint kernel.
 constexpr int RY_ADJ = 2, NW_ADJ = 4;  // 64 x 8 tiles
 
 int env_int(const char *name, int dflt) {
@@ -447,17 +474,18 @@ int blocks_per_cu(K kernel, int threads) {
   return per_cu;
 }
 
-// Tile map: z chunks so that about four rounds of resident blocks cover the
-// grid (measured at 576^3: full-depth columns leave slots idle, and very
-// short chunks re-read the 8-plane z halo too often).
-TileMap make_map(const StepGrid &g, int ty, int per_cu, int nch_override) {
+// Tile map: z chunks so that `rounds` rounds of resident blocks cover the grid
+// (default 4; measured at 576^3: full-depth columns leave slots idle, and
+// very short chunks re-read the 8-plane z halo too often).
+TileMap make_map(const StepGrid &g, int ty, int per_cu, int nch_override, int rounds = 4) {
   TileMap m;
   m.tiles_x = (g.nx + TX - 1) / TX;
   m.tiles_y = (g.ny + ty - 1) / ty;
   const int tiles = m.tiles_x * m.tiles_y;
   const int slots = per_cu * device_cus();
+  if (rounds <= 0) rounds = 4;
   int nch = nch_override;
-  if (nch <= 0) nch = (4 * slots + tiles / 2) / tiles;
+  if (nch <= 0) nch = (rounds * slots + tiles / 2) / tiles;
   nch = std::max(1, std::min(nch, (g.nz + 15) / 16));
   m.zc = (g.nz + nch - 1) / nch;
   m.nchunks = (g.nz + m.zc - 1) / m.zc;
@@ -465,16 +493,54 @@ TileMap make_map(const StepGrid &g, int ty, int per_cu, int nch_override) {
   return m;
 }
 
-template <int RY, int NW, bool VD>
+// Forward tile shapes selectable at run time: (rows per thread, wavefronts).
+template <int V>
+struct FwdShape;
+template <>
+struct FwdShape<0> {
+  static constexpr int RY = 4, NW = 4;  // 64 x 16
+};
+template <>
+struct FwdShape<1> {
+  static constexpr int RY = 2, NW = 4;  // 64 x 8
+};
+template <>
+struct FwdShape<2> {
+  static constexpr int RY = 4, NW = 8;  // 64 x 32
+};
+
+template <int V, bool VD>
+int fwd_per_cu() {
+  using S = FwdShape<V>;
+  static const int per_cu =
+      blocks_per_cu(k_forward<S::RY, S::NW, VD>, Tile<S::RY, S::NW>::NTHREADS);
+  return per_cu;
+}
+
+template <int V>
+int fwd_rows() {
+  return Tile<FwdShape<V>::RY, FwdShape<V>::NW>::TY;
+}
+
+template <int V, bool VD>
 hipError_t fwd_launch(const StepGrid &g, const float *cur, const float *prev, float *out,
                       const Source &src, int n, const RecTable &rec, const float *rec_scale,
-                      float *seis_tm, hipStream_t stream) {
-  using T = Tile<RY, NW>;
-  static const int per_cu = blocks_per_cu(k_forward<RY, NW, VD>, T::NTHREADS);
-  static const int nch = env_int("WFD_ZCHUNKS_FWD", 0);  // 0 = automatic
-  const TileMap map = make_map(g, T::TY, per_cu, nch);
-  hipLaunchKernelGGL((k_forward<RY, NW, VD>), dim3(map.nblocks), dim3(T::NTHREADS), 0,
-                     stream, g, cur, prev, out, src, n, rec, rec_scale, seis_tm, map);
+                      float *seis_tm, const Tuning &tu, hipStream_t stream) {
+  using S = FwdShape<V>;
+  static const int nch_env = env_int("WFD_ZCHUNKS_FWD", 0);  // 0 = automatic
+  const TileMap map = make_map(g, fwd_rows<V>(), fwd_per_cu<V, VD>(), nch_env, tu.rounds);
+  hipLaunchKernelGGL((k_forward<S::RY, S::NW, VD>), dim3(map.nblocks),
+                     dim3(Tile<S::RY, S::NW>::NTHREADS), 0, stream, g, cur, prev, out, src, n,
+                     rec, rec_scale, seis_tm, map);
+  return hipGetLastError();
+}
+
+template <int V, bool VD>
+hipError_t fwd_multi_launch(const WindowStep *wins, int nwin, int nblocks, int n,
+                            hipStream_t stream) {
+  using S = FwdShape<V>;
+  hipLaunchKernelGGL((k_forward_multi<S::RY, S::NW, VD>), dim3(nblocks),
+                     dim3(Tile<S::RY, S::NW>::NTHREADS), 0, stream, wins, nwin, n);
   return hipGetLastError();
 }
 
@@ -486,7 +552,7 @@ hipError_t adj_launch(const StepGrid &g, const float *cur, const float *prev, fl
   using T = Tile<RY, NW>;
   static const int per_cu = blocks_per_cu(k_adjoint<RY, NW, VD, ILLUM>, T::NTHREADS);
   static const int nch = env_int("WFD_ZCHUNKS_ADJ", 0);  // 0 = automatic
-  const TileMap map = make_map(g, T::TY, per_cu, nch);
+  const TileMap map = make_map(g, T::TY, per_cu, nch, 4);
   hipLaunchKernelGGL((k_adjoint<RY, NW, VD, ILLUM>), dim3(map.nblocks), dim3(T::NTHREADS), 0,
                      stream, g, cur, prev, out, rec, res_tm, m, wm, grad, illum, border, mnx, mny,
                      mnz, map);
@@ -497,15 +563,45 @@ hipError_t adj_launch(const StepGrid &g, const float *cur, const float *prev, fl
 
 hipError_t launch_forward_step(const StepGrid &g, const float *cur, const float *prev, float *out,
                                const Source &src, int n, const RecTable *rec,
-                               const float *rec_scale, float *seis_tm, hipStream_t stream) {
+                               const float *rec_scale, float *seis_tm, const Tuning &tu,
+                               hipStream_t stream) {
   const bool vd = g.m2 != nullptr;
   const RecTable none{};
   const RecTable &r = rec ? *rec : none;
   float *rec_out = rec ? seis_tm : nullptr;
-  return vd ? fwd_launch<RY_FWD, NW_FWD, true>(g, cur, prev, out, src, n, r, rec_scale, rec_out,
-                                               stream)
-            : fwd_launch<RY_FWD, NW_FWD, false>(g, cur, prev, out, src, n, r, rec_scale, rec_out,
-                                                stream);
+#define WFD_FWD(V)                                                                          \
+  return vd ? fwd_launch<V, true>(g, cur, prev, out, src, n, r, rec_scale, rec_out, tu, stream) \
+            : fwd_launch<V, false>(g, cur, prev, out, src, n, r, rec_scale, rec_out, tu, stream)
+  switch (tu.variant) {
+    case 1: WFD_FWD(1);
+    case 2: WFD_FWD(2);
+    default: WFD_FWD(0);
+  }
+#undef WFD_FWD
+}
+
+int forward_tile_map(const StepGrid &g, const Tuning &tu, TileMap *map) {
+  const bool vd = g.m2 != nullptr;
+  int ty = 16, per_cu = 4;
+  switch (tu.variant) {
+    case 1: ty = fwd_rows<1>(); per_cu = vd ? fwd_per_cu<1, true>() : fwd_per_cu<1, false>(); break;
+    case 2: ty = fwd_rows<2>(); per_cu = vd ? fwd_per_cu<2, true>() : fwd_per_cu<2, false>(); break;
+    default: ty = fwd_rows<0>(); per_cu = vd ? fwd_per_cu<0, true>() : fwd_per_cu<0, false>(); break;
+  }
+  *map = make_map(g, ty, per_cu, 0, tu.rounds);
+  return map->nblocks;
+}
+
+hipError_t launch_forward_multi(const WindowStep *wins, int nwin, int nblocks, int n, int variant,
+                                bool vd, hipStream_t stream) {
+  switch (variant) {
+    case 1: return vd ? fwd_multi_launch<1, true>(wins, nwin, nblocks, n, stream)
+                      : fwd_multi_launch<1, false>(wins, nwin, nblocks, n, stream);
+    case 2: return vd ? fwd_multi_launch<2, true>(wins, nwin, nblocks, n, stream)
+                      : fwd_multi_launch<2, false>(wins, nwin, nblocks, n, stream);
+    default: return vd ? fwd_multi_launch<0, true>(wins, nwin, nblocks, n, stream)
+                       : fwd_multi_launch<0, false>(wins, nwin, nblocks, n, stream);
+  }
 }
 
 hipError_t launch_adjoint_step(const StepGrid &g, const float *cur, const float *prev, float *out,

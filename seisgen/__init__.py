@@ -12,7 +12,7 @@ metres in ``(x, y, z)`` order, seismograms are trace-major ``[rec][ns]``.
 
 from .models import layered_model, gardner_density, blob_anomalies, smooth_noise
 from .wavelet import ricker
-from .configs import Workload, workload, WORKLOADS
+from .configs import Workload, workload, WORKLOADS, shot_window
 
 __all__ = [
     "layered_model",
@@ -23,4 +23,5 @@ __all__ = [
     "Workload",
     "workload",
     "WORKLOADS",
+    "shot_window",
 ]

@@ -18,6 +18,14 @@ c2        512^3 layered model with +/-5 % smooth perturbation, Gardner
           density).
 c2_small  the same generator on a small ragged grid (93 x 77 x 61, 16-cell
           sponge, 300 steps) for element-wise parity.
+c3        400 x 400 x 256 model from the c2 generator (seed 2503), 32-cell
+          sponge, 1500 steps, 24 shots on a 6 x 4 surface grid at depth
+          index 4; shot i runs on its own aperture window: a square in x-y of
+          side s_i drawn from integers(160, 321) (seed 3), centred on the shot,
+          clipped to the model, full depth, with receivers at every 2nd
+          surface node of the window (depth index 2) (batched multi-shot).
+c3_small  the same recipe on 96 x 80 x 48 with 4 shots (2 x 2), sides from
+          integers(24, 49), 8-cell sponge, 250 steps (element-wise parity).
 c4        200 x 200 x 160 smooth layered background + six +/-10 % blobs,
           20-cell sponge, 1200 steps, 8 shots, 2500 receivers (FWI gradient).
 c4_fd     32^3 layered model, 8-cell sponge, 300 steps, one shot, 64
@@ -123,6 +131,41 @@ def _c2_small() -> Workload:
                src=[[46, 38, 8]])
 
 
+def _c3(nx=400, ny=400, nz=256, border=32, nt=1500, shots_xy=(6, 4), side=(160, 321),
+        seed=2503, name="c3") -> Workload:
+    h = 10.0
+    vel = layered_model(seed, (nx, ny, nz), 0.05)
+    rho = gardner_density(vel)
+    dt = 0.4 * h / 4500.0
+    sx, sy = shots_xy
+    xs = [int(round((i + 0.5) * nx / sx)) for i in range(sx)]
+    ys = [int(round((j + 0.5) * ny / sy)) for j in range(sy)]
+    shots = [[x, y, 4] for y in ys for x in xs]
+    sides = np.random.default_rng(3).integers(side[0], side[1], size=len(shots))
+    win = []
+    for (x, y, _), s_ in zip(shots, sides):
+        ax, ay = x - s_ // 2, y - s_ // 2
+        win.append([max(0, ax), min(nx, ax + s_), max(0, ay), min(ny, ay + s_)])
+    w = Workload(name, nx, ny, nz, h, h, h, 0.0, 0.0, 0.0, border, dt, nt, vel, rho,
+                 ricker(nt, dt, 10.0, 0.1), _metres(shots, (h, h, h)), np.zeros((0, 3)))
+    w.extra["windows"] = np.asarray(win, dtype=np.int64)   # [shot] (x0, x1, y0, y1), nodes
+    return w
+
+
+def shot_window(w: Workload, i: int) -> Workload:
+    """Shot i of a windowed workload on its own grid: the model restricted to
+    its window (full depth), the origin moved to the window corner so that
+    positions stay in model metres, receivers at every 2nd surface node."""
+    x0, x1, y0, y1 = (int(v) for v in w.extra["windows"][i])
+    vel = np.ascontiguousarray(w.vel[:, y0:y1, x0:x1])
+    rho = None if w.rho is None else np.ascontiguousarray(w.rho[:, y0:y1, x0:x1])
+    rec = _surface_grid(x0 + 1, 2, (x1 - x0) // 2, y0 + 1, 2, (y1 - y0) // 2, 2)
+    return Workload(f"{w.name}_shot{i}", x1 - x0, y1 - y0, w.nz, w.dx, w.dy, w.dz,
+                    w.ox + x0 * w.dx, w.oy + y0 * w.dy, w.oz, w.border, w.dt, w.nt, vel, rho,
+                    w.wavelet, w.sources[i:i + 1].copy(),
+                    _metres(rec, (w.dx, w.dy, w.dz), (w.ox, w.oy, w.oz)))
+
+
 def _c4(variant: str = "true") -> Workload:
     nx, ny, nz, h = 200, 200, 160, 10.0
     bg = layered_model(4, (nx, ny, nz), 0.0)
@@ -177,6 +220,9 @@ WORKLOADS: Dict[str, Callable[[], Workload]] = {
     "c1_long": lambda: _c1(400),
     "c2": _c2,
     "c2_small": _c2_small,
+    "c3": _c3,
+    "c3_small": lambda: _c3(nx=96, ny=80, nz=48, border=8, nt=250, shots_xy=(2, 2),
+                            side=(24, 49), name="c3_small"),
     "c4": _c4,
     "c4_start": lambda: _c4("start"),
     "c4_fd": _c4_fd,
