@@ -216,7 +216,7 @@ def batch_bench(steps: int, warmup: int, autotune: bool):
           file=sys.stderr, flush=True)
     tuned = None
     if autotune:
-        tuned = [P.autotune(steps=10) for P in props]
+        tuned = [P.autotune(steps=10)[0] for P in props]
         print(f"[bench-batch] autotuned {tuned}", file=sys.stderr, flush=True)
     with torch.cuda.stream(stream):
         batch = ShotBatch(props, wav, [s.sources[0] for s in shots], [s.receivers for s in shots],
@@ -272,7 +272,8 @@ def main():
     ap.add_argument("--batch", action="store_true",
                     help="run the batched multi-shot forward benchmark instead")
     ap.add_argument("--autotune", action="store_true",
-                    help="with --batch: autotune each window's launch shape first")
+                    help="time every step-kernel launch shape at setup (untimed) and keep "
+                         "the fastest (with --batch: per window)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -323,6 +324,10 @@ def main():
     P.release_workspace()
     P.set_model(grid, vel, rho)
     del true
+    if args.autotune:
+        tuned, fus, aus = P.autotune(steps=10)
+        print(f"[bench] autotuned {tuned}: forward {fus:.1f} us, adjoint {aus:.1f} us per step",
+              file=sys.stderr, flush=True)
     ckpt = ("revolve", min(args.snapshots, w.nt))
     grad = torch.zeros((w.nz, w.ny, w.nx), dtype=torch.float32, device=dev)
     misfit = torch.zeros((), dtype=torch.float64, device=dev)
@@ -384,6 +389,8 @@ def main():
                                f"{w.nt} steps, {nrec} receivers",
                    "padded_points": pts, "nt": w.nt, "nrec": nrec,
                    "checkpoint": f"binomial, {ckpt[1]} stored pairs",
+                   "tuning": dict(zip(("fwd_variant", "fwd_rounds", "adj_variant",
+                                       "adj_rounds"), P.tuning())),
                    "parallelism": "1 GPU, one shot"},
         "roofline": {"bound": "hbm", "achieved": round(dom["GBps"], 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(dom["hbm_frac"], 4),

@@ -174,25 +174,36 @@ wfd_status wfd_gradient_finish(wfd_ctx *ctx, float *grad_dev, int32_t zero_top_p
 
 /* ---- launch tuning and batched shots ------------------------------------ */
 
-/* Forward-kernel launch shape of the context (the paper's per-architecture
- * CUDA_BLOCK_SIZE choice, re-done for CDNA4 tiles):
- *   variant 0: 64 x 16 tiles (4 rows per thread, 4 wavefronts)  [default]
- *           1: 64 x 8 tiles  (2 rows per thread, 4 wavefronts)
- *           2: 64 x 32 tiles (4 rows per thread, 8 wavefronts)
- *   rounds     z-chunking aims at this many rounds of resident blocks per
- *              launch (0 = default 4; at most 64).
+/* Launch shapes of the context's step kernels (the paper tunes its CUDA
+ * block size per architecture; these are the CDNA4 tile choices):
+ *   fwd_variant  forward tiles (rows per thread x wavefronts per block):
+ *                0: 2x8 = 64x16 tiles [default]  1: 4x4 = 64x16
+ *                2: 2x4 = 64x8                    3: 4x8 = 64x32
+ *   adj_variant  adjoint tiles: 0: 2x8 = 64x16 [default]  1: 2x4 = 64x8
+ *                2: 4x4 = 64x16
+ *   *_rounds     z chunking aims at this many rounds of resident blocks per
+ *                launch (at most 64); 0 = automatic: the chunk count that
+ *                minimises a model of the launch time (rounds of resident
+ *                blocks, a partly filled last round, z-halo re-reads).
  * Every shape computes bitwise the same result; only speed differs. */
-wfd_status wfd_set_tuning(wfd_ctx *ctx, int32_t variant, int32_t rounds);
-wfd_status wfd_get_tuning(const wfd_ctx *ctx, int32_t *variant, int32_t *rounds);
+typedef struct {
+  int32_t fwd_variant, fwd_rounds;
+  int32_t adj_variant, adj_rounds;
+} wfd_tuning;
 
-/* Time `steps` forward steps (no source, no receivers) for each variant in
- * {0, 1, 2} x rounds in {2, 4, 8} on the context's model with HIP events,
- * keep the fastest in the context and return it (any output may be NULL).
- *   work_dev, work_bytes  workspace of at least wfd_workspace_bytes(nrec=0,
- *                         NULL); its two field volumes are overwritten.
+wfd_status wfd_set_tuning(wfd_ctx *ctx, const wfd_tuning *tuning);
+wfd_status wfd_get_tuning(const wfd_ctx *ctx, wfd_tuning *tuning);
+
+/* Time `steps` steps of every forward shape, then of every adjoint shape,
+ * each with rounds in {0 (automatic), 2, 3, 4, 6, 8}, on the context's model (no source, no
+ * receivers) with HIP events; keep the fastest in the context.
+ *   work_dev, work_bytes  workspace of at least wfd_workspace_bytes(nrec = 0,
+ *                 binomial checkpointing with 1 stored pair); overwritten;
+ *   best_or_null  the chosen shapes;
+ *   us_or_null    [2] microseconds per forward and per adjoint step.
  * Waits on the stream. */
 wfd_status wfd_autotune(wfd_ctx *ctx, int32_t steps, void *work_dev, size_t work_bytes,
-                        int32_t *variant, int32_t *rounds, double *us_per_step);
+                        wfd_tuning *best_or_null, double *us_or_null);
 
 /* A batch of shots whose forward sweeps (Alg. 1) run together: each time
  * step is ONE kernel launch over the tiles of every shot, so small grids
@@ -214,8 +225,8 @@ wfd_status wfd_autotune(wfd_ctx *ctx, int32_t steps, void *work_dev, size_t work
  *                    descriptors.
  * Receiver tables are built and uploaded here, so a run repeats the same
  * acquisition.  Contexts, models, wavelet, workspaces and outputs must stay
- * allocated until wfd_batch_destroy; the contexts' tuning variant at creation
- * time (shot 0's) is used for every shot. */
+ * allocated until wfd_batch_destroy; shot 0's forward tile shape at creation
+ * time is used for every shot (each shot keeps its own z chunking). */
 typedef struct wfd_batch wfd_batch;
 wfd_status wfd_batch_create(wfd_batch **batch, int32_t nshot, wfd_ctx *const *ctxs,
                             const float *wavelet_dev, const double *src_xyz,

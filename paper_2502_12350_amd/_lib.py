@@ -32,6 +32,11 @@ class wfd_ckpt(C.Structure):
     _fields_ = [("mode", C.c_int32), ("n_snapshots", C.c_int32), ("mem_fraction", C.c_double)]
 
 
+class wfd_tuning(C.Structure):
+    _fields_ = [("fwd_variant", C.c_int32), ("fwd_rounds", C.c_int32),
+                ("adj_variant", C.c_int32), ("adj_rounds", C.c_int32)]
+
+
 class WfdError(RuntimeError):
     def __init__(self, status: int, message: str):
         self.status = status
@@ -54,10 +59,10 @@ _SIGS = {
     "wfd_gradient": (C.c_int, [_P, _P, _D3, C.c_int32, _D3, _P, C.POINTER(wfd_ckpt), _P, _P,
                                _P, _P, _P, C.c_size_t]),
     "wfd_gradient_finish": (C.c_int, [_P, _P, C.c_int32]),
-    "wfd_set_tuning": (C.c_int, [_P, C.c_int32, C.c_int32]),
-    "wfd_get_tuning": (C.c_int, [_P, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
-    "wfd_autotune": (C.c_int, [_P, C.c_int32, _P, C.c_size_t, C.POINTER(C.c_int32),
-                               C.POINTER(C.c_int32), C.POINTER(C.c_double)]),
+    "wfd_set_tuning": (C.c_int, [_P, C.POINTER(wfd_tuning)]),
+    "wfd_get_tuning": (C.c_int, [_P, C.POINTER(wfd_tuning)]),
+    "wfd_autotune": (C.c_int, [_P, C.c_int32, _P, C.c_size_t, C.POINTER(wfd_tuning),
+                               C.POINTER(C.c_double)]),
     "wfd_batch_create": (C.c_int, [C.POINTER(C.c_void_p), C.c_int32, C.POINTER(C.c_void_p), _P,
                                    _D3, C.POINTER(C.c_int32), C.POINTER(_D3),
                                    C.POINTER(C.c_void_p), C.POINTER(C.c_void_p),

@@ -292,26 +292,29 @@ class Propagator:
         return grad
 
     # launch tuning -----------------------------------------------------------
-    def set_tuning(self, variant: int, rounds: int = 0):
-        """Forward tile shape (0: 64x16, 1: 64x8, 2: 64x32) and z-chunk rounds."""
-        check(self.L.wfd_set_tuning(self._ctx, int(variant), int(rounds)))
+    def set_tuning(self, fwd_variant: int = 0, fwd_rounds: int = 0, adj_variant: int = 0,
+                   adj_rounds: int = 0):
+        """Tile shapes of the step kernels and their z-chunk rounds (wfd_tuning)."""
+        t = _lib.wfd_tuning(int(fwd_variant), int(fwd_rounds), int(adj_variant), int(adj_rounds))
+        check(self.L.wfd_set_tuning(self._ctx, C.byref(t)))
 
-    def tuning(self) -> Tuple[int, int]:
-        v, r = C.c_int32(), C.c_int32()
-        check(self.L.wfd_get_tuning(self._ctx, C.byref(v), C.byref(r)))
-        return v.value, r.value
+    def tuning(self) -> Tuple[int, int, int, int]:
+        """(fwd_variant, fwd_rounds, adj_variant, adj_rounds)."""
+        t = _lib.wfd_tuning()
+        check(self.L.wfd_get_tuning(self._ctx, C.byref(t)))
+        return t.fwd_variant, t.fwd_rounds, t.adj_variant, t.adj_rounds
 
-    def autotune(self, steps: int = 20) -> Tuple[int, int, float]:
-        """Time every launch shape on the current model, keep the fastest;
-        returns (variant, rounds, microseconds per step)."""
+    def autotune(self, steps: int = 20):
+        """Time every launch shape on the current model and keep the fastest;
+        returns (tuning tuple, forward us/step, adjoint us/step)."""
         if self.grid is None:
             raise RuntimeError("set_model first")
-        wptr, wbytes = self._workspace(self.workspace_bytes(0))
+        wptr, wbytes = self._workspace(self.workspace_bytes(0, ("revolve", 1)))
         self._sync_stream()
-        v, r, us = C.c_int32(), C.c_int32(), C.c_double()
-        check(self.L.wfd_autotune(self._ctx, int(steps), wptr, wbytes, C.byref(v), C.byref(r),
-                                  C.byref(us)))
-        return v.value, r.value, us.value
+        t = _lib.wfd_tuning()
+        us = (C.c_double * 2)()
+        check(self.L.wfd_autotune(self._ctx, int(steps), wptr, wbytes, C.byref(t), us))
+        return (t.fwd_variant, t.fwd_rounds, t.adj_variant, t.adj_rounds), us[0], us[1]
 
     # measurement -------------------------------------------------------------
     def set_profiling(self, on: bool):

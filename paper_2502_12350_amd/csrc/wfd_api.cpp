@@ -428,6 +428,24 @@ wfd_status common_checks(wfd_ctx *c, const float *wavelet, const double *src, in
 
 }  // namespace
 
+namespace {
+
+// Average time (ms) of `steps` launches of `launch` on the context's stream,
+// after one untimed launch.
+template <class F>
+hipError_t time_steps(wfd_ctx *c, int steps, hipEvent_t e0, hipEvent_t e1, F launch, float *ms) {
+  hipError_t err = launch();
+  if (err == hipSuccess) err = hipEventRecord(e0, c->stream);
+  for (int n = 0; n < steps && err == hipSuccess; ++n) err = launch();
+  if (err == hipSuccess) err = hipEventRecord(e1, c->stream);
+  if (err == hipSuccess) err = hipEventSynchronize(e1);
+  if (err == hipSuccess) err = hipEventElapsedTime(ms, e0, e1);
+  if (err == hipSuccess) *ms /= (float)steps;
+  return err;
+}
+
+}  // namespace
+
 extern "C" {
 
 const char *wfd_last_error(void) { return g_last_error.c_str(); }
@@ -728,7 +746,7 @@ wfd_status wfd_gradient(wfd_ctx *c, const float *wavelet, const double src_xyz[3
   auto adjoint = [&](int m, const float *wm) -> wfd_status {
     {
       Timed t(c, WFD_K_ADJOINT);
-      HIP_TRY(wfd::launch_adjoint_step(g, A1, A2, A2, rt, w.res_tm, m, wm, w.g, illum,
+      HIP_TRY(wfd::launch_adjoint_step(c->tuning, g, A1, A2, A2, rt, w.res_tm, m, wm, w.g, illum,
                                        c->grid.border, c->grid.nx, c->grid.ny, c->grid.nz,
                                        c->stream));
     }
@@ -856,37 +874,47 @@ wfd_status wfd_gradient_finish(wfd_ctx *c, float *grad, int32_t zero_top_planes)
   return zero(c, grad, (int64_t)zero_top_planes * c->grid.ny * c->grid.nx);
 }
 
-wfd_status wfd_set_tuning(wfd_ctx *c, int32_t variant, int32_t rounds) {
-  if (!c) return fail(WFD_E_ARG, "ctx is NULL");
-  if (variant < 0 || variant > 2) return fail(WFD_E_ARG, "tile variant must be 0, 1 or 2");
-  if (rounds < 0 || rounds > 64) return fail(WFD_E_ARG, "rounds must be in [0, 64]");
-  c->tuning.variant = variant;
-  c->tuning.rounds = rounds;
+wfd_status wfd_set_tuning(wfd_ctx *c, const wfd_tuning *t) {
+  if (!c || !t) return fail(WFD_E_ARG, "NULL argument");
+  if (t->fwd_variant < 0 || t->fwd_variant >= wfd::kFwdVariants)
+    return fail(WFD_E_ARG, "forward tile variant must be in [0, %d)", wfd::kFwdVariants);
+  if (t->adj_variant < 0 || t->adj_variant >= wfd::kAdjVariants)
+    return fail(WFD_E_ARG, "adjoint tile variant must be in [0, %d)", wfd::kAdjVariants);
+  if (t->fwd_rounds < 0 || t->fwd_rounds > 64 || t->adj_rounds < 0 || t->adj_rounds > 64)
+    return fail(WFD_E_ARG, "rounds must be in [0, 64]");
+  c->tuning = wfd::Tuning{t->fwd_variant, t->fwd_rounds, t->adj_variant, t->adj_rounds};
   return WFD_OK;
 }
 
-wfd_status wfd_get_tuning(const wfd_ctx *c, int32_t *variant, int32_t *rounds) {
-  if (!c || !variant || !rounds) return fail(WFD_E_ARG, "NULL argument");
-  *variant = c->tuning.variant;
-  *rounds = c->tuning.rounds;
+wfd_status wfd_get_tuning(const wfd_ctx *c, wfd_tuning *t) {
+  if (!c || !t) return fail(WFD_E_ARG, "NULL argument");
+  *t = wfd_tuning{c->tuning.variant, c->tuning.rounds, c->tuning.adj_variant,
+                  c->tuning.adj_rounds};
   return WFD_OK;
 }
+
 
 wfd_status wfd_autotune(wfd_ctx *c, int32_t steps, void *work, size_t work_bytes,
-                        int32_t *variant, int32_t *rounds, double *us_per_step) {
+                        wfd_tuning *best, double *us_per_step) {
   if (!c) return fail(WFD_E_ARG, "ctx is NULL");
   if (!c->has_model) return fail(WFD_E_STATE, "no model: call wfd_set_model first");
   if (steps < 1) return fail(WFD_E_ARG, "steps must be >= 1");
   if (!work) return fail(WFD_E_ARG, "workspace is NULL");
   if ((uintptr_t)work % kAlign) return fail(WFD_E_ARG, "workspace must be 256-byte aligned");
-  Work w = work_layout(c, 0, WorkKind::Forward, nullptr, 0, work);
+  const wfd_ckpt one{WFD_CKPT_REVOLVE, 1, 0.0};
+  Work w = work_layout(c, 0, WorkKind::Gradient, &one, 1, work);
   if (work_bytes < w.bytes)
     return fail(WFD_E_NOMEM, "workspace has %zu bytes, %zu needed", work_bytes, w.bytes);
   ScopedDevice sd(c->device);
   wfd_status s;
-  if ((s = zero(c, w.W1, c->vol)) != WFD_OK) return s;
-  if ((s = zero(c, w.W2, c->vol)) != WFD_OK) return s;
+  for (float *v : {w.W1, w.W2, w.P1, w.P2, w.g})
+    if ((s = zero(c, v, c->vol)) != WFD_OK) return s;
+  // an empty receiver table: every column starts (and ends) at entry 0
+  if ((s = zero(c, reinterpret_cast<float *>(w.col_start), (int64_t)c->Nx * c->Ny + 1)) !=
+      WFD_OK)
+    return s;
   const wfd::StepGrid g = step_grid(c);
+  const wfd::RecTable rt = rec_table(w, 0);
   // index -1 matches no point: nothing is injected (the pointers stay valid)
   const wfd::Source none_src{-1, w.sigma, w.sigma};
   hipEvent_t e0, e1;
@@ -895,41 +923,60 @@ wfd_status wfd_autotune(wfd_ctx *c, int32_t steps, void *work, size_t work_bytes
     (void)hipEventDestroy(e0);
     return fail(WFD_E_HIP, "hipEventCreate failed");
   }
-  const int rounds_opts[] = {2, 4, 8};
-  float best = 3.0e38f;
-  wfd::Tuning best_t{0, 4};
+  const int rounds_opts[] = {0, 2, 3, 4, 6, 8};
+  wfd::Tuning bt = c->tuning;
+  float best_f = 3.0e38f, best_a = 3.0e38f;
   hipError_t err = hipSuccess;
-  for (int v = 0; v < 3 && err == hipSuccess; ++v) {
+  for (int v = 0; v < wfd::kFwdVariants && err == hipSuccess; ++v)
     for (int r : rounds_opts) {
-      const wfd::Tuning tu{v, r};
+      wfd::Tuning tu = bt;
+      tu.variant = v;
+      tu.rounds = r;
       float *cur = w.W1, *prev = w.W2;
-      err = wfd::launch_forward_step(g, cur, prev, prev, none_src, 0, nullptr, nullptr, nullptr,
-                                     tu, c->stream);  // warm-up
-      std::swap(cur, prev);
-      if (err == hipSuccess) err = hipEventRecord(e0, c->stream);
-      for (int n = 0; n < steps && err == hipSuccess; ++n) {
-        err = wfd::launch_forward_step(g, cur, prev, prev, none_src, 0, nullptr, nullptr,
-                                       nullptr, tu, c->stream);
-        std::swap(cur, prev);
-      }
-      if (err == hipSuccess) err = hipEventRecord(e1, c->stream);
-      if (err == hipSuccess) err = hipEventSynchronize(e1);
       float ms = 0.0f;
-      if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
+      err = time_steps(c, steps, e0, e1, [&] {
+        hipError_t e = wfd::launch_forward_step(g, cur, prev, prev, none_src, 0, nullptr, nullptr,
+                                                nullptr, tu, c->stream);
+        std::swap(cur, prev);
+        return e;
+      }, &ms);
       if (err != hipSuccess) break;
-      if (ms < best) {
-        best = ms;
-        best_t = tu;
+      if (ms < best_f) {
+        best_f = ms;
+        bt.variant = v;
+        bt.rounds = r;
       }
     }
-  }
+  for (int v = 0; v < wfd::kAdjVariants && err == hipSuccess; ++v)
+    for (int r : rounds_opts) {
+      wfd::Tuning tu = bt;
+      tu.adj_variant = v;
+      tu.adj_rounds = r;
+      float *a1 = w.P1, *a2 = w.P2;
+      float ms = 0.0f;
+      err = time_steps(c, steps, e0, e1, [&] {
+        hipError_t e = wfd::launch_adjoint_step(tu, g, a1, a2, a2, rt, w.seis_tm, 1, w.W1, w.g,
+                                                nullptr, c->grid.border, c->grid.nx, c->grid.ny,
+                                                c->grid.nz, c->stream);
+        std::swap(a1, a2);
+        return e;
+      }, &ms);
+      if (err != hipSuccess) break;
+      if (ms < best_a) {
+        best_a = ms;
+        bt.adj_variant = v;
+        bt.adj_rounds = r;
+      }
+    }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   if (err != hipSuccess) return fail(WFD_E_HIP, "autotune: %s", hipGetErrorString(err));
-  c->tuning = best_t;
-  if (variant) *variant = best_t.variant;
-  if (rounds) *rounds = best_t.rounds;
-  if (us_per_step) *us_per_step = 1e3 * (double)best / steps;
+  c->tuning = bt;
+  if (best) *best = wfd_tuning{bt.variant, bt.rounds, bt.adj_variant, bt.adj_rounds};
+  if (us_per_step) {
+    us_per_step[0] = 1e3 * (double)best_f;
+    us_per_step[1] = 1e3 * (double)best_a;
+  }
   return WFD_OK;
 }
 

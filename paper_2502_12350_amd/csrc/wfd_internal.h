@@ -44,12 +44,18 @@ struct TileMap {
   int tiles_x, tiles_y, nchunks, zc, nblocks;
 };
 
-// Forward-kernel tuning: tile shape variant (0: 64x16 tiles of 4 rows per
-// thread, 1: 64x8 of 2 rows, 2: 64x32 of 4 rows in 8-wave blocks) and the
-// number of rounds of resident blocks the z chunking aims for (0 = 4).
+// Step-kernel tuning.  Tile shapes (rows per thread x wavefronts per block):
+//   forward  0: 2x8 (64x16 tiles)  1: 4x4 (64x16)  2: 2x4 (64x8)  3: 4x8 (64x32)
+//   adjoint  0: 2x8 (64x16)        1: 2x4 (64x8)   2: 4x4 (64x16)
+// and the number of rounds of resident blocks the z chunking aims for
+// (0 = chosen by the launch cost model).  Every shape computes bitwise the
+// same values.
+constexpr int kFwdVariants = 4, kAdjVariants = 3;
 struct Tuning {
   int variant = 0;
   int rounds = 0;
+  int adj_variant = 0;
+  int adj_rounds = 0;
 };
 
 // One shot's forward step inside a multi-window launch.
@@ -79,7 +85,8 @@ int forward_tile_map(const StepGrid &g, const Tuning &tu, TileMap *map);
 hipError_t launch_forward_multi(const WindowStep *wins, int nwin, int nblocks, int n, int variant,
                                 bool vd, hipStream_t stream);
 
-hipError_t launch_adjoint_step(const StepGrid &g, const float *cur, const float *prev, float *out,
+hipError_t launch_adjoint_step(const Tuning &tu, const StepGrid &g, const float *cur,
+                               const float *prev, float *out,
                                const RecTable &rec, const float *res_tm, int m,
                                const float *wm, float *grad, float *illum, int border, int mnx,
                                int mny, int mnz, hipStream_t stream);

@@ -13,7 +13,9 @@
 //
 // HBM traffic per point: forward 16 B (constant density) / 20 B (variable
 // density); adjoint + imaging 28 B / 32 B (+ 8 B with illumination).
+#include <algorithm>
 #include <climits>
+#include <cmath>
 #include <cstdlib>
 
 #include "wfd_internal.h"
@@ -55,7 +57,7 @@ __device__ __forceinline__ void tile_of(const TileMap &m, int b, int &tx, int &t
 }
 
 // Halo element h of a tile plane: global (gx, gy) and its LDS row / column.
-template <int RY, int NW>
+template <int RY, int NW, int K>
 __device__ __forceinline__ void halo_slot(int h, int x0, int y0, int &gx, int &gy, int &lrow,
                                           int &lcol) {
   constexpr int TY = Tile<RY, NW>::TY;
@@ -96,7 +98,11 @@ __device__ __forceinline__ void st_stream(float *f, int64_t p, float v) {
 }
 
 // Per-thread view of one stenciled field: register queue + halo staging.
-template <int RY, int NW>
+// K tags the kernel family (0 forward, 1 adjoint): each family gets its own
+// instantiations of the tile helpers.  With shared ones, hipcc allocated the
+// adjoint 137 VGPRs instead of 123 once a forward shape used the same tile,
+// dropping it from 4 to 3 waves per SIMD.
+template <int RY, int NW, int K>
 struct Marcher {
   using T = Tile<RY, NW>;
   float q[RY][9];   // planes z-4 .. z+4 of the thread's RY points
@@ -163,7 +169,7 @@ struct Marcher {
 };
 
 // Common per-thread tile geometry.
-template <int RY, int NW>
+template <int RY, int NW, int K>
 struct Geo {
   using T = Tile<RY, NW>;
   int lane, wave, x0, y0, x, z0, z1;
@@ -195,7 +201,7 @@ struct Geo {
       const int h = threadIdx.x + i * T::NTHREADS;
       if (h < T::NHALO) {
         int gx, gy, lrow, lcol;
-        halo_slot<RY, NW>(h, x0, y0, gx, gy, lrow, lcol);
+        halo_slot<RY, NW, K>(h, x0, y0, gx, gy, lrow, lcol);
         hin[i] = gx >= 0 && gx < g.nx && gy >= 0 && gy < g.ny;
         hoff[i] = hin[i] ? (uint32_t)gy * (uint32_t)g.pitch + (uint32_t)gx : 0u;
         hslot[i] = lrow * T::LX + lcol;
@@ -240,9 +246,9 @@ __device__ __forceinline__ void forward_tile(
     const RecTable &rec, const float *__restrict__ rec_scale, float *__restrict__ seis_tm,
     const TileMap &map, int b) {
   using T = Tile<RY, NW>;
-  Geo<RY, NW> geo;
+  Geo<RY, NW, 0> geo;
   if (!geo.init(g, map, b)) return;
-  Marcher<RY, NW> f;
+  Marcher<RY, NW, 0> f;
   f.prime(cur, g, geo.z0, geo.off, geo.in, geo.hoff, geo.hin);
   const float gxv = geo.x < g.nx ? g.gx[geo.x] : 0.0f;
   float gyv[RY];
@@ -346,9 +352,9 @@ __global__ void __launch_bounds__(TX * NW)
               float *__restrict__ illum, int border, int mnx, int mny, int mnz, TileMap map) {
   using T = Tile<RY, NW>;
   __shared__ float sm[2][2][T::LY][T::LX];  // [field][buffer]
-  Geo<RY, NW> geo;
+  Geo<RY, NW, 1> geo;
   if (!geo.init(g, map, blockIdx.x)) return;
-  Marcher<RY, NW> fa, fw;  // adjoint state psi^{m+1} and forward state w^m
+  Marcher<RY, NW, 1> fa, fw;  // adjoint state psi^{m+1} and forward state w^m
   fa.prime(cur, g, geo.z0, geo.off, geo.in, geo.hoff, geo.hin);
   fw.prime(wm, g, geo.z0, geo.off, geo.in, geo.hoff, geo.hin);
   const float gxv = geo.x < g.nx ? g.gx[geo.x] : 0.0f;
@@ -444,9 +450,6 @@ __global__ void __launch_bounds__(TX * NW)
   }
 }
 
-// Rows per thread and wavefronts per block of the adjoint kernel.
-constexpr int RY_ADJ = 2, NW_ADJ = 4;  // 64 x 8 tiles
-
 int env_int(const char *name, int dflt) {
   const char *v = std::getenv(name);
   if (!v || !*v) return dflt;
@@ -474,39 +477,97 @@ int blocks_per_cu(K kernel, int threads) {
   return per_cu;
 }
 
-// Tile map: z chunks so that `rounds` rounds of resident blocks cover the grid
-// (default 4; measured at 576^3: full-depth columns leave slots idle, and
-// very short chunks re-read the 8-plane z halo too often).
-TileMap make_map(const StepGrid &g, int ty, int per_cu, int nch_override, int rounds = 4) {
+// Tile map: the grid's (x, y) tiles times nch z chunks.  With `rounds` > 0 the
+// chunk count aims at that many rounds of resident blocks.  Otherwise it
+// minimises a cost model of the launch with R = blocks / resident slots:
+//   R <= 1:  one round, as long as one block (an under-filled device runs no
+//            faster per block);
+//   R > 1:   floor(R) full rounds plus a last round that costs its fill
+//            fraction but at least kTailFloor of a round,
+// each round lasting zc planes plus `halo` plane-equivalents for re-reading
+// the 8-plane z halo of the stencil fields.  Fitted to step times measured at
+// 576^3 (forward 64x16 and adjoint 64x8 tiles, 2 to 19 chunks): time / cost
+// was constant to within 3 per cent, with a last round of few blocks taking
+// about half a full one.
+constexpr double kTailFloor = 0.47;
+
+double launch_cost(double R, int zc, double halo) {
+  if (R <= 1.0) return zc + halo;
+  const double full = std::floor(R), f = R - full;
+  return (full + (f > 0.0 ? std::max(f, kTailFloor) : 0.0)) * (zc + halo);
+}
+
+TileMap make_map(const StepGrid &g, int ty, int per_cu, int nch_override, int rounds,
+                 double halo) {
   TileMap m;
   m.tiles_x = (g.nx + TX - 1) / TX;
   m.tiles_y = (g.ny + ty - 1) / ty;
-  const int tiles = m.tiles_x * m.tiles_y;
-  const int slots = per_cu * device_cus();
-  if (rounds <= 0) rounds = 4;
+  const int64_t tiles = (int64_t)m.tiles_x * m.tiles_y;
+  const int64_t slots = (int64_t)per_cu * device_cus();
+  const int max_nch = std::max(1, (g.nz + 15) / 16);
   int nch = nch_override;
-  if (nch <= 0) nch = (rounds * slots + tiles / 2) / tiles;
-  nch = std::max(1, std::min(nch, (g.nz + 15) / 16));
+  if (nch <= 0 && rounds > 0) nch = (int)((rounds * slots + tiles / 2) / tiles);
+  if (nch <= 0) {
+    double best = 1e300;
+    for (int c = 1; c <= max_nch; ++c) {
+      const int zc = (g.nz + c - 1) / c;
+      if ((g.nz + zc - 1) / zc != c) continue;  // same chunks as a smaller count
+      const double cost = launch_cost((double)(c * tiles) / (double)slots, zc, halo);
+      if (cost < best) {
+        best = cost;
+        nch = c;
+      }
+    }
+  }
+  nch = std::max(1, std::min(nch, max_nch));
   m.zc = (g.nz + nch - 1) / nch;
   m.nchunks = (g.nz + m.zc - 1) / m.zc;
-  m.nblocks = tiles * m.nchunks;
+  m.nblocks = (int)(tiles * m.nchunks);
   return m;
 }
 
+// Halo cost of the step kernels in plane-equivalents: 8 planes times the
+// stencil fields' share of the bytes per point (forward: 4 of 20 B with
+// variable density; adjoint: 8 of 32 B).
+constexpr double kFwdHalo = 8.0 * 4.0 / 20.0, kAdjHalo = 8.0 * 8.0 / 32.0;
+
 // Forward tile shapes selectable at run time: (rows per thread, wavefronts).
+// Variant 0 was the fastest at 576^3 (703 us per step against 747 us for
+// 4 x 4 with the same chunking).
 template <int V>
 struct FwdShape;
 template <>
 struct FwdShape<0> {
-  static constexpr int RY = 4, NW = 4;  // 64 x 16
+  static constexpr int RY = 2, NW = 8;  // 64 x 16
 };
 template <>
 struct FwdShape<1> {
-  static constexpr int RY = 2, NW = 4;  // 64 x 8
+  static constexpr int RY = 4, NW = 4;  // 64 x 16
 };
 template <>
 struct FwdShape<2> {
+  static constexpr int RY = 2, NW = 4;  // 64 x 8
+};
+template <>
+struct FwdShape<3> {
   static constexpr int RY = 4, NW = 8;  // 64 x 32
+};
+
+// Adjoint tile shapes selectable at run time (variants 0 and 1 are within
+// 0.5 per cent of each other at 576^3; 4 x 4 is 6 per cent slower).
+template <int V>
+struct AdjShape;
+template <>
+struct AdjShape<0> {
+  static constexpr int RY = 2, NW = 8;  // 64 x 16
+};
+template <>
+struct AdjShape<1> {
+  static constexpr int RY = 2, NW = 4;  // 64 x 8
+};
+template <>
+struct AdjShape<2> {
+  static constexpr int RY = 4, NW = 4;  // 64 x 16
 };
 
 template <int V, bool VD>
@@ -528,7 +589,8 @@ hipError_t fwd_launch(const StepGrid &g, const float *cur, const float *prev, fl
                       float *seis_tm, const Tuning &tu, hipStream_t stream) {
   using S = FwdShape<V>;
   static const int nch_env = env_int("WFD_ZCHUNKS_FWD", 0);  // 0 = automatic
-  const TileMap map = make_map(g, fwd_rows<V>(), fwd_per_cu<V, VD>(), nch_env, tu.rounds);
+  const TileMap map =
+      make_map(g, fwd_rows<V>(), fwd_per_cu<V, VD>(), nch_env, tu.rounds, kFwdHalo);
   hipLaunchKernelGGL((k_forward<S::RY, S::NW, VD>), dim3(map.nblocks),
                      dim3(Tile<S::RY, S::NW>::NTHREADS), 0, stream, g, cur, prev, out, src, n,
                      rec, rec_scale, seis_tm, map);
@@ -544,19 +606,38 @@ hipError_t fwd_multi_launch(const WindowStep *wins, int nwin, int nblocks, int n
   return hipGetLastError();
 }
 
-template <int RY, int NW, bool VD, bool ILLUM>
-hipError_t adj_launch(const StepGrid &g, const float *cur, const float *prev, float *out,
-                      const RecTable &rec, const float *res_tm, int m, const float *wm,
-                      float *grad, float *illum, int border, int mnx, int mny, int mnz,
-                      hipStream_t stream) {
-  using T = Tile<RY, NW>;
-  static const int per_cu = blocks_per_cu(k_adjoint<RY, NW, VD, ILLUM>, T::NTHREADS);
+template <int V, bool VD, bool ILLUM>
+hipError_t adj_launch(const Tuning &tu, const StepGrid &g, const float *cur, const float *prev,
+                      float *out, const RecTable &rec, const float *res_tm, int m,
+                      const float *wm, float *grad, float *illum, int border, int mnx, int mny,
+                      int mnz, hipStream_t stream) {
+  using S = AdjShape<V>;
+  using T = Tile<S::RY, S::NW>;
+  static const int per_cu = blocks_per_cu(k_adjoint<S::RY, S::NW, VD, ILLUM>, T::NTHREADS);
   static const int nch = env_int("WFD_ZCHUNKS_ADJ", 0);  // 0 = automatic
-  const TileMap map = make_map(g, T::TY, per_cu, nch, 4);
-  hipLaunchKernelGGL((k_adjoint<RY, NW, VD, ILLUM>), dim3(map.nblocks), dim3(T::NTHREADS), 0,
-                     stream, g, cur, prev, out, rec, res_tm, m, wm, grad, illum, border, mnx, mny,
-                     mnz, map);
+  const TileMap map = make_map(g, T::TY, per_cu, nch, tu.adj_rounds, kAdjHalo);
+  hipLaunchKernelGGL((k_adjoint<S::RY, S::NW, VD, ILLUM>), dim3(map.nblocks), dim3(T::NTHREADS),
+                     0, stream, g, cur, prev, out, rec, res_tm, m, wm, grad, illum, border, mnx,
+                     mny, mnz, map);
   return hipGetLastError();
+}
+
+template <int V>
+hipError_t adj_dispatch(const Tuning &tu, const StepGrid &g, const float *cur, const float *prev,
+                        float *out, const RecTable &rec, const float *res_tm, int m,
+                        const float *wm, float *grad, float *illum, int border, int mnx, int mny,
+                        int mnz, hipStream_t stream) {
+  const bool vd = g.m2 != nullptr;
+#define WFD_ADJ(VD_, IL_)                                                                     \
+  return adj_launch<V, VD_, IL_>(tu, g, cur, prev, out, rec, res_tm, m, wm, grad, illum, border, \
+                                 mnx, mny, mnz, stream)
+  if (vd) {
+    if (illum) WFD_ADJ(true, true);
+    WFD_ADJ(true, false);
+  }
+  if (illum) WFD_ADJ(false, true);
+  WFD_ADJ(false, false);
+#undef WFD_ADJ
 }
 
 }  // namespace
@@ -575,6 +656,7 @@ hipError_t launch_forward_step(const StepGrid &g, const float *cur, const float 
   switch (tu.variant) {
     case 1: WFD_FWD(1);
     case 2: WFD_FWD(2);
+    case 3: WFD_FWD(3);
     default: WFD_FWD(0);
   }
 #undef WFD_FWD
@@ -586,9 +668,10 @@ int forward_tile_map(const StepGrid &g, const Tuning &tu, TileMap *map) {
   switch (tu.variant) {
     case 1: ty = fwd_rows<1>(); per_cu = vd ? fwd_per_cu<1, true>() : fwd_per_cu<1, false>(); break;
     case 2: ty = fwd_rows<2>(); per_cu = vd ? fwd_per_cu<2, true>() : fwd_per_cu<2, false>(); break;
+    case 3: ty = fwd_rows<3>(); per_cu = vd ? fwd_per_cu<3, true>() : fwd_per_cu<3, false>(); break;
     default: ty = fwd_rows<0>(); per_cu = vd ? fwd_per_cu<0, true>() : fwd_per_cu<0, false>(); break;
   }
-  *map = make_map(g, ty, per_cu, 0, tu.rounds);
+  *map = make_map(g, ty, per_cu, 0, tu.rounds, kFwdHalo);
   return map->nblocks;
 }
 
@@ -599,25 +682,26 @@ hipError_t launch_forward_multi(const WindowStep *wins, int nwin, int nblocks, i
                       : fwd_multi_launch<1, false>(wins, nwin, nblocks, n, stream);
     case 2: return vd ? fwd_multi_launch<2, true>(wins, nwin, nblocks, n, stream)
                       : fwd_multi_launch<2, false>(wins, nwin, nblocks, n, stream);
+    case 3: return vd ? fwd_multi_launch<3, true>(wins, nwin, nblocks, n, stream)
+                      : fwd_multi_launch<3, false>(wins, nwin, nblocks, n, stream);
     default: return vd ? fwd_multi_launch<0, true>(wins, nwin, nblocks, n, stream)
                        : fwd_multi_launch<0, false>(wins, nwin, nblocks, n, stream);
   }
 }
 
-hipError_t launch_adjoint_step(const StepGrid &g, const float *cur, const float *prev, float *out,
-                               const RecTable &rec, const float *res_tm, int m,
-                               const float *wm, float *grad, float *illum, int border, int mnx,
-                               int mny, int mnz, hipStream_t stream) {
-  const bool vd = g.m2 != nullptr;
-  if (vd)
-    return illum ? adj_launch<RY_ADJ, NW_ADJ, true, true>(g, cur, prev, out, rec, res_tm, m, wm, grad,
-                                                  illum, border, mnx, mny, mnz, stream)
-                 : adj_launch<RY_ADJ, NW_ADJ, true, false>(g, cur, prev, out, rec, res_tm, m, wm, grad,
-                                                   illum, border, mnx, mny, mnz, stream);
-  return illum ? adj_launch<RY_ADJ, NW_ADJ, false, true>(g, cur, prev, out, rec, res_tm, m, wm, grad,
-                                                 illum, border, mnx, mny, mnz, stream)
-               : adj_launch<RY_ADJ, NW_ADJ, false, false>(g, cur, prev, out, rec, res_tm, m, wm, grad,
-                                                  illum, border, mnx, mny, mnz, stream);
+hipError_t launch_adjoint_step(const Tuning &tu, const StepGrid &g, const float *cur,
+                               const float *prev, float *out, const RecTable &rec,
+                               const float *res_tm, int m, const float *wm, float *grad,
+                               float *illum, int border, int mnx, int mny, int mnz,
+                               hipStream_t stream) {
+  switch (tu.adj_variant) {
+    case 1: return adj_dispatch<1>(tu, g, cur, prev, out, rec, res_tm, m, wm, grad, illum,
+                                   border, mnx, mny, mnz, stream);
+    case 2: return adj_dispatch<2>(tu, g, cur, prev, out, rec, res_tm, m, wm, grad, illum,
+                                   border, mnx, mny, mnz, stream);
+    default: return adj_dispatch<0>(tu, g, cur, prev, out, rec, res_tm, m, wm, grad, illum,
+                                    border, mnx, mny, mnz, stream);
+  }
 }
 
 }  // namespace wfd

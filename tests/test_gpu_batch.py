@@ -126,24 +126,45 @@ def test_batch_rejects_bad_arguments():
     b.close()
 
 
-@pytest.mark.parametrize("variant,rounds", [(0, 0), (0, 2), (1, 0), (1, 8), (2, 0), (2, 4)])
-def test_tile_shapes_are_bitwise_identical(variant, rounds):
+@pytest.mark.parametrize("variant,rounds", [(0, 0), (0, 2), (1, 0), (1, 8), (2, 0), (2, 4),
+                                            (3, 0), (3, 6)])
+def test_forward_tile_shapes_are_bitwise_identical(variant, rounds):
     torch = gpu_or_skip()
     w = seisgen.workload("c2_small")
-    say(f"[tuning] c2_small variant {variant} rounds {rounds}")
+    say(f"[tuning] forward c2_small variant {variant} rounds {rounds}")
     P = propagator(w)
     wav = torch.from_numpy(w.wavelet).cuda()
     base, fb = P.forward(wav, w.sources[0], w.receivers, final=True)
     base, fb = base.clone(), fb.clone()
     P.set_tuning(variant, rounds)
-    assert P.tuning() == (variant, rounds)
+    assert P.tuning() == (variant, rounds, 0, 0)
     s, f = P.forward(wav, w.sources[0], w.receivers, final=True)
     torch.cuda.synchronize()
     assert torch.equal(s, base)
     assert torch.equal(f, fb)
 
 
-def test_autotune_picks_a_shape_and_keeps_results():
+@pytest.mark.parametrize("adj_variant,adj_rounds", [(0, 2), (1, 0), (1, 8), (2, 0), (2, 3)])
+def test_adjoint_tile_shapes_are_bitwise_identical(adj_variant, adj_rounds):
+    torch = gpu_or_skip()
+    w = seisgen.workload("c4_fd_vd")
+    say(f"[tuning] adjoint c4_fd_vd variant {adj_variant} rounds {adj_rounds}")
+    P = propagator(w)
+    wav = torch.from_numpy(w.wavelet).cuda()
+    dobs = torch.zeros((len(w.receivers), w.nt), dtype=torch.float32, device="cuda")
+    illum0 = torch.zeros((w.nz, w.ny, w.nx), dtype=torch.float32, device="cuda")
+    J0, g0 = P.gradient(wav, w.sources[0], w.receivers, dobs, illum=illum0)
+    J0, g0 = float(J0.item()), g0.clone()
+    P.set_tuning(1, 3, adj_variant, adj_rounds)
+    illum1 = torch.zeros_like(illum0)
+    J1, g1 = P.gradient(wav, w.sources[0], w.receivers, dobs, illum=illum1)
+    torch.cuda.synchronize()
+    assert float(J1.item()) == J0 and J0 > 0
+    assert torch.equal(g1, g0)
+    assert torch.equal(illum1, illum0)
+
+
+def test_autotune_picks_shapes_and_keeps_results():
     torch = gpu_or_skip()
     from paper_2502_12350_amd import WfdError
     w = seisgen.workload("c2_small")
@@ -151,15 +172,26 @@ def test_autotune_picks_a_shape_and_keeps_results():
     P = propagator(w)
     wav = torch.from_numpy(w.wavelet).cuda()
     base = P.forward(wav, w.sources[0], w.receivers).clone()
-    v, r, us = P.autotune(steps=5)
-    say(f"  picked variant {v} rounds {r}: {us:.1f} us/step")
-    assert v in (0, 1, 2) and r in (2, 4, 8) and us > 0
-    assert P.tuning() == (v, r)
+    dobs = torch.zeros_like(base)
+    _, gbase = P.gradient(wav, w.sources[0], w.receivers, dobs)
+    gbase = gbase.clone()
+    t, fus, aus = P.autotune(steps=5)
+    say(f"  picked {t}: forward {fus:.1f} us/step, adjoint {aus:.1f} us/step")
+    assert t[0] in range(4) and t[2] in range(3)
+    assert t[1] in (0, 2, 3, 4, 6, 8) and t[3] in (0, 2, 3, 4, 6, 8)
+    assert fus > 0 and aus > 0
+    assert P.tuning() == t
     s = P.forward(wav, w.sources[0], w.receivers)
+    _, g = P.gradient(wav, w.sources[0], w.receivers, dobs)
     torch.cuda.synchronize()
     assert torch.equal(s, base)
+    assert torch.equal(g, gbase)
     with pytest.raises(WfdError):
-        P.set_tuning(3, 0)
+        P.set_tuning(4, 0)
+    with pytest.raises(WfdError):
+        P.set_tuning(0, 0, 3, 0)
+    with pytest.raises(WfdError):
+        P.set_tuning(0, 65)
     with pytest.raises(WfdError):
         P.autotune(steps=0)
 
