@@ -177,10 +177,10 @@ wfd_status wfd_gradient_finish(wfd_ctx *ctx, float *grad_dev, int32_t zero_top_p
 /* Launch shapes of the context's step kernels (the paper tunes its CUDA
  * block size per architecture; these are the CDNA4 tile choices):
  *   fwd_variant  forward tiles (rows per thread x wavefronts per block):
- *                0: 2x8 = 64x16 tiles [default]  1: 4x4 = 64x16
- *                2: 2x4 = 64x8                    3: 4x8 = 64x32
- *   adj_variant  adjoint tiles: 0: 2x8 = 64x16 [default]  1: 2x4 = 64x8
- *                2: 4x4 = 64x16
+ *                0: 2x8 = 64x16 tiles [default]  1: 2x16 = 64x32
+ *                2: 2x4 = 64x8                    3: 4x4 = 64x16
+ *   adj_variant  adjoint tiles: 0: 2x16 = 64x32 [default]  1: 2x8 = 64x16
+ *                2: 2x4 = 64x8
  *   *_rounds     z chunking aims at this many rounds of resident blocks per
  *                launch (at most 64); 0 = automatic: the chunk count that
  *                minimises a model of the launch time (rounds of resident

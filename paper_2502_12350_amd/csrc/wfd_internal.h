@@ -45,8 +45,8 @@ struct TileMap {
 };
 
 // Step-kernel tuning.  Tile shapes (rows per thread x wavefronts per block):
-//   forward  0: 2x8 (64x16 tiles)  1: 4x4 (64x16)  2: 2x4 (64x8)  3: 4x8 (64x32)
-//   adjoint  0: 2x8 (64x16)        1: 2x4 (64x8)   2: 4x4 (64x16)
+//   forward  0: 2x8 (64x16 tiles)  1: 2x16 (64x32)  2: 2x4 (64x8)  3: 4x4 (64x16)
+//   adjoint  0: 2x16 (64x32)       1: 2x8 (64x16)   2: 2x4 (64x8)
 // and the number of rounds of resident blocks the z chunking aims for
 // (0 = chosen by the launch cost model).  Every shape computes bitwise the
 // same values.

@@ -98,6 +98,11 @@ __device__ __forceinline__ void st_stream(float *f, int64_t p, float v) {
 }
 
 // Per-thread view of one stenciled field: register queue + halo staging.
+// The halo of a plane is loaded together with the plane's interior (five
+// planes ahead of its use), when the neighbouring tiles load the same lines
+// as their interior, and waits in a register delay line; loading it one plane
+// ahead instead needed L2 to keep four planes of every resident tile, and the
+// adjoint (two stenciled fields) then re-read its halo from HBM.
 // K tags the kernel family (0 forward, 1 adjoint): each family gets its own
 // instantiations of the tile helpers.  With shared ones, hipcc allocated the
 // adjoint 137 VGPRs instead of 123 once a forward shape used the same tile,
@@ -105,9 +110,9 @@ __device__ __forceinline__ void st_stream(float *f, int64_t p, float v) {
 template <int RY, int NW, int K>
 struct Marcher {
   using T = Tile<RY, NW>;
-  float q[RY][9];   // planes z-4 .. z+4 of the thread's RY points
-  float nxt[RY];    // plane z+5 (in flight)
-  float hv[T::HPT]; // halo of the plane written to LDS next
+  float q[RY][9];       // planes z-4 .. z+4 of the thread's RY points
+  float nxt[RY];        // plane z+5 (in flight)
+  float hq[5][T::HPT];  // halo of planes z .. z+4 (hq[0] is staged next)
 
   __device__ __forceinline__ static float ld(const float *f, const StepGrid &g, int z, uint32_t o,
                                              bool ok) {
@@ -121,7 +126,9 @@ struct Marcher {
 #pragma unroll
       for (int i = 0; i < 9; ++i) q[j][i] = ld(f, g, z0 - 4 + i, off[j], in[j]);
 #pragma unroll
-    for (int i = 0; i < T::HPT; ++i) hv[i] = ld(f, g, z0, hoff[i], hin[i]);
+    for (int d = 0; d < 5; ++d)
+#pragma unroll
+      for (int i = 0; i < T::HPT; ++i) hq[d][i] = ld(f, g, z0 + d, hoff[i], hin[i]);
   }
   __device__ __forceinline__ void stage(float (*s)[T::LX], int wave, int lane,
                                         const int *hslot) {
@@ -129,15 +136,20 @@ struct Marcher {
     for (int j = 0; j < RY; ++j) s[4 + wave * RY + j][4 + lane] = q[j][4];
 #pragma unroll
     for (int i = 0; i < T::HPT; ++i)
-      if (hslot[i] >= 0) (&s[0][0])[hslot[i]] = hv[i];
+      if (hslot[i] >= 0) (&s[0][0])[hslot[i]] = hq[0][i];
   }
+  // After stage(): the interior and the halo of plane z+5.
   __device__ __forceinline__ void fetch(const float *f, const StepGrid &g, int z,
                                         const uint32_t *off, const bool *in,
                                         const uint32_t *hoff, const bool *hin) {
 #pragma unroll
     for (int j = 0; j < RY; ++j) nxt[j] = ld(f, g, z + 5, off[j], in[j]);
 #pragma unroll
-    for (int i = 0; i < T::HPT; ++i) hv[i] = ld(f, g, z + 1, hoff[i], hin[i]);
+    for (int d = 0; d < 4; ++d)
+#pragma unroll
+      for (int i = 0; i < T::HPT; ++i) hq[d][i] = hq[d + 1][i];
+#pragma unroll
+    for (int i = 0; i < T::HPT; ++i) hq[4][i] = ld(f, g, z + 5, hoff[i], hin[i]);
   }
   __device__ __forceinline__ void shift() {
 #pragma unroll
@@ -532,8 +544,8 @@ TileMap make_map(const StepGrid &g, int ty, int per_cu, int nch_override, int ro
 constexpr double kFwdHalo = 8.0 * 4.0 / 20.0, kAdjHalo = 8.0 * 8.0 / 32.0;
 
 // Forward tile shapes selectable at run time: (rows per thread, wavefronts).
-// Variant 0 was the fastest at 576^3 (703 us per step against 747 us for
-// 4 x 4 with the same chunking).
+// Variant 0 was the fastest at 576^3 (694 us per step against 793 us for
+// 64 x 32 tiles and 745 us for 4 x 4 with the same chunking rule).
 template <int V>
 struct FwdShape;
 template <>
@@ -542,7 +554,7 @@ struct FwdShape<0> {
 };
 template <>
 struct FwdShape<1> {
-  static constexpr int RY = 4, NW = 4;  // 64 x 16
+  static constexpr int RY = 2, NW = 16;  // 64 x 32
 };
 template <>
 struct FwdShape<2> {
@@ -550,24 +562,26 @@ struct FwdShape<2> {
 };
 template <>
 struct FwdShape<3> {
-  static constexpr int RY = 4, NW = 8;  // 64 x 32
+  static constexpr int RY = 4, NW = 4;  // 64 x 16
 };
 
-// Adjoint tile shapes selectable at run time (variants 0 and 1 are within
-// 0.5 per cent of each other at 576^3; 4 x 4 is 6 per cent slower).
+// Adjoint tile shapes selectable at run time.  With two stenciled fields and
+// their halo delay lines, only the 64 x 32 tile (one halo value per thread
+// per plane) stays within 128 VGPRs (4 waves per SIMD): 1213 us per step at
+// 576^3 against 1432 us (64 x 8) and 1654 us (64 x 16).
 template <int V>
 struct AdjShape;
 template <>
 struct AdjShape<0> {
-  static constexpr int RY = 2, NW = 8;  // 64 x 16
+  static constexpr int RY = 2, NW = 16;  // 64 x 32
 };
 template <>
 struct AdjShape<1> {
-  static constexpr int RY = 2, NW = 4;  // 64 x 8
+  static constexpr int RY = 2, NW = 8;  // 64 x 16
 };
 template <>
 struct AdjShape<2> {
-  static constexpr int RY = 4, NW = 4;  // 64 x 16
+  static constexpr int RY = 2, NW = 4;  // 64 x 8
 };
 
 template <int V, bool VD>
