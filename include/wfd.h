@@ -265,6 +265,73 @@ wfd_status wfd_cfl_ratio(const wfd_grid *grid, double vmax, double m2max, double
 wfd_status wfd_checkpoint_plan(int32_t nt, int32_t n_snapshots, int32_t *actions,
                                int64_t capacity, int64_t *n_actions, int64_t *n_forward_steps);
 
+/* ---- learned gradient preconditioner (BF16 3-D CNN) ----------------------
+ *
+ * Replaces the paper's fixed gradient smoothing (GradientPreconditioning,
+ * Bessel or Laplace filters) by a small network of 3 x 3 x 3 convolutions
+ * with "same" zero padding: 2 -> 16 -> 16 -> 16 -> 1 channels, ReLU after the
+ * first three.  Stateless calls on device buffers, enqueued on `stream` (a
+ * hipStream_t, NULL = legacy default stream) on the current device.
+ *
+ * Layouts: BF16 values are passed as uint16_t bit patterns.  Volumes are
+ * channels-last [nz][ny][nx][C].  Master weights are FP32 W[27][cin][cout]
+ * with tap = 9 kz + 3 ky + kx reading the input at (z + kz - 1, y + ky - 1,
+ * x + kx - 1).  Convolutions take weights packed for the matrix cores by
+ * wfd_cnn_pack_weights.  All buffers are caller-owned; no call allocates.
+ * Supported layers: (cin, cout) = (2, 16), (16, 16), (16, 1). */
+
+#define WFD_CNN_REDUCE_BYTES 8192  /* workspace of wfd_cnn_mse / wfd_cnn_pack_input */
+
+/* Number of uint16_t of a packed weight matrix: flip = 0 for the forward
+ * convolution, 1 for the data-gradient convolution of the same layer. */
+wfd_status wfd_cnn_packed_elems(int32_t cin, int32_t cout, int32_t flip, int64_t *elems);
+
+/* Pack FP32 master weights w[27][cin][cout] into BF16 matrix-core operands:
+ *   flip = 0: A[16][K], A[co][tap * cin + ci] = bf16(w[tap][ci][co]);
+ *   flip = 1: A[16][K], A[ci][tap * cout + co] = bf16(w[26 - tap][ci][co])
+ * (rounded to nearest even; rows and columns past the layer are zero). */
+wfd_status wfd_cnn_pack_weights(const float *w_dev, int32_t cin, int32_t cout, int32_t flip,
+                                uint16_t *packed_dev, void *stream);
+
+/* out[p][co] = sum_{tap, ci} in[p + offset(tap)][ci] * A[co][tap * cin + ci]
+ * (+ bias[co]), then max(., 0) if relu, then 0 where mask[p][co] <= 0 if a
+ * mask is given; BF16 products, FP32 sums.  With the flip-packed weights of a
+ * layer (cin, cout) this is the data gradient of that layer: call it with
+ * cin' = cout and cout' = cin.  (cin, cout) in {(2,16), (16,16), (16,1),
+ * (1,16)}.  Written as BF16 (rounded to nearest even) and/or FP32
+ * channels-last; in, packed and outputs 16-byte aligned. */
+wfd_status wfd_cnn_conv(const uint16_t *in_dev, int32_t nx, int32_t ny, int32_t nz, int32_t cin,
+                        int32_t cout, const uint16_t *packed_dev, const float *bias_or_null,
+                        int32_t relu, const uint16_t *mask_or_null, uint16_t *out_bf16_or_null,
+                        float *out_f32_or_null, void *stream);
+
+/* Workspace of wfd_cnn_wgrad for an nx x ny x nz volume. */
+wfd_status wfd_cnn_wgrad_workspace_bytes(int32_t nx, int32_t ny, int32_t nz, size_t *bytes);
+
+/* Weight and bias gradients of layer (cin, cout) from its input `in` and the
+ * gradient dz of its output (before the layer's ReLU, i.e. already masked):
+ *   dw[tap][ci][co] = sum_p in[p + offset(tap)][ci] dz[p][co]   (FP32, written)
+ *   db[co] = sum_p dz[p][co]                                     (if non-NULL)
+ * BF16 products, FP32 sums in a fixed order (deterministic). */
+wfd_status wfd_cnn_wgrad(const uint16_t *in_dev, const uint16_t *dz_dev, int32_t nx, int32_t ny,
+                         int32_t nz, int32_t cin, int32_t cout, float *dw_dev,
+                         float *db_dev_or_null, void *work_dev, size_t work_bytes, void *stream);
+
+/* Mean squared error of y against t (n FP32 values each): loss_dev (FP64
+ * scalar, written) = mean((y - t)^2), dy_dev = bf16(2 (y - t) / n). */
+wfd_status wfd_cnn_mse(const float *y_dev, const float *t_dev, int64_t n, uint16_t *dy_dev,
+                       double *loss_dev, void *work_dev, size_t work_bytes, void *stream);
+
+/* One Adam step (Kingma & Ba 2015) on n FP32 parameters; step counts from 1. */
+wfd_status wfd_cnn_adam(float *w_dev, const float *g_dev, float *m_dev, float *v_dev, int32_t n,
+                        float lr, float beta1, float beta2, float eps, int32_t step,
+                        void *stream);
+
+/* Network input [n][2] = (bf16(grad / max|grad|), bf16(illum / max|illum|)),
+ * each channel left unscaled if its maximum is 0. */
+wfd_status wfd_cnn_pack_input(const float *grad_dev, const float *illum_dev, int64_t n,
+                              uint16_t *out_dev, void *work_dev, size_t work_bytes, void *stream);
+
 /* ---- measurement ---------------------------------------------------------- */
 
 enum {

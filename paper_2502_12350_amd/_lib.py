@@ -19,6 +19,7 @@ STATUS_NAMES = {0: "WFD_OK", -1: "WFD_E_ARG", -2: "WFD_E_CFL", -3: "WFD_E_RANGE"
 CKPT_FULL = 0
 CKPT_REVOLVE = 1
 K_FORWARD, K_ADJOINT, K_OTHER = 0, 1, 2
+CNN_REDUCE_BYTES = 8192
 
 
 class wfd_grid(C.Structure):
@@ -69,6 +70,18 @@ _SIGS = {
                                    C.POINTER(C.c_size_t)]),
     "wfd_batch_run": (C.c_int, [_P, C.c_int32]),
     "wfd_batch_destroy": (C.c_int, [_P]),
+    "wfd_cnn_packed_elems": (C.c_int, [C.c_int32, C.c_int32, C.c_int32, C.POINTER(C.c_int64)]),
+    "wfd_cnn_pack_weights": (C.c_int, [_P, C.c_int32, C.c_int32, C.c_int32, _P, _P]),
+    "wfd_cnn_conv": (C.c_int, [_P, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_int32, _P, _P,
+                               C.c_int32, _P, _P, _P, _P]),
+    "wfd_cnn_wgrad_workspace_bytes": (C.c_int, [C.c_int32, C.c_int32, C.c_int32,
+                                                C.POINTER(C.c_size_t)]),
+    "wfd_cnn_wgrad": (C.c_int, [_P, _P, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_int32,
+                                _P, _P, _P, C.c_size_t, _P]),
+    "wfd_cnn_mse": (C.c_int, [_P, _P, C.c_int64, _P, _P, _P, C.c_size_t, _P]),
+    "wfd_cnn_adam": (C.c_int, [_P, _P, _P, _P, C.c_int32, C.c_float, C.c_float, C.c_float,
+                               C.c_float, C.c_int32, _P]),
+    "wfd_cnn_pack_input": (C.c_int, [_P, _P, C.c_int64, _P, _P, C.c_size_t, _P]),
     "wfd_map_position": (C.c_int, [C.POINTER(wfd_grid), _D3, C.POINTER(C.c_int32)]),
     "wfd_cfl_ratio": (C.c_int, [C.POINTER(wfd_grid), C.c_double, C.c_double, _D3]),
     "wfd_checkpoint_plan": (C.c_int, [C.c_int32, C.c_int32, C.POINTER(C.c_int32), C.c_int64,

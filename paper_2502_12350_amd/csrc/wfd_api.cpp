@@ -1197,4 +1197,103 @@ wfd_status wfd_kernel_stats(wfd_ctx *c, int32_t kernel_class, int64_t *launches,
   return WFD_OK;
 }
 
+// ---- learned gradient preconditioner ---------------------------------------
+
+wfd_status wfd_cnn_packed_elems(int32_t cin, int32_t cout, int32_t flip, int64_t *elems) {
+  if (!elems) return fail(WFD_E_ARG, "NULL argument");
+  const bool layer = (cin == 2 && cout == 16) || (cin == 16 && cout == 16) ||
+                     (cin == 16 && cout == 1);
+  if (!layer || (flip != 0 && flip != 1))
+    return fail(WFD_E_ARG, "no network layer %d -> %d (flip %d)", cin, cout, flip);
+  const int rows_in = flip ? cout : cin;
+  *elems = 16LL * ((27 * rows_in + 31) / 32 * 32);
+  return WFD_OK;
+}
+
+wfd_status wfd_cnn_pack_weights(const float *w, int32_t cin, int32_t cout, int32_t flip,
+                                uint16_t *apk, void *stream) {
+  int64_t n = 0;
+  wfd_status s = wfd_cnn_packed_elems(cin, cout, flip, &n);
+  if (s != WFD_OK) return s;
+  if (!w || !apk) return fail(WFD_E_ARG, "NULL argument");
+  HIP_TRY(wfd::launch_pack_weights(w, cin, cout, flip, apk, (hipStream_t)stream));
+  return WFD_OK;
+}
+
+wfd_status wfd_cnn_conv(const uint16_t *in, int32_t nx, int32_t ny, int32_t nz, int32_t cin,
+                        int32_t cout, const uint16_t *apk, const float *bias, int32_t relu,
+                        const uint16_t *mask, uint16_t *out_bf16, float *out_f32, void *stream) {
+  const bool shape = (cin == 2 && cout == 16) || (cin == 16 && cout == 16) ||
+                     (cin == 16 && cout == 1) || (cin == 1 && cout == 16);
+  if (!shape) return fail(WFD_E_ARG, "no convolution %d -> %d channels", cin, cout);
+  if (nx < 1 || ny < 1 || nz < 1) return fail(WFD_E_ARG, "empty volume %d x %d x %d", nx, ny, nz);
+  if ((int64_t)((nx + 63) / 64) * ((ny + 1) / 2) * ((nz + 1) / 2) > 0x7fffffffLL)
+    return fail(WFD_E_ARG, "volume too large");
+  if (!in || !apk) return fail(WFD_E_ARG, "NULL input or weights");
+  if (!out_bf16 && !out_f32) return fail(WFD_E_ARG, "no output");
+  if ((uintptr_t)in % 16 || (uintptr_t)apk % 16 || (uintptr_t)out_bf16 % 16 ||
+      (uintptr_t)out_f32 % 16)
+    return fail(WFD_E_ARG, "buffers must be 16-byte aligned");
+  HIP_TRY(wfd::launch_conv(cin, cout, in, nx, ny, nz, apk, bias, relu, mask, out_bf16, out_f32,
+                           (hipStream_t)stream));
+  return WFD_OK;
+}
+
+wfd_status wfd_cnn_wgrad_workspace_bytes(int32_t nx, int32_t ny, int32_t nz, size_t *bytes) {
+  if (!bytes) return fail(WFD_E_ARG, "NULL argument");
+  if (nx < 1 || ny < 1 || nz < 1) return fail(WFD_E_ARG, "empty volume");
+  *bytes = wfd::cnn_wgrad_workspace_floats(nx, ny, nz) * sizeof(float);
+  return WFD_OK;
+}
+
+wfd_status wfd_cnn_wgrad(const uint16_t *in, const uint16_t *dz, int32_t nx, int32_t ny,
+                         int32_t nz, int32_t cin, int32_t cout, float *dw, float *db,
+                         void *work, size_t work_bytes, void *stream) {
+  const bool layer = (cin == 2 && cout == 16) || (cin == 16 && cout == 16) ||
+                     (cin == 16 && cout == 1);
+  if (!layer) return fail(WFD_E_ARG, "no network layer %d -> %d", cin, cout);
+  if (nx < 1 || ny < 1 || nz < 1) return fail(WFD_E_ARG, "empty volume");
+  if (!in || !dz || !dw || !work) return fail(WFD_E_ARG, "NULL argument");
+  if ((uintptr_t)in % 16) return fail(WFD_E_ARG, "input must be 16-byte aligned");
+  const size_t need = wfd::cnn_wgrad_workspace_floats(nx, ny, nz) * sizeof(float);
+  if (work_bytes < need)
+    return fail(WFD_E_NOMEM, "workspace has %zu bytes, %zu needed", work_bytes, need);
+  HIP_TRY(wfd::launch_wgrad(cin, cout, in, dz, nx, ny, nz, static_cast<float *>(work), dw, db,
+                            (hipStream_t)stream));
+  return WFD_OK;
+}
+
+wfd_status wfd_cnn_mse(const float *y, const float *t, int64_t n, uint16_t *dy, double *loss,
+                       void *work, size_t work_bytes, void *stream) {
+  if (!y || !t || !dy || !loss || !work) return fail(WFD_E_ARG, "NULL argument");
+  if (n < 1) return fail(WFD_E_ARG, "n must be >= 1");
+  if (work_bytes < WFD_CNN_REDUCE_BYTES)
+    return fail(WFD_E_NOMEM, "workspace must hold %d bytes", WFD_CNN_REDUCE_BYTES);
+  HIP_TRY(wfd::launch_mse(y, t, n, dy, static_cast<double *>(work), wfd::kCnnReduceBlocks, loss,
+                          (hipStream_t)stream));
+  return WFD_OK;
+}
+
+wfd_status wfd_cnn_adam(float *w, const float *g, float *m, float *v, int32_t n, float lr,
+                        float beta1, float beta2, float eps, int32_t step, void *stream) {
+  if (!w || !g || !m || !v) return fail(WFD_E_ARG, "NULL argument");
+  if (n < 1 || step < 1) return fail(WFD_E_ARG, "n and step must be >= 1");
+  if (!(lr > 0.0f) || !(beta1 >= 0.0f && beta1 < 1.0f) || !(beta2 >= 0.0f && beta2 < 1.0f))
+    return fail(WFD_E_ARG, "bad Adam hyper-parameters");
+  HIP_TRY(wfd::launch_adam(w, g, m, v, n, lr, beta1, beta2, eps, step, (hipStream_t)stream));
+  return WFD_OK;
+}
+
+wfd_status wfd_cnn_pack_input(const float *grad, const float *illum, int64_t n, uint16_t *out,
+                              void *work, size_t work_bytes, void *stream) {
+  if (!grad || !illum || !out || !work) return fail(WFD_E_ARG, "NULL argument");
+  if (n < 1) return fail(WFD_E_ARG, "n must be >= 1");
+  if (work_bytes < WFD_CNN_REDUCE_BYTES)
+    return fail(WFD_E_NOMEM, "workspace must hold %d bytes", WFD_CNN_REDUCE_BYTES);
+  HIP_TRY(wfd::launch_pack_input(grad, illum, n, static_cast<float *>(work), wfd::kCnnReduceBlocks,
+                                 out, (hipStream_t)stream));
+  return WFD_OK;
+}
+
 }  // extern "C"
+

@@ -1,0 +1,481 @@
+// Kernels of the learned gradient preconditioner: a 3-D CNN of 3x3x3
+// convolutions ("same" zero padding) with BF16 weights and activations and
+// FP32 accumulation on the CDNA4 matrix cores.
+//
+// Layouts.  Activations are channels-last BF16 [z][y][x][C] with C in
+// {1, 2, 16}.  Master weights are FP32 W[tap][ci][co] with tap = 9 kz + 3 ky +
+// kx reading the input at offset (kz - 1, ky - 1, kx - 1).  For the matrix
+// cores they are packed as A[16][K] BF16: row = output channel (rows past the
+// layer's outputs are zero), k = tap * CIN + ci, K = 27 CIN rounded up to a
+// multiple of 32 with zeros.
+//
+// Matrix-core mapping (v_mfma_f32_16x16x32_bf16, one wavefront, lane l,
+// element e; checked on the device): A[i][k] sits in lane i + 16 (k / 8),
+// element k % 8; B[k][j] in lane j + 16 (k / 8), element k % 8; the 16 x 16
+// FP32 result D[i][j] in lane j + 16 (i / 4), element i % 4.
+//
+// Convolution as an implicit GEMM: for a row of 16 output voxels,
+// D[co][voxel] = sum_k A[co][k] X[k][voxel] with X[tap * CIN + ci][voxel] =
+// input[voxel + offset(tap)][ci].  A block stages a 66 x 4 x 4 voxel brick of
+// the input (a 64 x 2 x 2 output tile plus a one-voxel halo) in LDS; each
+// wavefront computes one 64-voxel output row as four 16 x 16 tiles with the
+// packed weights held in registers.  The data gradient is the same kernel on
+// flipped, transposed weights; the weight gradient reduces over voxels with
+// the voxel index as the matrix-core K dimension.
+#include <hip/hip_runtime.h>
+
+#include <stdint.h>
+
+#include "wfd_internal.h"
+
+namespace wfd {
+namespace {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+typedef uint16_t u16x8 __attribute__((ext_vector_type(8)));
+
+constexpr int OX = 64, OY = 2, OZ = 2;  // output tile per block
+constexpr int LXB = OX + 2, LYB = OY + 2, LZB = OZ + 2;
+constexpr int BRICK = LXB * LYB * LZB;   // voxels staged per block
+constexpr int NTHR = 256;                // 4 wavefronts
+
+__device__ __forceinline__ uint16_t to_bf16(float f) {
+  uint32_t u = __float_as_uint(f);
+  u += 0x7FFFu + ((u >> 16) & 1u);  // round to nearest, ties to even
+  return (uint16_t)(u >> 16);
+}
+__device__ __forceinline__ float from_bf16(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
+__device__ __forceinline__ bool bf16_pos(uint16_t b) { return b != 0 && !(b & 0x8000u); }
+
+constexpr int kpad(int cin) { return (27 * cin + 31) / 32 * 32; }
+
+// Block -> output tile origin.
+__device__ __forceinline__ void tile_origin(int b, int nx, int ny, int &x0, int &y0, int &z0) {
+  const int tx = (nx + OX - 1) / OX, ty = (ny + OY - 1) / OY;
+  x0 = (b % tx) * OX;
+  y0 = ((b / tx) % ty) * OY;
+  z0 = (b / (tx * ty)) * OZ;
+}
+
+// Stage the input brick (zero outside the volume) into LDS, channels-last.
+template <int CIN>
+__device__ __forceinline__ void load_brick(uint16_t *lds, const uint16_t *__restrict__ in, int nx,
+                                           int ny, int nz, int x0, int y0, int z0) {
+  if (CIN == 16) {
+    for (int q = threadIdx.x; q < BRICK * 2; q += NTHR) {
+      const int v = q >> 1, half = q & 1;
+      const int lx = v % LXB, ly = (v / LXB) % LYB, lz = v / (LXB * LYB);
+      const int gx = x0 - 1 + lx, gy = y0 - 1 + ly, gz = z0 - 1 + lz;
+      u32x4 d = {0u, 0u, 0u, 0u};
+      if (gx >= 0 && gx < nx && gy >= 0 && gy < ny && gz >= 0 && gz < nz)
+        d = *reinterpret_cast<const u32x4 *>(in + (((int64_t)gz * ny + gy) * nx + gx) * 16 +
+                                             8 * half);
+      *reinterpret_cast<u32x4 *>(lds + v * 16 + 8 * half) = d;
+    }
+  } else {
+    for (int v = threadIdx.x; v < BRICK; v += NTHR) {
+      const int lx = v % LXB, ly = (v / LXB) % LYB, lz = v / (LXB * LYB);
+      const int gx = x0 - 1 + lx, gy = y0 - 1 + ly, gz = z0 - 1 + lz;
+      const bool ok = gx >= 0 && gx < nx && gy >= 0 && gy < ny && gz >= 0 && gz < nz;
+      const int64_t g = ((int64_t)gz * ny + gy) * nx + gx;
+#pragma unroll
+      for (int c = 0; c < CIN; ++c) lds[v * CIN + c] = ok ? in[g * CIN + c] : (uint16_t)0;
+    }
+  }
+}
+
+// LDS voxel index of output voxel (lx, ly, lz) of the tile read through tap t.
+__device__ __forceinline__ int tap_voxel(int t, int lx, int ly, int lz) {
+  const int dz = t / 9, dy = (t / 3) % 3, dx = t % 3;  // offsets + 1
+  return ((lz + dz) * LYB + (ly + dy)) * LXB + (lx + dx);
+}
+
+// B fragment of chunk c for the lane's output voxel (lx, ly, lz) and lane group g.
+template <int CIN>
+__device__ __forceinline__ bf16x8 gather_b(const uint16_t *lds, int c, int lx, int ly, int lz,
+                                           int g) {
+  if (CIN == 16) {
+    const int t = 2 * c + (g >> 1);
+    u32x4 d = {0u, 0u, 0u, 0u};
+    if (t < 27)
+      d = *reinterpret_cast<const u32x4 *>(lds + tap_voxel(t, lx, ly, lz) * 16 + 8 * (g & 1));
+    return __builtin_bit_cast(bf16x8, d);
+  } else {
+    u16x8 d;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const int k = 32 * c + 8 * g + e;
+      const int t = k / CIN, ci = k % CIN;
+      d[e] = t < 27 ? lds[tap_voxel(t, lx, ly, lz) * CIN + ci] : (uint16_t)0;
+    }
+    return __builtin_bit_cast(bf16x8, d);
+  }
+}
+
+// Convolution (forward or data gradient).  out = conv(in; A) [+ bias], then
+// relu, then * (mask > 0); written as BF16 and/or FP32 channels-last with COUT
+// channels.  Every output voxel of the tile is computed by exactly one lane.
+template <int CIN, int COUT>
+__global__ void __launch_bounds__(NTHR)
+    k_conv(const uint16_t *__restrict__ in, int nx, int ny, int nz,
+           const uint16_t *__restrict__ apk, const float *__restrict__ bias, int relu,
+           const uint16_t *__restrict__ mask, uint16_t *__restrict__ out_bf,
+           float *__restrict__ out_f) {
+  constexpr int K = kpad(CIN), NC = K / 32;
+  __shared__ __attribute__((aligned(16))) uint16_t lds[BRICK * CIN + 8];
+  int x0, y0, z0;
+  tile_origin(blockIdx.x, nx, ny, x0, y0, z0);
+  load_brick<CIN>(lds, in, nx, ny, nz, x0, y0, z0);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int j = lane & 15, g = lane >> 4;
+  // weights: A fragment of every chunk (row co = j, k = 32 c + 8 g + e)
+  bf16x8 a[NC];
+#pragma unroll
+  for (int c = 0; c < NC; ++c)
+    a[c] = __builtin_bit_cast(
+        bf16x8, *reinterpret_cast<const u32x4 *>(apk + (size_t)j * K + 32 * c + 8 * g));
+  __syncthreads();
+  const int ly = wave & 1, lz = wave >> 1;  // this wave's output row in the tile
+  const int gy = y0 + ly, gz = z0 + lz;
+  f32x4 acc[4];
+#pragma unroll
+  for (int tl = 0; tl < 4; ++tl) {
+    acc[tl] = f32x4{0.f, 0.f, 0.f, 0.f};
+    const int lx = 16 * tl + j;
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      const bf16x8 b = gather_b<CIN>(lds, c, lx, ly, lz, g);
+      acc[tl] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[c], b, acc[tl], 0, 0, 0);
+    }
+  }
+  if (gy >= ny || gz >= nz) return;
+  // epilogue: lane holds D[co = 4 g + e][voxel j] of each tile
+#pragma unroll
+  for (int tl = 0; tl < 4; ++tl) {
+    const int gx = x0 + 16 * tl + j;
+    if (gx >= nx) continue;
+    const int64_t vox = ((int64_t)gz * ny + gy) * nx + gx;
+    float v[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int co = 4 * g + e;
+      float s = acc[tl][e];
+      if (bias && co < COUT) s += bias[co];
+      if (relu) s = fmaxf(s, 0.0f);
+      if (mask && co < COUT && !bf16_pos(mask[vox * COUT + co])) s = 0.0f;
+      v[e] = s;
+    }
+    if (COUT == 16) {
+      if (out_bf) {
+        const uint32_t lo = (uint32_t)to_bf16(v[0]) | ((uint32_t)to_bf16(v[1]) << 16);
+        const uint32_t hi = (uint32_t)to_bf16(v[2]) | ((uint32_t)to_bf16(v[3]) << 16);
+        *reinterpret_cast<uint2 *>(out_bf + vox * 16 + 4 * g) = make_uint2(lo, hi);
+      }
+      if (out_f)
+        *reinterpret_cast<float4 *>(out_f + vox * 16 + 4 * g) = make_float4(v[0], v[1], v[2], v[3]);
+    } else if (g == 0) {  // single output channel: co = 0 is element 0 of group 0
+      if (out_bf) out_bf[vox] = to_bf16(v[0]);
+      if (out_f) out_f[vox] = v[0];
+    }
+  }
+}
+
+// Weight gradient partials: for every tap, D[co][ci] = sum over the block's
+// voxels of dz[voxel][co] * in[voxel + offset(tap)][ci].  Blocks walk tiles
+// with a grid stride; wave w owns taps w, w + 4, ...; each block writes
+// partial[block][tap][co][ci] (16 x 16 per tap, zero-padded channels), and
+// wave 0 also sums dz per channel for the bias gradient (partial_b[block][co]).
+template <int CIN, int COUT>
+__global__ void __launch_bounds__(NTHR)
+    k_wgrad(const uint16_t *__restrict__ in, const uint16_t *__restrict__ dz, int nx, int ny,
+            int nz, int ntiles, float *__restrict__ partial, float *__restrict__ partial_b) {
+  __shared__ __attribute__((aligned(16))) uint16_t lds[BRICK * CIN + 8];
+  __shared__ uint16_t ldz[OX * OY * OZ * COUT];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int j = lane & 15, g = lane >> 4;
+  constexpr int NT = 7;  // taps per wave (27 = 7 + 7 + 7 + 6)
+  f32x4 acc[NT];
+#pragma unroll
+  for (int i = 0; i < NT; ++i) acc[i] = f32x4{0.f, 0.f, 0.f, 0.f};
+  float bsum = 0.0f;  // wave 0: sum of dz[., co = j] over the lane's voxels
+  for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    int x0, y0, z0;
+    tile_origin(tile, nx, ny, x0, y0, z0);
+    __syncthreads();  // previous tile's reads are done
+    load_brick<CIN>(lds, in, nx, ny, nz, x0, y0, z0);
+    for (int q = threadIdx.x; q < OX * OY * OZ * COUT; q += NTHR) {
+      const int v = q / COUT, c = q % COUT;
+      const int lx = v % OX, ly = (v / OX) % OY, lz = v / (OX * OY);
+      const int gx = x0 + lx, gy = y0 + ly, gz = z0 + lz;
+      ldz[q] = (gx < nx && gy < ny && gz < nz) ? dz[(((int64_t)gz * ny + gy) * nx + gx) * COUT + c]
+                                               : (uint16_t)0;
+    }
+    __syncthreads();
+    // K = the tile's 256 voxels in 8 chunks of 32
+#pragma unroll 1
+    for (int kc = 0; kc < OX * OY * OZ / 32; ++kc) {
+      u16x8 av;
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const int v = 32 * kc + 8 * g + e;
+        av[e] = (j < COUT) ? ldz[v * COUT + j] : (uint16_t)0;
+      }
+      const bf16x8 A = __builtin_bit_cast(bf16x8, av);
+      if (wave == 0) {
+#pragma unroll
+        for (int e = 0; e < 8; ++e) bsum += from_bf16(av[e]);
+      }
+#pragma unroll
+      for (int i = 0; i < NT; ++i) {
+        const int t = wave + 4 * i;
+        if (t >= 27) continue;
+        u16x8 bv;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          const int v = 32 * kc + 8 * g + e;
+          const int lx = v % OX, ly = (v / OX) % OY, lz = v / (OX * OY);
+          bv[e] = (j < CIN) ? lds[tap_voxel(t, lx, ly, lz) * CIN + j] : (uint16_t)0;
+        }
+        acc[i] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A, __builtin_bit_cast(bf16x8, bv), acc[i],
+                                                        0, 0, 0);
+      }
+    }
+  }
+  if (wave == 0) {  // add the four lane groups' sums of channel j
+    bsum += __shfl_xor(bsum, 16);
+    bsum += __shfl_xor(bsum, 32);
+    if (g == 0) partial_b[(size_t)blockIdx.x * 16 + j] = bsum;
+  }
+  // lane holds D[co = 4 g + e][ci = j]
+#pragma unroll
+  for (int i = 0; i < NT; ++i) {
+    const int t = wave + 4 * i;
+    if (t >= 27) continue;
+    float *p = partial + ((size_t)blockIdx.x * 27 + t) * 256;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) p[(4 * g + e) * 16 + j] = acc[i][e];
+  }
+}
+
+// dW[tap][ci][co] = sum over blocks of partial[block][tap][co][ci], and
+// db[co] = sum over blocks of partial_b[block][co] (fixed order).
+__global__ void k_wgrad_reduce(const float *__restrict__ partial,
+                               const float *__restrict__ partial_b, int nblocks, int cin,
+                               int cout, float *__restrict__ dw, float *__restrict__ db) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int n = 27 * cin * cout;
+  if (i < n) {
+    const int co = i % cout, ci = (i / cout) % cin, t = i / (cout * cin);
+    float s = 0.0f;
+    for (int b = 0; b < nblocks; ++b) s += partial[((size_t)b * 27 + t) * 256 + co * 16 + ci];
+    dw[i] = s;
+  } else if (i < n + cout && db) {
+    const int co = i - n;
+    float s = 0.0f;
+    for (int b = 0; b < nblocks; ++b) s += partial_b[(size_t)b * 16 + co];
+    db[co] = s;
+  }
+}
+
+// Pack FP32 master weights W[tap][ci][co] into the matrix-core layout.
+// flip = 0: A[co][tap * cin + ci] = W[tap][ci][co]            (forward)
+// flip = 1: A[ci][tap * cout + co] = W[26 - tap][ci][co]      (data gradient)
+__global__ void k_pack_weights(const float *__restrict__ w, int cin, int cout, int flip,
+                               uint16_t *__restrict__ apk) {
+  const int rows_in = flip ? cout : cin;  // input channels of the packed conv
+  const int rows_out = flip ? cin : cout;
+  const int K = (27 * rows_in + 31) / 32 * 32;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= 16 * K) return;
+  const int r = i / K, k = i % K;
+  float v = 0.0f;
+  if (r < rows_out && k < 27 * rows_in) {
+    const int t = k / rows_in, c = k % rows_in;
+    v = flip ? w[((26 - t) * cin + r) * cout + c] : w[(t * cin + c) * cout + r];
+  }
+  apk[i] = to_bf16(v);
+}
+
+// Residual of the output against the target: loss partials (FP64, fixed
+// order inside a block) and dy = bf16(2 (y - t) / n).
+__global__ void k_mse(const float *__restrict__ y, const float *__restrict__ t, int64_t n,
+                      uint16_t *__restrict__ dy, double *__restrict__ partial) {
+  __shared__ double red[256];
+  double s = 0.0;
+  const double inv = 2.0 / (double)n;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const double d = (double)y[i] - (double)t[i];  // exact
+    s += d * d;
+    dy[i] = to_bf16((float)(inv * d));
+  }
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
+}
+
+__global__ void k_sum_f64(const double *__restrict__ partial, int n, double scale,
+                          double *__restrict__ out) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    double s = 0.0;
+    for (int i = 0; i < n; ++i) s += partial[i];
+    *out = s * scale;
+  }
+}
+
+// Adam (Kingma & Ba, Alg. 1) on FP32 parameters.
+__global__ void k_adam(float *__restrict__ w, const float *__restrict__ g, float *__restrict__ m,
+                       float *__restrict__ v, int n, float lr, float b1, float b2, float eps,
+                       float c1, float c2) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const float gi = g[i];
+  const float mi = b1 * m[i] + (1.0f - b1) * gi;
+  const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
+  m[i] = mi;
+  v[i] = vi;
+  w[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+}
+
+// Largest |x| per block (for the input scales).
+__global__ void k_absmax(const float *__restrict__ x, int64_t n, float *__restrict__ partial) {
+  __shared__ float red[256];
+  float s = 0.0f;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    s = fmaxf(s, fabsf(x[i]));
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] = fmaxf(red[threadIdx.x], red[threadIdx.x + w]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
+}
+
+// Network input [voxel][2] = bf16(grad / max|grad|), bf16(illum / max|illum|);
+// the maxima are reduced from the per-block partials first.
+__global__ void k_pack_input(const float *__restrict__ grad, const float *__restrict__ illum,
+                             int64_t n, const float *__restrict__ pg, const float *__restrict__ pi,
+                             int np, uint16_t *__restrict__ out) {
+  __shared__ float sg, si;
+  if (threadIdx.x == 0) {
+    float a = 0.0f, b = 0.0f;
+    for (int i = 0; i < np; ++i) {
+      a = fmaxf(a, pg[i]);
+      b = fmaxf(b, pi[i]);
+    }
+    sg = a;
+    si = b;
+  }
+  __syncthreads();
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const float a = sg > 0.0f ? grad[i] / sg : grad[i];
+    const float b = si > 0.0f ? illum[i] / si : illum[i];
+    out[2 * i] = to_bf16(a);
+    out[2 * i + 1] = to_bf16(b);
+  }
+}
+
+int conv_blocks(int nx, int ny, int nz) {
+  return ((nx + OX - 1) / OX) * ((ny + OY - 1) / OY) * ((nz + OZ - 1) / OZ);
+}
+
+}  // namespace
+
+int cnn_conv_blocks(int nx, int ny, int nz) { return conv_blocks(nx, ny, nz); }
+
+hipError_t launch_conv(int cin, int cout, const uint16_t *in, int nx, int ny, int nz,
+                       const uint16_t *apk, const float *bias, int relu, const uint16_t *mask,
+                       uint16_t *out_bf, float *out_f, hipStream_t stream) {
+  const dim3 grid(conv_blocks(nx, ny, nz)), block(NTHR);
+#define WFD_CONV(CI, CO)                                                                      \
+  hipLaunchKernelGGL((k_conv<CI, CO>), grid, block, 0, stream, in, nx, ny, nz, apk, bias, relu, \
+                     mask, out_bf, out_f)
+  if (cin == 16 && cout == 16) WFD_CONV(16, 16);
+  else if (cin == 2 && cout == 16) WFD_CONV(2, 16);
+  else if (cin == 1 && cout == 16) WFD_CONV(1, 16);
+  else if (cin == 16 && cout == 1) WFD_CONV(16, 1);
+  else return hipErrorInvalidValue;
+#undef WFD_CONV
+  return hipGetLastError();
+}
+
+int cnn_wgrad_blocks(int nx, int ny, int nz) {
+  const int tiles = conv_blocks(nx, ny, nz);
+  return tiles < 1024 ? tiles : 1024;
+}
+
+size_t cnn_wgrad_workspace_floats(int nx, int ny, int nz) {
+  return (size_t)cnn_wgrad_blocks(nx, ny, nz) * (27 * 256 + 16);
+}
+
+hipError_t launch_wgrad(int cin, int cout, const uint16_t *in, const uint16_t *dz, int nx, int ny,
+                        int nz, float *work, float *dw, float *db, hipStream_t stream) {
+  const int ntiles = conv_blocks(nx, ny, nz);
+  const int nb = cnn_wgrad_blocks(nx, ny, nz);
+  float *partial = work, *partial_b = work + (size_t)nb * 27 * 256;
+#define WFD_WG(CI, CO)                                                                        \
+  hipLaunchKernelGGL((k_wgrad<CI, CO>), dim3(nb), dim3(NTHR), 0, stream, in, dz, nx, ny, nz, \
+                     ntiles, partial, partial_b)
+  if (cin == 16 && cout == 16) WFD_WG(16, 16);
+  else if (cin == 2 && cout == 16) WFD_WG(2, 16);
+  else if (cin == 16 && cout == 1) WFD_WG(16, 1);
+  else return hipErrorInvalidValue;
+#undef WFD_WG
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const int n = 27 * cin * cout + cout;
+  hipLaunchKernelGGL(k_wgrad_reduce, dim3((n + 255) / 256), dim3(256), 0, stream, partial,
+                     partial_b, nb, cin, cout, dw, db);
+  return hipGetLastError();
+}
+
+hipError_t launch_pack_weights(const float *w, int cin, int cout, int flip, uint16_t *apk,
+                               hipStream_t stream) {
+  const int rows_in = flip ? cout : cin;
+  const int n = 16 * ((27 * rows_in + 31) / 32 * 32);
+  hipLaunchKernelGGL(k_pack_weights, dim3((n + 255) / 256), dim3(256), 0, stream, w, cin, cout,
+                     flip, apk);
+  return hipGetLastError();
+}
+
+hipError_t launch_mse(const float *y, const float *t, int64_t n, uint16_t *dy, double *partial,
+                      int npart, double *loss, hipStream_t stream) {
+  hipLaunchKernelGGL(k_mse, dim3(npart), dim3(256), 0, stream, y, t, n, dy, partial);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_sum_f64, dim3(1), dim3(64), 0, stream, partial, npart, 1.0 / (double)n,
+                     loss);
+  return hipGetLastError();
+}
+
+hipError_t launch_adam(float *w, const float *g, float *m, float *v, int n, float lr, float b1,
+                       float b2, float eps, int step, hipStream_t stream) {
+  const float c1 = 1.0f - powf(b1, (float)step), c2 = 1.0f - powf(b2, (float)step);
+  hipLaunchKernelGGL(k_adam, dim3((n + 255) / 256), dim3(256), 0, stream, w, g, m, v, n, lr, b1,
+                     b2, eps, c1, c2);
+  return hipGetLastError();
+}
+
+hipError_t launch_pack_input(const float *grad, const float *illum, int64_t n, float *partial,
+                             int npart, uint16_t *out, hipStream_t stream) {
+  hipLaunchKernelGGL(k_absmax, dim3(npart), dim3(256), 0, stream, grad, n, partial);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_absmax, dim3(npart), dim3(256), 0, stream, illum, n, partial + npart);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_pack_input, dim3(npart), dim3(256), 0, stream, grad, illum, n, partial,
+                     partial + npart, npart, out);
+  return hipGetLastError();
+}
+
+}  // namespace wfd

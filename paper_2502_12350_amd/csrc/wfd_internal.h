@@ -124,4 +124,24 @@ hipError_t launch_grad_fold(const float *g, const float *k, int pitch, int pny, 
 
 hipError_t launch_fill_zero(float *p, int64_t n, hipStream_t stream);
 
+// ---- CNN preconditioner kernels (wfd_cnn.hip) ----
+// BF16 values travel as uint16_t bit patterns.
+int cnn_conv_blocks(int nx, int ny, int nz);
+int cnn_wgrad_blocks(int nx, int ny, int nz);
+size_t cnn_wgrad_workspace_floats(int nx, int ny, int nz);
+constexpr int kCnnReduceBlocks = 512;  // partials of the loss and input-scale reductions
+hipError_t launch_conv(int cin, int cout, const uint16_t *in, int nx, int ny, int nz,
+                       const uint16_t *apk, const float *bias, int relu, const uint16_t *mask,
+                       uint16_t *out_bf, float *out_f, hipStream_t stream);
+hipError_t launch_wgrad(int cin, int cout, const uint16_t *in, const uint16_t *dz, int nx, int ny,
+                        int nz, float *work, float *dw, float *db, hipStream_t stream);
+hipError_t launch_pack_weights(const float *w, int cin, int cout, int flip, uint16_t *apk,
+                               hipStream_t stream);
+hipError_t launch_mse(const float *y, const float *t, int64_t n, uint16_t *dy, double *partial,
+                      int npart, double *loss, hipStream_t stream);
+hipError_t launch_adam(float *w, const float *g, float *m, float *v, int n, float lr, float b1,
+                       float b2, float eps, int step, hipStream_t stream);
+hipError_t launch_pack_input(const float *grad, const float *illum, int64_t n, float *partial,
+                             int npart, uint16_t *out, hipStream_t stream);
+
 }  // namespace wfd

@@ -1,0 +1,188 @@
+"""Learned gradient preconditioner: a 4-layer 3-D CNN on the library's
+BF16 matrix-core kernels (include/wfd.h, wfd_cnn_*).
+
+The paper preconditions the FWI gradient with a fixed smoothing filter (its
+GradientPreconditioning option).  Here a small network maps the raw gradient
+and the source illumination (each scaled by its maximum) to a model-update
+direction:
+
+    conv 3x3x3  2 -> 16, ReLU;  16 -> 16, ReLU;  16 -> 16, ReLU;  16 -> 1
+
+BF16 weights and activations, FP32 accumulation, FP32 master weights trained
+with Adam on the mean squared error against the scaled true perturbation.
+Every convolution, gradient, loss and optimizer step runs in the library's
+kernels; this module holds the buffers (torch tensors) and sequences calls.
+The plain illumination-compensated gradient g / (I + eps max I) stays the
+fallback: `direction` returns it whenever the network's direction is not a
+descent direction.
+"""
+
+from __future__ import annotations
+
+import ctypes as C
+from typing import List, Optional, Sequence, Tuple
+
+import numpy as np
+
+from . import _lib
+from ._lib import check
+
+LAYERS: Tuple[Tuple[int, int], ...] = ((2, 16), (16, 16), (16, 16), (16, 1))
+
+
+def _p(t) -> Optional[int]:
+    return None if t is None else t.data_ptr()
+
+
+class Preconditioner:
+    """Network parameters and training state on one GPU (torch's current stream)."""
+
+    def __init__(self, device: int = 0, seed: int = 0, params=None):
+        import torch
+        self.torch = torch
+        self.device = torch.device("cuda", device)
+        self.L = _lib.lib()
+        rng = np.random.default_rng(seed)
+        self.w: List = []
+        self.b: List = []
+        for li, (ci, co) in enumerate(LAYERS):
+            if params is not None:
+                w = np.asarray(params[f"w{li}"], dtype=np.float32).reshape(27, ci, co)
+                b = np.asarray(params[f"b{li}"], dtype=np.float32).reshape(co)
+            else:  # He-uniform
+                lim = np.sqrt(6.0 / (27 * ci))
+                w = rng.uniform(-lim, lim, size=(27, ci, co)).astype(np.float32)
+                b = np.zeros(co, dtype=np.float32)
+            self.w.append(torch.from_numpy(np.ascontiguousarray(w)).to(self.device))
+            self.b.append(torch.from_numpy(b).to(self.device))
+        self.packed = []
+        for ci, co in LAYERS:
+            n = [C.c_int64(), C.c_int64()]
+            for f in (0, 1):
+                check(self.L.wfd_cnn_packed_elems(ci, co, f, C.byref(n[f])))
+            self.packed.append(tuple(torch.empty(int(n[f].value), dtype=torch.bfloat16,
+                                                 device=self.device) for f in (0, 1)))
+        self.dw = [torch.zeros_like(w) for w in self.w]
+        self.db = [torch.zeros_like(b) for b in self.b]
+        self.m = [torch.zeros_like(t) for t in self.w + self.b]
+        self.v = [torch.zeros_like(t) for t in self.w + self.b]
+        self.step_count = 0
+        self._reduce = torch.empty(_lib.CNN_REDUCE_BYTES, dtype=torch.uint8, device=self.device)
+        self._acts = None
+        self.pack()
+
+    # -- plumbing -----------------------------------------------------------------
+    def _stream(self):
+        return C.c_void_p(self.torch.cuda.current_stream(self.device).cuda_stream)
+
+    def pack(self):
+        """Re-pack the BF16 matrix-core weights from the FP32 master weights."""
+        s = self._stream()
+        for li, (ci, co) in enumerate(LAYERS):
+            for f in (0, 1):
+                check(self.L.wfd_cnn_pack_weights(_p(self.w[li]), ci, co, f,
+                                                  _p(self.packed[li][f]), s))
+
+    def conv(self, x, li: int, *, relu: bool, out_f32: bool = False, flip: bool = False,
+             mask=None, bias: bool = True):
+        """One convolution of layer li (or its data gradient with flip=True)."""
+        torch = self.torch
+        nz, ny, nx = x.shape[:3]
+        ci, co = LAYERS[li]
+        if flip:
+            ci, co = co, ci
+        assert x.shape[3] == ci and x.dtype == torch.bfloat16 and x.is_contiguous()
+        ob = None if out_f32 else torch.empty((nz, ny, nx, co), dtype=torch.bfloat16,
+                                              device=self.device)
+        of = torch.empty((nz, ny, nx, co), dtype=torch.float32, device=self.device) \
+            if out_f32 else None
+        check(self.L.wfd_cnn_conv(_p(x), nx, ny, nz, ci, co, _p(self.packed[li][int(flip)]),
+                                  _p(self.b[li]) if (bias and not flip) else None, int(relu),
+                                  _p(mask), _p(ob), _p(of), self._stream()))
+        return of if out_f32 else ob
+
+    # -- network ------------------------------------------------------------------
+    def pack_input(self, grad, illum):
+        """[nz][ny][nx][2] BF16 network input from FP32 gradient and illumination."""
+        torch = self.torch
+        out = torch.empty(tuple(grad.shape) + (2,), dtype=torch.bfloat16, device=self.device)
+        check(self.L.wfd_cnn_pack_input(_p(grad.contiguous()), _p(illum.contiguous()),
+                                        grad.numel(), _p(out), _p(self._reduce),
+                                        self._reduce.numel(), self._stream()))
+        return out
+
+    def forward(self, x, keep: bool = False):
+        """Network output [nz][ny][nx] FP32 for a BF16 input [nz][ny][nx][2]."""
+        acts = [x]
+        for li in range(3):
+            acts.append(self.conv(acts[-1], li, relu=True))
+        y = self.conv(acts[-1], 3, relu=False, out_f32=True)[..., 0]
+        self._acts = acts if keep else None
+        return y
+
+    def backward(self, y, target):
+        """Gradients of mean((y - target)^2) into self.dw / self.db; returns the
+        loss (device FP64 scalar).  Needs forward(..., keep=True) first."""
+        torch = self.torch
+        acts = self._acts
+        assert acts is not None, "forward(keep=True) first"
+        nz, ny, nx = y.shape
+        loss = torch.zeros((), dtype=torch.float64, device=self.device)
+        dz = torch.empty((nz, ny, nx, 1), dtype=torch.bfloat16, device=self.device)
+        check(self.L.wfd_cnn_mse(_p(y), _p(target.contiguous()), y.numel(), _p(dz), _p(loss),
+                                 _p(self._reduce), self._reduce.numel(), self._stream()))
+        nb = C.c_size_t()
+        check(self.L.wfd_cnn_wgrad_workspace_bytes(nx, ny, nz, C.byref(nb)))
+        work = torch.empty(nb.value, dtype=torch.uint8, device=self.device)
+        for li in range(3, -1, -1):
+            ci, co = LAYERS[li]
+            check(self.L.wfd_cnn_wgrad(_p(acts[li]), _p(dz), nx, ny, nz, ci, co, _p(self.dw[li]),
+                                       _p(self.db[li]), _p(work), nb.value, self._stream()))
+            if li > 0:  # gradient of the layer input, masked by its ReLU
+                dz = self.conv(dz, li, relu=False, flip=True, mask=acts[li], bias=False)
+        return loss
+
+    def adam(self, lr: float = 1e-3, beta1: float = 0.9, beta2: float = 0.999, eps: float = 1e-8):
+        """One Adam step on all weights and biases, then re-pack."""
+        self.step_count += 1
+        s = self._stream()
+        for p, g, m, v in zip(self.w + self.b, self.dw + self.db, self.m, self.v):
+            check(self.L.wfd_cnn_adam(_p(p), _p(g), _p(m), _p(v), p.numel(), lr, beta1, beta2,
+                                      eps, self.step_count, s))
+        self.pack()
+
+    def train_step(self, x, target, lr: float = 1e-3):
+        y = self.forward(x, keep=True)
+        loss = self.backward(y, target)
+        self.adam(lr)
+        self._acts = None
+        return loss
+
+    # -- use in FWI ----------------------------------------------------------------
+    def direction(self, grad, illum, eps_illum: float = 1e-3):
+        """Descent direction for the gradient `grad` [nz][ny][nx]: the network
+        output (it predicts the scaled model perturbation), or the
+        illumination-compensated fallback when that does not descend.
+        Returns (direction, used_net)."""
+        torch = self.torch
+        d = self.forward(self.pack_input(grad, illum))
+        if float(torch.sum(d.double() * grad.double())) < 0.0:
+            return d, True
+        return -grad / (illum + eps_illum * illum.max()), False
+
+    # -- persistence -----------------------------------------------------------------
+    def state(self) -> dict:
+        out = {}
+        for li in range(len(LAYERS)):
+            out[f"w{li}"] = self.w[li].cpu().numpy()
+            out[f"b{li}"] = self.b[li].cpu().numpy()
+        return out
+
+    def save(self, path: str):
+        np.savez(path, **self.state())
+
+    @classmethod
+    def load(cls, path: str, device: int = 0):
+        with np.load(path, allow_pickle=False) as z:
+            params = {k: z[k] for k in z.files}
+        return cls(device, params=params)

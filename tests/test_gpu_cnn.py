@@ -1,0 +1,211 @@
+"""CNN preconditioner kernels on the GPU against the FP64 oracle (oracle/cnn.py).
+
+Each kernel is fed the same BF16-valued inputs as the oracle.  Products of
+BF16 values are exact in FP32, so the FP32 results differ from the oracle's
+FP64 sums only by summation order: rel-L2 <= 1e-5 (at most 432 terms).
+Where a result is stored as BF16, the GPU's FP32 sum and the oracle's FP64 sum
+can fall on either side of a rounding boundary, so BF16 outputs must match the
+rounded oracle except for at most 1 in 1000 values, each within one BF16 step.
+The volume 70 x 7 x 5 spans two 64-wide x tiles with a ragged tail, and
+ragged y and z tiles.
+"""
+
+import numpy as np
+import pytest
+
+from oracle import cnn
+from gpu_util import gpu_or_skip, rel_l2, say
+
+pytestmark = pytest.mark.gpu
+
+NZ, NY, NX = 5, 7, 70
+TOL = 1e-5
+
+
+def _bf(torch, a):
+    """Oracle BF16-valued array -> device bfloat16 tensor (exact)."""
+    return torch.from_numpy(np.asarray(a, dtype=np.float32)).to(torch.bfloat16).cuda()
+
+
+def _np(t):
+    return t.float().cpu().numpy().astype(np.float64)
+
+
+def _bf16_close(got, ref):
+    """BF16 outputs: equal to the rounded oracle up to rare one-step flips."""
+    ref_q = cnn.bf16(ref)
+    diff = got != ref_q
+    frac = float(np.mean(diff))
+    # one BF16 step at the value (values within 1e-5 of the largest count as
+    # that size: near zero the FP32 and FP64 sums can differ in sign)
+    step = np.maximum(np.abs(ref_q), 1e-5 * np.max(np.abs(ref_q))) * 2.0 ** -7 + 1e-38
+    worst = float(np.max(np.abs(got - ref_q)[diff] / step[diff])) if diff.any() else 0.0
+    return frac, worst
+
+
+def _net(torch, seed=0):
+    from paper_2502_12350_amd.precond import Preconditioner
+    P = Preconditioner(0, seed=seed)
+    rng = np.random.default_rng(seed + 100)
+    for b in P.b:  # non-zero biases exercise the bias path
+        b.copy_(torch.from_numpy(rng.standard_normal(b.numel()).astype(np.float32) * 0.1))
+    Ws = [cnn.bf16(w.cpu().numpy().astype(np.float64).reshape(3, 3, 3, *w.shape[1:]))
+          for w in P.w]
+    bs = [b.cpu().numpy().astype(np.float64) for b in P.b]
+    return P, Ws, bs
+
+
+@pytest.mark.parametrize("li", [0, 1, 3])
+def test_conv_forward_matches_oracle(li):
+    torch = gpu_or_skip()
+    P, Ws, bs = _net(torch, seed=li)
+    ci, co = [(2, 16), (16, 16), (16, 16), (16, 1)][li]
+    say(f"[cnn conv] layer {li}: {ci} -> {co} on {NX}x{NY}x{NZ}")
+    rng = np.random.default_rng(20 + li)
+    x = cnn.bf16(rng.standard_normal((NZ, NY, NX, ci)))
+    xd = _bf(torch, x)
+    ref = cnn.conv3d(x, Ws[li], bs[li])
+    got_f = _np(P.conv(xd, li, relu=False, out_f32=True))
+    e = rel_l2(got_f, ref)
+    say(f"  FP32 output rel-L2 {e:.2e}")
+    assert e <= TOL
+    if co == 16:
+        got_b = _np(P.conv(xd, li, relu=True))
+        frac, worst = _bf16_close(got_b, np.maximum(ref, 0.0))
+        say(f"  BF16 relu output: {frac:.1e} of values one step off (worst {worst:.2f} steps)")
+        assert frac <= 1e-3 and worst <= 1.0
+
+
+@pytest.mark.parametrize("li", [1, 2, 3])
+def test_data_gradient_matches_oracle(li):
+    torch = gpu_or_skip()
+    P, Ws, _ = _net(torch, seed=10 + li)
+    ci, co = [(2, 16), (16, 16), (16, 16), (16, 1)][li]
+    say(f"[cnn dgrad] layer {li}: {co} -> {ci}")
+    rng = np.random.default_rng(30 + li)
+    dz = cnn.bf16(rng.standard_normal((NZ, NY, NX, co)))
+    mask = cnn.bf16(np.maximum(rng.standard_normal((NZ, NY, NX, ci)), 0.0))
+    ref = cnn.conv3d_dgrad(dz, Ws[li])
+    got = _np(P.conv(_bf(torch, dz), li, relu=False, flip=True, bias=False, out_f32=True))
+    e = rel_l2(got, ref)
+    say(f"  rel-L2 {e:.2e}")
+    assert e <= TOL
+    got_m = _np(P.conv(_bf(torch, dz), li, relu=False, flip=True, bias=False,
+                       mask=_bf(torch, mask)))
+    frac, worst = _bf16_close(got_m, ref * (mask > 0))
+    assert frac <= 1e-3 and worst <= 1.0
+
+
+@pytest.mark.parametrize("li", [0, 1, 3])
+def test_weight_gradient_matches_oracle(li):
+    torch = gpu_or_skip()
+    import ctypes as C
+    from paper_2502_12350_amd import _lib
+    ci, co = [(2, 16), (16, 16), (16, 16), (16, 1)][li]
+    say(f"[cnn wgrad] layer {li}: {ci} -> {co}")
+    rng = np.random.default_rng(40 + li)
+    x = cnn.bf16(rng.standard_normal((NZ, NY, NX, ci)))
+    dz = cnn.bf16(rng.standard_normal((NZ, NY, NX, co)))
+    L = _lib.lib()
+    nb = C.c_size_t()
+    _lib.check(L.wfd_cnn_wgrad_workspace_bytes(NX, NY, NZ, C.byref(nb)))
+    work = torch.empty(nb.value, dtype=torch.uint8, device="cuda")
+    dw = torch.full((27, ci, co), float("nan"), device="cuda")
+    db = torch.full((co,), float("nan"), device="cuda")
+    xd, dzd = _bf(torch, x), _bf(torch, dz)
+    _lib.check(L.wfd_cnn_wgrad(xd.data_ptr(), dzd.data_ptr(), NX, NY, NZ, ci, co, dw.data_ptr(),
+                               db.data_ptr(), work.data_ptr(), nb.value, None))
+    torch.cuda.synchronize()
+    ref = cnn.conv3d_wgrad(x, dz).reshape(27, ci, co)
+    e = rel_l2(_np(dw), ref)
+    eb = rel_l2(_np(db), dz.reshape(-1, co).sum(axis=0))
+    say(f"  dW rel-L2 {e:.2e}, db rel-L2 {eb:.2e}")
+    assert e <= TOL and eb <= TOL
+
+
+def test_mse_adam_and_input_packing_match_oracle():
+    torch = gpu_or_skip()
+    import ctypes as C
+    from paper_2502_12350_amd import _lib
+    L = _lib.lib()
+    rng = np.random.default_rng(50)
+    n = NZ * NY * NX
+    y = rng.standard_normal(n).astype(np.float32)
+    t = rng.standard_normal(n).astype(np.float32)
+    work = torch.empty(_lib.CNN_REDUCE_BYTES, dtype=torch.uint8, device="cuda")
+    yd, td = torch.from_numpy(y).cuda(), torch.from_numpy(t).cuda()
+    dy = torch.empty(n, dtype=torch.bfloat16, device="cuda")
+    loss = torch.zeros((), dtype=torch.float64, device="cuda")
+    _lib.check(L.wfd_cnn_mse(yd.data_ptr(), td.data_ptr(), n, dy.data_ptr(), loss.data_ptr(),
+                             work.data_ptr(), work.numel(), None))
+    torch.cuda.synchronize()
+    ref = cnn.loss(y, t)
+    assert abs(float(loss.item()) - ref) <= 1e-12 * ref
+    assert np.array_equal(_np(dy), cnn.bf16(2.0 * (y.astype(np.float64) - t) / n))
+    # Adam: three steps against the oracle's closed form
+    w = rng.standard_normal(1000).astype(np.float32)
+    wd = torch.from_numpy(w).cuda()
+    md, vd = torch.zeros_like(wd), torch.zeros_like(wd)
+    wo, mo, vo = w.astype(np.float64), np.zeros(1000), np.zeros(1000)
+    for step in (1, 2, 3):
+        g = rng.standard_normal(1000).astype(np.float32)
+        _lib.check(L.wfd_cnn_adam(wd.data_ptr(), torch.from_numpy(g).cuda().data_ptr(),
+                                  md.data_ptr(), vd.data_ptr(), 1000, 1e-2, 0.9, 0.999, 1e-8,
+                                  step, None))
+        torch.cuda.synchronize()
+        wo, mo, vo = cnn.adam_step(wo, g.astype(np.float64), mo, vo, step, 1e-2)
+    assert rel_l2(_np(wd), wo) <= 1e-6
+    # network input
+    g = (rng.standard_normal((NZ, NY, NX)) * 1e-12).astype(np.float32)
+    il = (np.abs(rng.standard_normal((NZ, NY, NX))) * 1e4).astype(np.float32)
+    from paper_2502_12350_amd.precond import Preconditioner
+    P = Preconditioner(0)
+    got = _np(P.pack_input(torch.from_numpy(g).cuda(), torch.from_numpy(il).cuda()))
+    frac, worst = _bf16_close(got, np.stack([g / np.abs(g).max(), il / il.max()], axis=-1))
+    assert frac <= 1e-3 and worst <= 1.0
+
+
+def test_network_forward_backward_matches_oracle():
+    """The whole network: forward output and every weight/bias gradient against
+    the oracle's quantized chain rule (BF16 rounding flips of stored
+    activations propagate, so the bound is 1e-2)."""
+    torch = gpu_or_skip()
+    P, Ws, bs = _net(torch, seed=3)
+    say("[cnn network] forward + backward")
+    rng = np.random.default_rng(60)
+    a0 = cnn.bf16(rng.standard_normal((NZ, NY, NX, 2)))
+    t = rng.standard_normal((NZ, NY, NX, 1))
+    acts, y_ref = cnn.forward(a0, Ws, bs)
+    dWs, dbs = cnn.backward(acts, y_ref, t, Ws)
+    y = P.forward(_bf(torch, a0), keep=True)
+    loss = P.backward(y, torch.from_numpy(t[..., 0].astype(np.float32)).cuda())
+    torch.cuda.synchronize()
+    ey = rel_l2(_np(y), y_ref[..., 0])
+    say(f"  output rel-L2 {ey:.2e}; loss {float(loss.item()):.6e} vs {cnn.loss(y_ref, t):.6e}")
+    assert ey <= 1e-2
+    for li in range(4):
+        ew = rel_l2(_np(P.dw[li]), dWs[li].reshape(P.dw[li].shape))
+        eb = rel_l2(_np(P.db[li]), dbs[li])
+        say(f"  layer {li}: dW rel-L2 {ew:.2e}, db rel-L2 {eb:.2e}")
+        assert ew <= 1e-2 and eb <= 1e-2
+
+
+def test_training_lowers_the_loss_and_is_deterministic():
+    torch = gpu_or_skip()
+    from paper_2502_12350_amd.precond import Preconditioner
+    say("[cnn training] 60 Adam steps on a fixed pair")
+    rng = np.random.default_rng(70)
+    shape = (12, 20, 40)
+    g = rng.standard_normal(shape).astype(np.float32)
+    il = np.abs(rng.standard_normal(shape)).astype(np.float32)
+    tgt = torch.from_numpy(-0.5 * g).cuda()
+    runs = []
+    for _ in range(2):
+        P = Preconditioner(0, seed=5)
+        x = P.pack_input(torch.from_numpy(g).cuda(), torch.from_numpy(il).cuda())
+        losses = [float(P.train_step(x, tgt, lr=3e-3).item()) for _ in range(60)]
+        runs.append((losses, P.w[0].clone()))
+    (l1, w1), (l2, w2) = runs
+    say(f"  loss {l1[0]:.4e} -> {l1[-1]:.4e}")
+    assert l1[-1] < 0.2 * l1[0]
+    assert l1 == l2 and torch.equal(w1, w2)

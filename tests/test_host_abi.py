@@ -140,3 +140,23 @@ def test_checkpoint_plan_counts_for_the_gradient_workload():
     assert n == 3327
     _, n_full = api.checkpoint_plan(1200, 1200)
     assert n_full == 1200
+
+
+def test_cnn_packed_sizes_and_workspace():
+    import ctypes as C
+    from paper_2502_12350_amd import _lib
+    L = _lib.lib()
+    n = C.c_int64()
+    for (ci, co, flip), k in {(2, 16, 0): 64, (16, 16, 0): 448, (16, 1, 0): 448,
+                              (16, 1, 1): 32, (2, 16, 1): 448, (16, 16, 1): 448}.items():
+        assert L.wfd_cnn_packed_elems(ci, co, flip, C.byref(n)) == 0
+        assert n.value == 16 * k
+    assert L.wfd_cnn_packed_elems(3, 16, 0, C.byref(n)) == -1       # no such layer
+    assert L.wfd_cnn_packed_elems(16, 16, 2, C.byref(n)) == -1
+    b = C.c_size_t()
+    assert L.wfd_cnn_wgrad_workspace_bytes(70, 7, 5, C.byref(b)) == 0
+    tiles = 2 * 4 * 3                                                # 64 x 2 x 2 tiles
+    assert b.value == tiles * (27 * 256 + 16) * 4
+    assert L.wfd_cnn_wgrad_workspace_bytes(128, 128, 128, C.byref(b)) == 0
+    assert b.value == 1024 * (27 * 256 + 16) * 4                     # capped at 1024 blocks
+    assert L.wfd_cnn_conv(None, 8, 8, 8, 3, 16, None, None, 0, None, None, None, None) == -1
