@@ -257,6 +257,129 @@ def batch_bench(steps: int, warmup: int, autotune: bool):
     print(json.dumps(out), flush=True)
 
 
+def cnn_kernel_bench(n: int = 256, reps: int = 20):
+    """Matrix-core throughput of the preconditioner's kernels on an n^3 volume:
+    forward convolution of every layer, data and weight gradients, and one
+    whole training step; useful flops = 2 * 27 * cin * cout per voxel."""
+    import numpy as np
+    import torch
+    from paper_2502_12350_amd.precond import LAYERS, Preconditioner
+
+    P = Preconditioner(0, seed=1)
+    rng = np.random.default_rng(0)
+    shape = (n, n, n)
+    g = torch.from_numpy(rng.standard_normal(shape).astype(np.float32)).cuda()
+    il = torch.from_numpy(np.abs(rng.standard_normal(shape)).astype(np.float32)).cuda()
+    x = P.pack_input(g, il)
+    vox = n ** 3
+    gen = torch.Generator(device="cuda").manual_seed(0)
+    a16 = torch.randn(shape + (16,), generator=gen, device="cuda").to(torch.bfloat16)
+
+    def timed(fn):
+        for _ in range(2):
+            fn()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps * 1e-3
+
+    out = {}
+    for li, (ci, co) in enumerate(LAYERS):
+        inp = x if ci == 2 else a16
+        t = timed(lambda: P.conv(inp, li, relu=li < 3, out_f32=li == 3))
+        fl = 2.0 * 27 * ci * co * vox
+        out[f"conv_l{li}_{ci}x{co}"] = {"us": round(t * 1e6, 1), "TFLOPs": round(fl / t / 1e12, 1)}
+    t = timed(lambda: P.conv(a16, 1, relu=False, flip=True, bias=False, mask=a16))
+    out["dgrad_16x16"] = {"us": round(t * 1e6, 1),
+                          "TFLOPs": round(2.0 * 27 * 256 * vox / t / 1e12, 1)}
+    tgt = torch.zeros(shape, device="cuda")
+    y = P.forward(x, keep=True)
+    t = timed(lambda: P.backward(y, tgt))
+    fl_fwd = sum(2.0 * 27 * ci * co * vox for ci, co in LAYERS)
+    fl_bwd = fl_fwd + sum(2.0 * 27 * ci * co * vox for ci, co in LAYERS[1:])
+    out["backward_all_layers"] = {"us": round(t * 1e6, 1), "TFLOPs": round(fl_bwd / t / 1e12, 1)}
+    t = timed(lambda: P.forward(x))
+    out["forward_all_layers"] = {"us": round(t * 1e6, 1), "TFLOPs": round(fl_fwd / t / 1e12, 1)}
+    peak = 2500.0
+    l1 = out["conv_l1_16x16"]
+    res = {"metric": "CNN preconditioner matrix-core throughput", "unit": "TFLOP/s",
+           "value": l1["TFLOPs"], "higher_is_better": True, "n_gpus": 1, "dtype": "bf16",
+           "data": "synthetic", "config": {"workload": f"3-D CNN 2-16-16-16-1, 3x3x3, {n}^3 volume"},
+           "roofline": {"bound": "mfma", "achieved": l1["TFLOPs"], "peak": peak,
+                        "unit": "TFLOP/s", "frac": round(l1["TFLOPs"] / peak, 4),
+                        "traffic": None, "kernel": "k_conv<16, 16>"},
+           "kernels": out}
+    print(json.dumps(res), flush=True)
+
+
+def precond_fwi_bench(n_iter: int):
+    """FWI with the learned preconditioner against the plain method: the
+    256^3 recipe of the training models (seed 5999, never trained on), 20-cell
+    sponge, 1600 steps, 8 shots, 4096 receivers, constant density; start =
+    layered background, truth = background + 1-4 blobs.  Both runs use
+    steepest descent with the same quadratic line search; 'sd' steps along the
+    illumination-compensated gradient, 'cnn' along the network's direction
+    (falling back to the former when it does not descend)."""
+    import numpy as np
+    import torch
+    import seisgen
+    from paper_2502_12350_amd import GridSpec, Propagator
+    from paper_2502_12350_amd.fwi import Shots, fwi
+    from paper_2502_12350_amd.precond import Preconditioner, TRAINED
+
+    w = seisgen.workload("c5_eval")
+    g = GridSpec(**w.grid_kwargs())
+    dev = torch.device("cuda", 0)
+    P = Propagator(0)
+    P.set_model(g, torch.from_numpy(w.extra["v_true"]).to(dev))
+    wav = torch.from_numpy(w.wavelet).to(dev)
+    dobs = [P.forward(wav, s, w.receivers).clone() for s in w.sources]
+    torch.cuda.synchronize()
+    P.release_workspace()
+    shots = Shots(wav, np.asarray(w.sources), [w.receivers] * len(w.sources), dobs)
+    v0 = torch.from_numpy(w.vel).to(dev)
+    vt = w.extra["v_true"]
+    net = Preconditioner.load(TRAINED)
+    runs = {}
+    for method in ("sd", "cnn"):
+        print(f"[bench-precond] {method}", file=sys.stderr, flush=True)
+        v, tr = fwi(P, g, v0, None, shots, n_iter=n_iter, method=method, bounds=(1500.0, 4500.0),
+                    zero_top_planes=10, precond=net,
+                    progress=lambda it, J, t: print(f"[bench-precond] {method} iteration {it + 1}: "
+                                                    f"misfit {J:.4e} at {t:.1f} GPU-s",
+                                                    file=sys.stderr, flush=True))
+        runs[method] = {
+            "misfit": [float(x) for x in tr.misfit],
+            "gpu_seconds": [round(t, 3) for t in tr.gpu_seconds],
+            "misfit_cut_per_gpu_s": tr.misfit_cut_per_gpu_s(),
+            "gradients": tr.n_gradients, "forward_misfits": tr.n_misfits,
+            "network_steps": tr.n_network,
+            "model_error_rel": float(np.linalg.norm(v.cpu().numpy() - vt) /
+                                     np.linalg.norm(w.vel - vt)),
+            "_trace": tr}
+    sd, cnn = runs["sd"], runs["cnn"]
+    target = sd["misfit"][-1]  # equal final misfit: the plain method's
+    t_sd = sd["_trace"].time_to_reach(target / sd["misfit"][0])
+    t_cnn = cnn["_trace"].time_to_reach(target / cnn["misfit"][0])
+    for r in runs.values():
+        r.pop("_trace")
+    out = {"metric": "FWI misfit cut per GPU-s: learned preconditioner vs illumination-compensated "
+                     "gradient", "unit": "x", "higher_is_better": True, "n_gpus": 1,
+           "dtype": "f32 (stencil), bf16 (network)", "data": "synthetic",
+           "value": round(t_sd / t_cnn, 3) if t_cnn else None,
+           "config": {"workload": "FWI, 256^3 layered model + 1-4 blobs (seed 5999) + 20-cell "
+                                  "sponge, 1600 steps, 8 shots, 4096 receivers",
+                      "iterations": n_iter, "zero_top_planes": 10,
+                      "network": "2-16-16-16-1 3x3x3 BF16, trained on 512 solver pairs (128^3)"},
+           "gpu_s_to_plain_final_misfit": {"sd": t_sd, "cnn": t_cnn},
+           "methods": runs}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -269,6 +392,10 @@ def main():
     ap.add_argument("--copy-probe", action="store_true")
     ap.add_argument("--fwi", type=int, default=0, metavar="ITERS",
                     help="run the FWI benchmark with this many iterations per method instead")
+    ap.add_argument("--precond-fwi", type=int, default=0, metavar="ITERS",
+                    help="run FWI with the learned preconditioner against the plain method")
+    ap.add_argument("--cnn", type=int, default=0, metavar="N",
+                    help="time the CNN preconditioner kernels on an N^3 volume instead")
     ap.add_argument("--batch", action="store_true",
                     help="run the batched multi-shot forward benchmark instead")
     ap.add_argument("--autotune", action="store_true",
@@ -290,6 +417,12 @@ def main():
         return
     if args.batch:
         batch_bench(max(args.steps, 1), args.warmup, args.autotune)
+        return
+    if args.cnn:
+        cnn_kernel_bench(args.cnn)
+        return
+    if args.precond_fwi:
+        precond_fwi_bench(args.precond_fwi)
         return
 
     import numpy as np

@@ -327,9 +327,11 @@ wfd_status wfd_cnn_adam(float *w_dev, const float *g_dev, float *m_dev, float *v
                         float lr, float beta1, float beta2, float eps, int32_t step,
                         void *stream);
 
-/* Network input [n][2] = (bf16(grad / max|grad|), bf16(illum / max|illum|)),
- * each channel left unscaled if its maximum is 0. */
-wfd_status wfd_cnn_pack_input(const float *grad_dev, const float *illum_dev, int64_t n,
+/* Network input [n][2]: c = grad / (illum + eps max|illum|) (the plain
+ * illumination-compensated gradient) scaled by max|c|, and illum scaled by
+ * max|illum|, both rounded to BF16; a channel whose maximum is 0 is left
+ * unscaled (with max|illum| = 0, c = grad).  eps > 0. */
+wfd_status wfd_cnn_pack_input(const float *grad_dev, const float *illum_dev, int64_t n, float eps,
                               uint16_t *out_dev, void *work_dev, size_t work_bytes, void *stream);
 
 /* ---- measurement ---------------------------------------------------------- */

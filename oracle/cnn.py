@@ -6,9 +6,11 @@ code with the GPU path.
 
 The paper smooths the FWI gradient with a fixed filter (its
 GradientPreconditioning option: Bessel or Laplace).  The learned replacement
-is a 4-layer 3-D convolutional network mapping two input channels (the raw
-gradient and the source illumination, each scaled by its maximum magnitude)
-to one output channel, the model update direction:
+is a 4-layer 3-D convolutional network mapping two input channels to one
+output channel, the model update direction.  The inputs are the gradient
+divided by the regularised source illumination, g / (I + eps max I) (the
+plain preconditioned gradient the network has to improve on), and the
+illumination I itself, each scaled by its largest magnitude:
 
     z1 = C(a0; W1, b1)   a1 = q(relu(z1))        2 -> 16 channels
     z2 = C(a1; W2, b2)   a2 = q(relu(z2))       16 -> 16
@@ -116,13 +118,16 @@ def init_params(seed: int):
     return Ws, bs
 
 
-def pack_input(grad, illum) -> np.ndarray:
-    """Network input [z][y][x][2]: grad / max|grad| and illum / max illum, in BF16."""
+def pack_input(grad, illum, eps: float = 1e-3) -> np.ndarray:
+    """Network input [z][y][x][2] in BF16: c = grad / (illum + eps max|illum|)
+    scaled by max|c|, and illum scaled by max|illum| (a channel whose maximum
+    is 0 is left unscaled)."""
     g = np.asarray(grad, dtype=np.float64)
     i = np.asarray(illum, dtype=np.float64)
-    gs = np.max(np.abs(g))
-    is_ = np.max(np.abs(i))
-    a = np.stack([g / gs if gs > 0 else g, i / is_ if is_ > 0 else i], axis=-1)
+    im = np.max(np.abs(i))
+    c = g / (i + eps * im) if im > 0 else g
+    cm = np.max(np.abs(c))
+    a = np.stack([c / cm if cm > 0 else c, i / im if im > 0 else i], axis=-1)
     return bf16(a)
 
 

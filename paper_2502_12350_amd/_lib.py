@@ -81,7 +81,7 @@ _SIGS = {
     "wfd_cnn_mse": (C.c_int, [_P, _P, C.c_int64, _P, _P, _P, C.c_size_t, _P]),
     "wfd_cnn_adam": (C.c_int, [_P, _P, _P, _P, C.c_int32, C.c_float, C.c_float, C.c_float,
                                C.c_float, C.c_int32, _P]),
-    "wfd_cnn_pack_input": (C.c_int, [_P, _P, C.c_int64, _P, _P, C.c_size_t, _P]),
+    "wfd_cnn_pack_input": (C.c_int, [_P, _P, C.c_int64, C.c_float, _P, _P, C.c_size_t, _P]),
     "wfd_map_position": (C.c_int, [C.POINTER(wfd_grid), _D3, C.POINTER(C.c_int32)]),
     "wfd_cfl_ratio": (C.c_int, [C.POINTER(wfd_grid), C.c_double, C.c_double, _D3]),
     "wfd_checkpoint_plan": (C.c_int, [C.c_int32, C.c_int32, C.POINTER(C.c_int32), C.c_int64,

@@ -1284,14 +1284,15 @@ wfd_status wfd_cnn_adam(float *w, const float *g, float *m, float *v, int32_t n,
   return WFD_OK;
 }
 
-wfd_status wfd_cnn_pack_input(const float *grad, const float *illum, int64_t n, uint16_t *out,
-                              void *work, size_t work_bytes, void *stream) {
+wfd_status wfd_cnn_pack_input(const float *grad, const float *illum, int64_t n, float eps,
+                              uint16_t *out, void *work, size_t work_bytes, void *stream) {
   if (!grad || !illum || !out || !work) return fail(WFD_E_ARG, "NULL argument");
   if (n < 1) return fail(WFD_E_ARG, "n must be >= 1");
+  if (!(eps > 0.0f)) return fail(WFD_E_ARG, "eps must be > 0");
   if (work_bytes < WFD_CNN_REDUCE_BYTES)
     return fail(WFD_E_NOMEM, "workspace must hold %d bytes", WFD_CNN_REDUCE_BYTES);
-  HIP_TRY(wfd::launch_pack_input(grad, illum, n, static_cast<float *>(work), wfd::kCnnReduceBlocks,
-                                 out, (hipStream_t)stream));
+  HIP_TRY(wfd::launch_pack_input(grad, illum, n, eps, static_cast<float *>(work),
+                                 wfd::kCnnReduceBlocks, out, (hipStream_t)stream));
   return WFD_OK;
 }
 

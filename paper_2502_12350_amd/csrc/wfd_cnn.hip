@@ -343,13 +343,27 @@ __global__ void k_adam(float *__restrict__ w, const float *__restrict__ g, float
   w[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
 }
 
-// Largest |x| per block (for the input scales).
-__global__ void k_absmax(const float *__restrict__ x, int64_t n, float *__restrict__ partial) {
+// Largest |x| per block; with illum set, of x / (illum + eps * max|illum|),
+// the maximum of illum being reduced from the np entries of pmax first.
+__global__ void k_absmax(const float *__restrict__ x, const float *__restrict__ illum,
+                         const float *__restrict__ pmax, int np, float eps, int64_t n,
+                         float *__restrict__ partial) {
   __shared__ float red[256];
+  __shared__ float shift;
+  if (illum) {
+    if (threadIdx.x == 0) {
+      float m = 0.0f;
+      for (int i = 0; i < np; ++i) m = fmaxf(m, pmax[i]);
+      shift = eps * m;
+    }
+    __syncthreads();
+  }
   float s = 0.0f;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-       i += (int64_t)gridDim.x * blockDim.x)
-    s = fmaxf(s, fabsf(x[i]));
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const float v = illum ? (shift > 0.0f ? x[i] / (illum[i] + shift) : x[i]) : x[i];
+    s = fmaxf(s, fabsf(v));
+  }
   red[threadIdx.x] = s;
   __syncthreads();
   for (int w = 128; w > 0; w >>= 1) {
@@ -359,28 +373,29 @@ __global__ void k_absmax(const float *__restrict__ x, int64_t n, float *__restri
   if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
 }
 
-// Network input [voxel][2] = bf16(grad / max|grad|), bf16(illum / max|illum|);
-// the maxima are reduced from the per-block partials first.
+// Network input [voxel][2]: c = grad / (illum + eps max|illum|) scaled by
+// max|c|, and illum scaled by max|illum| (a channel with maximum 0 is left
+// unscaled).  pi, pc: per-block maxima of |illum| and |c|.
 __global__ void k_pack_input(const float *__restrict__ grad, const float *__restrict__ illum,
-                             int64_t n, const float *__restrict__ pg, const float *__restrict__ pi,
-                             int np, uint16_t *__restrict__ out) {
-  __shared__ float sg, si;
+                             int64_t n, float eps, const float *__restrict__ pi,
+                             const float *__restrict__ pc, int np, uint16_t *__restrict__ out) {
+  __shared__ float mi, mc;
   if (threadIdx.x == 0) {
     float a = 0.0f, b = 0.0f;
     for (int i = 0; i < np; ++i) {
-      a = fmaxf(a, pg[i]);
-      b = fmaxf(b, pi[i]);
+      a = fmaxf(a, pi[i]);
+      b = fmaxf(b, pc[i]);
     }
-    sg = a;
-    si = b;
+    mi = a;
+    mc = b;
   }
   __syncthreads();
+  const float shift = eps * mi;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x) {
-    const float a = sg > 0.0f ? grad[i] / sg : grad[i];
-    const float b = si > 0.0f ? illum[i] / si : illum[i];
-    out[2 * i] = to_bf16(a);
-    out[2 * i + 1] = to_bf16(b);
+    const float c = mi > 0.0f ? grad[i] / (illum[i] + shift) : grad[i];
+    out[2 * i] = to_bf16(mc > 0.0f ? c / mc : c);
+    out[2 * i + 1] = to_bf16(mi > 0.0f ? illum[i] / mi : illum[i]);
   }
 }
 
@@ -465,16 +480,19 @@ hipError_t launch_adam(float *w, const float *g, float *m, float *v, int n, floa
   return hipGetLastError();
 }
 
-hipError_t launch_pack_input(const float *grad, const float *illum, int64_t n, float *partial,
-                             int npart, uint16_t *out, hipStream_t stream) {
-  hipLaunchKernelGGL(k_absmax, dim3(npart), dim3(256), 0, stream, grad, n, partial);
+hipError_t launch_pack_input(const float *grad, const float *illum, int64_t n, float eps,
+                             float *partial, int npart, uint16_t *out, hipStream_t stream) {
+  float *pi = partial, *pc = partial + npart;
+  hipLaunchKernelGGL(k_absmax, dim3(npart), dim3(256), 0, stream, illum, nullptr, nullptr, 0, 0.0f,
+                     n, pi);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_absmax, dim3(npart), dim3(256), 0, stream, illum, n, partial + npart);
+  hipLaunchKernelGGL(k_absmax, dim3(npart), dim3(256), 0, stream, grad, illum, pi, npart, eps, n,
+                     pc);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_pack_input, dim3(npart), dim3(256), 0, stream, grad, illum, n, partial,
-                     partial + npart, npart, out);
+  hipLaunchKernelGGL(k_pack_input, dim3(npart), dim3(256), 0, stream, grad, illum, n, eps, pi, pc,
+                     npart, out);
   return hipGetLastError();
 }
 

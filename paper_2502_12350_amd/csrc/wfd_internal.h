@@ -141,7 +141,7 @@ hipError_t launch_mse(const float *y, const float *t, int64_t n, uint16_t *dy, d
                       int npart, double *loss, hipStream_t stream);
 hipError_t launch_adam(float *w, const float *g, float *m, float *v, int n, float lr, float b1,
                        float b2, float eps, int step, hipStream_t stream);
-hipError_t launch_pack_input(const float *grad, const float *illum, int64_t n, float *partial,
-                             int npart, uint16_t *out, hipStream_t stream);
+hipError_t launch_pack_input(const float *grad, const float *illum, int64_t n, float eps,
+                             float *partial, int npart, uint16_t *out, hipStream_t stream);
 
 }  // namespace wfd

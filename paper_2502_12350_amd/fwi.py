@@ -114,6 +114,7 @@ class FwiTrace:
     misfit: List[float] = field(default_factory=list)
     n_gradients: int = 0
     n_misfits: int = 0
+    n_network: int = 0   # iterations that used the learned direction
 
     def record(self, t: float, J: float):
         self.gpu_seconds.append(t)
@@ -169,11 +170,19 @@ def _project(v, bounds):
 def fwi(prop: Propagator, grid: GridSpec, v0, rho, shots: Shots, *, n_iter: int = 10,
         method: str = "sd", bounds: Optional[Tuple[float, float]] = None,
         max_rel_step: float = 0.02, eps_illum: float = 1.0e-3, memory: int = 5,
-        ckpt="auto", zero_top_planes: int = 0):
+        ckpt="auto", zero_top_planes: int = 0, precond=None, progress=None):
     """Alg. 2: repeat {gradient, model update} for n_iter iterations.
 
+    method "sd": steepest descent on the illumination-compensated gradient;
+    "lbfgs": projected L-BFGS with that preconditioner; "cnn": steepest
+    descent along the learned preconditioner's direction (`precond`, a
+    precond.Preconditioner), falling back to the illumination-compensated
+    gradient when the network's direction does not descend.
+
     Returns (final velocity, FwiTrace).  GPU-seconds are wall time of the
-    synchronised GPU work (the device runs nothing else meanwhile).
+    synchronised GPU work (the device runs nothing else meanwhile), including
+    the network's inference.  progress(iteration, misfit, gpu_seconds), if
+    given, is called after every iteration.
     """
     import torch
     trace = FwiTrace(method)
@@ -205,6 +214,8 @@ def fwi(prop: Propagator, grid: GridSpec, v0, rho, shots: Shots, *, n_iter: int 
     trace.record(clock[0], J)
     S, Y = [], []
     for it in range(n_iter):
+        if progress and it:
+            progress(it - 1, J, clock[0])
         P = 1.0 / (illum + eps_illum * illum.max())      # preconditioner (diagonal)
         if method == "lbfgs" and S:
             # two-loop recursion with H0 = gamma * P
@@ -222,6 +233,10 @@ def fwi(prop: Propagator, grid: GridSpec, v0, rho, shots: Shots, *, n_iter: int 
                 r += (a - b) * s_
             d = -r
             alpha0 = 1.0
+        elif method == "cnn":
+            d, used = timed(precond.direction, g, illum, eps_illum)
+            trace.n_network += int(used)
+            alpha0 = max_rel_step * float(v.abs().max()) / float(d.abs().max())
         else:
             d = -P * g
             alpha0 = max_rel_step * float(v.abs().max()) / float(d.abs().max())
@@ -267,4 +282,6 @@ def fwi(prop: Propagator, grid: GridSpec, v0, rho, shots: Shots, *, n_iter: int 
                     Y.pop(0)
         v, J, g = v_new, J_new, g_new
         trace.record(clock[0], J)
+    if progress:
+        progress(n_iter - 1, J, clock[0])
     return v, trace

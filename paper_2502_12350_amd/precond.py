@@ -2,9 +2,9 @@
 BF16 matrix-core kernels (include/wfd.h, wfd_cnn_*).
 
 The paper preconditions the FWI gradient with a fixed smoothing filter (its
-GradientPreconditioning option).  Here a small network maps the raw gradient
-and the source illumination (each scaled by its maximum) to a model-update
-direction:
+GradientPreconditioning option).  Here a small network maps the plain
+illumination-compensated gradient g / (I + eps max I) and the source
+illumination I (each scaled by its maximum) to a model-update direction:
 
     conv 3x3x3  2 -> 16, ReLU;  16 -> 16, ReLU;  16 -> 16, ReLU;  16 -> 1
 
@@ -28,6 +28,11 @@ from . import _lib
 from ._lib import check
 
 LAYERS: Tuple[Tuple[int, int], ...] = ((2, 16), (16, 16), (16, 16), (16, 1))
+
+# Weights trained by `python -m paper_2502_12350_amd.precond` on 512 solver
+# pairs (training record beside them).
+TRAINED = __import__("os").path.join(__import__("os").path.dirname(__file__), "weights",
+                                     "precond_c5.npz")
 
 
 def _p(t) -> Optional[int]:
@@ -102,12 +107,13 @@ class Preconditioner:
         return of if out_f32 else ob
 
     # -- network ------------------------------------------------------------------
-    def pack_input(self, grad, illum):
-        """[nz][ny][nx][2] BF16 network input from FP32 gradient and illumination."""
+    def pack_input(self, grad, illum, eps_illum: float = 1e-3):
+        """[nz][ny][nx][2] BF16 network input from FP32 gradient and illumination:
+        the illumination-compensated gradient and the illumination, each scaled."""
         torch = self.torch
         out = torch.empty(tuple(grad.shape) + (2,), dtype=torch.bfloat16, device=self.device)
         check(self.L.wfd_cnn_pack_input(_p(grad.contiguous()), _p(illum.contiguous()),
-                                        grad.numel(), _p(out), _p(self._reduce),
+                                        grad.numel(), eps_illum, _p(out), _p(self._reduce),
                                         self._reduce.numel(), self._stream()))
         return out
 
@@ -165,7 +171,7 @@ class Preconditioner:
         illumination-compensated fallback when that does not descend.
         Returns (direction, used_net)."""
         torch = self.torch
-        d = self.forward(self.pack_input(grad, illum))
+        d = self.forward(self.pack_input(grad, illum, eps_illum))
         if float(torch.sum(d.double() * grad.double())) < 0.0:
             return d, True
         return -grad / (illum + eps_illum * illum.max()), False
@@ -182,7 +188,131 @@ class Preconditioner:
         np.savez(path, **self.state())
 
     @classmethod
-    def load(cls, path: str, device: int = 0):
+    def load(cls, path: str = TRAINED, device: int = 0):
         with np.load(path, allow_pickle=False) as z:
             params = {k: z[k] for k in z.files}
         return cls(device, params=params)
+
+
+# ---------------------------------------------------------------------------
+# training on pairs generated by the solver
+# ---------------------------------------------------------------------------
+def solver_pair(prop, w, zero_top_planes: int = 10):
+    """Gradient and illumination at w.vel (the start model) for data modelled
+    on w.extra["v_true"], and the true perturbation: (grad, illum, dv) as FP32
+    device volumes [nz][ny][nx]."""
+    import torch
+    from .api import GridSpec
+    g = GridSpec(**w.grid_kwargs())
+    dev = prop.device
+    wav = torch.from_numpy(w.wavelet).to(dev)
+    vt = torch.from_numpy(w.extra["v_true"]).to(dev)
+    v0 = torch.from_numpy(w.vel).to(dev)
+    prop.set_model(g, vt)
+    dobs = [prop.forward(wav, s, w.receivers).clone() for s in w.sources]
+    prop.set_model(g, v0)
+    grad = torch.zeros_like(v0)
+    illum = torch.zeros_like(v0)
+    for s, d in zip(w.sources, dobs):
+        prop.gradient(wav, s, w.receivers, d, ckpt="full", grad=grad, illum=illum)
+    if zero_top_planes:
+        prop.gradient_finish(grad, zero_top_planes)
+    return grad, illum, vt - v0
+
+
+def cosine(a, b) -> float:
+    import torch
+    a, b = a.double(), b.double()
+    return float(torch.sum(a * b) / (torch.linalg.vector_norm(a) * torch.linalg.vector_norm(b)))
+
+
+def fallback_direction(grad, illum, eps_illum: float = 1e-3):
+    """The plain illumination-compensated descent direction -g / (I + eps max I)."""
+    return -grad / (illum + eps_illum * illum.max())
+
+
+def main(argv=None):
+    """python -m paper_2502_12350_amd.precond --models N --epochs E --out weights.npz
+
+    Generates N training pairs with the solver (models c5_model(5000 + i)),
+    trains the network, and reports the validation cosine between each
+    direction and the true perturbation (network vs the plain
+    illumination-compensated gradient)."""
+    import argparse
+    import json
+    import sys
+    import time
+    import torch
+    import seisgen
+    from .api import Propagator
+
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--models", type=int, default=512)
+    ap.add_argument("--val", type=int, default=16)
+    ap.add_argument("--size", type=int, default=128)
+    ap.add_argument("--epochs", type=int, default=4)
+    ap.add_argument("--lr", type=float, default=2e-3)
+    ap.add_argument("--decay", type=float, default=0.75, help="learning-rate factor per epoch")
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--out", default="precond.npz")
+    args = ap.parse_args(argv)
+
+    dev = torch.device("cuda", 0)
+    prop = Propagator(0)
+    net = Preconditioner(0, seed=args.seed)
+    xs, ts, val = [], [], []
+    t0 = time.perf_counter()
+    n_all = args.models + args.val
+    for i in range(n_all):
+        w = seisgen.c5_model(5000 + i, n=args.size)
+        grad, illum, dv = solver_pair(prop, w)
+        x = net.pack_input(grad, illum)
+        t = (dv / dv.abs().max()).contiguous()
+        if i < args.models:
+            xs.append(x)
+            ts.append(t)
+        else:
+            val.append((x, t, grad, illum, dv))
+        if (i + 1) % 32 == 0:
+            torch.cuda.synchronize()
+            print(f"[precond] {i + 1}/{n_all} pairs in {time.perf_counter() - t0:.1f} s",
+                  file=sys.stderr, flush=True)
+    prop.release_workspace()
+    t_data = time.perf_counter() - t0
+
+    def validate():
+        c_net, c_fb, loss = [], [], []
+        for x, t, grad, illum, dv in val:
+            y = net.forward(x)
+            loss.append(float(torch.mean((y - t) ** 2)))
+            c_net.append(cosine(y, dv))
+            c_fb.append(cosine(fallback_direction(grad, illum), dv))
+        return float(np.mean(loss)), float(np.mean(c_net)), float(np.mean(c_fb))
+
+    hist = [validate()]
+    print(f"[precond] before training: val loss {hist[0][0]:.4e}, cos net {hist[0][1]:.3f}, "
+          f"cos fallback {hist[0][2]:.3f}", file=sys.stderr, flush=True)
+    rng = np.random.default_rng(args.seed)
+    t1 = time.perf_counter()
+    steps = 0
+    for ep in range(args.epochs):
+        lr = args.lr * (args.decay ** ep)
+        for k in rng.permutation(len(xs)):
+            net.train_step(xs[k], ts[k], lr=lr)
+            steps += 1
+        torch.cuda.synchronize()
+        hist.append(validate())
+        print(f"[precond] epoch {ep + 1}: val loss {hist[-1][0]:.4e}, cos net {hist[-1][1]:.3f}, "
+              f"cos fallback {hist[-1][2]:.3f} ({time.perf_counter() - t1:.1f} s)",
+              file=sys.stderr, flush=True)
+    t_train = time.perf_counter() - t1
+    net.save(args.out)
+    print(json.dumps({"models": args.models, "size": args.size, "epochs": args.epochs,
+                      "train_steps": steps, "data_seconds": round(t_data, 1),
+                      "train_seconds": round(t_train, 1),
+                      "val": [{"loss": h[0], "cos_net": h[1], "cos_fallback": h[2]}
+                              for h in hist]}), flush=True)
+
+
+if __name__ == "__main__":
+    main()

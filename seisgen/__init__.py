@@ -12,7 +12,7 @@ metres in ``(x, y, z)`` order, seismograms are trace-major ``[rec][ns]``.
 
 from .models import layered_model, gardner_density, blob_anomalies, smooth_noise
 from .wavelet import ricker
-from .configs import Workload, workload, WORKLOADS, shot_window
+from .configs import Workload, workload, WORKLOADS, shot_window, c5_model
 
 __all__ = [
     "layered_model",
@@ -24,4 +24,5 @@ __all__ = [
     "workload",
     "WORKLOADS",
     "shot_window",
+    "c5_model",
 ]

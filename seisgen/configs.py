@@ -31,6 +31,13 @@ c4        200 x 200 x 160 smooth layered background + six +/-10 % blobs,
 c4_fd     32^3 layered model, 8-cell sponge, 300 steps, one shot, 64
           receivers, plus a smooth 1 % velocity perturbation direction for
           finite-difference gradient checks.
+c5_train  (function c5_model(seed)) training models of the learned
+          preconditioner: 128^3 layered background L(seed, 0), 1-4 blobs of
+          +/-10 % (sigma 4-10 cells) away from the faces, 16-cell sponge,
+          1000 steps, 10 Hz, 4 shots at depth 4 on a 2 x 2 grid, 32 x 32
+          receivers at depth 2; start model = background.
+c5_eval   the same recipe at 256^3 (seed 5999), 20-cell sponge, 1600
+          steps, 8 shots, 64 x 64 receivers.
 example   the paper's illustrative 25^3 setup (§3): h = 10 m, border 25,
           500 steps, dt = 1 ms, 10 Hz Ricker with amplitude 1e5, Gaussian
           velocity blob.
@@ -197,6 +204,29 @@ def _c4_fd(variable_density: bool = False, nt: int = 300) -> Workload:
     return w
 
 
+def c5_model(seed: int, n: int = 128, border: int = 16, nt: int = 1000,
+             shots_xy=(2, 2), rec_step: int = 4) -> Workload:
+    """One model of the learned-preconditioner recipe (see the module notes)."""
+    h = 10.0
+    rng = np.random.default_rng(seed)
+    bg = layered_model(seed, n, 0.0)
+    n_blobs = int(rng.integers(1, 5))
+    m = max(8, n // 8)
+    true = blob_anomalies(bg, seed=seed + 100000, n_blobs=n_blobs, amp=0.10,
+                          sigma_cells=(4.0, 10.0), centre_lo=(m, m, 2 * m),
+                          centre_hi=(n - m, n - m, n - m))
+    dt = 0.4 * h / (1.1 * 4500.0)
+    sx, sy = shots_xy
+    shots = [[int((i + 0.5) * n / sx), int((j + 0.5) * n / sy), 4]
+             for j in range(sy) for i in range(sx)]
+    k = n // rec_step
+    rec = _surface_grid(rec_step // 2, rec_step, k, rec_step // 2, rec_step, k, 2)
+    w = Workload(f"c5_{seed}", n, n, n, h, h, h, 0.0, 0.0, 0.0, border, dt, nt, bg, None,
+                 ricker(nt, dt, 10.0, 0.1), _metres(shots, (h, h, h)), _metres(rec, (h, h, h)))
+    w.extra["v_true"] = true
+    return w
+
+
 def _example() -> Workload:
     """Paper §3: 25^3 cells of 10 m, border 25, 500 steps of 1 ms, 10 Hz Ricker,
     amplitude 1e5; sources every 100 m from 20 m to 220 m, receivers every
@@ -228,6 +258,7 @@ WORKLOADS: Dict[str, Callable[[], Workload]] = {
     "c4_fd": _c4_fd,
     "c4_fd_vd": lambda: _c4_fd(True),
     "example": _example,
+    "c5_eval": lambda: c5_model(5999, n=256, border=20, nt=1600, shots_xy=(4, 2)),
 }
 
 

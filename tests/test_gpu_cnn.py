@@ -161,7 +161,8 @@ def test_mse_adam_and_input_packing_match_oracle():
     from paper_2502_12350_amd.precond import Preconditioner
     P = Preconditioner(0)
     got = _np(P.pack_input(torch.from_numpy(g).cuda(), torch.from_numpy(il).cuda()))
-    frac, worst = _bf16_close(got, np.stack([g / np.abs(g).max(), il / il.max()], axis=-1))
+    c = g.astype(np.float64) / (il + 1e-3 * il.max())
+    frac, worst = _bf16_close(got, np.stack([c / np.abs(c).max(), il / il.max()], axis=-1))
     assert frac <= 1e-3 and worst <= 1.0
 
 
@@ -198,11 +199,11 @@ def test_training_lowers_the_loss_and_is_deterministic():
     shape = (12, 20, 40)
     g = rng.standard_normal(shape).astype(np.float32)
     il = np.abs(rng.standard_normal(shape)).astype(np.float32)
-    tgt = torch.from_numpy(-0.5 * g).cuda()
     runs = []
     for _ in range(2):
         P = Preconditioner(0, seed=5)
         x = P.pack_input(torch.from_numpy(g).cuda(), torch.from_numpy(il).cuda())
+        tgt = (-0.5 * x[..., 0].float()).contiguous()   # a linear map of the first channel
         losses = [float(P.train_step(x, tgt, lr=3e-3).item()) for _ in range(60)]
         runs.append((losses, P.w[0].clone()))
     (l1, w1), (l2, w2) = runs

@@ -146,6 +146,20 @@ def test_pack_input_scales_each_channel():
     assert a.shape == (3, 4, 5, 2)
     assert np.max(np.abs(a[..., 0])) == 1.0 and np.max(a[..., 1]) == 1.0
     assert np.array_equal(a, cnn.bf16(a))
+    # constant illumination: channel 0 is the gradient scaled by its maximum
+    a = cnn.pack_input(g, np.full(g.shape, 7.0))
+    assert np.array_equal(a[..., 0], cnn.bf16(g / np.max(np.abs(g))))
+    assert np.all(a[..., 1] == 1.0)
+    # the compensation divides by I + eps max I: a point with I = 0 gets
+    # 1 / (eps max I) times its gradient, a point with I = max I about 1 / max I
+    g2 = np.array([1.0, 1.0]).reshape(1, 1, 2)
+    i2 = np.array([0.0, 4.0]).reshape(1, 1, 2)
+    a = cnn.pack_input(g2, i2, eps=1e-3)
+    assert a[0, 0, 0, 0] == 1.0
+    assert a[0, 0, 1, 0] == cnn.bf16((1.0 / 4.004) / (1.0 / 0.004))
+    # zero illumination everywhere: raw gradient, unscaled illumination
+    a = cnn.pack_input(g2, np.zeros_like(g2))
+    assert np.array_equal(a[..., 0], cnn.bf16(g2 / 1.0)) and np.all(a[..., 1] == 0.0)
 
 
 def test_adam_first_step_closed_form():
