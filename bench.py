@@ -344,15 +344,22 @@ def precond_fwi_bench(n_iter: int):
     v0 = torch.from_numpy(w.vel).to(dev)
     vt = w.extra["v_true"]
     net = Preconditioner.load(TRAINED)
+    vt_d = torch.from_numpy(vt).to(dev)
+    err0 = float(torch.linalg.vector_norm((v0 - vt_d).double()))
     runs = {}
     for method in ("sd", "cnn"):
         print(f"[bench-precond] {method}", file=sys.stderr, flush=True)
+        errs = [1.0]
+
+        def progress(it, J, t, v):
+            errs.append(float(torch.linalg.vector_norm((v - vt_d).double())) / err0)
+            print(f"[bench-precond] {method} iteration {it + 1}: misfit {J:.4e}, model error "
+                  f"{errs[-1]:.5f} at {t:.1f} GPU-s", file=sys.stderr, flush=True)
+
         v, tr = fwi(P, g, v0, None, shots, n_iter=n_iter, method=method, bounds=(1500.0, 4500.0),
-                    zero_top_planes=10, precond=net,
-                    progress=lambda it, J, t: print(f"[bench-precond] {method} iteration {it + 1}: "
-                                                    f"misfit {J:.4e} at {t:.1f} GPU-s",
-                                                    file=sys.stderr, flush=True))
+                    zero_top_planes=10, precond=net, progress=progress)
         runs[method] = {
+            "model_error_rel_per_iteration": [round(e, 6) for e in errs],
             "misfit": [float(x) for x in tr.misfit],
             "gpu_seconds": [round(t, 3) for t in tr.gpu_seconds],
             "misfit_cut_per_gpu_s": tr.misfit_cut_per_gpu_s(),
@@ -365,6 +372,15 @@ def precond_fwi_bench(n_iter: int):
     target = sd["misfit"][-1]  # equal final misfit: the plain method's
     t_sd = sd["_trace"].time_to_reach(target / sd["misfit"][0])
     t_cnn = cnn["_trace"].time_to_reach(target / cnn["misfit"][0])
+
+    def t_err(r, e):  # GPU-seconds until the model error is at most e
+        for t, x in zip(r["gpu_seconds"], r["model_error_rel_per_iteration"]):
+            if x <= e:
+                return t
+        return None
+
+    e_target = sd["model_error_rel_per_iteration"][-1]
+    te_sd, te_cnn = t_err(sd, e_target), t_err(cnn, e_target)
     for r in runs.values():
         r.pop("_trace")
     out = {"metric": "FWI misfit cut per GPU-s: learned preconditioner vs illumination-compensated "
@@ -376,6 +392,8 @@ def precond_fwi_bench(n_iter: int):
                       "iterations": n_iter, "zero_top_planes": 10,
                       "network": "2-16-16-16-1 3x3x3 BF16, trained on 512 solver pairs (128^3)"},
            "gpu_s_to_plain_final_misfit": {"sd": t_sd, "cnn": t_cnn},
+           "gpu_s_to_plain_final_model_error": {"sd": te_sd, "cnn": te_cnn},
+           "model_error_speedup": round(te_sd / te_cnn, 3) if te_cnn else None,
            "methods": runs}
     print(json.dumps(out), flush=True)
 

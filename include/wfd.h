@@ -270,7 +270,7 @@ wfd_status wfd_checkpoint_plan(int32_t nt, int32_t n_snapshots, int32_t *actions
  * Replaces the paper's fixed gradient smoothing (GradientPreconditioning,
  * Bessel or Laplace filters) by a small network of 3 x 3 x 3 convolutions
  * with "same" zero padding: 2 -> 16 -> 16 -> 16 -> 1 channels, ReLU after the
- * first three.  Stateless calls on device buffers, enqueued on `stream` (a
+ * first three, and the first input channel added to the output.  Stateless calls on device buffers, enqueued on `stream` (a
  * hipStream_t, NULL = legacy default stream) on the current device.
  *
  * Layouts: BF16 values are passed as uint16_t bit patterns.  Volumes are
@@ -295,15 +295,17 @@ wfd_status wfd_cnn_pack_weights(const float *w_dev, int32_t cin, int32_t cout, i
 
 /* out[p][co] = sum_{tap, ci} in[p + offset(tap)][ci] * A[co][tap * cin + ci]
  * (+ bias[co]), then max(., 0) if relu, then 0 where mask[p][co] <= 0 if a
- * mask is given; BF16 products, FP32 sums.  With the flip-packed weights of a
+ * mask is given, then (cout = 1 only) + residual[p][0] of a BF16
+ * residual[p][residual_channels] if given; BF16 products, FP32 sums.  With the flip-packed weights of a
  * layer (cin, cout) this is the data gradient of that layer: call it with
  * cin' = cout and cout' = cin.  (cin, cout) in {(2,16), (16,16), (16,1),
  * (1,16)}.  Written as BF16 (rounded to nearest even) and/or FP32
  * channels-last; in, packed and outputs 16-byte aligned. */
 wfd_status wfd_cnn_conv(const uint16_t *in_dev, int32_t nx, int32_t ny, int32_t nz, int32_t cin,
                         int32_t cout, const uint16_t *packed_dev, const float *bias_or_null,
-                        int32_t relu, const uint16_t *mask_or_null, uint16_t *out_bf16_or_null,
-                        float *out_f32_or_null, void *stream);
+                        int32_t relu, const uint16_t *mask_or_null,
+                        const uint16_t *residual_or_null, int32_t residual_channels,
+                        uint16_t *out_bf16_or_null, float *out_f32_or_null, void *stream);
 
 /* Workspace of wfd_cnn_wgrad for an nx x ny x nz volume. */
 wfd_status wfd_cnn_wgrad_workspace_bytes(int32_t nx, int32_t ny, int32_t nz, size_t *bytes);

@@ -15,7 +15,10 @@ illumination I itself, each scaled by its largest magnitude:
     z1 = C(a0; W1, b1)   a1 = q(relu(z1))        2 -> 16 channels
     z2 = C(a1; W2, b2)   a2 = q(relu(z2))       16 -> 16
     z3 = C(a2; W3, b3)   a3 = q(relu(z3))       16 -> 16
-    y  = C(a3; W4, b4)                          16 -> 1
+    y  = C(a3; W4, b4) + a0[..., 0]             16 -> 1
+
+The last term passes the first input channel (the scaled plain direction)
+through, so the network learns a correction to it.
 
 C is a 3 x 3 x 3 cross-correlation with zero padding ("same" size) plus a
 per-channel bias.  Weights and stored activations are BF16 (q = round to
@@ -138,7 +141,7 @@ def forward(a0, Ws, bs, quantize: bool = True):
     for layer in range(3):
         z = conv3d(acts[-1], Ws[layer], bs[layer])
         acts.append(q(np.maximum(z, 0.0)))
-    y = conv3d(acts[-1], Ws[3], bs[3])
+    y = conv3d(acts[-1], Ws[3], bs[3]) + acts[0][..., :1]
     return acts, y
 
 

@@ -73,7 +73,7 @@ _SIGS = {
     "wfd_cnn_packed_elems": (C.c_int, [C.c_int32, C.c_int32, C.c_int32, C.POINTER(C.c_int64)]),
     "wfd_cnn_pack_weights": (C.c_int, [_P, C.c_int32, C.c_int32, C.c_int32, _P, _P]),
     "wfd_cnn_conv": (C.c_int, [_P, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_int32, _P, _P,
-                               C.c_int32, _P, _P, _P, _P]),
+                               C.c_int32, _P, _P, C.c_int32, _P, _P, _P]),
     "wfd_cnn_wgrad_workspace_bytes": (C.c_int, [C.c_int32, C.c_int32, C.c_int32,
                                                 C.POINTER(C.c_size_t)]),
     "wfd_cnn_wgrad": (C.c_int, [_P, _P, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_int32,

@@ -1222,7 +1222,8 @@ wfd_status wfd_cnn_pack_weights(const float *w, int32_t cin, int32_t cout, int32
 
 wfd_status wfd_cnn_conv(const uint16_t *in, int32_t nx, int32_t ny, int32_t nz, int32_t cin,
                         int32_t cout, const uint16_t *apk, const float *bias, int32_t relu,
-                        const uint16_t *mask, uint16_t *out_bf16, float *out_f32, void *stream) {
+                        const uint16_t *mask, const uint16_t *residual, int32_t residual_channels,
+                        uint16_t *out_bf16, float *out_f32, void *stream) {
   const bool shape = (cin == 2 && cout == 16) || (cin == 16 && cout == 16) ||
                      (cin == 16 && cout == 1) || (cin == 1 && cout == 16);
   if (!shape) return fail(WFD_E_ARG, "no convolution %d -> %d channels", cin, cout);
@@ -1231,11 +1232,13 @@ wfd_status wfd_cnn_conv(const uint16_t *in, int32_t nx, int32_t ny, int32_t nz, 
     return fail(WFD_E_ARG, "volume too large");
   if (!in || !apk) return fail(WFD_E_ARG, "NULL input or weights");
   if (!out_bf16 && !out_f32) return fail(WFD_E_ARG, "no output");
+  if (residual && (cout != 1 || residual_channels < 1))
+    return fail(WFD_E_ARG, "a residual needs a single-output convolution and >= 1 channel");
   if ((uintptr_t)in % 16 || (uintptr_t)apk % 16 || (uintptr_t)out_bf16 % 16 ||
       (uintptr_t)out_f32 % 16)
     return fail(WFD_E_ARG, "buffers must be 16-byte aligned");
-  HIP_TRY(wfd::launch_conv(cin, cout, in, nx, ny, nz, apk, bias, relu, mask, out_bf16, out_f32,
-                           (hipStream_t)stream));
+  HIP_TRY(wfd::launch_conv(cin, cout, in, nx, ny, nz, apk, bias, relu, mask, residual,
+                           residual_channels, out_bf16, out_f32, (hipStream_t)stream));
   return WFD_OK;
 }
 

@@ -115,14 +115,15 @@ __device__ __forceinline__ bf16x8 gather_b(const uint16_t *lds, int c, int lx, i
 }
 
 // Convolution (forward or data gradient).  out = conv(in; A) [+ bias], then
-// relu, then * (mask > 0); written as BF16 and/or FP32 channels-last with COUT
+// relu, then * (mask > 0), then (single output channel only) + channel 0 of
+// res[voxel][res_c]; written as BF16 and/or FP32 channels-last with COUT
 // channels.  Every output voxel of the tile is computed by exactly one lane.
 template <int CIN, int COUT>
 __global__ void __launch_bounds__(NTHR)
     k_conv(const uint16_t *__restrict__ in, int nx, int ny, int nz,
            const uint16_t *__restrict__ apk, const float *__restrict__ bias, int relu,
-           const uint16_t *__restrict__ mask, uint16_t *__restrict__ out_bf,
-           float *__restrict__ out_f) {
+           const uint16_t *__restrict__ mask, const uint16_t *__restrict__ res, int res_c,
+           uint16_t *__restrict__ out_bf, float *__restrict__ out_f) {
   constexpr int K = kpad(CIN), NC = K / 32;
   __shared__ __attribute__((aligned(16))) uint16_t lds[BRICK * CIN + 8];
   int x0, y0, z0;
@@ -176,6 +177,7 @@ __global__ void __launch_bounds__(NTHR)
       if (out_f)
         *reinterpret_cast<float4 *>(out_f + vox * 16 + 4 * g) = make_float4(v[0], v[1], v[2], v[3]);
     } else if (g == 0) {  // single output channel: co = 0 is element 0 of group 0
+      if (res) v[0] += from_bf16(res[vox * res_c]);
       if (out_bf) out_bf[vox] = to_bf16(v[0]);
       if (out_f) out_f[vox] = v[0];
     }
@@ -409,11 +411,12 @@ int cnn_conv_blocks(int nx, int ny, int nz) { return conv_blocks(nx, ny, nz); }
 
 hipError_t launch_conv(int cin, int cout, const uint16_t *in, int nx, int ny, int nz,
                        const uint16_t *apk, const float *bias, int relu, const uint16_t *mask,
-                       uint16_t *out_bf, float *out_f, hipStream_t stream) {
+                       const uint16_t *res, int res_c, uint16_t *out_bf, float *out_f,
+                       hipStream_t stream) {
   const dim3 grid(conv_blocks(nx, ny, nz)), block(NTHR);
 #define WFD_CONV(CI, CO)                                                                      \
   hipLaunchKernelGGL((k_conv<CI, CO>), grid, block, 0, stream, in, nx, ny, nz, apk, bias, relu, \
-                     mask, out_bf, out_f)
+                     mask, res, res_c, out_bf, out_f)
   if (cin == 16 && cout == 16) WFD_CONV(16, 16);
   else if (cin == 2 && cout == 16) WFD_CONV(2, 16);
   else if (cin == 1 && cout == 16) WFD_CONV(1, 16);

@@ -132,7 +132,8 @@ size_t cnn_wgrad_workspace_floats(int nx, int ny, int nz);
 constexpr int kCnnReduceBlocks = 512;  // partials of the loss and input-scale reductions
 hipError_t launch_conv(int cin, int cout, const uint16_t *in, int nx, int ny, int nz,
                        const uint16_t *apk, const float *bias, int relu, const uint16_t *mask,
-                       uint16_t *out_bf, float *out_f, hipStream_t stream);
+                       const uint16_t *res, int res_c, uint16_t *out_bf, float *out_f,
+                       hipStream_t stream);
 hipError_t launch_wgrad(int cin, int cout, const uint16_t *in, const uint16_t *dz, int nx, int ny,
                         int nz, float *work, float *dw, float *db, hipStream_t stream);
 hipError_t launch_pack_weights(const float *w, int cin, int cout, int flip, uint16_t *apk,

@@ -114,7 +114,7 @@ class FwiTrace:
     misfit: List[float] = field(default_factory=list)
     n_gradients: int = 0
     n_misfits: int = 0
-    n_network: int = 0   # iterations that used the learned direction
+    n_network: int = 0   # accepted steps along the learned direction
 
     def record(self, t: float, J: float):
         self.gpu_seconds.append(t)
@@ -181,8 +181,8 @@ def fwi(prop: Propagator, grid: GridSpec, v0, rho, shots: Shots, *, n_iter: int 
 
     Returns (final velocity, FwiTrace).  GPU-seconds are wall time of the
     synchronised GPU work (the device runs nothing else meanwhile), including
-    the network's inference.  progress(iteration, misfit, gpu_seconds), if
-    given, is called after every iteration.
+    the network's inference.  progress(iteration, misfit, gpu_seconds, model),
+    if given, is called after every iteration.
     """
     import torch
     trace = FwiTrace(method)
@@ -213,10 +213,23 @@ def fwi(prop: Propagator, grid: GridSpec, v0, rho, shots: Shots, *, n_iter: int 
     J, g = grad_at(v)
     trace.record(clock[0], J)
     S, Y = [], []
+    dv_prev = None  # largest model change of the last accepted steepest-descent step
+
+    def first_step(d, warm: bool = True):
+        """Initial trial step: a largest model change of max_rel_step * max|v|
+        (the default), or with `warm` twice the last accepted change but at
+        least 5 % of the default."""
+        dmax = float(d.abs().max())
+        default = max_rel_step * float(v.abs().max())
+        if dv_prev is None or not warm:
+            return default / dmax
+        return max(2.0 * dv_prev, 0.05 * default) / dmax
+
     for it in range(n_iter):
         if progress and it:
-            progress(it - 1, J, clock[0])
+            progress(it - 1, J, clock[0], v)
         P = 1.0 / (illum + eps_illum * illum.max())      # preconditioner (diagonal)
+        used = False                                       # step along the network's direction
         if method == "lbfgs" and S:
             # two-loop recursion with H0 = gamma * P
             q = g.clone()
@@ -235,17 +248,17 @@ def fwi(prop: Propagator, grid: GridSpec, v0, rho, shots: Shots, *, n_iter: int 
             alpha0 = 1.0
         elif method == "cnn":
             d, used = timed(precond.direction, g, illum, eps_illum)
-            trace.n_network += int(used)
-            alpha0 = max_rel_step * float(v.abs().max()) / float(d.abs().max())
+            alpha0 = first_step(d)
         else:
             d = -P * g
-            alpha0 = max_rel_step * float(v.abs().max()) / float(d.abs().max())
+            alpha0 = first_step(d)
         gd = _dot(g, d)
         if gd >= 0:  # not a descent direction: restart from the preconditioned gradient
             S, Y = [], []
             d = -P * g
-            alpha0 = max_rel_step * float(v.abs().max()) / float(d.abs().max())
+            alpha0 = first_step(d)
             gd = _dot(g, d)
+            used = False
         if method == "lbfgs" and not S:
             # no curvature pairs yet: same quadratic step as steepest descent
             alpha = _quadratic_step(J_at, v, d, J, gd, alpha0, bounds)
@@ -267,9 +280,18 @@ def fwi(prop: Propagator, grid: GridSpec, v0, rho, shots: Shots, *, n_iter: int 
                 continue
         else:
             alpha = _quadratic_step(J_at, v, d, J, gd, alpha0, bounds)
+            if alpha is None and dv_prev is not None:  # warm start failed: default step
+                alpha = _quadratic_step(J_at, v, d, J, gd, first_step(d, warm=False), bounds)
+            if alpha is None and used:  # the network's direction failed: plain one
+                d = -P * g
+                gd = _dot(g, d)
+                used = False
+                alpha = _quadratic_step(J_at, v, d, J, gd, first_step(d, warm=False), bounds)
             if alpha is None:  # no decrease found: stop updating
                 trace.record(clock[0], J)
                 continue
+            trace.n_network += int(used)
+            dv_prev = alpha * float(d.abs().max())
         v_new = _project(v + alpha * d, bounds)
         J_new, g_new = grad_at(v_new)
         if method == "lbfgs":
@@ -283,5 +305,5 @@ def fwi(prop: Propagator, grid: GridSpec, v0, rho, shots: Shots, *, n_iter: int 
         v, J, g = v_new, J_new, g_new
         trace.record(clock[0], J)
     if progress:
-        progress(n_iter - 1, J, clock[0])
+        progress(n_iter - 1, J, clock[0], v)
     return v, trace

@@ -6,7 +6,9 @@ GradientPreconditioning option).  Here a small network maps the plain
 illumination-compensated gradient g / (I + eps max I) and the source
 illumination I (each scaled by its maximum) to a model-update direction:
 
-    conv 3x3x3  2 -> 16, ReLU;  16 -> 16, ReLU;  16 -> 16, ReLU;  16 -> 1
+    conv 3x3x3  2 -> 16, ReLU;  16 -> 16, ReLU;  16 -> 16, ReLU;  16 -> 1,
+    plus the first input channel (the network learns a correction of the
+    scaled plain direction)
 
 BF16 weights and activations, FP32 accumulation, FP32 master weights trained
 with Adam on the mean squared error against the scaled true perturbation.
@@ -29,10 +31,10 @@ from ._lib import check
 
 LAYERS: Tuple[Tuple[int, int], ...] = ((2, 16), (16, 16), (16, 16), (16, 1))
 
-# Weights trained by `python -m paper_2502_12350_amd.precond` on 512 solver
-# pairs (training record beside them).
-TRAINED = __import__("os").path.join(__import__("os").path.dirname(__file__), "weights",
-                                     "precond_c5.npz")
+# Weights trained by `python -m paper_2502_12350_amd.precond` on solver pairs
+# (the training record, with its command, is beside them).
+TRAINED = __import__("os").environ.get("WFD_PRECOND_WEIGHTS") or __import__("os").path.join(
+    __import__("os").path.dirname(__file__), "weights", "precond_c5.npz")
 
 
 def _p(t) -> Optional[int]:
@@ -89,7 +91,7 @@ class Preconditioner:
                                                   _p(self.packed[li][f]), s))
 
     def conv(self, x, li: int, *, relu: bool, out_f32: bool = False, flip: bool = False,
-             mask=None, bias: bool = True):
+             mask=None, bias: bool = True, residual=None):
         """One convolution of layer li (or its data gradient with flip=True)."""
         torch = self.torch
         nz, ny, nx = x.shape[:3]
@@ -103,7 +105,9 @@ class Preconditioner:
             if out_f32 else None
         check(self.L.wfd_cnn_conv(_p(x), nx, ny, nz, ci, co, _p(self.packed[li][int(flip)]),
                                   _p(self.b[li]) if (bias and not flip) else None, int(relu),
-                                  _p(mask), _p(ob), _p(of), self._stream()))
+                                  _p(mask), _p(residual),
+                                  0 if residual is None else residual.shape[-1],
+                                  _p(ob), _p(of), self._stream()))
         return of if out_f32 else ob
 
     # -- network ------------------------------------------------------------------
@@ -122,7 +126,7 @@ class Preconditioner:
         acts = [x]
         for li in range(3):
             acts.append(self.conv(acts[-1], li, relu=True))
-        y = self.conv(acts[-1], 3, relu=False, out_f32=True)[..., 0]
+        y = self.conv(acts[-1], 3, relu=False, out_f32=True, residual=x)[..., 0]
         self._acts = acts if keep else None
         return y
 
@@ -231,25 +235,39 @@ def fallback_direction(grad, illum, eps_illum: float = 1e-3):
     return -grad / (illum + eps_illum * illum.max())
 
 
-def main(argv=None):
-    """python -m paper_2502_12350_amd.precond --models N --epochs E --out weights.npz
+def recipe_model(size: int, seed: int):
+    """Training-recipe model of a given size: 128^3 (4 shots, 1000 steps) or
+    the 256^3 evaluation geometry (8 shots, 1600 steps, 20-cell sponge)."""
+    import seisgen
+    if size >= 256:
+        return seisgen.c5_model(seed, n=size, border=20, nt=1600, shots_xy=(4, 2))
+    return seisgen.c5_model(seed, n=size)
 
-    Generates N training pairs with the solver (models c5_model(5000 + i)),
-    trains the network, and reports the validation cosine between each
-    direction and the true perturbation (network vs the plain
-    illumination-compensated gradient)."""
+
+SEED_BASE = {128: 5000, 256: 6000}  # training seeds; validation continues after them
+
+
+def main(argv=None):
+    """python -m paper_2502_12350_amd.precond --data 128:512:1 --epochs E --out weights.npz
+
+    Generates training pairs with the solver (for each size:models:crops
+    entry, models of that size with seeds SEED_BASE[size] + i, each giving
+    `crops` random crops of --crop cells, or the whole volume when crops is
+    1 and the size equals the crop), trains the network, and reports the
+    validation cosine between each direction and the true perturbation
+    (network vs the plain illumination-compensated gradient) on whole
+    validation volumes."""
     import argparse
     import json
     import sys
     import time
     import torch
-    import seisgen
     from .api import Propagator
 
     ap = argparse.ArgumentParser()
-    ap.add_argument("--models", type=int, default=512)
-    ap.add_argument("--val", type=int, default=16)
-    ap.add_argument("--size", type=int, default=128)
+    ap.add_argument("--data", default="128:512:1", help="comma list of size:models:crops")
+    ap.add_argument("--val", default="128:16", help="comma list of size:models")
+    ap.add_argument("--crop", type=int, default=128)
     ap.add_argument("--epochs", type=int, default=4)
     ap.add_argument("--lr", type=float, default=2e-3)
     ap.add_argument("--decay", type=float, default=0.75, help="learning-rate factor per epoch")
@@ -257,42 +275,72 @@ def main(argv=None):
     ap.add_argument("--out", default="precond.npz")
     args = ap.parse_args(argv)
 
-    dev = torch.device("cuda", 0)
     prop = Propagator(0)
     net = Preconditioner(0, seed=args.seed)
+    rng = np.random.default_rng(args.seed)
     xs, ts, val = [], [], []
     t0 = time.perf_counter()
-    n_all = args.models + args.val
-    for i in range(n_all):
-        w = seisgen.c5_model(5000 + i, n=args.size)
+    done = 0
+
+    def pair(size, seed):
+        nonlocal done
+        w = recipe_model(size, seed)
         grad, illum, dv = solver_pair(prop, w)
-        x = net.pack_input(grad, illum)
-        t = (dv / dv.abs().max()).contiguous()
-        if i < args.models:
-            xs.append(x)
-            ts.append(t)
-        else:
-            val.append((x, t, grad, illum, dv))
-        if (i + 1) % 32 == 0:
+        done += 1
+        if done % 16 == 0:
             torch.cuda.synchronize()
-            print(f"[precond] {i + 1}/{n_all} pairs in {time.perf_counter() - t0:.1f} s",
-                  file=sys.stderr, flush=True)
+            print(f"[precond] {done} pairs in {time.perf_counter() - t0:.1f} s", file=sys.stderr,
+                  flush=True)
+        return grad, illum, dv
+
+    counts = {}
+    for item in args.data.split(","):
+        size, models, crops = (int(v) for v in item.split(":"))
+        counts[size] = models
+        for i in range(models):
+            grad, illum, dv = pair(size, SEED_BASE[size] + i)
+            x = net.pack_input(grad, illum)
+            t = dv / dv.abs().max()
+            c = args.crop
+            if crops == 1 and size <= c:
+                xs.append(x)
+                ts.append(t.contiguous())
+                continue
+            for _ in range(crops):
+                z0, y0, x0 = (int(v) for v in rng.integers(0, size - c + 1, 3))
+                xs.append(x[z0:z0 + c, y0:y0 + c, x0:x0 + c].contiguous())
+                ts.append(t[z0:z0 + c, y0:y0 + c, x0:x0 + c].contiguous())
+    for item in args.val.split(","):
+        size, models = (int(v) for v in item.split(":"))
+        for i in range(models):
+            grad, illum, dv = pair(size, SEED_BASE[size] + counts.get(size, 0) + i)
+            val.append((net.pack_input(grad, illum), dv / dv.abs().max(), grad, illum, dv, size))
     prop.release_workspace()
     t_data = time.perf_counter() - t0
 
     def validate():
-        c_net, c_fb, loss = [], [], []
-        for x, t, grad, illum, dv in val:
+        res = {}
+        for x, t, grad, illum, dv, size in val:
             y = net.forward(x)
-            loss.append(float(torch.mean((y - t) ** 2)))
-            c_net.append(cosine(y, dv))
-            c_fb.append(cosine(fallback_direction(grad, illum), dv))
-        return float(np.mean(loss)), float(np.mean(c_net)), float(np.mean(c_fb))
+            r = res.setdefault(size, ([], [], []))
+            r[0].append(float(torch.mean((y - t) ** 2)))
+            r[1].append(cosine(y, dv))
+            r[2].append(cosine(fallback_direction(grad, illum), dv))
+        return {str(k): {"loss": float(np.mean(v[0])), "cos_net": float(np.mean(v[1])),
+                         "cos_fallback": float(np.mean(v[2]))} for k, v in res.items()}
+
+    def show(tag, h):
+        print(f"[precond] {tag}: " + "; ".join(
+            f"{k}^3 val loss {v['loss']:.4e}, cos net {v['cos_net']:.3f}, "
+            f"cos fallback {v['cos_fallback']:.3f}" for k, v in h.items()),
+            file=sys.stderr, flush=True)
+
+    def score(h):  # mean validation cosine of the network's direction over the sizes
+        return float(np.mean([v["cos_net"] for v in h.values()]))
 
     hist = [validate()]
-    print(f"[precond] before training: val loss {hist[0][0]:.4e}, cos net {hist[0][1]:.3f}, "
-          f"cos fallback {hist[0][2]:.3f}", file=sys.stderr, flush=True)
-    rng = np.random.default_rng(args.seed)
+    show("before training", hist[0])
+    best = (score(hist[0]), 0, [t.clone() for t in net.w + net.b])
     t1 = time.perf_counter()
     steps = 0
     for ep in range(args.epochs):
@@ -302,16 +350,21 @@ def main(argv=None):
             steps += 1
         torch.cuda.synchronize()
         hist.append(validate())
-        print(f"[precond] epoch {ep + 1}: val loss {hist[-1][0]:.4e}, cos net {hist[-1][1]:.3f}, "
-              f"cos fallback {hist[-1][2]:.3f} ({time.perf_counter() - t1:.1f} s)",
-              file=sys.stderr, flush=True)
+        show(f"epoch {ep + 1} ({time.perf_counter() - t1:.1f} s)", hist[-1])
+        if score(hist[-1]) > best[0]:
+            best = (score(hist[-1]), ep + 1, [t.clone() for t in net.w + net.b])
     t_train = time.perf_counter() - t1
+    for dst, src in zip(net.w + net.b, best[2]):  # keep the best epoch's weights
+        dst.copy_(src)
+    net.pack()
+    print(f"[precond] kept epoch {best[1]} (mean validation cosine {best[0]:.3f})",
+          file=sys.stderr, flush=True)
     net.save(args.out)
-    print(json.dumps({"models": args.models, "size": args.size, "epochs": args.epochs,
-                      "train_steps": steps, "data_seconds": round(t_data, 1),
-                      "train_seconds": round(t_train, 1),
-                      "val": [{"loss": h[0], "cos_net": h[1], "cos_fallback": h[2]}
-                              for h in hist]}), flush=True)
+    print(json.dumps({"data": args.data, "val": args.val, "crop": args.crop,
+                      "epochs": args.epochs, "lr": args.lr, "decay": args.decay,
+                      "samples": len(xs), "train_steps": steps, "kept_epoch": best[1],
+                      "data_seconds": round(t_data, 1), "train_seconds": round(t_train, 1),
+                      "history": hist}), flush=True)
 
 
 if __name__ == "__main__":

@@ -159,4 +159,5 @@ def test_cnn_packed_sizes_and_workspace():
     assert b.value == tiles * (27 * 256 + 16) * 4
     assert L.wfd_cnn_wgrad_workspace_bytes(128, 128, 128, C.byref(b)) == 0
     assert b.value == 1024 * (27 * 256 + 16) * 4                     # capped at 1024 blocks
-    assert L.wfd_cnn_conv(None, 8, 8, 8, 3, 16, None, None, 0, None, None, None, None) == -1
+    assert L.wfd_cnn_conv(None, 8, 8, 8, 3, 16, None, None, 0, None, None, 0, None, None,
+                          None) == -1

@@ -139,6 +139,15 @@ def test_quantized_backward_rounds_where_stored():
     assert np.allclose(dWs[3], cnn.conv3d_wgrad(acts[3], dz), rtol=0, atol=0)
 
 
+def test_untrained_output_layer_passes_the_first_channel_through():
+    rng = np.random.default_rng(11)
+    Ws, bs = cnn.init_params(12)
+    Ws[3] = np.zeros_like(Ws[3])
+    a0 = cnn.bf16(_rand(rng, 3, 5, 4, 2))
+    _, y = cnn.forward(a0, Ws, bs)
+    assert np.array_equal(y[..., 0], a0[..., 0])
+
+
 def test_pack_input_scales_each_channel():
     rng = np.random.default_rng(10)
     g, i = _rand(rng, 3, 4, 5) * 1e-20, np.abs(_rand(rng, 3, 4, 5)) * 1e3
