@@ -16,10 +16,10 @@
 //
 // Convolution as an implicit GEMM: for a row of 16 output voxels,
 // D[co][voxel] = sum_k A[co][k] X[k][voxel] with X[tap * CIN + ci][voxel] =
-// input[voxel + offset(tap)][ci].  A block stages a 66 x 4 x 4 voxel brick of
-// the input (a 64 x 2 x 2 output tile plus a one-voxel halo) in LDS; each
-// wavefront computes one 64-voxel output row as four 16 x 16 tiles with the
-// packed weights held in registers.  The data gradient is the same kernel on
+// input[voxel + offset(tap)][ci].  A block stages a 66 x 6 x 4 voxel brick of
+// the input (a 64 x 4 x 2 output tile plus a one-voxel halo) in LDS; each of
+// its 8 wavefronts computes one 64-voxel output row as four 16 x 16 tiles
+// with the packed weights held in registers.  The data gradient is the same kernel on
 // flipped, transposed weights; the weight gradient reduces over voxels with
 // the voxel index as the matrix-core K dimension.
 #include <hip/hip_runtime.h>
@@ -36,10 +36,19 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 typedef uint16_t u16x8 __attribute__((ext_vector_type(8)));
 
-constexpr int OX = 64, OY = 2, OZ = 2;  // output tile per block
-constexpr int LXB = OX + 2, LYB = OY + 2, LZB = OZ + 2;
-constexpr int BRICK = LXB * LYB * LZB;   // voxels staged per block
-constexpr int NTHR = 256;                // 4 wavefronts
+// Output tile of a block: 64 x TY x TZ voxels; the staged input brick adds a
+// one-voxel halo on every side.
+template <int TY, int TZ>
+struct Brick {
+  static constexpr int OX = 64, OY = TY, OZ = TZ;
+  static constexpr int LX = OX + 2, LY = OY + 2, LZ = OZ + 2;
+  static constexpr int VOX = LX * LY * LZ;  // voxels staged per block
+  static constexpr int ROWS = OY * OZ;      // 64-voxel output rows per block
+};
+using ConvBrick = Brick<4, 2>;   // convolutions: 512 outputs, 1584 staged voxels
+using WgradBrick = Brick<2, 2>;  // weight gradient: 256 voxels per K sweep
+constexpr int NTHR = 256;        // 4 wavefronts (weight gradient)
+constexpr int CONV_THR = 512;    // 8 wavefronts, one output row each
 
 __device__ __forceinline__ uint16_t to_bf16(float f) {
   uint32_t u = __float_as_uint(f);
@@ -52,21 +61,22 @@ __device__ __forceinline__ bool bf16_pos(uint16_t b) { return b != 0 && !(b & 0x
 constexpr int kpad(int cin) { return (27 * cin + 31) / 32 * 32; }
 
 // Block -> output tile origin.
+template <class B>
 __device__ __forceinline__ void tile_origin(int b, int nx, int ny, int &x0, int &y0, int &z0) {
-  const int tx = (nx + OX - 1) / OX, ty = (ny + OY - 1) / OY;
-  x0 = (b % tx) * OX;
-  y0 = ((b / tx) % ty) * OY;
-  z0 = (b / (tx * ty)) * OZ;
+  const int tx = (nx + B::OX - 1) / B::OX, ty = (ny + B::OY - 1) / B::OY;
+  x0 = (b % tx) * B::OX;
+  y0 = ((b / tx) % ty) * B::OY;
+  z0 = (b / (tx * ty)) * B::OZ;
 }
 
 // Stage the input brick (zero outside the volume) into LDS, channels-last.
-template <int CIN>
+template <class B, int CIN, int NT>
 __device__ __forceinline__ void load_brick(uint16_t *lds, const uint16_t *__restrict__ in, int nx,
                                            int ny, int nz, int x0, int y0, int z0) {
   if (CIN == 16) {
-    for (int q = threadIdx.x; q < BRICK * 2; q += NTHR) {
+    for (int q = threadIdx.x; q < B::VOX * 2; q += NT) {
       const int v = q >> 1, half = q & 1;
-      const int lx = v % LXB, ly = (v / LXB) % LYB, lz = v / (LXB * LYB);
+      const int lx = v % B::LX, ly = (v / B::LX) % B::LY, lz = v / (B::LX * B::LY);
       const int gx = x0 - 1 + lx, gy = y0 - 1 + ly, gz = z0 - 1 + lz;
       u32x4 d = {0u, 0u, 0u, 0u};
       if (gx >= 0 && gx < nx && gy >= 0 && gy < ny && gz >= 0 && gz < nz)
@@ -75,8 +85,8 @@ __device__ __forceinline__ void load_brick(uint16_t *lds, const uint16_t *__rest
       *reinterpret_cast<u32x4 *>(lds + v * 16 + 8 * half) = d;
     }
   } else {
-    for (int v = threadIdx.x; v < BRICK; v += NTHR) {
-      const int lx = v % LXB, ly = (v / LXB) % LYB, lz = v / (LXB * LYB);
+    for (int v = threadIdx.x; v < B::VOX; v += NT) {
+      const int lx = v % B::LX, ly = (v / B::LX) % B::LY, lz = v / (B::LX * B::LY);
       const int gx = x0 - 1 + lx, gy = y0 - 1 + ly, gz = z0 - 1 + lz;
       const bool ok = gx >= 0 && gx < nx && gy >= 0 && gy < ny && gz >= 0 && gz < nz;
       const int64_t g = ((int64_t)gz * ny + gy) * nx + gx;
@@ -87,20 +97,21 @@ __device__ __forceinline__ void load_brick(uint16_t *lds, const uint16_t *__rest
 }
 
 // LDS voxel index of output voxel (lx, ly, lz) of the tile read through tap t.
+template <class B>
 __device__ __forceinline__ int tap_voxel(int t, int lx, int ly, int lz) {
   const int dz = t / 9, dy = (t / 3) % 3, dx = t % 3;  // offsets + 1
-  return ((lz + dz) * LYB + (ly + dy)) * LXB + (lx + dx);
+  return ((lz + dz) * B::LY + (ly + dy)) * B::LX + (lx + dx);
 }
 
 // B fragment of chunk c for the lane's output voxel (lx, ly, lz) and lane group g.
-template <int CIN>
+template <class B, int CIN>
 __device__ __forceinline__ bf16x8 gather_b(const uint16_t *lds, int c, int lx, int ly, int lz,
                                            int g) {
   if (CIN == 16) {
     const int t = 2 * c + (g >> 1);
     u32x4 d = {0u, 0u, 0u, 0u};
     if (t < 27)
-      d = *reinterpret_cast<const u32x4 *>(lds + tap_voxel(t, lx, ly, lz) * 16 + 8 * (g & 1));
+      d = *reinterpret_cast<const u32x4 *>(lds + tap_voxel<B>(t, lx, ly, lz) * 16 + 8 * (g & 1));
     return __builtin_bit_cast(bf16x8, d);
   } else {
     u16x8 d;
@@ -108,7 +119,7 @@ __device__ __forceinline__ bf16x8 gather_b(const uint16_t *lds, int c, int lx, i
     for (int e = 0; e < 8; ++e) {
       const int k = 32 * c + 8 * g + e;
       const int t = k / CIN, ci = k % CIN;
-      d[e] = t < 27 ? lds[tap_voxel(t, lx, ly, lz) * CIN + ci] : (uint16_t)0;
+      d[e] = t < 27 ? lds[tap_voxel<B>(t, lx, ly, lz) * CIN + ci] : (uint16_t)0;
     }
     return __builtin_bit_cast(bf16x8, d);
   }
@@ -119,16 +130,18 @@ __device__ __forceinline__ bf16x8 gather_b(const uint16_t *lds, int c, int lx, i
 // res[voxel][res_c]; written as BF16 and/or FP32 channels-last with COUT
 // channels.  Every output voxel of the tile is computed by exactly one lane.
 template <int CIN, int COUT>
-__global__ void __launch_bounds__(NTHR)
+__global__ void __launch_bounds__(CONV_THR)
     k_conv(const uint16_t *__restrict__ in, int nx, int ny, int nz,
            const uint16_t *__restrict__ apk, const float *__restrict__ bias, int relu,
            const uint16_t *__restrict__ mask, const uint16_t *__restrict__ res, int res_c,
            uint16_t *__restrict__ out_bf, float *__restrict__ out_f) {
+  using B = ConvBrick;
   constexpr int K = kpad(CIN), NC = K / 32;
-  __shared__ __attribute__((aligned(16))) uint16_t lds[BRICK * CIN + 8];
+  constexpr int RPW = B::ROWS / (CONV_THR / 64);  // output rows per wavefront
+  __shared__ __attribute__((aligned(16))) uint16_t lds[B::VOX * CIN + 8];
   int x0, y0, z0;
-  tile_origin(blockIdx.x, nx, ny, x0, y0, z0);
-  load_brick<CIN>(lds, in, nx, ny, nz, x0, y0, z0);
+  tile_origin<B>(blockIdx.x, nx, ny, x0, y0, z0);
+  load_brick<B, CIN, CONV_THR>(lds, in, nx, ny, nz, x0, y0, z0);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int j = lane & 15, g = lane >> 4;
   // weights: A fragment of every chunk (row co = j, k = 32 c + 8 g + e)
@@ -138,48 +151,55 @@ __global__ void __launch_bounds__(NTHR)
     a[c] = __builtin_bit_cast(
         bf16x8, *reinterpret_cast<const u32x4 *>(apk + (size_t)j * K + 32 * c + 8 * g));
   __syncthreads();
-  const int ly = wave & 1, lz = wave >> 1;  // this wave's output row in the tile
-  const int gy = y0 + ly, gz = z0 + lz;
-  f32x4 acc[4];
+#pragma unroll 1
+  for (int r = 0; r < RPW; ++r) {
+    const int row = wave * RPW + r;
+    const int ly = row % B::OY, lz = row / B::OY;  // this output row in the tile
+    const int gy = y0 + ly, gz = z0 + lz;
+    f32x4 acc[4];
 #pragma unroll
-  for (int tl = 0; tl < 4; ++tl) {
-    acc[tl] = f32x4{0.f, 0.f, 0.f, 0.f};
-    const int lx = 16 * tl + j;
+    for (int tl = 0; tl < 4; ++tl) acc[tl] = f32x4{0.f, 0.f, 0.f, 0.f};
+    // chunk-major: the four tiles' fragments of one chunk are in flight together
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
-      const bf16x8 b = gather_b<CIN>(lds, c, lx, ly, lz, g);
-      acc[tl] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[c], b, acc[tl], 0, 0, 0);
-    }
-  }
-  if (gy >= ny || gz >= nz) return;
-  // epilogue: lane holds D[co = 4 g + e][voxel j] of each tile
+      bf16x8 b[4];
 #pragma unroll
-  for (int tl = 0; tl < 4; ++tl) {
-    const int gx = x0 + 16 * tl + j;
-    if (gx >= nx) continue;
-    const int64_t vox = ((int64_t)gz * ny + gy) * nx + gx;
-    float v[4];
+      for (int tl = 0; tl < 4; ++tl) b[tl] = gather_b<B, CIN>(lds, c, 16 * tl + j, ly, lz, g);
 #pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      const int co = 4 * g + e;
-      float s = acc[tl][e];
-      if (bias && co < COUT) s += bias[co];
-      if (relu) s = fmaxf(s, 0.0f);
-      if (mask && co < COUT && !bf16_pos(mask[vox * COUT + co])) s = 0.0f;
-      v[e] = s;
+      for (int tl = 0; tl < 4; ++tl)
+        acc[tl] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[c], b[tl], acc[tl], 0, 0, 0);
     }
-    if (COUT == 16) {
-      if (out_bf) {
-        const uint32_t lo = (uint32_t)to_bf16(v[0]) | ((uint32_t)to_bf16(v[1]) << 16);
-        const uint32_t hi = (uint32_t)to_bf16(v[2]) | ((uint32_t)to_bf16(v[3]) << 16);
-        *reinterpret_cast<uint2 *>(out_bf + vox * 16 + 4 * g) = make_uint2(lo, hi);
+    if (gy >= ny || gz >= nz) continue;
+    // epilogue: lane holds D[co = 4 g + e][voxel j] of each tile
+#pragma unroll
+    for (int tl = 0; tl < 4; ++tl) {
+      const int gx = x0 + 16 * tl + j;
+      if (gx >= nx) continue;
+      const int64_t vox = ((int64_t)gz * ny + gy) * nx + gx;
+      float v[4];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int co = 4 * g + e;
+        float s = acc[tl][e];
+        if (bias && co < COUT) s += bias[co];
+        if (relu) s = fmaxf(s, 0.0f);
+        if (mask && co < COUT && !bf16_pos(mask[vox * COUT + co])) s = 0.0f;
+        v[e] = s;
       }
-      if (out_f)
-        *reinterpret_cast<float4 *>(out_f + vox * 16 + 4 * g) = make_float4(v[0], v[1], v[2], v[3]);
-    } else if (g == 0) {  // single output channel: co = 0 is element 0 of group 0
-      if (res) v[0] += from_bf16(res[vox * res_c]);
-      if (out_bf) out_bf[vox] = to_bf16(v[0]);
-      if (out_f) out_f[vox] = v[0];
+      if (COUT == 16) {
+        if (out_bf) {
+          const uint32_t lo = (uint32_t)to_bf16(v[0]) | ((uint32_t)to_bf16(v[1]) << 16);
+          const uint32_t hi = (uint32_t)to_bf16(v[2]) | ((uint32_t)to_bf16(v[3]) << 16);
+          *reinterpret_cast<uint2 *>(out_bf + vox * 16 + 4 * g) = make_uint2(lo, hi);
+        }
+        if (out_f)
+          *reinterpret_cast<float4 *>(out_f + vox * 16 + 4 * g) =
+              make_float4(v[0], v[1], v[2], v[3]);
+      } else if (g == 0) {  // single output channel: co = 0 is element 0 of group 0
+        if (res) v[0] += from_bf16(res[vox * res_c]);
+        if (out_bf) out_bf[vox] = to_bf16(v[0]);
+        if (out_f) out_f[vox] = v[0];
+      }
     }
   }
 }
@@ -193,7 +213,9 @@ template <int CIN, int COUT>
 __global__ void __launch_bounds__(NTHR)
     k_wgrad(const uint16_t *__restrict__ in, const uint16_t *__restrict__ dz, int nx, int ny,
             int nz, int ntiles, float *__restrict__ partial, float *__restrict__ partial_b) {
-  __shared__ __attribute__((aligned(16))) uint16_t lds[BRICK * CIN + 8];
+  using B = WgradBrick;
+  constexpr int OX = B::OX, OY = B::OY, OZ = B::OZ;
+  __shared__ __attribute__((aligned(16))) uint16_t lds[B::VOX * CIN + 8];
   __shared__ uint16_t ldz[OX * OY * OZ * COUT];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int j = lane & 15, g = lane >> 4;
@@ -204,9 +226,9 @@ __global__ void __launch_bounds__(NTHR)
   float bsum = 0.0f;  // wave 0: sum of dz[., co = j] over the lane's voxels
   for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
     int x0, y0, z0;
-    tile_origin(tile, nx, ny, x0, y0, z0);
+    tile_origin<B>(tile, nx, ny, x0, y0, z0);
     __syncthreads();  // previous tile's reads are done
-    load_brick<CIN>(lds, in, nx, ny, nz, x0, y0, z0);
+    load_brick<B, CIN, NTHR>(lds, in, nx, ny, nz, x0, y0, z0);
     for (int q = threadIdx.x; q < OX * OY * OZ * COUT; q += NTHR) {
       const int v = q / COUT, c = q % COUT;
       const int lx = v % OX, ly = (v / OX) % OY, lz = v / (OX * OY);
@@ -238,7 +260,7 @@ __global__ void __launch_bounds__(NTHR)
         for (int e = 0; e < 8; ++e) {
           const int v = 32 * kc + 8 * g + e;
           const int lx = v % OX, ly = (v / OX) % OY, lz = v / (OX * OY);
-          bv[e] = (j < CIN) ? lds[tap_voxel(t, lx, ly, lz) * CIN + j] : (uint16_t)0;
+          bv[e] = (j < CIN) ? lds[tap_voxel<B>(t, lx, ly, lz) * CIN + j] : (uint16_t)0;
         }
         acc[i] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A, __builtin_bit_cast(bf16x8, bv), acc[i],
                                                         0, 0, 0);
@@ -262,19 +284,21 @@ __global__ void __launch_bounds__(NTHR)
 }
 
 // dW[tap][ci][co] = sum over blocks of partial[block][tap][co][ci], and
-// db[co] = sum over blocks of partial_b[block][co] (fixed order).
+// db[co] = sum over blocks of partial_b[block][co] (fixed order).  Thread i
+// owns partial entry i of every block, so each block's partial is read
+// contiguously across threads.
 __global__ void k_wgrad_reduce(const float *__restrict__ partial,
                                const float *__restrict__ partial_b, int nblocks, int cin,
                                int cout, float *__restrict__ dw, float *__restrict__ db) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  const int n = 27 * cin * cout;
-  if (i < n) {
-    const int co = i % cout, ci = (i / cout) % cin, t = i / (cout * cin);
+  if (i < 27 * 256) {
+    const int t = i / 256, co = (i / 16) % 16, ci = i % 16;
+    if (co >= cout || ci >= cin) return;
     float s = 0.0f;
-    for (int b = 0; b < nblocks; ++b) s += partial[((size_t)b * 27 + t) * 256 + co * 16 + ci];
-    dw[i] = s;
-  } else if (i < n + cout && db) {
-    const int co = i - n;
+    for (int b = 0; b < nblocks; ++b) s += partial[(size_t)b * 27 * 256 + i];
+    dw[(t * cin + ci) * cout + co] = s;
+  } else if (i < 27 * 256 + cout && db) {
+    const int co = i - 27 * 256;
     float s = 0.0f;
     for (int b = 0; b < nblocks; ++b) s += partial_b[(size_t)b * 16 + co];
     db[co] = s;
@@ -401,19 +425,20 @@ __global__ void k_pack_input(const float *__restrict__ grad, const float *__rest
   }
 }
 
-int conv_blocks(int nx, int ny, int nz) {
-  return ((nx + OX - 1) / OX) * ((ny + OY - 1) / OY) * ((nz + OZ - 1) / OZ);
+template <class B>
+int tile_count(int nx, int ny, int nz) {
+  return ((nx + B::OX - 1) / B::OX) * ((ny + B::OY - 1) / B::OY) * ((nz + B::OZ - 1) / B::OZ);
 }
 
 }  // namespace
 
-int cnn_conv_blocks(int nx, int ny, int nz) { return conv_blocks(nx, ny, nz); }
+int cnn_conv_blocks(int nx, int ny, int nz) { return tile_count<ConvBrick>(nx, ny, nz); }
 
 hipError_t launch_conv(int cin, int cout, const uint16_t *in, int nx, int ny, int nz,
                        const uint16_t *apk, const float *bias, int relu, const uint16_t *mask,
                        const uint16_t *res, int res_c, uint16_t *out_bf, float *out_f,
                        hipStream_t stream) {
-  const dim3 grid(conv_blocks(nx, ny, nz)), block(NTHR);
+  const dim3 grid(tile_count<ConvBrick>(nx, ny, nz)), block(CONV_THR);
 #define WFD_CONV(CI, CO)                                                                      \
   hipLaunchKernelGGL((k_conv<CI, CO>), grid, block, 0, stream, in, nx, ny, nz, apk, bias, relu, \
                      mask, res, res_c, out_bf, out_f)
@@ -427,7 +452,7 @@ hipError_t launch_conv(int cin, int cout, const uint16_t *in, int nx, int ny, in
 }
 
 int cnn_wgrad_blocks(int nx, int ny, int nz) {
-  const int tiles = conv_blocks(nx, ny, nz);
+  const int tiles = tile_count<WgradBrick>(nx, ny, nz);
   return tiles < 1024 ? tiles : 1024;
 }
 
@@ -437,7 +462,7 @@ size_t cnn_wgrad_workspace_floats(int nx, int ny, int nz) {
 
 hipError_t launch_wgrad(int cin, int cout, const uint16_t *in, const uint16_t *dz, int nx, int ny,
                         int nz, float *work, float *dw, float *db, hipStream_t stream) {
-  const int ntiles = conv_blocks(nx, ny, nz);
+  const int ntiles = tile_count<WgradBrick>(nx, ny, nz);
   const int nb = cnn_wgrad_blocks(nx, ny, nz);
   float *partial = work, *partial_b = work + (size_t)nb * 27 * 256;
 #define WFD_WG(CI, CO)                                                                        \
@@ -450,7 +475,7 @@ hipError_t launch_wgrad(int cin, int cout, const uint16_t *in, const uint16_t *d
 #undef WFD_WG
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  const int n = 27 * cin * cout + cout;
+  const int n = 27 * 256 + cout;
   hipLaunchKernelGGL(k_wgrad_reduce, dim3((n + 255) / 256), dim3(256), 0, stream, partial,
                      partial_b, nb, cin, cout, dw, db);
   return hipGetLastError();
