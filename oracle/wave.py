@@ -42,13 +42,21 @@ R17 the gradient is taken with respect to velocity: dJ/dv = 2 g / v with
     g = k dJ/dk and k = dt^2 v^2 (MultiplyAdjoint read as this chain rule).
 R18 gradient cells in the sponge are folded back into the model-edge cells
     they replicate (transpose of R4).
+R23 free surface (§2.1, an option that lets the surface reflect waves): a
+    pressure-release surface at the top model plane zs.  Planes above it are
+    read as the antisymmetric image, w(zs - k) = -w(zs + k) (the image
+    method), sqrt(rho) is mirrored evenly about it for m^2, the planes at
+    and above it are held at zero, and there is no sponge on that side.  The
+    mirrored L is still symmetric, so the adjoint derivation below holds.
 
 Adjoint derivation used here (written out so that it can be checked by eye).
 Forward, with A = 2 I - K_m + K L, K = diag(k), K_m = diag(k m^2):
     w^{n+1} = G A w^n - G^2 w^{n-1} + G b_n,          w^0 = w^{-1} = 0.
 With e_j = dJ/dw^j (receiver residuals) the Lagrange multipliers obey
     lambda^j = e_j + A^T G lambda^{j+1} - G^2 lambda^{j+2},
-and L is symmetric (zero ghosts), so A^T = 2 I - K_m + L K.  Substituting
+and L is symmetric (zero ghosts, or the free surface's antisymmetric image:
+its (z, z') entry is c(z' - z) - c(2 zs - z - z'), symmetric in z and z'),
+so A^T = 2 I - K_m + L K.  Substituting
 psi^j = K G lambda^j gives exactly the forward recursion again:
     psi^j = G (2 psi^{j+1} - K_m psi^{j+1} + K L psi^{j+1} + K e_j - G psi^{j+2}).
 Since dA/dk = diag(L w - m^2 w), the gradient is
@@ -87,10 +95,16 @@ class Grid:
     border: int = 0
     dt: float = 1.0e-3
     nt: int = 1
+    free_surface: bool = False   # pressure-release surface at the top model plane (R23)
 
     @property
     def h(self) -> Tuple[float, float, float]:
         return (self.dx, self.dy, self.dz)
+
+    @property
+    def zs(self) -> Optional[int]:
+        """Padded z index of the free surface (the top model plane), or None."""
+        return self.border if self.free_surface else None
 
     @property
     def padded_shape(self) -> Tuple[int, int, int]:
@@ -101,12 +115,22 @@ class Grid:
 # ----------------------------------------------------------------------------
 # spatial operators
 # ----------------------------------------------------------------------------
-def second_derivative(u: np.ndarray, axis: int, h: float, periodic: bool = False) -> np.ndarray:
-    """8th-order central d^2u/dx_axis^2 with zero ghosts (R5) or periodic wrap."""
+def second_derivative(u: np.ndarray, axis: int, h: float, periodic: bool = False,
+                      mirror_zs: Optional[int] = None) -> np.ndarray:
+    """8th-order central d^2u/dx_axis^2 with zero ghosts (R5) or periodic wrap.
+    With mirror_zs (axis 0 only), every plane z < mirror_zs, including those
+    above the array, reads -u[2 mirror_zs - z] (zero past the array's end):
+    the antisymmetric image of a pressure-release surface at plane mirror_zs
+    (R23)."""
     pad = [(0, 0)] * u.ndim
     pad[axis] = (RADIUS, RADIUS)
     up = np.pad(u, pad, mode="wrap" if periodic else "constant")
     n = u.shape[axis]
+    if mirror_zs is not None and axis == 0:
+        for e in range(0, mirror_zs + RADIUS):   # extended index e <-> plane z = e - RADIUS
+            z = e - RADIUS
+            zm = 2 * mirror_zs - z
+            up[e] = -u[zm] if zm < n else 0.0
 
     def shifted(off):
         sl = [slice(None)] * u.ndim
@@ -119,12 +143,19 @@ def second_derivative(u: np.ndarray, axis: int, h: float, periodic: bool = False
     return out / (h * h)
 
 
-def laplacian(u: np.ndarray, h: Sequence[float], periodic: bool = False) -> np.ndarray:
+def laplacian(u: np.ndarray, h: Sequence[float], periodic: bool = False,
+              mirror_zs: Optional[int] = None) -> np.ndarray:
     """L u = d2/dx2 + d2/dy2 + d2/dz2 on a [z][y][x] array; h = (dx, dy, dz)."""
     dx, dy, dz = h
     return (second_derivative(u, 2, dx, periodic)
             + second_derivative(u, 1, dy, periodic)
-            + second_derivative(u, 0, dz, periodic))
+            + second_derivative(u, 0, dz, periodic, mirror_zs))
+
+
+def grid_laplacian(grid: "Grid", u: np.ndarray, periodic: bool = False) -> np.ndarray:
+    """L on the padded grid with the grid's top boundary (zero ghosts, or the
+    free surface's antisymmetric image)."""
+    return laplacian(u, grid.h, periodic, grid.zs)
 
 
 # ----------------------------------------------------------------------------
@@ -159,19 +190,21 @@ def fold_padding(gp: np.ndarray, n: int) -> np.ndarray:
     return out
 
 
-def sponge_profile(n: int, border: int, a: float = SPONGE_A) -> np.ndarray:
+def sponge_profile(n: int, border: int, a: float = SPONGE_A, free_top: bool = False) -> np.ndarray:
     """Per-axis damping g[i], i over the padded axis (R3): 1 inside the model,
-    exp(-(a * delta / N)^2) at distance delta into the sponge."""
+    exp(-(a * delta / N)^2) at distance delta into the sponge; with free_top
+    no damping before the model (the free surface's side, R23)."""
     total = n + 2 * border
     if border == 0:
         return np.ones(total)
     i = np.arange(total)
-    delta = np.maximum.reduce([border - i, np.zeros(total, dtype=np.int64), i - (border + n - 1)])
+    before = np.zeros(total, dtype=np.int64) if free_top else border - i
+    delta = np.maximum.reduce([before, np.zeros(total, dtype=np.int64), i - (border + n - 1)])
     return np.exp(-(a * delta / border) ** 2)
 
 
 def sponge(grid: Grid) -> np.ndarray:
-    gz = sponge_profile(grid.nz, grid.border)
+    gz = sponge_profile(grid.nz, grid.border, free_top=grid.free_surface)
     gy = sponge_profile(grid.ny, grid.border)
     gx = sponge_profile(grid.nx, grid.border)
     return gz[:, None, None] * gy[None, :, None] * gx[None, None, :]
@@ -197,6 +230,10 @@ def coefficients(grid: Grid, vel: np.ndarray, rho: Optional[np.ndarray] = None) 
         s = np.ones_like(k)
     else:
         s_ext = np.sqrt(pad_edge(rho, N + RADIUS))
+        if grid.free_surface:  # sqrt(rho) mirrored (even) about the surface, R23
+            P = N + RADIUS
+            for e in range(P):
+                s_ext[e] = s_ext[P + min(P - e, grid.nz - 1)]
         lap_s = laplacian(s_ext, grid.h)
         core = (slice(RADIUS, -RADIUS),) * 3
         s = s_ext[core]
@@ -236,11 +273,15 @@ def cfl_ratio(grid: Grid, vmax: float, m2max: float = 0.0) -> float:
 # ----------------------------------------------------------------------------
 def step(c: Coefficients, grid: Grid, w: np.ndarray, w_prev: np.ndarray,
          inj: Optional[np.ndarray] = None, periodic: bool = False) -> np.ndarray:
-    """One leapfrog step: G (2 w - k m2 w + k L w + inj - G w_prev)."""
-    acc = 2.0 * w - c.k * c.m2 * w + c.k * laplacian(w, grid.h, periodic)
+    """One leapfrog step: G (2 w - k m2 w + k L w + inj - G w_prev); with a
+    free surface the planes at and above it are held at zero (R23)."""
+    acc = 2.0 * w - c.k * c.m2 * w + c.k * grid_laplacian(grid, w, periodic)
     if inj is not None:
         acc = acc + inj
-    return c.G * (acc - c.G * w_prev)
+    out = c.G * (acc - c.G * w_prev)
+    if grid.free_surface:
+        out[:grid.zs + 1] = 0.0
+    return out
 
 
 @dataclass
@@ -412,7 +453,7 @@ def gradient(grid: Grid, vel, rho, wavelet, src_xyz, rec_xyz, dobs, *,
             if m0 not in seg_states:
                 seg_states = {m0: _segment(c, grid, geo, f, keep, m0, min(m0 + K, nt + 1))}
             wm = seg_states[m0][m - m0]
-            g += psi1 * (laplacian(wm, grid.h) - c.m2 * wm)
+            g += psi1 * (grid_laplacian(grid, wm) - c.m2 * wm)
             if illum is not None:
                 illum += wm * wm
         if psi_src is not None:
@@ -455,7 +496,7 @@ def energy(c: Coefficients, grid: Grid, w_new: np.ndarray, w: np.ndarray) -> flo
     + 1/2 sum w^{n+1} (-L + m^2) w^n  (conserved without sponge and source)."""
     dw = w_new - w
     kin = 0.5 * np.sum(dw * dw / c.k)
-    pot = 0.5 * np.sum(w_new * (-laplacian(w, grid.h) + c.m2 * w))
+    pot = 0.5 * np.sum(w_new * (-grid_laplacian(grid, w) + c.m2 * w))
     return float(kin + pot)
 
 

@@ -494,3 +494,57 @@ def test_paper_example_config_fixture():
     assert len(w.sources) == cfg["n_src"]
     assert abs(float(np.max(w.wavelet)) - cfg["amplitude"]) <= 1e-3 * cfg["amplitude"]
     assert int(cfg["stencil"]) == wave.RADIUS      # 'stencil = 4': radius-4, eighth order
+
+
+# ---------------------------------------------------------------------------
+# 11. free surface (R23): the discrete image principle, and the adjoint
+# ---------------------------------------------------------------------------
+def _mirror_case(nh=9, n=10, border=4, nt=60, seed=31):
+    """A half-space model with a free surface and the full-space model made by
+    mirroring it evenly about its top plane (full plane c = nh - 1)."""
+    h = 10.0
+    vh = seisgen.layered_model(seed, (n, n, nh), 0.05).astype(np.float64)
+    rh = seisgen.gardner_density(vh).astype(np.float64)
+    c = nh - 1
+    idx = np.abs(np.arange(2 * nh - 1) - c)           # full plane -> half plane
+    vf, rf = vh[idx], rh[idx]
+    dt = 0.4 * h / vh.max()
+    gh = oracle.Grid(n, n, nh, h, h, h, border=border, dt=dt, nt=nt, free_surface=True)
+    gf = oracle.Grid(n, n, 2 * nh - 1, h, h, h, oz=-c * h, border=border, dt=dt, nt=nt)
+    return gh, gf, vh, rh, vf, rf
+
+
+def test_free_surface_equals_antisymmetric_image_source():
+    """With a free surface the half-space solution equals, on every receiver,
+    the full-space solution of the mirrored model driven by the source minus
+    its mirror image (the field is odd about the surface)."""
+    gh, gf, vh, rh, vf, rf = _mirror_case()
+    rng = np.random.default_rng(5)
+    f = rng.standard_normal(gh.nt)
+    src = [45.0, 55.0, 30.0]
+    img = [45.0, 55.0, -30.0]
+    rec = [[15.0, 25.0, 10.0], [75.0, 35.0, 50.0], [45.0, 55.0, 80.0], [25.0, 85.0, 0.0]]
+    half = oracle.forward(gh, vh, rh, f, src, rec, fp32_inputs=False).seis
+    full = (oracle.forward(gf, vf, rf, f, src, rec, fp32_inputs=False).seis
+            - oracle.forward(gf, vf, rf, f, img, rec, fp32_inputs=False).seis)
+    assert np.max(np.abs(half[:3])) > 0
+    assert np.max(np.abs(half - full)) <= 1e-12 * np.max(np.abs(full))
+    assert np.all(half[3] == 0.0)                     # a receiver on the surface
+    # without the surface the half-space result differs (the pin is not vacuous)
+    gn = oracle.Grid(**{**gh.__dict__, "free_surface": False})
+    none = oracle.forward(gn, vh, rh, f, src, rec, fp32_inputs=False).seis
+    assert np.max(np.abs(none[:3] - full[:3])) > 1e-2 * np.max(np.abs(full))
+
+
+def test_free_surface_adjoint_dot_product():
+    g, vel, rho, src, rec = _small_vd_case()
+    g = oracle.Grid(**{**g.__dict__, "free_surface": True})
+    rng = np.random.default_rng(12)
+    f = rng.standard_normal(g.nt)
+    dp = rng.standard_normal((len(rec), g.nt))
+    Ff = oracle.forward(g, vel, rho, f, src, rec, fp32_inputs=False).seis
+    Ftd = oracle.adjoint_source_transpose(g, vel, rho, src, rec, dp, fp32_inputs=False)
+    lhs = float(np.sum(Ff * dp))
+    rhs = float(np.dot(f, Ftd))
+    assert np.max(np.abs(Ff)) > 0
+    assert abs(lhs - rhs) <= 1e-13 * max(abs(lhs), np.linalg.norm(Ff) * np.linalg.norm(dp))
