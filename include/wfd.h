@@ -71,6 +71,11 @@ typedef struct {
   int32_t border;     /* sponge cells on every face (>= 0; 0 = no sponge)      */
   double dt;          /* time step, s (> 0)                                    */
   int32_t nt;         /* number of time steps (>= 1)                           */
+  int32_t free_surface; /* 1: pressure-release free surface at the top model
+                           plane (z index 0; the image method: planes above it
+                           read as the negated mirror, sqrt(rho) mirrored
+                           evenly, no sponge on that side; the field is zero
+                           on and above it); 0: sponge on all six faces      */
 } wfd_grid;
 
 /* Forward-wavefield management for the gradient (§2.1 "three options"; the
@@ -335,6 +340,37 @@ wfd_status wfd_cnn_adam(float *w_dev, const float *g_dev, float *m_dev, float *v
  * unscaled (with max|illum| = 0, c = grad).  eps > 0. */
 wfd_status wfd_cnn_pack_input(const float *grad_dev, const float *illum_dev, int64_t n, float eps,
                               uint16_t *out_dev, void *work_dev, size_t work_bytes, void *stream);
+
+/* ---- gradient smoothing (GradientPreconditioning, §2.2) --------------------
+ *
+ * The paper smooths every gradient with a Bessel or a Laplace filter of
+ * lengths l_x, l_y, l_z (default twice the spacing).  Readings:
+ *   WFD_SMOOTH_LAPLACE  separable exponential kernel: along x, then y, then
+ *                       z, u = T^-1 g with T = [(1 + a^2) I - a (S + S^-1)]
+ *                       / (1 - a)^2, a = exp(-h / l), zero-flux (mirror) ends;
+ *                       its interior impulse response is (1-a)/(1+a) a^|n|;
+ *   WFD_SMOOTH_BESSEL   u = B^-1 g, B = I - sum_d l_d^2 D_dd with 3-point
+ *                       second differences and zero-flux ends (a K_1/2 Bessel
+ *                       kernel), by conjugate gradients to a relative residual
+ *                       tol (at most max_iter iterations; WFD_E_RANGE if not
+ *                       reached).
+ * Both keep constants.  A length of 0 leaves that axis unsmoothed (Laplace)
+ * or drops its term (Bessel). */
+enum { WFD_SMOOTH_LAPLACE = 1, WFD_SMOOTH_BESSEL = 2 };
+
+/* Workspace bytes of wfd_smooth. */
+wfd_status wfd_smooth_workspace_bytes(int32_t mode, int32_t nx, int32_t ny, int32_t nz,
+                                      size_t *bytes);
+
+/* Smooth in_dev [nz][ny][nx] FP32 into out_dev (may equal in_dev for the
+ * Laplace filter; must differ for Bessel).  lengths and spacing are (x, y, z)
+ * in metres.  Enqueued on `stream` (a hipStream_t); returns after the stream
+ * has drained (the Bessel solver reads its inner products on the host).
+ * iterations_or_null receives the conjugate-gradient iteration count. */
+wfd_status wfd_smooth(int32_t mode, const float *in_dev, float *out_dev, int32_t nx, int32_t ny,
+                      int32_t nz, const double lengths[3], const double spacing[3], double tol,
+                      int32_t max_iter, void *work_dev, size_t work_bytes,
+                      int32_t *iterations_or_null, void *stream);
 
 /* ---- measurement ---------------------------------------------------------- */
 

@@ -20,13 +20,15 @@ CKPT_FULL = 0
 CKPT_REVOLVE = 1
 K_FORWARD, K_ADJOINT, K_OTHER = 0, 1, 2
 CNN_REDUCE_BYTES = 8192
+SMOOTH_LAPLACE, SMOOTH_BESSEL = 1, 2
 
 
 class wfd_grid(C.Structure):
     _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32),
                 ("dx", C.c_double), ("dy", C.c_double), ("dz", C.c_double),
                 ("ox", C.c_double), ("oy", C.c_double), ("oz", C.c_double),
-                ("border", C.c_int32), ("dt", C.c_double), ("nt", C.c_int32)]
+                ("border", C.c_int32), ("dt", C.c_double), ("nt", C.c_int32),
+                ("free_surface", C.c_int32)]
 
 
 class wfd_ckpt(C.Structure):
@@ -82,6 +84,10 @@ _SIGS = {
     "wfd_cnn_adam": (C.c_int, [_P, _P, _P, _P, C.c_int32, C.c_float, C.c_float, C.c_float,
                                C.c_float, C.c_int32, _P]),
     "wfd_cnn_pack_input": (C.c_int, [_P, _P, C.c_int64, C.c_float, _P, _P, C.c_size_t, _P]),
+    "wfd_smooth_workspace_bytes": (C.c_int, [C.c_int32, C.c_int32, C.c_int32, C.c_int32,
+                                             C.POINTER(C.c_size_t)]),
+    "wfd_smooth": (C.c_int, [C.c_int32, _P, _P, C.c_int32, C.c_int32, C.c_int32, _D3, _D3,
+                             C.c_double, C.c_int32, _P, C.c_size_t, C.POINTER(C.c_int32), _P]),
     "wfd_map_position": (C.c_int, [C.POINTER(wfd_grid), _D3, C.POINTER(C.c_int32)]),
     "wfd_cfl_ratio": (C.c_int, [C.POINTER(wfd_grid), C.c_double, C.c_double, _D3]),
     "wfd_checkpoint_plan": (C.c_int, [C.c_int32, C.c_int32, C.POINTER(C.c_int32), C.c_int64,

@@ -32,11 +32,12 @@ class GridSpec:
     border: int = 0
     dt: float = 1.0e-3
     nt: int = 1
+    free_surface: bool = False
 
     def c(self) -> wfd_grid:
         return wfd_grid(int(self.nx), int(self.ny), int(self.nz), float(self.dx), float(self.dy),
                         float(self.dz), float(self.ox), float(self.oy), float(self.oz),
-                        int(self.border), float(self.dt), int(self.nt))
+                        int(self.border), float(self.dt), int(self.nt), int(bool(self.free_surface)))
 
     @property
     def padded_shape(self) -> Tuple[int, int, int]:
@@ -49,7 +50,7 @@ def _grid(g) -> GridSpec:
         return g
     if isinstance(g, dict):
         return GridSpec(**g)
-    return GridSpec(**{k: getattr(g, k) for k in GridSpec.__dataclass_fields__})
+    return GridSpec(**{k: getattr(g, k) for k in GridSpec.__dataclass_fields__ if hasattr(g, k)})
 
 
 def _xyz(a) -> np.ndarray:
@@ -106,6 +107,30 @@ def checkpoint_plan(nt: int, n_snapshots: int):
                                 buf.ctypes.data_as(C.POINTER(C.c_int32)), na.value,
                                 C.byref(na), C.byref(ns)))
     return buf, ns.value
+
+
+def smooth(x, mode: str, lengths, spacing, *, tol: float = 1e-6, max_iter: int = 500, out=None):
+    """The paper's gradient smoothing (GradientPreconditioning) of a device
+    volume x [nz][ny][nx] FP32: mode "laplace" or "bessel", lengths and
+    spacing (x, y, z) in metres.  Returns (smoothed volume, CG iterations)."""
+    import torch
+    L = _lib.lib()
+    m = {"laplace": _lib.SMOOTH_LAPLACE, "bessel": _lib.SMOOTH_BESSEL}[mode]
+    if not (x.is_cuda and x.dtype == torch.float32 and x.is_contiguous() and x.dim() == 3):
+        raise ValueError("x must be a contiguous 3-D float32 CUDA tensor")
+    nz, ny, nx = x.shape
+    if out is None:
+        out = torch.empty_like(x)
+    nb = C.c_size_t()
+    check(L.wfd_smooth_workspace_bytes(m, nx, ny, nz, C.byref(nb)))
+    work = torch.empty(nb.value, dtype=torch.uint8, device=x.device)
+    lens = np.ascontiguousarray(lengths, dtype=np.float64)
+    hs = np.ascontiguousarray(spacing, dtype=np.float64)
+    it = C.c_int32()
+    check(L.wfd_smooth(m, _ptr(x), _ptr(out), nx, ny, nz, _dptr(lens), _dptr(hs), float(tol),
+                       int(max_iter), _ptr(work), nb.value, C.byref(it),
+                       C.c_void_p(torch.cuda.current_stream(x.device).cuda_stream)))
+    return out, it.value
 
 
 def model_bytes(grid, variable_density: bool) -> int:

@@ -174,6 +174,8 @@ wfd_status check_grid(const wfd_grid *g) {
   if (g->border < 0) return fail(WFD_E_ARG, "border must be >= 0 (got %d)", g->border);
   if (!(g->dt > 0) || !std::isfinite(g->dt)) return fail(WFD_E_ARG, "dt must be finite and > 0");
   if (g->nt < 1) return fail(WFD_E_ARG, "nt must be >= 1 (got %d)", g->nt);
+  if (g->free_surface != 0 && g->free_surface != 1)
+    return fail(WFD_E_ARG, "free_surface must be 0 or 1 (got %d)", g->free_surface);
   const int64_t Nx = (int64_t)g->nx + 2 * g->border, Ny = (int64_t)g->ny + 2 * g->border,
                 Nz = (int64_t)g->nz + 2 * g->border;
   if (Nx > (1 << 24) || Ny > (1 << 24) || Nz > (1 << 24) || Nx * Ny > (int64_t(1) << 30))
@@ -205,11 +207,14 @@ ModelLayout model_layout(const wfd_grid &g, bool vd, void *base) {
   return L;
 }
 
-std::vector<float> sponge_table(int n, int border) {
+// Sponge profile of one padded axis; free_top: no damping before the model
+// (the side of a free surface).
+std::vector<float> sponge_table(int n, int border, bool free_top = false) {
   std::vector<float> t(n + 2 * border, 1.0f);
   if (border == 0) return t;
   for (int i = 0; i < n + 2 * border; ++i) {
-    int d = std::max(std::max(border - i, 0), i - (border + n - 1));
+    const int before = free_top ? 0 : border - i;
+    int d = std::max(std::max(before, 0), i - (border + n - 1));
     const double r = 0.4 * (double)d / (double)border;
     t[i] = (float)std::exp(-r * r);
   }
@@ -296,6 +301,7 @@ wfd::StepGrid step_grid(const wfd_ctx *c) {
   g.gz = c->gz;
   g.k = c->k;
   g.m2 = c->vd ? c->m2 : nullptr;
+  g.zs = c->grid.free_surface ? c->grid.border : wfd::kNoSurface;
   return g;
 }
 
@@ -534,7 +540,7 @@ wfd_status wfd_set_model(wfd_ctx *c, const wfd_grid *grid, const float *vel,
   }
   std::vector<float> tx = sponge_table(grid->nx, grid->border);
   std::vector<float> ty = sponge_table(grid->ny, grid->border);
-  std::vector<float> tz = sponge_table(grid->nz, grid->border);
+  std::vector<float> tz = sponge_table(grid->nz, grid->border, grid->free_surface != 0);
   HIP_TRY(hipMemcpyAsync(c->gx, tx.data(), tx.size() * 4, hipMemcpyHostToDevice, c->stream));
   HIP_TRY(hipMemcpyAsync(c->gy, ty.data(), ty.size() * 4, hipMemcpyHostToDevice, c->stream));
   HIP_TRY(hipMemcpyAsync(c->gz, tz.data(), tz.size() * 4, hipMemcpyHostToDevice, c->stream));
@@ -547,7 +553,7 @@ wfd_status wfd_set_model(wfd_ctx *c, const wfd_grid *grid, const float *vel,
   if (vd) {
     Timed t(c, WFD_K_OTHER);
     HIP_TRY(wfd::launch_precompute_m2(rho, grid->nx, grid->ny, grid->nz, grid->border,
-                                      1.0 / (grid->dx * grid->dx), 1.0 / (grid->dy * grid->dy),
+                                      grid->free_surface, 1.0 / (grid->dx * grid->dx), 1.0 / (grid->dy * grid->dy),
                                       1.0 / (grid->dz * grid->dz), c->m2, c->pitch, c->Ny, c->Nz,
                                       c->sqrt_rho, L.part_m, kReducePartials, c->stream));
   }
@@ -1299,5 +1305,138 @@ wfd_status wfd_cnn_pack_input(const float *grad, const float *illum, int64_t n, 
   return WFD_OK;
 }
 
+// ---- gradient smoothing ------------------------------------------------------
+
+namespace {
+constexpr int kSmoothPartials = 512;
+
+size_t smooth_bytes(int mode, int nx, int ny, int nz) {
+  const size_t vol = (size_t)nx * ny * nz;
+  if (mode == WFD_SMOOTH_LAPLACE) return align_up(2 * (size_t)(nx + ny + nz) * sizeof(double));
+  return align_up(3 * vol * sizeof(float)) + align_up(kSmoothPartials * sizeof(double));
+}
+
+double sum_partials_host(const double *dev, std::vector<double> &host, hipStream_t s,
+                         hipError_t &err) {
+  err = hipMemcpyAsync(host.data(), dev, host.size() * sizeof(double), hipMemcpyDeviceToHost, s);
+  if (err == hipSuccess) err = hipStreamSynchronize(s);
+  double t = 0.0;
+  for (double v : host) t += v;
+  return t;
+}
+}  // namespace
+
+wfd_status wfd_smooth_workspace_bytes(int32_t mode, int32_t nx, int32_t ny, int32_t nz,
+                                      size_t *bytes) {
+  if (!bytes) return fail(WFD_E_ARG, "NULL argument");
+  if (mode != WFD_SMOOTH_LAPLACE && mode != WFD_SMOOTH_BESSEL)
+    return fail(WFD_E_ARG, "unknown smoothing mode %d", mode);
+  if (nx < 1 || ny < 1 || nz < 1) return fail(WFD_E_ARG, "empty volume");
+  *bytes = smooth_bytes(mode, nx, ny, nz);
+  return WFD_OK;
+}
+
+wfd_status wfd_smooth(int32_t mode, const float *in, float *out, int32_t nx, int32_t ny,
+                      int32_t nz, const double lengths[3], const double spacing[3], double tol,
+                      int32_t max_iter, void *work, size_t work_bytes, int32_t *iterations,
+                      void *stream_) {
+  if (mode != WFD_SMOOTH_LAPLACE && mode != WFD_SMOOTH_BESSEL)
+    return fail(WFD_E_ARG, "unknown smoothing mode %d", mode);
+  if (!in || !out || !lengths || !spacing || !work) return fail(WFD_E_ARG, "NULL argument");
+  if (nx < 1 || ny < 1 || nz < 1) return fail(WFD_E_ARG, "empty volume");
+  for (int d = 0; d < 3; ++d) {
+    if (!(lengths[d] >= 0.0) || !std::isfinite(lengths[d]))
+      return fail(WFD_E_ARG, "lengths must be finite and >= 0");
+    if (!(spacing[d] > 0.0) || !std::isfinite(spacing[d]))
+      return fail(WFD_E_ARG, "spacing must be finite and > 0");
+  }
+  const size_t need = smooth_bytes(mode, nx, ny, nz);
+  if (work_bytes < need)
+    return fail(WFD_E_NOMEM, "workspace has %zu bytes, %zu needed", work_bytes, need);
+  hipStream_t st = (hipStream_t)stream_;
+  const int64_t n = (int64_t)nx * ny * nz;
+  if (mode == WFD_SMOOTH_LAPLACE) {
+    if (out != in) HIP_TRY(hipMemcpyAsync(out, in, n * sizeof(float), hipMemcpyDeviceToDevice, st));
+    const int len[3] = {nx, ny, nz};
+    const int64_t lines[3] = {(int64_t)ny * nz, (int64_t)nx * nz, (int64_t)nx * ny};
+    double *dev = static_cast<double *>(work);
+    std::vector<double> host(2 * (size_t)(nx + ny + nz), 0.0);
+    size_t off = 0;
+    double a_of[3];
+    size_t off_of[3];
+    for (int d = 0; d < 3; ++d) {
+      const int m = len[d];
+      const double a = lengths[d] > 0.0 ? std::exp(-spacing[d] / lengths[d]) : 0.0;
+      a_of[d] = a;
+      off_of[d] = off;
+      double *cp = host.data() + off, *inv = host.data() + off + m;
+      for (int i = 0; i < m; ++i) {
+        double b = 1.0 + a * a;
+        if (m == 1) b = (1.0 - a) * (1.0 - a);
+        else if (i == 0 || i == m - 1) b = 1.0 + a * a - a;  // zero-flux ends
+        const double den = i == 0 ? b : b + a * cp[i - 1];
+        inv[i] = 1.0 / den;
+        cp[i] = -a / den;
+      }
+      off += 2 * (size_t)m;
+    }
+    HIP_TRY(hipMemcpyAsync(dev, host.data(), host.size() * sizeof(double), hipMemcpyHostToDevice,
+                           st));
+    for (int d = 0; d < 3; ++d) {
+      if (lengths[d] <= 0.0) continue;
+      const double a = a_of[d];
+      HIP_TRY(wfd::launch_tri_lines(out, d, len[d], lines[d], nx, ny, dev + off_of[d],
+                                    dev + off_of[d] + len[d], a, (1.0 - a) * (1.0 - a), st));
+    }
+    HIP_TRY(hipStreamSynchronize(st));  // the host coefficients may go now
+    if (iterations) *iterations = 0;
+    return WFD_OK;
+  }
+  // Bessel: conjugate gradients on B u = g from u = 0
+  if (out == in) return fail(WFD_E_ARG, "the Bessel filter needs out != in");
+  if (max_iter < 1) return fail(WFD_E_ARG, "max_iter must be >= 1");
+  if (!(tol > 0.0)) return fail(WFD_E_ARG, "tol must be > 0");
+  char *base = static_cast<char *>(work);
+  float *r = reinterpret_cast<float *>(base);
+  float *p = r + n;
+  float *ap = p + n;
+  double *part = reinterpret_cast<double *>(base + align_up(3 * (size_t)n * sizeof(float)));
+  const float cx = (float)(lengths[0] * lengths[0] / (spacing[0] * spacing[0]));
+  const float cy = (float)(lengths[1] * lengths[1] / (spacing[1] * spacing[1]));
+  const float cz = (float)(lengths[2] * lengths[2] / (spacing[2] * spacing[2]));
+  std::vector<double> hp(kSmoothPartials);
+  hipError_t e = hipSuccess;
+  HIP_TRY(wfd::launch_cg_start(in, r, out, n, part, kSmoothPartials, st));
+  const double gg = sum_partials_host(part, hp, st, e);
+  if (e != hipSuccess) return fail(WFD_E_HIP, "smoothing: %s", hipGetErrorString(e));
+  if (iterations) *iterations = 0;
+  if (gg == 0.0) return WFD_OK;
+  HIP_TRY(wfd::launch_cg_direction(p, r, n, 0.0f, kSmoothPartials, st));
+  double rr = gg;
+  int it = 0;
+  while (it < max_iter && rr > tol * tol * gg) {
+    HIP_TRY(wfd::launch_bessel_apply(p, ap, nx, ny, nz, cx, cy, cz, part, kSmoothPartials, st));
+    const double pap = sum_partials_host(part, hp, st, e);
+    if (e != hipSuccess) return fail(WFD_E_HIP, "smoothing: %s", hipGetErrorString(e));
+    const double alpha = rr / pap;
+    HIP_TRY(wfd::launch_cg_update(out, r, p, ap, n, (float)alpha, part, kSmoothPartials, st));
+    const double rr_new = sum_partials_host(part, hp, st, e);
+    if (e != hipSuccess) return fail(WFD_E_HIP, "smoothing: %s", hipGetErrorString(e));
+    ++it;
+    if (rr_new <= tol * tol * gg) {
+      rr = rr_new;
+      break;
+    }
+    HIP_TRY(wfd::launch_cg_direction(p, r, n, (float)(rr_new / rr), kSmoothPartials, st));
+    rr = rr_new;
+  }
+  if (iterations) *iterations = it;
+  if (rr > tol * tol * gg)
+    return fail(WFD_E_RANGE, "smoothing: no convergence in %d iterations (residual %.3g)", it,
+                std::sqrt(rr / gg));
+  return WFD_OK;
+}
+
 }  // extern "C"
+
 

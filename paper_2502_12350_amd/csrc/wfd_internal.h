@@ -17,7 +17,11 @@ struct StepGrid {
   const float *gx, *gy, *gz;  // 1-D sponge tables
   const float *k;        // dt^2 v^2
   const float *m2;       // mass term (variable density) or nullptr
+  int zs;                // free-surface plane (planes above read as its negated
+                         // mirror, planes at and above it stay zero), or
+                         // kNoSurface, below every plane a kernel touches
 };
+constexpr int kNoSurface = -(1 << 24);
 
 // Receivers grouped by (y, x) column of the padded grid.  Entry e is one
 // distinct receiver node at depth ent_z[e]; the receivers sharing it are
@@ -96,9 +100,9 @@ hipError_t launch_precompute_k(const float *vel, int mnx, int mny, int mnz, int 
                                float *k, int pitch, int ny, int nz, float *partial_max,
                                int n_partial, hipStream_t stream);
 hipError_t launch_precompute_m2(const float *rho, int mnx, int mny, int mnz, int border,
-                                double idx2, double idy2, double idz2, float *m2, int pitch,
-                                int ny, int nz, float *sqrt_rho, float *partial_max,
-                                int n_partial, hipStream_t stream);
+                                int free_surface, double idx2, double idy2, double idz2,
+                                float *m2, int pitch, int ny, int nz, float *sqrt_rho,
+                                float *partial_max, int n_partial, hipStream_t stream);
 
 // Per-shot scalars: sigma and per-receiver forward / adjoint scales.
 hipError_t launch_shot_setup(const float *k, const float *sqrt_rho, int border, int mnx, int mny,
@@ -144,5 +148,18 @@ hipError_t launch_adam(float *w, const float *g, float *m, float *v, int n, floa
                        float b2, float eps, int step, hipStream_t stream);
 hipError_t launch_pack_input(const float *grad, const float *illum, int64_t n, float eps,
                              float *partial, int npart, uint16_t *out, hipStream_t stream);
+
+// ---- gradient smoothing kernels (wfd_smooth.hip) ----
+hipError_t launch_tri_lines(float *u, int axis, int n, int64_t nlines, int nx, int ny,
+                            const double *cp, const double *inv_den, double a, double scale,
+                            hipStream_t stream);
+hipError_t launch_bessel_apply(const float *x, float *y, int nx, int ny, int nz, float cx,
+                               float cy, float cz, double *part, int npart, hipStream_t stream);
+hipError_t launch_cg_update(float *x, float *r, const float *p, const float *ap, int64_t n,
+                            float alpha, double *part, int npart, hipStream_t stream);
+hipError_t launch_cg_direction(float *p, const float *r, int64_t n, float beta, int npart,
+                               hipStream_t stream);
+hipError_t launch_cg_start(const float *g, float *r, float *x, int64_t n, double *part, int npart,
+                           hipStream_t stream);
 
 }  // namespace wfd

@@ -39,16 +39,20 @@ __global__ void __launch_bounds__(256)
   if (threadIdx.x == 0) part[blockIdx.x] = red[0];
 }
 
+// sqrt(rho) at model node (x, y, z), edge-replicated beyond the model; with a
+// free surface, mirrored evenly about the top plane first.
 __device__ __forceinline__ double sqrt_rho_at(const float *rho, int mnx, int mny, int mnz,
-                                              int x, int y, int z) {
+                                              int x, int y, int z, bool fs) {
+  if (fs && z < 0) z = -z;
   const int mx = clampi(x, 0, mnx - 1), my = clampi(y, 0, mny - 1), mz = clampi(z, 0, mnz - 1);
   return sqrt((double)rho[((int64_t)mz * mny + my) * mnx + mx]);
 }
 
-// m^2 = L8(s) / s with s = sqrt(rho) edge-replicated beyond the model (FP64);
+// m^2 = L8(s) / s with s = sqrt(rho) edge-replicated beyond the model, mirrored
+// evenly above a free surface (FP64);
 // also s on the model grid for source / receiver scales; per-block max m^2.
 __global__ void __launch_bounds__(256)
-    k_precompute_m2(const float *__restrict__ rho, int mnx, int mny, int mnz, int border,
+    k_precompute_m2(const float *__restrict__ rho, int mnx, int mny, int mnz, int border, int fs,
                     double idx2, double idy2, double idz2, float *__restrict__ m2, int pitch,
                     int ny, int nz, float *__restrict__ sqrt_rho, float *__restrict__ part) {
   const int nx = mnx + 2 * border;
@@ -61,15 +65,15 @@ __global__ void __launch_bounds__(256)
     const int y = (int)((i / nx) % ny);
     const int z = (int)(i / ((int64_t)nx * ny));
     const int mx = x - border, my = y - border, mz = z - border;
-    const double s = sqrt_rho_at(rho, mnx, mny, mnz, mx, my, mz);
+    const double s = sqrt_rho_at(rho, mnx, mny, mnz, mx, my, mz, fs != 0);
     double lx = w[0] * s, ly = w[0] * s, lz = w[0] * s;
     for (int j = 1; j <= 4; ++j) {
-      lx += w[j] * (sqrt_rho_at(rho, mnx, mny, mnz, mx + j, my, mz) +
-                    sqrt_rho_at(rho, mnx, mny, mnz, mx - j, my, mz));
-      ly += w[j] * (sqrt_rho_at(rho, mnx, mny, mnz, mx, my + j, mz) +
-                    sqrt_rho_at(rho, mnx, mny, mnz, mx, my - j, mz));
-      lz += w[j] * (sqrt_rho_at(rho, mnx, mny, mnz, mx, my, mz + j) +
-                    sqrt_rho_at(rho, mnx, mny, mnz, mx, my, mz - j));
+      lx += w[j] * (sqrt_rho_at(rho, mnx, mny, mnz, mx + j, my, mz, fs != 0) +
+                    sqrt_rho_at(rho, mnx, mny, mnz, mx - j, my, mz, fs != 0));
+      ly += w[j] * (sqrt_rho_at(rho, mnx, mny, mnz, mx, my + j, mz, fs != 0) +
+                    sqrt_rho_at(rho, mnx, mny, mnz, mx, my - j, mz, fs != 0));
+      lz += w[j] * (sqrt_rho_at(rho, mnx, mny, mnz, mx, my, mz + j, fs != 0) +
+                    sqrt_rho_at(rho, mnx, mny, mnz, mx, my, mz - j, fs != 0));
     }
     const double val = (lx * idx2 + ly * idy2 + lz * idz2) / s;
     m2[(int64_t)z * pitch * ny + (int64_t)y * pitch + x] = (float)val;
@@ -215,11 +219,12 @@ hipError_t launch_precompute_k(const float *vel, int mnx, int mny, int mnz, int 
 }
 
 hipError_t launch_precompute_m2(const float *rho, int mnx, int mny, int mnz, int border,
-                                double idx2, double idy2, double idz2, float *m2, int pitch,
-                                int ny, int nz, float *sqrt_rho, float *partial_max,
-                                int n_partial, hipStream_t stream) {
+                                int free_surface, double idx2, double idy2, double idz2,
+                                float *m2, int pitch, int ny, int nz, float *sqrt_rho,
+                                float *partial_max, int n_partial, hipStream_t stream) {
   hipLaunchKernelGGL(k_precompute_m2, dim3(n_partial), dim3(256), 0, stream, rho, mnx, mny, mnz,
-                     border, idx2, idy2, idz2, m2, pitch, ny, nz, sqrt_rho, partial_max);
+                     border, free_surface, idx2, idy2, idz2, m2, pitch, ny, nz, sqrt_rho,
+                     partial_max);
   return hipGetLastError();
 }
 

@@ -114,8 +114,14 @@ struct Marcher {
   float nxt[RY];        // plane z+5 (in flight)
   float hq[5][T::HPT];  // halo of planes z .. z+4 (hq[0] is staged next)
 
+  // Plane z of the field at offset o: zero past the grid, and above a free
+  // surface the negated mirror image about it.
   __device__ __forceinline__ static float ld(const float *f, const StepGrid &g, int z, uint32_t o,
                                              bool ok) {
+    if (z < g.zs) {
+      const int zm = 2 * g.zs - z;
+      return (ok && zm < g.nz) ? -f[(int64_t)zm * g.plane + o] : 0.0f;
+    }
     return (ok && z >= 0 && z < g.nz) ? f[(int64_t)z * g.plane + o] : 0.0f;
   }
   __device__ __forceinline__ void prime(const float *f, const StepGrid &g, int z0,
@@ -308,7 +314,7 @@ __device__ __forceinline__ void forward_tile(
       const int64_t p = zoff + geo.off[j];
       if (geo.in[j] && p == src.idx) acc += src.sigma[0] * src.wavelet[n];
       const float G = gxv * gyv[j] * gzv;
-      const float o = G * (acc - G * pv[j]);
+      const float o = z > g.zs ? G * (acc - G * pv[j]) : 0.0f;  // zero at/above a free surface
       if (geo.in[j]) st_stream(out, p, o);
       if (cc[j].ez == z) {
         for (int r = rec.ent_rp[cc[j].e]; r < rec.ent_rp[cc[j].e + 1]; ++r) {
@@ -441,8 +447,9 @@ __global__ void __launch_bounds__(TX * NW)
       const float G = gxv * gyv[j] * gzv;
       const int64_t p = zoff + geo.off[j];
       if (geo.in[j]) {
-        st_stream(out, p, G * (acc - G * pv[j]));
-        st_stream(grad, p, gv[j] + ca * (VD ? lap_w - mv[j] * cw : lap_w));
+        const bool live = z > g.zs;  // at and above a free surface psi and w stay zero
+        st_stream(out, p, live ? G * (acc - G * pv[j]) : 0.0f);
+        st_stream(grad, p, live ? gv[j] + ca * (VD ? lap_w - mv[j] * cw : lap_w) : gv[j]);
         if (ILLUM) {
           const int ix = geo.x - border, iy = geo.yv[j] - border, iz = z - border;
           if (ix >= 0 && ix < mnx && iy >= 0 && iy < mny && iz >= 0 && iz < mnz)

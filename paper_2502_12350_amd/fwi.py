@@ -75,8 +75,11 @@ class WaveFn:
 
 
 def evaluate(prop: Propagator, grid: GridSpec, vel, rho, shots: Shots, ckpt="auto",
-             illum=None, zero_top_planes: int = 0):
-    """(misfit, dJ/dv) summed over shots; illum (if given) accumulates sum (w^n)^2."""
+             illum=None, zero_top_planes: int = 0, smoothing=None):
+    """(misfit, dJ/dv) summed over shots; illum (if given) accumulates sum (w^n)^2.
+    smoothing = (mode, lengths) applies the paper's gradient smoothing ("laplace"
+    or "bessel", lengths (x, y, z) in metres) before the top planes are zeroed
+    (GradientPreconditioning, then ZeroesNearSurface, as in Alg. 3)."""
     import torch
     prop.set_model(grid, vel.contiguous(), rho)
     misfit = torch.zeros((), dtype=torch.float64, device=prop.device)
@@ -86,6 +89,10 @@ def evaluate(prop: Propagator, grid: GridSpec, vel, rho, shots: Shots, ckpt="aut
         ck = auto_checkpoint(prop, len(rec)) if ckpt == "auto" else ckpt
         prop.gradient(shots.wavelet, shots.sources[s], rec, shots.dobs[s], ckpt=ck, grad=grad,
                       misfit=misfit, illum=illum)
+    if smoothing is not None:
+        from .api import smooth
+        mode, lengths = smoothing
+        grad, _ = smooth(grad, mode, lengths, (grid.dx, grid.dy, grid.dz))
     if zero_top_planes:
         prop.gradient_finish(grad, zero_top_planes)
     return misfit, grad
@@ -162,15 +169,45 @@ def _quadratic_step(J_at, v, d, J0, gd, a1, bounds):
 
 
 def _project(v, bounds):
-    if bounds is None:
+    """Clamp to the velocity bounds: None, or (lower, upper) where either side
+    may be None (the paper's L-BFGS-b bound types: unbounded, lower only,
+    both, upper only)."""
+    if bounds is None or (bounds[0] is None and bounds[1] is None):
         return v
     return v.clamp(bounds[0], bounds[1])
+
+
+def _save_state(path, it, v, g, illum, J, S, Y, dv_prev, trace):
+    """Everything the loop needs to continue after iteration it - 1."""
+    import os
+    tmp = path + ".tmp.npz"
+    np.savez(tmp, it=np.int64(it), v=v.cpu().numpy(), g=g.cpu().numpy(),
+             illum=illum.cpu().numpy(), J=np.float64(J),
+             S=np.stack([s.cpu().numpy() for s in S]) if S else np.zeros((0,) + tuple(v.shape)),
+             Y=np.stack([y.cpu().numpy() for y in Y]) if Y else np.zeros((0,) + tuple(v.shape)),
+             dv_prev=np.float64(np.nan if dv_prev is None else dv_prev),
+             misfit=np.asarray(trace.misfit, dtype=np.float64),
+             gpu_seconds=np.asarray(trace.gpu_seconds, dtype=np.float64),
+             counts=np.asarray([trace.n_gradients, trace.n_misfits, trace.n_network]))
+    os.replace(tmp, path)  # a crash while writing leaves the previous state
+
+
+def _load_state(path, device):
+    import torch
+    with np.load(path, allow_pickle=False) as z:
+        st = {k: z[k] for k in z.files}
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(device)
+    dv = float(st["dv_prev"])
+    return (int(st["it"]), t(st["v"]), t(st["g"]), t(st["illum"]), float(st["J"]),
+            [t(a) for a in st["S"]], [t(a) for a in st["Y"]], None if np.isnan(dv) else dv,
+            st["misfit"].tolist(), st["gpu_seconds"].tolist(), st["counts"].tolist())
 
 
 def fwi(prop: Propagator, grid: GridSpec, v0, rho, shots: Shots, *, n_iter: int = 10,
         method: str = "sd", bounds: Optional[Tuple[float, float]] = None,
         max_rel_step: float = 0.02, eps_illum: float = 1.0e-3, memory: int = 5,
-        ckpt="auto", zero_top_planes: int = 0, precond=None, progress=None):
+        ckpt="auto", zero_top_planes: int = 0, precond=None, progress=None, smoothing=None,
+        state_file: Optional[str] = None):
     """Alg. 2: repeat {gradient, model update} for n_iter iterations.
 
     method "sd": steepest descent on the illumination-compensated gradient;
@@ -182,7 +219,14 @@ def fwi(prop: Propagator, grid: GridSpec, v0, rho, shots: Shots, *, n_iter: int 
     Returns (final velocity, FwiTrace).  GPU-seconds are wall time of the
     synchronised GPU work (the device runs nothing else meanwhile), including
     the network's inference.  progress(iteration, misfit, gpu_seconds, model),
-    if given, is called after every iteration.
+    if given, is called after every iteration.  smoothing = (mode, lengths)
+    smooths every gradient as the paper's GradientPreconditioning does.
+
+    state_file: fault tolerance in the manner of the paper's DeLIA restart.
+    The loop state (model, gradient, illumination, L-BFGS pairs, step memory,
+    history) is written there after every iteration, atomically; if the file
+    exists when fwi starts, the run continues from it and ends exactly as an
+    uninterrupted run would.
     """
     import torch
     trace = FwiTrace(method)
@@ -196,13 +240,15 @@ def fwi(prop: Propagator, grid: GridSpec, v0, rho, shots: Shots, *, n_iter: int 
         clock[0] += time.perf_counter() - t0
         return out
 
+    import os
+    resume = state_file is not None and os.path.exists(state_file)
     v = _project(v0.clone(), bounds)
     illum = torch.zeros_like(v)
 
     def grad_at(vv):
         illum.zero_()
         J, g = timed(evaluate, prop, grid, vv, rho, shots, ckpt=ckpt, illum=illum,
-                     zero_top_planes=zero_top_planes)
+                     zero_top_planes=zero_top_planes, smoothing=smoothing)
         trace.n_gradients += 1
         return float(J.item()), g
 
@@ -210,10 +256,19 @@ def fwi(prop: Propagator, grid: GridSpec, v0, rho, shots: Shots, *, n_iter: int 
         trace.n_misfits += 1
         return float(timed(misfit_only, prop, grid, vv, rho, shots).item())
 
-    J, g = grad_at(v)
-    trace.record(clock[0], J)
     S, Y = [], []
     dv_prev = None  # largest model change of the last accepted steepest-descent step
+    start = 0
+    if resume:
+        (start, v, g, il, J, S, Y, dv_prev, trace.misfit, trace.gpu_seconds,
+         (trace.n_gradients, trace.n_misfits, trace.n_network)) = _load_state(state_file, v.device)
+        illum.copy_(il)
+        clock[0] = trace.gpu_seconds[-1]
+    else:
+        J, g = grad_at(v)
+        trace.record(clock[0], J)
+        if state_file is not None:
+            _save_state(state_file, 0, v, g, illum, J, S, Y, dv_prev, trace)
 
     def first_step(d, warm: bool = True):
         """Initial trial step: a largest model change of max_rel_step * max|v|
@@ -225,8 +280,8 @@ def fwi(prop: Propagator, grid: GridSpec, v0, rho, shots: Shots, *, n_iter: int 
             return default / dmax
         return max(2.0 * dv_prev, 0.05 * default) / dmax
 
-    for it in range(n_iter):
-        if progress and it:
+    for it in range(start, n_iter):
+        if progress and it > start:
             progress(it - 1, J, clock[0], v)
         P = 1.0 / (illum + eps_illum * illum.max())      # preconditioner (diagonal)
         used = False                                       # step along the network's direction
@@ -264,6 +319,8 @@ def fwi(prop: Propagator, grid: GridSpec, v0, rho, shots: Shots, *, n_iter: int 
             alpha = _quadratic_step(J_at, v, d, J, gd, alpha0, bounds)
             if alpha is None:
                 trace.record(clock[0], J)
+                if state_file is not None:
+                    _save_state(state_file, it + 1, v, g, illum, J, S, Y, dv_prev, trace)
                 continue
         elif method == "lbfgs":
             # Armijo backtracking; no acceptable step leaves the model unchanged
@@ -277,6 +334,8 @@ def fwi(prop: Propagator, grid: GridSpec, v0, rho, shots: Shots, *, n_iter: int 
             if not ok:
                 S, Y = [], []
                 trace.record(clock[0], J)
+                if state_file is not None:
+                    _save_state(state_file, it + 1, v, g, illum, J, S, Y, dv_prev, trace)
                 continue
         else:
             alpha = _quadratic_step(J_at, v, d, J, gd, alpha0, bounds)
@@ -289,6 +348,8 @@ def fwi(prop: Propagator, grid: GridSpec, v0, rho, shots: Shots, *, n_iter: int 
                 alpha = _quadratic_step(J_at, v, d, J, gd, first_step(d, warm=False), bounds)
             if alpha is None:  # no decrease found: stop updating
                 trace.record(clock[0], J)
+                if state_file is not None:
+                    _save_state(state_file, it + 1, v, g, illum, J, S, Y, dv_prev, trace)
                 continue
             trace.n_network += int(used)
             dv_prev = alpha * float(d.abs().max())
@@ -304,6 +365,8 @@ def fwi(prop: Propagator, grid: GridSpec, v0, rho, shots: Shots, *, n_iter: int 
                     Y.pop(0)
         v, J, g = v_new, J_new, g_new
         trace.record(clock[0], J)
+        if state_file is not None:
+            _save_state(state_file, it + 1, v, g, illum, J, S, Y, dv_prev, trace)
     if progress:
         progress(n_iter - 1, J, clock[0], v)
     return v, trace

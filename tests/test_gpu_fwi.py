@@ -155,3 +155,26 @@ def test_gradient_workload_revolve_20_pairs_equals_full_storage():
     assert steps == oracle.forward_steps_closed_form(w.nt + 1, 21)
     assert Jf == Jr and Jf > 0
     assert torch.equal(gf, gr)
+
+
+@pytest.mark.parametrize("method", ["sd", "lbfgs"])
+def test_fwi_restart_from_state_file_matches_uninterrupted_run(method, tmp_path):
+    """Fault tolerance: a run stopped after 2 of 4 iterations and restarted
+    from its state file ends bitwise where an uninterrupted run ends."""
+    torch = gpu_or_skip()
+    from paper_2502_12350_amd import Propagator
+    from paper_2502_12350_amd.fwi import fwi
+    w, g, shots, _ = _small_case(torch)
+    say(f"[fwi restart] {method}")
+    P = Propagator(0)
+    v0 = torch.from_numpy(w.vel).cuda()
+    kw = dict(method=method, bounds=(1500.0, None), zero_top_planes=6)
+    v_ref, tr_ref = fwi(P, g, v0, None, shots, n_iter=4, state_file=str(tmp_path / "a.npz"), **kw)
+    state = str(tmp_path / "b.npz")
+    fwi(P, g, v0, None, shots, n_iter=2, state_file=state, **kw)       # "interrupted"
+    v, tr = fwi(P, g, v0, None, shots, n_iter=4, state_file=state, **kw)
+    torch.cuda.synchronize()
+    assert torch.equal(v, v_ref)
+    assert tr.misfit == tr_ref.misfit
+    assert tr.n_gradients == tr_ref.n_gradients and tr.n_misfits == tr_ref.n_misfits
+    assert float(v.min()) >= 1500.0                                   # lower bound only

@@ -274,3 +274,94 @@ def test_errors_are_status_codes():
     import ctypes
     n = ctypes.c_size_t()
     assert Q.L.wfd_workspace_bytes(Q._ctx, 1, None, ctypes.byref(n)) == -6   # WFD_E_STATE
+
+
+# ---------------------------------------------------------------------------
+# free surface (the paper's optional reflecting surface; reading R23)
+# ---------------------------------------------------------------------------
+def _fs_prop(torch, w, vel=None, rho="same"):
+    from paper_2502_12350_amd import GridSpec, Propagator
+    P = Propagator(0)
+    r = w.rho if isinstance(rho, str) else rho
+    v = w.vel if vel is None else vel
+    P.set_model(GridSpec(**w.grid_kwargs(), free_surface=True),
+                torch.from_numpy(np.ascontiguousarray(v)).cuda(),
+                None if r is None else torch.from_numpy(np.ascontiguousarray(r)).cuda())
+    return P
+
+
+def test_free_surface_forward_matches_oracle():
+    torch = gpu_or_skip()
+    w = seisgen.workload("c2_small")
+    say(f"[free surface forward] c2_small padded {w.padded_shape} nt {w.nt}")
+    P = _fs_prop(torch, w)
+    wav = torch.from_numpy(w.wavelet).cuda()
+    seis, fin = P.forward(wav, w.sources[0], w.receivers, final=True)
+    torch.cuda.synchronize()
+    g = oracle.Grid(**w.grid_kwargs(), free_surface=True)
+    ref = oracle.forward(g, w.vel, w.rho, w.wavelet, w.sources[0], w.receivers)
+    e = rel_l2(seis.cpu().numpy(), ref.seis)
+    say(f"  seismogram rel-L2 {e:.3e}")
+    assert e <= SEIS_TOL
+    last = fin[0].cpu().numpy()
+    assert rel_l2(last, ref.last) <= SEIS_TOL
+    assert np.all(last[:w.border + 1] == 0.0)          # at and above the surface
+    # the surface changes the answer (reflections), so the check is not vacuous
+    plain = oracle.forward(oracle_grid(w), w.vel, w.rho, w.wavelet, w.sources[0], w.receivers)
+    assert rel_l2(plain.seis, ref.seis) > 1e-2
+
+
+def test_free_surface_gradient_matches_oracle():
+    torch = gpu_or_skip()
+    w = seisgen.workload("c4_fd_vd")
+    say("[free surface gradient] c4_fd_vd")
+    g = oracle.Grid(**w.grid_kwargs(), free_surface=True)
+    true = (w.vel + 5.0 * w.extra["dv"]).astype(np.float32)
+    dobs = oracle.forward(g, true, w.rho, w.wavelet, w.sources[0], w.receivers).seis
+    ref = oracle.gradient(g, w.vel, w.rho, w.wavelet, w.sources[0], w.receivers, dobs,
+                          illumination=True)
+    P = _fs_prop(torch, w)
+    wav = torch.from_numpy(w.wavelet).cuda()
+    illum = torch.zeros((w.nz, w.ny, w.nx), device="cuda")
+    J, grad = P.gradient(wav, w.sources[0], w.receivers,
+                         torch.from_numpy(dobs.astype(np.float32)).cuda(), illum=illum)
+    J2, grad2 = P.gradient(wav, w.sources[0], w.receivers,
+                           torch.from_numpy(dobs.astype(np.float32)).cuda(), ckpt=("revolve", 7))
+    torch.cuda.synchronize()
+    eJ = abs(float(J.item()) - ref.misfit) / ref.misfit
+    eg = rel_l2(grad.cpu().numpy(), ref.grad)
+    say(f"  misfit rel {eJ:.2e}, gradient rel-L2 {eg:.2e}")
+    assert eJ <= SEIS_TOL and eg <= GRAD_TOL
+    assert rel_l2(illum.cpu().numpy(), ref.illum) <= SEIS_TOL
+    assert torch.equal(grad, grad2)
+
+
+def test_free_surface_image_principle_on_gpu():
+    """GPU alone: the half-space solution with a free surface equals the
+    full-space solution of the evenly mirrored model driven by the source
+    minus its mirror image."""
+    torch = gpu_or_skip()
+    from paper_2502_12350_amd import GridSpec, Propagator
+    say("[free surface image principle]")
+    nh, n, h = 40, 48, 10.0
+    vh = seisgen.layered_model(77, (n, n, nh), 0.05)
+    rh = seisgen.gardner_density(vh)
+    c = nh - 1
+    idx = np.abs(np.arange(2 * nh - 1) - c)
+    vf, rf = np.ascontiguousarray(vh[idx]), np.ascontiguousarray(rh[idx])
+    dt = 0.4 * h / float(vh.max())
+    nt = 300
+    wav = torch.from_numpy(seisgen.ricker(nt, dt, 15.0)).cuda()
+    gh = GridSpec(n, n, nh, h, h, h, border=8, dt=dt, nt=nt, free_surface=True)
+    gf = GridSpec(n, n, 2 * nh - 1, h, h, h, oz=-c * h, border=8, dt=dt, nt=nt)
+    src, img = [235.0, 245.0, 60.0], [235.0, 245.0, -60.0]
+    rec = np.array([[10.0 * i + 5.0, 240.0, 30.0] for i in range(45)])
+    Ph, Pf = Propagator(0), Propagator(0)
+    Ph.set_model(gh, torch.from_numpy(vh).cuda(), torch.from_numpy(rh).cuda())
+    Pf.set_model(gf, torch.from_numpy(vf).cuda(), torch.from_numpy(rf).cuda())
+    half = Ph.forward(wav, src, rec).double()
+    full = Pf.forward(wav, src, rec).double() - Pf.forward(wav, img, rec).double()
+    torch.cuda.synchronize()
+    e = float(torch.linalg.vector_norm(half - full) / torch.linalg.vector_norm(full))
+    say(f"  rel-L2 {e:.2e}")
+    assert float(full.abs().max()) > 0 and e <= 1e-5
