@@ -8,13 +8,14 @@ code with the GPU path.
 from . import wave
 from . import cnn
 from . import smooth
+from . import resample
 from .wave import (FD8, Grid, coefficients, laplacian, second_derivative, pad_edge,
                    fold_padding, sponge_profile, node_index, cfl_ratio,
                    laplacian_symbol_max, forward, misfit, gradient,
                    adjoint_source_transpose, energy, step)
 from .revolve import binomial, forward_steps_closed_form, optimal_cost_table
 
-__all__ = ["wave", "cnn", "smooth", "FD8", "Grid", "coefficients", "laplacian", "second_derivative",
+__all__ = ["wave", "cnn", "smooth", "resample", "FD8", "Grid", "coefficients", "laplacian", "second_derivative",
            "pad_edge", "fold_padding", "sponge_profile", "node_index", "cfl_ratio",
            "laplacian_symbol_max", "forward", "misfit", "gradient",
            "adjoint_source_transpose", "energy", "step", "binomial",
