@@ -372,6 +372,17 @@ wfd_status wfd_smooth(int32_t mode, const float *in_dev, float *out_dev, int32_t
                       int32_t max_iter, void *work_dev, size_t work_bytes,
                       int32_t *iterations_or_null, void *stream);
 
+/* ---- time resampling of seismic data (§2.1) ---------------------------------
+ * Traces [nrec][nt] with sample k at time (k + 1) dt (the trace convention of
+ * wfd_forward).  WFD_RESAMPLE_NEAREST: out[m] = in[n] with n = round-half-up
+ * (t_m / dt_in) - 1 clamped to the trace; WFD_RESAMPLE_SINC: out[m] =
+ * sum_n in[n] sinc((t_m - t_n) / dt_in) over the whole trace (FP64 sums).
+ * in and out are distinct device buffers; enqueued on `stream`. */
+enum { WFD_RESAMPLE_NEAREST = 1, WFD_RESAMPLE_SINC = 2 };
+wfd_status wfd_resample(int32_t mode, const float *in_dev, int32_t nrec, int32_t nt_in,
+                        double dt_in, float *out_dev, int32_t nt_out, double dt_out,
+                        void *stream);
+
 /* ---- measurement ---------------------------------------------------------- */
 
 enum {

@@ -21,6 +21,7 @@ CKPT_REVOLVE = 1
 K_FORWARD, K_ADJOINT, K_OTHER = 0, 1, 2
 CNN_REDUCE_BYTES = 8192
 SMOOTH_LAPLACE, SMOOTH_BESSEL = 1, 2
+RESAMPLE_NEAREST, RESAMPLE_SINC = 1, 2
 
 
 class wfd_grid(C.Structure):
@@ -88,6 +89,8 @@ _SIGS = {
                                              C.POINTER(C.c_size_t)]),
     "wfd_smooth": (C.c_int, [C.c_int32, _P, _P, C.c_int32, C.c_int32, C.c_int32, _D3, _D3,
                              C.c_double, C.c_int32, _P, C.c_size_t, C.POINTER(C.c_int32), _P]),
+    "wfd_resample": (C.c_int, [C.c_int32, _P, C.c_int32, C.c_int32, C.c_double, _P, C.c_int32,
+                               C.c_double, _P]),
     "wfd_map_position": (C.c_int, [C.POINTER(wfd_grid), _D3, C.POINTER(C.c_int32)]),
     "wfd_cfl_ratio": (C.c_int, [C.POINTER(wfd_grid), C.c_double, C.c_double, _D3]),
     "wfd_checkpoint_plan": (C.c_int, [C.c_int32, C.c_int32, C.POINTER(C.c_int32), C.c_int64,

@@ -133,6 +133,23 @@ def smooth(x, mode: str, lengths, spacing, *, tol: float = 1e-6, max_iter: int =
     return out, it.value
 
 
+def resample(traces, dt_in: float, nt_out: int, dt_out: float, mode: str = "sinc"):
+    """Resample device traces [nrec][nt] (sample k at (k + 1) dt) to nt_out
+    samples of step dt_out by "nearest" or "sinc" interpolation."""
+    import torch
+    L = _lib.lib()
+    m = {"nearest": _lib.RESAMPLE_NEAREST, "sinc": _lib.RESAMPLE_SINC}[mode]
+    if not (traces.is_cuda and traces.dtype == torch.float32 and traces.is_contiguous()
+            and traces.dim() == 2):
+        raise ValueError("traces must be a contiguous 2-D float32 CUDA tensor")
+    nrec, nt_in = traces.shape
+    out = torch.empty((nrec, int(nt_out)), dtype=torch.float32, device=traces.device)
+    check(L.wfd_resample(m, _ptr(traces), nrec, nt_in, float(dt_in), _ptr(out), int(nt_out),
+                         float(dt_out),
+                         C.c_void_p(torch.cuda.current_stream(traces.device).cuda_stream)))
+    return out
+
+
 def model_bytes(grid, variable_density: bool) -> int:
     g = _grid(grid).c()
     n = C.c_size_t()

@@ -1437,6 +1437,22 @@ wfd_status wfd_smooth(int32_t mode, const float *in, float *out, int32_t nx, int
   return WFD_OK;
 }
 
+wfd_status wfd_resample(int32_t mode, const float *in, int32_t nrec, int32_t nt_in, double dt_in,
+                        float *out, int32_t nt_out, double dt_out, void *stream) {
+  if (mode != WFD_RESAMPLE_NEAREST && mode != WFD_RESAMPLE_SINC)
+    return fail(WFD_E_ARG, "unknown resampling mode %d", mode);
+  if (nrec < 0 || nt_in < 1 || nt_out < 1) return fail(WFD_E_ARG, "bad trace sizes");
+  if (!(dt_in > 0.0) || !(dt_out > 0.0) || !std::isfinite(dt_in) || !std::isfinite(dt_out))
+    return fail(WFD_E_ARG, "sample steps must be finite and > 0");
+  if (nrec == 0) return WFD_OK;
+  if (!in || !out) return fail(WFD_E_ARG, "NULL argument");
+  if (in == out) return fail(WFD_E_ARG, "in and out must differ");
+  HIP_TRY(wfd::launch_resample(in, nrec, nt_in, dt_in, out, nt_out, dt_out,
+                               mode == WFD_RESAMPLE_SINC, (hipStream_t)stream));
+  return WFD_OK;
+}
+
 }  // extern "C"
+
 
 

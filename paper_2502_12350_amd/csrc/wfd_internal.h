@@ -161,5 +161,7 @@ hipError_t launch_cg_direction(float *p, const float *r, int64_t n, float beta, 
                                hipStream_t stream);
 hipError_t launch_cg_start(const float *g, float *r, float *x, int64_t n, double *part, int npart,
                            hipStream_t stream);
+hipError_t launch_resample(const float *in, int nrec, int nt_in, double dt_in, float *out,
+                           int nt_out, double dt_out, int sinc, hipStream_t stream);
 
 }  // namespace wfd

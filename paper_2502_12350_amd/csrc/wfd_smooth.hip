@@ -179,3 +179,50 @@ hipError_t launch_cg_start(const float *g, float *r, float *x, int64_t n, double
 }
 
 }  // namespace wfd
+
+// ---- time resampling of traces -------------------------------------------------
+// Trace sample k sits at (k + 1) dt.  nearest: round half up, clamped.  sinc:
+// out[m] = sum_n in[n] sinc(a_m - n) with a_m = t_m / dt_in - 1; using
+// sin(pi (a - n)) = (-1)^n sin(pi a) each term is one division (FP64 sums);
+// an integer a_m selects the input sample.
+namespace wfd {
+namespace {
+
+__global__ void k_resample(const float *__restrict__ in, int nrec, int nt_in, double dt_in,
+                           float *__restrict__ out, int nt_out, double dt_out, int sinc) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (int64_t)nrec * nt_out) return;
+  const int r = (int)(i / nt_out), m = (int)(i % nt_out);
+  const float *tr = in + (int64_t)r * nt_in;
+  const double a = (double)(m + 1) * dt_out / dt_in - 1.0;
+  if (!sinc) {
+    int n = (int)floor(a + 1.0 + 0.5) - 1;
+    n = n < 0 ? 0 : (n > nt_in - 1 ? nt_in - 1 : n);
+    out[i] = tr[n];
+    return;
+  }
+  const double an = rint(a);
+  if (fabs(a - an) < 1e-12) {  // on an input sample
+    const int n = (int)an;
+    out[i] = (n >= 0 && n < nt_in) ? tr[n] : 0.0f;
+    return;
+  }
+  double s = 0.0;
+  for (int n = 0; n < nt_in; ++n) {
+    const double term = (double)tr[n] / (a - (double)n);
+    s += (n & 1) ? -term : term;
+  }
+  out[i] = (float)(s * sin(M_PI * a) / M_PI);
+}
+
+}  // namespace
+
+hipError_t launch_resample(const float *in, int nrec, int nt_in, double dt_in, float *out,
+                           int nt_out, double dt_out, int sinc, hipStream_t stream) {
+  const int64_t n = (int64_t)nrec * nt_out;
+  hipLaunchKernelGGL(k_resample, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream, in, nrec,
+                     nt_in, dt_in, out, nt_out, dt_out, sinc);
+  return hipGetLastError();
+}
+
+}  // namespace wfd

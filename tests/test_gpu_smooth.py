@@ -72,3 +72,23 @@ def test_fwi_gradient_smoothing_is_applied_before_zeroing():
     ref[:3] = 0.0
     torch.cuda.synchronize()
     assert float((sm - ref).abs().max()) <= 1e-6 * float(ref.abs().max())
+
+
+@pytest.mark.parametrize("mode", ["nearest", "sinc"])
+def test_resampling_matches_oracle(mode):
+    torch = gpu_or_skip()
+    from oracle import resample as ors
+    from paper_2502_12350_amd import resample
+    rng = np.random.default_rng(9)
+    d = rng.standard_normal((37, 300)).astype(np.float32)
+    for dt_in, nt_out, dt_out in ((2e-3, 600, 1e-3), (1e-3, 130, 2.3e-3), (1.5e-3, 300, 1.5e-3)):
+        ref = ors.resample(d, dt_in, nt_out, dt_out, mode)
+        got = resample(torch.from_numpy(d).cuda(), dt_in, nt_out, dt_out, mode)
+        torch.cuda.synchronize()
+        g = got.cpu().numpy().astype(np.float64)
+        if mode == "nearest":
+            assert np.array_equal(g, ref)
+        else:
+            e = rel_l2(g, ref)
+            say(f"[resample sinc] dt {dt_in} -> {dt_out}: rel-L2 {e:.2e}")
+            assert e <= 1e-6
