@@ -103,16 +103,18 @@ __device__ __forceinline__ void st_stream(float *f, int64_t p, float v) {
 // as their interior, and waits in a register delay line; loading it one plane
 // ahead instead needed L2 to keep four planes of every resident tile, and the
 // adjoint (two stenciled fields) then re-read its halo from HBM.
+// DL is the delay-line depth: the halo of plane z is loaded DL planes before
+// it is staged (5: with the interior of that plane; 1: one plane ahead).
 // K tags the kernel family (0 forward, 1 adjoint): each family gets its own
 // instantiations of the tile helpers.  With shared ones, hipcc allocated the
 // adjoint 137 VGPRs instead of 123 once a forward shape used the same tile,
 // dropping it from 4 to 3 waves per SIMD.
-template <int RY, int NW, int K>
+template <int RY, int NW, int K, int DL = 5>
 struct Marcher {
   using T = Tile<RY, NW>;
-  float q[RY][9];       // planes z-4 .. z+4 of the thread's RY points
-  float nxt[RY];        // plane z+5 (in flight)
-  float hq[5][T::HPT];  // halo of planes z .. z+4 (hq[0] is staged next)
+  float q[RY][9];        // planes z-4 .. z+4 of the thread's RY points
+  float nxt[RY];         // plane z+5 (in flight)
+  float hq[DL][T::HPT];  // halo of planes z .. z+DL-1 (hq[0] is staged next)
 
   // Plane z of the field at offset o: zero past the grid, and above a free
   // surface the negated mirror image about it.
@@ -132,7 +134,7 @@ struct Marcher {
 #pragma unroll
       for (int i = 0; i < 9; ++i) q[j][i] = ld(f, g, z0 - 4 + i, off[j], in[j]);
 #pragma unroll
-    for (int d = 0; d < 5; ++d)
+    for (int d = 0; d < DL; ++d)
 #pragma unroll
       for (int i = 0; i < T::HPT; ++i) hq[d][i] = ld(f, g, z0 + d, hoff[i], hin[i]);
   }
@@ -144,18 +146,18 @@ struct Marcher {
     for (int i = 0; i < T::HPT; ++i)
       if (hslot[i] >= 0) (&s[0][0])[hslot[i]] = hq[0][i];
   }
-  // After stage(): the interior and the halo of plane z+5.
+  // After stage(): the interior of plane z+5 and the halo of plane z+DL.
   __device__ __forceinline__ void fetch(const float *f, const StepGrid &g, int z,
                                         const uint32_t *off, const bool *in,
                                         const uint32_t *hoff, const bool *hin) {
 #pragma unroll
     for (int j = 0; j < RY; ++j) nxt[j] = ld(f, g, z + 5, off[j], in[j]);
 #pragma unroll
-    for (int d = 0; d < 4; ++d)
+    for (int d = 0; d < DL - 1; ++d)
 #pragma unroll
       for (int i = 0; i < T::HPT; ++i) hq[d][i] = hq[d + 1][i];
 #pragma unroll
-    for (int i = 0; i < T::HPT; ++i) hq[4][i] = ld(f, g, z + 5, hoff[i], hin[i]);
+    for (int i = 0; i < T::HPT; ++i) hq[DL - 1][i] = ld(f, g, z + DL, hoff[i], hin[i]);
   }
   __device__ __forceinline__ void shift() {
 #pragma unroll
@@ -362,6 +364,9 @@ __global__ void __launch_bounds__(TX * NW)
                            d.seis_tm, d.map, b - d.block_begin);
 }
 
+// Halo delay-line depths of the adjoint's two fields.
+constexpr int kDelayPsi = 5, kDelayW = 5;
+
 template <int RY, int NW, bool VD, bool ILLUM>
 __global__ void __launch_bounds__(TX * NW)
     k_adjoint(StepGrid g, const float *__restrict__ cur, const float *prev, float *out,
@@ -372,7 +377,8 @@ __global__ void __launch_bounds__(TX * NW)
   __shared__ float sm[2][2][T::LY][T::LX];  // [field][buffer]
   Geo<RY, NW, 1> geo;
   if (!geo.init(g, map, blockIdx.x)) return;
-  Marcher<RY, NW, 1> fa, fw;  // adjoint state psi^{m+1} and forward state w^m
+  Marcher<RY, NW, 1, kDelayPsi> fa;  // adjoint state psi^{m+1}
+  Marcher<RY, NW, 1, kDelayW> fw;    // forward state w^m
   fa.prime(cur, g, geo.z0, geo.off, geo.in, geo.hoff, geo.hin);
   fw.prime(wm, g, geo.z0, geo.off, geo.in, geo.hoff, geo.hin);
   const float gxv = geo.x < g.nx ? g.gx[geo.x] : 0.0f;

@@ -161,3 +161,35 @@ def test_cnn_packed_sizes_and_workspace():
     assert b.value == 1024 * (27 * 256 + 16) * 4                     # capped at 1024 blocks
     assert L.wfd_cnn_conv(None, 8, 8, 8, 3, 16, None, None, 0, None, None, 0, None, None,
                           None) == -1
+
+
+def test_smoothing_and_resampling_host_paths():
+    import ctypes as C
+    from paper_2502_12350_amd import _lib
+    L = _lib.lib()
+    b = C.c_size_t()
+    assert L.wfd_smooth_workspace_bytes(_lib.SMOOTH_LAPLACE, 10, 20, 30, C.byref(b)) == 0
+    assert b.value >= 2 * (10 + 20 + 30) * 8
+    assert L.wfd_smooth_workspace_bytes(_lib.SMOOTH_BESSEL, 10, 20, 30, C.byref(b)) == 0
+    assert b.value >= 3 * 10 * 20 * 30 * 4
+    assert L.wfd_smooth_workspace_bytes(7, 10, 20, 30, C.byref(b)) == -1
+    assert L.wfd_smooth_workspace_bytes(_lib.SMOOTH_BESSEL, 0, 20, 30, C.byref(b)) == -1
+    # argument errors are found before anything touches a device
+    assert L.wfd_resample(9, None, 1, 10, 1e-3, None, 10, 1e-3, None) == -1
+    assert L.wfd_resample(_lib.RESAMPLE_SINC, None, 1, 10, 0.0, None, 10, 1e-3, None) == -1
+    assert L.wfd_resample(_lib.RESAMPLE_SINC, None, 0, 10, 1e-3, None, 10, 1e-3, None) == 0
+    lens = (C.c_double * 3)(10.0, 10.0, 10.0)
+    hs = (C.c_double * 3)(10.0, 0.0, 10.0)
+    assert L.wfd_smooth(_lib.SMOOTH_LAPLACE, 1, 2, 4, 4, 4, lens, hs, 1e-6, 10, 3, 64, None,
+                        None) == -1                                       # zero spacing
+
+
+def test_free_surface_flag_is_validated():
+    import ctypes as C
+    from paper_2502_12350_amd import _lib
+    L = _lib.lib()
+    g = _lib.wfd_grid(16, 16, 16, 10.0, 10.0, 10.0, 0.0, 0.0, 0.0, 4, 1e-3, 10, 2)
+    n = C.c_size_t()
+    assert L.wfd_model_bytes(C.byref(g), 0, C.byref(n)) == -1
+    g.free_surface = 1
+    assert L.wfd_model_bytes(C.byref(g), 0, C.byref(n)) == 0
