@@ -398,6 +398,88 @@ def precond_fwi_bench(n_iter: int):
     print(json.dumps(out), flush=True)
 
 
+def kernel_table_bench(steps: int = 40):
+    """Per-kernel rates: forward and adjoint at the 576^3 size, constant and
+    variable density (%HBM there), the cache-resident 64^3 and 240x240x200
+    forwards (Gpt/s only), against the nominal 8 TB/s and a streaming rate
+    measured on the same box."""
+    import numpy as np
+    import torch
+    import seisgen
+    from paper_2502_12350_amd import GridSpec, Propagator, K_FORWARD, K_ADJOINT
+
+    dev = torch.device("cuda", 0)
+    # streaming reference: torch addcmul over 1 GiB arrays (3 reads + 1 write)
+    n = 1 << 28
+    a, b, c = (torch.ones(n, device=dev) for _ in range(3))
+    o = torch.empty(n, device=dev)
+    torch.addcmul(a, b, c, out=o)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(10):
+        torch.addcmul(a, b, c, out=o)
+    e1.record()
+    torch.cuda.synchronize()
+    stream_gbs = 16.0 * n * 10 / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del a, b, c, o
+    torch.cuda.empty_cache()
+    rows = {}
+
+    def run(name, w, rho, adjoint, hbm):
+        g = GridSpec(**{**w.grid_kwargs(), "nt": steps})
+        P = Propagator(0)
+        P.set_model(g, torch.from_numpy(w.vel).to(dev),
+                    None if rho is None else torch.from_numpy(rho).to(dev))
+        wav = torch.from_numpy(w.wavelet[:steps]).to(dev)
+        rec = w.receivers
+        if adjoint:
+            dobs = torch.zeros((len(rec), steps), device=dev)
+            ck = ("revolve", 8)
+            P.gradient(wav, w.sources[0], rec, dobs, ckpt=ck)
+            P.set_profiling(True)
+            P.gradient(wav, w.sources[0], rec, dobs, ckpt=ck)
+            nl, ms = P.kernel_stats(K_ADJOINT)
+        else:
+            P.forward(wav, w.sources[0], rec)
+            P.set_profiling(True)
+            P.forward(wav, w.sources[0], rec)
+            nl, ms = P.kernel_stats(K_FORWARD)
+        P.set_profiling(False)
+        us = 1e3 * ms / nl
+        pts, mpts = w.padded_points, w.nx * w.ny * w.nz
+        bpp = (32 if adjoint else 20) if rho is not None else (28 if adjoint else 16)
+        r = {"us_per_step": round(us, 1), "gpts_padded": round(pts / us / 1e3, 1),
+             "gpts_model": round(mpts / us / 1e3, 1), "bytes_per_point": bpp}
+        if hbm:
+            gbs = pts * bpp / us / 1e3
+            r.update({"GBps": round(gbs, 0), "frac_of_8TBs": round(gbs / HBM_PEAK_GBS, 4),
+                      "frac_of_streaming": round(gbs / stream_gbs, 4)})
+        rows[name] = r
+        print(f"[bench-kernels] {name}: {r}", file=sys.stderr, flush=True)
+        P.release_workspace()
+        del P
+        torch.cuda.empty_cache()
+
+    c2 = seisgen.workload("c2")
+    run("forward_vd_576", c2, c2.rho, False, True)
+    run("forward_cd_576", c2, None, False, True)
+    run("adjoint_vd_576", c2, c2.rho, True, True)
+    run("adjoint_cd_576", c2, None, True, True)
+    del c2
+    c1 = seisgen.workload("c1")
+    run("forward_cd_c1_80cubed", c1, None, False, False)
+    c4 = seisgen.workload("c4")
+    run("forward_cd_c4_240x240x200", c4, None, False, False)
+    out = {"metric": "per-kernel Gpt/s and %HBM", "unit": "Gpt/s", "n_gpus": 1, "dtype": "f32",
+           "data": "synthetic", "steps": steps,
+           "streaming_reference_GBps": round(stream_gbs, 0),
+           "config": {"workload": "576^3 padded (c2 model), constant and variable density; "
+                                  "80^3 (c1) and 240x240x200 (c4) cache-resident forwards"},
+           "kernels": rows}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -410,6 +492,8 @@ def main():
     ap.add_argument("--copy-probe", action="store_true")
     ap.add_argument("--fwi", type=int, default=0, metavar="ITERS",
                     help="run the FWI benchmark with this many iterations per method instead")
+    ap.add_argument("--kernels", action="store_true",
+                    help="per-kernel table: forward/adjoint CD and VD at 576^3, cache-resident sizes")
     ap.add_argument("--precond-fwi", type=int, default=0, metavar="ITERS",
                     help="run FWI with the learned preconditioner against the plain method")
     ap.add_argument("--cnn", type=int, default=0, metavar="N",
@@ -441,6 +525,9 @@ def main():
         return
     if args.precond_fwi:
         precond_fwi_bench(args.precond_fwi)
+        return
+    if args.kernels:
+        kernel_table_bench()
         return
 
     import numpy as np
@@ -550,6 +637,7 @@ def main():
         "kernels": {n: {k: (round(v, 4) if isinstance(v, float) else v) for k, v in d.items()}
                     for n, d in kern.items()},
         "other_ms_per_step": round(mso / args.steps, 3),
+        "model_point_gpts": round(w.nx * w.ny * w.nz * 2.0 * w.nt / (ms_step * 1e-3) / 1e9, 3),
         "misfit": float(misfit.item()) / (args.warmup + args.steps),
         "kernel_source": kernel_hash(),
     }
