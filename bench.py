@@ -398,7 +398,7 @@ def precond_fwi_bench(n_iter: int):
     print(json.dumps(out), flush=True)
 
 
-def kernel_table_bench(steps: int = 40):
+def kernel_table_bench(steps: int = 200):
     """Per-kernel rates: forward and adjoint at the 576^3 size, constant and
     variable density (%HBM there), the cache-resident 64^3 and 240x240x200
     forwards (Gpt/s only), against the nominal 8 TB/s and a streaming rate

@@ -76,19 +76,45 @@ typedef struct {
                            read as the negated mirror, sqrt(rho) mirrored
                            evenly, no sponge on that side; the field is zero
                            on and above it); 0: sponge on all six faces      */
+  int32_t cpml;       /* absorbing boundary in the border cells (§2.1):
+                         0: damping (the Cerjan sponge);
+                         1: CPML (Roden and Gedney's convolutional PML) with
+                         d(delta) = d0 (delta/N)^2, d0 = -3 vmax ln(1e-3) /
+                         (2 N h), alpha = pi fpeak (1 - delta/N), kappa = 1,
+                         delta the depth into the layer in cells; no layer on
+                         the free-surface side                             */
+  double fpeak;       /* CPML: source peak frequency, Hz (>= 0; 0 = alpha 0)  */
+  double cpml_vmax;   /* CPML: velocity of d0, m/s (> 0), or 0 = the model's
+                         largest velocity.  The layer's coefficients are held
+                         fixed in the gradient (like dt).                  */
 } wfd_grid;
 
-/* Forward-wavefield management for the gradient (§2.1 "three options"; the
- * disk option is not provided). */
+/* Forward-wavefield management for the gradient (§2.1, the three options:
+ * the whole wavefield in memory, the whole wavefield in secondary storage,
+ * optimal checkpointing).  The secondary store here is host RAM reached over
+ * PCIe (WFD_CKPT_HOST); writing it to a file is left to the caller. */
 enum {
-  WFD_CKPT_FULL = 0,    /* keep w^1 .. w^nt in the workspace                   */
-  WFD_CKPT_REVOLVE = 1  /* keep n_snapshots leapfrog pairs, recompute the rest */
+  WFD_CKPT_FULL = 0,    /* keep w^1 .. w^nt in the device workspace            */
+  WFD_CKPT_REVOLVE = 1, /* keep n_snapshots leapfrog pairs, recompute the rest */
+  WFD_CKPT_HOST = 2     /* keep w^1 .. w^nt in caller-owned pinned host memory;
+                           the device workspace holds a ring of 4 staging
+                           volumes.  Copies run on a second stream of the
+                           context, overlapped with the step kernels, and are
+                           complete when the caller's stream reaches the end of
+                           the call.  The gradient is bitwise that of FULL.   */
 };
 typedef struct {
-  int32_t mode;         /* WFD_CKPT_FULL or WFD_CKPT_REVOLVE                    */
+  int32_t mode;         /* WFD_CKPT_FULL, WFD_CKPT_REVOLVE or WFD_CKPT_HOST     */
   int32_t n_snapshots;  /* REVOLVE: pairs kept (>= 1); 0 = derive from
                            mem_fraction of the device's free memory            */
   double mem_fraction;  /* (0, 1]; like the paper's check_mem (default 0.8)    */
+  void *host_store;     /* HOST: page-locked host buffer (hipHostMalloc, or a
+                           torch tensor made with pin_memory=True) of at least
+                           wfd_host_store_bytes(); slot m-1 receives w^m on the
+                           padded grid as [Nz][Ny][pitch] FP32, pitch = Nx
+                           rounded up to a multiple of 64 (the columns past
+                           Nx are padding).  Other modes: ignored.            */
+  uint64_t host_bytes;  /* HOST: size of host_store in bytes                   */
 } wfd_ckpt;
 
 typedef struct wfd_ctx wfd_ctx;
@@ -127,6 +153,10 @@ wfd_status wfd_set_model(wfd_ctx *ctx, const wfd_grid *grid, const float *vel_de
 wfd_status wfd_workspace_bytes(const wfd_ctx *ctx, int32_t nrec, const wfd_ckpt *ckpt_or_null,
                                size_t *bytes);
 
+/* Bytes of the host store that WFD_CKPT_HOST needs for the context's model:
+ * nt pitched padded volumes of FP32 (nt * Nz * Ny * pitch * 4). */
+wfd_status wfd_host_store_bytes(const wfd_ctx *ctx, size_t *bytes);
+
 /* Forward modeling of one shot (Alg. 1 body; ModelingStep + ReadReceiver).
  *   wavelet_dev   [nt] FP32 source signature f(n dt), device;
  *   src_xyz       host [3] source position, m;
@@ -154,7 +184,10 @@ wfd_status wfd_forward_misfit(wfd_ctx *ctx, const float *wavelet_dev, const doub
 /* Workspace bytes of wfd_forward_misfit for nrec receivers. */
 wfd_status wfd_misfit_workspace_bytes(const wfd_ctx *ctx, int32_t nrec, size_t *bytes);
 
-/* Misfit and velocity gradient of one shot (Alg. 3 body for one shot):
+/* Misfit and velocity gradient of one shot (Alg. 3 body for one shot).
+ * With the CPML boundary only WFD_CKPT_FULL is accepted (the layer's
+ * correction of every step is kept for the imaging condition, on the shell
+ * of points the layer reaches); other modes return WFD_E_ARG.  The steps:
  * forward sweep with recording and wavefield saving, res = d - d_obs,
  * J = 1/2 sum res^2, discrete adjoint sweep (exact transpose of the forward
  * recursion) with the zero-lag cross-correlation imaging condition, then

@@ -6,9 +6,11 @@ space and second order in time, as hand-written HIP kernels for gfx950
 behind a C ABI (include/wfd.h).  PyTorch supplies device memory and streams.
 """
 
-from ._lib import WfdError, LIB_PATH, CKPT_FULL, CKPT_REVOLVE, K_FORWARD, K_ADJOINT, K_OTHER
-from .api import GridSpec, Propagator, ShotBatch, smooth, resample, map_position, cfl_ratio, checkpoint_plan, model_bytes
+from ._lib import (WfdError, LIB_PATH, CKPT_FULL, CKPT_REVOLVE, CKPT_HOST, K_FORWARD, K_ADJOINT,
+                   K_OTHER)
+from .api import (GridSpec, Propagator, ShotBatch, smooth, resample, map_position, cfl_ratio,
+                  checkpoint_plan, model_bytes)
 
-__all__ = ["WfdError", "LIB_PATH", "CKPT_FULL", "CKPT_REVOLVE", "K_FORWARD", "K_ADJOINT",
-           "K_OTHER", "GridSpec", "Propagator", "ShotBatch", "smooth", "resample", "map_position", "cfl_ratio", "checkpoint_plan",
-           "model_bytes"]
+__all__ = ["WfdError", "LIB_PATH", "CKPT_FULL", "CKPT_REVOLVE", "CKPT_HOST", "K_FORWARD",
+           "K_ADJOINT", "K_OTHER", "GridSpec", "Propagator", "ShotBatch", "smooth", "resample",
+           "map_position", "cfl_ratio", "checkpoint_plan", "model_bytes"]

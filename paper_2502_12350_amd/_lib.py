@@ -18,6 +18,7 @@ STATUS_NAMES = {0: "WFD_OK", -1: "WFD_E_ARG", -2: "WFD_E_CFL", -3: "WFD_E_RANGE"
                 -4: "WFD_E_NOMEM", -5: "WFD_E_HIP", -6: "WFD_E_STATE"}
 CKPT_FULL = 0
 CKPT_REVOLVE = 1
+CKPT_HOST = 2
 K_FORWARD, K_ADJOINT, K_OTHER = 0, 1, 2
 CNN_REDUCE_BYTES = 8192
 SMOOTH_LAPLACE, SMOOTH_BESSEL = 1, 2
@@ -29,11 +30,13 @@ class wfd_grid(C.Structure):
                 ("dx", C.c_double), ("dy", C.c_double), ("dz", C.c_double),
                 ("ox", C.c_double), ("oy", C.c_double), ("oz", C.c_double),
                 ("border", C.c_int32), ("dt", C.c_double), ("nt", C.c_int32),
-                ("free_surface", C.c_int32)]
+                ("free_surface", C.c_int32), ("cpml", C.c_int32), ("fpeak", C.c_double),
+                ("cpml_vmax", C.c_double)]
 
 
 class wfd_ckpt(C.Structure):
-    _fields_ = [("mode", C.c_int32), ("n_snapshots", C.c_int32), ("mem_fraction", C.c_double)]
+    _fields_ = [("mode", C.c_int32), ("n_snapshots", C.c_int32), ("mem_fraction", C.c_double),
+                ("host_store", C.c_void_p), ("host_bytes", C.c_uint64)]
 
 
 class wfd_tuning(C.Structure):
@@ -57,6 +60,7 @@ _SIGS = {
     "wfd_model_bytes": (C.c_int, [C.POINTER(wfd_grid), C.c_int32, C.POINTER(C.c_size_t)]),
     "wfd_set_model": (C.c_int, [_P, C.POINTER(wfd_grid), _P, _P, _P, C.c_size_t]),
     "wfd_workspace_bytes": (C.c_int, [_P, C.c_int32, C.POINTER(wfd_ckpt), C.POINTER(C.c_size_t)]),
+    "wfd_host_store_bytes": (C.c_int, [_P, C.POINTER(C.c_size_t)]),
     "wfd_forward": (C.c_int, [_P, _P, _D3, C.c_int32, _D3, _P, _P, _P, C.c_size_t]),
     "wfd_forward_misfit": (C.c_int, [_P, _P, _D3, C.c_int32, _D3, _P, _P, _P, _P, C.c_size_t]),
     "wfd_misfit_workspace_bytes": (C.c_int, [_P, C.c_int32, C.POINTER(C.c_size_t)]),

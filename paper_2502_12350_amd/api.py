@@ -33,11 +33,15 @@ class GridSpec:
     dt: float = 1.0e-3
     nt: int = 1
     free_surface: bool = False
+    cpml: bool = False          # CPML layer in the border cells instead of the sponge
+    fpeak: float = 0.0          # CPML: source peak frequency (Hz), alpha_max = pi fpeak
+    cpml_vmax: float = 0.0      # CPML: velocity of d0 (m/s); 0 = the model's maximum
 
     def c(self) -> wfd_grid:
         return wfd_grid(int(self.nx), int(self.ny), int(self.nz), float(self.dx), float(self.dy),
                         float(self.dz), float(self.ox), float(self.oy), float(self.oz),
-                        int(self.border), float(self.dt), int(self.nt), int(bool(self.free_surface)))
+                        int(self.border), float(self.dt), int(self.nt), int(bool(self.free_surface)),
+                        int(bool(self.cpml)), float(self.fpeak), float(self.cpml_vmax))
 
     @property
     def padded_shape(self) -> Tuple[int, int, int]:
@@ -66,9 +70,19 @@ def _ptr(t) -> Optional[int]:
 
 
 def _ckpt(ckpt) -> wfd_ckpt:
-    """'full' | ('revolve', n_snapshots) | ('revolve', 0, mem_fraction) | wfd_ckpt."""
+    """'full' | ('revolve', n_snapshots) | ('revolve', 0, mem_fraction) |
+    ('host', pinned_cpu_tensor) | wfd_ckpt ('host' alone is resolved by the
+    Propagator, which then keeps a pinned store of its own)."""
     if isinstance(ckpt, wfd_ckpt):
         return ckpt
+    if isinstance(ckpt, tuple) and ckpt[0] == "host":
+        store = ckpt[1]
+        if getattr(store, "is_cuda", True) or not store.is_contiguous():
+            raise ValueError("the host store must be a contiguous CPU tensor (pin_memory=True)")
+        return wfd_ckpt(_lib.CKPT_HOST, 0, 0.8, store.data_ptr(),
+                        store.numel() * store.element_size())
+    if ckpt == "host":
+        return wfd_ckpt(_lib.CKPT_HOST, 0, 0.8, None, 0)
     if ckpt in (None, "full"):
         return wfd_ckpt(_lib.CKPT_FULL, 0, 0.8)
     if isinstance(ckpt, tuple) and ckpt[0] == "revolve":
@@ -173,6 +187,7 @@ class Propagator:
         self.grid: Optional[GridSpec] = None
         self._model = None
         self._work = None
+        self._host = None
 
     def _stream(self):
         return C.c_void_p(self.torch.cuda.current_stream(self.device).cuda_stream)
@@ -244,6 +259,22 @@ class Propagator:
 
     def release_workspace(self):
         self._work = None
+        self._host = None
+
+    def host_store_bytes(self) -> int:
+        """Bytes of the pinned host store of the 'host' checkpoint mode."""
+        n = C.c_size_t()
+        check(self.L.wfd_host_store_bytes(self._ctx, C.byref(n)))
+        return n.value
+
+    def _host_store(self):
+        """A pinned host store of this model's size, kept between calls."""
+        nbytes = self.host_store_bytes()
+        if getattr(self, "_host", None) is None or self._host.numel() * 4 < nbytes:
+            self._host = None
+            self._host = self.torch.empty((nbytes + 3) // 4, dtype=self.torch.float32,
+                                          pin_memory=True)
+        return self._host
 
     def forward(self, wavelet, src_xyz, rec_xyz, *, final: bool = False, seis=None):
         """Seismograms [nrec][nt] (and, if final, [2][Nz][Ny][Nx] = w^nt, w^(nt-1))."""
@@ -317,7 +348,8 @@ class Propagator:
             self._dev(illum, "illum", (g.nz, g.ny, g.nx), torch.float32)
         out_seis = (torch.empty((nrec, g.nt), dtype=torch.float32, device=self.device)
                     if seis else None)
-        ck = _ckpt(ckpt)
+        ck = _ckpt(("host", self._host_store()) if isinstance(ckpt, str) and ckpt == "host"
+                   else ckpt)
         wptr, wbytes = self._workspace(self.workspace_bytes(nrec, ck))
         self._sync_stream()
         check(self.L.wfd_gradient(self._ctx, _ptr(wavelet), _dptr(src), nrec, _dptr(rec),

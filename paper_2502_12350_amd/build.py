@@ -21,7 +21,10 @@ INCLUDE = os.path.join(ROOT, "include")
 BUILD_DIR = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libwfd.so")
 
-SOURCES = ["wfd_step.hip", "wfd_kernels.hip", "wfd_cnn.hip", "wfd_smooth.hip", "wfd_api.cpp", "wfd_plan.cpp"]
+SOURCES = [
+    "wfd_step.hip", "wfd_kernels.hip", "wfd_cnn.hip", "wfd_smooth.hip", "wfd_cpml.hip", "wfd_api.cpp",
+    "wfd_plan.cpp",
+]
 ARCH = "gfx950"
 
 

@@ -60,6 +60,9 @@ constexpr int kMaxBatch = 64;  // shots per wfd_batch
 
 }  // namespace
 
+// Device staging volumes of the host-stored forward wavefield (WFD_CKPT_HOST).
+constexpr int kHostRing = 4;
+
 struct wfd_ctx {
   int device = 0;
   hipStream_t stream = nullptr;
@@ -72,6 +75,9 @@ struct wfd_ctx {
   bool vd = false;
   float *k = nullptr, *m2 = nullptr, *sqrt_rho = nullptr;
   float *gx = nullptr, *gy = nullptr, *gz = nullptr;
+  bool cpml = false;         // CPML layer instead of the sponge
+  wfd::CpmlTables cpml_tab{};
+  wfd::Shell shell{};        // the points the layer's terms reach
 
   // host staging of the receiver tables (kept alive until the upload ends)
   std::vector<char> stage;
@@ -79,6 +85,13 @@ struct wfd_ctx {
   bool upload_pending = false;
 
   wfd::Tuning tuning;  // forward tile shape / z chunking (wfd_set_tuning, wfd_autotune)
+
+  // host-stored forward wavefield (WFD_CKPT_HOST): a copy stream and the
+  // events that order it against the step kernels, created on first use
+  hipStream_t copy_stream = nullptr;
+  hipEvent_t host_ev_step[kHostRing] = {};  // recorded on the compute stream
+  hipEvent_t host_ev_copy[kHostRing] = {};  // recorded on the copy stream
+  hipEvent_t host_ev_end = nullptr;
 
   // profiling
   bool prof = false;
@@ -100,6 +113,7 @@ struct wfd_batch {
   std::vector<wfd::WindowStep> h_wins[2];
   int nblocks = 0, variant = 0, nt = 0;
   bool vd = false;
+  bool fs = false;  // some shot has a free surface
   hipStream_t stream = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
@@ -176,6 +190,12 @@ wfd_status check_grid(const wfd_grid *g) {
   if (g->nt < 1) return fail(WFD_E_ARG, "nt must be >= 1 (got %d)", g->nt);
   if (g->free_surface != 0 && g->free_surface != 1)
     return fail(WFD_E_ARG, "free_surface must be 0 or 1 (got %d)", g->free_surface);
+  if (g->cpml != 0 && g->cpml != 1)
+    return fail(WFD_E_ARG, "cpml must be 0 or 1 (got %d)", g->cpml);
+  if (g->cpml && (!(g->fpeak >= 0) || !std::isfinite(g->fpeak)))
+    return fail(WFD_E_ARG, "fpeak must be finite and >= 0");
+  if (g->cpml && (!(g->cpml_vmax >= 0) || !std::isfinite(g->cpml_vmax)))
+    return fail(WFD_E_ARG, "cpml_vmax must be finite and >= 0");
   const int64_t Nx = (int64_t)g->nx + 2 * g->border, Ny = (int64_t)g->ny + 2 * g->border,
                 Nz = (int64_t)g->nz + 2 * g->border;
   if (Nx > (1 << 24) || Ny > (1 << 24) || Nz > (1 << 24) || Nx * Ny > (int64_t(1) << 30))
@@ -188,6 +208,7 @@ int pitch_of(int Nx) { return (Nx + 63) / 64 * 64; }
 // Model buffer layout (shared by wfd_model_bytes and wfd_set_model).
 struct ModelLayout {
   float *k, *m2, *sqrt_rho, *gx, *gy, *gz, *part_v, *part_m;
+  float *cpml[6];  // a_x, b_x, a_y, b_y, a_z, b_z (CPML only)
   size_t bytes;
 };
 ModelLayout model_layout(const wfd_grid &g, bool vd, void *base) {
@@ -203,8 +224,73 @@ ModelLayout model_layout(const wfd_grid &g, bool vd, void *base) {
   L.gz = cv.take<float>(Nz);
   L.part_v = cv.take<float>(kReducePartials);
   L.part_m = cv.take<float>(kReducePartials);
+  if (g.cpml) {
+    const int len[6] = {Nx, Nx, Ny, Ny, Nz, Nz};
+    for (int i = 0; i < 6; ++i) L.cpml[i] = cv.take<float>(len[i]);
+  }
   L.bytes = align_up(cv.off);
   return L;
+}
+
+// CPML recursive-convolution coefficients along one padded axis: depth delta
+// into the layer, d = d0 (delta/N)^2 with d0 = -3 vmax ln(1e-3) / (2 N h),
+// alpha = pi fpeak (1 - delta/N), b = exp(-(d + alpha) dt),
+// a = d (b - 1) / (d + alpha) (0 outside the layer).  FP64, stored as FP32.
+void cpml_table(int n, int border, double h, double dt, double vmax, double fpeak,
+                bool free_top, std::vector<float> &a, std::vector<float> &b) {
+  const int total = n + 2 * border;
+  a.assign(total, 0.0f);
+  b.assign(total, 1.0f);
+  if (border == 0) return;
+  const double d0 = -3.0 * vmax * std::log(1.0e-3) / (2.0 * border * h);
+  for (int i = 0; i < total; ++i) {
+    const int before = free_top ? 0 : border - i;
+    const int delta = std::max(std::max(before, 0), i - (border + n - 1));
+    if (delta == 0) continue;
+    const double r = (double)delta / border;
+    const double d = d0 * r * r;
+    const double alpha = M_PI * fpeak * (1.0 - r);
+    const double bb = std::exp(-(d + alpha) * dt);
+    b[i] = (float)bb;
+    a[i] = (float)(d * (bb - 1.0) / (d + alpha));
+  }
+}
+
+// The shell: padded points within 4 cells (along an axis) of that axis'
+// layer, i.e. the grid minus the inner box, as up to 6 boxes.
+wfd::Shell make_shell(const wfd_grid &g, int Nx, int Ny, int Nz) {
+  const int N = g.border;
+  auto inner = [&](int n, int total, bool low_layer, int &lo, int &hi) {
+    lo = (N > 0 && low_layer) ? N + wfd::kStencilRadius : 0;
+    hi = N > 0 ? N + n - 1 - wfd::kStencilRadius : total - 1;  // inclusive
+  };
+  int zlo, zhi, ylo, yhi, xlo, xhi;
+  inner(g.nz, Nz, g.free_surface == 0, zlo, zhi);
+  inner(g.ny, Ny, true, ylo, yhi);
+  inner(g.nx, Nx, true, xlo, xhi);
+  wfd::Shell sh{};
+  auto add = [&](int z0, int z1, int y0, int y1, int x0, int x1) {
+    if (z1 <= z0 || y1 <= y0 || x1 <= x0) return;
+    const int b = sh.nbox++;
+    sh.z0[b] = z0, sh.z1[b] = z1, sh.y0[b] = y0, sh.y1[b] = y1, sh.x0[b] = x0, sh.x1[b] = x1;
+  };
+  if (N == 0) {
+    // no layer: empty shell
+  } else if (zlo > zhi || ylo > yhi || xlo > xhi) {
+    add(0, Nz, 0, Ny, 0, Nx);  // the inner box is empty: every point
+  } else {
+    add(0, zlo, 0, Ny, 0, Nx);
+    add(zhi + 1, Nz, 0, Ny, 0, Nx);
+    add(zlo, zhi + 1, 0, ylo, 0, Nx);
+    add(zlo, zhi + 1, yhi + 1, Ny, 0, Nx);
+    add(zlo, zhi + 1, ylo, yhi + 1, 0, xlo);
+    add(zlo, zhi + 1, ylo, yhi + 1, xhi + 1, Nx);
+  }
+  sh.start[0] = 0;
+  for (int b = 0; b < sh.nbox; ++b)
+    sh.start[b + 1] = sh.start[b] + (int64_t)(sh.z1[b] - sh.z0[b]) * (sh.y1[b] - sh.y0[b]) *
+                                        (sh.x1[b] - sh.x0[b]);
+  return sh;
 }
 
 // Sponge profile of one padded axis; free_top: no damping before the model
@@ -235,11 +321,14 @@ struct Work {
   float *res_tm, *P1, *P2, *g, *store;
   double *partial;
   int64_t n_store_vols;
+  float *mem[6];   // CPML memory variables psi_x..z, zeta_x..z (adjoint: mu, nu)
+  float *cstore;   // CPML: correction C^n of every step on the shell (gradient)
   size_t bytes;
 };
 
 int64_t snapshots_for(const wfd_ctx *c, const wfd_ckpt *ck) {
   if (ck->mode == WFD_CKPT_FULL) return c->grid.nt;
+  if (ck->mode == WFD_CKPT_HOST) return 0;
   if (ck->n_snapshots > 0) return ck->n_snapshots;
   size_t free_b = 0, total_b = 0;
   if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) return 0;
@@ -247,6 +336,49 @@ int64_t snapshots_for(const wfd_ctx *c, const wfd_ckpt *ck) {
   const double pair = 2.0 * (double)c->vol * sizeof(float);
   int64_t s = (int64_t)(frac * (double)free_b / pair);
   return std::max<int64_t>(1, std::min<int64_t>(s, c->grid.nt));
+}
+
+wfd_status check_ckpt_mode(const wfd_ckpt *ck) {
+  if (ck->mode != WFD_CKPT_FULL && ck->mode != WFD_CKPT_REVOLVE && ck->mode != WFD_CKPT_HOST)
+    return fail(WFD_E_ARG, "unknown checkpoint mode %d", ck->mode);
+  if (ck->mode == WFD_CKPT_REVOLVE && ck->n_snapshots < 0)
+    return fail(WFD_E_ARG, "n_snapshots must be >= 0");
+  return WFD_OK;
+}
+
+size_t host_store_bytes(const wfd_ctx *c) {
+  return (size_t)c->grid.nt * (size_t)c->vol * sizeof(float);
+}
+
+// The host store of WFD_CKPT_HOST: present, large enough and page-locked
+// (pageable memory would make every copy synchronous).
+wfd_status check_host_store(const wfd_ctx *c, const wfd_ckpt *ck) {
+  if (!ck->host_store) return fail(WFD_E_ARG, "host store is NULL");
+  if (ck->host_bytes < host_store_bytes(c))
+    return fail(WFD_E_NOMEM, "host store has %llu bytes, %zu needed",
+                (unsigned long long)ck->host_bytes, host_store_bytes(c));
+  hipPointerAttribute_t attr{};
+  if (hipPointerGetAttributes(&attr, ck->host_store) != hipSuccess ||
+      attr.type != hipMemoryTypeHost) {
+    (void)hipGetLastError();
+    return fail(WFD_E_ARG, "host store must be page-locked host memory (hipHostMalloc)");
+  }
+  return WFD_OK;
+}
+
+// The copy stream and events of WFD_CKPT_HOST (default priority, non-blocking
+// with respect to the legacy stream).
+wfd_status ensure_copy_stream(wfd_ctx *c) {
+  if (c->host_ev_end) return WFD_OK;
+  if (!c->copy_stream) HIP_TRY(hipStreamCreateWithFlags(&c->copy_stream, hipStreamNonBlocking));
+  for (int i = 0; i < kHostRing; ++i) {
+    if (!c->host_ev_step[i])
+      HIP_TRY(hipEventCreateWithFlags(&c->host_ev_step[i], hipEventDisableTiming));
+    if (!c->host_ev_copy[i])
+      HIP_TRY(hipEventCreateWithFlags(&c->host_ev_copy[i], hipEventDisableTiming));
+  }
+  HIP_TRY(hipEventCreateWithFlags(&c->host_ev_end, hipEventDisableTiming));  // last: marks done
+  return WFD_OK;
 }
 
 enum class WorkKind { Forward, Misfit, Gradient };
@@ -275,11 +407,18 @@ Work work_layout(const wfd_ctx *c, int nrec, WorkKind kind, const wfd_ckpt *ck, 
     w.res_tm = cv.take<float>((size_t)c->grid.nt * std::max(nrec, 1));
     w.partial = cv.take<double>((size_t)std::max(1, wfd::residual_partial_count(nrec, c->grid.nt)));
   }
+  if (c->cpml) {
+    for (int i = 0; i < 6; ++i) w.mem[i] = cv.take<float>((size_t)c->vol);
+    if (kind == WorkKind::Gradient && ck && ck->mode == WFD_CKPT_FULL)
+      w.cstore = cv.take<float>((size_t)c->grid.nt * (size_t)c->shell.start[c->shell.nbox]);
+  }
   if (kind == WorkKind::Gradient) {
     w.P1 = cv.take<float>((size_t)c->vol);
     w.P2 = cv.take<float>((size_t)c->vol);
     w.g = cv.take<float>((size_t)c->vol);
-    w.n_store_vols = ck->mode == WFD_CKPT_FULL ? (int64_t)c->grid.nt : 2 * nsnap;
+    w.n_store_vols = ck->mode == WFD_CKPT_FULL   ? (int64_t)c->grid.nt
+                     : ck->mode == WFD_CKPT_HOST ? (int64_t)kHostRing
+                                                 : 2 * nsnap;
     w.store = cv.take<float>((size_t)w.n_store_vols * (size_t)c->vol);
   }
   w.bytes = align_up(cv.off);
@@ -487,6 +626,13 @@ wfd_status wfd_destroy(wfd_ctx *c) {
   if (c->upload_pending) (void)hipEventSynchronize(c->upload_done);
   if (c->upload_done) (void)hipEventDestroy(c->upload_done);
   for (hipEvent_t e : c->pool) (void)hipEventDestroy(e);
+  if (c->copy_stream) (void)hipStreamSynchronize(c->copy_stream);
+  for (int i = 0; i < kHostRing; ++i) {
+    if (c->host_ev_step[i]) (void)hipEventDestroy(c->host_ev_step[i]);
+    if (c->host_ev_copy[i]) (void)hipEventDestroy(c->host_ev_copy[i]);
+  }
+  if (c->host_ev_end) (void)hipEventDestroy(c->host_ev_end);
+  if (c->copy_stream) (void)hipStreamDestroy(c->copy_stream);
   delete c;
   return WFD_OK;
 }
@@ -527,6 +673,7 @@ wfd_status wfd_set_model(wfd_ctx *c, const wfd_grid *grid, const float *vel,
   c->gx = L.gx;
   c->gy = L.gy;
   c->gz = L.gz;
+  c->cpml = grid->cpml != 0;
 
   // pitch padding of the coefficient volumes is never read by the kernels
   // but is cleared so the buffer holds no stale values
@@ -538,9 +685,12 @@ wfd_status wfd_set_model(wfd_ctx *c, const wfd_grid *grid, const float *vel,
     Timed t(c, WFD_K_OTHER);
     HIP_TRY(wfd::launch_fill_zero(c->m2, c->vol, c->stream));
   }
-  std::vector<float> tx = sponge_table(grid->nx, grid->border);
-  std::vector<float> ty = sponge_table(grid->ny, grid->border);
-  std::vector<float> tz = sponge_table(grid->nz, grid->border, grid->free_surface != 0);
+  // with the CPML layer the sponge tables are all ones (no damping)
+  const int sb = c->cpml ? 0 : grid->border;
+  std::vector<float> tx = sponge_table(grid->nx + 2 * grid->border - 2 * sb, sb);
+  std::vector<float> ty = sponge_table(grid->ny + 2 * grid->border - 2 * sb, sb);
+  std::vector<float> tz =
+      sponge_table(grid->nz + 2 * grid->border - 2 * sb, sb, grid->free_surface != 0);
   HIP_TRY(hipMemcpyAsync(c->gx, tx.data(), tx.size() * 4, hipMemcpyHostToDevice, c->stream));
   HIP_TRY(hipMemcpyAsync(c->gy, ty.data(), ty.size() * 4, hipMemcpyHostToDevice, c->stream));
   HIP_TRY(hipMemcpyAsync(c->gz, tz.data(), tz.size() * 4, hipMemcpyHostToDevice, c->stream));
@@ -574,6 +724,22 @@ wfd_status wfd_set_model(wfd_ctx *c, const wfd_grid *grid, const float *vel,
                 "unstable: dt^2 vmax^2 (Lambda + m2max) / 4 = %g >= 1 (vmax %g, dt %g); "
                 "reduce dt below %g",
                 ratio, vmax, grid->dt, grid->dt / std::sqrt(ratio));
+  if (c->cpml) {
+    const double v = grid->cpml_vmax > 0 ? grid->cpml_vmax : vmax;
+    std::vector<float> ab[6];
+    cpml_table(grid->nx, grid->border, grid->dx, grid->dt, v, grid->fpeak, false, ab[0], ab[1]);
+    cpml_table(grid->ny, grid->border, grid->dy, grid->dt, v, grid->fpeak, false, ab[2], ab[3]);
+    cpml_table(grid->nz, grid->border, grid->dz, grid->dt, v, grid->fpeak,
+               grid->free_surface != 0, ab[4], ab[5]);
+    for (int i = 0; i < 6; ++i)
+      HIP_TRY(hipMemcpyAsync(L.cpml[i], ab[i].data(), ab[i].size() * sizeof(float),
+                             hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    c->cpml_tab = wfd::CpmlTables{L.cpml[0], L.cpml[1], L.cpml[2], L.cpml[3], L.cpml[4],
+                                  L.cpml[5], (float)(1.0 / grid->dx), (float)(1.0 / grid->dy),
+                                  (float)(1.0 / grid->dz)};
+    c->shell = make_shell(*grid, c->Nx, c->Ny, c->Nz);
+  }
   c->has_model = true;
   return WFD_OK;
 }
@@ -592,10 +758,8 @@ wfd_status wfd_workspace_bytes(const wfd_ctx *c, int32_t nrec, const wfd_ckpt *c
   if (nrec < 0) return fail(WFD_E_ARG, "nrec must be >= 0");
   int64_t nsnap = 0;
   if (ck) {
-    if (ck->mode != WFD_CKPT_FULL && ck->mode != WFD_CKPT_REVOLVE)
-      return fail(WFD_E_ARG, "unknown checkpoint mode %d", ck->mode);
-    if (ck->mode == WFD_CKPT_REVOLVE && ck->n_snapshots < 0)
-      return fail(WFD_E_ARG, "n_snapshots must be >= 0");
+    wfd_status s = check_ckpt_mode(ck);
+    if (s != WFD_OK) return s;
     ScopedDevice sd(c->device);
     nsnap = snapshots_for(c, ck);
   }
@@ -604,7 +768,50 @@ wfd_status wfd_workspace_bytes(const wfd_ctx *c, int32_t nrec, const wfd_ckpt *c
   return WFD_OK;
 }
 
+wfd_status wfd_host_store_bytes(const wfd_ctx *c, size_t *bytes) {
+  if (!c || !bytes) return fail(WFD_E_ARG, "NULL argument");
+  if (!c->has_model) return fail(WFD_E_STATE, "no model: call wfd_set_model first");
+  *bytes = host_store_bytes(c);
+  return WFD_OK;
+}
+
 namespace {
+
+// The CPML layer's share of forward step n (after the step kernel wrote out
+// from cur): memory variables, the correction k C added to out, C kept in
+// cstore when given, and the receivers read from out afterwards.
+wfd_status cpml_forward_terms(wfd_ctx *c, const wfd::StepGrid &g, const Work &w,
+                              const float *cur, float *out, float *cstore, int nrec, int n) {
+  Timed t(c, WFD_K_OTHER);
+  HIP_TRY(wfd::launch_cpml_psi(g, c->cpml_tab, c->shell, cur, w.mem[0], w.mem[1], w.mem[2],
+                               c->stream));
+  HIP_TRY(wfd::launch_cpml_zeta(g, c->cpml_tab, c->shell, cur, w.mem[0], w.mem[1], w.mem[2],
+                                w.mem[3], w.mem[4], w.mem[5], out, cstore, c->stream));
+  if (nrec > 0)
+    HIP_TRY(wfd::launch_record(out, w.rec_idx, w.rec_scale, nrec, n, w.seis_tm, c->stream));
+  return WFD_OK;
+}
+
+// The CPML layer's share of adjoint step m: nu and mu from phi^{m+1} (phi1)
+// before the step kernel, then (pre = false) the correction of phi^m and the
+// imaging term phi^{m+1} C^m.
+wfd_status cpml_adjoint_terms(wfd_ctx *c, const wfd::StepGrid &g, const Work &w,
+                              const float *phi1, float *phi, int m, bool pre) {
+  Timed t(c, WFD_K_OTHER);
+  float *const *v = w.mem;  // mu = v[0..2], nu = v[3..5]
+  if (pre) {
+    HIP_TRY(wfd::launch_cpml_nu(g, c->cpml_tab, c->shell, phi1, v[3], v[4], v[5], c->stream));
+    HIP_TRY(wfd::launch_cpml_mu(g, c->cpml_tab, c->shell, phi1, v[3], v[4], v[5], v[0], v[1],
+                                v[2], c->stream));
+    return WFD_OK;
+  }
+  const float *cst = (m < c->grid.nt && w.cstore)
+                         ? w.cstore + (size_t)m * (size_t)c->shell.start[c->shell.nbox]
+                         : nullptr;
+  HIP_TRY(wfd::launch_cpml_adjoint(g, c->cpml_tab, c->shell, v[3], v[4], v[5], v[0], v[1], v[2],
+                                   phi, phi1, cst, w.g, c->stream));
+  return WFD_OK;
+}
 
 // Forward sweep of one shot; optionally the trace output, the final states and
 // the misfit against observed data (then the workspace also holds the residual).
@@ -628,13 +835,19 @@ wfd_status forward_core(wfd_ctx *c, const float *wavelet, const double src_xyz[3
   const wfd::StepGrid g = step_grid(c);
   const wfd::RecTable rt = rec_table(w, nrec);
   const wfd::Source src{src_idx, w.sigma, wavelet};
+  if (c->cpml)
+    for (float *m : w.mem)
+      if ((s = zero(c, m, c->vol)) != WFD_OK) return s;
   float *cur = w.W1, *prev = w.W2;
   for (int n = 0; n < c->grid.nt; ++n) {
     {
       Timed t(c, WFD_K_FORWARD);
-      HIP_TRY(wfd::launch_forward_step(g, cur, prev, prev, src, n, nrec > 0 ? &rt : nullptr,
-                                       w.rec_scale, w.seis_tm, c->tuning, c->stream));
+      HIP_TRY(wfd::launch_forward_step(g, cur, prev, prev, src, n,
+                                       (nrec > 0 && !c->cpml) ? &rt : nullptr, w.rec_scale,
+                                       w.seis_tm, c->tuning, c->stream));
     }
+    if (c->cpml && (s = cpml_forward_terms(c, g, w, cur, prev, nullptr, nrec, n)) != WFD_OK)
+      return s;
     std::swap(cur, prev);
   }
   if (nrec > 0 && seis) {
@@ -689,18 +902,23 @@ wfd_status wfd_gradient(wfd_ctx *c, const float *wavelet, const double src_xyz[3
   wfd_status s = common_checks(c, wavelet, src_xyz, nrec, rec_xyz);
   if (s != WFD_OK) return s;
   if (!ck) return fail(WFD_E_ARG, "checkpoint policy is NULL");
-  if (ck->mode != WFD_CKPT_FULL && ck->mode != WFD_CKPT_REVOLVE)
-    return fail(WFD_E_ARG, "unknown checkpoint mode %d", ck->mode);
-  if (ck->mode == WFD_CKPT_REVOLVE && ck->n_snapshots < 0)
-    return fail(WFD_E_ARG, "n_snapshots must be >= 0");
+  if ((s = check_ckpt_mode(ck)) != WFD_OK) return s;
   if (nrec > 0 && !dobs) return fail(WFD_E_ARG, "observed data is NULL");
   if (!misfit || !grad) return fail(WFD_E_ARG, "misfit / gradient output is NULL");
   if (!work) return fail(WFD_E_ARG, "workspace is NULL");
   if ((uintptr_t)work % kAlign) return fail(WFD_E_ARG, "workspace must be 256-byte aligned");
   ScopedDevice sd(c->device);
+  if (c->cpml && ck->mode != WFD_CKPT_FULL)
+    return fail(WFD_E_ARG, "the CPML gradient needs full storage (WFD_CKPT_FULL)");
+  if (ck->mode == WFD_CKPT_HOST) {
+    if ((s = check_host_store(c, ck)) != WFD_OK) return s;
+    if ((s = ensure_copy_stream(c)) != WFD_OK) return s;
+  }
   int64_t nsnap = 0;
   if (ck->mode == WFD_CKPT_FULL) {
     nsnap = c->grid.nt;
+  } else if (ck->mode == WFD_CKPT_HOST) {
+    nsnap = 0;
   } else if (ck->n_snapshots > 0) {
     nsnap = ck->n_snapshots;
   } else {
@@ -750,20 +968,29 @@ wfd_status wfd_gradient(wfd_ctx *c, const float *wavelet, const double src_xyz[3
     return WFD_OK;
   };
   auto adjoint = [&](int m, const float *wm) -> wfd_status {
+    if (c->cpml && (s = cpml_adjoint_terms(c, g, w, A1, A2, m, true)) != WFD_OK) return s;
     {
       Timed t(c, WFD_K_ADJOINT);
       HIP_TRY(wfd::launch_adjoint_step(c->tuning, g, A1, A2, A2, rt, w.res_tm, m, wm, w.g, illum,
                                        c->grid.border, c->grid.nx, c->grid.ny, c->grid.nz,
                                        c->stream));
     }
+    if (c->cpml && (s = cpml_adjoint_terms(c, g, w, A1, A2, m, false)) != WFD_OK) return s;
     std::swap(A1, A2);
     return WFD_OK;
   };
   auto fwd = [&](const float *cur, const float *prev, float *out, int n, bool rec) -> wfd_status {
-    Timed t(c, WFD_K_FORWARD);
-    HIP_TRY(wfd::launch_forward_step(g, cur, prev, out, src, n,
-                                     (rec && nrec > 0) ? &rt : nullptr, w.rec_scale, w.seis_tm,
-                                     c->tuning, c->stream));
+    {
+      Timed t(c, WFD_K_FORWARD);
+      HIP_TRY(wfd::launch_forward_step(g, cur, prev, out, src, n,
+                                       (rec && nrec > 0 && !c->cpml) ? &rt : nullptr, w.rec_scale,
+                                       w.seis_tm, c->tuning, c->stream));
+    }
+    if (c->cpml) {  // full storage only: every step is recorded once, in order
+      float *cst = w.cstore + (size_t)n * (size_t)c->shell.start[c->shell.nbox];
+      if ((s = cpml_forward_terms(c, g, w, cur, out, cst, rec ? nrec : 0, n)) != WFD_OK)
+        return s;
+    }
     return WFD_OK;
   };
 
@@ -774,11 +1001,61 @@ wfd_status wfd_gradient(wfd_ctx *c, const float *wavelet, const double src_xyz[3
       if (m < 0) return w.W2;
       return w.store + (size_t)(m - 1) * (size_t)c->vol;
     };
+    if (c->cpml)
+      for (float *m : w.mem)
+        if ((s = zero(c, m, c->vol)) != WFD_OK) return s;
     for (int n = 0; n < nt; ++n)
       if ((s = fwd(S(n), S(n - 1), S(n + 1), n, true)) != WFD_OK) return s;
     if ((s = residual()) != WFD_OK) return s;
+    if (c->cpml)  // the adjoint's mu and nu start at zero
+      for (float *m : w.mem)
+        if ((s = zero(c, m, c->vol)) != WFD_OK) return s;
     for (int m = nt; m >= 1; --m)
       if ((s = adjoint(m, S(m))) != WFD_OK) return s;
+  } else if (ck->mode == WFD_CKPT_HOST) {
+    // w^m (m >= 1) is staged in D[(m - 1) % R] and kept in host slot m - 1.
+    // Forward: once the step that writes D[i] is done, the copy stream moves
+    // it to the host; the step that next writes D[i] waits for that copy.
+    // Adjoint (m = nt .. 1): the last R states are still staged; w^(m-R) is
+    // fetched into D[i] as soon as the adjoint step that read w^m from D[i]
+    // is done, so each fetch overlaps R - 1 adjoint steps.
+    const int R = kHostRing;
+    float *D[kHostRing];
+    for (int i = 0; i < R; ++i) D[i] = w.store + (size_t)i * (size_t)c->vol;
+    float *host = static_cast<float *>(ck->host_store);
+    const size_t vbytes = (size_t)c->vol * sizeof(float);
+    hipStream_t cs = c->copy_stream;
+    auto S = [&](int m) -> float * {
+      if (m == 0) return w.W1;
+      if (m < 0) return w.W2;
+      return D[(m - 1) % R];
+    };
+    for (int n = 0; n < nt; ++n) {
+      const int i = n % R;  // receives w^(n+1)
+      if (n >= R) HIP_TRY(hipStreamWaitEvent(c->stream, c->host_ev_copy[i], 0));
+      if ((s = fwd(S(n), S(n - 1), D[i], n, true)) != WFD_OK) return s;
+      HIP_TRY(hipEventRecord(c->host_ev_step[i], c->stream));
+      HIP_TRY(hipStreamWaitEvent(cs, c->host_ev_step[i], 0));
+      HIP_TRY(hipMemcpyAsync(host + (size_t)n * (size_t)c->vol, D[i], vbytes,
+                             hipMemcpyDeviceToHost, cs));
+      HIP_TRY(hipEventRecord(c->host_ev_copy[i], cs));
+    }
+    if ((s = residual()) != WFD_OK) return s;
+    for (int m = nt; m >= 1; --m) {
+      const int i = (m - 1) % R;
+      if (m <= nt - R) HIP_TRY(hipStreamWaitEvent(c->stream, c->host_ev_copy[i], 0));
+      if ((s = adjoint(m, D[i])) != WFD_OK) return s;
+      if (m - R >= 1) {
+        HIP_TRY(hipEventRecord(c->host_ev_step[i], c->stream));
+        HIP_TRY(hipStreamWaitEvent(cs, c->host_ev_step[i], 0));
+        HIP_TRY(hipMemcpyAsync(D[i], host + (size_t)(m - R - 1) * (size_t)c->vol, vbytes,
+                               hipMemcpyHostToDevice, cs));
+        HIP_TRY(hipEventRecord(c->host_ev_copy[i], cs));
+      }
+    }
+    // the caller's stream passes the end of the call only after every copy
+    HIP_TRY(hipEventRecord(c->host_ev_end, cs));
+    HIP_TRY(hipStreamWaitEvent(c->stream, c->host_ev_end, 0));
   } else {
     std::vector<int32_t> plan;
     int64_t nsteps = 0;
@@ -1004,6 +1281,7 @@ wfd_status wfd_batch_create(wfd_batch **out, int32_t nshot, wfd_ctx *const *ctxs
     if (c->stream != c0->stream) return fail(WFD_E_ARG, "shot %d: contexts must share one stream", i);
     if (c->grid.nt != c0->grid.nt) return fail(WFD_E_ARG, "shot %d: nt differs", i);
     if (c->vd != c0->vd) return fail(WFD_E_ARG, "shot %d: density mode differs", i);
+    if (c->cpml) return fail(WFD_E_ARG, "shot %d: batches take sponge boundaries only", i);
     if (nrec[i] < 0 || (nrec[i] > 0 && (!rec_xyz || !rec_xyz[i] || !seis || !seis[i])))
       return fail(WFD_E_ARG, "shot %d: receivers / output missing", i);
     if (!work[i] || (uintptr_t)work[i] % kAlign)
@@ -1017,6 +1295,7 @@ wfd_status wfd_batch_create(wfd_batch **out, int32_t nshot, wfd_ctx *const *ctxs
   b->stream = c0->stream;
   b->nt = c0->grid.nt;
   b->vd = c0->vd;
+  for (int i = 0; i < nshot; ++i) b->fs = b->fs || ctxs[i]->grid.free_surface != 0;
   b->variant = c0->tuning.variant;
   b->h_wins[0].resize(nshot);
   b->h_wins[1].resize(nshot);
@@ -1099,7 +1378,7 @@ wfd_status batch_enqueue(wfd_batch *b) {
   for (int n = 0; n < b->nt; ++n) {
     Timed t(c0, WFD_K_FORWARD);
     HIP_TRY(wfd::launch_forward_multi(b->d_wins[n & 1], nwin, b->nblocks, n, b->variant, b->vd,
-                                      b->stream));
+                                      b->fs, b->stream));
   }
   for (int i = 0; i < nwin; ++i)
     if (b->nrec[i] > 0)

@@ -1,0 +1,319 @@
+// CPML absorbing layer (§2.1: the convolutional PML of Roden and Gedney, the
+// paper's alternative to damping), on the second-order equation.
+//
+// In the layer each second derivative is taken in stretched coordinates,
+// d2/dx~2 w = D2 w + D1 psi + zeta, with the recursive convolutions
+//   psi_d  = b_d psi_d  + a_d D1_d w
+//   zeta_d = b_d zeta_d + a_d (D2_d w + D1_d psi_d)
+// so the leapfrog step gains k C with C = sum_d (D1_d psi_d + zeta_d).  The
+// step kernels do everything else (with unit sponge tables); these kernels
+// add the layer's terms on the shell, the points within reach of them.  The
+// adjoint is the exact transpose:
+//   nu_d = phi^{m+1} + b_d nu_d,   mu_d = b_d mu_d - D1_d (a_d nu_d + phi^{m+1}),
+//   phi^m += k sum_d [D2_d (a_d nu_d) - D1_d (a_d mu_d)],
+// and the imaging condition gains phi^{m+1} C^m.
+//
+// D1 is the eighth-order central first difference (4/5, -1/5, 4/105, -1/280)
+// and D2 the second difference of L; cells outside the padded grid are zero,
+// and D2 along z reads the free surface's negated image like L does.  These
+// kernels are gathers over a few hundred million points at most and are
+// bound by L2 traffic, not by their arithmetic.
+#include <hip/hip_runtime.h>
+
+#include <stdint.h>
+
+#include "wfd_internal.h"
+
+namespace wfd {
+namespace {
+
+__device__ __forceinline__ float d1c(int j) {
+  return j == 1 ? 0.8f : j == 2 ? -0.2f : j == 3 ? (float)(4.0 / 105.0) : (float)(-1.0 / 280.0);
+}
+__device__ __forceinline__ float d2c(int j) {
+  return j == 0   ? (float)(-205.0 / 72.0)
+         : j == 1 ? 1.6f
+         : j == 2 ? -0.2f
+         : j == 3 ? (float)(8.0 / 315.0)
+                  : (float)(-1.0 / 560.0);
+}
+
+__device__ __forceinline__ int64_t lin(const StepGrid &g, int x, int y, int z) {
+  return (int64_t)z * g.plane + (int64_t)y * g.pitch + x;
+}
+
+// Shell point q -> (x, y, z).
+__device__ __forceinline__ void decode(const Shell &sh, int64_t q, int &x, int &y, int &z) {
+  int b = 0;
+  while (b + 1 < sh.nbox && q >= sh.start[b + 1]) ++b;
+  const int64_t l = q - sh.start[b];
+  const int nxb = sh.x1[b] - sh.x0[b], nyb = sh.y1[b] - sh.y0[b];
+  x = sh.x0[b] + (int)(l % nxb);
+  const int64_t r = l / nxb;
+  y = sh.y0[b] + (int)(r % nyb);
+  z = sh.z0[b] + (int)(r / nyb);
+}
+
+// A field along one axis through (x, y, z), optionally weighted by that axis'
+// a table, zero outside the grid; with `image`, z planes above the free
+// surface read the negated mirror (as L does).
+struct Line {
+  const float *u;
+  const float *a;  // weight per index along the axis, or nullptr
+  int64_t base;    // linear index of the point
+  int64_t stride;  // elements between neighbours along the axis
+  int i, n;        // index along the axis and the axis length
+  __device__ __forceinline__ float operator()(int j) const {  // value at offset j
+    const int ii = i + j;
+    if (ii < 0 || ii >= n) return 0.0f;
+    const float v = u[base + (int64_t)j * stride];
+    return a ? a[ii] * v : v;
+  }
+};
+
+__device__ __forceinline__ float first_diff(const Line &f) {
+  float s = 0.0f;
+#pragma unroll
+  for (int j = 1; j <= 4; ++j) s += d1c(j) * (f(j) - f(-j));
+  return s;
+}
+
+// Second difference along the line; for z lines with a free surface at zs,
+// offsets landing above it read -value(2 zs - z').
+__device__ __forceinline__ float second_diff(const Line &f, int zs) {
+  float s = d2c(0) * f(0);
+#pragma unroll
+  for (int j = 1; j <= 4; ++j) {
+    const float up = f(j);
+    float dn;
+    const int zz = f.i - j;
+    if (zz < zs) {
+      const int zm = 2 * zs - zz;  // image plane
+      dn = zm < f.n ? -f(zm - f.i) : 0.0f;
+    } else {
+      dn = f(-j);
+    }
+    s += d2c(j) * (up + dn);
+  }
+  return s;
+}
+
+struct Axes {
+  Line x, y, z;
+};
+__device__ __forceinline__ Axes lines(const StepGrid &g, const float *u, const float *ax,
+                                      const float *ay, const float *az, int x, int y, int z) {
+  const int64_t p = lin(g, x, y, z);
+  return Axes{Line{u, ax, p, 1, x, g.nx}, Line{u, ay, p, g.pitch, y, g.ny},
+              Line{u, az, p, g.plane, z, g.nz}};
+}
+
+constexpr int kThreads = 256;
+
+__global__ void __launch_bounds__(kThreads)
+    k_cpml_psi(StepGrid g, CpmlTables t, Shell sh, const float *__restrict__ w, float *px,
+               float *py, float *pz) {
+  const int64_t total = sh.start[sh.nbox];
+  for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < total;
+       q += (int64_t)gridDim.x * blockDim.x) {
+    int x, y, z;
+    decode(sh, q, x, y, z);
+    const int64_t p = lin(g, x, y, z);
+    const Axes L = lines(g, w, nullptr, nullptr, nullptr, x, y, z);
+    float a = t.ax[x];
+    if (a != 0.0f) px[p] = t.bx[x] * px[p] + a * (first_diff(L.x) * t.ihx);
+    a = t.ay[y];
+    if (a != 0.0f) py[p] = t.by[y] * py[p] + a * (first_diff(L.y) * t.ihy);
+    a = t.az[z];
+    if (a != 0.0f) pz[p] = t.bz[z] * pz[p] + a * (first_diff(L.z) * t.ihz);
+  }
+}
+
+__global__ void __launch_bounds__(kThreads)
+    k_cpml_zeta(StepGrid g, CpmlTables t, Shell sh, const float *__restrict__ w,
+                const float *__restrict__ px, const float *__restrict__ py,
+                const float *__restrict__ pz, float *zx, float *zy, float *zz, float *out,
+                float *cstore) {
+  const int64_t total = sh.start[sh.nbox];
+  for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < total;
+       q += (int64_t)gridDim.x * blockDim.x) {
+    int x, y, z;
+    decode(sh, q, x, y, z);
+    const int64_t p = lin(g, x, y, z);
+    const Axes W = lines(g, w, nullptr, nullptr, nullptr, x, y, z);
+    float C = 0.0f;
+    {
+      const float d1p = first_diff(Line{px, nullptr, p, 1, x, g.nx}) * t.ihx;
+      C += d1p;
+      const float a = t.ax[x];
+      if (a != 0.0f) {
+        const float v = t.bx[x] * zx[p] + a * (second_diff(W.x, kNoSurface) * g.cx + d1p);
+        zx[p] = v;
+        C += v;
+      }
+    }
+    {
+      const float d1p = first_diff(Line{py, nullptr, p, g.pitch, y, g.ny}) * t.ihy;
+      C += d1p;
+      const float a = t.ay[y];
+      if (a != 0.0f) {
+        const float v = t.by[y] * zy[p] + a * (second_diff(W.y, kNoSurface) * g.cy + d1p);
+        zy[p] = v;
+        C += v;
+      }
+    }
+    {
+      const float d1p = first_diff(Line{pz, nullptr, p, g.plane, z, g.nz}) * t.ihz;
+      C += d1p;
+      const float a = t.az[z];
+      if (a != 0.0f) {
+        const float v = t.bz[z] * zz[p] + a * (second_diff(W.z, g.zs) * g.cz + d1p);
+        zz[p] = v;
+        C += v;
+      }
+    }
+    if (z > g.zs) out[p] += g.k[p] * C;
+    if (cstore) cstore[q] = C;
+  }
+}
+
+__global__ void __launch_bounds__(kThreads)
+    k_cpml_nu(StepGrid g, CpmlTables t, Shell sh, const float *__restrict__ phi1, float *nx_,
+              float *ny_, float *nz_) {
+  const int64_t total = sh.start[sh.nbox];
+  for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < total;
+       q += (int64_t)gridDim.x * blockDim.x) {
+    int x, y, z;
+    decode(sh, q, x, y, z);
+    const int64_t p = lin(g, x, y, z);
+    const float f = phi1[p];
+    if (t.ax[x] != 0.0f) nx_[p] = f + t.bx[x] * nx_[p];
+    if (t.ay[y] != 0.0f) ny_[p] = f + t.by[y] * ny_[p];
+    if (t.az[z] != 0.0f) nz_[p] = f + t.bz[z] * nz_[p];
+  }
+}
+
+__global__ void __launch_bounds__(kThreads)
+    k_cpml_mu(StepGrid g, CpmlTables t, Shell sh, const float *__restrict__ phi1,
+              const float *__restrict__ nx_, const float *__restrict__ ny_,
+              const float *__restrict__ nz_, float *mx, float *my, float *mz) {
+  const int64_t total = sh.start[sh.nbox];
+  for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < total;
+       q += (int64_t)gridDim.x * blockDim.x) {
+    int x, y, z;
+    decode(sh, q, x, y, z);
+    const int64_t p = lin(g, x, y, z);
+    const Axes F = lines(g, phi1, nullptr, nullptr, nullptr, x, y, z);
+    // D1 of (a nu + phi1) = D1 of a nu + D1 of phi1
+    if (t.ax[x] != 0.0f) {
+      const float d = first_diff(Line{nx_, t.ax, p, 1, x, g.nx}) + first_diff(F.x);
+      mx[p] = t.bx[x] * mx[p] - d * t.ihx;
+    }
+    if (t.ay[y] != 0.0f) {
+      const float d = first_diff(Line{ny_, t.ay, p, g.pitch, y, g.ny}) + first_diff(F.y);
+      my[p] = t.by[y] * my[p] - d * t.ihy;
+    }
+    if (t.az[z] != 0.0f) {
+      const float d = first_diff(Line{nz_, t.az, p, g.plane, z, g.nz}) + first_diff(F.z);
+      mz[p] = t.bz[z] * mz[p] - d * t.ihz;
+    }
+  }
+}
+
+__global__ void __launch_bounds__(kThreads)
+    k_cpml_adjoint(StepGrid g, CpmlTables t, Shell sh, const float *__restrict__ nx_,
+                   const float *__restrict__ ny_, const float *__restrict__ nz_,
+                   const float *__restrict__ mx, const float *__restrict__ my,
+                   const float *__restrict__ mz, float *phi, const float *__restrict__ phi1,
+                   const float *__restrict__ cstore, float *grad) {
+  const int64_t total = sh.start[sh.nbox];
+  for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < total;
+       q += (int64_t)gridDim.x * blockDim.x) {
+    int x, y, z;
+    decode(sh, q, x, y, z);
+    const int64_t p = lin(g, x, y, z);
+    const float corr =
+        second_diff(Line{nx_, t.ax, p, 1, x, g.nx}, kNoSurface) * g.cx -
+        first_diff(Line{mx, t.ax, p, 1, x, g.nx}) * t.ihx +
+        second_diff(Line{ny_, t.ay, p, g.pitch, y, g.ny}, kNoSurface) * g.cy -
+        first_diff(Line{my, t.ay, p, g.pitch, y, g.ny}) * t.ihy +
+        second_diff(Line{nz_, t.az, p, g.plane, z, g.nz}, g.zs) * g.cz -
+        first_diff(Line{mz, t.az, p, g.plane, z, g.nz}) * t.ihz;
+    if (z > g.zs) phi[p] += g.k[p] * corr;
+    if (cstore) grad[p] += phi1[p] * cstore[q];
+  }
+}
+
+__global__ void k_record(const float *__restrict__ field, const int64_t *__restrict__ idx,
+                         const float *__restrict__ scale, int nrec, int n,
+                         float *__restrict__ seis_tm) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r < nrec) seis_tm[(int64_t)n * nrec + r] = scale[r] * field[idx[r]];
+}
+
+unsigned blocks_for(const Shell &sh) {
+  const int64_t total = sh.start[sh.nbox];
+  const int64_t b = (total + kThreads - 1) / kThreads;
+  return (unsigned)(b < 1 ? 1 : (b > 16384 ? 16384 : b));
+}
+
+}  // namespace
+
+hipError_t launch_cpml_psi(const StepGrid &g, const CpmlTables &t, const Shell &sh,
+                           const float *cur, float *psi_x, float *psi_y, float *psi_z,
+                           hipStream_t stream) {
+  if (sh.start[sh.nbox] == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_cpml_psi, dim3(blocks_for(sh)), dim3(kThreads), 0, stream, g, t, sh, cur,
+                     psi_x, psi_y, psi_z);
+  return hipGetLastError();
+}
+
+hipError_t launch_cpml_zeta(const StepGrid &g, const CpmlTables &t, const Shell &sh,
+                            const float *cur, const float *psi_x, const float *psi_y,
+                            const float *psi_z, float *zeta_x, float *zeta_y, float *zeta_z,
+                            float *out, float *cstore, hipStream_t stream) {
+  if (sh.start[sh.nbox] == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_cpml_zeta, dim3(blocks_for(sh)), dim3(kThreads), 0, stream, g, t, sh, cur,
+                     psi_x, psi_y, psi_z, zeta_x, zeta_y, zeta_z, out, cstore);
+  return hipGetLastError();
+}
+
+hipError_t launch_cpml_nu(const StepGrid &g, const CpmlTables &t, const Shell &sh,
+                          const float *phi1, float *nu_x, float *nu_y, float *nu_z,
+                          hipStream_t stream) {
+  if (sh.start[sh.nbox] == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_cpml_nu, dim3(blocks_for(sh)), dim3(kThreads), 0, stream, g, t, sh, phi1,
+                     nu_x, nu_y, nu_z);
+  return hipGetLastError();
+}
+
+hipError_t launch_cpml_mu(const StepGrid &g, const CpmlTables &t, const Shell &sh,
+                          const float *phi1, const float *nu_x, const float *nu_y,
+                          const float *nu_z, float *mu_x, float *mu_y, float *mu_z,
+                          hipStream_t stream) {
+  if (sh.start[sh.nbox] == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_cpml_mu, dim3(blocks_for(sh)), dim3(kThreads), 0, stream, g, t, sh, phi1,
+                     nu_x, nu_y, nu_z, mu_x, mu_y, mu_z);
+  return hipGetLastError();
+}
+
+hipError_t launch_cpml_adjoint(const StepGrid &g, const CpmlTables &t, const Shell &sh,
+                               const float *nu_x, const float *nu_y, const float *nu_z,
+                               const float *mu_x, const float *mu_y, const float *mu_z,
+                               float *phi, const float *phi1, const float *cstore, float *grad,
+                               hipStream_t stream) {
+  if (sh.start[sh.nbox] == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_cpml_adjoint, dim3(blocks_for(sh)), dim3(kThreads), 0, stream, g, t, sh,
+                     nu_x, nu_y, nu_z, mu_x, mu_y, mu_z, phi, phi1, cstore, grad);
+  return hipGetLastError();
+}
+
+hipError_t launch_record(const float *field, const int64_t *idx, const float *scale, int nrec,
+                         int n, float *seis_tm, hipStream_t stream) {
+  if (nrec <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_record, dim3((unsigned)((nrec + 255) / 256)), dim3(256), 0, stream, field,
+                     idx, scale, nrec, n, seis_tm);
+  return hipGetLastError();
+}
+
+}  // namespace wfd

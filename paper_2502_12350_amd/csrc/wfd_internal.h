@@ -86,8 +86,9 @@ hipError_t launch_forward_step(const StepGrid &g, const float *cur, const float 
 int forward_tile_map(const StepGrid &g, const Tuning &tu, TileMap *map);
 
 // One step of every window in wins[0..nwin) (device array), nblocks blocks.
+// fs: some window has a free surface (selects the kernels with image loads).
 hipError_t launch_forward_multi(const WindowStep *wins, int nwin, int nblocks, int n, int variant,
-                                bool vd, hipStream_t stream);
+                                bool vd, bool fs, hipStream_t stream);
 
 hipError_t launch_adjoint_step(const Tuning &tu, const StepGrid &g, const float *cur,
                                const float *prev, float *out,
@@ -163,5 +164,55 @@ hipError_t launch_cg_start(const float *g, float *r, float *x, int64_t n, double
                            hipStream_t stream);
 hipError_t launch_resample(const float *in, int nrec, int nt_in, double dt_in, float *out,
                            int nt_out, double dt_out, int sinc, hipStream_t stream);
+
+// ---- CPML absorbing layer (wfd_cpml.hip) ----
+constexpr int kStencilRadius = 4;  // reach of the eighth-order differences
+// Recursive-convolution coefficients a, b per padded index of each axis.
+struct CpmlTables {
+  const float *ax, *bx, *ay, *by, *az, *bz;
+  float ihx, ihy, ihz;  // 1 / h per axis
+};
+// The points the layer's terms reach: the padded grid minus the inner box
+// more than 4 cells from every layer, as up to 6 boxes [lo, hi) in (z, y, x).
+// Point q of the shell lies in the box b with start[b] <= q < start[b + 1],
+// at offset q - start[b] in x-fastest order.
+constexpr int kShellBoxes = 6;
+struct Shell {
+  int nbox;
+  int z0[kShellBoxes], z1[kShellBoxes], y0[kShellBoxes], y1[kShellBoxes];
+  int x0[kShellBoxes], x1[kShellBoxes];
+  int64_t start[kShellBoxes + 1];
+};
+// Forward: psi_d = b psi_d + a D1_d w (cur) on the layer.
+hipError_t launch_cpml_psi(const StepGrid &g, const CpmlTables &t, const Shell &sh,
+                           const float *cur, float *psi_x, float *psi_y, float *psi_z,
+                           hipStream_t stream);
+// Forward: zeta_d = b zeta_d + a (D2_d w + D1_d psi_d) on the layer; C = sum_d
+// (D1_d psi_d + zeta_d); out += k C below the free surface; C to cstore[q]
+// when cstore is given.
+hipError_t launch_cpml_zeta(const StepGrid &g, const CpmlTables &t, const Shell &sh,
+                            const float *cur, const float *psi_x, const float *psi_y,
+                            const float *psi_z, float *zeta_x, float *zeta_y, float *zeta_z,
+                            float *out, float *cstore, hipStream_t stream);
+// Adjoint: nu_d = phi1 + b nu_d on the layer.
+hipError_t launch_cpml_nu(const StepGrid &g, const CpmlTables &t, const Shell &sh,
+                          const float *phi1, float *nu_x, float *nu_y, float *nu_z,
+                          hipStream_t stream);
+// Adjoint: mu_d = b mu_d - D1_d (a nu_d + phi1) on the layer.
+hipError_t launch_cpml_mu(const StepGrid &g, const CpmlTables &t, const Shell &sh,
+                          const float *phi1, const float *nu_x, const float *nu_y,
+                          const float *nu_z, float *mu_x, float *mu_y, float *mu_z,
+                          hipStream_t stream);
+// Adjoint: phi += k sum_d [D2_d (a nu_d) - D1_d (a mu_d)] below the free
+// surface; g += phi1 C (C from cstore) when cstore is given.
+hipError_t launch_cpml_adjoint(const StepGrid &g, const CpmlTables &t, const Shell &sh,
+                               const float *nu_x, const float *nu_y, const float *nu_z,
+                               const float *mu_x, const float *mu_y, const float *mu_z,
+                               float *phi, const float *phi1, const float *cstore, float *grad,
+                               hipStream_t stream);
+// seis_tm[n][r] = scale[r] field[idx[r]] (receivers read after the layer's
+// correction).
+hipError_t launch_record(const float *field, const int64_t *idx, const float *scale, int nrec,
+                         int n, float *seis_tm, hipStream_t stream);
 
 }  // namespace wfd

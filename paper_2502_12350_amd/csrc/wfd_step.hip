@@ -109,7 +109,9 @@ __device__ __forceinline__ void st_stream(float *f, int64_t p, float v) {
 // instantiations of the tile helpers.  With shared ones, hipcc allocated the
 // adjoint 137 VGPRs instead of 123 once a forward shape used the same tile,
 // dropping it from 4 to 3 waves per SIMD.
-template <int RY, int NW, int K, int DL = 5>
+// FS: the grid may have a free surface.  Without one, plane loads carry no
+// image branch: a uniform branch in every load cost 7 % of the step time.
+template <int RY, int NW, int K, bool FS, int DL = 5>
 struct Marcher {
   using T = Tile<RY, NW>;
   float q[RY][9];        // planes z-4 .. z+4 of the thread's RY points
@@ -120,7 +122,7 @@ struct Marcher {
   // surface the negated mirror image about it.
   __device__ __forceinline__ static float ld(const float *f, const StepGrid &g, int z, uint32_t o,
                                              bool ok) {
-    if (z < g.zs) {
+    if (FS && z < g.zs) {
       const int zm = 2 * g.zs - z;
       return (ok && zm < g.nz) ? -f[(int64_t)zm * g.plane + o] : 0.0f;
     }
@@ -259,7 +261,7 @@ using LdsPlane = float[Tile<RY, NW>::LY][Tile<RY, NW>::LX];
 
 // One leapfrog step over tile block b of a grid; records the receivers of
 // step n when seis_tm is set (recomputation sweeps pass none).
-template <int RY, int NW, bool VD>
+template <int RY, int NW, bool VD, bool FS>
 __device__ __forceinline__ void forward_tile(
     LdsPlane<RY, NW> *sm, const StepGrid &g,
     const float *__restrict__ cur, const float *prev, float *out, const Source &src, int n,
@@ -268,7 +270,7 @@ __device__ __forceinline__ void forward_tile(
   using T = Tile<RY, NW>;
   Geo<RY, NW, 0> geo;
   if (!geo.init(g, map, b)) return;
-  Marcher<RY, NW, 0> f;
+  Marcher<RY, NW, 0, FS> f;
   f.prime(cur, g, geo.z0, geo.off, geo.in, geo.hoff, geo.hin);
   const float gxv = geo.x < g.nx ? g.gx[geo.x] : 0.0f;
   float gyv[RY];
@@ -316,7 +318,7 @@ __device__ __forceinline__ void forward_tile(
       const int64_t p = zoff + geo.off[j];
       if (geo.in[j] && p == src.idx) acc += src.sigma[0] * src.wavelet[n];
       const float G = gxv * gyv[j] * gzv;
-      const float o = z > g.zs ? G * (acc - G * pv[j]) : 0.0f;  // zero at/above a free surface
+      const float o = (!FS || z > g.zs) ? G * (acc - G * pv[j]) : 0.0f;  // zero at/above a free surface
       if (geo.in[j]) st_stream(out, p, o);
       if (cc[j].ez == z) {
         for (int r = rec.ent_rp[cc[j].e]; r < rec.ent_rp[cc[j].e + 1]; ++r) {
@@ -336,21 +338,21 @@ __device__ __forceinline__ void forward_tile(
   }
 }
 
-template <int RY, int NW, bool VD>
+template <int RY, int NW, bool VD, bool FS>
 __global__ void __launch_bounds__(TX * NW)
     k_forward(StepGrid g, const float *__restrict__ cur, const float *prev, float *out,
               Source src, int n, RecTable rec, const float *__restrict__ rec_scale,
               float *__restrict__ seis_tm, TileMap map) {
   using T = Tile<RY, NW>;
   __shared__ float sm[2][T::LY][T::LX];
-  forward_tile<RY, NW, VD>(sm, g, cur, prev, out, src, n, rec, rec_scale, seis_tm, map,
+  forward_tile<RY, NW, VD, FS>(sm, g, cur, prev, out, src, n, rec, rec_scale, seis_tm, map,
                            blockIdx.x);
 }
 
 // Several grids (one per shot) advanced by one launch: block b belongs to the
 // window whose [block_begin, block_end) contains it.  Window ranges start at
 // multiples of 8 so that each window keeps the XCD-aware tile order.
-template <int RY, int NW, bool VD>
+template <int RY, int NW, bool VD, bool FS>
 __global__ void __launch_bounds__(TX * NW)
     k_forward_multi(const WindowStep *__restrict__ wins, int nwin, int n) {
   using T = Tile<RY, NW>;
@@ -360,14 +362,14 @@ __global__ void __launch_bounds__(TX * NW)
   while (w + 1 < nwin && b >= wins[w + 1].block_begin) ++w;
   const WindowStep &d = wins[w];
   if (b >= d.block_end) return;
-  forward_tile<RY, NW, VD>(sm, d.g, d.cur, d.prev, d.out, d.src, n, d.rec, d.rec_scale,
+  forward_tile<RY, NW, VD, FS>(sm, d.g, d.cur, d.prev, d.out, d.src, n, d.rec, d.rec_scale,
                            d.seis_tm, d.map, b - d.block_begin);
 }
 
 // Halo delay-line depths of the adjoint's two fields.
 constexpr int kDelayPsi = 5, kDelayW = 5;
 
-template <int RY, int NW, bool VD, bool ILLUM>
+template <int RY, int NW, bool VD, bool ILLUM, bool FS>
 __global__ void __launch_bounds__(TX * NW)
     k_adjoint(StepGrid g, const float *__restrict__ cur, const float *prev, float *out,
               RecTable rec, const float *__restrict__ res_tm, int m,
@@ -377,8 +379,8 @@ __global__ void __launch_bounds__(TX * NW)
   __shared__ float sm[2][2][T::LY][T::LX];  // [field][buffer]
   Geo<RY, NW, 1> geo;
   if (!geo.init(g, map, blockIdx.x)) return;
-  Marcher<RY, NW, 1, kDelayPsi> fa;  // adjoint state psi^{m+1}
-  Marcher<RY, NW, 1, kDelayW> fw;    // forward state w^m
+  Marcher<RY, NW, 1, FS, kDelayPsi> fa;  // adjoint state psi^{m+1}
+  Marcher<RY, NW, 1, FS, kDelayW> fw;    // forward state w^m
   fa.prime(cur, g, geo.z0, geo.off, geo.in, geo.hoff, geo.hin);
   fw.prime(wm, g, geo.z0, geo.off, geo.in, geo.hoff, geo.hin);
   const float gxv = geo.x < g.nx ? g.gx[geo.x] : 0.0f;
@@ -453,7 +455,7 @@ __global__ void __launch_bounds__(TX * NW)
       const float G = gxv * gyv[j] * gzv;
       const int64_t p = zoff + geo.off[j];
       if (geo.in[j]) {
-        const bool live = z > g.zs;  // at and above a free surface psi and w stay zero
+        const bool live = !FS || z > g.zs;  // at and above a free surface psi and w stay zero
         st_stream(out, p, live ? G * (acc - G * pv[j]) : 0.0f);
         st_stream(grad, p, live ? gv[j] + ca * (VD ? lap_w - mv[j] * cw : lap_w) : gv[j]);
         if (ILLUM) {
@@ -597,11 +599,11 @@ struct AdjShape<2> {
   static constexpr int RY = 2, NW = 4;  // 64 x 8
 };
 
-template <int V, bool VD>
+template <int V, bool VD, bool FS>
 int fwd_per_cu() {
   using S = FwdShape<V>;
   static const int per_cu =
-      blocks_per_cu(k_forward<S::RY, S::NW, VD>, Tile<S::RY, S::NW>::NTHREADS);
+      blocks_per_cu(k_forward<S::RY, S::NW, VD, FS>, Tile<S::RY, S::NW>::NTHREADS);
   return per_cu;
 }
 
@@ -610,40 +612,40 @@ int fwd_rows() {
   return Tile<FwdShape<V>::RY, FwdShape<V>::NW>::TY;
 }
 
-template <int V, bool VD>
+template <int V, bool VD, bool FS>
 hipError_t fwd_launch(const StepGrid &g, const float *cur, const float *prev, float *out,
                       const Source &src, int n, const RecTable &rec, const float *rec_scale,
                       float *seis_tm, const Tuning &tu, hipStream_t stream) {
   using S = FwdShape<V>;
   static const int nch_env = env_int("WFD_ZCHUNKS_FWD", 0);  // 0 = automatic
   const TileMap map =
-      make_map(g, fwd_rows<V>(), fwd_per_cu<V, VD>(), nch_env, tu.rounds, kFwdHalo);
-  hipLaunchKernelGGL((k_forward<S::RY, S::NW, VD>), dim3(map.nblocks),
+      make_map(g, fwd_rows<V>(), fwd_per_cu<V, VD, FS>(), nch_env, tu.rounds, kFwdHalo);
+  hipLaunchKernelGGL((k_forward<S::RY, S::NW, VD, FS>), dim3(map.nblocks),
                      dim3(Tile<S::RY, S::NW>::NTHREADS), 0, stream, g, cur, prev, out, src, n,
                      rec, rec_scale, seis_tm, map);
   return hipGetLastError();
 }
 
-template <int V, bool VD>
+template <int V, bool VD, bool FS>
 hipError_t fwd_multi_launch(const WindowStep *wins, int nwin, int nblocks, int n,
                             hipStream_t stream) {
   using S = FwdShape<V>;
-  hipLaunchKernelGGL((k_forward_multi<S::RY, S::NW, VD>), dim3(nblocks),
+  hipLaunchKernelGGL((k_forward_multi<S::RY, S::NW, VD, FS>), dim3(nblocks),
                      dim3(Tile<S::RY, S::NW>::NTHREADS), 0, stream, wins, nwin, n);
   return hipGetLastError();
 }
 
-template <int V, bool VD, bool ILLUM>
+template <int V, bool VD, bool ILLUM, bool FS>
 hipError_t adj_launch(const Tuning &tu, const StepGrid &g, const float *cur, const float *prev,
                       float *out, const RecTable &rec, const float *res_tm, int m,
                       const float *wm, float *grad, float *illum, int border, int mnx, int mny,
                       int mnz, hipStream_t stream) {
   using S = AdjShape<V>;
   using T = Tile<S::RY, S::NW>;
-  static const int per_cu = blocks_per_cu(k_adjoint<S::RY, S::NW, VD, ILLUM>, T::NTHREADS);
+  static const int per_cu = blocks_per_cu(k_adjoint<S::RY, S::NW, VD, ILLUM, FS>, T::NTHREADS);
   static const int nch = env_int("WFD_ZCHUNKS_ADJ", 0);  // 0 = automatic
   const TileMap map = make_map(g, T::TY, per_cu, nch, tu.adj_rounds, kAdjHalo);
-  hipLaunchKernelGGL((k_adjoint<S::RY, S::NW, VD, ILLUM>), dim3(map.nblocks), dim3(T::NTHREADS),
+  hipLaunchKernelGGL((k_adjoint<S::RY, S::NW, VD, ILLUM, FS>), dim3(map.nblocks), dim3(T::NTHREADS),
                      0, stream, g, cur, prev, out, rec, res_tm, m, wm, grad, illum, border, mnx,
                      mny, mnz, map);
   return hipGetLastError();
@@ -654,10 +656,12 @@ hipError_t adj_dispatch(const Tuning &tu, const StepGrid &g, const float *cur, c
                         float *out, const RecTable &rec, const float *res_tm, int m,
                         const float *wm, float *grad, float *illum, int border, int mnx, int mny,
                         int mnz, hipStream_t stream) {
-  const bool vd = g.m2 != nullptr;
-#define WFD_ADJ(VD_, IL_)                                                                     \
-  return adj_launch<V, VD_, IL_>(tu, g, cur, prev, out, rec, res_tm, m, wm, grad, illum, border, \
-                                 mnx, mny, mnz, stream)
+  const bool vd = g.m2 != nullptr, fs = g.zs != kNoSurface;
+#define WFD_ADJ(VD_, IL_)                                                                       \
+  return fs ? adj_launch<V, VD_, IL_, true>(tu, g, cur, prev, out, rec, res_tm, m, wm, grad,    \
+                                            illum, border, mnx, mny, mnz, stream)               \
+            : adj_launch<V, VD_, IL_, false>(tu, g, cur, prev, out, rec, res_tm, m, wm, grad,   \
+                                             illum, border, mnx, mny, mnz, stream)
   if (vd) {
     if (illum) WFD_ADJ(true, true);
     WFD_ADJ(true, false);
@@ -673,13 +677,14 @@ hipError_t launch_forward_step(const StepGrid &g, const float *cur, const float 
                                const Source &src, int n, const RecTable *rec,
                                const float *rec_scale, float *seis_tm, const Tuning &tu,
                                hipStream_t stream) {
-  const bool vd = g.m2 != nullptr;
+  const bool vd = g.m2 != nullptr, fs = g.zs != kNoSurface;
   const RecTable none{};
   const RecTable &r = rec ? *rec : none;
   float *rec_out = rec ? seis_tm : nullptr;
-#define WFD_FWD(V)                                                                          \
-  return vd ? fwd_launch<V, true>(g, cur, prev, out, src, n, r, rec_scale, rec_out, tu, stream) \
-            : fwd_launch<V, false>(g, cur, prev, out, src, n, r, rec_scale, rec_out, tu, stream)
+#define WFD_FWD1(V, VD_)                                                                     \
+  (fs ? fwd_launch<V, VD_, true>(g, cur, prev, out, src, n, r, rec_scale, rec_out, tu, stream) \
+      : fwd_launch<V, VD_, false>(g, cur, prev, out, src, n, r, rec_scale, rec_out, tu, stream))
+#define WFD_FWD(V) return vd ? WFD_FWD1(V, true) : WFD_FWD1(V, false)
   switch (tu.variant) {
     case 1: WFD_FWD(1);
     case 2: WFD_FWD(2);
@@ -687,33 +692,40 @@ hipError_t launch_forward_step(const StepGrid &g, const float *cur, const float 
     default: WFD_FWD(0);
   }
 #undef WFD_FWD
+#undef WFD_FWD1
 }
 
 int forward_tile_map(const StepGrid &g, const Tuning &tu, TileMap *map) {
-  const bool vd = g.m2 != nullptr;
+  const bool vd = g.m2 != nullptr, fs = g.zs != kNoSurface;
   int ty = 16, per_cu = 4;
+#define WFD_PCU(V)                                                                 \
+  (vd ? (fs ? fwd_per_cu<V, true, true>() : fwd_per_cu<V, true, false>())          \
+      : (fs ? fwd_per_cu<V, false, true>() : fwd_per_cu<V, false, false>()))
   switch (tu.variant) {
-    case 1: ty = fwd_rows<1>(); per_cu = vd ? fwd_per_cu<1, true>() : fwd_per_cu<1, false>(); break;
-    case 2: ty = fwd_rows<2>(); per_cu = vd ? fwd_per_cu<2, true>() : fwd_per_cu<2, false>(); break;
-    case 3: ty = fwd_rows<3>(); per_cu = vd ? fwd_per_cu<3, true>() : fwd_per_cu<3, false>(); break;
-    default: ty = fwd_rows<0>(); per_cu = vd ? fwd_per_cu<0, true>() : fwd_per_cu<0, false>(); break;
+    case 1: ty = fwd_rows<1>(); per_cu = WFD_PCU(1); break;
+    case 2: ty = fwd_rows<2>(); per_cu = WFD_PCU(2); break;
+    case 3: ty = fwd_rows<3>(); per_cu = WFD_PCU(3); break;
+    default: ty = fwd_rows<0>(); per_cu = WFD_PCU(0); break;
   }
+#undef WFD_PCU
   *map = make_map(g, ty, per_cu, 0, tu.rounds, kFwdHalo);
   return map->nblocks;
 }
 
 hipError_t launch_forward_multi(const WindowStep *wins, int nwin, int nblocks, int n, int variant,
-                                bool vd, hipStream_t stream) {
+                                bool vd, bool fs, hipStream_t stream) {
+#define WFD_MULTI(V)                                                                       \
+  return vd ? (fs ? fwd_multi_launch<V, true, true>(wins, nwin, nblocks, n, stream)         \
+                  : fwd_multi_launch<V, true, false>(wins, nwin, nblocks, n, stream))       \
+            : (fs ? fwd_multi_launch<V, false, true>(wins, nwin, nblocks, n, stream)        \
+                  : fwd_multi_launch<V, false, false>(wins, nwin, nblocks, n, stream))
   switch (variant) {
-    case 1: return vd ? fwd_multi_launch<1, true>(wins, nwin, nblocks, n, stream)
-                      : fwd_multi_launch<1, false>(wins, nwin, nblocks, n, stream);
-    case 2: return vd ? fwd_multi_launch<2, true>(wins, nwin, nblocks, n, stream)
-                      : fwd_multi_launch<2, false>(wins, nwin, nblocks, n, stream);
-    case 3: return vd ? fwd_multi_launch<3, true>(wins, nwin, nblocks, n, stream)
-                      : fwd_multi_launch<3, false>(wins, nwin, nblocks, n, stream);
-    default: return vd ? fwd_multi_launch<0, true>(wins, nwin, nblocks, n, stream)
-                       : fwd_multi_launch<0, false>(wins, nwin, nblocks, n, stream);
+    case 1: WFD_MULTI(1);
+    case 2: WFD_MULTI(2);
+    case 3: WFD_MULTI(3);
+    default: WFD_MULTI(0);
   }
+#undef WFD_MULTI
 }
 
 hipError_t launch_adjoint_step(const Tuning &tu, const StepGrid &g, const float *cur,

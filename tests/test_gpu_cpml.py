@@ -1,0 +1,150 @@
+"""CPML absorbing layer on the GPU (§2.1, reading R26) against the oracle
+(oracle/cpml.py): seismograms and final states with constant and variable
+density, with a free surface, receivers in the band the layer reaches, the
+gradient through full storage, its central-difference check, and the
+layer's absorption against the sponge's."""
+
+import numpy as np
+import pytest
+
+import oracle
+import seisgen
+from gpu_util import gpu_or_skip, oracle_grid, rel_l2, say
+from oracle import cpml as ocpml
+
+pytestmark = pytest.mark.gpu
+
+SEIS_TOL = 1e-4
+GRAD_TOL = 1e-3
+VMAX = 4600.0   # velocity of the layer's d0, fixed (above every model's maximum)
+FPEAK = 15.0
+
+
+def _workload(vd, fs=False, nt=200):
+    w = seisgen.workload("c4_fd_vd" if vd else "c4_fd")
+    w.nt = nt
+    w.wavelet = w.wavelet[:nt].copy()
+    # receivers on the model faces and edges (inside the layer's reach) and inside
+    rec = [[0, 0, 0], [31, 31, 31], [0, 16, 5], [16, 31, 20], [3, 4, 31], [16, 16, 10]]
+    w.receivers = w.nodes_to_metres(rec + [[2 + 4 * i, 2 + 4 * j, 4] for i in range(8)
+                                           for j in range(8)])
+    g = oracle_grid(w)
+    g.free_surface = fs
+    return w, g
+
+
+def _prop(w, fs, vel=None):
+    torch = gpu_or_skip()
+    from paper_2502_12350_amd import GridSpec, Propagator
+    P = Propagator(0)
+    gs = GridSpec(**w.grid_kwargs(), free_surface=fs, cpml=True, fpeak=FPEAK, cpml_vmax=VMAX)
+    v = w.vel if vel is None else vel
+    P.set_model(gs, torch.from_numpy(np.ascontiguousarray(v)).cuda(),
+                None if w.rho is None else torch.from_numpy(w.rho).cuda())
+    return P
+
+
+@pytest.mark.parametrize("vd,fs", [(False, False), (True, False), (True, True)])
+def test_cpml_forward_matches_oracle(vd, fs):
+    torch = gpu_or_skip()
+    w, g = _workload(vd, fs)
+    say(f"[cpml forward] vd {vd} free surface {fs} padded {w.padded_shape} nt {w.nt}")
+    ref = ocpml.forward(g, w.vel, w.rho, w.wavelet, w.sources[0], w.receivers, vmax=VMAX,
+                        fpeak=FPEAK)
+    P = _prop(w, fs)
+    seis, fin = P.forward(torch.from_numpy(w.wavelet).cuda(), w.sources[0], w.receivers,
+                          final=True)
+    torch.cuda.synchronize()
+    es = rel_l2(seis.cpu().numpy(), ref.seis)
+    ef = rel_l2(fin[0].cpu().numpy(), ref.last)
+    say(f"  seismograms rel-L2 {es:.2e}, final state {ef:.2e}")
+    assert es <= SEIS_TOL and ef <= SEIS_TOL
+    # the per-receiver check covers the receivers within reach of the layer
+    for r in range(6):
+        assert rel_l2(seis[r].cpu().numpy(), ref.seis[r]) <= 10 * SEIS_TOL
+
+
+@pytest.mark.parametrize("vd,fs", [(False, False), (True, True)])
+def test_cpml_gradient_matches_oracle(vd, fs):
+    torch = gpu_or_skip()
+    w, g = _workload(vd, fs, nt=150)
+    say(f"[cpml gradient] vd {vd} free surface {fs}")
+    true = (w.vel + 5.0 * w.extra["dv"]).astype(np.float32)
+    dobs = ocpml.forward(g, true, w.rho, w.wavelet, w.sources[0], w.receivers, vmax=VMAX,
+                         fpeak=FPEAK).seis.astype(np.float32)
+    ref = ocpml.gradient(g, w.vel, w.rho, w.wavelet, w.sources[0], w.receivers, dobs,
+                         vmax=VMAX, fpeak=FPEAK, illumination=True)
+    P = _prop(w, fs)
+    il = torch.zeros((w.nz, w.ny, w.nx), dtype=torch.float32, device="cuda")
+    J, gr, seis = P.gradient(torch.from_numpy(w.wavelet).cuda(), w.sources[0], w.receivers,
+                             torch.from_numpy(dobs).cuda(), ckpt="full", illum=il, seis=True)
+    torch.cuda.synchronize()
+    eJ = abs(float(J.item()) - ref.misfit) / ref.misfit
+    eg = rel_l2(gr.cpu().numpy(), ref.grad)
+    say(f"  misfit rel {eJ:.2e}, gradient rel-L2 {eg:.2e}")
+    assert rel_l2(seis.cpu().numpy(), ref.seis) <= SEIS_TOL
+    assert eJ <= SEIS_TOL and eg <= GRAD_TOL
+    assert rel_l2(il.cpu().numpy(), ref.illum) <= SEIS_TOL
+
+
+def test_cpml_gradient_finite_difference_on_gpu():
+    torch = gpu_or_skip()
+    w, g = _workload(True, False, nt=200)
+    true = (w.vel + 5.0 * w.extra["dv"]).astype(np.float32)
+    Pt = _prop(w, False, vel=true)
+    wav = torch.from_numpy(w.wavelet).cuda()
+    dobs = Pt.forward(wav, w.sources[0], w.receivers).clone()
+    P = _prop(w, False)
+    J, gr = P.gradient(wav, w.sources[0], w.receivers, dobs, ckpt="full")
+    dv = w.extra["dv"].astype(np.float64)
+    an = float(np.sum(gr.cpu().numpy().astype(np.float64) * dv))
+    eps = 1.0
+
+    def Jv(v):
+        Q = _prop(w, False, vel=v.astype(np.float32))
+        return float(Q.forward_misfit(wav, w.sources[0], w.receivers, dobs).item())
+
+    fd = (Jv(w.vel + eps * dv) - Jv(w.vel - eps * dv)) / (2 * eps)
+    say(f"[cpml FD] analytic {an:.6e} finite difference {fd:.6e}")
+    assert abs(fd - an) <= 1e-3 * abs(an)
+
+
+def test_cpml_absorbs_better_than_the_sponge_on_gpu():
+    torch = gpu_or_skip()
+    from paper_2502_12350_amd import GridSpec, Propagator
+    n, N, h, c = 48, 12, 10.0, 2000.0
+    dt = 0.35 * h / c
+    nt = 260
+    t = np.arange(nt) * dt
+    arg = (np.pi * 25.0 * (t - 1.2 / 25.0)) ** 2
+    wav = torch.tensor(((1 - 2 * arg) * np.exp(-arg)).astype(np.float32), device="cuda")
+    src = [24 * h, 24 * h, 24 * h]
+    vel = torch.full((n, n, n), c, device="cuda")
+    late = {}
+    for cp in (False, True):
+        P = Propagator(0)
+        P.set_model(GridSpec(n, n, n, h, h, h, border=N, dt=dt, nt=nt, cpml=cp, fpeak=25.0), vel)
+        _, fin = P.forward(wav, src, [src], final=True)
+        torch.cuda.synchronize()
+        core = (slice(N, N + n),) * 3
+        d = (fin[0] - fin[1]).cpu().numpy()[core]
+        late[cp] = float(np.sum(d.astype(np.float64) ** 2))
+    say(f"[cpml absorption] late energy cpml {late[True]:.3e} sponge {late[False]:.3e}")
+    assert late[True] < 0.05 * late[False]
+
+
+def test_cpml_errors():
+    torch = gpu_or_skip()
+    from paper_2502_12350_amd import WfdError, GridSpec, Propagator, ShotBatch
+    w, g = _workload(False, False, nt=20)
+    P = _prop(w, False)
+    wav = torch.from_numpy(w.wavelet).cuda()
+    dobs = torch.zeros((len(w.receivers), w.nt), device="cuda")
+    with pytest.raises(WfdError, match="full storage"):
+        P.gradient(wav, w.sources[0], w.receivers, dobs, ckpt=("revolve", 3))
+    with pytest.raises(WfdError, match="sponge boundaries only"):
+        ShotBatch([P], wav, [w.sources[0]], [w.receivers])
+    Q = Propagator(0)
+    with pytest.raises(WfdError, match="fpeak"):
+        Q.set_model(GridSpec(**w.grid_kwargs(), cpml=True, fpeak=-1.0),
+                    torch.from_numpy(w.vel).cuda())

@@ -63,7 +63,7 @@ def test_model_bytes_scales_with_density_option():
 def test_map_position_matches_oracle():
     rng = np.random.default_rng(1)
     g = api.GridSpec(37, 23, 19, 7.5, 10.0, 4.0, ox=-30.0, oy=100.0, oz=5.0, border=6)
-    og = oracle.Grid(**g.__dict__)
+    og = oracle.Grid(**{k: v for k, v in g.__dict__.items() if k in oracle.Grid.__dataclass_fields__})
     for _ in range(400):
         xyz = [rng.uniform(-40, 250), rng.uniform(90, 330), rng.uniform(0, 85)]
         # also exact half-way points
@@ -193,3 +193,25 @@ def test_free_surface_flag_is_validated():
     assert L.wfd_model_bytes(C.byref(g), 0, C.byref(n)) == -1
     g.free_surface = 1
     assert L.wfd_model_bytes(C.byref(g), 0, C.byref(n)) == 0
+
+
+def test_cpml_fields_are_validated_and_sized():
+    import ctypes as C
+    from paper_2502_12350_amd import _lib
+    L = _lib.lib()
+    g = _lib.wfd_grid(16, 16, 16, 10.0, 10.0, 10.0, 0.0, 0.0, 0.0, 4, 1e-3, 10, 0, 0, 0.0, 0.0)
+    n0, n1 = C.c_size_t(), C.c_size_t()
+    assert L.wfd_model_bytes(C.byref(g), 0, C.byref(n0)) == 0
+    g.cpml = 2
+    assert L.wfd_model_bytes(C.byref(g), 0, C.byref(n1)) == -1
+    g.cpml = 1
+    g.fpeak = -1.0
+    assert L.wfd_model_bytes(C.byref(g), 0, C.byref(n1)) == -1
+    assert "fpeak" in L.wfd_last_error().decode()
+    g.fpeak = 12.0
+    g.cpml_vmax = float("nan")
+    assert L.wfd_model_bytes(C.byref(g), 0, C.byref(n1)) == -1
+    g.cpml_vmax = 3000.0
+    assert L.wfd_model_bytes(C.byref(g), 0, C.byref(n1)) == 0
+    # six 1-D coefficient tables of 24 floats each, 256-byte aligned
+    assert n1.value - n0.value == 6 * 256
