@@ -191,6 +191,94 @@ def fwi_bench(n_iter: int):
     print(json.dumps(out), flush=True)
 
 
+def options_bench():
+    """Cost of the paper's boundary and storage options.  (1) One gradient shot
+    of the 200x200x160 + 20 workload (1200 steps, 2500 receivers) with the
+    forward wavefield in device memory, in 20 binomial checkpoints and in
+    pinned host memory over PCIe, and with the CPML layer instead of the
+    sponge (full storage).  (2) The 576^3 variable-density forward (c2 model,
+    100 steps) with the sponge and with the CPML layer."""
+    import numpy as np
+    import torch
+    import seisgen
+    from paper_2502_12350_amd import GridSpec, Propagator, K_FORWARD, K_OTHER
+
+    dev = torch.device("cuda", 0)
+    out = {"metric": "seconds per gradient shot / ms per forward step by option", "unit": "s",
+           "n_gpus": 1, "dtype": "f32", "data": "synthetic", "config": {}}
+
+    w = seisgen.workload("c4_start")
+    g = GridSpec(**w.grid_kwargs())
+    wav = torch.from_numpy(w.wavelet).to(dev)
+    P = Propagator(0)
+    P.set_model(g, torch.from_numpy(w.extra["v_true"]).to(dev))
+    dobs = P.forward(wav, w.sources[0], w.receivers).clone()
+    P.set_model(g, torch.from_numpy(w.vel).to(dev))
+    rows, grads = {}, {}
+
+    def timed_gradient(Q, ck, name):
+        Q.gradient(wav, w.sources[0], w.receivers, dobs, ckpt=ck)  # warm (allocations)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        J, gr = Q.gradient(wav, w.sources[0], w.receivers, dobs, ckpt=ck)
+        torch.cuda.synchronize()
+        rows[name] = {"seconds": round(time.perf_counter() - t0, 4),
+                      "device_workspace_GiB": round(Q.workspace_bytes(len(w.receivers), ck) / 2**30, 2)}
+        grads[name] = gr.clone()
+        print(f"[bench-options] gradient {name}: {rows[name]}", file=sys.stderr, flush=True)
+
+    timed_gradient(P, "full", "full_device")
+    P.release_workspace()
+    timed_gradient(P, ("revolve", 20), "revolve_20_pairs")
+    P.release_workspace()
+    timed_gradient(P, "host", "host_memory")
+    rows["host_memory"]["host_GiB"] = round(P.host_store_bytes() / 2**30, 2)
+    P.release_workspace()
+    del P
+    torch.cuda.empty_cache()
+    Q = Propagator(0)
+    gc = GridSpec(**w.grid_kwargs(), cpml=True, fpeak=10.0)
+    Q.set_model(gc, torch.from_numpy(w.vel).to(dev))
+    timed_gradient(Q, "full", "cpml_full_device")
+    del Q
+    torch.cuda.empty_cache()
+    out["gradient_one_shot_200x200x160"] = {
+        **rows,
+        "bitwise_equal_full_revolve_host": bool(torch.equal(grads["full_device"], grads["revolve_20_pairs"])
+                                               and torch.equal(grads["full_device"], grads["host_memory"]))}
+
+    c2 = seisgen.workload("c2")
+    fw = {}
+    for cp in (False, True):
+        nt = 100
+        gs = GridSpec(**{**c2.grid_kwargs(), "nt": nt}, cpml=cp, fpeak=10.0)
+        R = Propagator(0)
+        R.set_model(gs, torch.from_numpy(c2.vel).to(dev), torch.from_numpy(c2.rho).to(dev))
+        wv = torch.from_numpy(c2.wavelet[:nt]).to(dev)
+        R.forward(wv, c2.sources[0], c2.receivers)
+        torch.cuda.synchronize()
+        R.set_profiling(True)
+        t0 = time.perf_counter()
+        R.forward(wv, c2.sources[0], c2.receivers)
+        torch.cuda.synchronize()
+        wall = (time.perf_counter() - t0) * 1e3 / nt
+        nf, msf = R.kernel_stats(K_FORWARD)
+        no, mso = R.kernel_stats(K_OTHER)
+        R.set_profiling(False)
+        fw["cpml" if cp else "sponge"] = {"ms_per_step": round(wall, 3),
+                                          "step_kernel_us": round(1e3 * msf / nf, 1),
+                                          "other_kernels_us_per_step": round(1e3 * mso / nt, 1)}
+        print(f"[bench-options] forward 576^3 {'cpml' if cp else 'sponge'}: {fw['cpml' if cp else 'sponge']}",
+              file=sys.stderr, flush=True)
+        R.release_workspace()
+        del R
+        torch.cuda.empty_cache()
+    out["forward_576_vd"] = fw
+    out["config"] = {"workload": "gradient: 200x200x160 + 20 sponge/layer, 1200 steps, 2500 receivers, "
+                                 "one shot; forward: 512^3 VD + 32, 100 steps, 65536 receivers"}
+    print(json.dumps(out), flush=True)
+
+
 def batch_bench(steps: int, warmup: int, autotune: bool):
     """Batched multi-shot forward: 24 shots on the 400x400x256 variable-density
     model, each on its own aperture window (sides 160-320 cells, clipped),
@@ -492,6 +580,8 @@ def main():
     ap.add_argument("--copy-probe", action="store_true")
     ap.add_argument("--fwi", type=int, default=0, metavar="ITERS",
                     help="run the FWI benchmark with this many iterations per method instead")
+    ap.add_argument("--options", action="store_true",
+                    help="cost of wavefield storage modes and of the CPML layer")
     ap.add_argument("--kernels", action="store_true",
                     help="per-kernel table: forward/adjoint CD and VD at 576^3, cache-resident sizes")
     ap.add_argument("--precond-fwi", type=int, default=0, metavar="ITERS",
@@ -528,6 +618,9 @@ def main():
         return
     if args.kernels:
         kernel_table_bench()
+        return
+    if args.options:
+        options_bench()
         return
 
     import numpy as np

@@ -269,6 +269,10 @@ wfd::Shell make_shell(const wfd_grid &g, int Nx, int Ny, int Nz) {
   inner(g.ny, Ny, true, ylo, yhi);
   inner(g.nx, Nx, true, xlo, xhi);
   wfd::Shell sh{};
+  const bool empty_inner = N == 0 || zlo > zhi || ylo > yhi || xlo > xhi;
+  sh.lo[0] = empty_inner ? Nx : xlo, sh.hi[0] = empty_inner ? -1 : xhi;
+  sh.lo[1] = empty_inner ? Ny : ylo, sh.hi[1] = empty_inner ? -1 : yhi;
+  sh.lo[2] = empty_inner ? Nz : zlo, sh.hi[2] = empty_inner ? -1 : zhi;
   auto add = [&](int z0, int z1, int y0, int y1, int x0, int x1) {
     if (z1 <= z0 || y1 <= y0 || x1 <= x0) return;
     const int b = sh.nbox++;
@@ -739,6 +743,9 @@ wfd_status wfd_set_model(wfd_ctx *c, const wfd_grid *grid, const float *vel,
                                   L.cpml[5], (float)(1.0 / grid->dx), (float)(1.0 / grid->dy),
                                   (float)(1.0 / grid->dz)};
     c->shell = make_shell(*grid, c->Nx, c->Ny, c->Nz);
+    for (int b = 0; b < c->shell.nbox; ++b)
+      if (c->shell.start[b + 1] - c->shell.start[b] >= (int64_t(1) << 31))
+        return fail(WFD_E_ARG, "padded grid too large for the CPML layer's point boxes");
   }
   c->has_model = true;
   return WFD_OK;

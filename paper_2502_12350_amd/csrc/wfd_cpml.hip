@@ -42,16 +42,24 @@ __device__ __forceinline__ int64_t lin(const StepGrid &g, int x, int y, int z) {
   return (int64_t)z * g.plane + (int64_t)y * g.pitch + x;
 }
 
-// Shell point q -> (x, y, z).
+// Shell point q -> (x, y, z).  Offsets inside a box fit 32 bits (the host
+// checks), so the divisions are 32-bit: 64-bit ones are long software
+// sequences and dominated these kernels.
 __device__ __forceinline__ void decode(const Shell &sh, int64_t q, int &x, int &y, int &z) {
   int b = 0;
   while (b + 1 < sh.nbox && q >= sh.start[b + 1]) ++b;
-  const int64_t l = q - sh.start[b];
-  const int nxb = sh.x1[b] - sh.x0[b], nyb = sh.y1[b] - sh.y0[b];
-  x = sh.x0[b] + (int)(l % nxb);
-  const int64_t r = l / nxb;
-  y = sh.y0[b] + (int)(r % nyb);
-  z = sh.z0[b] + (int)(r / nyb);
+  const uint32_t l = (uint32_t)(q - sh.start[b]);
+  const uint32_t nxb = (uint32_t)(sh.x1[b] - sh.x0[b]), nyb = (uint32_t)(sh.y1[b] - sh.y0[b]);
+  const uint32_t r = l / nxb;
+  x = sh.x0[b] + (int)(l - r * nxb);
+  const uint32_t zz = r / nyb;
+  y = sh.y0[b] + (int)(r - zz * nyb);
+  z = sh.z0[b] + (int)zz;
+}
+
+// Within reach (4 cells) of the layer of axis d = 0, 1, 2 (x, y, z).
+__device__ __forceinline__ bool near(const Shell &sh, int d, int i) {
+  return i < sh.lo[d] || i > sh.hi[d];
 }
 
 // A field along one axis through (x, y, z), optionally weighted by that axis'
@@ -142,7 +150,7 @@ __global__ void __launch_bounds__(kThreads)
     const int64_t p = lin(g, x, y, z);
     const Axes W = lines(g, w, nullptr, nullptr, nullptr, x, y, z);
     float C = 0.0f;
-    {
+    if (near(sh, 0, x)) {
       const float d1p = first_diff(Line{px, nullptr, p, 1, x, g.nx}) * t.ihx;
       C += d1p;
       const float a = t.ax[x];
@@ -152,7 +160,7 @@ __global__ void __launch_bounds__(kThreads)
         C += v;
       }
     }
-    {
+    if (near(sh, 1, y)) {
       const float d1p = first_diff(Line{py, nullptr, p, g.pitch, y, g.ny}) * t.ihy;
       C += d1p;
       const float a = t.ay[y];
@@ -162,7 +170,7 @@ __global__ void __launch_bounds__(kThreads)
         C += v;
       }
     }
-    {
+    if (near(sh, 2, z)) {
       const float d1p = first_diff(Line{pz, nullptr, p, g.plane, z, g.nz}) * t.ihz;
       C += d1p;
       const float a = t.az[z];
@@ -232,13 +240,16 @@ __global__ void __launch_bounds__(kThreads)
     int x, y, z;
     decode(sh, q, x, y, z);
     const int64_t p = lin(g, x, y, z);
-    const float corr =
-        second_diff(Line{nx_, t.ax, p, 1, x, g.nx}, kNoSurface) * g.cx -
-        first_diff(Line{mx, t.ax, p, 1, x, g.nx}) * t.ihx +
-        second_diff(Line{ny_, t.ay, p, g.pitch, y, g.ny}, kNoSurface) * g.cy -
-        first_diff(Line{my, t.ay, p, g.pitch, y, g.ny}) * t.ihy +
-        second_diff(Line{nz_, t.az, p, g.plane, z, g.nz}, g.zs) * g.cz -
-        first_diff(Line{mz, t.az, p, g.plane, z, g.nz}) * t.ihz;
+    float corr = 0.0f;
+    if (near(sh, 0, x))
+      corr += second_diff(Line{nx_, t.ax, p, 1, x, g.nx}, kNoSurface) * g.cx -
+              first_diff(Line{mx, t.ax, p, 1, x, g.nx}) * t.ihx;
+    if (near(sh, 1, y))
+      corr += second_diff(Line{ny_, t.ay, p, g.pitch, y, g.ny}, kNoSurface) * g.cy -
+              first_diff(Line{my, t.ay, p, g.pitch, y, g.ny}) * t.ihy;
+    if (near(sh, 2, z))
+      corr += second_diff(Line{nz_, t.az, p, g.plane, z, g.nz}, g.zs) * g.cz -
+              first_diff(Line{mz, t.az, p, g.plane, z, g.nz}) * t.ihz;
     if (z > g.zs) phi[p] += g.k[p] * corr;
     if (cstore) grad[p] += phi1[p] * cstore[q];
   }
