@@ -5,15 +5,17 @@
  * §2.1, Eq. 1): constant density p_tt = c^2 lap(p) + S, or variable density
  * q_tt = c^2 (lap(q) - m^2 q) + S / sqrt(rho) with q = p / sqrt(rho) and
  * m^2 = lap(sqrt(rho)) / sqrt(rho), S = f(t) delta(x - x_S).  The scheme is
- * second order in time (leapfrog) and eighth order in space (§2.1), with a
- * damping sponge of `border` cells (§2.1 absorbing boundaries; §2.2.1
- * parameter table).  It serves forward modeling (Alg. 1) and the per-shot
- * body of the FWI gradient (Alg. 3): forward sweep with receiver recording
- * and wavefield saving, misfit, backward (adjoint) sweep with the
- * cross-correlation imaging condition, and the chain rule to the velocity
- * gradient.  Forward-wavefield management follows the paper's two in-memory
- * options (§2.1): keep every state, or optimal checkpointing with
- * recomputation.
+ * second order in time (leapfrog) and eighth order in space (§2.1), with an
+ * absorbing boundary of `border` cells (§2.1; §2.2.1 parameter table): a
+ * damping sponge, or a CPML layer; optionally a free surface on top.  It
+ * serves forward modeling (Alg. 1) and the per-shot body of the FWI gradient
+ * (Alg. 3): forward sweep with receiver recording and wavefield saving,
+ * misfit, backward (adjoint) sweep with the cross-correlation imaging
+ * condition, and the chain rule to the velocity gradient.  Forward-wavefield
+ * management follows the paper's three options (§2.1): keep every state in
+ * memory, keep it in secondary (here host) storage, or optimal checkpointing
+ * with recomputation.  Gradient smoothing, time resampling and the layers of
+ * a learned gradient preconditioner are separate calls below.
  *
  * Conventions (§2.2.2, data format)
  *   - volumes are C-order [z][y][x], x fastest, FP32;
@@ -23,9 +25,9 @@
  *   - seismograms are trace-major [nrec][nt] FP32: sample n of a trace is
  *     the recorded pressure at time (n + 1) dt, wavelet sample n is the
  *     source value at time n dt;
- *   - the sponge is added outside the model on all six faces; the padded
- *     grid is Nd = nd + 2 border, with the model's edge values replicated
- *     into the sponge.
+ *   - the absorbing border is added outside the model on all six faces
+ *     (five with a free surface); the padded grid is Nd = nd + 2 border,
+ *     with the model's edge values replicated into the border.
  *
  * Ownership and ordering
  *   - the caller owns every device buffer (model buffer, workspace, inputs,
