@@ -25,9 +25,10 @@
  *   - seismograms are trace-major [nrec][nt] FP32: sample n of a trace is
  *     the recorded pressure at time (n + 1) dt, wavelet sample n is the
  *     source value at time n dt;
- *   - the absorbing border is added outside the model on all six faces
- *     (five with a free surface); the padded grid is Nd = nd + 2 border,
- *     with the model's edge values replicated into the border.
+ *   - the border is added outside the model on all six faces (with a free
+ *     surface the top one holds zeros and absorbs nothing); the padded grid
+ *     is Nd = nd + 2 border, with the model's edge values replicated into
+ *     the border.
  *
  * Ownership and ordering
  *   - the caller owns every device buffer (model buffer, workspace, inputs,
