@@ -118,6 +118,43 @@ def copy_probe(gib: float = 4.0, reps: int = 10):
                       "addcmul_r3w1_GBps": round(16 * n / t_r3w1 / 1e9, 1)}), flush=True)
 
 
+def stream_probe(reps: int = 10):
+    """Achievable streaming bandwidth: the library's plain float4 probe
+    kernels (no reuse) reading R and writing W arrays of 576^3 floats, over
+    several grid sizes, plain and nontemporal; the best rate per mix."""
+    import ctypes as C
+    import torch
+    from paper_2502_12350_amd import _lib
+    L = _lib.lib()
+    n = 576 ** 3
+    buf = torch.ones(8 * n, dtype=torch.float32, device="cuda")
+    st = C.c_void_p(torch.cuda.current_stream().cuda_stream)
+    rows = {}
+    for r, w in ((1, 1), (3, 1), (4, 1), (6, 2)):
+        best = None
+        for nt in (0, 1):
+            for blocks in (2048, 8192, 32768):
+                def run():
+                    _lib.check(L.wfd_stream_probe(r, w, nt, C.c_void_p(buf.data_ptr()), n, blocks, st))
+                for _ in range(2):
+                    run()
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                torch.cuda.synchronize()
+                e0.record()
+                for _ in range(reps):
+                    run()
+                e1.record()
+                torch.cuda.synchronize()
+                gbs = (r + w) * 4.0 * n / (e0.elapsed_time(e1) / reps * 1e-3) / 1e9
+                print(f"[stream-probe] R{r}W{w} nontemporal {nt} blocks {blocks}: {gbs:.0f} GB/s",
+                      file=sys.stderr, flush=True)
+                if best is None or gbs > best[0]:
+                    best = (gbs, nt, blocks)
+        rows[f"r{r}w{w}"] = {"GBps": round(best[0], 0), "nontemporal": best[1], "blocks": best[2]}
+    print(json.dumps({"metric": "streaming probe bandwidth", "unit": "GB/s", "n_floats_per_array": n,
+                      "best": rows}), flush=True)
+
+
 def fwi_bench(n_iter: int):
     """FWI on the gradient workload: 200x200x160 model + 20-cell sponge, 1200
     steps, 8 shots x 2500 receivers, true model = smooth background + six
@@ -578,6 +615,8 @@ def main():
     ap.add_argument("--snapshots", type=int, default=96)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe", action="store_true")
+    ap.add_argument("--stream-probe", action="store_true",
+                    help="achievable streaming bandwidth of plain float4 kernels")
     ap.add_argument("--fwi", type=int, default=0, metavar="ITERS",
                     help="run the FWI benchmark with this many iterations per method instead")
     ap.add_argument("--options", action="store_true",
@@ -601,6 +640,9 @@ def main():
               "design shards shots and all-reduces the gradient, see DESIGN.md) -- "
               f"--gpus {args.gpus} is not supported", file=sys.stderr, flush=True)
         sys.exit(2)
+    if args.stream_probe:
+        stream_probe()
+        return
     if args.copy_probe:
         copy_probe()
         return

@@ -436,6 +436,19 @@ wfd_status wfd_set_profiling(wfd_ctx *ctx, int32_t enable);
  * profiling was enabled.  Waits for the stream. */
 wfd_status wfd_kernel_stats(wfd_ctx *ctx, int32_t kernel_class, int64_t *launches, double *total_ms);
 
+/* Streaming probe (measurement only, not part of the method): one launch of
+ * a plain kernel that reads `reads` arrays and writes `writes` arrays of n
+ * FP32 values as float4, grid-stride over `blocks` blocks of 256 threads, with
+ * nontemporal loads and stores when nontemporal = 1.  It is the achievable-
+ * bandwidth reference for the step kernels' rooflines: (1,1) a copy, (3,1)
+ * and (4,1) the forward step's stream mixes without stencil reuse, (6,2) the
+ * adjoint's.  buf_dev holds the inputs then the outputs, reads + writes
+ * arrays of n values; n must be a positive multiple of 4 and buf_dev 16-byte
+ * aligned.  Other (reads, writes) pairs return WFD_E_ARG.  Launches on
+ * hip_stream (a hipStream_t, NULL = legacy default) and returns at once. */
+wfd_status wfd_stream_probe(int32_t reads, int32_t writes, int32_t nontemporal, float *buf_dev,
+                            int64_t n, int32_t blocks, void *hip_stream);
+
 /* Thread-local text of the last error ("" if none). */
 const char *wfd_last_error(void);
 

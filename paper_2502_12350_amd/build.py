@@ -22,8 +22,8 @@ BUILD_DIR = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libwfd.so")
 
 SOURCES = [
-    "wfd_step.hip", "wfd_kernels.hip", "wfd_cnn.hip", "wfd_smooth.hip", "wfd_cpml.hip", "wfd_api.cpp",
-    "wfd_plan.cpp",
+    "wfd_step.hip", "wfd_kernels.hip", "wfd_cnn.hip", "wfd_smooth.hip", "wfd_cpml.hip",
+    "wfd_probe.hip", "wfd_api.cpp", "wfd_plan.cpp",
 ]
 ARCH = "gfx950"
 

@@ -1489,6 +1489,20 @@ wfd_status wfd_kernel_stats(wfd_ctx *c, int32_t kernel_class, int64_t *launches,
   return WFD_OK;
 }
 
+wfd_status wfd_stream_probe(int32_t reads, int32_t writes, int32_t nontemporal, float *buf,
+                            int64_t n, int32_t blocks, void *hip_stream) {
+  const bool mix = (reads == 1 && writes == 1) || (reads == 3 && writes == 1) ||
+                   (reads == 4 && writes == 1) || (reads == 6 && writes == 2);
+  if (!mix) return fail(WFD_E_ARG, "no probe reads %d arrays and writes %d", reads, writes);
+  if (!buf || (uintptr_t)buf % 16) return fail(WFD_E_ARG, "buffer NULL or not 16-byte aligned");
+  if (n <= 0 || n % 4) return fail(WFD_E_ARG, "n must be a positive multiple of 4");
+  if (blocks < 1 || nontemporal < 0 || nontemporal > 1)
+    return fail(WFD_E_ARG, "blocks must be >= 1 and nontemporal 0 or 1");
+  HIP_TRY(wfd::launch_stream_probe(reads, writes, nontemporal != 0, buf, n, blocks,
+                                   (hipStream_t)hip_stream));
+  return WFD_OK;
+}
+
 // ---- learned gradient preconditioner ---------------------------------------
 
 wfd_status wfd_cnn_packed_elems(int32_t cin, int32_t cout, int32_t flip, int64_t *elems) {

@@ -1,0 +1,62 @@
+// Streaming probes: plain kernels that read R arrays and write W arrays of
+// float4 with a grid-stride loop and no reuse, for the achievable-bandwidth
+// reference beside the step kernels' rooflines.  (R, W) = (1, 1), (3, 1),
+// (4, 1) and (6, 2) match a copy, the forward step's streams without the
+// stencil reuse, and the adjoint's.
+#include <hip/hip_runtime.h>
+
+#include <stdint.h>
+
+#include "wfd_internal.h"
+
+namespace wfd {
+namespace {
+
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+template <int R, int W, bool NT>
+__global__ void __launch_bounds__(256)
+    k_stream(const v4f *__restrict__ in, v4f *__restrict__ out, int64_t n4) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n4;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    v4f s = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const v4f *p = in + (int64_t)r * n4 + i;
+      s += NT ? __builtin_nontemporal_load(p) : *p;
+    }
+#pragma unroll
+    for (int w = 0; w < W; ++w) {
+      v4f *p = out + (int64_t)w * n4 + i;
+      if (NT)
+        __builtin_nontemporal_store(s, p);
+      else
+        *p = s;
+    }
+  }
+}
+
+template <int R, int W>
+hipError_t stream_launch(bool nt, float *buf, int64_t n, int blocks, hipStream_t stream) {
+  const int64_t n4 = n / 4;
+  const v4f *in = reinterpret_cast<const v4f *>(buf);
+  v4f *out = reinterpret_cast<v4f *>(buf) + (int64_t)R * n4;
+  if (nt)
+    hipLaunchKernelGGL((k_stream<R, W, true>), dim3(blocks), dim3(256), 0, stream, in, out, n4);
+  else
+    hipLaunchKernelGGL((k_stream<R, W, false>), dim3(blocks), dim3(256), 0, stream, in, out, n4);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_stream_probe(int reads, int writes, bool nt, float *buf, int64_t n, int blocks,
+                               hipStream_t stream) {
+  if (reads == 1 && writes == 1) return stream_launch<1, 1>(nt, buf, n, blocks, stream);
+  if (reads == 3 && writes == 1) return stream_launch<3, 1>(nt, buf, n, blocks, stream);
+  if (reads == 4 && writes == 1) return stream_launch<4, 1>(nt, buf, n, blocks, stream);
+  if (reads == 6 && writes == 2) return stream_launch<6, 2>(nt, buf, n, blocks, stream);
+  return hipErrorInvalidValue;
+}
+
+}  // namespace wfd

@@ -215,3 +215,16 @@ def test_cpml_fields_are_validated_and_sized():
     assert L.wfd_model_bytes(C.byref(g), 0, C.byref(n1)) == 0
     # six 1-D coefficient tables of 24 floats each, 256-byte aligned
     assert n1.value - n0.value == 6 * 256
+
+
+def test_stream_probe_argument_checks():
+    import ctypes as C
+    from paper_2502_12350_amd import _lib
+    L = _lib.lib()
+    buf = C.c_void_p(4096)  # never dereferenced: every call below fails its checks first
+    assert L.wfd_stream_probe(2, 1, 0, buf, 1024, 64, None) == -1
+    assert "no probe" in L.wfd_last_error().decode()
+    assert L.wfd_stream_probe(3, 1, 0, None, 1024, 64, None) == -1
+    assert L.wfd_stream_probe(3, 1, 0, buf, 1022, 64, None) == -1
+    assert L.wfd_stream_probe(3, 1, 2, buf, 1024, 64, None) == -1
+    assert L.wfd_stream_probe(3, 1, 0, buf, 1024, 0, None) == -1
