@@ -277,6 +277,7 @@ wfd::Shell make_shell(const wfd_grid &g, int Nx, int Ny, int Nz) {
     if (z1 <= z0 || y1 <= y0 || x1 <= x0) return;
     const int b = sh.nbox++;
     sh.z0[b] = z0, sh.z1[b] = z1, sh.y0[b] = y0, sh.y1[b] = y1, sh.x0[b] = x0, sh.x1[b] = x1;
+    sh.zfirst[b] = (z1 - z0) < (y1 - y0);
   };
   if (N == 0) {
     // no layer: empty shell

@@ -49,12 +49,20 @@ __device__ __forceinline__ void decode(const Shell &sh, int64_t q, int &x, int &
   int b = 0;
   while (b + 1 < sh.nbox && q >= sh.start[b + 1]) ++b;
   const uint32_t l = (uint32_t)(q - sh.start[b]);
-  const uint32_t nxb = (uint32_t)(sh.x1[b] - sh.x0[b]), nyb = (uint32_t)(sh.y1[b] - sh.y0[b]);
+  const uint32_t nxb = (uint32_t)(sh.x1[b] - sh.x0[b]);
   const uint32_t r = l / nxb;
   x = sh.x0[b] + (int)(l - r * nxb);
-  const uint32_t zz = r / nyb;
-  y = sh.y0[b] + (int)(r - zz * nyb);
-  z = sh.z0[b] + (int)zz;
+  if (sh.zfirst[b]) {
+    const uint32_t nzb = (uint32_t)(sh.z1[b] - sh.z0[b]);
+    const uint32_t yy = r / nzb;
+    z = sh.z0[b] + (int)(r - yy * nzb);
+    y = sh.y0[b] + (int)yy;
+  } else {
+    const uint32_t nyb = (uint32_t)(sh.y1[b] - sh.y0[b]);
+    const uint32_t zz = r / nyb;
+    y = sh.y0[b] + (int)(r - zz * nyb);
+    z = sh.z0[b] + (int)zz;
+  }
 }
 
 // Within reach (4 cells) of the layer of axis d = 0, 1, 2 (x, y, z).
@@ -66,16 +74,22 @@ __device__ __forceinline__ bool near(const Shell &sh, int d, int i) {
 // a table, zero outside the grid; with `image`, z planes above the free
 // surface read the negated mirror (as L does).
 struct Line {
-  const float *u;
+  const float *p;  // the point
   const float *a;  // weight per index along the axis, or nullptr
-  int64_t base;    // linear index of the point
   int64_t stride;  // elements between neighbours along the axis
   int i, n;        // index along the axis and the axis length
+  bool inner;      // i - 4 .. i + 4 all inside [0, n): no bounds tests
+  __device__ __forceinline__ Line(const float *u, const float *a_, int64_t base, int64_t stride_,
+                                  int i_, int n_)
+      : p(u + base), a(a_), stride(stride_), i(i_), n(n_),
+        inner(i_ >= kStencilRadius && i_ + kStencilRadius < n_) {}
   __device__ __forceinline__ float operator()(int j) const {  // value at offset j
-    const int ii = i + j;
-    if (ii < 0 || ii >= n) return 0.0f;
-    const float v = u[base + (int64_t)j * stride];
-    return a ? a[ii] * v : v;
+    if (!inner) {
+      const int ii = i + j;
+      if (ii < 0 || ii >= n) return 0.0f;
+    }
+    const float v = p[j * stride];
+    return a ? a[i + j] * v : v;
   }
 };
 
@@ -90,6 +104,11 @@ __device__ __forceinline__ float first_diff(const Line &f) {
 // offsets landing above it read -value(2 zs - z').
 __device__ __forceinline__ float second_diff(const Line &f, int zs) {
   float s = d2c(0) * f(0);
+  if (f.i - kStencilRadius >= zs) {  // no image plane within reach (also: no surface)
+#pragma unroll
+    for (int j = 1; j <= 4; ++j) s += d2c(j) * (f(j) + f(-j));
+    return s;
+  }
 #pragma unroll
   for (int j = 1; j <= 4; ++j) {
     const float up = f(j);

@@ -175,8 +175,9 @@ struct CpmlTables {
 // The points the layer's terms reach: the padded grid minus the inner box
 // more than 4 cells from every layer, as up to 6 boxes [lo, hi) in (z, y, x).
 // Point q of the shell lies in the box b with start[b] <= q < start[b + 1],
-// at offset q - start[b] in x-fastest order; every box holds fewer than 2^31
-// points.  lo/hi are the inner box (inclusive) per axis x, y, z: a point
+// at offset q - start[b] in x-fastest order, then the box's thinner of z and
+// y (so the z or y neighbours of a row are a few rows away and stay in L2);
+// every box holds fewer than 2^31 points.  lo/hi are the inner box (inclusive) per axis x, y, z: a point
 // outside [lo, hi] along an axis is within reach of that axis' layer.
 constexpr int kShellBoxes = 6;
 struct Shell {
@@ -184,6 +185,7 @@ struct Shell {
   int z0[kShellBoxes], z1[kShellBoxes], y0[kShellBoxes], y1[kShellBoxes];
   int x0[kShellBoxes], x1[kShellBoxes];
   int64_t start[kShellBoxes + 1];
+  int zfirst[kShellBoxes];  // 1: order x, z, y (z before y), for boxes thin in z
   int lo[3], hi[3];
 };
 // Forward: psi_d = b psi_d + a D1_d w (cur) on the layer.
