@@ -214,3 +214,57 @@ def test_c3_full_size_batch_graph_equals_per_shot():
         assert torch.equal(b.seis[i], ref), f"shot {i}"
         assert bool(torch.isfinite(ref).all()) and float(ref.abs().max()) > 0
     b.close()
+
+
+def test_batch_with_free_surface_windows_equals_per_shot():
+    # windows 0 and 2 have a free surface: the batch runs the kernels with
+    # image loads for every window, and each window must still equal its own
+    # forward (which uses the kernels without them when it has no surface)
+    torch = gpu_or_skip()
+    from paper_2502_12350_amd import GridSpec, Propagator, ShotBatch
+    w, shots = _windows("c3_small")
+    say(f"[batch] c3_small with free surfaces on windows 0 and 2")
+    props = []
+    for i, s in enumerate(shots):
+        P = Propagator(0)
+        P.set_model(GridSpec(**s.grid_kwargs(), free_surface=i in (0, 2)),
+                    torch.from_numpy(s.vel).cuda(), torch.from_numpy(s.rho).cuda())
+        props.append(P)
+    wav = torch.from_numpy(shots[0].wavelet).cuda()
+    recs = [s.receivers for s in shots]
+    b = ShotBatch(props, wav, [s.sources[0] for s in shots], recs)
+    seis = [t.clone() for t in b.run()]
+    torch.cuda.synchronize()
+    for i, (s, P) in enumerate(zip(shots, props)):
+        ref = P.forward(wav, s.sources[0], recs[i])
+        torch.cuda.synchronize()
+        assert torch.equal(seis[i], ref), f"shot {i}"
+    # the surface changes the traces of its windows
+    Q = Propagator(0)
+    Q.set_model(GridSpec(**shots[0].grid_kwargs()), torch.from_numpy(shots[0].vel).cuda(),
+                torch.from_numpy(shots[0].rho).cuda())
+    plain = Q.forward(wav, shots[0].sources[0], recs[0])
+    torch.cuda.synchronize()
+    assert not torch.equal(plain, seis[0])
+    b.close()
+
+
+@pytest.mark.parametrize("variant,adj_variant", [(1, 1), (2, 2), (3, 1)])
+def test_tile_shapes_bitwise_identical_with_free_surface(variant, adj_variant):
+    torch = gpu_or_skip()
+    from paper_2502_12350_amd import GridSpec, Propagator
+    w = seisgen.workload("c4_fd_vd")
+    say(f"[tuning] free surface, forward variant {variant}, adjoint variant {adj_variant}")
+    P = Propagator(0)
+    P.set_model(GridSpec(**w.grid_kwargs(), free_surface=True), torch.from_numpy(w.vel).cuda(),
+                torch.from_numpy(w.rho).cuda())
+    wav = torch.from_numpy(w.wavelet).cuda()
+    dobs = torch.zeros((len(w.receivers), w.nt), dtype=torch.float32, device="cuda")
+    J0, g0, s0 = P.gradient(wav, w.sources[0], w.receivers, dobs, seis=True)
+    J0, g0, s0 = float(J0.item()), g0.clone(), s0.clone()
+    P.set_tuning(variant, 0, adj_variant, 0)
+    J1, g1, s1 = P.gradient(wav, w.sources[0], w.receivers, dobs, seis=True)
+    torch.cuda.synchronize()
+    assert float(J1.item()) == J0 and J0 > 0
+    assert torch.equal(s1, s0)
+    assert torch.equal(g1, g0)
