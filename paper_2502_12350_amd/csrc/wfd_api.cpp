@@ -292,9 +292,18 @@ wfd::Shell make_shell(const wfd_grid &g, int Nx, int Ny, int Nz) {
     add(zlo, zhi + 1, ylo, yhi + 1, xhi + 1, Nx);
   }
   sh.start[0] = 0;
-  for (int b = 0; b < sh.nbox; ++b)
-    sh.start[b + 1] = sh.start[b] + (int64_t)(sh.z1[b] - sh.z0[b]) * (sh.y1[b] - sh.y0[b]) *
-                                        (sh.x1[b] - sh.x0[b]);
+  sh.bstart[0] = 0;
+  for (int b = 0; b < sh.nbox; ++b) {
+    const int nxb = sh.x1[b] - sh.x0[b], nyb = sh.y1[b] - sh.y0[b], nzb = sh.z1[b] - sh.z0[b];
+    sh.start[b + 1] = sh.start[b] + (int64_t)nzb * nyb * nxb;
+    // a plane of the box within reach of a z layer
+    sh.zq[b] = sh.z0[b] < sh.lo[2] || sh.z1[b] - 1 > sh.hi[2];
+    sh.cz[b] = sh.zq[b] ? wfd::kShellChunkZ : wfd::kShellChunk;
+    sh.tx[b] = (nxb + wfd::kShellTileX - 1) / wfd::kShellTileX;
+    sh.ty[b] = (nyb + wfd::kShellTileY - 1) / wfd::kShellTileY;
+    sh.nch[b] = (nzb + sh.cz[b] - 1) / sh.cz[b];
+    sh.bstart[b + 1] = sh.bstart[b] + (int64_t)sh.tx[b] * sh.ty[b] * sh.nch[b];
+  }
   return sh;
 }
 

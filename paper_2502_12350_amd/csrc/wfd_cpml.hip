@@ -136,71 +136,161 @@ __device__ __forceinline__ Axes lines(const StepGrid &g, const float *u, const f
 }
 
 constexpr int kThreads = 256;
+static_assert(kThreads == kShellTileX * kShellTileY, "a column block is one x-y tile");
+
+// The (x, y) column and z chunk of this thread (column marching).  Returns
+// false for lanes past the box's x or y extent.
+struct Column {
+  int b, x, y, z0, z1;
+  uint32_t nxb, nyb, nzb;
+  int64_t pxy;  // offset of (x, y) in a plane
+  __device__ __forceinline__ bool init(const Shell &sh, const StepGrid &g) {
+    const int64_t blk = blockIdx.x;
+    b = 0;
+    while (b + 1 < sh.nbox && blk >= sh.bstart[b + 1]) ++b;
+    uint32_t l = (uint32_t)(blk - sh.bstart[b]);
+    const uint32_t ch = l % (uint32_t)sh.nch[b];
+    l /= (uint32_t)sh.nch[b];
+    const uint32_t ty = l % (uint32_t)sh.ty[b], tx = l / (uint32_t)sh.ty[b];
+    x = sh.x0[b] + (int)tx * kShellTileX + (int)(threadIdx.x % kShellTileX);
+    y = sh.y0[b] + (int)ty * kShellTileY + (int)(threadIdx.x / kShellTileX);
+    z0 = sh.z0[b] + (int)ch * sh.cz[b];
+    z1 = min(z0 + sh.cz[b], sh.z1[b]);
+    nxb = (uint32_t)(sh.x1[b] - sh.x0[b]);
+    nyb = (uint32_t)(sh.y1[b] - sh.y0[b]);
+    nzb = (uint32_t)(sh.z1[b] - sh.z0[b]);
+    pxy = (int64_t)y * g.pitch + x;
+    return x < sh.x1[b] && y < sh.y1[b];
+  }
+  // index of (x, y, z) in the shell's point order (the correction store)
+  __device__ __forceinline__ int64_t q(const Shell &sh, int z) const {
+    const uint32_t xo = (uint32_t)(x - sh.x0[b]), yo = (uint32_t)(y - sh.y0[b]),
+                   zo = (uint32_t)(z - sh.z0[b]);
+    const uint32_t l = sh.zfirst[b] ? xo + nxb * (zo + nzb * yo) : xo + nxb * (yo + nyb * zo);
+    return sh.start[b] + (int64_t)l;
+  }
+};
+
+// Nine planes z-4 .. z+4 of a quantity along the thread's column; f(z') gives
+// plane z'.  prime() at the chunk's first plane, then advance() per plane.
+struct ZWin {
+  float v[9];
+  template <class F>
+  __device__ __forceinline__ void prime(F f, int z) {
+#pragma unroll
+    for (int i = 0; i < 9; ++i) v[i] = f(z - 4 + i);
+  }
+  template <class F>
+  __device__ __forceinline__ void advance(F f, int z) {  // to plane z + 1
+#pragma unroll
+    for (int i = 0; i < 8; ++i) v[i] = v[i + 1];
+    v[8] = f(z + 5);
+  }
+  __device__ __forceinline__ float d1() const {
+    float s = 0.0f;
+#pragma unroll
+    for (int j = 1; j <= 4; ++j) s += d1c(j) * (v[4 + j] - v[4 - j]);
+    return s;
+  }
+  __device__ __forceinline__ float d2() const {
+    float s = d2c(0) * v[4];
+#pragma unroll
+    for (int j = 1; j <= 4; ++j) s += d2c(j) * (v[4 + j] + v[4 - j]);
+    return s;
+  }
+};
+
+// Plane z' of a column of u (offset pxy): zero outside the grid; with `image`,
+// planes above the free surface read the negated mirror (as L does).
+__device__ __forceinline__ float zval(const float *u, const StepGrid &g, int64_t pxy, int zz,
+                                      bool image) {
+  if (image && zz < g.zs) {
+    const int zm = 2 * g.zs - zz;
+    return zm < g.nz ? -u[(int64_t)zm * g.plane + pxy] : 0.0f;
+  }
+  return (zz >= 0 && zz < g.nz) ? u[(int64_t)zz * g.plane + pxy] : 0.0f;
+}
 
 __global__ void __launch_bounds__(kThreads)
     k_cpml_psi(StepGrid g, CpmlTables t, Shell sh, const float *__restrict__ w, float *px,
                float *py, float *pz) {
-  const int64_t total = sh.start[sh.nbox];
-  for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < total;
-       q += (int64_t)gridDim.x * blockDim.x) {
-    int x, y, z;
-    decode(sh, q, x, y, z);
-    const int64_t p = lin(g, x, y, z);
-    const Axes L = lines(g, w, nullptr, nullptr, nullptr, x, y, z);
-    float a = t.ax[x];
-    if (a != 0.0f) px[p] = t.bx[x] * px[p] + a * (first_diff(L.x) * t.ihx);
-    a = t.ay[y];
-    if (a != 0.0f) py[p] = t.by[y] * py[p] + a * (first_diff(L.y) * t.ihy);
-    a = t.az[z];
-    if (a != 0.0f) pz[p] = t.bz[z] * pz[p] + a * (first_diff(L.z) * t.ihz);
+  Column c;
+  if (!c.init(sh, g)) return;
+  const bool zq = sh.zq[c.b];
+  const float ax = t.ax[c.x], bx = t.bx[c.x], ay = t.ay[c.y], by = t.by[c.y];
+  auto wz = [&](int zz) { return zval(w, g, c.pxy, zz, false); };
+  ZWin qw;
+  if (zq) qw.prime(wz, c.z0);
+  for (int z = c.z0; z < c.z1; ++z) {
+    const int64_t p = (int64_t)z * g.plane + c.pxy;
+    if (ax != 0.0f) px[p] = bx * px[p] + ax * (first_diff(Line{w, nullptr, p, 1, c.x, g.nx}) * t.ihx);
+    if (ay != 0.0f)
+      py[p] = by * py[p] + ay * (first_diff(Line{w, nullptr, p, g.pitch, c.y, g.ny}) * t.ihy);
+    if (zq) {
+      const float az = t.az[z];
+      if (az != 0.0f) pz[p] = t.bz[z] * pz[p] + az * (qw.d1() * t.ihz);
+      qw.advance(wz, z);
+    }
   }
 }
 
 __global__ void __launch_bounds__(kThreads)
     k_cpml_zeta(StepGrid g, CpmlTables t, Shell sh, const float *__restrict__ w,
                 const float *__restrict__ px, const float *__restrict__ py,
-                const float *__restrict__ pz, float *zx, float *zy, float *zz, float *out,
+                const float *__restrict__ pz, float *zx, float *zy, float *zz_, float *out,
                 float *cstore) {
-  const int64_t total = sh.start[sh.nbox];
-  for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < total;
-       q += (int64_t)gridDim.x * blockDim.x) {
-    int x, y, z;
-    decode(sh, q, x, y, z);
-    const int64_t p = lin(g, x, y, z);
-    const Axes W = lines(g, w, nullptr, nullptr, nullptr, x, y, z);
+  Column c;
+  if (!c.init(sh, g)) return;
+  const bool zq = sh.zq[c.b];
+  const bool nx = near(sh, 0, c.x), ny = near(sh, 1, c.y);
+  const float ax = t.ax[c.x], bx = t.bx[c.x], ay = t.ay[c.y], by = t.by[c.y];
+  auto wz = [&](int zz) { return zval(w, g, c.pxy, zz, true); };
+  auto pzz = [&](int zz) { return zval(pz, g, c.pxy, zz, false); };
+  ZWin qw, qp;
+  if (zq) {
+    qw.prime(wz, c.z0);
+    qp.prime(pzz, c.z0);
+  }
+  for (int z = c.z0; z < c.z1; ++z) {
+    const int64_t p = (int64_t)z * g.plane + c.pxy;
     float C = 0.0f;
-    if (near(sh, 0, x)) {
-      const float d1p = first_diff(Line{px, nullptr, p, 1, x, g.nx}) * t.ihx;
+    if (nx) {
+      const float d1p = first_diff(Line{px, nullptr, p, 1, c.x, g.nx}) * t.ihx;
       C += d1p;
-      const float a = t.ax[x];
-      if (a != 0.0f) {
-        const float v = t.bx[x] * zx[p] + a * (second_diff(W.x, kNoSurface) * g.cx + d1p);
+      if (ax != 0.0f) {
+        const float v =
+            bx * zx[p] + ax * (second_diff(Line{w, nullptr, p, 1, c.x, g.nx}, kNoSurface) * g.cx + d1p);
         zx[p] = v;
         C += v;
       }
     }
-    if (near(sh, 1, y)) {
-      const float d1p = first_diff(Line{py, nullptr, p, g.pitch, y, g.ny}) * t.ihy;
+    if (ny) {
+      const float d1p = first_diff(Line{py, nullptr, p, g.pitch, c.y, g.ny}) * t.ihy;
       C += d1p;
-      const float a = t.ay[y];
-      if (a != 0.0f) {
-        const float v = t.by[y] * zy[p] + a * (second_diff(W.y, kNoSurface) * g.cy + d1p);
+      if (ay != 0.0f) {
+        const float v = by * zy[p] +
+                        ay * (second_diff(Line{w, nullptr, p, g.pitch, c.y, g.ny}, kNoSurface) *
+                                  g.cy + d1p);
         zy[p] = v;
         C += v;
       }
     }
-    if (near(sh, 2, z)) {
-      const float d1p = first_diff(Line{pz, nullptr, p, g.plane, z, g.nz}) * t.ihz;
-      C += d1p;
-      const float a = t.az[z];
-      if (a != 0.0f) {
-        const float v = t.bz[z] * zz[p] + a * (second_diff(W.z, g.zs) * g.cz + d1p);
-        zz[p] = v;
-        C += v;
+    if (zq) {
+      if (near(sh, 2, z)) {
+        const float d1p = qp.d1() * t.ihz;
+        C += d1p;
+        const float az = t.az[z];
+        if (az != 0.0f) {
+          const float v = t.bz[z] * zz_[p] + az * (qw.d2() * g.cz + d1p);
+          zz_[p] = v;
+          C += v;
+        }
       }
+      qw.advance(wz, z);
+      qp.advance(pzz, z);
     }
     if (z > g.zs) out[p] += g.k[p] * C;
-    if (cstore) cstore[q] = C;
+    if (cstore) cstore[c.q(sh, z)] = C;
   }
 }
 
@@ -224,25 +314,34 @@ __global__ void __launch_bounds__(kThreads)
     k_cpml_mu(StepGrid g, CpmlTables t, Shell sh, const float *__restrict__ phi1,
               const float *__restrict__ nx_, const float *__restrict__ ny_,
               const float *__restrict__ nz_, float *mx, float *my, float *mz) {
-  const int64_t total = sh.start[sh.nbox];
-  for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < total;
-       q += (int64_t)gridDim.x * blockDim.x) {
-    int x, y, z;
-    decode(sh, q, x, y, z);
-    const int64_t p = lin(g, x, y, z);
-    const Axes F = lines(g, phi1, nullptr, nullptr, nullptr, x, y, z);
-    // D1 of (a nu + phi1) = D1 of a nu + D1 of phi1
-    if (t.ax[x] != 0.0f) {
-      const float d = first_diff(Line{nx_, t.ax, p, 1, x, g.nx}) + first_diff(F.x);
-      mx[p] = t.bx[x] * mx[p] - d * t.ihx;
+  Column c;
+  if (!c.init(sh, g)) return;
+  const bool zq = sh.zq[c.b];
+  const float ax = t.ax[c.x], bx = t.bx[c.x], ay = t.ay[c.y], by = t.by[c.y];
+  // D1 of (a nu + phi1); along z from a queue of a_z nu_z + phi1
+  auto fz = [&](int zz) {
+    return (zz >= 0 && zz < g.nz) ? t.az[zz] * nz_[(int64_t)zz * g.plane + c.pxy] +
+                                        phi1[(int64_t)zz * g.plane + c.pxy]
+                                  : 0.0f;
+  };
+  ZWin qf;
+  if (zq) qf.prime(fz, c.z0);
+  for (int z = c.z0; z < c.z1; ++z) {
+    const int64_t p = (int64_t)z * g.plane + c.pxy;
+    if (ax != 0.0f) {
+      const float d = first_diff(Line{nx_, t.ax, p, 1, c.x, g.nx}) +
+                      first_diff(Line{phi1, nullptr, p, 1, c.x, g.nx});
+      mx[p] = bx * mx[p] - d * t.ihx;
     }
-    if (t.ay[y] != 0.0f) {
-      const float d = first_diff(Line{ny_, t.ay, p, g.pitch, y, g.ny}) + first_diff(F.y);
-      my[p] = t.by[y] * my[p] - d * t.ihy;
+    if (ay != 0.0f) {
+      const float d = first_diff(Line{ny_, t.ay, p, g.pitch, c.y, g.ny}) +
+                      first_diff(Line{phi1, nullptr, p, g.pitch, c.y, g.ny});
+      my[p] = by * my[p] - d * t.ihy;
     }
-    if (t.az[z] != 0.0f) {
-      const float d = first_diff(Line{nz_, t.az, p, g.plane, z, g.nz}) + first_diff(F.z);
-      mz[p] = t.bz[z] * mz[p] - d * t.ihz;
+    if (zq) {
+      const float az = t.az[z];
+      if (az != 0.0f) mz[p] = t.bz[z] * mz[p] - qf.d1() * t.ihz;
+      qf.advance(fz, z);
     }
   }
 }
@@ -253,24 +352,44 @@ __global__ void __launch_bounds__(kThreads)
                    const float *__restrict__ mx, const float *__restrict__ my,
                    const float *__restrict__ mz, float *phi, const float *__restrict__ phi1,
                    const float *__restrict__ cstore, float *grad) {
-  const int64_t total = sh.start[sh.nbox];
-  for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < total;
-       q += (int64_t)gridDim.x * blockDim.x) {
-    int x, y, z;
-    decode(sh, q, x, y, z);
-    const int64_t p = lin(g, x, y, z);
+  Column c;
+  if (!c.init(sh, g)) return;
+  const bool zq = sh.zq[c.b];
+  const bool nx = near(sh, 0, c.x), ny = near(sh, 1, c.y);
+  // along z: a_z nu_z (image planes above a free surface, for D2) and a_z mu_z
+  auto nuz = [&](int zz) {
+    int z2 = zz;
+    float sgn = 1.0f;
+    if (zz < g.zs) {
+      z2 = 2 * g.zs - zz;
+      sgn = -1.0f;
+    }
+    return (z2 >= 0 && z2 < g.nz) ? sgn * t.az[z2] * nz_[(int64_t)z2 * g.plane + c.pxy] : 0.0f;
+  };
+  auto muz = [&](int zz) {
+    return (zz >= 0 && zz < g.nz) ? t.az[zz] * mz[(int64_t)zz * g.plane + c.pxy] : 0.0f;
+  };
+  ZWin qn, qm;
+  if (zq) {
+    qn.prime(nuz, c.z0);
+    qm.prime(muz, c.z0);
+  }
+  for (int z = c.z0; z < c.z1; ++z) {
+    const int64_t p = (int64_t)z * g.plane + c.pxy;
     float corr = 0.0f;
-    if (near(sh, 0, x))
-      corr += second_diff(Line{nx_, t.ax, p, 1, x, g.nx}, kNoSurface) * g.cx -
-              first_diff(Line{mx, t.ax, p, 1, x, g.nx}) * t.ihx;
-    if (near(sh, 1, y))
-      corr += second_diff(Line{ny_, t.ay, p, g.pitch, y, g.ny}, kNoSurface) * g.cy -
-              first_diff(Line{my, t.ay, p, g.pitch, y, g.ny}) * t.ihy;
-    if (near(sh, 2, z))
-      corr += second_diff(Line{nz_, t.az, p, g.plane, z, g.nz}, g.zs) * g.cz -
-              first_diff(Line{mz, t.az, p, g.plane, z, g.nz}) * t.ihz;
+    if (nx)
+      corr += second_diff(Line{nx_, t.ax, p, 1, c.x, g.nx}, kNoSurface) * g.cx -
+              first_diff(Line{mx, t.ax, p, 1, c.x, g.nx}) * t.ihx;
+    if (ny)
+      corr += second_diff(Line{ny_, t.ay, p, g.pitch, c.y, g.ny}, kNoSurface) * g.cy -
+              first_diff(Line{my, t.ay, p, g.pitch, c.y, g.ny}) * t.ihy;
+    if (zq) {
+      if (near(sh, 2, z)) corr += qn.d2() * g.cz - qm.d1() * t.ihz;
+      qn.advance(nuz, z);
+      qm.advance(muz, z);
+    }
     if (z > g.zs) phi[p] += g.k[p] * corr;
-    if (cstore) grad[p] += phi1[p] * cstore[q];
+    if (cstore) grad[p] += phi1[p] * cstore[c.q(sh, z)];
   }
 }
 
@@ -287,13 +406,15 @@ unsigned blocks_for(const Shell &sh) {
   return (unsigned)(b < 1 ? 1 : (b > 16384 ? 16384 : b));
 }
 
+unsigned columns_for(const Shell &sh) { return (unsigned)sh.bstart[sh.nbox]; }
+
 }  // namespace
 
 hipError_t launch_cpml_psi(const StepGrid &g, const CpmlTables &t, const Shell &sh,
                            const float *cur, float *psi_x, float *psi_y, float *psi_z,
                            hipStream_t stream) {
   if (sh.start[sh.nbox] == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_cpml_psi, dim3(blocks_for(sh)), dim3(kThreads), 0, stream, g, t, sh, cur,
+  hipLaunchKernelGGL(k_cpml_psi, dim3(columns_for(sh)), dim3(kThreads), 0, stream, g, t, sh, cur,
                      psi_x, psi_y, psi_z);
   return hipGetLastError();
 }
@@ -303,7 +424,7 @@ hipError_t launch_cpml_zeta(const StepGrid &g, const CpmlTables &t, const Shell 
                             const float *psi_z, float *zeta_x, float *zeta_y, float *zeta_z,
                             float *out, float *cstore, hipStream_t stream) {
   if (sh.start[sh.nbox] == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_cpml_zeta, dim3(blocks_for(sh)), dim3(kThreads), 0, stream, g, t, sh, cur,
+  hipLaunchKernelGGL(k_cpml_zeta, dim3(columns_for(sh)), dim3(kThreads), 0, stream, g, t, sh, cur,
                      psi_x, psi_y, psi_z, zeta_x, zeta_y, zeta_z, out, cstore);
   return hipGetLastError();
 }
@@ -322,7 +443,7 @@ hipError_t launch_cpml_mu(const StepGrid &g, const CpmlTables &t, const Shell &s
                           const float *nu_z, float *mu_x, float *mu_y, float *mu_z,
                           hipStream_t stream) {
   if (sh.start[sh.nbox] == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_cpml_mu, dim3(blocks_for(sh)), dim3(kThreads), 0, stream, g, t, sh, phi1,
+  hipLaunchKernelGGL(k_cpml_mu, dim3(columns_for(sh)), dim3(kThreads), 0, stream, g, t, sh, phi1,
                      nu_x, nu_y, nu_z, mu_x, mu_y, mu_z);
   return hipGetLastError();
 }
@@ -333,7 +454,7 @@ hipError_t launch_cpml_adjoint(const StepGrid &g, const CpmlTables &t, const She
                                float *phi, const float *phi1, const float *cstore, float *grad,
                                hipStream_t stream) {
   if (sh.start[sh.nbox] == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_cpml_adjoint, dim3(blocks_for(sh)), dim3(kThreads), 0, stream, g, t, sh,
+  hipLaunchKernelGGL(k_cpml_adjoint, dim3(columns_for(sh)), dim3(kThreads), 0, stream, g, t, sh,
                      nu_x, nu_y, nu_z, mu_x, mu_y, mu_z, phi, phi1, cstore, grad);
   return hipGetLastError();
 }

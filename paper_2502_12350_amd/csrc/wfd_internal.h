@@ -187,7 +187,15 @@ struct Shell {
   int64_t start[kShellBoxes + 1];
   int zfirst[kShellBoxes];  // 1: order x, z, y (z before y), for boxes thin in z
   int lo[3], hi[3];
+  // Column marching: a block of 64 x 4 threads owns one (x, y) tile of a box
+  // and marches a chunk of cz planes; tx, ty, nch tile counts per box, bstart
+  // the first block of each box, zq whether the box reaches z-derivative terms
+  // (then each thread keeps nine-plane queues along z and the chunks are long,
+  // kShellChunkZ; other boxes take short chunks, kShellChunk, for parallelism).
+  int tx[kShellBoxes], ty[kShellBoxes], nch[kShellBoxes], zq[kShellBoxes], cz[kShellBoxes];
+  int64_t bstart[kShellBoxes + 1];
 };
+constexpr int kShellTileX = 64, kShellTileY = 4, kShellChunkZ = 16, kShellChunk = 8;
 // Forward: psi_d = b psi_d + a D1_d w (cur) on the layer.
 hipError_t launch_cpml_psi(const StepGrid &g, const CpmlTables &t, const Shell &sh,
                            const float *cur, float *psi_x, float *psi_y, float *psi_z,
