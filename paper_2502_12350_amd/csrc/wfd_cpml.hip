@@ -15,9 +15,11 @@
 //
 // D1 is the eighth-order central first difference (4/5, -1/5, 4/105, -1/280)
 // and D2 the second difference of L; cells outside the padded grid are zero,
-// and D2 along z reads the free surface's negated image like L does.  These
-// kernels are gathers over a few hundred million points at most and are
-// bound by L2 traffic, not by their arithmetic.
+// and D2 along z reads the free surface's negated image like L does.  A block
+// of 64 x 4 threads owns an (x, y) tile of one shell box and marches a chunk
+// of planes; where the box is within reach of a z layer each thread keeps
+// nine-plane queues along z, and x and y neighbours come through the caches.
+// The point-wise nu update runs one thread per shell point.
 #include <hip/hip_runtime.h>
 
 #include <stdint.h>
@@ -71,8 +73,7 @@ __device__ __forceinline__ bool near(const Shell &sh, int d, int i) {
 }
 
 // A field along one axis through (x, y, z), optionally weighted by that axis'
-// a table, zero outside the grid; with `image`, z planes above the free
-// surface read the negated mirror (as L does).
+// a table, zero outside the grid.
 struct Line {
   const float *p;  // the point
   const float *a;  // weight per index along the axis, or nullptr
@@ -100,39 +101,12 @@ __device__ __forceinline__ float first_diff(const Line &f) {
   return s;
 }
 
-// Second difference along the line; for z lines with a free surface at zs,
-// offsets landing above it read -value(2 zs - z').
-__device__ __forceinline__ float second_diff(const Line &f, int zs) {
+// Second difference along the line (x or y: no image planes).
+__device__ __forceinline__ float second_diff(const Line &f) {
   float s = d2c(0) * f(0);
-  if (f.i - kStencilRadius >= zs) {  // no image plane within reach (also: no surface)
 #pragma unroll
-    for (int j = 1; j <= 4; ++j) s += d2c(j) * (f(j) + f(-j));
-    return s;
-  }
-#pragma unroll
-  for (int j = 1; j <= 4; ++j) {
-    const float up = f(j);
-    float dn;
-    const int zz = f.i - j;
-    if (zz < zs) {
-      const int zm = 2 * zs - zz;  // image plane
-      dn = zm < f.n ? -f(zm - f.i) : 0.0f;
-    } else {
-      dn = f(-j);
-    }
-    s += d2c(j) * (up + dn);
-  }
+  for (int j = 1; j <= 4; ++j) s += d2c(j) * (f(j) + f(-j));
   return s;
-}
-
-struct Axes {
-  Line x, y, z;
-};
-__device__ __forceinline__ Axes lines(const StepGrid &g, const float *u, const float *ax,
-                                      const float *ay, const float *az, int x, int y, int z) {
-  const int64_t p = lin(g, x, y, z);
-  return Axes{Line{u, ax, p, 1, x, g.nx}, Line{u, ay, p, g.pitch, y, g.ny},
-              Line{u, az, p, g.plane, z, g.nz}};
 }
 
 constexpr int kThreads = 256;
@@ -259,7 +233,7 @@ __global__ void __launch_bounds__(kThreads)
       C += d1p;
       if (ax != 0.0f) {
         const float v =
-            bx * zx[p] + ax * (second_diff(Line{w, nullptr, p, 1, c.x, g.nx}, kNoSurface) * g.cx + d1p);
+            bx * zx[p] + ax * (second_diff(Line{w, nullptr, p, 1, c.x, g.nx}) * g.cx + d1p);
         zx[p] = v;
         C += v;
       }
@@ -269,7 +243,7 @@ __global__ void __launch_bounds__(kThreads)
       C += d1p;
       if (ay != 0.0f) {
         const float v = by * zy[p] +
-                        ay * (second_diff(Line{w, nullptr, p, g.pitch, c.y, g.ny}, kNoSurface) *
+                        ay * (second_diff(Line{w, nullptr, p, g.pitch, c.y, g.ny}) *
                                   g.cy + d1p);
         zy[p] = v;
         C += v;
@@ -378,10 +352,10 @@ __global__ void __launch_bounds__(kThreads)
     const int64_t p = (int64_t)z * g.plane + c.pxy;
     float corr = 0.0f;
     if (nx)
-      corr += second_diff(Line{nx_, t.ax, p, 1, c.x, g.nx}, kNoSurface) * g.cx -
+      corr += second_diff(Line{nx_, t.ax, p, 1, c.x, g.nx}) * g.cx -
               first_diff(Line{mx, t.ax, p, 1, c.x, g.nx}) * t.ihx;
     if (ny)
-      corr += second_diff(Line{ny_, t.ay, p, g.pitch, c.y, g.ny}, kNoSurface) * g.cy -
+      corr += second_diff(Line{ny_, t.ay, p, g.pitch, c.y, g.ny}) * g.cy -
               first_diff(Line{my, t.ay, p, g.pitch, c.y, g.ny}) * t.ihy;
     if (zq) {
       if (near(sh, 2, z)) corr += qn.d2() * g.cz - qm.d1() * t.ihz;
