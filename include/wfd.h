@@ -188,9 +188,11 @@ wfd_status wfd_forward_misfit(wfd_ctx *ctx, const float *wavelet_dev, const doub
 wfd_status wfd_misfit_workspace_bytes(const wfd_ctx *ctx, int32_t nrec, size_t *bytes);
 
 /* Misfit and velocity gradient of one shot (Alg. 3 body for one shot).
- * With the CPML boundary only WFD_CKPT_FULL is accepted (the layer's
- * correction of every step is kept for the imaging condition, on the shell
- * of points the layer reaches); other modes return WFD_E_ARG.  The steps:
+ * With the CPML boundary WFD_CKPT_FULL keeps the layer's correction of every
+ * step (on the shell of points the layer reaches) for the imaging condition;
+ * WFD_CKPT_REVOLVE keeps six memory-variable volumes with each checkpoint
+ * (a checkpoint then costs 8 volumes, not 2) and recomputes a visited step's
+ * correction; WFD_CKPT_HOST returns WFD_E_ARG.  The steps:
  * forward sweep with recording and wavefield saving, res = d - d_obs,
  * J = 1/2 sum res^2, discrete adjoint sweep (exact transpose of the forward
  * recursion) with the zero-lag cross-correlation imaging condition, then

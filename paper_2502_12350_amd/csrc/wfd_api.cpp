@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -336,7 +337,13 @@ struct Work {
   double *partial;
   int64_t n_store_vols;
   float *mem[6];   // CPML memory variables psi_x..z, zeta_x..z (adjoint: mu, nu)
-  float *cstore;   // CPML: correction C^n of every step on the shell (gradient)
+  float *cstore;   // CPML, full storage: correction C^n of every step on the shell
+  // CPML with checkpointing: the adjoint's own mu, nu; one memory-variable set
+  // per checkpoint slot; the correction of the latest forward step and one
+  // recomputed for a visit (both on the shell)
+  float *amem[6];
+  float *smem;
+  float *lastc, *visitc;
   size_t bytes;
 };
 
@@ -347,7 +354,8 @@ int64_t snapshots_for(const wfd_ctx *c, const wfd_ckpt *ck) {
   size_t free_b = 0, total_b = 0;
   if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) return 0;
   const double frac = (ck->mem_fraction > 0 && ck->mem_fraction <= 1.0) ? ck->mem_fraction : 0.8;
-  const double pair = 2.0 * (double)c->vol * sizeof(float);
+  // a checkpoint holds a leapfrog pair, and with CPML six memory variables
+  const double pair = (c->cpml ? 8.0 : 2.0) * (double)c->vol * sizeof(float);
   int64_t s = (int64_t)(frac * (double)free_b / pair);
   return std::max<int64_t>(1, std::min<int64_t>(s, c->grid.nt));
 }
@@ -422,9 +430,16 @@ Work work_layout(const wfd_ctx *c, int nrec, WorkKind kind, const wfd_ckpt *ck, 
     w.partial = cv.take<double>((size_t)std::max(1, wfd::residual_partial_count(nrec, c->grid.nt)));
   }
   if (c->cpml) {
+    const size_t S = (size_t)c->shell.start[c->shell.nbox];
     for (int i = 0; i < 6; ++i) w.mem[i] = cv.take<float>((size_t)c->vol);
     if (kind == WorkKind::Gradient && ck && ck->mode == WFD_CKPT_FULL)
-      w.cstore = cv.take<float>((size_t)c->grid.nt * (size_t)c->shell.start[c->shell.nbox]);
+      w.cstore = cv.take<float>((size_t)c->grid.nt * S);
+    if (kind == WorkKind::Gradient && ck && ck->mode == WFD_CKPT_REVOLVE) {
+      for (int i = 0; i < 6; ++i) w.amem[i] = cv.take<float>((size_t)c->vol);
+      w.smem = cv.take<float>((size_t)nsnap * 6 * (size_t)c->vol);
+      w.lastc = cv.take<float>(std::max<size_t>(S, 1));
+      w.visitc = cv.take<float>(std::max<size_t>(S, 1));
+    }
   }
   if (kind == WorkKind::Gradient) {
     w.P1 = cv.take<float>((size_t)c->vol);
@@ -798,13 +813,14 @@ namespace {
 // from cur): memory variables, the correction k C added to out, C kept in
 // cstore when given, and the receivers read from out afterwards.
 wfd_status cpml_forward_terms(wfd_ctx *c, const wfd::StepGrid &g, const Work &w,
-                              const float *cur, float *out, float *cstore, int nrec, int n) {
+                              const float *cur, float *out, float *cstore, int nrec, int n,
+                              float *const *mem = nullptr) {
   Timed t(c, WFD_K_OTHER);
-  HIP_TRY(wfd::launch_cpml_psi(g, c->cpml_tab, c->shell, cur, w.mem[0], w.mem[1], w.mem[2],
-                               c->stream));
-  HIP_TRY(wfd::launch_cpml_zeta(g, c->cpml_tab, c->shell, cur, w.mem[0], w.mem[1], w.mem[2],
-                                w.mem[3], w.mem[4], w.mem[5], out, cstore, c->stream));
-  if (nrec > 0)
+  float *const *m = mem ? mem : w.mem;  // out == nullptr: only the memory variables and C
+  HIP_TRY(wfd::launch_cpml_psi(g, c->cpml_tab, c->shell, cur, m[0], m[1], m[2], c->stream));
+  HIP_TRY(wfd::launch_cpml_zeta(g, c->cpml_tab, c->shell, cur, m[0], m[1], m[2], m[3], m[4],
+                                m[5], out, cstore, c->stream));
+  if (nrec > 0 && out)
     HIP_TRY(wfd::launch_record(out, w.rec_idx, w.rec_scale, nrec, n, w.seis_tm, c->stream));
   return WFD_OK;
 }
@@ -813,18 +829,20 @@ wfd_status cpml_forward_terms(wfd_ctx *c, const wfd::StepGrid &g, const Work &w,
 // before the step kernel, then (pre = false) the correction of phi^m and the
 // imaging term phi^{m+1} C^m.
 wfd_status cpml_adjoint_terms(wfd_ctx *c, const wfd::StepGrid &g, const Work &w,
-                              const float *phi1, float *phi, int m, bool pre) {
+                              const float *phi1, float *phi, int m, bool pre,
+                              const float *corr_m = nullptr) {
   Timed t(c, WFD_K_OTHER);
-  float *const *v = w.mem;  // mu = v[0..2], nu = v[3..5]
+  float *const *v = w.smem ? w.amem : w.mem;  // mu = v[0..2], nu = v[3..5]
   if (pre) {
     HIP_TRY(wfd::launch_cpml_nu(g, c->cpml_tab, c->shell, phi1, v[3], v[4], v[5], c->stream));
     HIP_TRY(wfd::launch_cpml_mu(g, c->cpml_tab, c->shell, phi1, v[3], v[4], v[5], v[0], v[1],
                                 v[2], c->stream));
     return WFD_OK;
   }
-  const float *cst = (m < c->grid.nt && w.cstore)
-                         ? w.cstore + (size_t)m * (size_t)c->shell.start[c->shell.nbox]
-                         : nullptr;
+  const float *cst = m >= c->grid.nt ? nullptr
+                     : corr_m      ? corr_m
+                     : w.cstore    ? w.cstore + (size_t)m * (size_t)c->shell.start[c->shell.nbox]
+                                   : nullptr;
   HIP_TRY(wfd::launch_cpml_adjoint(g, c->cpml_tab, c->shell, v[3], v[4], v[5], v[0], v[1], v[2],
                                    phi, phi1, cst, w.g, c->stream));
   return WFD_OK;
@@ -925,8 +943,8 @@ wfd_status wfd_gradient(wfd_ctx *c, const float *wavelet, const double src_xyz[3
   if (!work) return fail(WFD_E_ARG, "workspace is NULL");
   if ((uintptr_t)work % kAlign) return fail(WFD_E_ARG, "workspace must be 256-byte aligned");
   ScopedDevice sd(c->device);
-  if (c->cpml && ck->mode != WFD_CKPT_FULL)
-    return fail(WFD_E_ARG, "the CPML gradient needs full storage (WFD_CKPT_FULL)");
+  if (c->cpml && ck->mode == WFD_CKPT_HOST)
+    return fail(WFD_E_ARG, "the CPML gradient needs device storage (full or checkpointed)");
   if (ck->mode == WFD_CKPT_HOST) {
     if ((s = check_host_store(c, ck)) != WFD_OK) return s;
     if ((s = ensure_copy_stream(c)) != WFD_OK) return s;
@@ -941,7 +959,7 @@ wfd_status wfd_gradient(wfd_ctx *c, const float *wavelet, const double src_xyz[3
   } else {
     // derived count: as many pairs as the given workspace holds
     const size_t base = work_layout(c, nrec, WorkKind::Gradient, ck, 0, nullptr).bytes;
-    const size_t pair = align_up((size_t)c->vol * sizeof(float)) * 2;
+    const size_t pair = align_up((size_t)c->vol * sizeof(float)) * (c->cpml ? 8 : 2);
     nsnap = work_bytes > base ? (int64_t)((work_bytes - base) / pair) : 0;
     nsnap = std::min<int64_t>(nsnap, c->grid.nt);
     if (nsnap < 1) return fail(WFD_E_NOMEM, "workspace holds no checkpoint pair");
@@ -984,7 +1002,7 @@ wfd_status wfd_gradient(wfd_ctx *c, const float *wavelet, const double src_xyz[3
     }
     return WFD_OK;
   };
-  auto adjoint = [&](int m, const float *wm) -> wfd_status {
+  auto adjoint = [&](int m, const float *wm, const float *corr_m = nullptr) -> wfd_status {
     if (c->cpml && (s = cpml_adjoint_terms(c, g, w, A1, A2, m, true)) != WFD_OK) return s;
     {
       Timed t(c, WFD_K_ADJOINT);
@@ -992,10 +1010,12 @@ wfd_status wfd_gradient(wfd_ctx *c, const float *wavelet, const double src_xyz[3
                                        c->grid.border, c->grid.nx, c->grid.ny, c->grid.nz,
                                        c->stream));
     }
-    if (c->cpml && (s = cpml_adjoint_terms(c, g, w, A1, A2, m, false)) != WFD_OK) return s;
+    if (c->cpml && (s = cpml_adjoint_terms(c, g, w, A1, A2, m, false, corr_m)) != WFD_OK)
+      return s;
     std::swap(A1, A2);
     return WFD_OK;
   };
+  int last_c_step = -1;  // CPML with checkpointing: the step whose C w.lastc holds
   auto fwd = [&](const float *cur, const float *prev, float *out, int n, bool rec) -> wfd_status {
     {
       Timed t(c, WFD_K_FORWARD);
@@ -1003,10 +1023,12 @@ wfd_status wfd_gradient(wfd_ctx *c, const float *wavelet, const double src_xyz[3
                                        (rec && nrec > 0 && !c->cpml) ? &rt : nullptr, w.rec_scale,
                                        w.seis_tm, c->tuning, c->stream));
     }
-    if (c->cpml) {  // full storage only: every step is recorded once, in order
-      float *cst = w.cstore + (size_t)n * (size_t)c->shell.start[c->shell.nbox];
+    if (c->cpml) {  // full storage keeps every step's C; checkpointing the latest
+      float *cst = w.cstore ? w.cstore + (size_t)n * (size_t)c->shell.start[c->shell.nbox]
+                            : w.lastc;
       if ((s = cpml_forward_terms(c, g, w, cur, out, cst, rec ? nrec : 0, n)) != WFD_OK)
         return s;
+      last_c_step = n;
     }
     return WFD_OK;
   };
@@ -1102,6 +1124,22 @@ wfd_status wfd_gradient(wfd_ctx *c, const float *wavelet, const double src_xyz[3
         if (pins[i] == 0 && (int)i != not1 && (int)i != not2) return (int)i;
       return -1;
     };
+    // CPML: a state m also carries the memory variables of step m - 1, kept in
+    // w.mem while m is the working state and copied to and from slot sets.
+    auto slot_mem = [&](size_t slot) {
+      std::array<float *, 6> m;
+      for (int i = 0; i < 6; ++i) m[i] = w.smem + (slot * 6 + (size_t)i) * (size_t)c->vol;
+      return m;
+    };
+    auto copy_mem = [&](float *const *dst, float *const *src) -> wfd_status {
+      for (int i = 0; i < 6; ++i)
+        HIP_TRY(hipMemcpyAsync(dst[i], src[i], (size_t)c->vol * sizeof(float),
+                               hipMemcpyDeviceToDevice, c->stream));
+      return WFD_OK;
+    };
+    if (c->cpml)
+      for (float *m : w.amem)
+        if ((s = zero(c, m, c->vol)) != WFD_OK) return s;
     for (size_t i = 0; i + 3 <= plan.size(); i += 3) {
       const int op = plan[i], a = plan[i + 1], b = plan[i + 2];
       if (op == wfd::kAdvance) {
@@ -1112,11 +1150,17 @@ wfd_status wfd_gradient(wfd_ctx *c, const float *wavelet, const double src_xyz[3
             if (cur < 0 || prev < 0) return fail(WFD_E_STATE, "checkpoint pool exhausted");
             if ((s = zero(c, buf[cur], c->vol)) != WFD_OK) return s;
             if ((s = zero(c, buf[prev], c->vol)) != WFD_OK) return s;
+            if (c->cpml)
+              for (float *m : w.mem)
+                if ((s = zero(c, m, c->vol)) != WFD_OK) return s;
           } else {
             Slot *sl = slot_of(a);
             if (!sl) return fail(WFD_E_STATE, "checkpoint plan: state %d not stored", a);
             cur = sl->a;
             prev = sl->b;
+            if (c->cpml && (s = copy_mem(w.mem, slot_mem((size_t)(sl - slots.data())).data())) !=
+                               WFD_OK)
+              return s;
           }
         }
         for (int n = a; n < b; ++n) {
@@ -1136,6 +1180,7 @@ wfd_status wfd_gradient(wfd_ctx *c, const float *wavelet, const double src_xyz[3
         sl.b = prev;
         ++pins[cur];
         ++pins[prev];
+        if (c->cpml && (s = copy_mem(slot_mem((size_t)b).data(), w.mem)) != WFD_OK) return s;
       } else if (op == wfd::kVisit) {
         if ((s = residual()) != WFD_OK) return s;
         const float *wm = nullptr;
@@ -1146,7 +1191,29 @@ wfd_status wfd_gradient(wfd_ctx *c, const float *wavelet, const double src_xyz[3
         else if (cur_state == a + 1)
           wm = buf[prev];
         if (!wm) return fail(WFD_E_STATE, "checkpoint plan: state %d unavailable", a);
-        if ((s = adjoint(a, wm)) != WFD_OK) return s;
+        const float *corr = nullptr;
+        if (c->cpml && a < nt) {
+          // C^a comes from the step that leaves state a: the latest forward
+          // step, or recomputed from state a and its memory variables (the
+          // visit is the state's last use, so they may be overwritten)
+          if (last_c_step == a) {
+            corr = w.lastc;
+          } else if (cur_state == a) {
+            if ((s = cpml_forward_terms(c, g, w, buf[cur], nullptr, w.visitc, 0, a)) != WFD_OK)
+              return s;
+            corr = w.visitc;
+          } else if (Slot *sl = slot_of(a)) {
+            const auto m = slot_mem((size_t)(sl - slots.data()));
+            if ((s = cpml_forward_terms(c, g, w, buf[sl->a], nullptr, w.visitc, 0, a,
+                                        m.data())) != WFD_OK)
+              return s;
+            corr = w.visitc;
+          } else {
+            return fail(WFD_E_STATE, "checkpoint plan: the layer's correction of step %d is lost",
+                        a);
+          }
+        }
+        if ((s = adjoint(a, wm, corr)) != WFD_OK) return s;
       } else if (op == wfd::kFree) {
         Slot &sl = slots[(size_t)b];
         --pins[sl.a];

@@ -263,7 +263,7 @@ __global__ void __launch_bounds__(kThreads)
       qw.advance(wz, z);
       qp.advance(pzz, z);
     }
-    if (z > g.zs) out[p] += g.k[p] * C;
+    if (out && z > g.zs) out[p] += g.k[p] * C;
     if (cstore) cstore[c.q(sh, z)] = C;
   }
 }

@@ -43,12 +43,11 @@ class Shots:
 
 def auto_checkpoint(prop: Propagator, nrec: int, fraction: float = 0.8):
     """Full storage when it fits in `fraction` of the free device memory,
-    else binomial checkpointing sized to that memory (the paper's check_mem).
-    A CPML grid always takes full storage (the only mode its gradient has)."""
+    else binomial checkpointing sized to that memory (the paper's check_mem;
+    on a CPML grid each checkpoint also holds the layer's memory variables,
+    which the library counts)."""
     import torch
     free, _ = torch.cuda.mem_get_info(prop.device)
-    if prop.grid is not None and prop.grid.cpml:
-        return "full"
     if prop.workspace_bytes(nrec, "full") <= fraction * free:
         return "full"
     return ("revolve", 0, fraction)
