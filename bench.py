@@ -594,6 +594,42 @@ def kernel_table_bench(steps: int = 200):
     del c2
     c1 = seisgen.workload("c1")
     run("forward_cd_c1_80cubed", c1, None, False, False)
+    # the same forward with its time loop replayed as one HIP graph (a one-shot
+    # batch): on this launch-bound grid the graph removes the launch gaps
+    from paper_2502_12350_amd import ShotBatch
+    gs1 = GridSpec(**{**c1.grid_kwargs(), "nt": steps})
+    P1 = Propagator(0)
+    P1.set_model(gs1, torch.from_numpy(c1.vel).to(dev))
+    side = torch.cuda.Stream()  # graph capture needs a non-default stream
+    wav1 = torch.from_numpy(c1.wavelet[:steps]).to(dev)
+    torch.cuda.synchronize()
+    with torch.cuda.stream(side):
+        b1 = ShotBatch([P1], wav1, [c1.sources[0]], [c1.receivers], stream=side)
+    for use_graph, tune in ((False, False), (True, False), (True, True)):
+        if tune:  # launch shapes picked by the autotuner for this grid
+            b1.close()
+            tuned, fus, _ = P1.autotune(steps=20)
+            print(f"[bench-kernels] c1 autotuned {tuned}: forward {fus:.1f} us per step",
+                  file=sys.stderr, flush=True)
+            with torch.cuda.stream(side):
+                b1 = ShotBatch([P1], wav1, [c1.sources[0]], [c1.receivers], stream=side)
+        with torch.cuda.stream(side):
+            b1.run(use_graph)
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(side)
+            for _ in range(5):
+                b1.run(use_graph)
+            e1.record(side)
+        torch.cuda.synchronize()
+        us = 1e3 * e0.elapsed_time(e1) / 5 / steps
+        name = "forward_cd_c1_80cubed_" + ("graph" if use_graph else "batch_eager") + \
+            ("_autotuned" if tune else "")
+        rows[name] = {"us_per_step": round(us, 2), "gpts_padded": round(c1.padded_points / us / 1e3, 1),
+                      "gpts_model": round(c1.nx * c1.ny * c1.nz / us / 1e3, 1), "bytes_per_point": 16,
+                      "note": "wall time per step incl. launch gaps (events around the whole loop)"}
+        print(f"[bench-kernels] {name}: {rows[name]}", file=sys.stderr, flush=True)
+    b1.close()
     c4 = seisgen.workload("c4")
     run("forward_cd_c4_240x240x200", c4, None, False, False)
     out = {"metric": "per-kernel Gpt/s and %HBM", "unit": "Gpt/s", "n_gpus": 1, "dtype": "f32",
