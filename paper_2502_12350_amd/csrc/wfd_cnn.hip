@@ -16,12 +16,13 @@
 //
 // Convolution as an implicit GEMM: for a row of 16 output voxels,
 // D[co][voxel] = sum_k A[co][k] X[k][voxel] with X[tap * CIN + ci][voxel] =
-// input[voxel + offset(tap)][ci].  A block stages a 66 x 6 x 4 voxel brick of
-// the input (a 64 x 4 x 2 output tile plus a one-voxel halo) in LDS; each of
-// its 8 wavefronts computes one 64-voxel output row as four 16 x 16 tiles
-// with the packed weights held in registers.  The data gradient is the same kernel on
-// flipped, transposed weights; the weight gradient reduces over voxels with
-// the voxel index as the matrix-core K dimension.
+// input[voxel + offset(tap)][ci].  A convolution block marches a 64 x 4
+// output tile along z with a ring of input planes in LDS (k_conv); each of its
+// 4 wavefronts computes one 64-voxel output row as four 16 x 16 tiles with the
+// packed weights held in registers.  The data gradient is the same kernel on
+// flipped, transposed weights; the weight gradient stages 66 x 4 x 4 input
+// bricks and reduces over voxels with the voxel index as the matrix-core K
+// dimension.
 #include <hip/hip_runtime.h>
 
 #include <stdint.h>
@@ -45,10 +46,8 @@ struct Brick {
   static constexpr int VOX = LX * LY * LZ;  // voxels staged per block
   static constexpr int ROWS = OY * OZ;      // 64-voxel output rows per block
 };
-using ConvBrick = Brick<4, 2>;   // convolutions: 512 outputs, 1584 staged voxels
 using WgradBrick = Brick<2, 2>;  // weight gradient: 256 voxels per K sweep
 constexpr int NTHR = 256;        // 4 wavefronts (weight gradient)
-constexpr int CONV_THR = 512;    // 8 wavefronts, one output row each
 
 __device__ __forceinline__ uint16_t to_bf16(float f) {
   uint32_t u = __float_as_uint(f);
@@ -129,19 +128,123 @@ __device__ __forceinline__ bf16x8 gather_b(const uint16_t *lds, int c, int lx, i
 // relu, then * (mask > 0), then (single output channel only) + channel 0 of
 // res[voxel][res_c]; written as BF16 and/or FP32 channels-last with COUT
 // channels.  Every output voxel of the tile is computed by exactly one lane.
+//
+// A block owns a 64 x 4 output tile in x-y and marches CM_ZC output planes
+// along z.  Input planes (the tile plus a one-voxel halo, 66 x 6 voxels) live
+// in a four-slot LDS ring, plane p in slot p & 3: output plane z reads planes
+// z - 1 .. z + 1 while plane z + 2 is fetched, into registers before the
+// matrix-core work and into its slot after it, so one barrier per plane
+// suffices (the slot written held plane z - 2, read only before the previous
+// barrier).  Each of the 4 wavefronts computes one 64-voxel output row as
+// four 16 x 16 tiles with the packed weights held in registers.
+constexpr int CM_TY = 4, CM_ZC = 16, CM_THR = 256;
+constexpr int CM_LX = 66, CM_LY = CM_TY + 2, CM_PLANE = CM_LX * CM_LY, CM_SLOTS = 4;
+// CIN = 16: a plane is CM_PLANE * 2 sixteen-byte items, at most CM_PF per thread
+constexpr int CM_PF = (CM_PLANE * 2 + CM_THR - 1) / CM_THR;
+
+inline int cm_tiles(int nx, int ny, int nz) {
+  return ((nx + 63) / 64) * ((ny + CM_TY - 1) / CM_TY) * ((nz + CM_ZC - 1) / CM_ZC);
+}
+
+// CIN = 16: fetch plane gz into registers, then store it into its slot.
+__device__ __forceinline__ void cm_fetch16(u32x4 *pf, const uint16_t *__restrict__ in, int nx,
+                                           int ny, int nz, int x0, int y0, int gz) {
+#pragma unroll
+  for (int i = 0; i < CM_PF; ++i) {
+    const int q = threadIdx.x + i * CM_THR;
+    const int v = q >> 1, half = q & 1;
+    const int lx = v % CM_LX, ly = v / CM_LX;
+    const int gx = x0 - 1 + lx, gy = y0 - 1 + ly;
+    u32x4 d = {0u, 0u, 0u, 0u};
+    if (q < CM_PLANE * 2 && gx >= 0 && gx < nx && gy >= 0 && gy < ny && gz >= 0 && gz < nz)
+      d = *reinterpret_cast<const u32x4 *>(in + (((int64_t)gz * ny + gy) * nx + gx) * 16 +
+                                           8 * half);
+    pf[i] = d;
+  }
+}
+__device__ __forceinline__ void cm_store16(uint16_t *lds, int slot, const u32x4 *pf) {
+#pragma unroll
+  for (int i = 0; i < CM_PF; ++i) {
+    const int q = threadIdx.x + i * CM_THR;
+    if (q < CM_PLANE * 2)
+      *reinterpret_cast<u32x4 *>(lds + (slot * CM_PLANE + (q >> 1)) * 16 + 8 * (q & 1)) = pf[i];
+  }
+}
+
+// CIN = 1 or 2: fetch plane gz into registers (one voxel's channels per item),
+// then store it into its slot.
+constexpr int CM_PFS = (CM_PLANE + CM_THR - 1) / CM_THR;
+template <int CIN>
+__device__ __forceinline__ void cm_fetch_small(uint32_t *pf, const uint16_t *__restrict__ in,
+                                               int nx, int ny, int nz, int x0, int y0, int gz) {
+#pragma unroll
+  for (int i = 0; i < CM_PFS; ++i) {
+    const int v = threadIdx.x + i * CM_THR;
+    const int lx = v % CM_LX, ly = v / CM_LX;
+    const int gx = x0 - 1 + lx, gy = y0 - 1 + ly;
+    uint32_t d = 0u;
+    if (v < CM_PLANE && gx >= 0 && gx < nx && gy >= 0 && gy < ny && gz >= 0 && gz < nz) {
+      const int64_t g = ((int64_t)gz * ny + gy) * nx + gx;
+      d = CIN == 2 ? *reinterpret_cast<const uint32_t *>(in + g * 2) : (uint32_t)in[g];
+    }
+    pf[i] = d;
+  }
+}
+template <int CIN>
+__device__ __forceinline__ void cm_store_small(uint16_t *lds, int slot, const uint32_t *pf) {
+#pragma unroll
+  for (int i = 0; i < CM_PFS; ++i) {
+    const int v = threadIdx.x + i * CM_THR;
+    if (v >= CM_PLANE) continue;
+    if (CIN == 2)
+      *reinterpret_cast<uint32_t *>(lds + (slot * CM_PLANE + v) * 2) = pf[i];
+    else
+      lds[slot * CM_PLANE + v] = (uint16_t)pf[i];
+  }
+}
+
+// B fragment of chunk c for output voxel lx of row ly and lane group g; sl[d]
+// is the slot of input plane z - 1 + d.
+template <int CIN>
+__device__ __forceinline__ bf16x8 cm_gather(const uint16_t *lds, int c, int lx, int ly,
+                                            const int *sl, int g) {
+  if (CIN == 16) {
+    const int t = 2 * c + (g >> 1);
+    u32x4 d = {0u, 0u, 0u, 0u};
+    if (t < 27) {
+      const int dz = t / 9, dy = (t / 3) % 3, dx = t % 3;
+      const int v = sl[dz] * CM_PLANE + (ly + dy) * CM_LX + lx + dx;
+      d = *reinterpret_cast<const u32x4 *>(lds + v * 16 + 8 * (g & 1));
+    }
+    return __builtin_bit_cast(bf16x8, d);
+  } else {
+    u16x8 d;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const int k = 32 * c + 8 * g + e;
+      const int t = k / CIN, ci = k % CIN;
+      uint16_t val = 0;
+      if (t < 27) {
+        const int dz = t / 9, dy = (t / 3) % 3, dx = t % 3;
+        val = lds[(sl[dz] * CM_PLANE + (ly + dy) * CM_LX + lx + dx) * CIN + ci];
+      }
+      d[e] = val;
+    }
+    return __builtin_bit_cast(bf16x8, d);
+  }
+}
+
 template <int CIN, int COUT>
-__global__ void __launch_bounds__(CONV_THR)
+__global__ void __launch_bounds__(CM_THR)
     k_conv(const uint16_t *__restrict__ in, int nx, int ny, int nz,
            const uint16_t *__restrict__ apk, const float *__restrict__ bias, int relu,
            const uint16_t *__restrict__ mask, const uint16_t *__restrict__ res, int res_c,
            uint16_t *__restrict__ out_bf, float *__restrict__ out_f) {
-  using B = ConvBrick;
   constexpr int K = kpad(CIN), NC = K / 32;
-  constexpr int RPW = B::ROWS / (CONV_THR / 64);  // output rows per wavefront
-  __shared__ __attribute__((aligned(16))) uint16_t lds[B::VOX * CIN + 8];
-  int x0, y0, z0;
-  tile_origin<B>(blockIdx.x, nx, ny, x0, y0, z0);
-  load_brick<B, CIN, CONV_THR>(lds, in, nx, ny, nz, x0, y0, z0);
+  __shared__ __attribute__((aligned(16))) uint16_t lds[CM_SLOTS * CM_PLANE * CIN + 8];
+  const int tx = (nx + 63) / 64, ty = (ny + CM_TY - 1) / CM_TY;
+  const int x0 = (blockIdx.x % tx) * 64, y0 = ((blockIdx.x / tx) % ty) * CM_TY;
+  const int zs = (blockIdx.x / (tx * ty)) * CM_ZC, ze = min(zs + CM_ZC, nz);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int j = lane & 15, g = lane >> 4;
   // weights: A fragment of every chunk (row co = j, k = 32 c + 8 g + e)
@@ -150,12 +253,32 @@ __global__ void __launch_bounds__(CONV_THR)
   for (int c = 0; c < NC; ++c)
     a[c] = __builtin_bit_cast(
         bf16x8, *reinterpret_cast<const u32x4 *>(apk + (size_t)j * K + 32 * c + 8 * g));
+  // prologue: planes zs - 1 .. zs + 1
+  for (int p = zs - 1; p <= zs + 1; ++p) {
+    if (CIN == 16) {
+      u32x4 pf[CM_PF];
+      cm_fetch16(pf, in, nx, ny, nz, x0, y0, p);
+      cm_store16(lds, p & 3, pf);
+    } else {
+      uint32_t pf[CM_PFS];
+      cm_fetch_small<CIN>(pf, in, nx, ny, nz, x0, y0, p);
+      cm_store_small<CIN>(lds, p & 3, pf);
+    }
+  }
   __syncthreads();
+  const int ly = wave, gy = y0 + ly;  // this wave's output row
 #pragma unroll 1
-  for (int r = 0; r < RPW; ++r) {
-    const int row = wave * RPW + r;
-    const int ly = row % B::OY, lz = row / B::OY;  // this output row in the tile
-    const int gy = y0 + ly, gz = z0 + lz;
+  for (int z = zs; z < ze; ++z) {
+    const bool more = z + 1 < ze;  // plane z + 2 is needed for output plane z + 1
+    u32x4 pf[CIN == 16 ? CM_PF : 1];
+    uint32_t pfs[CIN == 16 ? 1 : CM_PFS];
+    if (more) {
+      if (CIN == 16)
+        cm_fetch16(pf, in, nx, ny, nz, x0, y0, z + 2);
+      else
+        cm_fetch_small<CIN>(pfs, in, nx, ny, nz, x0, y0, z + 2);
+    }
+    const int sl[3] = {(z - 1) & 3, z & 3, (z + 1) & 3};
     f32x4 acc[4];
 #pragma unroll
     for (int tl = 0; tl < 4; ++tl) acc[tl] = f32x4{0.f, 0.f, 0.f, 0.f};
@@ -164,51 +287,63 @@ __global__ void __launch_bounds__(CONV_THR)
     for (int c = 0; c < NC; ++c) {
       bf16x8 b[4];
 #pragma unroll
-      for (int tl = 0; tl < 4; ++tl) b[tl] = gather_b<B, CIN>(lds, c, 16 * tl + j, ly, lz, g);
+      for (int tl = 0; tl < 4; ++tl) b[tl] = cm_gather<CIN>(lds, c, 16 * tl + j, ly, sl, g);
 #pragma unroll
       for (int tl = 0; tl < 4; ++tl)
         acc[tl] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[c], b[tl], acc[tl], 0, 0, 0);
     }
-    if (gy >= ny || gz >= nz) continue;
-    // epilogue: lane holds D[co = 4 g + e][voxel j] of each tile
+    if (gy < ny) {
+      // epilogue: lane holds D[co = 4 g + e][voxel j] of each tile
 #pragma unroll
-    for (int tl = 0; tl < 4; ++tl) {
-      const int gx = x0 + 16 * tl + j;
-      if (gx >= nx) continue;
-      const int64_t vox = ((int64_t)gz * ny + gy) * nx + gx;
-      float v[4];
-#pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const int co = 4 * g + e;
-        float s = acc[tl][e];
-        if (bias && co < COUT) s += bias[co];
-        if (relu) s = fmaxf(s, 0.0f);
-        if (mask && co < COUT && !bf16_pos(mask[vox * COUT + co])) s = 0.0f;
-        v[e] = s;
-      }
-      if (COUT == 16) {
-        if (out_bf) {
-          const uint32_t lo = (uint32_t)to_bf16(v[0]) | ((uint32_t)to_bf16(v[1]) << 16);
-          const uint32_t hi = (uint32_t)to_bf16(v[2]) | ((uint32_t)to_bf16(v[3]) << 16);
-          *reinterpret_cast<uint2 *>(out_bf + vox * 16 + 4 * g) = make_uint2(lo, hi);
+      for (int tl = 0; tl < 4; ++tl) {
+        const int gx = x0 + 16 * tl + j;
+        if (gx >= nx) continue;
+        const int64_t vox = ((int64_t)z * ny + gy) * nx + gx;
+        uint16_t mk[4] = {1, 1, 1, 1};  // positive bits unless a mask is given
+        if (mask) {
+          if (COUT == 16) {  // the lane's four channels 4g .. 4g + 3 in one load
+            const uint2 m2 = *reinterpret_cast<const uint2 *>(mask + vox * 16 + 4 * g);
+            mk[0] = (uint16_t)m2.x, mk[1] = (uint16_t)(m2.x >> 16);
+            mk[2] = (uint16_t)m2.y, mk[3] = (uint16_t)(m2.y >> 16);
+          } else if (g == 0) {
+            mk[0] = mask[vox * COUT];
+          }
         }
-        if (out_f)
-          *reinterpret_cast<float4 *>(out_f + vox * 16 + 4 * g) =
-              make_float4(v[0], v[1], v[2], v[3]);
-      } else if (g == 0) {  // single output channel: co = 0 is element 0 of group 0
-        if (res) v[0] += from_bf16(res[vox * res_c]);
-        if (out_bf) out_bf[vox] = to_bf16(v[0]);
-        if (out_f) out_f[vox] = v[0];
+        float v[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int co = 4 * g + e;
+          float s = acc[tl][e];
+          if (bias && co < COUT) s += bias[co];
+          if (relu) s = fmaxf(s, 0.0f);
+          if (mask && co < COUT && !bf16_pos(mk[e])) s = 0.0f;
+          v[e] = s;
+        }
+        if (COUT == 16) {
+          if (out_bf) {
+            const uint32_t lo = (uint32_t)to_bf16(v[0]) | ((uint32_t)to_bf16(v[1]) << 16);
+            const uint32_t hi = (uint32_t)to_bf16(v[2]) | ((uint32_t)to_bf16(v[3]) << 16);
+            *reinterpret_cast<uint2 *>(out_bf + vox * 16 + 4 * g) = make_uint2(lo, hi);
+          }
+          if (out_f)
+            *reinterpret_cast<float4 *>(out_f + vox * 16 + 4 * g) =
+                make_float4(v[0], v[1], v[2], v[3]);
+        } else if (g == 0) {  // single output channel: co = 0 is element 0 of group 0
+          if (res) v[0] += from_bf16(res[vox * res_c]);
+          if (out_bf) out_bf[vox] = to_bf16(v[0]);
+          if (out_f) out_f[vox] = v[0];
+        }
       }
     }
+    if (more) {
+      if (CIN == 16)
+        cm_store16(lds, (z + 2) & 3, pf);
+      else
+        cm_store_small<CIN>(lds, (z + 2) & 3, pfs);
+    }
+    __syncthreads();
   }
 }
-
-// Weight gradient partials: for every tap, D[co][ci] = sum over the block's
-// voxels of dz[voxel][co] * in[voxel + offset(tap)][ci].  Blocks walk tiles
-// with a grid stride; wave w owns taps w, w + 4, ...; each block writes
-// partial[block][tap][co][ci] (16 x 16 per tap, zero-padded channels), and
-// wave 0 also sums dz per channel for the bias gradient (partial_b[block][co]).
 template <int CIN, int COUT>
 __global__ void __launch_bounds__(NTHR)
     k_wgrad(const uint16_t *__restrict__ in, const uint16_t *__restrict__ dz, int nx, int ny,
@@ -432,13 +567,13 @@ int tile_count(int nx, int ny, int nz) {
 
 }  // namespace
 
-int cnn_conv_blocks(int nx, int ny, int nz) { return tile_count<ConvBrick>(nx, ny, nz); }
+int cnn_conv_blocks(int nx, int ny, int nz) { return cm_tiles(nx, ny, nz); }
 
 hipError_t launch_conv(int cin, int cout, const uint16_t *in, int nx, int ny, int nz,
                        const uint16_t *apk, const float *bias, int relu, const uint16_t *mask,
                        const uint16_t *res, int res_c, uint16_t *out_bf, float *out_f,
                        hipStream_t stream) {
-  const dim3 grid(tile_count<ConvBrick>(nx, ny, nz)), block(CONV_THR);
+  const dim3 grid(cm_tiles(nx, ny, nz)), block(CM_THR);
 #define WFD_CONV(CI, CO)                                                                      \
   hipLaunchKernelGGL((k_conv<CI, CO>), grid, block, 0, stream, in, nx, ny, nz, apk, bias, relu, \
                      mask, res, res_c, out_bf, out_f)
