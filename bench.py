@@ -495,8 +495,9 @@ def batch_fwi_bench(n_iter: int = 3):
 
 def cnn_kernel_bench(n: int = 256, reps: int = 20):
     """Matrix-core throughput of the preconditioner's kernels on an n^3 volume:
-    forward convolution of every layer, data and weight gradients, and one
-    whole training step; useful flops = 2 * 27 * cin * cout per voxel."""
+    forward convolution of every layer, the 16 -> 16 data and weight
+    gradients (the latter with its fixed-order reduction), and the whole
+    forward and backward passes; useful flops = 2 * 27 * cin * cout per voxel."""
     import numpy as np
     import torch
     from paper_2502_12350_amd.precond import LAYERS, Preconditioner
@@ -531,6 +532,22 @@ def cnn_kernel_bench(n: int = 256, reps: int = 20):
         out[f"conv_l{li}_{ci}x{co}"] = {"us": round(t * 1e6, 1), "TFLOPs": round(fl / t / 1e12, 1)}
     t = timed(lambda: P.conv(a16, 1, relu=False, flip=True, bias=False, mask=a16))
     out["dgrad_16x16"] = {"us": round(t * 1e6, 1),
+                          "TFLOPs": round(2.0 * 27 * 256 * vox / t / 1e12, 1)}
+    import ctypes as C
+    nb = C.c_size_t()
+    P.L.wfd_cnn_wgrad_workspace_bytes(n, n, n, C.byref(nb))
+    work = torch.empty(nb.value, dtype=torch.uint8, device="cuda")
+    b16 = torch.randn(shape + (16,), generator=gen, device="cuda").to(torch.bfloat16)
+    stream = torch.cuda.current_stream().cuda_stream
+
+    def wgrad():
+        rc = P.L.wfd_cnn_wgrad(a16.data_ptr(), b16.data_ptr(), n, n, n, 16, 16,
+                               P.dw[1].data_ptr(), P.db[1].data_ptr(), work.data_ptr(), nb.value,
+                               C.c_void_p(stream))
+        assert rc == 0, rc
+
+    t = timed(wgrad)
+    out["wgrad_16x16"] = {"us": round(t * 1e6, 1),
                           "TFLOPs": round(2.0 * 27 * 256 * vox / t / 1e12, 1)}
     tgt = torch.zeros(shape, device="cuda")
     y = P.forward(x, keep=True)

@@ -20,12 +20,14 @@
 // output tile along z with a ring of input planes in LDS (k_conv); each of its
 // 4 wavefronts computes one 64-voxel output row as four 16 x 16 tiles with the
 // packed weights held in registers.  The data gradient is the same kernel on
-// flipped, transposed weights; the weight gradient stages 66 x 4 x 4 input
-// bricks and reduces over voxels with the voxel index as the matrix-core K
+// flipped, transposed weights; the weight gradient marches the same tiles
+// and reduces over voxels with the voxel index as the matrix-core K
 // dimension.
 #include <hip/hip_runtime.h>
 
 #include <stdint.h>
+
+#include <algorithm>
 
 #include "wfd_internal.h"
 
@@ -37,18 +39,6 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 typedef uint16_t u16x8 __attribute__((ext_vector_type(8)));
 
-// Output tile of a block: 64 x TY x TZ voxels; the staged input brick adds a
-// one-voxel halo on every side.
-template <int TY, int TZ>
-struct Brick {
-  static constexpr int OX = 64, OY = TY, OZ = TZ;
-  static constexpr int LX = OX + 2, LY = OY + 2, LZ = OZ + 2;
-  static constexpr int VOX = LX * LY * LZ;  // voxels staged per block
-  static constexpr int ROWS = OY * OZ;      // 64-voxel output rows per block
-};
-using WgradBrick = Brick<2, 2>;  // weight gradient: 256 voxels per K sweep
-constexpr int NTHR = 256;        // 4 wavefronts (weight gradient)
-
 __device__ __forceinline__ uint16_t to_bf16(float f) {
   uint32_t u = __float_as_uint(f);
   u += 0x7FFFu + ((u >> 16) & 1u);  // round to nearest, ties to even
@@ -58,71 +48,6 @@ __device__ __forceinline__ float from_bf16(uint16_t b) { return __uint_as_float(
 __device__ __forceinline__ bool bf16_pos(uint16_t b) { return b != 0 && !(b & 0x8000u); }
 
 constexpr int kpad(int cin) { return (27 * cin + 31) / 32 * 32; }
-
-// Block -> output tile origin.
-template <class B>
-__device__ __forceinline__ void tile_origin(int b, int nx, int ny, int &x0, int &y0, int &z0) {
-  const int tx = (nx + B::OX - 1) / B::OX, ty = (ny + B::OY - 1) / B::OY;
-  x0 = (b % tx) * B::OX;
-  y0 = ((b / tx) % ty) * B::OY;
-  z0 = (b / (tx * ty)) * B::OZ;
-}
-
-// Stage the input brick (zero outside the volume) into LDS, channels-last.
-template <class B, int CIN, int NT>
-__device__ __forceinline__ void load_brick(uint16_t *lds, const uint16_t *__restrict__ in, int nx,
-                                           int ny, int nz, int x0, int y0, int z0) {
-  if (CIN == 16) {
-    for (int q = threadIdx.x; q < B::VOX * 2; q += NT) {
-      const int v = q >> 1, half = q & 1;
-      const int lx = v % B::LX, ly = (v / B::LX) % B::LY, lz = v / (B::LX * B::LY);
-      const int gx = x0 - 1 + lx, gy = y0 - 1 + ly, gz = z0 - 1 + lz;
-      u32x4 d = {0u, 0u, 0u, 0u};
-      if (gx >= 0 && gx < nx && gy >= 0 && gy < ny && gz >= 0 && gz < nz)
-        d = *reinterpret_cast<const u32x4 *>(in + (((int64_t)gz * ny + gy) * nx + gx) * 16 +
-                                             8 * half);
-      *reinterpret_cast<u32x4 *>(lds + v * 16 + 8 * half) = d;
-    }
-  } else {
-    for (int v = threadIdx.x; v < B::VOX; v += NT) {
-      const int lx = v % B::LX, ly = (v / B::LX) % B::LY, lz = v / (B::LX * B::LY);
-      const int gx = x0 - 1 + lx, gy = y0 - 1 + ly, gz = z0 - 1 + lz;
-      const bool ok = gx >= 0 && gx < nx && gy >= 0 && gy < ny && gz >= 0 && gz < nz;
-      const int64_t g = ((int64_t)gz * ny + gy) * nx + gx;
-#pragma unroll
-      for (int c = 0; c < CIN; ++c) lds[v * CIN + c] = ok ? in[g * CIN + c] : (uint16_t)0;
-    }
-  }
-}
-
-// LDS voxel index of output voxel (lx, ly, lz) of the tile read through tap t.
-template <class B>
-__device__ __forceinline__ int tap_voxel(int t, int lx, int ly, int lz) {
-  const int dz = t / 9, dy = (t / 3) % 3, dx = t % 3;  // offsets + 1
-  return ((lz + dz) * B::LY + (ly + dy)) * B::LX + (lx + dx);
-}
-
-// B fragment of chunk c for the lane's output voxel (lx, ly, lz) and lane group g.
-template <class B, int CIN>
-__device__ __forceinline__ bf16x8 gather_b(const uint16_t *lds, int c, int lx, int ly, int lz,
-                                           int g) {
-  if (CIN == 16) {
-    const int t = 2 * c + (g >> 1);
-    u32x4 d = {0u, 0u, 0u, 0u};
-    if (t < 27)
-      d = *reinterpret_cast<const u32x4 *>(lds + tap_voxel<B>(t, lx, ly, lz) * 16 + 8 * (g & 1));
-    return __builtin_bit_cast(bf16x8, d);
-  } else {
-    u16x8 d;
-#pragma unroll
-    for (int e = 0; e < 8; ++e) {
-      const int k = 32 * c + 8 * g + e;
-      const int t = k / CIN, ci = k % CIN;
-      d[e] = t < 27 ? lds[tap_voxel<B>(t, lx, ly, lz) * CIN + ci] : (uint16_t)0;
-    }
-    return __builtin_bit_cast(bf16x8, d);
-  }
-}
 
 // Convolution (forward or data gradient).  out = conv(in; A) [+ bias], then
 // relu, then * (mask > 0), then (single output channel only) + channel 0 of
@@ -215,6 +140,20 @@ __device__ __forceinline__ bf16x8 cm_gather(const uint16_t *lds, int c, int lx, 
       const int dz = t / 9, dy = (t / 3) % 3, dx = t % 3;
       const int v = sl[dz] * CM_PLANE + (ly + dy) * CM_LX + lx + dx;
       d = *reinterpret_cast<const u32x4 *>(lds + v * 16 + 8 * (g & 1));
+    }
+    return __builtin_bit_cast(bf16x8, d);
+  } else if (CIN == 2) {  // elements (2u, 2u + 1) are both channels of tap 4 (c, g) + u
+    u32x4 d;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int t = 16 * c + 4 * g + u;
+      uint32_t val = 0u;
+      if (t < 27) {
+        const int dz = t / 9, dy = (t / 3) % 3, dx = t % 3;
+        val = *reinterpret_cast<const uint32_t *>(
+            lds + (sl[dz] * CM_PLANE + (ly + dy) * CM_LX + lx + dx) * 2);
+      }
+      d[u] = val;
     }
     return __builtin_bit_cast(bf16x8, d);
   } else {
@@ -344,99 +283,266 @@ __global__ void __launch_bounds__(CM_THR)
     __syncthreads();
   }
 }
+// Weight gradient: dW[tap][ci][co] = sum over voxels v of dz[v][co] *
+// in[v + offset(tap)][ci], and db[co] = sum of dz[v][co], with the voxel index
+// as the matrix-core K dimension: A[co][k] = dz[voxel k][co], B[k][ci] =
+// in[voxel k + offset][ci], k = 32 consecutive voxels of one output row.
+//
+// A block marches a 64 x 4 output tile along z like the convolution, with a
+// four-slot ring of input planes and a two-slot ring of dz planes in LDS.  In
+// LDS the planes are channel-planar, [row][channel][x] with rows of 72, so
+// the eight consecutive voxels of one channel that a lane contributes to a
+// fragment are one aligned 16-byte read (a row stride of 36 dwords puts the
+// 16 channels of a lane group on distinct banks).  For the three x taps of a
+// (kz, ky) pair a lane reads 10 elements once and shifts them in registers.
+// Each wavefront owns one output row and accumulates all 27 taps (and the
+// bias, as a product with a ones fragment) over every plane of every tile it
+// visits; the grid is persistent, and each wavefront writes one row of
+// partial sums that two fixed-order passes reduce.
+constexpr int WG_TY = 4, WG_ZC = 16, WG_THR = 256, WG_RX = 72, WG_LY = WG_TY + 2;
+constexpr int WG_ROW = 27 * 256 + 16;  // partial sums of a wavefront: [tap][co][ci], then db[co]
+constexpr int WG_MAXB = 512, WG_SEG = 32;
+
+inline int wg_tiles(int nx, int ny, int nz) {
+  return ((nx + 63) / 64) * ((ny + WG_TY - 1) / WG_TY) * ((nz + WG_ZC - 1) / WG_ZC);
+}
+
+// The two channel values of voxels a (low half) and b (high half).
+__device__ __forceinline__ uint32_t wg_lo(uint32_t a, uint32_t b) { return (a & 0xFFFFu) | (b << 16); }
+__device__ __forceinline__ uint32_t wg_hi(uint32_t a, uint32_t b) {
+  return (a >> 16) | (b & 0xFFFF0000u);
+}
+
+// Input plane gz (66 x 6 voxels from (x0 - 1, y0 - 1)) in pairs of voxels
+// (lx = 2p, 2p + 1): item = (row, channel half, pair).  Fetched into
+// registers, then stored as one dword per channel.
+template <int CIN>
+struct WgIn {
+  static constexpr int HALVES = CIN == 16 ? 2 : 1;
+  static constexpr int ITEMS = WG_LY * HALVES * 33;
+  static constexpr int PER = (ITEMS + WG_THR - 1) / WG_THR;
+  static constexpr int SLOT = WG_LY * CIN * WG_RX;  // elements per slot
+  u32x4 a[PER], b[PER];
+  __device__ __forceinline__ void fetch(const uint16_t *__restrict__ in, int nx, int ny, int nz,
+                                        int x0, int y0, int gz) {
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+      const int q = threadIdx.x + i * WG_THR;
+      const int pr = q % 33, h = (q / 33) % HALVES, ly = q / (33 * HALVES);
+      const int gy = y0 - 1 + ly, xa = x0 - 1 + 2 * pr;
+      const bool row = q < ITEMS && gy >= 0 && gy < ny && gz >= 0 && gz < nz;
+      const int64_t base = ((int64_t)gz * ny + gy) * nx;
+      u32x4 va = {0u, 0u, 0u, 0u}, vb = {0u, 0u, 0u, 0u};
+      if (CIN == 16) {
+        if (row && xa >= 0 && xa < nx)
+          va = *reinterpret_cast<const u32x4 *>(in + (base + xa) * 16 + 8 * h);
+        if (row && xa + 1 < nx)
+          vb = *reinterpret_cast<const u32x4 *>(in + (base + xa + 1) * 16 + 8 * h);
+      } else {  // CIN = 2: one dword per voxel
+        if (row && xa >= 0 && xa < nx) va[0] = *reinterpret_cast<const uint32_t *>(in + (base + xa) * 2);
+        if (row && xa + 1 < nx) vb[0] = *reinterpret_cast<const uint32_t *>(in + (base + xa + 1) * 2);
+      }
+      a[i] = va;
+      b[i] = vb;
+    }
+  }
+  __device__ __forceinline__ void store(uint32_t *lds, int slot) const {
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+      const int q = threadIdx.x + i * WG_THR;
+      if (q >= ITEMS) continue;
+      const int pr = q % 33, h = (q / 33) % HALVES, ly = q / (33 * HALVES);
+      uint32_t *d = lds + (slot * SLOT + (ly * CIN + 8 * h) * WG_RX) / 2 + pr;
+      if (CIN == 16) {
+#pragma unroll
+        for (int w = 0; w < 4; ++w) {
+          d[(2 * w) * (WG_RX / 2)] = wg_lo(a[i][w], b[i][w]);
+          d[(2 * w + 1) * (WG_RX / 2)] = wg_hi(a[i][w], b[i][w]);
+        }
+      } else {
+        d[0] = wg_lo(a[i][0], b[i][0]);
+        d[WG_RX / 2] = wg_hi(a[i][0], b[i][0]);
+      }
+    }
+  }
+};
+
+// dz plane gz of the output tile (64 x 4 voxels from (x0, y0)), same scheme.
+template <int COUT>
+struct WgDz {
+  static constexpr int HALVES = COUT == 16 ? 2 : 1;
+  static constexpr int ITEMS = WG_TY * HALVES * 32;
+  static constexpr int PER = (ITEMS + WG_THR - 1) / WG_THR;
+  static constexpr int SLOT = WG_TY * COUT * WG_RX;
+  u32x4 a[PER], b[PER];
+  __device__ __forceinline__ void fetch(const uint16_t *__restrict__ dz, int nx, int ny, int x0,
+                                        int y0, int gz) {
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+      const int q = threadIdx.x + i * WG_THR;
+      const int pr = q % 32, h = (q / 32) % HALVES, r = q / (32 * HALVES);
+      const int gy = y0 + r, xa = x0 + 2 * pr;
+      const bool row = q < ITEMS && gy < ny;
+      const int64_t base = ((int64_t)gz * ny + gy) * nx;
+      u32x4 va = {0u, 0u, 0u, 0u}, vb = {0u, 0u, 0u, 0u};
+      if (COUT == 16) {
+        if (row && xa < nx) va = *reinterpret_cast<const u32x4 *>(dz + (base + xa) * 16 + 8 * h);
+        if (row && xa + 1 < nx)
+          vb = *reinterpret_cast<const u32x4 *>(dz + (base + xa + 1) * 16 + 8 * h);
+      } else {  // COUT = 1: one element per voxel
+        if (row && xa < nx) va[0] = dz[base + xa];
+        if (row && xa + 1 < nx) vb[0] = dz[base + xa + 1];
+      }
+      a[i] = va;
+      b[i] = vb;
+    }
+  }
+  __device__ __forceinline__ void store(uint32_t *lds, int slot) const {
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+      const int q = threadIdx.x + i * WG_THR;
+      if (q >= ITEMS) continue;
+      const int pr = q % 32, h = (q / 32) % HALVES, r = q / (32 * HALVES);
+      uint32_t *d = lds + (slot * SLOT + (r * COUT + 8 * h) * WG_RX) / 2 + pr;
+      if (COUT == 16) {
+#pragma unroll
+        for (int w = 0; w < 4; ++w) {
+          d[(2 * w) * (WG_RX / 2)] = wg_lo(a[i][w], b[i][w]);
+          d[(2 * w + 1) * (WG_RX / 2)] = wg_hi(a[i][w], b[i][w]);
+        }
+      } else {
+        d[0] = wg_lo(a[i][0], b[i][0]);
+      }
+    }
+  }
+};
+
 template <int CIN, int COUT>
-__global__ void __launch_bounds__(NTHR)
+__global__ void __launch_bounds__(WG_THR)
     k_wgrad(const uint16_t *__restrict__ in, const uint16_t *__restrict__ dz, int nx, int ny,
-            int nz, int ntiles, float *__restrict__ partial, float *__restrict__ partial_b) {
-  using B = WgradBrick;
-  constexpr int OX = B::OX, OY = B::OY, OZ = B::OZ;
-  __shared__ __attribute__((aligned(16))) uint16_t lds[B::VOX * CIN + 8];
-  __shared__ uint16_t ldz[OX * OY * OZ * COUT];
+            int nz, int ntiles, float *__restrict__ partial) {
+  using In = WgIn<CIN>;
+  using Dz = WgDz<COUT>;
+  __shared__ __attribute__((aligned(16))) uint32_t lin[4 * In::SLOT / 2];
+  __shared__ __attribute__((aligned(16))) uint32_t ldz[2 * Dz::SLOT / 2];
+  const uint16_t *lin16 = reinterpret_cast<const uint16_t *>(lin);
+  const uint16_t *ldz16 = reinterpret_cast<const uint16_t *>(ldz);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int j = lane & 15, g = lane >> 4;
-  constexpr int NT = 7;  // taps per wave (27 = 7 + 7 + 7 + 6)
-  f32x4 acc[NT];
+  const int tx = (nx + 63) / 64, ty = (ny + WG_TY - 1) / WG_TY;
+  f32x4 acc[27];
 #pragma unroll
-  for (int i = 0; i < NT; ++i) acc[i] = f32x4{0.f, 0.f, 0.f, 0.f};
-  float bsum = 0.0f;  // wave 0: sum of dz[., co = j] over the lane's voxels
+  for (int t = 0; t < 27; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+  f32x4 accb = {0.f, 0.f, 0.f, 0.f};
+  const uint32_t one2 = 0x3F803F80u;  // two BF16 ones
+  const bf16x8 ones = __builtin_bit_cast(bf16x8, u32x4{one2, one2, one2, one2});
   for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
-    int x0, y0, z0;
-    tile_origin<B>(tile, nx, ny, x0, y0, z0);
-    __syncthreads();  // previous tile's reads are done
-    load_brick<B, CIN, NTHR>(lds, in, nx, ny, nz, x0, y0, z0);
-    for (int q = threadIdx.x; q < OX * OY * OZ * COUT; q += NTHR) {
-      const int v = q / COUT, c = q % COUT;
-      const int lx = v % OX, ly = (v / OX) % OY, lz = v / (OX * OY);
-      const int gx = x0 + lx, gy = y0 + ly, gz = z0 + lz;
-      ldz[q] = (gx < nx && gy < ny && gz < nz) ? dz[(((int64_t)gz * ny + gy) * nx + gx) * COUT + c]
-                                               : (uint16_t)0;
+    const int x0 = (tile % tx) * 64, y0 = ((tile / tx) % ty) * WG_TY;
+    const int zs = (tile / (tx * ty)) * WG_ZC, ze = min(zs + WG_ZC, nz);
+    {  // prologue: input planes zs - 1 .. zs + 1 and dz plane zs
+      In pin;
+      for (int p = zs - 1; p <= zs + 1; ++p) {
+        pin.fetch(in, nx, ny, nz, x0, y0, p);
+        pin.store(lin, p & 3);
+      }
+      Dz pdz;
+      pdz.fetch(dz, nx, ny, x0, y0, zs);
+      pdz.store(ldz, zs & 1);
     }
     __syncthreads();
-    // K = the tile's 256 voxels in 8 chunks of 32
+    const bool row_live = y0 + wave < ny;
 #pragma unroll 1
-    for (int kc = 0; kc < OX * OY * OZ / 32; ++kc) {
-      u16x8 av;
-#pragma unroll
-      for (int e = 0; e < 8; ++e) {
-        const int v = 32 * kc + 8 * g + e;
-        av[e] = (j < COUT) ? ldz[v * COUT + j] : (uint16_t)0;
+    for (int z = zs; z < ze; ++z) {
+      const bool more = z + 1 < ze;
+      In nin;
+      Dz ndz;
+      if (more) {
+        nin.fetch(in, nx, ny, nz, x0, y0, z + 2);
+        ndz.fetch(dz, nx, ny, x0, y0, z + 1);
       }
-      const bf16x8 A = __builtin_bit_cast(bf16x8, av);
-      if (wave == 0) {
+      if (row_live) {
 #pragma unroll
-        for (int e = 0; e < 8; ++e) bsum += from_bf16(av[e]);
-      }
+        for (int xb = 0; xb < 64; xb += 32) {
+          if (x0 + xb >= nx) break;  // the chunk's dz are all zero
+          u32x4 av = {0u, 0u, 0u, 0u};
+          if (j < COUT)
+            av = *reinterpret_cast<const u32x4 *>(
+                ldz16 + (z & 1) * Dz::SLOT + (wave * COUT + j) * WG_RX + xb + 8 * g);
+          const bf16x8 A = __builtin_bit_cast(bf16x8, av);
+          accb = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A, ones, accb, 0, 0, 0);
 #pragma unroll
-      for (int i = 0; i < NT; ++i) {
-        const int t = wave + 4 * i;
-        if (t >= 27) continue;
-        u16x8 bv;
+          for (int kz = 0; kz < 3; ++kz) {
+            const uint16_t *pl = lin16 + ((z - 1 + kz) & 3) * In::SLOT;
 #pragma unroll
-        for (int e = 0; e < 8; ++e) {
-          const int v = 32 * kc + 8 * g + e;
-          const int lx = v % OX, ly = (v / OX) % OY, lz = v / (OX * OY);
-          bv[e] = (j < CIN) ? lds[tap_voxel<B>(t, lx, ly, lz) * CIN + j] : (uint16_t)0;
+            for (int ky = 0; ky < 3; ++ky) {
+              u32x4 w = {0u, 0u, 0u, 0u};
+              uint32_t w4 = 0u;
+              if (j < CIN) {
+                const uint16_t *r = pl + ((wave + ky) * CIN + j) * WG_RX + xb + 8 * g;
+                w = *reinterpret_cast<const u32x4 *>(r);
+                w4 = *reinterpret_cast<const uint32_t *>(r + 8);
+              }
+              const u32x4 s1 = {__builtin_amdgcn_alignbyte(w[1], w[0], 2),
+                                __builtin_amdgcn_alignbyte(w[2], w[1], 2),
+                                __builtin_amdgcn_alignbyte(w[3], w[2], 2),
+                                __builtin_amdgcn_alignbyte(w4, w[3], 2)};
+              const u32x4 s2 = {w[1], w[2], w[3], w4};
+              const int t = 9 * kz + 3 * ky;
+              acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A, __builtin_bit_cast(bf16x8, w),
+                                                               acc[t], 0, 0, 0);
+              acc[t + 1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                  A, __builtin_bit_cast(bf16x8, s1), acc[t + 1], 0, 0, 0);
+              acc[t + 2] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                  A, __builtin_bit_cast(bf16x8, s2), acc[t + 2], 0, 0, 0);
+            }
+          }
         }
-        acc[i] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A, __builtin_bit_cast(bf16x8, bv), acc[i],
-                                                        0, 0, 0);
       }
+      if (more) {
+        nin.store(lin, (z + 2) & 3);
+        ndz.store(ldz, (z + 1) & 1);
+      }
+      __syncthreads();
     }
   }
-  if (wave == 0) {  // add the four lane groups' sums of channel j
-    bsum += __shfl_xor(bsum, 16);
-    bsum += __shfl_xor(bsum, 32);
-    if (g == 0) partial_b[(size_t)blockIdx.x * 16 + j] = bsum;
-  }
-  // lane holds D[co = 4 g + e][ci = j]
+  // lane holds D[co = 4 g + e][ci = j] of every tap: each wavefront writes
+  // its own partial row; the bias sums D_b[co][j] are the same for every j
+  float *row = partial + ((size_t)blockIdx.x * 4 + wave) * WG_ROW;
 #pragma unroll
-  for (int i = 0; i < NT; ++i) {
-    const int t = wave + 4 * i;
-    if (t >= 27) continue;
-    float *p = partial + ((size_t)blockIdx.x * 27 + t) * 256;
+  for (int t = 0; t < 27; ++t)
 #pragma unroll
-    for (int e = 0; e < 4; ++e) p[(4 * g + e) * 16 + j] = acc[i][e];
+    for (int e = 0; e < 4; ++e) row[t * 256 + (4 * g + e) * 16 + j] = acc[t][e];
+  if (j == 0) {
+#pragma unroll
+    for (int e = 0; e < 4; ++e) row[27 * 256 + 4 * g + e] = accb[e];
   }
 }
 
-// dW[tap][ci][co] = sum over blocks of partial[block][tap][co][ci], and
-// db[co] = sum over blocks of partial_b[block][co] (fixed order).  Thread i
-// owns partial entry i of every block, so each block's partial is read
-// contiguously across threads.
-__global__ void k_wgrad_reduce(const float *__restrict__ partial,
-                               const float *__restrict__ partial_b, int nblocks, int cin,
-                               int cout, float *__restrict__ dw, float *__restrict__ db) {
+// Fixed-order reduction of the wavefronts' partial rows: pass 1 sums each
+// segment of WG_SEG rows in order, pass 2 sums the segment totals in order
+// and scatters them into dW[tap][ci][co] and db[co].
+__global__ void k_wgrad_seg(const float *__restrict__ partial, int nrows,
+                            float *__restrict__ seg) {
+  const int col = blockIdx.x * blockDim.x + threadIdx.x;
+  if (col >= WG_ROW) return;
+  const int r0 = blockIdx.y * WG_SEG, r1 = min(r0 + WG_SEG, nrows);
+  float s = 0.0f;
+  for (int r = r0; r < r1; ++r) s += partial[(size_t)r * WG_ROW + col];
+  seg[(size_t)blockIdx.y * WG_ROW + col] = s;
+}
+
+__global__ void k_wgrad_final(const float *__restrict__ seg, int nseg, int cin, int cout,
+                              float *__restrict__ dw, float *__restrict__ db) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= WG_ROW) return;
+  float s = 0.0f;
+  for (int k = 0; k < nseg; ++k) s += seg[(size_t)k * WG_ROW + i];
   if (i < 27 * 256) {
     const int t = i / 256, co = (i / 16) % 16, ci = i % 16;
-    if (co >= cout || ci >= cin) return;
-    float s = 0.0f;
-    for (int b = 0; b < nblocks; ++b) s += partial[(size_t)b * 27 * 256 + i];
-    dw[(t * cin + ci) * cout + co] = s;
-  } else if (i < 27 * 256 + cout && db) {
+    if (co < cout && ci < cin) dw[(t * cin + ci) * cout + co] = s;
+  } else {
     const int co = i - 27 * 256;
-    float s = 0.0f;
-    for (int b = 0; b < nblocks; ++b) s += partial_b[(size_t)b * 16 + co];
-    db[co] = s;
+    if (co < cout && db) db[co] = s;
   }
 }
 
@@ -560,10 +666,6 @@ __global__ void k_pack_input(const float *__restrict__ grad, const float *__rest
   }
 }
 
-template <class B>
-int tile_count(int nx, int ny, int nz) {
-  return ((nx + B::OX - 1) / B::OX) * ((ny + B::OY - 1) / B::OY) * ((nz + B::OZ - 1) / B::OZ);
-}
 
 }  // namespace
 
@@ -586,23 +688,23 @@ hipError_t launch_conv(int cin, int cout, const uint16_t *in, int nx, int ny, in
   return hipGetLastError();
 }
 
-int cnn_wgrad_blocks(int nx, int ny, int nz) {
-  const int tiles = tile_count<WgradBrick>(nx, ny, nz);
-  return tiles < 1024 ? tiles : 1024;
-}
+int cnn_wgrad_blocks(int nx, int ny, int nz) { return std::min(wg_tiles(nx, ny, nz), WG_MAXB); }
 
+// partial rows (four per block) followed by the segment totals
 size_t cnn_wgrad_workspace_floats(int nx, int ny, int nz) {
-  return (size_t)cnn_wgrad_blocks(nx, ny, nz) * (27 * 256 + 16);
+  const int rows = 4 * cnn_wgrad_blocks(nx, ny, nz);
+  return (size_t)(rows + (rows + WG_SEG - 1) / WG_SEG) * WG_ROW;
 }
 
 hipError_t launch_wgrad(int cin, int cout, const uint16_t *in, const uint16_t *dz, int nx, int ny,
                         int nz, float *work, float *dw, float *db, hipStream_t stream) {
-  const int ntiles = tile_count<WgradBrick>(nx, ny, nz);
-  const int nb = cnn_wgrad_blocks(nx, ny, nz);
-  float *partial = work, *partial_b = work + (size_t)nb * 27 * 256;
-#define WFD_WG(CI, CO)                                                                        \
-  hipLaunchKernelGGL((k_wgrad<CI, CO>), dim3(nb), dim3(NTHR), 0, stream, in, dz, nx, ny, nz, \
-                     ntiles, partial, partial_b)
+  const int ntiles = wg_tiles(nx, ny, nz);
+  const int nb = cnn_wgrad_blocks(nx, ny, nz), rows = 4 * nb;
+  const int nseg = (rows + WG_SEG - 1) / WG_SEG;
+  float *partial = work, *seg = work + (size_t)rows * WG_ROW;
+#define WFD_WG(CI, CO)                                                                          \
+  hipLaunchKernelGGL((k_wgrad<CI, CO>), dim3(nb), dim3(WG_THR), 0, stream, in, dz, nx, ny, nz, \
+                     ntiles, partial)
   if (cin == 16 && cout == 16) WFD_WG(16, 16);
   else if (cin == 2 && cout == 16) WFD_WG(2, 16);
   else if (cin == 16 && cout == 1) WFD_WG(16, 1);
@@ -610,9 +712,11 @@ hipError_t launch_wgrad(int cin, int cout, const uint16_t *in, const uint16_t *d
 #undef WFD_WG
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  const int n = 27 * 256 + cout;
-  hipLaunchKernelGGL(k_wgrad_reduce, dim3((n + 255) / 256), dim3(256), 0, stream, partial,
-                     partial_b, nb, cin, cout, dw, db);
+  const int cb = (WG_ROW + 255) / 256;
+  hipLaunchKernelGGL(k_wgrad_seg, dim3(cb, nseg), dim3(256), 0, stream, partial, rows, seg);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_wgrad_final, dim3(cb), dim3(256), 0, stream, seg, nseg, cin, cout, dw, db);
   return hipGetLastError();
 }
 

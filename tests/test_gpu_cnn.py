@@ -123,6 +123,42 @@ def test_weight_gradient_matches_oracle(li):
     assert e <= TOL and eb <= TOL
 
 
+@pytest.mark.parametrize("ci,co", [(16, 16), (2, 16), (16, 1)])
+def test_weight_gradient_many_tiles_per_block(ci, co):
+    # 200 x 130 x 70: 4 x 33 x 5 marching tiles (ragged in x, y and z), more
+    # than the 512 blocks of the persistent grid, so blocks visit several
+    # tiles and 2048 wavefront rows are reduced.  Each wavefront sums up to
+    # 8192 exact BF16 products per entry in FP32, each rounding at most 2^-24
+    # of a running sum; the bound 2e-5 leaves a factor 4 over sqrt(8192) 2^-24.
+    torch = gpu_or_skip()
+    import ctypes as C
+    from paper_2502_12350_amd import _lib
+    nz, ny, nx = 70, 130, 200
+    say(f"[cnn wgrad] {nx}x{ny}x{nz}: {ci} -> {co}")
+    rng = np.random.default_rng(7 + ci + co)
+    x = cnn.bf16(rng.standard_normal((nz, ny, nx, ci)))
+    dz = cnn.bf16(rng.standard_normal((nz, ny, nx, co)))
+    L = _lib.lib()
+    nb = C.c_size_t()
+    _lib.check(L.wfd_cnn_wgrad_workspace_bytes(nx, ny, nz, C.byref(nb)))
+    work = torch.empty(nb.value, dtype=torch.uint8, device="cuda")
+    dw = torch.full((27, ci, co), float("nan"), device="cuda")
+    db = torch.full((co,), float("nan"), device="cuda")
+    xd, dzd = _bf(torch, x), _bf(torch, dz)
+    res = []
+    for _ in range(2):
+        _lib.check(L.wfd_cnn_wgrad(xd.data_ptr(), dzd.data_ptr(), nx, ny, nz, ci, co,
+                                   dw.data_ptr(), db.data_ptr(), work.data_ptr(), nb.value, None))
+        torch.cuda.synchronize()
+        res.append((dw.clone(), db.clone()))
+    assert torch.equal(res[0][0], res[1][0]) and torch.equal(res[0][1], res[1][1])
+    ref = cnn.conv3d_wgrad(x, dz).reshape(27, ci, co)
+    e = rel_l2(_np(dw), ref)
+    eb = rel_l2(_np(db), dz.reshape(-1, co).astype(np.float64).sum(axis=0))
+    say(f"  dW rel-L2 {e:.2e}, db rel-L2 {eb:.2e}")
+    assert e <= 2e-5 and eb <= 2e-5
+
+
 def test_mse_adam_and_input_packing_match_oracle():
     torch = gpu_or_skip()
     import ctypes as C

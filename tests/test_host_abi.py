@@ -154,11 +154,17 @@ def test_cnn_packed_sizes_and_workspace():
     assert L.wfd_cnn_packed_elems(3, 16, 0, C.byref(n)) == -1       # no such layer
     assert L.wfd_cnn_packed_elems(16, 16, 2, C.byref(n)) == -1
     b = C.c_size_t()
+    # one partial row of 27 * 256 + 16 floats per wavefront (4 per block, one
+    # block per 64 x 4 x 16 tile, at most 512 blocks), then one row per
+    # segment of 32 rows
+    row = (27 * 256 + 16) * 4
     assert L.wfd_cnn_wgrad_workspace_bytes(70, 7, 5, C.byref(b)) == 0
-    tiles = 2 * 4 * 3                                                # 64 x 2 x 2 tiles
-    assert b.value == tiles * (27 * 256 + 16) * 4
+    tiles = 2 * 2 * 1
+    assert b.value == (4 * tiles + 1) * row
     assert L.wfd_cnn_wgrad_workspace_bytes(128, 128, 128, C.byref(b)) == 0
-    assert b.value == 1024 * (27 * 256 + 16) * 4                     # capped at 1024 blocks
+    assert b.value == (4 * 512 + 64) * row                            # 2 x 32 x 8 tiles
+    assert L.wfd_cnn_wgrad_workspace_bytes(256, 256, 256, C.byref(b)) == 0
+    assert b.value == (4 * 512 + 64) * row                            # capped at 512 blocks
     assert L.wfd_cnn_conv(None, 8, 8, 8, 3, 16, None, None, 0, None, None, 0, None, None,
                           None) == -1
 
