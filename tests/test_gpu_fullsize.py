@@ -136,7 +136,7 @@ def test_c2_gradient_directional_derivative_full_size():
     torch = gpu_or_skip()
     from paper_2502_12350_amd import GridSpec, Propagator
     w = _c2()
-    dv = (w.vel * seisgen.smooth_noise(w.vel.shape, 77, 8.0, 0.01)).astype(np.float32)
+    dv = (w.vel * seisgen.smooth_noise((w.nx, w.ny, w.nz), 77, 8.0, 0.01)).astype(np.float32)
     wav = torch.from_numpy(w.wavelet).cuda()
     P = Propagator(0)
     gs = GridSpec(**w.grid_kwargs())

@@ -178,3 +178,47 @@ def test_fwi_restart_from_state_file_matches_uninterrupted_run(method, tmp_path)
     assert tr.misfit == tr_ref.misfit
     assert tr.n_gradients == tr_ref.n_gradients and tr.n_misfits == tr_ref.n_misfits
     assert float(v.min()) >= 1500.0                                   # lower bound only
+
+
+def test_gradient_workload_eight_shots_against_central_differences():
+    """The gradient workload's sizes (200x200x160, 8 shots, 1200 steps, 2500
+    receivers each, binomial checkpointing with 20 stored pairs): the
+    directional derivative of the summed misfit along a smooth whole-model
+    perturbation dv (1 % of v at most), with observed data from v + 5 dv,
+    against central differences at eps = 0.25 and 0.5, combined by Richardson
+    extrapolation (the O(eps^2) term cancels).  Along a direction unrelated
+    to the residual the derivative would be about 1e-3 of the misfit, below
+    what FP32 traces resolve in a difference of misfits."""
+    torch = gpu_or_skip()
+    from paper_2502_12350_amd import GridSpec, Propagator
+    w = seisgen.workload("c4_start")
+    g = GridSpec(**w.grid_kwargs())
+    dv = (w.vel * seisgen.smooth_noise((w.nx, w.ny, w.nz), 78, 8.0, 0.01)).astype(np.float32)
+    P = Propagator(0)
+    P.set_model(g, torch.from_numpy(w.vel + 5.0 * dv).cuda())
+    wav = torch.from_numpy(w.wavelet).cuda()
+    dobs = [P.forward(wav, s, w.receivers).clone() for s in w.sources]
+    P.set_model(g, torch.from_numpy(w.vel).cuda())
+    grad = torch.zeros((w.nz, w.ny, w.nx), dtype=torch.float32, device="cuda")
+    J = torch.zeros((), dtype=torch.float64, device="cuda")
+    for s, d in zip(w.sources, dobs):
+        P.gradient(wav, s, w.receivers, d, ckpt=("revolve", 20), grad=grad, misfit=J)
+    torch.cuda.synchronize()
+    an = float(np.sum(grad.cpu().numpy().astype(np.float64) * dv))
+    P.release_workspace()
+
+    def Jv(v):
+        P.set_model(g, torch.from_numpy(np.ascontiguousarray(v, dtype=np.float32)).cuda())
+        m = torch.zeros((), dtype=torch.float64, device="cuda")
+        for s, d in zip(w.sources, dobs):
+            P.forward_misfit(wav, s, w.receivers, d, misfit=m)
+        return float(m.item())
+
+    eps = 0.25
+    fd1 = (Jv(w.vel + eps * dv) - Jv(w.vel - eps * dv)) / (2 * eps)
+    fd2 = (Jv(w.vel + 2 * eps * dv) - Jv(w.vel - 2 * eps * dv)) / (4 * eps)
+    fd = (4 * fd1 - fd2) / 3
+    say(f"[c4 gradient FD] J {float(J.item()):.6e} analytic {an:.6e} central differences "
+        f"{fd1:.6e} {fd2:.6e} extrapolated {fd:.6e}")
+    assert float(J.item()) > 0 and an < 0
+    assert abs(fd - an) <= 1e-3 * abs(an)
