@@ -564,7 +564,7 @@ def cnn_kernel_bench(n: int = 256, reps: int = 20):
            "data": "synthetic", "config": {"workload": f"3-D CNN 2-16-16-16-1, 3x3x3, {n}^3 volume"},
            "roofline": {"bound": "mfma", "achieved": l1["TFLOPs"], "peak": peak,
                         "unit": "TFLOP/s", "frac": round(l1["TFLOPs"] / peak, 4),
-                        "traffic": None, "kernel": "k_conv<16, 16>"},
+                        "traffic": None, "kernel": "k_conv16<16>"},
            "kernels": out}
     print(json.dumps(res), flush=True)
 

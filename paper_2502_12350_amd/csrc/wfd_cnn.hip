@@ -55,13 +55,15 @@ constexpr int kpad(int cin) { return (27 * cin + 31) / 32 * 32; }
 // channels.  Every output voxel of the tile is computed by exactly one lane.
 //
 // A block owns a 64 x 4 output tile in x-y and marches CM_ZC output planes
-// along z.  Input planes (the tile plus a one-voxel halo, 66 x 6 voxels) live
-// in a four-slot LDS ring, plane p in slot p & 3: output plane z reads planes
-// z - 1 .. z + 1 while plane z + 2 is fetched, into registers before the
-// matrix-core work and into its slot after it, so one barrier per plane
-// suffices (the slot written held plane z - 2, read only before the previous
-// barrier).  Each of the 4 wavefronts computes one 64-voxel output row as
-// four 16 x 16 tiles with the packed weights held in registers.
+// along z.  Input planes (the tile plus a one-voxel halo, 66 x 6 voxels) go
+// through an LDS ring; each of the 4 wavefronts computes one 64-voxel output
+// row as four 16 x 16 tiles with the packed weights held in registers.  With
+// one or two input channels (k_conv) all 27 taps of an output voxel fit in one
+// or two K chunks: output plane z reads planes z - 1 .. z + 1 from a four-slot
+// ring (plane p in slot p & 3) while plane z + 2 is fetched, into registers
+// before the matrix-core work and into its slot after it, so one barrier per
+// plane suffices (the slot written held plane z - 2, read only before the
+// previous barrier).  With 16 input channels, k_conv16 below.
 constexpr int CM_TY = 4, CM_ZC = 16, CM_THR = 256;
 constexpr int CM_LX = 66, CM_LY = CM_TY + 2, CM_PLANE = CM_LX * CM_LY, CM_SLOTS = 4;
 // CIN = 16: a plane is CM_PLANE * 2 sixteen-byte items, at most CM_PF per thread
@@ -128,21 +130,12 @@ __device__ __forceinline__ void cm_store_small(uint16_t *lds, int slot, const ui
   }
 }
 
-// B fragment of chunk c for output voxel lx of row ly and lane group g; sl[d]
-// is the slot of input plane z - 1 + d.
+// B fragment of chunk c (one or two input channels) for output voxel lx of
+// row ly and lane group g; sl[d] is the slot of input plane z - 1 + d.
 template <int CIN>
 __device__ __forceinline__ bf16x8 cm_gather(const uint16_t *lds, int c, int lx, int ly,
                                             const int *sl, int g) {
-  if (CIN == 16) {
-    const int t = 2 * c + (g >> 1);
-    u32x4 d = {0u, 0u, 0u, 0u};
-    if (t < 27) {
-      const int dz = t / 9, dy = (t / 3) % 3, dx = t % 3;
-      const int v = sl[dz] * CM_PLANE + (ly + dy) * CM_LX + lx + dx;
-      d = *reinterpret_cast<const u32x4 *>(lds + v * 16 + 8 * (g & 1));
-    }
-    return __builtin_bit_cast(bf16x8, d);
-  } else if (CIN == 2) {  // elements (2u, 2u + 1) are both channels of tap 4 (c, g) + u
+  if (CIN == 2) {  // elements (2u, 2u + 1) are both channels of tap 4 (c, g) + u
     u32x4 d;
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
@@ -173,12 +166,66 @@ __device__ __forceinline__ bf16x8 cm_gather(const uint16_t *lds, int c, int lx, 
   }
 }
 
+// Epilogue of one output row of 4 x 16 voxels: lane holds D[co = 4 g + e][voxel
+// j] of each tile.  Bias, relu, the mask and (single output channel only) the
+// residual, then BF16 and/or FP32 stores.
+template <int COUT>
+__device__ __forceinline__ void cm_epilogue(const f32x4 *acc, int nx, int ny, int z, int x0,
+                                            int gy, int j, int g, const float *__restrict__ bias,
+                                            int relu, const uint16_t *__restrict__ mask,
+                                            const uint16_t *__restrict__ res, int res_c,
+                                            uint16_t *__restrict__ out_bf,
+                                            float *__restrict__ out_f) {
+  if (gy >= ny) return;
+#pragma unroll
+  for (int tl = 0; tl < 4; ++tl) {
+    const int gx = x0 + 16 * tl + j;
+    if (gx >= nx) continue;
+    const int64_t vox = ((int64_t)z * ny + gy) * nx + gx;
+    uint16_t mk[4] = {1, 1, 1, 1};  // positive bits unless a mask is given
+    if (mask) {
+      if (COUT == 16) {  // the lane's four channels 4g .. 4g + 3 in one load
+        const uint2 m2 = *reinterpret_cast<const uint2 *>(mask + vox * 16 + 4 * g);
+        mk[0] = (uint16_t)m2.x, mk[1] = (uint16_t)(m2.x >> 16);
+        mk[2] = (uint16_t)m2.y, mk[3] = (uint16_t)(m2.y >> 16);
+      } else if (g == 0) {
+        mk[0] = mask[vox * COUT];
+      }
+    }
+    float v[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int co = 4 * g + e;
+      float s = acc[tl][e];
+      if (bias && co < COUT) s += bias[co];
+      if (relu) s = fmaxf(s, 0.0f);
+      if (mask && co < COUT && !bf16_pos(mk[e])) s = 0.0f;
+      v[e] = s;
+    }
+    if (COUT == 16) {
+      if (out_bf) {
+        const uint32_t lo = (uint32_t)to_bf16(v[0]) | ((uint32_t)to_bf16(v[1]) << 16);
+        const uint32_t hi = (uint32_t)to_bf16(v[2]) | ((uint32_t)to_bf16(v[3]) << 16);
+        *reinterpret_cast<uint2 *>(out_bf + vox * 16 + 4 * g) = make_uint2(lo, hi);
+      }
+      if (out_f)
+        *reinterpret_cast<float4 *>(out_f + vox * 16 + 4 * g) =
+            make_float4(v[0], v[1], v[2], v[3]);
+    } else if (g == 0) {  // single output channel: co = 0 is element 0 of group 0
+      if (res) v[0] += from_bf16(res[vox * res_c]);
+      if (out_bf) out_bf[vox] = to_bf16(v[0]);
+      if (out_f) out_f[vox] = v[0];
+    }
+  }
+}
+
 template <int CIN, int COUT>
 __global__ void __launch_bounds__(CM_THR)
     k_conv(const uint16_t *__restrict__ in, int nx, int ny, int nz,
            const uint16_t *__restrict__ apk, const float *__restrict__ bias, int relu,
            const uint16_t *__restrict__ mask, const uint16_t *__restrict__ res, int res_c,
            uint16_t *__restrict__ out_bf, float *__restrict__ out_f) {
+  static_assert(CIN == 1 || CIN == 2, "16 input channels: k_conv16");
   constexpr int K = kpad(CIN), NC = K / 32;
   __shared__ __attribute__((aligned(16))) uint16_t lds[CM_SLOTS * CM_PLANE * CIN + 8];
   const int tx = (nx + 63) / 64, ty = (ny + CM_TY - 1) / CM_TY;
@@ -194,29 +241,17 @@ __global__ void __launch_bounds__(CM_THR)
         bf16x8, *reinterpret_cast<const u32x4 *>(apk + (size_t)j * K + 32 * c + 8 * g));
   // prologue: planes zs - 1 .. zs + 1
   for (int p = zs - 1; p <= zs + 1; ++p) {
-    if (CIN == 16) {
-      u32x4 pf[CM_PF];
-      cm_fetch16(pf, in, nx, ny, nz, x0, y0, p);
-      cm_store16(lds, p & 3, pf);
-    } else {
-      uint32_t pf[CM_PFS];
-      cm_fetch_small<CIN>(pf, in, nx, ny, nz, x0, y0, p);
-      cm_store_small<CIN>(lds, p & 3, pf);
-    }
+    uint32_t pf[CM_PFS];
+    cm_fetch_small<CIN>(pf, in, nx, ny, nz, x0, y0, p);
+    cm_store_small<CIN>(lds, p & 3, pf);
   }
   __syncthreads();
   const int ly = wave, gy = y0 + ly;  // this wave's output row
 #pragma unroll 1
   for (int z = zs; z < ze; ++z) {
     const bool more = z + 1 < ze;  // plane z + 2 is needed for output plane z + 1
-    u32x4 pf[CIN == 16 ? CM_PF : 1];
-    uint32_t pfs[CIN == 16 ? 1 : CM_PFS];
-    if (more) {
-      if (CIN == 16)
-        cm_fetch16(pf, in, nx, ny, nz, x0, y0, z + 2);
-      else
-        cm_fetch_small<CIN>(pfs, in, nx, ny, nz, x0, y0, z + 2);
-    }
+    uint32_t pfs[CM_PFS];
+    if (more) cm_fetch_small<CIN>(pfs, in, nx, ny, nz, x0, y0, z + 2);
     const int sl[3] = {(z - 1) & 3, z & 3, (z + 1) & 3};
     f32x4 acc[4];
 #pragma unroll
@@ -231,58 +266,138 @@ __global__ void __launch_bounds__(CM_THR)
       for (int tl = 0; tl < 4; ++tl)
         acc[tl] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[c], b[tl], acc[tl], 0, 0, 0);
     }
-    if (gy < ny) {
-      // epilogue: lane holds D[co = 4 g + e][voxel j] of each tile
-#pragma unroll
-      for (int tl = 0; tl < 4; ++tl) {
-        const int gx = x0 + 16 * tl + j;
-        if (gx >= nx) continue;
-        const int64_t vox = ((int64_t)z * ny + gy) * nx + gx;
-        uint16_t mk[4] = {1, 1, 1, 1};  // positive bits unless a mask is given
-        if (mask) {
-          if (COUT == 16) {  // the lane's four channels 4g .. 4g + 3 in one load
-            const uint2 m2 = *reinterpret_cast<const uint2 *>(mask + vox * 16 + 4 * g);
-            mk[0] = (uint16_t)m2.x, mk[1] = (uint16_t)(m2.x >> 16);
-            mk[2] = (uint16_t)m2.y, mk[3] = (uint16_t)(m2.y >> 16);
-          } else if (g == 0) {
-            mk[0] = mask[vox * COUT];
-          }
-        }
-        float v[4];
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          const int co = 4 * g + e;
-          float s = acc[tl][e];
-          if (bias && co < COUT) s += bias[co];
-          if (relu) s = fmaxf(s, 0.0f);
-          if (mask && co < COUT && !bf16_pos(mk[e])) s = 0.0f;
-          v[e] = s;
-        }
-        if (COUT == 16) {
-          if (out_bf) {
-            const uint32_t lo = (uint32_t)to_bf16(v[0]) | ((uint32_t)to_bf16(v[1]) << 16);
-            const uint32_t hi = (uint32_t)to_bf16(v[2]) | ((uint32_t)to_bf16(v[3]) << 16);
-            *reinterpret_cast<uint2 *>(out_bf + vox * 16 + 4 * g) = make_uint2(lo, hi);
-          }
-          if (out_f)
-            *reinterpret_cast<float4 *>(out_f + vox * 16 + 4 * g) =
-                make_float4(v[0], v[1], v[2], v[3]);
-        } else if (g == 0) {  // single output channel: co = 0 is element 0 of group 0
-          if (res) v[0] += from_bf16(res[vox * res_c]);
-          if (out_bf) out_bf[vox] = to_bf16(v[0]);
-          if (out_f) out_f[vox] = v[0];
-        }
-      }
-    }
-    if (more) {
-      if (CIN == 16)
-        cm_store16(lds, (z + 2) & 3, pf);
-      else
-        cm_store_small<CIN>(lds, (z + 2) & 3, pfs);
-    }
+    cm_epilogue<COUT>(acc, nx, ny, z, x0, gy, j, g, bias, relu, mask, res, res_c, out_bf, out_f);
+    if (more) cm_store_small<CIN>(lds, (z + 2) & 3, pfs);
     __syncthreads();
   }
 }
+// Convolution with 16 input channels, input-plane major.  An input plane p
+// feeds output planes p + 1, p and p - 1 through the taps kz = 0, 1, 2, so
+// the K dimension is split as k = 144 kz + k' with k' = 16 (3 ky + kx) + ci
+// (five chunks of 32, the last half zero): each B fragment of plane p is read
+// from LDS once and used by the three kz slices of the weights, and the
+// matrix-core work per output plane is 15 instead of 14 products while the
+// LDS fragment reads drop from 14 to 5.  With 16 output channels the three
+// kz products go to three rotating accumulators (output planes p + 1, p,
+// p - 1); with one output channel the rows of A are the three kz slices of
+// the single weight row, one product per chunk leaves the three partial sums
+// in rows 0..2, and two running sums per voxel complete the output.  Output
+// plane p - 1 is complete after input plane p.  Input planes go through a
+// two-slot LDS ring (the next plane is fetched into registers during the
+// matrix-core work and stored after it, one barrier per plane).
+template <int COUT>
+__global__ void __launch_bounds__(CM_THR)
+    k_conv16(const uint16_t *__restrict__ in, int nx, int ny, int nz,
+             const uint16_t *__restrict__ apk, const float *__restrict__ bias, int relu,
+             const uint16_t *__restrict__ mask, const uint16_t *__restrict__ res, int res_c,
+             uint16_t *__restrict__ out_bf, float *__restrict__ out_f) {
+  constexpr int K = kpad(16), NC = 5, KP = 144;  // K' = 9 taps x 16 channels
+  constexpr int NA = COUT == 16 ? 3 : 1;         // A fragments per chunk
+  __shared__ __attribute__((aligned(16))) uint16_t lds[2 * CM_PLANE * 16 + 8];
+  const int tx = (nx + 63) / 64, ty = (ny + CM_TY - 1) / CM_TY;
+  const int x0 = (blockIdx.x % tx) * 64, y0 = ((blockIdx.x / tx) % ty) * CM_TY;
+  const int zs = (blockIdx.x / (tx * ty)) * CM_ZC, ze = min(zs + CM_ZC, nz);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int j = lane & 15, g = lane >> 4;
+  // A fragments: lane (i + 16 g) holds k' = 32 c + 8 g .. + 7 of row i.
+  // COUT = 16: a[kz][c], row i = co.  COUT = 1: a[0][c], row i = kz (rows 3..15 zero).
+  bf16x8 a[NA][NC];
+#pragma unroll
+  for (int q = 0; q < NA; ++q)
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      const int kp = 32 * c + 8 * g;
+      const int row = COUT == 16 ? j : 0, kz = COUT == 16 ? q : j;
+      u32x4 d = {0u, 0u, 0u, 0u};
+      if (kp < KP && (COUT == 16 || j < 3))
+        d = *reinterpret_cast<const u32x4 *>(apk + (size_t)row * K + KP * kz + kp);
+      a[q][c] = __builtin_bit_cast(bf16x8, d);
+    }
+  {  // prologue: input plane zs - 1
+    u32x4 pf[CM_PF];
+    cm_fetch16(pf, in, nx, ny, nz, x0, y0, zs - 1);
+    cm_store16(lds, (zs - 1) & 1, pf);
+  }
+  __syncthreads();
+  const int ly = wave, gy = y0 + ly;  // this wave's output row
+  // COUT = 16: acc[0] -> output p + 1, acc[1] -> p, acc[2] -> p - 1 (per tile)
+  // COUT = 1: s1 = partial of output p, s2 = partial of output p - 1
+  f32x4 acc[3][4];
+  float s1[4], s2[4];
+#pragma unroll
+  for (int tl = 0; tl < 4; ++tl) {
+    s1[tl] = s2[tl] = 0.0f;
+#pragma unroll
+    for (int q = 0; q < 3; ++q) acc[q][tl] = f32x4{0.f, 0.f, 0.f, 0.f};
+  }
+#pragma unroll 1
+  for (int p = zs - 1; p <= ze; ++p) {
+    const bool more = p + 1 <= ze;
+    u32x4 pf[CM_PF];
+    if (more) cm_fetch16(pf, in, nx, ny, nz, x0, y0, p + 1);
+    const uint16_t *pl = lds + (p & 1) * CM_PLANE * 16;
+    // every input plane feeds three accumulators; those of output planes
+    // outside [zs, ze) (at the first two and last two input planes) are never
+    // written out, and branch-free products schedule better than skipping them
+    const bool to_prev = p - 1 >= zs;
+    f32x4 d[4];
+#pragma unroll
+    for (int tl = 0; tl < 4; ++tl) d[tl] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      const int t = 2 * c + (g >> 1);  // tap ky * 3 + kx of this lane's k'
+      bf16x8 b[4];
+#pragma unroll
+      for (int tl = 0; tl < 4; ++tl) {
+        u32x4 v = {0u, 0u, 0u, 0u};
+        if (t < 9) {
+          const int vox = (ly + t / 3) * CM_LX + 16 * tl + j + t % 3;
+          v = *reinterpret_cast<const u32x4 *>(pl + vox * 16 + 8 * (g & 1));
+        }
+        b[tl] = __builtin_bit_cast(bf16x8, v);
+      }
+      if (COUT == 16) {
+#pragma unroll
+        for (int tl = 0; tl < 4; ++tl) {
+          acc[0][tl] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0][c], b[tl], acc[0][tl], 0, 0, 0);
+          acc[1][tl] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[1][c], b[tl], acc[1][tl], 0, 0, 0);
+          acc[2][tl] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[2][c], b[tl], acc[2][tl], 0, 0, 0);
+        }
+      } else {
+#pragma unroll
+        for (int tl = 0; tl < 4; ++tl)
+          d[tl] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0][c], b[tl], d[tl], 0, 0, 0);
+      }
+    }
+    if (to_prev) {  // output plane p - 1 is complete
+      if (COUT == 16) {
+        cm_epilogue<COUT>(acc[2], nx, ny, p - 1, x0, gy, j, g, bias, relu, mask, res, res_c,
+                          out_bf, out_f);
+      } else {  // lanes of group 0 hold (P0, P1, P2) of voxel j in elements 0..2
+        f32x4 o[4];
+#pragma unroll
+        for (int tl = 0; tl < 4; ++tl) o[tl] = f32x4{s2[tl] + d[tl][2], 0.f, 0.f, 0.f};
+        cm_epilogue<COUT>(o, nx, ny, p - 1, x0, gy, j, g, bias, relu, mask, res, res_c, out_bf,
+                          out_f);
+      }
+    }
+    // rotate: output p becomes p - 1 for the next plane, p + 1 becomes p
+#pragma unroll
+    for (int tl = 0; tl < 4; ++tl) {
+      if (COUT == 16) {
+        acc[2][tl] = acc[1][tl];
+        acc[1][tl] = acc[0][tl];
+        acc[0][tl] = f32x4{0.f, 0.f, 0.f, 0.f};
+      } else {
+        s2[tl] = s1[tl] + d[tl][1];
+        s1[tl] = d[tl][0];
+      }
+    }
+    if (more) cm_store16(lds, (p + 1) & 1, pf);
+    __syncthreads();
+  }
+}
+
 // Weight gradient: dW[tap][ci][co] = sum over voxels v of dz[v][co] *
 // in[v + offset(tap)][ci], and db[co] = sum of dz[v][co], with the voxel index
 // as the matrix-core K dimension: A[co][k] = dz[voxel k][co], B[k][ci] =
@@ -679,11 +794,15 @@ hipError_t launch_conv(int cin, int cout, const uint16_t *in, int nx, int ny, in
 #define WFD_CONV(CI, CO)                                                                      \
   hipLaunchKernelGGL((k_conv<CI, CO>), grid, block, 0, stream, in, nx, ny, nz, apk, bias, relu, \
                      mask, res, res_c, out_bf, out_f)
-  if (cin == 16 && cout == 16) WFD_CONV(16, 16);
+#define WFD_CONV16(CO)                                                                        \
+  hipLaunchKernelGGL((k_conv16<CO>), grid, block, 0, stream, in, nx, ny, nz, apk, bias, relu,  \
+                     mask, res, res_c, out_bf, out_f)
+  if (cin == 16 && cout == 16) WFD_CONV16(16);
   else if (cin == 2 && cout == 16) WFD_CONV(2, 16);
   else if (cin == 1 && cout == 16) WFD_CONV(1, 16);
-  else if (cin == 16 && cout == 1) WFD_CONV(16, 1);
+  else if (cin == 16 && cout == 1) WFD_CONV16(1);
   else return hipErrorInvalidValue;
+#undef WFD_CONV16
 #undef WFD_CONV
   return hipGetLastError();
 }

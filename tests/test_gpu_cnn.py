@@ -159,6 +159,40 @@ def test_weight_gradient_many_tiles_per_block(ci, co):
     assert e <= 2e-5 and eb <= 2e-5
 
 
+@pytest.mark.parametrize("li,flip", [(1, False), (3, False), (1, True)])
+def test_convolution_over_several_z_chunks(li, flip):
+    # 70 x 7 x 37: three 16-plane chunks per column, the last one ragged; the
+    # 16-input-channel kernel carries partial sums of three output planes
+    # across its input planes, so chunk starts and ends are the cases to see
+    torch = gpu_or_skip()
+    nz, ny, nx = 37, 7, 70
+    P, Ws, bs = _net(torch, seed=li + 10)
+    ci, co = [(2, 16), (16, 16), (16, 16), (16, 1)][li]
+    rng = np.random.default_rng(60 + li)
+    say(f"[cnn conv] {nx}x{ny}x{nz} layer {li} flip {flip}")
+    if flip:  # data gradient: dz (co channels) -> input-gradient (ci channels), ReLU mask
+        dz = cnn.bf16(rng.standard_normal((nz, ny, nx, co)))
+        act = cnn.bf16(rng.standard_normal((nz, ny, nx, ci)))
+        got = P.conv(_bf(torch, dz), li, relu=False, flip=True, bias=False, mask=_bf(torch, act))
+        ref = cnn.conv3d_dgrad(dz, Ws[li]) * (act > 0)
+    else:
+        x = cnn.bf16(rng.standard_normal((nz, ny, nx, ci)))
+        got = P.conv(_bf(torch, x), li, relu=li < 3, out_f32=True)
+        ref = cnn.conv3d(x, Ws[li], bs[li])
+        if li < 3:
+            ref = np.maximum(ref, 0.0)
+    torch.cuda.synchronize()
+    g = _np(got).reshape(ref.shape)
+    if got.dtype == torch.bfloat16:
+        frac, worst = _bf16_close(g, ref)
+        say(f"  BF16 mismatches {frac:.2e}, worst {worst:.2f} steps")
+        assert frac <= 1e-3 and worst <= 1.0
+    else:
+        e = rel_l2(g, ref)
+        say(f"  rel-L2 {e:.2e}")
+        assert e <= TOL
+
+
 def test_mse_adam_and_input_packing_match_oracle():
     torch = gpu_or_skip()
     import ctypes as C
