@@ -453,9 +453,12 @@ struct WgIn {
           va = *reinterpret_cast<const u32x4 *>(in + (base + xa) * 16 + 8 * h);
         if (row && xa + 1 < nx)
           vb = *reinterpret_cast<const u32x4 *>(in + (base + xa + 1) * 16 + 8 * h);
-      } else {  // CIN = 2: one dword per voxel
+      } else if (CIN == 2) {  // one dword per voxel
         if (row && xa >= 0 && xa < nx) va[0] = *reinterpret_cast<const uint32_t *>(in + (base + xa) * 2);
         if (row && xa + 1 < nx) vb[0] = *reinterpret_cast<const uint32_t *>(in + (base + xa + 1) * 2);
+      } else {  // CIN = 1: one element per voxel
+        if (row && xa >= 0 && xa < nx) va[0] = in[base + xa];
+        if (row && xa + 1 < nx) vb[0] = in[base + xa + 1];
       }
       a[i] = va;
       b[i] = vb;
@@ -476,7 +479,7 @@ struct WgIn {
         }
       } else {
         d[0] = wg_lo(a[i][0], b[i][0]);
-        d[WG_RX / 2] = wg_hi(a[i][0], b[i][0]);
+        if (CIN == 2) d[WG_RX / 2] = wg_hi(a[i][0], b[i][0]);
       }
     }
   }
@@ -628,6 +631,148 @@ __global__ void __launch_bounds__(WG_THR)
 #pragma unroll
     for (int e = 0; e < 4; ++e) row[t * 256 + (4 * g + e) * 16 + j] = acc[t][e];
   if (j == 0) {
+#pragma unroll
+    for (int e = 0; e < 4; ++e) row[27 * 256 + 4 * g + e] = accb[e];
+  }
+}
+
+// Eight consecutive elements starting s = 0, 1 or 2 elements past an aligned
+// position, from the ten read there (w0..w3 and w4).
+__device__ __forceinline__ u32x4 wg_shift(const u32x4 &w, uint32_t w4, int s) {
+  const uint32_t sh = 2u * (uint32_t)(s & 1);
+  const uint32_t n[5] = {w[0], w[1], w[2], w[3], w4};
+  u32x4 r;
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+    r[i] = s == 2 ? n[i + 1] : __builtin_amdgcn_alignbyte(n[i + 1], n[i], sh);
+  return r;
+}
+
+// Weight gradients of the layers with a single output channel (MODE 0: 16
+// -> 1) or two input channels (MODE 1: 2 -> 16).  In k_wgrad these run
+// 16 x 16 tiles with 15 of 16 rows (or 14 of 16 columns) zero.  Here the idle
+// rows or columns carry other taps, each lane reading its operand at its own
+// tap's offset:
+//   MODE 0: A[tap][k] = dz[voxel k - offset(tap)], B[k][ci] = in[voxel k][ci]
+//           (D = dW[tap][ci] summed over voxels k; 16 taps per product, 2
+//           products per chunk, the centre tap's row of A against ones gives
+//           db);
+//   MODE 1: A[co][k] = dz[voxel k][co], B[k][(tap, ci)] = in[voxel k +
+//           offset(tap)][ci] (8 taps x 2 channels per product, 4 products).
+// The shifted operand is marched with its one-voxel halo in a four-slot ring
+// (planes z - 1 .. z + 1 and the next), the other one plane at a time, as in
+// k_wgrad; a lane's eight voxels of a tap are read as ten aligned elements and
+// shifted in registers by its tap's x offset.
+template <int MODE>
+__global__ void __launch_bounds__(WG_THR)
+    k_wgrad_pack(const uint16_t *__restrict__ in, const uint16_t *__restrict__ dz, int nx, int ny,
+                 int nz, int ntiles, float *__restrict__ partial) {
+  constexpr int RC = MODE == 0 ? 1 : 2;  // channels of the shifted (ringed) operand
+  constexpr int NQ = MODE == 0 ? 2 : 4;  // shifted fragments per chunk
+  using Ring = WgIn<RC>;
+  using Flat = WgDz<16>;
+  const uint16_t *ring_src = MODE == 0 ? dz : in;
+  const uint16_t *flat_src = MODE == 0 ? in : dz;
+  __shared__ __attribute__((aligned(16))) uint32_t lring[4 * Ring::SLOT / 2];
+  __shared__ __attribute__((aligned(16))) uint32_t lflat[2 * Flat::SLOT / 2];
+  const uint16_t *ring16 = reinterpret_cast<const uint16_t *>(lring);
+  const uint16_t *flat16 = reinterpret_cast<const uint16_t *>(lflat);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int j = lane & 15, g = lane >> 4;
+  const int tx = (nx + 63) / 64, ty = (ny + WG_TY - 1) / WG_TY;
+  // the lane's tap and channel in each shifted fragment
+  int tk[NQ], ch[NQ];
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) {
+    tk[q] = MODE == 0 ? 16 * q + j : 8 * q + (j >> 1);
+    ch[q] = MODE == 0 ? 0 : (j & 1);
+  }
+  f32x4 acc[NQ];
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) acc[q] = f32x4{0.f, 0.f, 0.f, 0.f};
+  f32x4 accb = {0.f, 0.f, 0.f, 0.f};
+  const uint32_t one2 = 0x3F803F80u;  // two BF16 ones
+  const bf16x8 ones = __builtin_bit_cast(bf16x8, u32x4{one2, one2, one2, one2});
+  for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    const int x0 = (tile % tx) * 64, y0 = ((tile / tx) % ty) * WG_TY;
+    const int zs = (tile / (tx * ty)) * WG_ZC, ze = min(zs + WG_ZC, nz);
+    {  // prologue: ring planes zs - 1 .. zs + 1 and flat plane zs
+      Ring pr;
+      for (int p = zs - 1; p <= zs + 1; ++p) {
+        pr.fetch(ring_src, nx, ny, nz, x0, y0, p);
+        pr.store(lring, p & 3);
+      }
+      Flat pf;
+      pf.fetch(flat_src, nx, ny, x0, y0, zs);
+      pf.store(lflat, zs & 1);
+    }
+    __syncthreads();
+    const bool row_live = y0 + wave < ny;
+#pragma unroll 1
+    for (int z = zs; z < ze; ++z) {
+      const bool more = z + 1 < ze;
+      Ring nr;
+      Flat nf;
+      if (more) {
+        nr.fetch(ring_src, nx, ny, nz, x0, y0, z + 2);
+        nf.fetch(flat_src, nx, ny, x0, y0, z + 1);
+      }
+      if (row_live) {
+#pragma unroll
+        for (int xb = 0; xb < 64; xb += 32) {
+          if (x0 + xb >= nx) break;  // the chunk's voxels are all outside
+          const bf16x8 F = __builtin_bit_cast(
+              bf16x8, *reinterpret_cast<const u32x4 *>(flat16 + (z & 1) * Flat::SLOT +
+                                                       (wave * 16 + j) * WG_RX + xb + 8 * g));
+          if (MODE == 1) accb = __builtin_amdgcn_mfma_f32_16x16x32_bf16(F, ones, accb, 0, 0, 0);
+#pragma unroll
+          for (int q = 0; q < NQ; ++q) {
+            u32x4 sv = {0u, 0u, 0u, 0u};
+            const int t = tk[q];
+            if (t < 27) {
+              const int kz = t / 9, ky = (t / 3) % 3, kx = t % 3;
+              const int pl = MODE == 0 ? z + 1 - kz : z - 1 + kz;
+              const int row = MODE == 0 ? wave + 2 - ky : wave + ky;
+              const uint16_t *r =
+                  ring16 + (pl & 3) * Ring::SLOT + (row * RC + ch[q]) * WG_RX + xb + 8 * g;
+              sv = wg_shift(*reinterpret_cast<const u32x4 *>(r),
+                            *reinterpret_cast<const uint32_t *>(r + 8), MODE == 0 ? 2 - kx : kx);
+            }
+            const bf16x8 S = __builtin_bit_cast(bf16x8, sv);
+            if (MODE == 0) {
+              acc[q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(S, F, acc[q], 0, 0, 0);
+              if (q == 0) accb = __builtin_amdgcn_mfma_f32_16x16x32_bf16(S, ones, accb, 0, 0, 0);
+            } else {
+              acc[q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(F, S, acc[q], 0, 0, 0);
+            }
+          }
+        }
+      }
+      if (more) {
+        nr.store(lring, (z + 2) & 3);
+        nf.store(lflat, (z + 1) & 1);
+      }
+      __syncthreads();
+    }
+  }
+  // lane holds D[i = 4 g + e][j] of each product; one partial row per wavefront
+  float *row = partial + ((size_t)blockIdx.x * 4 + wave) * WG_ROW;
+#pragma unroll
+  for (int q = 0; q < NQ; ++q)
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int i = 4 * g + e;
+      if (MODE == 0) {  // D[tap = 16 q + i][ci = j]
+        const int t = 16 * q + i;
+        if (t < 27) row[t * 256 + j] = acc[q][e];
+      } else {          // D[co = i][(tap, ci) = j]
+        const int t = 8 * q + (j >> 1);
+        if (t < 27) row[t * 256 + i * 16 + (j & 1)] = acc[q][e];
+      }
+    }
+  if (MODE == 0) {  // db from the centre tap's row (13 = 4 * 3 + 1)
+    if (j == 0 && g == 3) row[27 * 256] = accb[1];
+  } else if (j == 0) {
 #pragma unroll
     for (int e = 0; e < 4; ++e) row[27 * 256 + 4 * g + e] = accb[e];
   }
@@ -824,11 +969,15 @@ hipError_t launch_wgrad(int cin, int cout, const uint16_t *in, const uint16_t *d
 #define WFD_WG(CI, CO)                                                                          \
   hipLaunchKernelGGL((k_wgrad<CI, CO>), dim3(nb), dim3(WG_THR), 0, stream, in, dz, nx, ny, nz, \
                      ntiles, partial)
+#define WFD_WGP(M)                                                                            \
+  hipLaunchKernelGGL((k_wgrad_pack<M>), dim3(nb), dim3(WG_THR), 0, stream, in, dz, nx, ny, nz, \
+                     ntiles, partial)
   if (cin == 16 && cout == 16) WFD_WG(16, 16);
-  else if (cin == 2 && cout == 16) WFD_WG(2, 16);
-  else if (cin == 16 && cout == 1) WFD_WG(16, 1);
+  else if (cin == 2 && cout == 16) WFD_WGP(1);
+  else if (cin == 16 && cout == 1) WFD_WGP(0);
   else return hipErrorInvalidValue;
 #undef WFD_WG
+#undef WFD_WGP
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const int cb = (WG_ROW + 255) / 256;
