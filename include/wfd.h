@@ -343,7 +343,9 @@ wfd_status wfd_cnn_pack_weights(const float *w_dev, int32_t cin, int32_t cout, i
  * layer (cin, cout) this is the data gradient of that layer: call it with
  * cin' = cout and cout' = cin.  (cin, cout) in {(2,16), (16,16), (16,1),
  * (1,16)}.  Written as BF16 (rounded to nearest even) and/or FP32
- * channels-last; in, packed and outputs 16-byte aligned. */
+ * channels-last; in, packed and outputs 16-byte aligned, a 16-channel mask
+ * 8-byte aligned.  WFD_E_ARG for another layer shape, an empty volume, a
+ * misaligned or missing buffer, or a residual with more than one output. */
 wfd_status wfd_cnn_conv(const uint16_t *in_dev, int32_t nx, int32_t ny, int32_t nz, int32_t cin,
                         int32_t cout, const uint16_t *packed_dev, const float *bias_or_null,
                         int32_t relu, const uint16_t *mask_or_null,
@@ -357,7 +359,9 @@ wfd_status wfd_cnn_wgrad_workspace_bytes(int32_t nx, int32_t ny, int32_t nz, siz
  * gradient dz of its output (before the layer's ReLU, i.e. already masked):
  *   dw[tap][ci][co] = sum_p in[p + offset(tap)][ci] dz[p][co]   (FP32, written)
  *   db[co] = sum_p dz[p][co]                                     (if non-NULL)
- * BF16 products, FP32 sums in a fixed order (deterministic). */
+ * BF16 products, FP32 sums in a fixed order (deterministic).  in and (for
+ * 16 output channels) dz 16-byte aligned; work (device, caller-owned) at
+ * least wfd_cnn_wgrad_workspace_bytes, else WFD_E_NOMEM. */
 wfd_status wfd_cnn_wgrad(const uint16_t *in_dev, const uint16_t *dz_dev, int32_t nx, int32_t ny,
                          int32_t nz, int32_t cin, int32_t cout, float *dw_dev,
                          float *db_dev_or_null, void *work_dev, size_t work_bytes, void *stream);

@@ -1603,6 +1603,16 @@ wfd_status wfd_cnn_pack_weights(const float *w, int32_t cin, int32_t cout, int32
   return WFD_OK;
 }
 
+namespace {
+// The CNN kernels tile a volume into 64 x 4 x 16-voxel marches and index
+// tiles with 32-bit integers: the tile count must stay below 2^31.
+bool cnn_volume_ok(int32_t nx, int32_t ny, int32_t nz) {
+  if (nx < 1 || ny < 1 || nz < 1) return false;
+  const int64_t a = ((int64_t)nx + 63) / 64, b = ((int64_t)ny + 3) / 4, c = ((int64_t)nz + 15) / 16;
+  return a * b <= INT32_MAX && a * b * c <= INT32_MAX;
+}
+}  // namespace
+
 wfd_status wfd_cnn_conv(const uint16_t *in, int32_t nx, int32_t ny, int32_t nz, int32_t cin,
                         int32_t cout, const uint16_t *apk, const float *bias, int32_t relu,
                         const uint16_t *mask, const uint16_t *residual, int32_t residual_channels,
@@ -1610,10 +1620,11 @@ wfd_status wfd_cnn_conv(const uint16_t *in, int32_t nx, int32_t ny, int32_t nz, 
   const bool shape = (cin == 2 && cout == 16) || (cin == 16 && cout == 16) ||
                      (cin == 16 && cout == 1) || (cin == 1 && cout == 16);
   if (!shape) return fail(WFD_E_ARG, "no convolution %d -> %d channels", cin, cout);
-  if (nx < 1 || ny < 1 || nz < 1) return fail(WFD_E_ARG, "empty volume %d x %d x %d", nx, ny, nz);
-  if ((int64_t)((nx + 63) / 64) * ((ny + 1) / 2) * ((nz + 1) / 2) > 0x7fffffffLL)
-    return fail(WFD_E_ARG, "volume too large");
+  if (!cnn_volume_ok(nx, ny, nz))
+    return fail(WFD_E_ARG, "volume %d x %d x %d empty or too large", nx, ny, nz);
   if (!in || !apk) return fail(WFD_E_ARG, "NULL input or weights");
+  if (mask && cout == 16 && (uintptr_t)mask % 8)
+    return fail(WFD_E_ARG, "a 16-channel mask must be 8-byte aligned");
   if (!out_bf16 && !out_f32) return fail(WFD_E_ARG, "no output");
   if (residual && (cout != 1 || residual_channels < 1))
     return fail(WFD_E_ARG, "a residual needs a single-output convolution and >= 1 channel");
@@ -1627,7 +1638,8 @@ wfd_status wfd_cnn_conv(const uint16_t *in, int32_t nx, int32_t ny, int32_t nz, 
 
 wfd_status wfd_cnn_wgrad_workspace_bytes(int32_t nx, int32_t ny, int32_t nz, size_t *bytes) {
   if (!bytes) return fail(WFD_E_ARG, "NULL argument");
-  if (nx < 1 || ny < 1 || nz < 1) return fail(WFD_E_ARG, "empty volume");
+  if (!cnn_volume_ok(nx, ny, nz))
+    return fail(WFD_E_ARG, "volume %d x %d x %d empty or too large", nx, ny, nz);
   *bytes = wfd::cnn_wgrad_workspace_floats(nx, ny, nz) * sizeof(float);
   return WFD_OK;
 }
@@ -1638,9 +1650,12 @@ wfd_status wfd_cnn_wgrad(const uint16_t *in, const uint16_t *dz, int32_t nx, int
   const bool layer = (cin == 2 && cout == 16) || (cin == 16 && cout == 16) ||
                      (cin == 16 && cout == 1);
   if (!layer) return fail(WFD_E_ARG, "no network layer %d -> %d", cin, cout);
-  if (nx < 1 || ny < 1 || nz < 1) return fail(WFD_E_ARG, "empty volume");
+  if (!cnn_volume_ok(nx, ny, nz))
+    return fail(WFD_E_ARG, "volume %d x %d x %d empty or too large", nx, ny, nz);
   if (!in || !dz || !dw || !work) return fail(WFD_E_ARG, "NULL argument");
   if ((uintptr_t)in % 16) return fail(WFD_E_ARG, "input must be 16-byte aligned");
+  if (cout == 16 && (uintptr_t)dz % 16)
+    return fail(WFD_E_ARG, "a 16-channel output gradient must be 16-byte aligned");
   const size_t need = wfd::cnn_wgrad_workspace_floats(nx, ny, nz) * sizeof(float);
   if (work_bytes < need)
     return fail(WFD_E_NOMEM, "workspace has %zu bytes, %zu needed", work_bytes, need);

@@ -167,6 +167,15 @@ def test_cnn_packed_sizes_and_workspace():
     assert b.value == (4 * 512 + 64) * row                            # capped at 512 blocks
     assert L.wfd_cnn_conv(None, 8, 8, 8, 3, 16, None, None, 0, None, None, 0, None, None,
                           None) == -1
+    # argument checks that fail before any device work (pointers never dereferenced)
+    big = 1 << 30
+    assert L.wfd_cnn_wgrad(256, 256, 2 ** 30, 2 ** 30, 2 ** 30, 16, 16, 256, 256, 256, big,
+                           None) == -1                                    # too many tiles
+    assert L.wfd_cnn_wgrad(256, 258, 8, 8, 8, 16, 16, 256, 256, 256, big, None) == -1  # dz
+    assert L.wfd_cnn_wgrad(258, 256, 8, 8, 8, 16, 16, 256, 256, 256, big, None) == -1  # in
+    assert L.wfd_cnn_wgrad(256, 256, 8, 8, 8, 16, 16, 256, 256, 256, 16, None) == -4   # work
+    assert L.wfd_cnn_conv(256, 8, 8, 8, 16, 16, 256, None, 0, 260, None, 0, 256, None,
+                          None) == -1                                     # mask alignment
 
 
 def test_smoothing_and_resampling_host_paths():
