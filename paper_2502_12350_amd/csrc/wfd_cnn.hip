@@ -414,7 +414,7 @@ __global__ void __launch_bounds__(CM_THR)
 // bias, as a product with a ones fragment) over every plane of every tile it
 // visits; the grid is persistent, and each wavefront writes one row of
 // partial sums that two fixed-order passes reduce.
-constexpr int WG_TY = 4, WG_ZC = 16, WG_THR = 256, WG_RX = 72, WG_LY = WG_TY + 2;
+constexpr int WG_TY = 4, WG_ZC = 16, WG_THR = 256, WG_RX = 80, WG_LY = WG_TY + 2;
 constexpr int WG_ROW = 27 * 256 + 16;  // partial sums of a wavefront: [tap][co][ci], then db[co]
 constexpr int WG_MAXB = 512, WG_SEG = 32;
 
@@ -600,6 +600,9 @@ __global__ void __launch_bounds__(WG_THR)
                 w = *reinterpret_cast<const u32x4 *>(r);
                 w4 = *reinterpret_cast<const uint32_t *>(r + 8);
               }
+              // keep the shifted fragments in registers: without this the
+              // compiler re-reads w1..w4 from LDS as dwords (bank conflicts)
+              asm volatile("" : "+v"(w), "+v"(w4));
               const u32x4 s1 = {__builtin_amdgcn_alignbyte(w[1], w[0], 2),
                                 __builtin_amdgcn_alignbyte(w[2], w[1], 2),
                                 __builtin_amdgcn_alignbyte(w[3], w[2], 2),
