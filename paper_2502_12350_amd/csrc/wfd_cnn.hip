@@ -69,6 +69,14 @@ constexpr int CM_LX = 66, CM_LY = CM_TY + 2, CM_PLANE = CM_LX * CM_LY, CM_SLOTS 
 // CIN = 16: a plane is CM_PLANE * 2 sixteen-byte items, at most CM_PF per thread
 constexpr int CM_PF = (CM_PLANE * 2 + CM_THR - 1) / CM_THR;
 
+// Block b runs on XCD b mod 8, and each XCD has its own L2: tiles are
+// numbered so that XCD k gets one contiguous range of them, and neighbouring
+// columns (which fetch each other's halo) share an L2.
+__device__ __forceinline__ int xcd_tile(int b, int nb) {
+  const int per = nb / 8, rem = nb % 8, xcd = b % 8, slot = b / 8;
+  return xcd < rem ? xcd * (per + 1) + slot : rem * (per + 1) + (xcd - rem) * per + slot;
+}
+
 inline int cm_tiles(int nx, int ny, int nz) {
   return ((nx + 63) / 64) * ((ny + CM_TY - 1) / CM_TY) * ((nz + CM_ZC - 1) / CM_ZC);
 }
@@ -229,8 +237,9 @@ __global__ void __launch_bounds__(CM_THR)
   constexpr int K = kpad(CIN), NC = K / 32;
   __shared__ __attribute__((aligned(16))) uint16_t lds[CM_SLOTS * CM_PLANE * CIN + 8];
   const int tx = (nx + 63) / 64, ty = (ny + CM_TY - 1) / CM_TY;
-  const int x0 = (blockIdx.x % tx) * 64, y0 = ((blockIdx.x / tx) % ty) * CM_TY;
-  const int zs = (blockIdx.x / (tx * ty)) * CM_ZC, ze = min(zs + CM_ZC, nz);
+  const int tile = xcd_tile(blockIdx.x, gridDim.x);
+  const int x0 = (tile % tx) * 64, y0 = ((tile / tx) % ty) * CM_TY;
+  const int zs = (tile / (tx * ty)) * CM_ZC, ze = min(zs + CM_ZC, nz);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int j = lane & 15, g = lane >> 4;
   // weights: A fragment of every chunk (row co = j, k = 32 c + 8 g + e)
@@ -295,8 +304,9 @@ __global__ void __launch_bounds__(CM_THR)
   constexpr int NA = COUT == 16 ? 3 : 1;         // A fragments per chunk
   __shared__ __attribute__((aligned(16))) uint16_t lds[2 * CM_PLANE * 16 + 8];
   const int tx = (nx + 63) / 64, ty = (ny + CM_TY - 1) / CM_TY;
-  const int x0 = (blockIdx.x % tx) * 64, y0 = ((blockIdx.x / tx) % ty) * CM_TY;
-  const int zs = (blockIdx.x / (tx * ty)) * CM_ZC, ze = min(zs + CM_ZC, nz);
+  const int tile = xcd_tile(blockIdx.x, gridDim.x);
+  const int x0 = (tile % tx) * 64, y0 = ((tile / tx) % ty) * CM_TY;
+  const int zs = (tile / (tx * ty)) * CM_ZC, ze = min(zs + CM_ZC, nz);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int j = lane & 15, g = lane >> 4;
   // A fragments: lane (i + 16 g) holds k' = 32 c + 8 g .. + 7 of row i.
