@@ -1268,7 +1268,9 @@ wfd_status wfd_autotune(wfd_ctx *c, int32_t steps, void *work, size_t work_bytes
   if (steps < 1) return fail(WFD_E_ARG, "steps must be >= 1");
   if (!work) return fail(WFD_E_ARG, "workspace is NULL");
   if ((uintptr_t)work % kAlign) return fail(WFD_E_ARG, "workspace must be 256-byte aligned");
-  const wfd_ckpt one{WFD_CKPT_REVOLVE, 1, 0.0};
+  wfd_ckpt one{};  // one stored pair, no host store
+  one.mode = WFD_CKPT_REVOLVE;
+  one.n_snapshots = 1;
   Work w = work_layout(c, 0, WorkKind::Gradient, &one, 1, work);
   if (work_bytes < w.bytes)
     return fail(WFD_E_NOMEM, "workspace has %zu bytes, %zu needed", work_bytes, w.bytes);
