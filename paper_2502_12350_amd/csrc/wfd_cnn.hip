@@ -295,7 +295,7 @@ __global__ void __launch_bounds__(CM_THR)
 // two-slot LDS ring (the next plane is fetched into registers during the
 // matrix-core work and stored after it, one barrier per plane).
 template <int COUT>
-__global__ void __launch_bounds__(CM_THR)
+__global__ void __launch_bounds__(CM_THR, COUT == 16 ? 3 : 1)
     k_conv16(const uint16_t *__restrict__ in, int nx, int ny, int nz,
              const uint16_t *__restrict__ apk, const float *__restrict__ bias, int relu,
              const uint16_t *__restrict__ mask, const uint16_t *__restrict__ res, int res_c,
@@ -310,19 +310,29 @@ __global__ void __launch_bounds__(CM_THR)
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int j = lane & 15, g = lane >> 4;
   // A fragments: lane (i + 16 g) holds k' = 32 c + 8 g .. + 7 of row i.
-  // COUT = 16: a[kz][c], row i = co.  COUT = 1: a[0][c], row i = kz (rows 3..15 zero).
-  bf16x8 a[NA][NC];
-#pragma unroll
-  for (int q = 0; q < NA; ++q)
+  // COUT = 16: fragment (kz, c), row i = co, kept in LDS (read once per chunk,
+  // a conflict-free 16-byte read per lane), so that the kernel fits 128
+  // registers and 4 waves per SIMD hide the plane loads' latency.
+  // COUT = 1: a[0][c] in registers, row i = kz (rows 3..15 zero).
+  __shared__ __attribute__((aligned(16))) u32x4 alds[COUT == 16 ? NA * NC * 64 : 1];
+  bf16x8 a[COUT == 16 ? 1 : NA][NC];
+  if (COUT == 16) {
+    for (int idx = threadIdx.x; idx < NA * NC * 64; idx += CM_THR) {
+      const int q = idx / (NC * 64), c = (idx / 64) % NC, ln = idx % 64;
+      const int kp = 32 * c + 8 * (ln >> 4);
+      u32x4 d = {0u, 0u, 0u, 0u};
+      if (kp < KP) d = *reinterpret_cast<const u32x4 *>(apk + (size_t)(ln & 15) * K + KP * q + kp);
+      alds[idx] = d;
+    }
+  } else {
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
       const int kp = 32 * c + 8 * g;
-      const int row = COUT == 16 ? j : 0, kz = COUT == 16 ? q : j;
       u32x4 d = {0u, 0u, 0u, 0u};
-      if (kp < KP && (COUT == 16 || j < 3))
-        d = *reinterpret_cast<const u32x4 *>(apk + (size_t)row * K + KP * kz + kp);
-      a[q][c] = __builtin_bit_cast(bf16x8, d);
+      if (kp < KP && j < 3) d = *reinterpret_cast<const u32x4 *>(apk + KP * j + kp);
+      a[0][c] = __builtin_bit_cast(bf16x8, d);
     }
+  }
   {  // prologue: input plane zs - 1
     u32x4 pf[CM_PF];
     cm_fetch16(pf, in, nx, ny, nz, x0, y0, zs - 1);
@@ -367,11 +377,14 @@ __global__ void __launch_bounds__(CM_THR)
         b[tl] = __builtin_bit_cast(bf16x8, v);
       }
       if (COUT == 16) {
+        const bf16x8 a0 = __builtin_bit_cast(bf16x8, alds[(0 * NC + c) * 64 + lane]);
+        const bf16x8 a1 = __builtin_bit_cast(bf16x8, alds[(1 * NC + c) * 64 + lane]);
+        const bf16x8 a2 = __builtin_bit_cast(bf16x8, alds[(2 * NC + c) * 64 + lane]);
 #pragma unroll
         for (int tl = 0; tl < 4; ++tl) {
-          acc[0][tl] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0][c], b[tl], acc[0][tl], 0, 0, 0);
-          acc[1][tl] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[1][c], b[tl], acc[1][tl], 0, 0, 0);
-          acc[2][tl] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[2][c], b[tl], acc[2][tl], 0, 0, 0);
+          acc[0][tl] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, b[tl], acc[0][tl], 0, 0, 0);
+          acc[1][tl] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, b[tl], acc[1][tl], 0, 0, 0);
+          acc[2][tl] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a2, b[tl], acc[2][tl], 0, 0, 0);
         }
       } else {
 #pragma unroll
