@@ -38,17 +38,17 @@ def kernel_hash() -> str:
     return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
 
 
-def committed_traffic(kernel: str):
-    """HBM bytes per launch of `kernel` from the committed counter summary, if it
-    was taken on the current kernel source."""
+def committed_traffic(kernel: str, density: str):
+    """HBM bytes per launch of `kernel` ("variable" or "constant" density) from
+    the committed counter summary, if it was taken on the current kernel source."""
     path = os.path.join(ROOT, "profiles", "hbm_traffic.md")
     if not os.path.exists(path):
         return None
-    pat = re.compile(r"^TRAFFIC kernel=(\S+) source=(\S+) bytes_per_launch=(\d+)")
+    pat = re.compile(r"^TRAFFIC kernel=(\S+) density=(\S+) source=(\S+) bytes_per_launch=(\d+)")
     for line in open(path):
         m = pat.match(line.strip())
-        if m and m.group(1) == kernel and m.group(2) == kernel_hash():
-            return int(m.group(3))
+        if m and m.group(1) == kernel and m.group(2) == density and m.group(3) == kernel_hash():
+            return int(m.group(4))
     return None
 
 
@@ -778,6 +778,8 @@ def main():
     ap.add_argument("--nt", type=int, default=0, help="override the number of time steps")
     ap.add_argument("--snapshots", type=int, default=96)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--constant-density", action="store_true",
+                    help="drop the density model (constant-density kernels; not the headline)")
     ap.add_argument("--copy-probe", action="store_true")
     ap.add_argument("--stream-probe", action="store_true",
                     help="achievable streaming bandwidth of plain float4 kernels")
@@ -847,7 +849,7 @@ def main():
     grid = GridSpec(**w.grid_kwargs())
     dev = torch.device("cuda", 0)
     vel = torch.from_numpy(w.vel).to(dev)
-    rho = None if w.rho is None else torch.from_numpy(w.rho).to(dev)
+    rho = None if (w.rho is None or args.constant_density) else torch.from_numpy(w.rho).to(dev)
     wav = torch.from_numpy(w.wavelet).to(dev)
     nrec = len(w.receivers)
     print(f"[bench] workload {w.name}: model {w.nx}x{w.ny}x{w.nz}, padded "
@@ -912,7 +914,7 @@ def main():
     dom_name = max(kern, key=lambda n: kern[n]["share"])
     dom = kern[dom_name]
     lib_kernel = {"fd_step": "k_forward", "adjoint_imaging": "k_adjoint"}[dom_name]
-    traffic = committed_traffic(lib_kernel)
+    traffic = committed_traffic(lib_kernel, "variable" if vd else "constant")
     out = {
         "metric": "Gpt/s & %HBM peak (fwd/adjoint 8th-order stencil); FWI misfit cut per GPU-s",
         "value": round(value, 3),
@@ -926,7 +928,8 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": f"one-shot forward + adjoint gradient pass, variable density, "
+        "config": {"workload": f"one-shot forward + adjoint gradient pass, "
+                               f"{'variable' if vd else 'constant'} density, "
                                f"{w.nx}x{w.ny}x{w.nz} model + {w.border}-cell sponge, "
                                f"{w.nt} steps, {nrec} receivers",
                    "padded_points": pts, "nt": w.nt, "nrec": nrec,
