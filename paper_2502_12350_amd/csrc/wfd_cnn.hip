@@ -228,7 +228,7 @@ __device__ __forceinline__ void cm_epilogue(const f32x4 *acc, int nx, int ny, in
 }
 
 template <int CIN, int COUT>
-__global__ void __launch_bounds__(CM_THR)
+__global__ void __launch_bounds__(CM_THR, 4)  // 4 waves per SIMD fit without spills; 5 spill
     k_conv(const uint16_t *__restrict__ in, int nx, int ny, int nz,
            const uint16_t *__restrict__ apk, const float *__restrict__ bias, int relu,
            const uint16_t *__restrict__ mask, const uint16_t *__restrict__ res, int res_c,
