@@ -76,21 +76,52 @@ class WaveFn:
         return _Fn.apply(vel)
 
 
+def _save_shot_state(path, key, done, grad, misfit, illum):
+    """Partial sums of one gradient evaluation after `done` shots."""
+    import os
+    tmp = path + ".tmp.npz"
+    np.savez(tmp, key=np.array(key), done=np.int64(done), grad=grad.cpu().numpy(),
+             misfit=np.float64(misfit.item()),
+             illum=illum.cpu().numpy() if illum is not None else np.zeros(0, np.float32))
+    os.replace(tmp, path)
+
+
 def evaluate(prop: Propagator, grid: GridSpec, vel, rho, shots: Shots, ckpt="auto",
-             illum=None, zero_top_planes: int = 0, smoothing=None):
+             illum=None, zero_top_planes: int = 0, smoothing=None, shot_state=None,
+             shot_key: str = "", shot_hook=None):
     """(misfit, dJ/dv) summed over shots; illum (if given) accumulates sum (w^n)^2.
     smoothing = (mode, lengths) applies the paper's gradient smoothing ("laplace"
     or "bessel", lengths (x, y, z) in metres) before the top planes are zeroed
-    (GradientPreconditioning, then ZeroesNearSurface, as in Alg. 3)."""
+    (GradientPreconditioning, then ZeroesNearSurface, as in Alg. 3).
+
+    shot_state: a file that receives the partial sums (gradient, misfit,
+    illumination) after every shot, tagged with shot_key; an evaluation with
+    the same key that finds it continues after the shots it holds, and ends
+    with bitwise the sums of an uninterrupted one (shots are added in the same
+    order).  shot_hook(shot_key, s), if given, is called after shot s."""
+    import os
     import torch
     prop.set_model(grid, vel.contiguous(), rho)
     misfit = torch.zeros((), dtype=torch.float64, device=prop.device)
     grad = torch.zeros_like(vel)
-    for s in range(len(shots)):
+    first = 0
+    if shot_state is not None and os.path.exists(shot_state):
+        with np.load(shot_state, allow_pickle=False) as z:
+            if str(z["key"]) == shot_key:
+                first = int(z["done"])
+                grad.copy_(torch.from_numpy(z["grad"]))
+                misfit.fill_(float(z["misfit"]))
+                if illum is not None:
+                    illum.copy_(torch.from_numpy(z["illum"]))
+    for s in range(first, len(shots)):
         rec = shots.receivers[s]
         ck = auto_checkpoint(prop, len(rec)) if ckpt == "auto" else ckpt
         prop.gradient(shots.wavelet, shots.sources[s], rec, shots.dobs[s], ckpt=ck, grad=grad,
                       misfit=misfit, illum=illum)
+        if shot_state is not None:
+            _save_shot_state(shot_state, shot_key, s + 1, grad, misfit, illum)
+        if shot_hook is not None:
+            shot_hook(shot_key, s)
     if smoothing is not None:
         from .api import smooth
         mode, lengths = smoothing
@@ -209,7 +240,7 @@ def fwi(prop: Propagator, grid: GridSpec, v0, rho, shots: Shots, *, n_iter: int 
         method: str = "sd", bounds: Optional[Tuple[float, float]] = None,
         max_rel_step: float = 0.02, eps_illum: float = 1.0e-3, memory: int = 5,
         ckpt="auto", zero_top_planes: int = 0, precond=None, progress=None, smoothing=None,
-        state_file: Optional[str] = None):
+        state_file: Optional[str] = None, shot_hook=None):
     """Alg. 2: repeat {gradient, model update} for n_iter iterations.
 
     method "sd": steepest descent on the illumination-compensated gradient;
@@ -228,7 +259,11 @@ def fwi(prop: Propagator, grid: GridSpec, v0, rho, shots: Shots, *, n_iter: int 
     The loop state (model, gradient, illumination, L-BFGS pairs, step memory,
     history) is written there after every iteration, atomically; if the file
     exists when fwi starts, the run continues from it and ends exactly as an
-    uninterrupted run would.
+    uninterrupted run would.  Within a gradient evaluation the partial sums
+    are also kept after every shot (state_file + ".shot.npz", keyed by the
+    iteration), so a failure in the middle of one costs only the shot that
+    was running.  shot_hook(key, s) is called after each shot (monitoring;
+    the tests use it to fail on purpose).
     """
     import torch
     trace = FwiTrace(method)
@@ -247,10 +282,13 @@ def fwi(prop: Propagator, grid: GridSpec, v0, rho, shots: Shots, *, n_iter: int 
     v = _project(v0.clone(), bounds)
     illum = torch.zeros_like(v)
 
-    def grad_at(vv):
+    shot_state = None if state_file is None else state_file + ".shot.npz"
+
+    def grad_at(vv, key):
         illum.zero_()
         J, g = timed(evaluate, prop, grid, vv, rho, shots, ckpt=ckpt, illum=illum,
-                     zero_top_planes=zero_top_planes, smoothing=smoothing)
+                     zero_top_planes=zero_top_planes, smoothing=smoothing,
+                     shot_state=shot_state, shot_key=key, shot_hook=shot_hook)
         trace.n_gradients += 1
         return float(J.item()), g
 
@@ -267,7 +305,7 @@ def fwi(prop: Propagator, grid: GridSpec, v0, rho, shots: Shots, *, n_iter: int 
         illum.copy_(il)
         clock[0] = trace.gpu_seconds[-1]
     else:
-        J, g = grad_at(v)
+        J, g = grad_at(v, "0")
         trace.record(clock[0], J)
         if state_file is not None:
             _save_state(state_file, 0, v, g, illum, J, S, Y, dv_prev, trace)
@@ -356,7 +394,7 @@ def fwi(prop: Propagator, grid: GridSpec, v0, rho, shots: Shots, *, n_iter: int 
             trace.n_network += int(used)
             dv_prev = alpha * float(d.abs().max())
         v_new = _project(v + alpha * d, bounds)
-        J_new, g_new = grad_at(v_new)
+        J_new, g_new = grad_at(v_new, str(it + 1))
         if method == "lbfgs":
             s_, y_ = v_new - v, g_new - g
             if _dot(s_, y_) > 0:

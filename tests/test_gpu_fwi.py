@@ -180,6 +180,41 @@ def test_fwi_restart_from_state_file_matches_uninterrupted_run(method, tmp_path)
     assert float(v.min()) >= 1500.0                                   # lower bound only
 
 
+def test_fwi_restart_after_a_failure_in_the_middle_of_a_gradient(tmp_path):
+    """Fault tolerance at shot granularity: a run that fails after shot 1 of
+    the gradient evaluation of iteration 2 (four shots) and is restarted from
+    its state files continues with shot 2 of that evaluation, and ends bitwise
+    where an uninterrupted run ends."""
+    torch = gpu_or_skip()
+    from paper_2502_12350_amd import Propagator
+    from paper_2502_12350_amd.fwi import fwi
+    w, g, shots, _ = _small_case(torch)
+    assert len(shots) == 4
+    P = Propagator(0)
+    v0 = torch.from_numpy(w.vel).cuda()
+    kw = dict(method="sd", bounds=(1500.0, 4500.0), zero_top_planes=6, n_iter=3)
+    v_ref, tr_ref = fwi(P, g, v0, None, shots, state_file=str(tmp_path / "a.npz"), **kw)
+
+    class Failure(Exception):
+        pass
+
+    def fail(key, s):
+        if key == "2" and s == 1:
+            raise Failure()
+
+    state = str(tmp_path / "b.npz")
+    with pytest.raises(Failure):
+        fwi(P, g, v0, None, shots, state_file=state, shot_hook=fail, **kw)
+    seen = []
+    v, tr = fwi(P, g, v0, None, shots, state_file=state,
+                shot_hook=lambda key, s: seen.append((key, s)), **kw)
+    torch.cuda.synchronize()
+    say(f"[fwi shot restart] shots run after the restart: {seen}")
+    assert seen[0] == ("2", 2)                      # shots 0 and 1 came from the state file
+    assert torch.equal(v, v_ref)
+    assert tr.misfit == tr_ref.misfit
+
+
 def test_gradient_workload_eight_shots_against_central_differences():
     """The gradient workload's sizes (200x200x160, 8 shots, 1200 steps, 2500
     receivers each, binomial checkpointing with 20 stored pairs): the
