@@ -116,9 +116,11 @@ class Preconditioner:
         the illumination-compensated gradient and the illumination, each scaled."""
         torch = self.torch
         out = torch.empty(tuple(grad.shape) + (2,), dtype=torch.bfloat16, device=self.device)
-        check(self.L.wfd_cnn_pack_input(_p(grad.contiguous()), _p(illum.contiguous()),
-                                        grad.numel(), eps_illum, _p(out), _p(self._reduce),
-                                        self._reduce.numel(), self._stream()))
+        # contiguous copies (if any) are held until the call: a copy freed
+        # before it could hand its memory to the next one
+        g, il = grad.contiguous(), illum.contiguous()
+        check(self.L.wfd_cnn_pack_input(_p(g), _p(il), grad.numel(), eps_illum, _p(out),
+                                        _p(self._reduce), self._reduce.numel(), self._stream()))
         return out
 
     def forward(self, x, keep: bool = False):
@@ -139,8 +141,9 @@ class Preconditioner:
         nz, ny, nx = y.shape
         loss = torch.zeros((), dtype=torch.float64, device=self.device)
         dz = torch.empty((nz, ny, nx, 1), dtype=torch.bfloat16, device=self.device)
-        check(self.L.wfd_cnn_mse(_p(y), _p(target.contiguous()), y.numel(), _p(dz), _p(loss),
-                                 _p(self._reduce), self._reduce.numel(), self._stream()))
+        tc = target.contiguous()
+        check(self.L.wfd_cnn_mse(_p(y), _p(tc), y.numel(), _p(dz), _p(loss), _p(self._reduce),
+                                 self._reduce.numel(), self._stream()))
         nb = C.c_size_t()
         check(self.L.wfd_cnn_wgrad_workspace_bytes(nx, ny, nz, C.byref(nb)))
         work = torch.empty(nb.value, dtype=torch.uint8, device=self.device)

@@ -193,6 +193,42 @@ def test_convolution_over_several_z_chunks(li, flip):
         assert e <= TOL
 
 
+@pytest.mark.parametrize("shape", [(1, 1, 3), (2, 5, 1), (3, 1, 65), (17, 4, 64)])
+def test_tiny_and_degenerate_volumes(shape):
+    # one plane, one row, one voxel wide, exactly one tile: every convolution
+    # shape (forward, masked data gradient) and every weight gradient
+    torch = gpu_or_skip()
+    import ctypes as C
+    from paper_2502_12350_amd import _lib
+    nz, ny, nx = shape
+    say(f"[cnn tiny] {nx}x{ny}x{nz}")
+    P, Ws, bs = _net(torch, seed=3)
+    rng = np.random.default_rng(90 + nz + ny + nx)
+    L = _lib.lib()
+    nb = C.c_size_t()
+    _lib.check(L.wfd_cnn_wgrad_workspace_bytes(nx, ny, nz, C.byref(nb)))
+    work = torch.empty(nb.value, dtype=torch.uint8, device="cuda")
+    for li, (ci, co) in enumerate([(2, 16), (16, 16), (16, 16), (16, 1)]):
+        x = cnn.bf16(rng.standard_normal((nz, ny, nx, ci)))
+        got = _np(P.conv(_bf(torch, x), li, relu=False, out_f32=True)).reshape(nz, ny, nx, co)
+        assert rel_l2(got, cnn.conv3d(x, Ws[li], bs[li])) <= TOL
+        dz = cnn.bf16(rng.standard_normal((nz, ny, nx, co)))
+        if li > 0:
+            got = _np(P.conv(_bf(torch, dz), li, relu=False, flip=True, bias=False,
+                             out_f32=True)).reshape(nz, ny, nx, ci)
+            assert rel_l2(got, cnn.conv3d_dgrad(dz, Ws[li])) <= TOL
+        if li != 2:
+            dw = torch.full((27, ci, co), float("nan"), device="cuda")
+            db = torch.full((co,), float("nan"), device="cuda")
+            xd, dzd = _bf(torch, x), _bf(torch, dz)  # alive until the kernels have run
+            _lib.check(L.wfd_cnn_wgrad(xd.data_ptr(), dzd.data_ptr(), nx, ny, nz, ci, co,
+                                       dw.data_ptr(), db.data_ptr(), work.data_ptr(), nb.value,
+                                       None))
+            torch.cuda.synchronize()
+            assert rel_l2(_np(dw), cnn.conv3d_wgrad(x, dz).reshape(27, ci, co)) <= TOL
+            assert rel_l2(_np(db), dz.reshape(-1, co).astype(np.float64).sum(axis=0)) <= TOL
+
+
 def test_mse_adam_and_input_packing_match_oracle():
     torch = gpu_or_skip()
     import ctypes as C
@@ -219,9 +255,9 @@ def test_mse_adam_and_input_packing_match_oracle():
     wo, mo, vo = w.astype(np.float64), np.zeros(1000), np.zeros(1000)
     for step in (1, 2, 3):
         g = rng.standard_normal(1000).astype(np.float32)
-        _lib.check(L.wfd_cnn_adam(wd.data_ptr(), torch.from_numpy(g).cuda().data_ptr(),
-                                  md.data_ptr(), vd.data_ptr(), 1000, 1e-2, 0.9, 0.999, 1e-8,
-                                  step, None))
+        gd = torch.from_numpy(g).cuda()  # alive until the kernel has run
+        _lib.check(L.wfd_cnn_adam(wd.data_ptr(), gd.data_ptr(), md.data_ptr(), vd.data_ptr(),
+                                  1000, 1e-2, 0.9, 0.999, 1e-8, step, None))
         torch.cuda.synchronize()
         wo, mo, vo = cnn.adam_step(wo, g.astype(np.float64), mo, vo, step, 1e-2)
     assert rel_l2(_np(wd), wo) <= 1e-6
