@@ -804,8 +804,8 @@ def main():
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus > 1 or world > 1:
-        print("bench.py: this build measures one GPU only (one shot per GPU; the multi-GPU "
-              "design shards shots and all-reduces the gradient, see DESIGN.md) -- "
+        print("bench.py: one GPU only (one shot per GPU; a multi-GPU run would shard the "
+              "shots and all-reduce the gradient once per evaluation) -- "
               f"--gpus {args.gpus} is not supported", file=sys.stderr, flush=True)
         sys.exit(2)
     if args.stream_probe:

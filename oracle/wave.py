@@ -20,7 +20,7 @@ What it computes (paper references are to arXiv 2502.12350, "Mamute"):
 * §2.2.2: volumes are [z][y][x] with x fastest; positions are metres in
   (x, y, z) order; seismograms are trace-major [rec][ns].
 
-Readings taken where the paper is silent (each is listed in the design doc):
+Readings taken where the paper is silent:
 
 R1  8th-order central second-derivative weights (-205/72, 8/5, -1/5, 8/315,
     -1/560).
