@@ -229,6 +229,61 @@ def test_tiny_and_degenerate_volumes(shape):
             assert rel_l2(_np(db), dz.reshape(-1, co).astype(np.float64).sum(axis=0)) <= TOL
 
 
+def test_full_size_256_sampled_outputs_and_weight_gradient():
+    # the 256^3 volume of the kernel benchmark, in its launch configuration:
+    # the 16 -> 16 convolution and its data gradient at 2000 sampled voxels
+    # (plus the 8 corners), each against the oracle on the voxel's 3x3x3
+    # neighbourhood (zero outside the volume); the 16 -> 16 weight gradient in
+    # full against the oracle's FP64 sums over all 16.7 M voxels
+    torch = gpu_or_skip()
+    import ctypes as C
+    from paper_2502_12350_amd import _lib
+    n = 256
+    P, Ws, bs = _net(torch, seed=5)
+    rng = np.random.default_rng(256)
+    x = cnn.bf16(rng.standard_normal((n, n, n, 16), dtype=np.float32))
+    xd = _bf(torch, x)
+    y = P.conv(xd, 1, relu=False, out_f32=True)
+    dg = P.conv(xd, 1, relu=False, flip=True, bias=False, out_f32=True)
+    torch.cuda.synchronize()
+    pts = [tuple(int(v) for v in rng.integers(0, n, 3)) for _ in range(2000)]
+    pts += [(a, b, c) for a in (0, n - 1) for b in (0, n - 1) for c in (0, n - 1)]
+    idx = torch.tensor(pts, device="cuda")
+    gy = y[idx[:, 0], idx[:, 1], idx[:, 2]].double().cpu().numpy()
+    gd = dg[idx[:, 0], idx[:, 1], idx[:, 2]].double().cpu().numpy()
+    worst_y = worst_d = 0.0
+    for i, (z, yy, xx) in enumerate(pts):
+        sub = np.zeros((3, 3, 3, 16))
+        z0, z1, y0, y1, x0, x1 = max(z - 1, 0), min(z + 2, n), max(yy - 1, 0), min(yy + 2, n), \
+            max(xx - 1, 0), min(xx + 2, n)
+        sub[z0 - z + 1:z1 - z + 1, y0 - yy + 1:y1 - yy + 1, x0 - xx + 1:x1 - xx + 1] = \
+            x[z0:z1, y0:y1, x0:x1]
+        ry = cnn.conv3d(sub, Ws[1], bs[1])[1, 1, 1]
+        rd = cnn.conv3d_dgrad(sub, Ws[1])[1, 1, 1]
+        worst_y = max(worst_y, float(np.linalg.norm(gy[i] - ry) / np.linalg.norm(ry)))
+        worst_d = max(worst_d, float(np.linalg.norm(gd[i] - rd) / np.linalg.norm(rd)))
+    say(f"[cnn 256^3] worst sampled rel error: conv {worst_y:.2e}, data gradient {worst_d:.2e}")
+    assert worst_y <= TOL and worst_d <= TOL
+    del y, dg
+    dz = cnn.bf16(rng.standard_normal((n, n, n, 16), dtype=np.float32))
+    dzd = _bf(torch, dz)
+    L = _lib.lib()
+    nb = C.c_size_t()
+    _lib.check(L.wfd_cnn_wgrad_workspace_bytes(n, n, n, C.byref(nb)))
+    work = torch.empty(nb.value, dtype=torch.uint8, device="cuda")
+    dw = torch.full((27, 16, 16), float("nan"), device="cuda")
+    db = torch.full((16,), float("nan"), device="cuda")
+    _lib.check(L.wfd_cnn_wgrad(xd.data_ptr(), dzd.data_ptr(), n, n, n, 16, 16, dw.data_ptr(),
+                               db.data_ptr(), work.data_ptr(), nb.value, None))
+    torch.cuda.synchronize()
+    e = rel_l2(_np(dw), cnn.conv3d_wgrad(x, dz).reshape(27, 16, 16))
+    eb = rel_l2(_np(db), dz.reshape(-1, 16).sum(axis=0))
+    say(f"  weight gradient rel-L2 {e:.2e}, bias gradient {eb:.2e}")
+    # FP32 partial sums over up to 8 tiles x 16 planes x 64 voxels per wavefront,
+    # then 2048 rows: the bound of the 200x130x70 case
+    assert e <= 2e-5 and eb <= 2e-5
+
+
 def test_mse_adam_and_input_packing_match_oracle():
     torch = gpu_or_skip()
     import ctypes as C
