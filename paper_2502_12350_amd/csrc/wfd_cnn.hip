@@ -17,12 +17,13 @@
 // Convolution as an implicit GEMM: for a row of 16 output voxels,
 // D[co][voxel] = sum_k A[co][k] X[k][voxel] with X[tap * CIN + ci][voxel] =
 // input[voxel + offset(tap)][ci].  A convolution block marches a 64 x 4
-// output tile along z with a ring of input planes in LDS (k_conv); each of its
-// 4 wavefronts computes one 64-voxel output row as four 16 x 16 tiles with the
-// packed weights held in registers.  The data gradient is the same kernel on
-// flipped, transposed weights; the weight gradient marches the same tiles
-// and reduces over voxels with the voxel index as the matrix-core K
-// dimension.
+// output tile along z with a ring of input planes in LDS; each of its 4
+// wavefronts computes one 64-voxel output row as four 16 x 16 tiles (k_conv
+// for one or two input channels, k_conv16 for 16, input-plane major).  The
+// data gradient is the same kernel on flipped, transposed weights; the weight
+// gradient marches the same tiles and reduces over voxels with the voxel
+// index as the matrix-core K dimension (k_wgrad, and k_wgrad_pack for the
+// layers with one output or two input channels).
 #include <hip/hip_runtime.h>
 
 #include <stdint.h>
@@ -432,7 +433,7 @@ __global__ void __launch_bounds__(CM_THR, COUT == 16 ? 3 : 1)
 // the eight consecutive voxels of one channel that a lane contributes to a
 // fragment are one aligned 16-byte read.  A row stride of 40 dwords makes
 // these reads free of bank conflicts (measured: strides of 36, 44 and 52
-// dwords cost 4 extra cycles per read); the two planes rings then take 80 KB,
+// dwords cost 4 extra cycles per read); the two plane rings then take 80 KB,
 // and two blocks still fit a CU's LDS.  For the three x taps of a
 // (kz, ky) pair a lane reads 10 elements once and shifts them in registers.
 // Each wavefront owns one output row and accumulates all 27 taps (and the
