@@ -113,8 +113,9 @@ typedef struct {
   double mem_fraction;  /* (0, 1]; like the paper's check_mem (default 0.8)    */
   void *host_store;     /* HOST: page-locked host buffer (hipHostMalloc, or a
                            torch tensor made with pin_memory=True) of at least
-                           wfd_host_store_bytes(); slot m-1 receives w^m on the
-                           padded grid as [Nz][Ny][pitch] FP32, pitch = Nx
+                           wfd_host_store_bytes(); slot m-1 receives 2^e w^m
+                           (e: the call's field exponent, wfd_gradient_opts) on
+                           the padded grid as [Nz][Ny][pitch] FP32, pitch = Nx
                            rounded up to a multiple of 64 (the columns past
                            Nx are padding).  Other modes: ignored.            */
   uint64_t host_bytes;  /* HOST: size of host_store in bytes                   */
@@ -210,6 +211,40 @@ wfd_status wfd_gradient(wfd_ctx *ctx, const float *wavelet_dev, const double src
                         const wfd_ckpt *ckpt, float *seis_dev_or_null, double *misfit_dev,
                         float *grad_dev, float *illum_dev_or_null, void *work_dev,
                         size_t work_bytes);
+
+/* Options of wfd_gradient_ex (a zeroed struct gives wfd_gradient's behaviour).
+ *
+ * Field scaling.  The step kernels carry every field times 2^e, an exact
+ * power of two chosen per call on the device so that the source term
+ * sigma max|f| 2^e lies in [1, 2) (sigma = dt^2 / (hx hy hz sqrt(rho_src)),
+ * Eq. 1 source term; |e| <= 120).  The time stepping is linear in the field,
+ * so the mantissas are those of an unscaled run, while a quiet source or a
+ * coarse grid no longer drives FP32 products into the subnormal range.
+ * Seismograms, final states and the misfit are returned in physical units.
+ * The gradient and the illumination are quadratic in the source amplitude
+ * and can lie below FP32's range on their own; they are returned times
+ * 2^out_exp2 (exact). */
+typedef struct {
+  float *wavelet_grad_dev;  /* [nt] FP32 device, accumulated (+=) 2^out_exp2 dJ/df[n],
+                               the gradient of the misfit with respect to wavelet
+                               sample n (the transpose of the wavelet -> data map
+                               applied to the residual: sigma psi^(n+1)[src] /
+                               k_src), or NULL                                    */
+  int32_t out_exp2;         /* grad_dev, illum_dev_or_null and wavelet_grad_dev
+                               accumulate 2^out_exp2 times their quantity; 0 =
+                               physical units; |out_exp2| <= 240 (else WFD_E_ARG) */
+  int32_t *field_exp2_dev;  /* device int32 that receives the call's field
+                               exponent e, or NULL                                */
+} wfd_gradient_opts;
+
+/* wfd_gradient with options (NULL = wfd_gradient).  With WFD_CKPT_HOST the
+ * host store holds the scaled states 2^e w^m (e as in field_exp2_dev). */
+wfd_status wfd_gradient_ex(wfd_ctx *ctx, const float *wavelet_dev, const double src_xyz[3],
+                           int32_t nrec, const double *rec_xyz, const float *dobs_dev,
+                           const wfd_ckpt *ckpt, float *seis_dev_or_null, double *misfit_dev,
+                           float *grad_dev, float *illum_dev_or_null,
+                           const wfd_gradient_opts *opts_or_null, void *work_dev,
+                           size_t work_bytes);
 
 /* ZeroesNearSurface (Alg. 3; zeroes_nplanes_gradient in §3): set the top
  * `zero_top_planes` z-planes of grad_dev [nz][ny][nx] to zero. */

@@ -44,6 +44,11 @@ class wfd_tuning(C.Structure):
                 ("adj_variant", C.c_int32), ("adj_rounds", C.c_int32)]
 
 
+class wfd_gradient_opts(C.Structure):
+    _fields_ = [("wavelet_grad_dev", C.c_void_p), ("out_exp2", C.c_int32),
+                ("field_exp2_dev", C.c_void_p)]
+
+
 class WfdError(RuntimeError):
     def __init__(self, status: int, message: str):
         self.status = status
@@ -67,6 +72,8 @@ _SIGS = {
     "wfd_misfit_workspace_bytes": (C.c_int, [_P, C.c_int32, C.POINTER(C.c_size_t)]),
     "wfd_gradient": (C.c_int, [_P, _P, _D3, C.c_int32, _D3, _P, C.POINTER(wfd_ckpt), _P, _P,
                                _P, _P, _P, C.c_size_t]),
+    "wfd_gradient_ex": (C.c_int, [_P, _P, _D3, C.c_int32, _D3, _P, C.POINTER(wfd_ckpt), _P, _P,
+                                  _P, _P, C.POINTER(wfd_gradient_opts), _P, C.c_size_t]),
     "wfd_gradient_finish": (C.c_int, [_P, _P, C.c_int32]),
     "wfd_set_tuning": (C.c_int, [_P, C.POINTER(wfd_tuning)]),
     "wfd_get_tuning": (C.c_int, [_P, C.POINTER(wfd_tuning)]),

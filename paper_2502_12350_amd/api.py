@@ -325,8 +325,14 @@ class Propagator:
         return (misfit, out_seis) if seis else misfit
 
     def gradient(self, wavelet, src_xyz, rec_xyz, dobs, *, ckpt="full", grad=None, misfit=None,
-                 illum=None, seis: bool = False):
-        """Accumulate one shot's misfit and dJ/dv; returns (misfit, grad[, seis])."""
+                 illum=None, seis: bool = False, wavelet_grad=None, out_exp2: int = 0,
+                 field_exp2=None):
+        """Accumulate one shot's misfit and dJ/dv; returns (misfit, grad[, seis]).
+
+        wavelet_grad: optional [nt] float32 device tensor, += dJ/df (the
+        gradient with respect to the wavelet samples); out_exp2: grad, illum
+        and wavelet_grad accumulate 2^out_exp2 times their value; field_exp2:
+        optional int32 device scalar that receives the call's field exponent."""
         torch = self.torch
         g = self.grid
         if g is None:
@@ -348,13 +354,18 @@ class Propagator:
             self._dev(illum, "illum", (g.nz, g.ny, g.nx), torch.float32)
         out_seis = (torch.empty((nrec, g.nt), dtype=torch.float32, device=self.device)
                     if seis else None)
+        if wavelet_grad is not None:
+            self._dev(wavelet_grad, "wavelet_grad", (g.nt,), torch.float32)
+        if field_exp2 is not None:
+            self._dev(field_exp2, "field_exp2", (), torch.int32)
+        opts = _lib.wfd_gradient_opts(_ptr(wavelet_grad), int(out_exp2), _ptr(field_exp2))
         ck = _ckpt(("host", self._host_store()) if isinstance(ckpt, str) and ckpt == "host"
                    else ckpt)
         wptr, wbytes = self._workspace(self.workspace_bytes(nrec, ck))
         self._sync_stream()
-        check(self.L.wfd_gradient(self._ctx, _ptr(wavelet), _dptr(src), nrec, _dptr(rec),
-                                  _ptr(dobs), C.byref(ck), _ptr(out_seis), _ptr(misfit),
-                                  _ptr(grad), _ptr(illum), wptr, wbytes))
+        check(self.L.wfd_gradient_ex(self._ctx, _ptr(wavelet), _dptr(src), nrec, _dptr(rec),
+                                     _ptr(dobs), C.byref(ck), _ptr(out_seis), _ptr(misfit),
+                                     _ptr(grad), _ptr(illum), C.byref(opts), wptr, wbytes))
         return (misfit, grad, out_seis) if seis else (misfit, grad)
 
     def gradient_finish(self, grad, zero_top_planes: int):

@@ -328,7 +328,8 @@ struct Work {
   int *col_start, *ent_z, *ent_rp, *perm, *rec_model_idx;
   int64_t *rec_idx;
   // device-computed scalars / scales
-  float *sigma, *rec_scale, *rec_adj;
+  wfd::ShotScale *scale;  // sigma 2^e and the field exponent e
+  float *rec_scale, *rec_adj;
   float *seis_tm;
   float *W1, *W2;
   wfd::WindowStep *wins;  // batch step descriptors (two parities x kMaxBatch)
@@ -418,7 +419,7 @@ Work work_layout(const wfd_ctx *c, int nrec, WorkKind kind, const wfd_ckpt *ck, 
   w.perm = cv.take<int>((size_t)std::max(nrec, 1));
   w.rec_model_idx = cv.take<int>((size_t)std::max(nrec, 1));
   w.rec_idx = cv.take<int64_t>((size_t)std::max(nrec, 1));
-  w.sigma = cv.take<float>(1);
+  w.scale = cv.take<wfd::ShotScale>(1);
   w.rec_scale = cv.take<float>((size_t)std::max(nrec, 1));
   w.rec_adj = cv.take<float>((size_t)std::max(nrec, 1));
   w.seis_tm = cv.take<float>((size_t)c->grid.nt * std::max(nrec, 1));
@@ -478,8 +479,8 @@ int64_t lin(const wfd_ctx *c, const int32_t ijk[3]) {
 }
 
 // Map positions, group receivers by column, upload tables, launch shot setup.
-wfd_status prepare_shot(wfd_ctx *c, const double src_xyz[3], int nrec, const double *rec_xyz,
-                        const Work &w, int64_t &src_idx) {
+wfd_status prepare_shot(wfd_ctx *c, const float *wavelet, const double src_xyz[3], int nrec,
+                        const double *rec_xyz, const Work &w, int64_t &src_idx) {
   const wfd_grid &g = c->grid;
   int32_t s[3];
   if (!wfd::map_position(g, src_xyz, s))
@@ -566,9 +567,9 @@ wfd_status prepare_shot(wfd_ctx *c, const double src_xyz[3], int nrec, const dou
   const double dt2_over_h3 = g.dt * g.dt / (g.dx * g.dy * g.dz);
   {
     Timed t(c, WFD_K_OTHER);
-    HIP_TRY(wfd::launch_shot_setup(c->k, c->vd ? c->sqrt_rho : nullptr, g.border, g.nx, g.ny,
-                                   src_idx, src_model, dt2_over_h3, w.rec_idx, w.rec_model_idx,
-                                   nrec, w.sigma, w.rec_scale, w.rec_adj, c->stream));
+    HIP_TRY(wfd::launch_shot_setup(c->k, c->vd ? c->sqrt_rho : nullptr, src_idx, src_model,
+                                   dt2_over_h3, wavelet, g.nt, w.rec_idx, w.rec_model_idx, nrec,
+                                   w.scale, w.rec_scale, w.rec_adj, c->stream));
   }
   return WFD_OK;
 }
@@ -863,13 +864,13 @@ wfd_status forward_core(wfd_ctx *c, const float *wavelet, const double src_xyz[3
     return fail(WFD_E_NOMEM, "workspace has %zu bytes, %zu needed", work_bytes, w.bytes);
   ScopedDevice sd(c->device);
   int64_t src_idx = 0;
-  s = prepare_shot(c, src_xyz, nrec, rec_xyz, w, src_idx);
+  s = prepare_shot(c, wavelet, src_xyz, nrec, rec_xyz, w, src_idx);
   if (s != WFD_OK) return s;
   if ((s = zero(c, w.W1, c->vol)) != WFD_OK) return s;
   if ((s = zero(c, w.W2, c->vol)) != WFD_OK) return s;
   const wfd::StepGrid g = step_grid(c);
   const wfd::RecTable rt = rec_table(w, nrec);
-  const wfd::Source src{src_idx, w.sigma, wavelet};
+  const wfd::Source src{src_idx, &w.scale->sigma, wavelet};
   if (c->cpml)
     for (float *m : w.mem)
       if ((s = zero(c, m, c->vol)) != WFD_OK) return s;
@@ -893,19 +894,19 @@ wfd_status forward_core(wfd_ctx *c, const float *wavelet, const double src_xyz[3
     int np = 0;
     {
       Timed t(c, WFD_K_OTHER);
-      HIP_TRY(wfd::launch_residual(w.seis_tm, dobs, w.rec_adj, nrec, c->grid.nt, w.res_tm,
-                                   w.partial, &np, c->stream));
+      HIP_TRY(wfd::launch_residual(w.seis_tm, dobs, w.rec_adj, w.scale, nrec, c->grid.nt,
+                                   w.res_tm, w.partial, &np, c->stream));
     }
     Timed t(c, WFD_K_OTHER);
     HIP_TRY(wfd::launch_sum_partials(w.partial, np, misfit, c->stream));
   }
-  if (final_dev) {
-    const size_t row = (size_t)c->Nx * sizeof(float);
+  if (final_dev) {  // the last two states, back from 2^e w to w
     const size_t dense = (size_t)c->Nx * c->Ny * c->Nz;
-    HIP_TRY(hipMemcpy2DAsync(final_dev, row, cur, (size_t)c->pitch * 4, row,
-                             (size_t)c->Ny * c->Nz, hipMemcpyDeviceToDevice, c->stream));
-    HIP_TRY(hipMemcpy2DAsync(final_dev + dense, row, prev, (size_t)c->pitch * 4, row,
-                             (size_t)c->Ny * c->Nz, hipMemcpyDeviceToDevice, c->stream));
+    Timed t(c, WFD_K_OTHER);
+    HIP_TRY(wfd::launch_unscale_copy(cur, final_dev, c->Nx, c->Ny, c->Nz, c->pitch, w.scale,
+                                     c->stream));
+    HIP_TRY(wfd::launch_unscale_copy(prev, final_dev + dense, c->Nx, c->Ny, c->Nz, c->pitch,
+                                     w.scale, c->stream));
   }
   return WFD_OK;
 }
@@ -934,6 +935,21 @@ wfd_status wfd_gradient(wfd_ctx *c, const float *wavelet, const double src_xyz[3
                         const double *rec_xyz, const float *dobs, const wfd_ckpt *ck,
                         float *seis, double *misfit, float *grad, float *illum, void *work,
                         size_t work_bytes) {
+  return wfd_gradient_ex(c, wavelet, src_xyz, nrec, rec_xyz, dobs, ck, seis, misfit, grad, illum,
+                         nullptr, work, work_bytes);
+}
+
+wfd_status wfd_gradient_ex(wfd_ctx *c, const float *wavelet, const double src_xyz[3],
+                           int32_t nrec, const double *rec_xyz, const float *dobs,
+                           const wfd_ckpt *ck, float *seis, double *misfit, float *grad,
+                           float *illum, const wfd_gradient_opts *opts, void *work,
+                           size_t work_bytes) {
+  float *const wavelet_grad = opts ? opts->wavelet_grad_dev : nullptr;
+  const int out_exp2 = opts ? opts->out_exp2 : 0;
+  int32_t *const field_exp2 = opts ? opts->field_exp2_dev : nullptr;
+  if (out_exp2 < -2 * wfd::kMaxFieldExp || out_exp2 > 2 * wfd::kMaxFieldExp)
+    return fail(WFD_E_ARG, "out_exp2 must be in [-%d, %d]", 2 * wfd::kMaxFieldExp,
+                2 * wfd::kMaxFieldExp);
   wfd_status s = common_checks(c, wavelet, src_xyz, nrec, rec_xyz);
   if (s != WFD_OK) return s;
   if (!ck) return fail(WFD_E_ARG, "checkpoint policy is NULL");
@@ -970,12 +986,19 @@ wfd_status wfd_gradient(wfd_ctx *c, const float *wavelet, const double src_xyz[3
   if (work_bytes < w.bytes)
     return fail(WFD_E_NOMEM, "workspace has %zu bytes, %zu needed", work_bytes, w.bytes);
   int64_t src_idx = 0;
-  s = prepare_shot(c, src_xyz, nrec, rec_xyz, w, src_idx);
+  s = prepare_shot(c, wavelet, src_xyz, nrec, rec_xyz, w, src_idx);
   if (s != WFD_OK) return s;
   const int nt = c->grid.nt;
   const wfd::StepGrid g = step_grid(c);
   const wfd::RecTable rt = rec_table(w, nrec);
-  const wfd::Source src{src_idx, w.sigma, wavelet};
+  const wfd::Source src{src_idx, &w.scale->sigma, wavelet};
+  const wfd::IllumOut il{illum, c->grid.border, c->grid.nx, c->grid.ny, c->grid.nz, w.scale,
+                         out_exp2};
+  if (field_exp2) {
+    Timed t(c, WFD_K_OTHER);
+    HIP_TRY(hipMemcpyAsync(field_exp2, &w.scale->e, sizeof(int32_t), hipMemcpyDeviceToDevice,
+                           c->stream));
+  }
   for (float *p : {w.W1, w.W2, w.P1, w.P2, w.g})
     if ((s = zero(c, p, c->vol)) != WFD_OK) return s;
 
@@ -989,8 +1012,8 @@ wfd_status wfd_gradient(wfd_ctx *c, const float *wavelet, const double src_xyz[3
     int np = 0;
     {
       Timed t(c, WFD_K_OTHER);
-      HIP_TRY(wfd::launch_residual(w.seis_tm, dobs, w.rec_adj, nrec, nt, w.res_tm, w.partial, &np,
-                                   c->stream));
+      HIP_TRY(wfd::launch_residual(w.seis_tm, dobs, w.rec_adj, w.scale, nrec, nt, w.res_tm,
+                                   w.partial, &np, c->stream));
     }
     {
       Timed t(c, WFD_K_OTHER);
@@ -1006,12 +1029,16 @@ wfd_status wfd_gradient(wfd_ctx *c, const float *wavelet, const double src_xyz[3
     if (c->cpml && (s = cpml_adjoint_terms(c, g, w, A1, A2, m, true)) != WFD_OK) return s;
     {
       Timed t(c, WFD_K_ADJOINT);
-      HIP_TRY(wfd::launch_adjoint_step(c->tuning, g, A1, A2, A2, rt, w.res_tm, m, wm, w.g, illum,
-                                       c->grid.border, c->grid.nx, c->grid.ny, c->grid.nz,
+      HIP_TRY(wfd::launch_adjoint_step(c->tuning, g, A1, A2, A2, rt, w.res_tm, m, wm, w.g, il,
                                        c->stream));
     }
     if (c->cpml && (s = cpml_adjoint_terms(c, g, w, A1, A2, m, false, corr_m)) != WFD_OK)
       return s;
+    if (wavelet_grad) {  // psi^m (in A2) at the source
+      Timed t(c, WFD_K_OTHER);
+      HIP_TRY(wfd::launch_source_gradient(A2, c->k, src_idx, w.scale, out_exp2, m, wavelet_grad,
+                                          c->stream));
+    }
     std::swap(A1, A2);
     return WFD_OK;
   };
@@ -1225,7 +1252,8 @@ wfd_status wfd_gradient(wfd_ctx *c, const float *wavelet, const double src_xyz[3
   {
     Timed t(c, WFD_K_OTHER);
     HIP_TRY(wfd::launch_grad_fold(w.g, c->k, c->pitch, c->Ny, c->grid.border, c->grid.nx,
-                                  c->grid.ny, c->grid.nz, c->grid.dt, grad, c->stream));
+                                  c->grid.ny, c->grid.nz, c->grid.dt, w.scale, out_exp2, grad,
+                                  c->stream));
   }
   return WFD_OK;
 }
@@ -1285,7 +1313,7 @@ wfd_status wfd_autotune(wfd_ctx *c, int32_t steps, void *work, size_t work_bytes
   const wfd::StepGrid g = step_grid(c);
   const wfd::RecTable rt = rec_table(w, 0);
   // index -1 matches no point: nothing is injected (the pointers stay valid)
-  const wfd::Source none_src{-1, w.sigma, w.sigma};
+  const wfd::Source none_src{-1, &w.scale->sigma, &w.scale->sigma};
   hipEvent_t e0, e1;
   HIP_TRY(hipEventCreate(&e0));
   if (hipEventCreate(&e1) != hipSuccess) {
@@ -1325,8 +1353,7 @@ wfd_status wfd_autotune(wfd_ctx *c, int32_t steps, void *work, size_t work_bytes
       float ms = 0.0f;
       err = time_steps(c, steps, e0, e1, [&] {
         hipError_t e = wfd::launch_adjoint_step(tu, g, a1, a2, a2, rt, w.seis_tm, 1, w.W1, w.g,
-                                                nullptr, c->grid.border, c->grid.nx, c->grid.ny,
-                                                c->grid.nz, c->stream);
+                                                wfd::IllumOut{}, c->stream);
         std::swap(a1, a2);
         return e;
       }, &ms);
@@ -1395,7 +1422,7 @@ wfd_status wfd_batch_create(wfd_batch **out, int32_t nshot, wfd_ctx *const *ctxs
                   w.bytes);
     }
     int64_t src_idx = 0;
-    wfd_status s = prepare_shot(c, src_xyz + 3 * (size_t)i, nrec[i],
+    wfd_status s = prepare_shot(c, wavelet, src_xyz + 3 * (size_t)i, nrec[i],
                                 nrec[i] > 0 ? rec_xyz[i] : nullptr, w, src_idx);
     if (s != WFD_OK) {
       delete b;
@@ -1415,7 +1442,7 @@ wfd_status wfd_batch_create(wfd_batch **out, int32_t nshot, wfd_ctx *const *ctxs
     wfd::WindowStep d{};
     d.g = step_grid(c);
     const int nb = wfd::forward_tile_map(d.g, tu, &d.map);
-    d.src = wfd::Source{src_idx, w.sigma, wavelet};
+    d.src = wfd::Source{src_idx, &w.scale->sigma, wavelet};
     d.rec = rec_table(w, nrec[i]);
     d.rec_scale = w.rec_scale;
     d.seis_tm = nrec[i] > 0 ? w.seis_tm : nullptr;

@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "wfd.h"
+
 namespace wfd {
 
 // Padded-grid geometry and coefficient volumes seen by every step kernel.
@@ -34,8 +36,23 @@ struct RecTable {
   int nrec;
 };
 
+// Per-shot scales, computed on the device from the wavelet (no host sync).
+// The step kernels carry the field times 2^e, an exact power of two chosen so
+// that the source term sigma max|f| 2^e lies in [1, 2): the fields stay far
+// from FP32's subnormal range whatever the source amplitude and grid spacing.
+// Every operation of the time stepping is linear in the field, so the scaled
+// run has bitwise the mantissas of the unscaled one; recordings, final states,
+// the gradient and the illumination undo the factor on output.
+struct ShotScale {
+  float sigma;       // injection factor sigma 2^e (first member: Source::sigma)
+  float sigma_phys;  // sigma = dt^2 / (hx hy hz sqrt(rho_src))
+  int e;             // field exponent
+  int pad;
+};
+constexpr int kMaxFieldExp = 120;  // |e| bound: 2^-120 sqrt(rho) stays a normal FP32
+
 // Source: padded node (linear index into a pitched volume), device scalar
-// sigma = dt^2 / (hx hy hz sqrt(rho_src)) and the wavelet.
+// sigma 2^e (the first member of the shot's ShotScale) and the wavelet.
 struct Source {
   int64_t idx;
   const float *sigma;
@@ -90,11 +107,20 @@ int forward_tile_map(const StepGrid &g, const Tuning &tu, TileMap *map);
 hipError_t launch_forward_multi(const WindowStep *wins, int nwin, int nblocks, int n, int variant,
                                 bool vd, bool fs, hipStream_t stream);
 
+// Illumination output of the adjoint step: illum[model cell] += 2^(out_exp2 -
+// 2 e) (w^m)^2 with e from the shot's scale (the field kernels carry 2^e w).
+struct IllumOut {
+  float *p;  // [mnz][mny][mnx] or nullptr
+  int border, mnx, mny, mnz;
+  const ShotScale *sc;
+  int out_exp2;
+};
+
 hipError_t launch_adjoint_step(const Tuning &tu, const StepGrid &g, const float *cur,
                                const float *prev, float *out,
                                const RecTable &rec, const float *res_tm, int m,
-                               const float *wm, float *grad, float *illum, int border, int mnx,
-                               int mny, int mnz, hipStream_t stream);
+                               const float *wm, float *grad, const IllumOut &illum,
+                               hipStream_t stream);
 
 // Model preparation.
 hipError_t launch_precompute_k(const float *vel, int mnx, int mny, int mnz, int border, double dt,
@@ -105,17 +131,32 @@ hipError_t launch_precompute_m2(const float *rho, int mnx, int mny, int mnz, int
                                 float *m2, int pitch, int ny, int nz, float *sqrt_rho,
                                 float *partial_max, int n_partial, hipStream_t stream);
 
-// Per-shot scalars: sigma and per-receiver forward / adjoint scales.
-hipError_t launch_shot_setup(const float *k, const float *sqrt_rho, int border, int mnx, int mny,
-                             int64_t src_idx, int src_model_idx, double dt2_over_h3,
+// Per-shot scales: the ShotScale (sigma, field exponent e from max|wavelet|)
+// and per-receiver recording scales sqrt(rho_r) 2^-e (physical pressure out
+// of the scaled field) and adjoint injection scales k_r sqrt(rho_r) (the
+// residual kernel applies 2^e).
+hipError_t launch_shot_setup(const float *k, const float *sqrt_rho, int64_t src_idx,
+                             int src_model_idx, double dt2_over_h3, const float *wavelet, int nt,
                              const int64_t *rec_idx, const int *rec_model_idx, int nrec,
-                             float *sigma, float *rec_scale, float *rec_adj, hipStream_t stream);
+                             ShotScale *sc, float *rec_scale, float *rec_adj, hipStream_t stream);
 
-// Residual + misfit: res_tm[n][r] = adj[r] * (seis_tm[n][r] - dobs[r][n]),
-// partial[b] = 1/2 sum res^2 (FP64) per block; then misfit += sum partial.
-hipError_t launch_residual(const float *seis_tm, const float *dobs, const float *rec_adj, int nrec,
-                           int nt, float *res_tm, double *partial, int *n_partial,
-                           hipStream_t stream);
+// dst[z][y][x] (dense Nz x Ny x Nx) = 2^-e src[z][y][pitch x]: a field of the
+// step kernels in physical units.
+hipError_t launch_unscale_copy(const float *src, float *dst, int nx, int ny, int nz, int pitch,
+                               const ShotScale *sc, hipStream_t stream);
+
+// wg[m - 1] += 2^(out_exp2 - e) sigma psi[src_idx] / k[src_idx]: sample m - 1
+// of the misfit's gradient with respect to the wavelet, from the adjoint
+// state psi^m of the step that was just taken.
+hipError_t launch_source_gradient(const float *psi, const float *k, int64_t src_idx,
+                                  const ShotScale *sc, int out_exp2, int m, float *wg,
+                                  hipStream_t stream);
+
+// Residual + misfit: res_tm[n][r] = 2^e adj[r] (seis_tm[n][r] - dobs[r][n]),
+// partial[b] = 1/2 sum (seis - dobs)^2 (FP64) per block; then misfit += sum partial.
+hipError_t launch_residual(const float *seis_tm, const float *dobs, const float *rec_adj,
+                           const ShotScale *sc, int nrec, int nt, float *res_tm, double *partial,
+                           int *n_partial, hipStream_t stream);
 int residual_partial_count(int nrec, int nt);
 hipError_t launch_sum_partials(const double *partial, int n, double *misfit, hipStream_t stream);
 
@@ -123,9 +164,12 @@ hipError_t launch_sum_partials(const double *partial, int n, double *misfit, hip
 hipError_t launch_transpose(const float *src_tm, float *dst_rm, int nrec, int nt,
                             hipStream_t stream);
 
-// grad[m] += 2 / v * sum of g over the padded cells that replicate model cell m.
+// grad[m] += 2^(out_exp2 - 2 e) 2 / v * sum of g over the padded cells that
+// replicate model cell m (g carries the factor 2^(2 e) of the two scaled
+// fields it correlates).
 hipError_t launch_grad_fold(const float *g, const float *k, int pitch, int pny, int border,
-                            int mnx, int mny, int mnz, double dt, float *grad, hipStream_t stream);
+                            int mnx, int mny, int mnz, double dt, const ShotScale *sc,
+                            int out_exp2, float *grad, hipStream_t stream);
 
 hipError_t launch_fill_zero(float *p, int64_t n, hipStream_t stream);
 

@@ -1,6 +1,6 @@
 // HIP kernels for gfx950 (MI355X) around the step kernels (wfd_step.hip):
 // model preparation (Eq. 1 coefficients, in FP64 where it matters), per-shot
-// source / receiver scales, the misfit with a deterministic FP64 reduction
+// source / receiver scales with the field's power-of-two exponent, the misfit with a deterministic FP64 reduction
 // (Alg. 3, SeismicData::Misfit), seismogram transposes and the gradient
 // finish (chain rule to dJ/dv with the sponge fold).
 #include "wfd_internal.h"
@@ -91,30 +91,79 @@ __global__ void __launch_bounds__(256)
   if (threadIdx.x == 0) part[blockIdx.x] = red[0];
 }
 
+// Field exponent e of a source term of size x = sigma max|f|: x 2^e in [1, 2),
+// clamped to [-kMaxFieldExp, kMaxFieldExp]; 0 for a silent (or non-finite) source.
+__device__ __forceinline__ int field_exponent(double x) {
+  if (!(x > 0.0) || !(x < 1.0e300)) return 0;
+  const int e = -ilogb(x);
+  return e < -kMaxFieldExp ? -kMaxFieldExp : (e > kMaxFieldExp ? kMaxFieldExp : e);
+}
+
+// Every block reduces max|f| itself (nt values), so that all of them take the
+// same exponent without a second launch.
 __global__ void __launch_bounds__(256)
     k_shot_setup(const float *__restrict__ k, const float *__restrict__ sqrt_rho, int64_t src_idx,
-                 int src_model_idx, double dt2_over_h3, const int64_t *__restrict__ rec_idx,
-                 const int *__restrict__ rec_model_idx, int nrec, float *__restrict__ sigma,
-                 float *__restrict__ rec_scale, float *__restrict__ rec_adj) {
+                 int src_model_idx, double dt2_over_h3, const float *__restrict__ wavelet, int nt,
+                 const int64_t *__restrict__ rec_idx, const int *__restrict__ rec_model_idx,
+                 int nrec, ShotScale *__restrict__ sc, float *__restrict__ rec_scale,
+                 float *__restrict__ rec_adj) {
+  (void)src_idx;
+  __shared__ float red[256];
+  float fm = 0.0f;
+  for (int n = threadIdx.x; n < nt; n += 256) fm = fmaxf(fm, fabsf(wavelet[n]));
+  red[threadIdx.x] = fm;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) red[threadIdx.x] = fmaxf(red[threadIdx.x], red[threadIdx.x + s]);
+    __syncthreads();
+  }
+  const double s_src = sqrt_rho ? (double)sqrt_rho[src_model_idx] : 1.0;
+  const double sigma = dt2_over_h3 / s_src;
+  const int e = field_exponent(sigma * (double)red[0]);
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i == 0) {
-    const double s = sqrt_rho ? (double)sqrt_rho[src_model_idx] : 1.0;
-    sigma[0] = (float)(dt2_over_h3 / s);
+    sc->sigma = (float)ldexp(sigma, e);
+    sc->sigma_phys = (float)sigma;
+    sc->e = e;
+    sc->pad = 0;
   }
   if (i < nrec) {
     const float s = sqrt_rho ? sqrt_rho[rec_model_idx[i]] : 1.0f;
-    rec_scale[i] = s;
+    rec_scale[i] = ldexpf(s, -e);
     rec_adj[i] = k[rec_idx[i]] * s;
   }
 }
 
+__global__ void __launch_bounds__(256)
+    k_unscale_copy(const float *__restrict__ src, float *__restrict__ dst, int nx, int ny, int nz,
+                   int pitch, const ShotScale *__restrict__ sc) {
+  const int e = sc->e;
+  const int64_t total = (int64_t)nx * ny * nz;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t row = i / nx;
+    const int x = (int)(i - row * nx);
+    dst[i] = ldexpf(src[row * pitch + x], -e);
+  }
+}
+
+__global__ void k_source_gradient(const float *__restrict__ psi, const float *__restrict__ k,
+                                  int64_t src_idx, const ShotScale *__restrict__ sc, int out_exp2,
+                                  int m, float *__restrict__ wg) {
+  if (threadIdx.x != 0) return;
+  const double v = (double)sc->sigma_phys * (double)psi[src_idx] / (double)k[src_idx];
+  wg[m - 1] += (float)ldexp(v, out_exp2 - sc->e);
+}
+
 constexpr int TT = 32;  // transpose tile
 
-// res_tm[n][r] = adj[r] (seis_tm[n][r] - dobs[r][n]); per-block 1/2 sum res^2.
+// res_tm[n][r] = 2^e adj[r] (seis_tm[n][r] - dobs[r][n]) (the adjoint field
+// carries 2^e like the forward one); per-block 1/2 sum res^2 (physical).
 __global__ void __launch_bounds__(256)
     k_residual(const float *__restrict__ seis_tm, const float *__restrict__ dobs,
-               const float *__restrict__ adj, int nrec, int nt, float *__restrict__ res_tm,
-               double *__restrict__ partial) {
+               const float *__restrict__ adj, const ShotScale *__restrict__ sc, int nrec, int nt,
+               float *__restrict__ res_tm, double *__restrict__ partial) {
+  const int e = sc->e;
   __shared__ float tile[TT][TT + 1];
   __shared__ double red[256];
   const int r0 = blockIdx.y * TT, n0 = blockIdx.x * TT;
@@ -129,7 +178,7 @@ __global__ void __launch_bounds__(256)
     const int n = n0 + j, r = r0 + tx;
     if (r < nrec && n < nt) {
       const float res = seis_tm[(int64_t)n * nrec + r] - tile[tx][j];
-      res_tm[(int64_t)n * nrec + r] = adj[r] * res;
+      res_tm[(int64_t)n * nrec + r] = ldexpf(adj[r] * res, e);
       acc += 0.5 * (double)res * (double)res;
     }
   }
@@ -181,7 +230,8 @@ __device__ __forceinline__ void fold_range(int i, int n, int border, int &lo, in
 
 __global__ void __launch_bounds__(256)
     k_grad_fold(const float *__restrict__ g, const float *__restrict__ k, int pitch, int pny,
-                int border, int mnx, int mny, int mnz, double dt, float *__restrict__ grad) {
+                int border, int mnx, int mny, int mnz, double dt,
+                const ShotScale *__restrict__ sc, int out_exp2, float *__restrict__ grad) {
   const int64_t total = (int64_t)mnx * mny * mnz;
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= total) return;
@@ -199,7 +249,7 @@ __global__ void __launch_bounds__(256)
       for (int x = x0; x <= x1; ++x) s += g[(int64_t)z * plane + (int64_t)y * pitch + x];
   const float kc = k[(int64_t)(iz + border) * plane + (int64_t)(iy + border) * pitch + ix + border];
   const double v = sqrt((double)kc) / dt;
-  grad[i] += (float)(2.0 * s / v);
+  grad[i] += (float)ldexp(2.0 * s / v, out_exp2 - 2 * sc->e);
 }
 
 __global__ void __launch_bounds__(256) k_fill_zero(float *p, int64_t n) {
@@ -228,17 +278,33 @@ hipError_t launch_precompute_m2(const float *rho, int mnx, int mny, int mnz, int
   return hipGetLastError();
 }
 
-hipError_t launch_shot_setup(const float *k, const float *sqrt_rho, int border, int mnx, int mny,
-                             int64_t src_idx, int src_model_idx, double dt2_over_h3,
+hipError_t launch_shot_setup(const float *k, const float *sqrt_rho, int64_t src_idx,
+                             int src_model_idx, double dt2_over_h3, const float *wavelet, int nt,
                              const int64_t *rec_idx, const int *rec_model_idx, int nrec,
-                             float *sigma, float *rec_scale, float *rec_adj, hipStream_t stream) {
-  (void)border;
-  (void)mnx;
-  (void)mny;
+                             ShotScale *sc, float *rec_scale, float *rec_adj, hipStream_t stream) {
   const int n = nrec > 1 ? nrec : 1;
   hipLaunchKernelGGL(k_shot_setup, dim3((n + 255) / 256), dim3(256), 0, stream, k, sqrt_rho,
-                     src_idx, src_model_idx, dt2_over_h3, rec_idx, rec_model_idx, nrec, sigma,
-                     rec_scale, rec_adj);
+                     src_idx, src_model_idx, dt2_over_h3, wavelet, nt, rec_idx, rec_model_idx,
+                     nrec, sc, rec_scale, rec_adj);
+  return hipGetLastError();
+}
+
+hipError_t launch_unscale_copy(const float *src, float *dst, int nx, int ny, int nz, int pitch,
+                               const ShotScale *sc, hipStream_t stream) {
+  const int64_t total = (int64_t)nx * ny * nz;
+  if (total <= 0) return hipSuccess;
+  int64_t blocks = (total + 255) / 256;
+  if (blocks > 65536) blocks = 65536;
+  hipLaunchKernelGGL(k_unscale_copy, dim3((unsigned)blocks), dim3(256), 0, stream, src, dst, nx,
+                     ny, nz, pitch, sc);
+  return hipGetLastError();
+}
+
+hipError_t launch_source_gradient(const float *psi, const float *k, int64_t src_idx,
+                                  const ShotScale *sc, int out_exp2, int m, float *wg,
+                                  hipStream_t stream) {
+  hipLaunchKernelGGL(k_source_gradient, dim3(1), dim3(64), 0, stream, psi, k, src_idx, sc,
+                     out_exp2, m, wg);
   return hipGetLastError();
 }
 
@@ -246,13 +312,13 @@ int residual_partial_count(int nrec, int nt) {
   return ((nt + TT - 1) / TT) * ((nrec + TT - 1) / TT);
 }
 
-hipError_t launch_residual(const float *seis_tm, const float *dobs, const float *rec_adj, int nrec,
-                           int nt, float *res_tm, double *partial, int *n_partial,
-                           hipStream_t stream) {
+hipError_t launch_residual(const float *seis_tm, const float *dobs, const float *rec_adj,
+                           const ShotScale *sc, int nrec, int nt, float *res_tm, double *partial,
+                           int *n_partial, hipStream_t stream) {
   dim3 grid((nt + TT - 1) / TT, (nrec + TT - 1) / TT);
   *n_partial = (int)(grid.x * grid.y);
-  hipLaunchKernelGGL(k_residual, grid, dim3(TT, 8), 0, stream, seis_tm, dobs, rec_adj, nrec, nt,
-                     res_tm, partial);
+  hipLaunchKernelGGL(k_residual, grid, dim3(TT, 8), 0, stream, seis_tm, dobs, rec_adj, sc, nrec,
+                     nt, res_tm, partial);
   return hipGetLastError();
 }
 
@@ -269,10 +335,11 @@ hipError_t launch_transpose(const float *src_tm, float *dst_rm, int nrec, int nt
 }
 
 hipError_t launch_grad_fold(const float *g, const float *k, int pitch, int pny, int border,
-                            int mnx, int mny, int mnz, double dt, float *grad, hipStream_t stream) {
+                            int mnx, int mny, int mnz, double dt, const ShotScale *sc,
+                            int out_exp2, float *grad, hipStream_t stream) {
   const int64_t total = (int64_t)mnx * mny * mnz;
   hipLaunchKernelGGL(k_grad_fold, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, stream, g,
-                     k, pitch, pny, border, mnx, mny, mnz, dt, grad);
+                     k, pitch, pny, border, mnx, mny, mnz, dt, sc, out_exp2, grad);
   return hipGetLastError();
 }
 

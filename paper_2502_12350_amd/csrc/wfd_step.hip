@@ -373,8 +373,8 @@ template <int RY, int NW, bool VD, bool ILLUM, bool FS>
 __global__ void __launch_bounds__(TX * NW)
     k_adjoint(StepGrid g, const float *__restrict__ cur, const float *prev, float *out,
               RecTable rec, const float *__restrict__ res_tm, int m,
-              const float *__restrict__ wm, float *__restrict__ grad,
-              float *__restrict__ illum, int border, int mnx, int mny, int mnz, TileMap map) {
+              const float *__restrict__ wm, float *__restrict__ grad, IllumOut il,
+              TileMap map) {
   using T = Tile<RY, NW>;
   __shared__ float sm[2][2][T::LY][T::LX];  // [field][buffer]
   Geo<RY, NW, 1> geo;
@@ -393,6 +393,7 @@ __global__ void __launch_bounds__(TX * NW)
   }
   const float c0 = W0 * (g.cx + g.cy + g.cz);
   const float *res_row = res_tm + (int64_t)(m - 1) * rec.nrec;
+  const int iexp = ILLUM ? il.out_exp2 - 2 * il.sc->e : 0;  // (2^e w)^2 -> 2^out_exp2 w^2
   float pv[RY], kv[RY], mv[RY], gv[RY];
 #pragma unroll
   for (int j = 0; j < RY; ++j) {
@@ -459,9 +460,9 @@ __global__ void __launch_bounds__(TX * NW)
         st_stream(out, p, live ? G * (acc - G * pv[j]) : 0.0f);
         st_stream(grad, p, live ? gv[j] + ca * (VD ? lap_w - mv[j] * cw : lap_w) : gv[j]);
         if (ILLUM) {
-          const int ix = geo.x - border, iy = geo.yv[j] - border, iz = z - border;
-          if (ix >= 0 && ix < mnx && iy >= 0 && iy < mny && iz >= 0 && iz < mnz)
-            illum[((int64_t)iz * mny + iy) * mnx + ix] += cw * cw;
+          const int ix = geo.x - il.border, iy = geo.yv[j] - il.border, iz = z - il.border;
+          if (ix >= 0 && ix < il.mnx && iy >= 0 && iy < il.mny && iz >= 0 && iz < il.mnz)
+            il.p[((int64_t)iz * il.mny + iy) * il.mnx + ix] += ldexpf(cw * cw, iexp);
         }
       }
     }
@@ -638,35 +639,32 @@ hipError_t fwd_multi_launch(const WindowStep *wins, int nwin, int nblocks, int n
 template <int V, bool VD, bool ILLUM, bool FS>
 hipError_t adj_launch(const Tuning &tu, const StepGrid &g, const float *cur, const float *prev,
                       float *out, const RecTable &rec, const float *res_tm, int m,
-                      const float *wm, float *grad, float *illum, int border, int mnx, int mny,
-                      int mnz, hipStream_t stream) {
+                      const float *wm, float *grad, const IllumOut &illum, hipStream_t stream) {
   using S = AdjShape<V>;
   using T = Tile<S::RY, S::NW>;
   static const int per_cu = blocks_per_cu(k_adjoint<S::RY, S::NW, VD, ILLUM, FS>, T::NTHREADS);
   static const int nch = env_int("WFD_ZCHUNKS_ADJ", 0);  // 0 = automatic
   const TileMap map = make_map(g, T::TY, per_cu, nch, tu.adj_rounds, kAdjHalo);
   hipLaunchKernelGGL((k_adjoint<S::RY, S::NW, VD, ILLUM, FS>), dim3(map.nblocks), dim3(T::NTHREADS),
-                     0, stream, g, cur, prev, out, rec, res_tm, m, wm, grad, illum, border, mnx,
-                     mny, mnz, map);
+                     0, stream, g, cur, prev, out, rec, res_tm, m, wm, grad, illum, map);
   return hipGetLastError();
 }
 
 template <int V>
 hipError_t adj_dispatch(const Tuning &tu, const StepGrid &g, const float *cur, const float *prev,
                         float *out, const RecTable &rec, const float *res_tm, int m,
-                        const float *wm, float *grad, float *illum, int border, int mnx, int mny,
-                        int mnz, hipStream_t stream) {
+                        const float *wm, float *grad, const IllumOut &illum, hipStream_t stream) {
   const bool vd = g.m2 != nullptr, fs = g.zs != kNoSurface;
 #define WFD_ADJ(VD_, IL_)                                                                       \
   return fs ? adj_launch<V, VD_, IL_, true>(tu, g, cur, prev, out, rec, res_tm, m, wm, grad,    \
-                                            illum, border, mnx, mny, mnz, stream)               \
+                                            illum, stream)                                      \
             : adj_launch<V, VD_, IL_, false>(tu, g, cur, prev, out, rec, res_tm, m, wm, grad,   \
-                                             illum, border, mnx, mny, mnz, stream)
+                                             illum, stream)
   if (vd) {
-    if (illum) WFD_ADJ(true, true);
+    if (illum.p) WFD_ADJ(true, true);
     WFD_ADJ(true, false);
   }
-  if (illum) WFD_ADJ(false, true);
+  if (illum.p) WFD_ADJ(false, true);
   WFD_ADJ(false, false);
 #undef WFD_ADJ
 }
@@ -731,15 +729,11 @@ hipError_t launch_forward_multi(const WindowStep *wins, int nwin, int nblocks, i
 hipError_t launch_adjoint_step(const Tuning &tu, const StepGrid &g, const float *cur,
                                const float *prev, float *out, const RecTable &rec,
                                const float *res_tm, int m, const float *wm, float *grad,
-                               float *illum, int border, int mnx, int mny, int mnz,
-                               hipStream_t stream) {
+                               const IllumOut &illum, hipStream_t stream) {
   switch (tu.adj_variant) {
-    case 1: return adj_dispatch<1>(tu, g, cur, prev, out, rec, res_tm, m, wm, grad, illum,
-                                   border, mnx, mny, mnz, stream);
-    case 2: return adj_dispatch<2>(tu, g, cur, prev, out, rec, res_tm, m, wm, grad, illum,
-                                   border, mnx, mny, mnz, stream);
-    default: return adj_dispatch<0>(tu, g, cur, prev, out, rec, res_tm, m, wm, grad, illum,
-                                    border, mnx, mny, mnz, stream);
+    case 1: return adj_dispatch<1>(tu, g, cur, prev, out, rec, res_tm, m, wm, grad, illum, stream);
+    case 2: return adj_dispatch<2>(tu, g, cur, prev, out, rec, res_tm, m, wm, grad, illum, stream);
+    default: return adj_dispatch<0>(tu, g, cur, prev, out, rec, res_tm, m, wm, grad, illum, stream);
   }
 }
 

@@ -1,0 +1,277 @@
+"""The adjoint sweep and imaging condition on the GPU (Alg. 3 backward loop,
+§2.1 adjoint-state method), checked where earlier tests could not reach:
+
+* element-wise against the FP64 oracle on a grid that spans several adjoint
+  tiles in x and y, each with a ragged tail, and several z chunks, with
+  constant density, variable density and a free surface, including a
+  per-cell check of the columns next to every tile seam;
+* the adjoint dot-product test <F f, d'> = <f, F^T d'> for the linear map F
+  from the wavelet to the data, with F^T taken from the library's wavelet
+  gradient (which reads the adjoint state at the source after every step);
+* the power-of-two field scaling: a source 2^-60 quieter on a 50 m grid,
+  whose fields, products and gradient would otherwise sit deep in (or below)
+  FP32's subnormal range, matches the oracle and equals the loud run once the
+  exact factors are undone.
+"""
+
+import numpy as np
+import pytest
+
+import oracle
+import oracle_jobs
+import seisgen
+from gpu_util import gpu_or_skip, oracle_grid, propagator, rel_l2, say
+
+pytestmark = pytest.mark.gpu
+
+SEIS_TOL = 1e-4
+GRAD_TOL = 1e-3
+DOT_TOL = 1e-5
+
+
+def _prop(w, free_surface=False, vel=None):
+    torch = gpu_or_skip()
+    from paper_2502_12350_amd import GridSpec, Propagator
+    P = Propagator(0)
+    g = GridSpec(**w.grid_kwargs(), free_surface=free_surface)
+    v = w.vel if vel is None else vel
+    P.set_model(g, torch.from_numpy(np.ascontiguousarray(v)).cuda(),
+                None if w.rho is None else torch.from_numpy(w.rho).cuda())
+    return P
+
+
+def _gpu_gradient(P, w, dobs, tuning=None):
+    torch = gpu_or_skip()
+    if tuning is not None:
+        P.set_tuning(*tuning)
+    wav = torch.from_numpy(w.wavelet).cuda()
+    il = torch.zeros((w.nz, w.ny, w.nx), dtype=torch.float32, device="cuda")
+    J, g, seis = P.gradient(wav, w.sources[0], w.receivers, torch.from_numpy(dobs).cuda(),
+                            illum=il, seis=True)
+    torch.cuda.synchronize()
+    return float(J.item()), g.cpu().numpy(), seis.cpu().numpy(), il.cpu().numpy()
+
+
+# ---------------------------------------------------------------------------
+# gradient parity across tile seams
+# ---------------------------------------------------------------------------
+# c2_small is 93 x 77 x 61 + 16 = 125 x 109 x 93 padded.  The default adjoint
+# tiles are 64 x 32: two x tiles (64 + a ragged 61) and four y tiles (32, 32,
+# 32 and a ragged 13), so the padded x seam is at 64 and the y seams at 32, 64
+# and 96.  Few tiles fill few of the device's slots, so the launch-cost model
+# takes the largest chunk count, ceil(93 / 16) = 6 chunks of 16 planes: five
+# z seams.  The 64 x 16 and 64 x 8 tiles move the y seams.
+X_SEAMS = (64,)
+Y_SEAMS = (32, 64, 96)
+
+
+def _near(seams, border, n, reach=4):
+    """Model indices within `reach` cells of a padded-grid seam."""
+    idx = set()
+    for s in seams:
+        for p in range(s - reach, s + reach):
+            i = p - border
+            if 0 <= i < n:
+                idx.add(i)
+    return np.array(sorted(idx))
+
+
+def _seam_report(g, ref, w):
+    scale = float(np.max(np.abs(ref)))
+    xs = _near(X_SEAMS, w.border, w.nx)
+    ys = _near(Y_SEAMS, w.border, w.ny)
+    ex = float(np.max(np.abs(g[:, :, xs] - ref[:, :, xs]))) / scale
+    ey = float(np.max(np.abs(g[:, ys, :] - ref[:, ys, :]))) / scale
+    d = np.abs(g - ref)
+    eall = float(np.max(d)) / scale
+    at = np.unravel_index(int(np.argmax(d)), d.shape)
+    return ex, ey, eall, tuple(int(i) for i in at)
+
+
+@pytest.mark.oracle_refs("c2_small_vd", "c2_small_cd", "c2_small_fs")
+@pytest.mark.parametrize("variant", ["vd", "cd", "fs"])
+def test_gradient_across_tile_seams_matches_oracle(variant):
+    w, fs = oracle_jobs.c2_small_case(variant)
+    say(f"[gradient seams] c2_small {variant} padded {w.padded_shape} nt {w.nt} "
+        f"nrec {len(w.receivers)}")
+    dobs, ref = oracle_jobs.result(f"c2_small_{variant}")
+    P = _prop(w, free_surface=fs)
+    J, g, seis, il = _gpu_gradient(P, w, dobs)
+    eJ = abs(J - ref.misfit) / ref.misfit
+    eg = rel_l2(g, ref.grad)
+    ex, ey, eall, at = _seam_report(g, ref.grad, w)
+    say(f"  |res| / |d| {rel_l2(ref.seis, dobs):.3f}  misfit rel {eJ:.2e}  gradient rel-L2 "
+        f"{eg:.2e}  max cell error / max|g|: x seams {ex:.2e}, y seams {ey:.2e}, anywhere "
+        f"{eall:.2e} at model (z, y, x) {at}")
+    assert rel_l2(seis, ref.seis) <= SEIS_TOL
+    assert eJ <= SEIS_TOL
+    assert eg <= GRAD_TOL
+    assert rel_l2(il, ref.illum) <= SEIS_TOL
+    # every cell next to a seam within 1e-3 of the gradient's peak
+    assert ex <= GRAD_TOL and ey <= GRAD_TOL
+
+
+@pytest.mark.oracle_refs("c2_small_vd")
+@pytest.mark.parametrize("adj_variant", [1, 2])
+def test_gradient_other_adjoint_tiles_match_oracle(adj_variant):
+    """64 x 16 and 64 x 8 adjoint tiles (y seams every 16 / 8 rows), with
+    binomial checkpointing (3 stored pairs) instead of full storage."""
+    torch = gpu_or_skip()
+    w, fs = oracle_jobs.c2_small_case("vd")
+    dobs, ref = oracle_jobs.result("c2_small_vd")
+    say(f"[gradient seams] c2_small vd, adjoint tile variant {adj_variant}, revolve 3")
+    P = _prop(w)
+    P.set_tuning(0, 0, adj_variant, 0)
+    wav = torch.from_numpy(w.wavelet).cuda()
+    J, g = P.gradient(wav, w.sources[0], w.receivers, torch.from_numpy(dobs).cuda(),
+                      ckpt=("revolve", 3))
+    torch.cuda.synchronize()
+    g = g.cpu().numpy()
+    eg = rel_l2(g, ref.grad)
+    scale = float(np.max(np.abs(ref.grad)))
+    ys = _near(range(0, 109, 16 if adj_variant == 1 else 8), w.border, w.ny)
+    ey = float(np.max(np.abs(g[:, ys, :] - ref.grad[:, ys, :]))) / scale
+    say(f"  misfit rel {abs(float(J.item()) - ref.misfit) / ref.misfit:.2e}  gradient rel-L2 "
+        f"{eg:.2e}  y seams {ey:.2e}")
+    assert abs(float(J.item()) - ref.misfit) <= SEIS_TOL * ref.misfit
+    assert eg <= GRAD_TOL and ey <= GRAD_TOL
+
+
+def test_adjoint_tile_shapes_bitwise_on_ragged_grid():
+    """Every adjoint tile shape gives bitwise the same gradient on c2_small
+    (seams, ragged tiles and z chunks in different places)."""
+    torch = gpu_or_skip()
+    w, _ = oracle_jobs.c2_small_case("vd")
+    dobs = np.random.default_rng(5).standard_normal((len(w.receivers), w.nt)).astype(
+        np.float32) * np.float32(1e-12)
+    say("[adjoint tiles bitwise] c2_small")
+    out = []
+    for v in (0, 1, 2):
+        P = _prop(w)
+        P.set_tuning(0, 0, v, 0)
+        J, g, _, il = _gpu_gradient(P, w, dobs)
+        out.append((J, g, il))
+    for J, g, il in out[1:]:
+        assert J == out[0][0]
+        assert np.array_equal(g, out[0][1])
+        assert np.array_equal(il, out[0][2])
+
+
+# ---------------------------------------------------------------------------
+# dot-product test of the adjoint on the GPU
+# ---------------------------------------------------------------------------
+def _wavelet_transpose(P, w, dprime):
+    """F^T d' from the library: zero wavelet (so the synthetic data vanish)
+    and observed data -d', so that the residual is exactly d'."""
+    torch = gpu_or_skip()
+    zero = torch.zeros(w.nt, dtype=torch.float32, device="cuda")
+    wg = torch.zeros(w.nt, dtype=torch.float32, device="cuda")
+    P.gradient(zero, w.sources[0], w.receivers, torch.from_numpy(-dprime).cuda(),
+               wavelet_grad=wg)
+    torch.cuda.synchronize()
+    return wg.cpu().numpy().astype(np.float64)
+
+
+@pytest.mark.parametrize("name", ["c4_fd_vd", "c2_small"])
+def test_adjoint_dot_product(name):
+    torch = gpu_or_skip()
+    w = seisgen.workload(name)
+    rng = np.random.default_rng(20250217)
+    f = rng.standard_normal(w.nt).astype(np.float32)
+    dprime = rng.standard_normal((len(w.receivers), w.nt)).astype(np.float32)
+    say(f"[dot test] {name} padded {w.padded_shape} nt {w.nt} nrec {len(w.receivers)}")
+    P = propagator(w)
+    Ff = P.forward(torch.from_numpy(f).cuda(), w.sources[0], w.receivers)
+    torch.cuda.synchronize()
+    Ff = Ff.cpu().numpy().astype(np.float64)
+    FTd = _wavelet_transpose(P, w, dprime)
+    lhs = float(np.sum(Ff * dprime.astype(np.float64)))
+    rhs = float(np.sum(f.astype(np.float64) * FTd))
+    e = abs(lhs - rhs) / max(abs(lhs), abs(rhs))
+    say(f"  <Ff, d'> = {lhs:.9e}  <f, F^T d'> = {rhs:.9e}  rel {e:.2e}")
+    assert e <= DOT_TOL
+
+
+def test_wavelet_gradient_matches_oracle():
+    """F^T d' element-wise against the oracle's transpose (c4_fd_vd)."""
+    w = seisgen.workload("c4_fd_vd")
+    rng = np.random.default_rng(11)
+    dprime = rng.standard_normal((len(w.receivers), w.nt)).astype(np.float32)
+    say("[wavelet gradient] c4_fd_vd")
+    gpu = _wavelet_transpose(propagator(w), w, dprime)
+    ref = oracle.adjoint_source_transpose(oracle_grid(w), w.vel, w.rho, w.sources[0],
+                                          w.receivers, dprime)
+    e = rel_l2(gpu, ref)
+    say(f"  rel-L2 {e:.2e}")
+    assert e <= SEIS_TOL
+
+
+# ---------------------------------------------------------------------------
+# power-of-two field scaling
+# ---------------------------------------------------------------------------
+QUIET = 60   # the source is 2^-60 times the usual one
+
+
+def _coarse_case():
+    """c4_fd_vd on a 50 m grid (dt from Courant 0.4), 3 Hz Ricker."""
+    w = seisgen.workload("c4_fd_vd")
+    h = 50.0
+    k = h / w.dx
+    w.dx = w.dy = w.dz = h
+    w.dt = 0.4 * h / float(np.max(w.vel))
+    w.sources = w.sources * k
+    w.receivers = w.receivers * k
+    w.wavelet = seisgen.ricker(w.nt, w.dt, 3.0)
+    return w
+
+
+def test_quiet_source_on_coarse_grid_matches_oracle_and_loud_run():
+    torch = gpu_or_skip()
+    w = _coarse_case()
+    true = (w.vel + 5.0 * w.extra["dv"]).astype(np.float32)
+    quiet = np.ldexp(w.wavelet, -QUIET).astype(np.float32)
+    g = oracle_grid(w)
+    dobs_q = oracle.forward(g, true, w.rho, quiet, w.sources[0], w.receivers).seis
+    dobs_q = dobs_q.astype(np.float32)
+    ref = oracle.gradient(g, w.vel, w.rho, quiet, w.sources[0], w.receivers, dobs_q,
+                          illumination=True)
+    say(f"[quiet source] h 50 m, source 2^-{QUIET}: max|d| {np.max(np.abs(ref.seis)):.2e}, "
+        f"J {ref.misfit:.2e}, max|dJ/dv| {np.max(np.abs(ref.grad)):.2e}, "
+        f"max|g| (imaging sum) {np.max(np.abs(ref.g)):.2e}")
+    out = 2 * QUIET   # the gradient and illumination scale as the amplitude squared
+
+    def run(wavelet, dobs, out_exp2):
+        P = propagator(w)
+        wav = torch.from_numpy(wavelet).cuda()
+        il = torch.zeros((w.nz, w.ny, w.nx), dtype=torch.float32, device="cuda")
+        wg = torch.zeros(w.nt, dtype=torch.float32, device="cuda")
+        e = torch.zeros((), dtype=torch.int32, device="cuda")
+        J, gr, seis = P.gradient(wav, w.sources[0], w.receivers, torch.from_numpy(dobs).cuda(),
+                                 illum=il, seis=True, wavelet_grad=wg, out_exp2=out_exp2,
+                                 field_exp2=e)
+        torch.cuda.synchronize()
+        return (float(J.item()), gr.cpu().numpy(), seis.cpu().numpy(), il.cpu().numpy(),
+                wg.cpu().numpy(), int(e.item()))
+
+    Jq, gq, sq, ilq, wgq, eq = run(quiet, dobs_q, out)
+    say(f"  field exponent {eq}")
+    es = rel_l2(sq, ref.seis)
+    eJ = abs(Jq - ref.misfit) / ref.misfit
+    eg = rel_l2(gq, np.ldexp(ref.grad, out))
+    ei = rel_l2(ilq, np.ldexp(ref.illum, out))
+    say(f"  vs oracle: seismogram {es:.2e}, misfit {eJ:.2e}, gradient {eg:.2e}, "
+        f"illumination {ei:.2e}")
+    assert es <= SEIS_TOL and eJ <= SEIS_TOL and eg <= GRAD_TOL and ei <= SEIS_TOL
+
+    # The loud run carries the same internal field: its exponent is exactly
+    # QUIET lower.  Inputs that were subnormal or zero in FP32 at the quiet
+    # scale (the far tail of the wavelet, traces before the first arrival)
+    # differ in their last bits, so the comparison is to 1e-6, not bitwise.
+    dobs_l = np.ldexp(dobs_q, QUIET).astype(np.float32)
+    Jl, gl, sl, ill, wgl, el = run(w.wavelet, dobs_l, 0)
+    assert el == eq - QUIET
+    assert rel_l2(np.ldexp(sq.astype(np.float64), QUIET), sl) <= 1e-6
+    assert rel_l2(gq, gl) <= 1e-6
+    assert rel_l2(ilq, ill) <= 1e-6
+    assert rel_l2(np.ldexp(wgq.astype(np.float64), -QUIET), wgl) <= 1e-6
+    assert abs(Jl - np.ldexp(Jq, 2 * QUIET)) <= 1e-6 * Jl

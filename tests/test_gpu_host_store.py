@@ -52,7 +52,7 @@ def test_host_store_equals_full_storage_bitwise(nt):
 
 
 def test_host_slots_hold_the_forward_states():
-    # slot m-1 of a caller-provided store is w^m: compare slots with the final
+    # slot m-1 of a caller-provided store is 2^e w^m: compare slots with the final
     # state of forward runs that stop after m steps (same kernels, same bits)
     torch = gpu_or_skip()
     w, dobs = _case(40)
@@ -60,9 +60,12 @@ def test_host_slots_hold_the_forward_states():
     nbytes = P.host_store_bytes()
     store = torch.empty(nbytes // 4, dtype=torch.float32, pin_memory=True)
     store.fill_(np.nan)
+    e = torch.zeros((), dtype=torch.int32, device="cuda")
     P.gradient(torch.from_numpy(w.wavelet).cuda(), w.sources[0], w.receivers, dobs,
-               ckpt=("host", store))
+               ckpt=("host", store), field_exp2=e)
     torch.cuda.synchronize()
+    e = int(e.item())   # the slots hold 2^e w^m (exact power-of-two field scaling)
+    say(f"  field exponent {e}")
     Nz, Ny, Nx = w.padded_shape
     pitch = (Nx + 63) // 64 * 64          # rows of the pitched device volumes
     assert nbytes == w.nt * Nz * Ny * pitch * 4
@@ -77,7 +80,7 @@ def test_host_slots_hold_the_forward_states():
                            final=True)
         torch.cuda.synchronize()
         say(f"  slot {m - 1} vs forward to step {m}")
-        assert torch.equal(slots[m - 1], fin[0].cpu())
+        assert torch.equal(slots[m - 1] * (2.0 ** -e), fin[0].cpu())
 
 
 def test_host_store_reused_across_calls_and_accumulates():
