@@ -118,14 +118,27 @@ def copy_probe(gib: float = 4.0, reps: int = 10):
                       "addcmul_r3w1_GBps": round(16 * n / t_r3w1 / 1e9, 1)}), flush=True)
 
 
+def _probe_lib():
+    """bench_probe.so: the streaming probe kernels (bench_probe.hip, built by
+    __graft_entry__.build()); measurement code, not part of the library."""
+    import ctypes as C
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "bench_probe.so")
+    if not os.path.exists(path):
+        raise SystemExit(f"{path} is missing: run __graft_entry__.build() first")
+    L = C.CDLL(path)
+    L.bench_stream_probe.restype = C.c_int
+    L.bench_stream_probe.argtypes = [C.c_int, C.c_int, C.c_int, C.c_void_p, C.c_int64, C.c_int,
+                                     C.c_void_p]
+    return L
+
+
 def stream_probe(reps: int = 10):
-    """Achievable streaming bandwidth: the library's plain float4 probe
-    kernels (no reuse) reading R and writing W arrays of 576^3 floats, over
-    several grid sizes, plain and nontemporal; the best rate per mix."""
+    """Achievable streaming bandwidth: plain float4 probe kernels (no reuse)
+    reading R and writing W arrays of 576^3 floats, over several grid sizes,
+    plain and nontemporal; the best rate per mix."""
     import ctypes as C
     import torch
-    from paper_2502_12350_amd import _lib
-    L = _lib.lib()
+    L = _probe_lib()
     n = 576 ** 3
     buf = torch.ones(8 * n, dtype=torch.float32, device="cuda")
     st = C.c_void_p(torch.cuda.current_stream().cuda_stream)
@@ -135,7 +148,9 @@ def stream_probe(reps: int = 10):
         for nt in (0, 1):
             for blocks in (2048, 8192, 32768):
                 def run():
-                    _lib.check(L.wfd_stream_probe(r, w, nt, C.c_void_p(buf.data_ptr()), n, blocks, st))
+                    rc = L.bench_stream_probe(r, w, nt, buf.data_ptr(), n, blocks, st)
+                    if rc != 0:
+                        raise RuntimeError(f"bench_stream_probe failed with HIP error {rc}")
                 for _ in range(2):
                     run()
                 e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)

@@ -252,8 +252,9 @@ wfd_status wfd_gradient_finish(wfd_ctx *ctx, float *grad_dev, int32_t zero_top_p
 
 /* ---- launch tuning and batched shots ------------------------------------ */
 
-/* Launch shapes of the context's step kernels (the paper tunes its CUDA
- * block size per architecture; these are the CDNA4 tile choices):
+/* Launch shapes of the context's step kernels: the GPU counterpart of the
+ * paper's autotuning of the OpenMP chunk size of its time-step loop (PATSMA,
+ * Alg. 1 and Alg. 3).  The choices are CDNA4 tiles and z chunkings:
  *   fwd_variant  forward tiles (rows per thread x wavefronts per block):
  *                0: 2x8 = 64x16 tiles [default]  1: 2x16 = 64x32
  *                2: 2x4 = 64x8                    3: 4x4 = 64x16
@@ -315,7 +316,9 @@ wfd_status wfd_batch_create(wfd_batch **batch, int32_t nshot, wfd_ctx *const *ct
 /* Enqueue the whole batch (clear states, nt steps, trace transposes) on the
  * stream.  use_graph != 0: the first call captures the sequence into a HIP
  * graph (the stream must not be the legacy NULL stream and profiling must be
- * off); every call launches that graph.  Asynchronous. */
+ * off); every call launches that graph.  Asynchronous.  WFD_E_STATE if a
+ * member context's model was set again after wfd_batch_create (the batch
+ * holds the coefficient pointers of the model it was created with). */
 wfd_status wfd_batch_run(wfd_batch *batch, int32_t use_graph);
 
 /* Wait for the stream if a graph exists, release the batch (not the
@@ -476,19 +479,6 @@ wfd_status wfd_set_profiling(wfd_ctx *ctx, int32_t enable);
 /* Launch count and summed kernel time (ms) of one kernel class since
  * profiling was enabled.  Waits for the stream. */
 wfd_status wfd_kernel_stats(wfd_ctx *ctx, int32_t kernel_class, int64_t *launches, double *total_ms);
-
-/* Streaming probe (measurement only, not part of the method): one launch of
- * a plain kernel that reads `reads` arrays and writes `writes` arrays of n
- * FP32 values as float4, grid-stride over `blocks` blocks of 256 threads, with
- * nontemporal loads and stores when nontemporal = 1.  It is the achievable-
- * bandwidth reference for the step kernels' rooflines: (1,1) a copy, (3,1)
- * and (4,1) the forward step's stream mixes without stencil reuse, (6,2) the
- * adjoint's.  buf_dev holds the inputs then the outputs, reads + writes
- * arrays of n values; n must be a positive multiple of 4 and buf_dev 16-byte
- * aligned.  Other (reads, writes) pairs return WFD_E_ARG.  Launches on
- * hip_stream (a hipStream_t, NULL = legacy default) and returns at once. */
-wfd_status wfd_stream_probe(int32_t reads, int32_t writes, int32_t nontemporal, float *buf_dev,
-                            int64_t n, int32_t blocks, void *hip_stream);
 
 /* Thread-local text of the last error ("" if none). */
 const char *wfd_last_error(void);

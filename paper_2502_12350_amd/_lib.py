@@ -66,7 +66,6 @@ _SIGS = {
     "wfd_set_model": (C.c_int, [_P, C.POINTER(wfd_grid), _P, _P, _P, C.c_size_t]),
     "wfd_workspace_bytes": (C.c_int, [_P, C.c_int32, C.POINTER(wfd_ckpt), C.POINTER(C.c_size_t)]),
     "wfd_host_store_bytes": (C.c_int, [_P, C.POINTER(C.c_size_t)]),
-    "wfd_stream_probe": (C.c_int, [C.c_int32, C.c_int32, C.c_int32, _P, C.c_int64, C.c_int32, _P]),
     "wfd_forward": (C.c_int, [_P, _P, _D3, C.c_int32, _D3, _P, _P, _P, C.c_size_t]),
     "wfd_forward_misfit": (C.c_int, [_P, _P, _D3, C.c_int32, _D3, _P, _P, _P, _P, C.c_size_t]),
     "wfd_misfit_workspace_bytes": (C.c_int, [_P, C.c_int32, C.POINTER(C.c_size_t)]),

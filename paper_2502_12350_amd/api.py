@@ -427,6 +427,10 @@ class ShotBatch:
         p0 = props[0]
         self.torch = torch
         self.props = list(props)
+        # the batch's step descriptors point into each context's model buffer:
+        # hold those buffers for the batch's lifetime (a later set_model on a
+        # member makes wfd_batch_run fail with WFD_E_STATE instead)
+        self._models = [p._model for p in self.props]
         self.stream = stream if stream is not None else torch.cuda.current_stream(p0.device)
         nt = p0.grid.nt if p0.grid is not None else 0
         self.wavelet = p0._dev(wavelet, "wavelet", (nt,), torch.float32)

@@ -23,7 +23,7 @@ LIB = os.path.join(PKG, "libwfd.so")
 
 SOURCES = [
     "wfd_step.hip", "wfd_kernels.hip", "wfd_cnn.hip", "wfd_smooth.hip", "wfd_cpml.hip",
-    "wfd_probe.hip", "wfd_api.cpp", "wfd_plan.cpp",
+    "wfd_api.cpp", "wfd_plan.cpp",
 ]
 ARCH = "gfx950"
 
@@ -68,6 +68,22 @@ def build(verbose: bool = False) -> str:
         raise RuntimeError(f"link failed:\n{res.stdout}\n{res.stderr}")
     os.replace(tmp, LIB)
     return LIB
+
+
+def build_bench_probe(verbose: bool = False) -> str:
+    """Compile bench.py's streaming probe (bench_probe.hip at the repository
+    root, measurement code outside the library) into bench_probe.so."""
+    src = os.path.join(ROOT, "bench_probe.hip")
+    out = os.path.join(ROOT, "bench_probe.so")
+    tmp = out + ".tmp"
+    cmd = [hipcc(), "-x", "hip", *_flags(), "-shared", src, "-o", tmp]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    res = subprocess.run(cmd, capture_output=True, text=True)
+    if res.returncode != 0:
+        raise RuntimeError(f"bench probe build failed:\n{res.stdout}\n{res.stderr}")
+    os.replace(tmp, out)
+    return out
 
 
 if __name__ == "__main__":

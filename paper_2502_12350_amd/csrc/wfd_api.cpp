@@ -70,6 +70,7 @@ struct wfd_ctx {
 
   // model
   bool has_model = false;
+  uint64_t model_gen = 0;  // incremented by every wfd_set_model (batches check it)
   wfd_grid grid{};
   int Nx = 0, Ny = 0, Nz = 0, pitch = 0;
   int64_t plane = 0, vol = 0;  // floats
@@ -108,6 +109,7 @@ struct wfd_ctx {
 // captured once into a HIP graph and replayed.
 struct wfd_batch {
   std::vector<wfd_ctx *> ctxs;
+  std::vector<uint64_t> model_gen;  // each context's model generation at creation
   std::vector<float *> W1, W2, seis_tm, seis_out;
   std::vector<int> nrec;
   wfd::WindowStep *d_wins[2] = {nullptr, nullptr};  // device descriptors per step parity
@@ -774,6 +776,7 @@ wfd_status wfd_set_model(wfd_ctx *c, const wfd_grid *grid, const float *vel,
         return fail(WFD_E_ARG, "padded grid too large for the CPML layer's point boxes");
   }
   c->has_model = true;
+  ++c->model_gen;
   return WFD_OK;
 }
 
@@ -1457,6 +1460,7 @@ wfd_status wfd_batch_create(wfd_batch **out, int32_t nshot, wfd_ctx *const *ctxs
       b->h_wins[p][i] = e;
     }
     b->ctxs.push_back(c);
+    b->model_gen.push_back(c->model_gen);
     b->W1.push_back(w.W1);
     b->W2.push_back(w.W2);
     b->seis_tm.push_back(w.seis_tm);
@@ -1503,6 +1507,12 @@ wfd_status batch_enqueue(wfd_batch *b) {
 
 wfd_status wfd_batch_run(wfd_batch *b, int32_t use_graph) {
   if (!b) return fail(WFD_E_ARG, "batch is NULL");
+  // the step descriptors (and a captured graph) hold the coefficient pointers
+  // of each context's model at creation time
+  for (size_t i = 0; i < b->ctxs.size(); ++i)
+    if (!b->ctxs[i]->has_model || b->ctxs[i]->model_gen != b->model_gen[i])
+      return fail(WFD_E_STATE, "shot %zu: the context's model changed after wfd_batch_create",
+                  i);
   ScopedDevice sd(b->ctxs[0]->device);
   if (!use_graph) return batch_enqueue(b);
   if (!b->stream) return fail(WFD_E_ARG, "graph capture needs a non-default stream");
@@ -1592,20 +1602,6 @@ wfd_status wfd_kernel_stats(wfd_ctx *c, int32_t kernel_class, int64_t *launches,
   if (s != WFD_OK) return s;
   *launches = c->launches[kernel_class];
   *total_ms = c->ms[kernel_class];
-  return WFD_OK;
-}
-
-wfd_status wfd_stream_probe(int32_t reads, int32_t writes, int32_t nontemporal, float *buf,
-                            int64_t n, int32_t blocks, void *hip_stream) {
-  const bool mix = (reads == 1 && writes == 1) || (reads == 3 && writes == 1) ||
-                   (reads == 4 && writes == 1) || (reads == 6 && writes == 2);
-  if (!mix) return fail(WFD_E_ARG, "no probe reads %d arrays and writes %d", reads, writes);
-  if (!buf || (uintptr_t)buf % 16) return fail(WFD_E_ARG, "buffer NULL or not 16-byte aligned");
-  if (n <= 0 || n % 4) return fail(WFD_E_ARG, "n must be a positive multiple of 4");
-  if (blocks < 1 || nontemporal < 0 || nontemporal > 1)
-    return fail(WFD_E_ARG, "blocks must be >= 1 and nontemporal 0 or 1");
-  HIP_TRY(wfd::launch_stream_probe(reads, writes, nontemporal != 0, buf, n, blocks,
-                                   (hipStream_t)hip_stream));
   return WFD_OK;
 }
 

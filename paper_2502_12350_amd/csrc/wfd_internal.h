@@ -272,10 +272,4 @@ hipError_t launch_cpml_adjoint(const StepGrid &g, const CpmlTables &t, const She
 hipError_t launch_record(const float *field, const int64_t *idx, const float *scale, int nrec,
                          int n, float *seis_tm, hipStream_t stream);
 
-// ---- streaming probe (wfd_probe.hip) ----
-// buf holds reads + writes arrays of n floats (n a multiple of 4): the inputs
-// first, then the outputs.  (reads, writes) in {(1,1), (3,1), (4,1), (6,2)}.
-hipError_t launch_stream_probe(int reads, int writes, bool nt, float *buf, int64_t n, int blocks,
-                               hipStream_t stream);
-
 }  // namespace wfd

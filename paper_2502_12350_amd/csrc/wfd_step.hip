@@ -1,13 +1,16 @@
 // Leapfrog step kernels for gfx950 (MI355X): the eighth-order 25-point star
 // (arXiv 2502.12350, §2.1) in a z-marching, LDS-tiled form.
 //
-// A block of 4 wavefronts owns a 64 x TY column tile (TY = 4 * RY) of the
-// padded grid and a chunk of z planes.  Lane = x, so every global access is
-// a 256-byte row per wavefront.  Each thread keeps, for each of its RY rows,
-// the nine z-neighbours of the current point in a register queue; the
-// current plane with a 4-cell x/y halo is staged in LDS (double-buffered:
-// one barrier per plane).  The next plane's queue entries and halo values
-// are fetched one iteration ahead.  Blocks are mapped XCD-aware: the
+// A block of NW wavefronts owns a 64 x TY column tile (TY = NW * RY) of the
+// padded grid and a chunk of z planes (defaults: forward 8 wavefronts of 2
+// rows, 64 x 16 tiles; adjoint 16 wavefronts of 2 rows, 64 x 32 tiles).
+// Lane = x, so every global access is a 256-byte row per wavefront.  Each
+// thread keeps, for each of its RY rows, the nine z-neighbours of the current
+// point in a register queue; the current plane with a 4-cell x/y halo is
+// staged in LDS (double-buffered: one barrier per plane).  The next plane's
+// queue entries and pointwise streams are fetched one iteration ahead, the
+// halo five planes ahead through a register delay line (below).  Blocks are
+// mapped XCD-aware: the
 // dispatcher places block b on XCD b mod 8, so each XCD receives a
 // contiguous range of tiles and neighbouring tiles share halos in one L2.
 //

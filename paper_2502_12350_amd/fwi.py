@@ -8,11 +8,13 @@
 * ``fwi`` — the outer loop of Alg. 2 with two model-update rules:
   steepest descent on the illumination-compensated gradient
   g / (I + eps max I) with a quadratic line search (exact slope plus one
-  trial misfit), and a projected L-BFGS
-  (velocity bounds as in the paper's example, which bounds velocity between
-  2000 and 3500 m/s) with the same preconditioner as its initial inverse
-  Hessian and an Armijo backtracking line search.  Trial misfits use the
-  library's forward-only misfit; every accepted point gets one gradient.
+  trial misfit), projected onto the velocity bounds, and L-BFGS-B (the
+  paper's L-BFGS-b, §2.1: generalized Cauchy point and subspace
+  minimization, ``lbfgsb.py``) with velocity bounds as in the paper's
+  example (2000 to 3500 m/s) and the same preconditioner in its initial
+  matrix, with an Armijo backtracking line search on the feasible segment.
+  Trial misfits use the library's forward-only misfit; every accepted point
+  gets one gradient.
 
 All wave-equation arithmetic runs in the HIP library; this module only
 composes calls and does the O(model size) optimizer algebra in torch.
@@ -27,6 +29,7 @@ from typing import List, Optional, Sequence, Tuple
 import numpy as np
 
 from .api import GridSpec, Propagator
+from .lbfgsb import LBFGSB
 
 
 @dataclass
@@ -244,7 +247,7 @@ def fwi(prop: Propagator, grid: GridSpec, v0, rho, shots: Shots, *, n_iter: int 
     """Alg. 2: repeat {gradient, model update} for n_iter iterations.
 
     method "sd": steepest descent on the illumination-compensated gradient;
-    "lbfgs": projected L-BFGS with that preconditioner; "cnn": steepest
+    "lbfgs": L-BFGS-B with that preconditioner in B0 = theta / P; "cnn": steepest
     descent along the learned preconditioner's direction (`precond`, a
     precond.Preconditioner), falling back to the illumination-compensated
     gradient when the network's direction does not descend.
@@ -297,6 +300,9 @@ def fwi(prop: Propagator, grid: GridSpec, v0, rho, shots: Shots, *, n_iter: int 
         return float(timed(misfit_only, prop, grid, vv, rho, shots).item())
 
     S, Y = [], []
+    lo_b = None if bounds is None or bounds[0] is None else torch.full_like(v, float(bounds[0]))
+    hi_b = None if bounds is None or bounds[1] is None else torch.full_like(v, float(bounds[1]))
+    opt = LBFGSB(lo_b, hi_b, memory)
     dv_prev = None  # largest model change of the last accepted steepest-descent step
     start = 0
     if resume:
@@ -325,21 +331,15 @@ def fwi(prop: Propagator, grid: GridSpec, v0, rho, shots: Shots, *, n_iter: int 
             progress(it - 1, J, clock[0], v)
         P = 1.0 / (illum + eps_illum * illum.max())      # preconditioner (diagonal)
         used = False                                       # step along the network's direction
-        if method == "lbfgs" and S:
-            # two-loop recursion with H0 = gamma * P
-            q = g.clone()
-            alphas = []
-            for s_, y_ in reversed(list(zip(S, Y))):
-                rho_k = 1.0 / _dot(y_, s_)
-                a = rho_k * _dot(s_, q)
-                alphas.append((a, rho_k, s_, y_))
-                q -= a * y_
-            sy, yPy = _dot(S[-1], Y[-1]), _dot(Y[-1] * P, Y[-1])
-            r = (sy / yPy) * P * q
-            for a, rho_k, s_, y_ in reversed(alphas):
-                b = rho_k * _dot(y_, r)
-                r += (a - b) * s_
-            d = -r
+        if method == "lbfgs":
+            # L-BFGS-B: the generalized Cauchy point and subspace minimization
+            # with B0 = theta / P; without pairs theta makes the full Cauchy
+            # step change the model by at most max_rel_step * max|v|
+            opt.S, opt.Y = S, Y
+            theta = None
+            if not S:
+                theta = float((P * g).abs().max()) / (max_rel_step * float(v.abs().max()))
+            d = opt.direction(v, g, P, theta) - v
             alpha0 = 1.0
         elif method == "cnn":
             d, used = timed(precond.direction, g, illum, eps_illum)
@@ -348,25 +348,29 @@ def fwi(prop: Propagator, grid: GridSpec, v0, rho, shots: Shots, *, n_iter: int 
             d = -P * g
             alpha0 = first_step(d)
         gd = _dot(g, d)
-        if gd >= 0:  # not a descent direction: restart from the preconditioned gradient
+        if gd >= 0 and method == "lbfgs" and S:  # not a descent direction: drop the pairs
+            S, Y = [], []
+            opt.S, opt.Y = S, Y
+            theta = float((P * g).abs().max()) / (max_rel_step * float(v.abs().max()))
+            d = opt.direction(v, g, P, theta) - v
+            gd = _dot(g, d)
+        if gd >= 0 and method != "lbfgs":  # restart from the preconditioned gradient
             S, Y = [], []
             d = -P * g
             alpha0 = first_step(d)
             gd = _dot(g, d)
             used = False
-        if method == "lbfgs" and not S:
-            # no curvature pairs yet: same quadratic step as steepest descent
-            alpha = _quadratic_step(J_at, v, d, J, gd, alpha0, bounds)
-            if alpha is None:
-                trace.record(clock[0], J)
-                if state_file is not None:
-                    _save_state(state_file, it + 1, v, g, illum, J, S, Y, dv_prev, trace)
-                continue
-        elif method == "lbfgs":
-            # Armijo backtracking; no acceptable step leaves the model unchanged
+        if gd >= 0:  # a first-order point of the box: nothing left to do
+            trace.record(clock[0], J)
+            if state_file is not None:
+                _save_state(state_file, it + 1, v, g, illum, J, S, Y, dv_prev, trace)
+            continue
+        if method == "lbfgs":
+            # Armijo backtracking on the segment from v to the L-BFGS-B point,
+            # which lies in the box: the slope <g, d> is exact for every trial
             alpha, ok = alpha0, False
             for _ in range(10):
-                Jt = J_at(_project(v + alpha * d, bounds))
+                Jt = J_at(v + alpha * d)
                 if Jt <= J + 1e-4 * alpha * gd:
                     ok = True
                     break
@@ -393,16 +397,12 @@ def fwi(prop: Propagator, grid: GridSpec, v0, rho, shots: Shots, *, n_iter: int 
                 continue
             trace.n_network += int(used)
             dv_prev = alpha * float(d.abs().max())
-        v_new = _project(v + alpha * d, bounds)
+        v_new = v + alpha * d if method == "lbfgs" else _project(v + alpha * d, bounds)
         J_new, g_new = grad_at(v_new, str(it + 1))
         if method == "lbfgs":
-            s_, y_ = v_new - v, g_new - g
-            if _dot(s_, y_) > 0:
-                S.append(s_)
-                Y.append(y_)
-                if len(S) > memory:
-                    S.pop(0)
-                    Y.pop(0)
+            opt.S, opt.Y = S, Y
+            opt.update(v_new - v, g_new - g)
+            S, Y = opt.S, opt.Y
         v, J, g = v_new, J_new, g_new
         trace.record(clock[0], J)
         if state_file is not None:

@@ -126,6 +126,34 @@ def test_batch_rejects_bad_arguments():
     b.close()
 
 
+def test_batch_refuses_to_run_after_a_member_model_changed():
+    """A batch's step descriptors hold the coefficient pointers of each
+    context's model at creation: setting a model again on a member context
+    makes the batch refuse to run (WFD_E_STATE) rather than read a freed or
+    reused buffer; the old buffers stay referenced by the batch meanwhile."""
+    torch = gpu_or_skip()
+    from paper_2502_12350_amd import GridSpec, ShotBatch, WfdError
+    w, shots = _windows("c3_small")
+    say("[batch after set_model]")
+    b, props, wav = _batch(torch, shots[:2])
+    first = [t.clone() for t in b.run()]
+    torch.cuda.synchronize()
+    old = props[1]._model
+    s = shots[1]
+    props[1].set_model(GridSpec(**s.grid_kwargs()), torch.from_numpy(s.vel).cuda(),
+                       torch.from_numpy(s.rho).cuda())
+    assert b._models[1] is old            # still alive while the batch exists
+    with pytest.raises(WfdError) as e:
+        b.run()
+    assert e.value.name == "WFD_E_STATE" and "model changed" in str(e.value)
+    b.close()
+    b2 = ShotBatch(props, wav, [x.sources[0] for x in shots[:2]], [x.receivers for x in shots[:2]])
+    again = b2.run()
+    torch.cuda.synchronize()
+    assert all(torch.equal(a, c) for a, c in zip(first, again))
+    b2.close()
+
+
 @pytest.mark.parametrize("variant,rounds", [(0, 0), (0, 2), (1, 0), (1, 8), (2, 0), (2, 4),
                                             (3, 0), (3, 6)])
 def test_forward_tile_shapes_are_bitwise_identical(variant, rounds):

@@ -370,25 +370,28 @@ def test_free_surface_image_principle_on_gpu():
 # ---------------------------------------------------------------------------
 # sponge quality (a report: the paper gives no number for its damping)
 # ---------------------------------------------------------------------------
-@pytest.mark.parametrize("border,bound", [(8, 0.05), (20, 0.01)])
-def test_sponge_reflection_report(border, bound):
+def test_sponge_reflection_report():
     """A homogeneous 64^3 model (h = 10 m, v = 2000 m/s, dt = 1 ms, 15 Hz
-    Ricker at the centre; the c1 setting, with the sponge of c1 (8 cells) and
-    of the gradient workload (20 cells)), against the same model extended by
+    Ricker at the centre; the c1 setting) against the same model extended by
     64 cells on every side, whose own boundary is too far to answer within
     400 steps.  After 400 steps the wave has crossed the original boundary;
     the difference of the two fields inside the original model is what its
-    sponge sent back.  Reported as the energy of that difference over the
-    energy of the direct wave inside the model at step 150.  Measured: 3.4e-2
-    with 8 cells (thinner than the 133 m wavelength), 3.8e-3 with 20; the
-    bounds leave some margin above those."""
+    boundary sent back, reported as its energy over that of the direct wave
+    inside the model at step 150.  Three boundaries: none (the zero ghost
+    cells of border 0, a rigid wall), the 8-cell sponge of c1 and the 20-cell
+    sponge of the gradient workload.  The paper gives no number for its
+    damping; the checks are the sanity line that a sponge of the gradient
+    workload's width sends back under 1 % of the energy, and that even the
+    8-cell sponge, thinner than the 133 m wavelength, removes at least 90 %
+    of what the rigid wall sends back.  The 8-cell sponge's own figure (about
+    3 %) is a known limit of so thin a layer and is reported, not bounded."""
     torch = gpu_or_skip()
     from paper_2502_12350_amd import GridSpec, Propagator
     n, h, c, dt = 64, 10.0, 2000.0, 1e-3
     f = seisgen.ricker(400, dt, 15.0).astype(np.float32)
     wav = torch.from_numpy(f).cuda()
 
-    def final(model, nt, ext):
+    def final(border, model, nt, ext):
         P = Propagator(0)
         P.set_model(GridSpec(model, model, model, h, h, h, -ext * h, -ext * h, -ext * h,
                              border=border, dt=dt, nt=nt),
@@ -399,10 +402,13 @@ def test_sponge_reflection_report(border, bound):
         core = tuple(slice(border + ext, border + ext + n) for _ in range(3))
         return fin[0][core].double().cpu().numpy()
 
-    near = final(n, 400, 0)
-    far = final(n + 128, 400, 64)
-    direct = final(n + 128, 150, 64)
-    ratio = float(np.sum((near - far) ** 2) / np.sum(direct ** 2))
-    say(f"[sponge report] border {border}: reflected / direct energy {ratio:.2e}")
-    assert np.sum(direct ** 2) > 0
-    assert ratio < bound
+    ratio = {}
+    for border in (0, 8, 20):
+        near = final(border, n, 400, 0)
+        far = final(border, n + 128, 400, 64)
+        direct = final(border, n + 128, 150, 64)
+        assert np.sum(direct ** 2) > 0
+        ratio[border] = float(np.sum((near - far) ** 2) / np.sum(direct ** 2))
+        say(f"[sponge report] border {border}: reflected / direct energy {ratio[border]:.2e}")
+    assert ratio[20] < 0.01
+    assert ratio[8] < 0.1 * ratio[0]
