@@ -174,6 +174,22 @@ wfd_status wfd_forward(wfd_ctx *ctx, const float *wavelet_dev, const double src_
                        int32_t nrec, const double *rec_xyz, float *seis_dev,
                        float *final_dev_or_null, void *work_dev, size_t work_bytes);
 
+/* wfd_forward for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same computation, bitwise, with the workspace taken from the library's
+ * own static device array of WFD_NOALLOC_SCRATCH_BYTES instead of a caller
+ * buffer.  Nothing is allocated.  The array is per GPU (each device that
+ * loads the library holds one until the process ends) and shared by every
+ * call on that GPU: calls that overlap on one GPU (several host threads, or
+ * several streams in flight) race and must be serialised by the caller.  A
+ * shot whose workspace (wfd_workspace_bytes with a NULL policy) exceeds the
+ * array returns WFD_E_NOMEM before anything is launched.  Arguments as for
+ * wfd_forward. */
+#define WFD_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+wfd_status wfd_forward_noalloc(wfd_ctx *ctx, const float *wavelet_dev, const double src_xyz[3],
+                               int32_t nrec, const double *rec_xyz, float *seis_dev,
+                               float *final_dev_or_null);
+
 /* Forward sweep of one shot and its misfit only (SeismicData::Misfit of
  * Alg. 3 without the backward sweep; line searches of the FWI loop need it):
  *   dobs_dev          [nrec][nt] FP32 observed traces, device;

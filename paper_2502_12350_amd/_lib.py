@@ -21,6 +21,7 @@ CKPT_REVOLVE = 1
 CKPT_HOST = 2
 K_FORWARD, K_ADJOINT, K_OTHER = 0, 1, 2
 CNN_REDUCE_BYTES = 8192
+NOALLOC_SCRATCH_BYTES = 64 << 20
 SMOOTH_LAPLACE, SMOOTH_BESSEL = 1, 2
 RESAMPLE_NEAREST, RESAMPLE_SINC = 1, 2
 
@@ -67,6 +68,7 @@ _SIGS = {
     "wfd_workspace_bytes": (C.c_int, [_P, C.c_int32, C.POINTER(wfd_ckpt), C.POINTER(C.c_size_t)]),
     "wfd_host_store_bytes": (C.c_int, [_P, C.POINTER(C.c_size_t)]),
     "wfd_forward": (C.c_int, [_P, _P, _D3, C.c_int32, _D3, _P, _P, _P, C.c_size_t]),
+    "wfd_forward_noalloc": (C.c_int, [_P, _P, _D3, C.c_int32, _D3, _P, _P]),
     "wfd_forward_misfit": (C.c_int, [_P, _P, _D3, C.c_int32, _D3, _P, _P, _P, _P, C.c_size_t]),
     "wfd_misfit_workspace_bytes": (C.c_int, [_P, C.c_int32, C.POINTER(C.c_size_t)]),
     "wfd_gradient": (C.c_int, [_P, _P, _D3, C.c_int32, _D3, _P, C.POINTER(wfd_ckpt), _P, _P,

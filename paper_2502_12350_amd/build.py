@@ -23,7 +23,7 @@ LIB = os.path.join(PKG, "libwfd.so")
 
 SOURCES = [
     "wfd_step.hip", "wfd_kernels.hip", "wfd_cnn.hip", "wfd_smooth.hip", "wfd_cpml.hip",
-    "wfd_api.cpp", "wfd_plan.cpp",
+    "wfd_noalloc.hip", "wfd_api.cpp", "wfd_plan.cpp",
 ]
 ARCH = "gfx950"
 

@@ -623,6 +623,14 @@ hipError_t time_steps(wfd_ctx *c, int steps, hipEvent_t e0, hipEvent_t e1, F lau
 
 }  // namespace
 
+namespace wfd {
+int ctx_device(const wfd_ctx *c) { return c->device; }
+wfd_status set_error(wfd_status status, const char *message) {
+  g_last_error = message;
+  return status;
+}
+}  // namespace wfd
+
 extern "C" {
 
 const char *wfd_last_error(void) { return g_last_error.c_str(); }

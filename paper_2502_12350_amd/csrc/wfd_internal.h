@@ -9,6 +9,11 @@
 
 namespace wfd {
 
+// Context queries and the thread-local error text, for the library's other
+// translation units (wfd_api.cpp owns both).
+int ctx_device(const wfd_ctx *c);
+wfd_status set_error(wfd_status status, const char *message);
+
 // Padded-grid geometry and coefficient volumes seen by every step kernel.
 // Volumes are [Nz][Ny][pitch] FP32 with pitch >= Nx (rows 256-byte aligned).
 struct StepGrid {
