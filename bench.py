@@ -88,7 +88,56 @@ def cpu_baseline(w, n_steps: int = 2):
                       f"{shape[2]}x{shape[1]}x{shape[0]} padded slab (32-plane model crop, same "
                       f"32-cell sponge), single process",
             "host_cpus": os.cpu_count(),
-            "seconds": round(t_f + t_a, 2)}
+            "seconds": round(t_f + t_a, 2),
+            "legs": cpu_legs()}
+
+
+def cpu_legs(n_steps: int = 2):
+    """The other workloads' oracle figures, one process: the whole 64^3 plain
+    forward run (200 steps on 80^3 padded points), and one shot of the
+    gradient workload (240 x 240 x 200 padded, 1200 steps) estimated from
+    timed steps: the oracle's gradient takes nt forward steps, about nt more
+    to recompute its segments, and nt adjoint steps with the imaging term."""
+    import numpy as np
+    import oracle
+    import seisgen
+
+    c1 = seisgen.workload("c1")
+    t0 = time.perf_counter()
+    oracle.forward(oracle.Grid(**c1.grid_kwargs()), c1.vel, c1.rho, c1.wavelet, c1.sources[0],
+                   c1.receivers)
+    t_c1 = time.perf_counter() - t0
+    c4 = seisgen.workload("c4_start")
+    g = oracle.Grid(**c4.grid_kwargs())
+    c = oracle.coefficients(g, c4.vel.astype(np.float64), None)
+    shape = g.padded_shape
+    rng = np.random.default_rng(1)
+    f = [rng.standard_normal(shape) * 1e-6 for _ in range(4)]
+    gacc = np.zeros(shape)
+    t_f = t_a = 0.0
+    for _ in range(n_steps):
+        t0 = time.perf_counter()
+        f[1] = oracle.step(c, g, f[0], f[1])
+        t1 = time.perf_counter()
+        f[3] = oracle.step(c, g, f[2], f[3])
+        gacc += f[2] * (oracle.laplacian(f[0], g.h) - c.m2 * f[0])
+        t2 = time.perf_counter()
+        t_f += t1 - t0
+        t_a += t2 - t1
+        f = [f[1], f[0], f[3], f[2]]
+    per_f, per_a = t_f / n_steps, t_a / n_steps
+    shot = c4.nt * (2 * per_f + per_a)
+    pts4 = shape[0] * shape[1] * shape[2]
+    return {"c1_full_run": {"seconds": round(t_c1, 2),
+                            "gpts": round(c1.padded_points * c1.nt / t_c1 / 1e9, 5),
+                            "what": "oracle.forward, 64^3 + 8-cell sponge, 200 steps, 64 receivers"},
+            "c4_shot_estimate": {"seconds": round(shot, 1),
+                                 "gpts": round(2 * c4.nt * pts4 / shot / 1e9, 5),
+                                 "what": f"{c4.nt} x (2 forward + 1 adjoint/imaging) steps at "
+                                         f"{shape[2]}x{shape[1]}x{shape[0]}, from "
+                                         f"{n_steps} timed steps of each",
+                                 "forward_step_s": round(per_f, 3),
+                                 "adjoint_step_s": round(per_a, 3)}}
 
 
 def copy_probe(gib: float = 4.0, reps: int = 10):

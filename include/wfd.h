@@ -271,11 +271,14 @@ wfd_status wfd_gradient_finish(wfd_ctx *ctx, float *grad_dev, int32_t zero_top_p
 /* Launch shapes of the context's step kernels: the GPU counterpart of the
  * paper's autotuning of the OpenMP chunk size of its time-step loop (PATSMA,
  * Alg. 1 and Alg. 3).  The choices are CDNA4 tiles and z chunkings:
- *   fwd_variant  forward tiles (rows per thread x wavefronts per block):
- *                0: 2x8 = 64x16 tiles [default]  1: 2x16 = 64x32
- *                2: 2x4 = 64x8                    3: 4x4 = 64x16
- *   adj_variant  adjoint tiles: 0: 2x16 = 64x32 [default]  1: 2x8 = 64x16
- *                2: 2x4 = 64x8
+ *   fwd_variant  forward tiles (rows per thread x wavefronts per block x
+ *                64-column groups per thread):
+ *                0: 2x8x1 = 64x16 tiles [default]  1: 2x16x1 = 64x32
+ *                2: 2x4x1 = 64x8                     3: 4x4x1 = 64x16
+ *                4: 1x16x3 = 192x16
+ *   adj_variant  adjoint tiles: 0: 2x16x1 = 64x32 [default]
+ *                1: 2x8x1 = 64x16 with a two-plane halo delay
+ *                2: 2x4x1 = 64x8  3: 2x8x1 = 64x16, halo loaded one plane ahead
  *   *_rounds     z chunking aims at this many rounds of resident blocks per
  *                launch (at most 64); 0 = automatic: the chunk count that
  *                minimises a model of the launch time (rounds of resident

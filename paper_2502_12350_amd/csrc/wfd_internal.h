@@ -70,13 +70,16 @@ struct TileMap {
   int tiles_x, tiles_y, nchunks, zc, nblocks;
 };
 
-// Step-kernel tuning.  Tile shapes (rows per thread x wavefronts per block):
-//   forward  0: 2x8 (64x16 tiles)  1: 2x16 (64x32)  2: 2x4 (64x8)  3: 4x4 (64x16)
-//   adjoint  0: 2x16 (64x32)       1: 2x8 (64x16)   2: 2x4 (64x8)
+// Step-kernel tuning.  Tile shapes (rows per thread x wavefronts per block
+// x 64-column groups per thread):
+//   forward  0: 2x8x1 (64x16 tiles)  1: 2x16x1 (64x32)  2: 2x4x1 (64x8)
+//            3: 4x4x1 (64x16)        4: 1x16x3 (192x16)
+//   adjoint  0: 2x16x1 (64x32)       1: 2x8x1 (64x16, 2-plane halo delay)
+//            2: 2x4x1 (64x8)         3: 2x8x1 (64x16, halo one plane ahead)
 // and the number of rounds of resident blocks the z chunking aims for
 // (0 = chosen by the launch cost model).  Every shape computes bitwise the
 // same values.
-constexpr int kFwdVariants = 4, kAdjVariants = 3;
+constexpr int kFwdVariants = 5, kAdjVariants = 4;
 struct Tuning {
   int variant = 0;
   int rounds = 0;

@@ -20,6 +20,9 @@ c2_small  the same generator on a small ragged grid (93 x 77 x 61, 16-cell
           sponge, 300 steps) for element-wise parity; extra["v_true"] adds
           three +/-8 % blobs to a 3 % faster background (the observed-data
           model of gradient parity).
+c2_crop   a 128^3 crop of the c2 model (x, y in [192, 320), z in [0, 128)),
+          c2's sponge, dt, wavelet, source node and receivers inside the crop,
+          500 steps (element-wise parity on the c2 model itself).
 c3        400 x 400 x 256 model from the c2 generator (seed 2503), 32-cell
           sponge, 1500 steps, 24 shots on a 6 x 4 surface grid at depth
           index 4; shot i runs on its own aperture window: a square in x-y of
@@ -147,6 +150,23 @@ def _c2_small() -> Workload:
     return w
 
 
+def _c2_crop(n: int = 128, nt: int = 500) -> Workload:
+    """A 128^3 crop of the c2 model (same generator, seed and density): x, y
+    in [192, 320), z in [0, 128), so the source node (256, 256, 8) and the
+    receivers of c2 that fall inside it keep their positions; the c2 sponge
+    (32 cells), dt and wavelet; 500 steps."""
+    full = _c2()
+    x0 = y0 = (512 - n) // 2
+    vel = np.ascontiguousarray(full.vel[:n, y0:y0 + n, x0:x0 + n])
+    rho = np.ascontiguousarray(full.rho[:n, y0:y0 + n, x0:x0 + n])
+    h = full.dx
+    src = [[256 - x0, 256 - y0, 8]]
+    rec = _surface_grid(1, 2, n // 2, 1, 2, n // 2, 4)   # c2's odd nodes inside the crop
+    return Workload("c2_crop", n, n, n, h, h, h, 0.0, 0.0, 0.0, full.border, full.dt, nt, vel,
+                    rho, full.wavelet[:nt].copy(), _metres(src, (h, h, h)),
+                    _metres(rec, (h, h, h)))
+
+
 def _c3(nx=400, ny=400, nz=256, border=32, nt=1500, shots_xy=(6, 4), side=(160, 321),
         seed=2503, name="c3") -> Workload:
     h = 10.0
@@ -259,6 +279,7 @@ WORKLOADS: Dict[str, Callable[[], Workload]] = {
     "c1_long": lambda: _c1(400),
     "c2": _c2,
     "c2_small": _c2_small,
+    "c2_crop": _c2_crop,
     "c3": _c3,
     "c3_small": lambda: _c3(nx=96, ny=80, nz=48, border=8, nt=250, shots_xy=(2, 2),
                             side=(24, 49), name="c3_small"),

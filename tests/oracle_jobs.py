@@ -44,10 +44,29 @@ def _gradient_c2_small(variant: str):
     return dobs, ref
 
 
+_wl = {}
+
+
+def cached_workload(name: str):
+    """seisgen.workload(name), built once per session (c2_crop cuts the 512^3
+    c2 model, about 20 s)."""
+    with _lock:
+        if name not in _wl:
+            _wl[name] = seisgen.workload(name)
+        return _wl[name]
+
+
+def _forward_c2_crop():
+    w = cached_workload("c2_crop")
+    return oracle.forward(oracle.Grid(**w.grid_kwargs()), w.vel, w.rho, w.wavelet, w.sources[0],
+                          w.receivers)
+
+
 CASES = {
     "c2_small_vd": lambda: _gradient_c2_small("vd"),
     "c2_small_cd": lambda: _gradient_c2_small("cd"),
     "c2_small_fs": lambda: _gradient_c2_small("fs"),
+    "c2_crop": _forward_c2_crop,
 }
 
 

@@ -146,7 +146,7 @@ def test_adjoint_tile_shapes_bitwise_on_ragged_grid():
         np.float32) * np.float32(1e-12)
     say("[adjoint tiles bitwise] c2_small")
     out = []
-    for v in (0, 1, 2):
+    for v in (0, 1, 2, 3):
         P = _prop(w)
         P.set_tuning(0, 0, v, 0)
         J, g, _, il = _gpu_gradient(P, w, dobs)

@@ -155,7 +155,7 @@ def test_batch_refuses_to_run_after_a_member_model_changed():
 
 
 @pytest.mark.parametrize("variant,rounds", [(0, 0), (0, 2), (1, 0), (1, 8), (2, 0), (2, 4),
-                                            (3, 0), (3, 6)])
+                                            (3, 0), (3, 6), (4, 0), (4, 3)])
 def test_forward_tile_shapes_are_bitwise_identical(variant, rounds):
     torch = gpu_or_skip()
     w = seisgen.workload("c2_small")
@@ -172,7 +172,8 @@ def test_forward_tile_shapes_are_bitwise_identical(variant, rounds):
     assert torch.equal(f, fb)
 
 
-@pytest.mark.parametrize("adj_variant,adj_rounds", [(0, 2), (1, 0), (1, 8), (2, 0), (2, 3)])
+@pytest.mark.parametrize("adj_variant,adj_rounds", [(0, 2), (1, 0), (1, 8), (2, 0), (2, 3), (3, 0),
+                                                    (3, 4)])
 def test_adjoint_tile_shapes_are_bitwise_identical(adj_variant, adj_rounds):
     torch = gpu_or_skip()
     w = seisgen.workload("c4_fd_vd")
@@ -277,7 +278,7 @@ def test_batch_with_free_surface_windows_equals_per_shot():
     b.close()
 
 
-@pytest.mark.parametrize("variant,adj_variant", [(1, 1), (2, 2), (3, 1)])
+@pytest.mark.parametrize("variant,adj_variant", [(1, 1), (2, 2), (3, 1), (4, 3)])
 def test_tile_shapes_bitwise_identical_with_free_surface(variant, adj_variant):
     torch = gpu_or_skip()
     from paper_2502_12350_amd import GridSpec, Propagator

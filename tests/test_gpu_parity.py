@@ -49,6 +49,22 @@ def test_forward_variable_density_ragged_matches_oracle():
     assert rel_l2(fin[0], ref.last) <= SEIS_TOL
 
 
+@pytest.mark.oracle_refs("c2_crop")
+def test_forward_c2_model_crop_matches_oracle():
+    """The variable-density forward on a 128^3 crop of the 512^3 benchmark
+    model itself (c2's generator, seed, density, sponge, dt and wavelet; its
+    source node and the 4096 receivers inside the crop), 500 steps."""
+    import oracle_jobs
+    w = oracle_jobs.cached_workload("c2_crop")
+    say(f"[forward VD] c2_crop padded {w.padded_shape} nt {w.nt} nrec {len(w.receivers)}")
+    seis, fin = gpu_forward(w, final=True)
+    ref = oracle_jobs.result("c2_crop")
+    e = rel_l2(seis, ref.seis)
+    ef = rel_l2(fin[0], ref.last)
+    say(f"  seismogram rel-L2 {e:.3e}  final field rel-L2 {ef:.3e}")
+    assert e <= SEIS_TOL and ef <= SEIS_TOL
+
+
 def test_forward_edge_geometry():
     """Source and receivers on model corners / faces, duplicates, ragged tiles."""
     n = (37, 29, 23)
