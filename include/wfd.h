@@ -344,6 +344,50 @@ wfd_status wfd_batch_run(wfd_batch *batch, int32_t use_graph);
  * caller's buffers).  NULL is accepted. */
 wfd_status wfd_batch_destroy(wfd_batch *batch);
 
+/* A batch of shots whose whole gradients (Alg. 3 body for each shot) run
+ * together: every forward step and every adjoint step of the binomial
+ * checkpointing schedule is ONE kernel launch over the tiles of every shot,
+ * and the whole sequence can be captured once into a HIP graph.  The shots
+ * share the schedule (equal nt and n_snapshots), so their stored states and
+ * recomputations line up.  Each shot has its own context (model on its own
+ * grid, e.g. the window around its source) and workspace; results are
+ * bitwise those of wfd_gradient on each context with WFD_CKPT_REVOLVE and
+ * n_snapshots pairs.
+ *   nshot            1..64;
+ *   ctxs[i]          contexts with a model on one device and stream, equal nt,
+ *                    one density mode, sponge boundaries (no CPML), each used
+ *                    once; shot 0's tile shapes (wfd_set_tuning) are used for
+ *                    every shot;
+ *   wavelet_dev      [nt] FP32 source signature shared by all shots;
+ *   src_xyz          host [nshot][3]; nrec, rec_xyz per shot as in wfd_batch_create;
+ *   dobs_dev[i]      [nrec[i]][nt] FP32 observed traces of shot i;
+ *   n_snapshots      checkpoint pairs per shot (>= 1);
+ *   misfit_dev[i]    device FP64 scalar, accumulated (+= J_i);
+ *   grad_dev[i]      [nz][ny][nx] of shot i's grid, accumulated (+= dJ_i/dv);
+ *   illum_dev_or_null  NULL, or per-shot [nz][ny][nx] accumulated illumination
+ *                    (given for every shot or for none);
+ *   work_dev[i], work_bytes[i]  per-shot workspace of at least
+ *                    wfd_workspace_bytes(ctxs[i], nrec[i], REVOLVE n_snapshots),
+ *                    256-byte aligned; shot 0's also holds the descriptors.
+ * Receiver tables and scales are built here.  Everything must stay allocated
+ * until wfd_gbatch_destroy; a context whose model is set again makes
+ * wfd_gbatch_run return WFD_E_STATE. */
+typedef struct wfd_gbatch wfd_gbatch;
+wfd_status wfd_gbatch_create(wfd_gbatch **batch, int32_t nshot, wfd_ctx *const *ctxs,
+                             const float *wavelet_dev, const double *src_xyz,
+                             const int32_t *nrec, const double *const *rec_xyz,
+                             const float *const *dobs_dev, int32_t n_snapshots,
+                             double *const *misfit_dev, float *const *grad_dev,
+                             float *const *illum_dev_or_null, void *const *work_dev,
+                             const size_t *work_bytes);
+
+/* Enqueue the batched gradients (as wfd_batch_run: use_graph != 0 captures the
+ * sequence into a HIP graph on the first call and replays it). */
+wfd_status wfd_gbatch_run(wfd_gbatch *batch, int32_t use_graph);
+
+/* Wait for the stream if a graph exists and release the batch.  NULL is accepted. */
+wfd_status wfd_gbatch_destroy(wfd_gbatch *batch);
+
 /* ---- host-only helpers (no GPU needed) --------------------------------- */
 
 /* Padded-grid node (ix, iy, iz) of a position in metres (rule above). */

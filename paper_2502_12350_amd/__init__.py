@@ -8,9 +8,10 @@ behind a C ABI (include/wfd.h).  PyTorch supplies device memory and streams.
 
 from ._lib import (WfdError, LIB_PATH, CKPT_FULL, CKPT_REVOLVE, CKPT_HOST, K_FORWARD, K_ADJOINT,
                    K_OTHER)
-from .api import (GridSpec, Propagator, ShotBatch, smooth, resample, map_position, cfl_ratio,
-                  checkpoint_plan, model_bytes)
+from .api import (GridSpec, Propagator, ShotBatch, GradientBatch, smooth, resample, map_position,
+                  cfl_ratio, checkpoint_plan, model_bytes)
 
 __all__ = ["WfdError", "LIB_PATH", "CKPT_FULL", "CKPT_REVOLVE", "CKPT_HOST", "K_FORWARD",
-           "K_ADJOINT", "K_OTHER", "GridSpec", "Propagator", "ShotBatch", "smooth", "resample",
+           "K_ADJOINT", "K_OTHER", "GridSpec", "Propagator", "ShotBatch", "GradientBatch", "smooth",
+           "resample",
            "map_position", "cfl_ratio", "checkpoint_plan", "model_bytes"]

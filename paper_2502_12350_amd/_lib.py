@@ -85,6 +85,13 @@ _SIGS = {
                                    C.POINTER(C.c_void_p), C.POINTER(C.c_void_p),
                                    C.POINTER(C.c_size_t)]),
     "wfd_batch_run": (C.c_int, [_P, C.c_int32]),
+    "wfd_gbatch_create": (C.c_int, [C.POINTER(C.c_void_p), C.c_int32, C.POINTER(C.c_void_p), _P,
+                                    _D3, C.POINTER(C.c_int32), C.POINTER(_D3),
+                                    C.POINTER(C.c_void_p), C.c_int32, C.POINTER(C.c_void_p),
+                                    C.POINTER(C.c_void_p), C.POINTER(C.c_void_p),
+                                    C.POINTER(C.c_void_p), C.POINTER(C.c_size_t)]),
+    "wfd_gbatch_run": (C.c_int, [_P, C.c_int32]),
+    "wfd_gbatch_destroy": (C.c_int, [_P]),
     "wfd_batch_destroy": (C.c_int, [_P]),
     "wfd_cnn_packed_elems": (C.c_int, [C.c_int32, C.c_int32, C.c_int32, C.POINTER(C.c_int64)]),
     "wfd_cnn_pack_weights": (C.c_int, [_P, C.c_int32, C.c_int32, C.c_int32, _P, _P]),

@@ -480,3 +480,87 @@ class ShotBatch:
             self.close()
         except Exception:
             pass
+
+
+class GradientBatch:
+    """Misfits and velocity gradients of several shots computed together: every
+    forward and adjoint step of the shared binomial checkpointing schedule is
+    one launch over all shots' tiles, optionally replayed as one HIP graph.
+
+    Each shot has its own Propagator (its own model, typically the window
+    around its source) on one device; the results equal each Propagator's
+    gradient(..., ckpt=("revolve", n_snapshots)) bitwise.  run() adds every
+    shot's misfit and gradient (and illumination) into the tensors it returns.
+    """
+
+    def __init__(self, props: Sequence[Propagator], wavelet, src_xyz, rec_xyz, dobs,
+                 n_snapshots: int, illum: bool = False, stream=None):
+        if not props:
+            raise ValueError("no shots")
+        torch = props[0].torch
+        p0 = props[0]
+        self.torch = torch
+        self.props = list(props)
+        self._models = [p._model for p in self.props]
+        self.stream = stream if stream is not None else torch.cuda.current_stream(p0.device)
+        nt = p0.grid.nt if p0.grid is not None else 0
+        self.wavelet = p0._dev(wavelet, "wavelet", (nt,), torch.float32)
+        n = len(self.props)
+        if len(src_xyz) != n or len(rec_xyz) != n or len(dobs) != n:
+            raise ValueError("one source, receiver array and data array per shot")
+        self._src = np.ascontiguousarray(np.concatenate([_xyz(s) for s in src_xyz]),
+                                         dtype=np.float64)
+        self._rec = [_xyz(r) if r is not None and len(r) else np.zeros((0, 3)) for r in rec_xyz]
+        nrec = [r.shape[0] for r in self._rec]
+        self.dobs = [p._dev(d, "dobs", (k, nt), torch.float32) if k else None
+                     for p, d, k in zip(self.props, dobs, nrec)]
+        self.misfit = torch.zeros(n, dtype=torch.float64, device=p0.device)
+        self.grad = [torch.zeros((p.grid.nz, p.grid.ny, p.grid.nx), dtype=torch.float32,
+                                 device=p0.device) for p in self.props]
+        self.illum = ([torch.zeros_like(g) for g in self.grad] if illum else None)
+        self._work = []
+        ctxs = (C.c_void_p * n)()
+        works = (C.c_void_p * n)()
+        wbytes = (C.c_size_t * n)()
+        dob = (C.c_void_p * n)()
+        mis = (C.c_void_p * n)()
+        grd = (C.c_void_p * n)()
+        ill = (C.c_void_p * n)()
+        recp = (_lib._D3 * n)()
+        for i, p in enumerate(self.props):
+            if p.grid is None:
+                raise RuntimeError(f"shot {i}: set_model first")
+            check(p.L.wfd_set_stream(p._ctx, C.c_void_p(self.stream.cuda_stream)))
+            nb = p.workspace_bytes(nrec[i], ("revolve", int(n_snapshots)))
+            buf, ptr = p._buffer(nb)
+            self._work.append(buf)
+            ctxs[i], works[i], wbytes[i] = p._ctx.value, ptr, nb
+            dob[i] = _ptr(self.dobs[i])
+            mis[i] = self.misfit.data_ptr() + 8 * i
+            grd[i] = _ptr(self.grad[i])
+            ill[i] = _ptr(self.illum[i]) if illum else None
+            if nrec[i]:
+                recp[i] = _dptr(self._rec[i])
+        nr = (C.c_int32 * n)(*nrec)
+        self._b = C.c_void_p()
+        check(p0.L.wfd_gbatch_create(C.byref(self._b), n, ctxs, _ptr(self.wavelet),
+                                     _dptr(self._src), nr, recp, dob, int(n_snapshots), mis, grd,
+                                     ill if illum else None, works, wbytes))
+        self.L = p0.L
+
+    def run(self, use_graph: bool = False):
+        """Enqueue every shot's gradient on the batch stream (accumulating into
+        self.misfit [nshot], self.grad and self.illum); returns (misfit, grad)."""
+        check(self.L.wfd_gbatch_run(self._b, int(bool(use_graph))))
+        return self.misfit, self.grad
+
+    def close(self):
+        if getattr(self, "_b", None):
+            check(self.L.wfd_gbatch_destroy(self._b))
+            self._b = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -335,6 +335,7 @@ struct Work {
   float *seis_tm;
   float *W1, *W2;
   wfd::WindowStep *wins;  // batch step descriptors (two parities x kMaxBatch)
+  wfd::GradWindow *gwins;  // batched-gradient window descriptors (kMaxBatch)
   // gradient only
   float *res_tm, *P1, *P2, *g, *store;
   double *partial;
@@ -428,6 +429,7 @@ Work work_layout(const wfd_ctx *c, int nrec, WorkKind kind, const wfd_ckpt *ck, 
   w.W1 = cv.take<float>((size_t)c->vol);
   w.W2 = cv.take<float>((size_t)c->vol);
   w.wins = kind == WorkKind::Forward ? cv.take<wfd::WindowStep>(2 * kMaxBatch) : nullptr;
+  w.gwins = kind == WorkKind::Gradient ? cv.take<wfd::GradWindow>(kMaxBatch) : nullptr;
   if (kind != WorkKind::Forward) {
     w.res_tm = cv.take<float>((size_t)c->grid.nt * std::max(nrec, 1));
     w.partial = cv.take<double>((size_t)std::max(1, wfd::residual_partial_count(nrec, c->grid.nt)));
@@ -1551,6 +1553,303 @@ wfd_status wfd_batch_destroy(wfd_batch *b) {
   delete b;
   return WFD_OK;
 }
+
+// A batch of shots whose whole gradients (Alg. 3 body) run together: every
+// forward and adjoint step is one launch over the tiles of every shot, with
+// binomial checkpointing on one plan shared by all shots.
+struct wfd_gbatch {
+  std::vector<wfd_ctx *> ctxs;
+  std::vector<uint64_t> model_gen;
+  std::vector<Work> work;
+  std::vector<int> nrec;
+  std::vector<const float *> dobs;
+  std::vector<double *> misfit;
+  std::vector<float *> grad;
+  std::vector<int32_t> plan;
+  wfd::GradWindow *d_wins = nullptr;  // in shot 0's workspace
+  int fblocks = 0, ablocks = 0, variant = 0, adj_variant = 0, nt = 0, nsnap = 0;
+  bool vd = false, fs = false, illum = false;
+  hipStream_t stream = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+wfd_status wfd_gbatch_create(wfd_gbatch **out, int32_t nshot, wfd_ctx *const *ctxs,
+                             const float *wavelet, const double *src_xyz, const int32_t *nrec,
+                             const double *const *rec_xyz, const float *const *dobs,
+                             int32_t n_snapshots, double *const *misfit_dev,
+                             float *const *grad_dev, float *const *illum_dev_or_null,
+                             void *const *work_dev, const size_t *work_bytes) {
+  if (!out) return fail(WFD_E_ARG, "batch pointer is NULL");
+  *out = nullptr;
+  if (nshot < 1 || nshot > kMaxBatch)
+    return fail(WFD_E_ARG, "batch size must be in [1, %d] (got %d)", kMaxBatch, nshot);
+  if (!ctxs || !src_xyz || !nrec || !work_dev || !work_bytes || !wavelet || !misfit_dev ||
+      !grad_dev)
+    return fail(WFD_E_ARG, "NULL argument");
+  if (n_snapshots < 1) return fail(WFD_E_ARG, "n_snapshots must be >= 1");
+  wfd_ctx *c0 = ctxs[0];
+  const bool illum = illum_dev_or_null && illum_dev_or_null[0];
+  for (int i = 0; i < nshot; ++i) {
+    wfd_ctx *c = ctxs[i];
+    if (!c || !c->has_model) return fail(WFD_E_STATE, "shot %d: context without a model", i);
+    if (c->device != c0->device) return fail(WFD_E_ARG, "shot %d: other device", i);
+    if (c->stream != c0->stream) return fail(WFD_E_ARG, "shot %d: contexts must share one stream", i);
+    if (c->grid.nt != c0->grid.nt) return fail(WFD_E_ARG, "shot %d: nt differs", i);
+    if (c->vd != c0->vd) return fail(WFD_E_ARG, "shot %d: density mode differs", i);
+    if (c->cpml) return fail(WFD_E_ARG, "shot %d: batches take sponge boundaries only", i);
+    if (nrec[i] < 0 || (nrec[i] > 0 && (!rec_xyz || !rec_xyz[i] || !dobs || !dobs[i])))
+      return fail(WFD_E_ARG, "shot %d: receivers / observed data missing", i);
+    if (!misfit_dev[i] || !grad_dev[i]) return fail(WFD_E_ARG, "shot %d: misfit / gradient output is NULL", i);
+    if (illum != (illum_dev_or_null && illum_dev_or_null[i]))
+      return fail(WFD_E_ARG, "shot %d: illumination outputs must be given for all shots or none", i);
+    if (!work_dev[i] || (uintptr_t)work_dev[i] % kAlign)
+      return fail(WFD_E_ARG, "shot %d: workspace NULL or not 256-byte aligned", i);
+    for (int j = 0; j < i; ++j)
+      if (ctxs[j] == c) return fail(WFD_E_ARG, "shot %d: context used twice", i);
+  }
+  ScopedDevice sd(c0->device);
+  wfd_gbatch *b = new (std::nothrow) wfd_gbatch();
+  if (!b) return fail(WFD_E_NOMEM, "out of host memory");
+  b->stream = c0->stream;
+  b->nt = c0->grid.nt;
+  b->nsnap = n_snapshots;
+  b->vd = c0->vd;
+  b->illum = illum;
+  b->variant = c0->tuning.variant;
+  b->adj_variant = c0->tuning.adj_variant;
+  for (int i = 0; i < nshot; ++i) b->fs = b->fs || ctxs[i]->grid.free_surface != 0;
+  int64_t nsteps = 0;
+  wfd::build_checkpoint_plan(b->nt, n_snapshots, b->plan, nsteps);
+  wfd_ckpt ck{};
+  ck.mode = WFD_CKPT_REVOLVE;
+  ck.n_snapshots = n_snapshots;
+  std::vector<wfd::GradWindow> h((size_t)nshot);
+  int foff = 0, aoff = 0;
+  for (int i = 0; i < nshot; ++i) {
+    wfd_ctx *c = ctxs[i];
+    Work w = work_layout(c, nrec[i], WorkKind::Gradient, &ck, n_snapshots, work_dev[i]);
+    if (work_bytes[i] < w.bytes) {
+      delete b;
+      return fail(WFD_E_NOMEM, "shot %d: workspace has %zu bytes, %zu needed", i, work_bytes[i],
+                  w.bytes);
+    }
+    int64_t src_idx = 0;
+    wfd_status s = prepare_shot(c, wavelet, src_xyz + 3 * (size_t)i, nrec[i],
+                                nrec[i] > 0 ? rec_xyz[i] : nullptr, w, src_idx);
+    if (s != WFD_OK) {
+      delete b;
+      return s;
+    }
+    wfd::Tuning tu = c->tuning;
+    tu.variant = b->variant;  // one tile shape per launch
+    tu.adj_variant = b->adj_variant;
+    wfd::GradWindow &d = h[(size_t)i];
+    d.g = step_grid(c);
+    const int nf = wfd::forward_tile_map(d.g, tu, &d.fmap);
+    const int na = wfd::adjoint_tile_map(d.g, tu, illum, &d.amap);
+    d.src = wfd::Source{src_idx, &w.scale->sigma, wavelet};
+    d.rec = rec_table(w, nrec[i]);
+    d.rec_scale = w.rec_scale;
+    d.seis_tm = w.seis_tm;
+    d.res_tm = w.res_tm;
+    d.W1 = w.W1;
+    d.W2 = w.W2;
+    d.store = w.store;
+    d.vol = c->vol;
+    d.P1 = w.P1;
+    d.P2 = w.P2;
+    d.gimg = w.g;
+    d.il = wfd::IllumOut{illum ? illum_dev_or_null[i] : nullptr, c->grid.border, c->grid.nx,
+                         c->grid.ny, c->grid.nz, w.scale, 0};
+    d.fblock_begin = foff;
+    d.fblock_end = foff + nf;
+    d.ablock_begin = aoff;
+    d.ablock_end = aoff + na;
+    foff += (nf + 7) / 8 * 8;  // ranges start at multiples of 8: XCD-aware order
+    aoff += (na + 7) / 8 * 8;
+    b->ctxs.push_back(c);
+    b->model_gen.push_back(c->model_gen);
+    b->work.push_back(w);
+    b->nrec.push_back(nrec[i]);
+    b->dobs.push_back(nrec[i] > 0 ? dobs[i] : nullptr);
+    b->misfit.push_back(misfit_dev[i]);
+    b->grad.push_back(grad_dev[i]);
+  }
+  b->fblocks = foff;
+  b->ablocks = aoff;
+  b->d_wins = b->work[0].gwins;
+  if (hipMemcpyAsync(b->d_wins, h.data(), (size_t)nshot * sizeof(wfd::GradWindow),
+                     hipMemcpyHostToDevice, b->stream) != hipSuccess ||
+      hipStreamSynchronize(b->stream) != hipSuccess) {  // the host descriptors may go now
+    delete b;
+    return fail(WFD_E_HIP, "descriptor upload failed");
+  }
+  *out = b;
+  return WFD_OK;
+}
+
+namespace {
+
+// The whole batched gradient on the stream: clears, the shared checkpoint plan
+// (one launch per forward step and per adjoint step over every shot's
+// tiles), residuals and misfits after the forward sweep, then the fold.
+wfd_status gbatch_enqueue(wfd_gbatch *b) {
+  wfd_ctx *c0 = b->ctxs[0];
+  const int nwin = (int)b->ctxs.size();
+  const int nt = b->nt;
+  hipStream_t st = b->stream;
+  auto pool = [&](int i, int k) -> float * {
+    const Work &w = b->work[(size_t)i];
+    return k == 0 ? w.W1 : (k == 1 ? w.W2 : w.store + (size_t)(k - 2) * (size_t)b->ctxs[i]->vol);
+  };
+  for (int i = 0; i < nwin; ++i) {
+    const Work &w = b->work[(size_t)i];
+    for (float *p : {w.W1, w.W2, w.P1, w.P2, w.g})
+      HIP_TRY(wfd::launch_fill_zero(p, b->ctxs[i]->vol, st));
+  }
+  const int nbuf = 2 + 2 * b->nsnap;
+  std::vector<int> pins((size_t)nbuf, 0);
+  struct Slot {
+    int state = -1, a = -1, b = -1;
+  };
+  std::vector<Slot> slots((size_t)b->nsnap);
+  int cur_state = -1, cur = -1, prev = -1, reached = 0, parity = 0;
+  bool residual_done = false;
+  auto slot_of = [&](int state) -> Slot * {
+    for (auto &sl : slots)
+      if (sl.state == state) return &sl;
+    return nullptr;
+  };
+  auto free_buffer = [&](int not1, int not2) -> int {
+    for (int i = 0; i < nbuf; ++i)
+      if (pins[(size_t)i] == 0 && i != not1 && i != not2) return i;
+    return -1;
+  };
+  for (size_t i = 0; i + 3 <= b->plan.size(); i += 3) {
+    const int op = b->plan[i], a = b->plan[i + 1], bb = b->plan[i + 2];
+    if (op == wfd::kAdvance) {
+      if (cur_state != a) {
+        if (a == 0) {
+          cur = free_buffer(-1, -1);
+          prev = free_buffer(cur, -1);
+          if (cur < 0 || prev < 0) return fail(WFD_E_STATE, "checkpoint pool exhausted");
+          for (int s = 0; s < nwin; ++s) {
+            HIP_TRY(wfd::launch_fill_zero(pool(s, cur), b->ctxs[s]->vol, st));
+            HIP_TRY(wfd::launch_fill_zero(pool(s, prev), b->ctxs[s]->vol, st));
+          }
+        } else {
+          Slot *sl = slot_of(a);
+          if (!sl) return fail(WFD_E_STATE, "checkpoint plan: state %d not stored", a);
+          cur = sl->a;
+          prev = sl->b;
+        }
+      }
+      for (int n = a; n < bb; ++n) {
+        const int o = pins[(size_t)prev] == 0 ? prev : free_buffer(cur, prev);
+        if (o < 0) return fail(WFD_E_STATE, "checkpoint pool exhausted");
+        {
+          Timed t(c0, WFD_K_FORWARD);
+          HIP_TRY(wfd::launch_forward_pool(b->d_wins, nwin, b->fblocks, n, cur, prev, o,
+                                           n >= reached ? 1 : 0, b->variant, b->vd, b->fs, st));
+        }
+        if (n >= reached) reached = n + 1;
+        prev = cur;
+        cur = o;
+      }
+      cur_state = bb;
+    } else if (op == wfd::kStore) {
+      if (cur_state != a) return fail(WFD_E_STATE, "checkpoint plan: store of non-current state");
+      Slot &sl = slots[(size_t)bb];
+      sl.state = a;
+      sl.a = cur;
+      sl.b = prev;
+      ++pins[(size_t)cur];
+      ++pins[(size_t)prev];
+    } else if (op == wfd::kVisit) {
+      if (!residual_done) {
+        residual_done = true;
+        for (int s = 0; s < nwin; ++s) {
+          if (b->nrec[(size_t)s] == 0) continue;
+          const Work &w = b->work[(size_t)s];
+          int np = 0;
+          Timed t(c0, WFD_K_OTHER);
+          HIP_TRY(wfd::launch_residual(w.seis_tm, b->dobs[(size_t)s], w.rec_adj, w.scale,
+                                       b->nrec[(size_t)s], nt, w.res_tm, w.partial, &np, st));
+          HIP_TRY(wfd::launch_sum_partials(w.partial, np, b->misfit[(size_t)s], st));
+        }
+      }
+      int wk = -1;
+      if (cur_state == a)
+        wk = cur;
+      else if (Slot *sl = slot_of(a))
+        wk = sl->a;
+      else if (cur_state == a + 1)
+        wk = prev;
+      if (wk < 0) return fail(WFD_E_STATE, "checkpoint plan: state %d unavailable", a);
+      {
+        Timed t(c0, WFD_K_ADJOINT);
+        HIP_TRY(wfd::launch_adjoint_multi(b->d_wins, nwin, b->ablocks, a, parity, wk,
+                                          b->adj_variant, b->vd, b->illum, b->fs, st));
+      }
+      parity ^= 1;
+    } else if (op == wfd::kFree) {
+      Slot &sl = slots[(size_t)bb];
+      --pins[(size_t)sl.a];
+      --pins[(size_t)sl.b];
+      sl = Slot{};
+    }
+  }
+  for (int s = 0; s < nwin; ++s) {
+    wfd_ctx *c = b->ctxs[(size_t)s];
+    const Work &w = b->work[(size_t)s];
+    Timed t(c0, WFD_K_OTHER);
+    HIP_TRY(wfd::launch_grad_fold(w.g, c->k, c->pitch, c->Ny, c->grid.border, c->grid.nx,
+                                  c->grid.ny, c->grid.nz, c->grid.dt, w.scale, 0,
+                                  b->grad[(size_t)s], st));
+  }
+  return WFD_OK;
+}
+
+}  // namespace
+
+wfd_status wfd_gbatch_run(wfd_gbatch *b, int32_t use_graph) {
+  if (!b) return fail(WFD_E_ARG, "batch is NULL");
+  for (size_t i = 0; i < b->ctxs.size(); ++i)
+    if (!b->ctxs[i]->has_model || b->ctxs[i]->model_gen != b->model_gen[i])
+      return fail(WFD_E_STATE, "shot %zu: the context's model changed after wfd_gbatch_create",
+                  i);
+  ScopedDevice sd(b->ctxs[0]->device);
+  if (!use_graph) return gbatch_enqueue(b);
+  if (!b->stream) return fail(WFD_E_ARG, "graph capture needs a non-default stream");
+  if (b->ctxs[0]->prof) return fail(WFD_E_STATE, "profiling events cannot be captured");
+  if (!b->exec) {
+    HIP_TRY(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
+    wfd_status s = gbatch_enqueue(b);
+    hipGraph_t graph = nullptr;
+    const hipError_t e = hipStreamEndCapture(b->stream, &graph);
+    if (s != WFD_OK) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return s;
+    }
+    if (e != hipSuccess) return fail(WFD_E_HIP, "hipStreamEndCapture: %s", hipGetErrorString(e));
+    b->graph = graph;
+    HIP_TRY(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
+  }
+  HIP_TRY(hipGraphLaunch(b->exec, b->stream));
+  return WFD_OK;
+}
+
+wfd_status wfd_gbatch_destroy(wfd_gbatch *b) {
+  if (!b) return WFD_OK;
+  ScopedDevice sd(b->ctxs[0]->device);
+  if (b->exec || b->graph) (void)hipStreamSynchronize(b->stream);
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  delete b;
+  return WFD_OK;
+}
+
 
 wfd_status wfd_map_position(const wfd_grid *grid, const double xyz[3], int32_t ijk[3]) {
   wfd_status s = check_grid(grid);

@@ -101,6 +101,34 @@ struct WindowStep {
   int block_begin, block_end;
 };
 
+// Illumination output of the adjoint step: illum[model cell] += 2^(out_exp2 -
+// 2 e) (w^m)^2 with e from the shot's scale (the field kernels carry 2^e w).
+struct IllumOut {
+  float *p;  // [mnz][mny][mnx] or nullptr
+  int border, mnx, mny, mnz;
+  const ShotScale *sc;
+  int out_exp2;
+};
+
+// One shot of a batched gradient (wfd_gbatch): its grid, tile maps of the
+// forward and adjoint launches, source, receivers, and the buffers.  The
+// forward states live in a pool: W1, W2, then the checkpoint store; every
+// shot uses the same pool indices at every step (one plan for all shots).
+struct GradWindow {
+  StepGrid g;
+  TileMap fmap, amap;
+  Source src;
+  RecTable rec;
+  const float *rec_scale;
+  float *seis_tm;        // [nt][nrec] recorded traces
+  const float *res_tm;   // [nt][nrec] scaled residuals
+  float *W1, *W2, *store;
+  int64_t vol;           // floats per pitched volume
+  float *P1, *P2, *gimg;  // adjoint pair and imaging sum
+  IllumOut il;
+  int fblock_begin, fblock_end, ablock_begin, ablock_end;
+};
+
 // Kernel launchers; all enqueue on `stream` and return the launch status.
 hipError_t launch_forward_step(const StepGrid &g, const float *cur, const float *prev, float *out,
                                const Source &src, int n, const RecTable *rec,
@@ -115,20 +143,25 @@ int forward_tile_map(const StepGrid &g, const Tuning &tu, TileMap *map);
 hipError_t launch_forward_multi(const WindowStep *wins, int nwin, int nblocks, int n, int variant,
                                 bool vd, bool fs, hipStream_t stream);
 
-// Illumination output of the adjoint step: illum[model cell] += 2^(out_exp2 -
-// 2 e) (w^m)^2 with e from the shot's scale (the field kernels carry 2^e w).
-struct IllumOut {
-  float *p;  // [mnz][mny][mnx] or nullptr
-  int border, mnx, mny, mnz;
-  const ShotScale *sc;
-  int out_exp2;
-};
-
 hipError_t launch_adjoint_step(const Tuning &tu, const StepGrid &g, const float *cur,
                                const float *prev, float *out,
                                const RecTable &rec, const float *res_tm, int m,
                                const float *wm, float *grad, const IllumOut &illum,
                                hipStream_t stream);
+
+// Blocks of one adjoint launch over g with tuning tu (and its tile map).
+int adjoint_tile_map(const StepGrid &g, const Tuning &tu, bool illum, TileMap *map);
+
+// Batched gradient: one forward step of every window (pool buffers cur_k,
+// prev_k -> out_k; receivers recorded when record != 0), and one adjoint step
+// of every window (psi^{m+1} in P1 for parity 0 else P2; w^m = pool buffer
+// wm_k).  variant / adj_variant: the tile shapes of the windows' maps.
+hipError_t launch_forward_pool(const GradWindow *wins, int nwin, int nblocks, int n, int cur_k,
+                               int prev_k, int out_k, int record, int variant, bool vd, bool fs,
+                               hipStream_t stream);
+hipError_t launch_adjoint_multi(const GradWindow *wins, int nwin, int nblocks, int m, int parity,
+                                int wm_k, int adj_variant, bool vd, bool illum, bool fs,
+                                hipStream_t stream);
 
 // Model preparation.
 hipError_t launch_precompute_k(const float *vel, int mnx, int mny, int mnz, int border, double dt,

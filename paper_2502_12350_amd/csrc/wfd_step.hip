@@ -400,6 +400,116 @@ __global__ void __launch_bounds__(WAVE * NW)
 
 // DL: halo delay-line depth of the adjoint's two fields (the tile shapes
 // below choose it: each delay stage costs two registers per halo value).
+// One adjoint step fused with the imaging condition over tile block b of a
+// grid: psi^m (out, in place over psi^{m+2} = prev) from psi^{m+1} (cur), the
+// residuals of sample m-1 injected at the receivers, and
+// g += psi^{m+1} (L w^m - m2 w^m) (+ the illumination).  sm[0] stages psi,
+// sm[1] w.
+template <int RY, int NW, int NI, int DL, bool VD, bool ILLUM, bool FS>
+__device__ __forceinline__ void adjoint_tile(
+    const StepGrid g, const float *__restrict__ cur, const float *prev,
+    float *out, const RecTable rec, const float *__restrict__ res_tm, int m,
+    const float *__restrict__ wm, float *__restrict__ grad, const IllumOut il,
+    const TileMap map, int b) {
+  using T = Tile<RY, NW, NI>;
+  constexpr int NP = T::NP;
+  __shared__ float sm[2][2][T::LY][T::LX];  // [field][buffer]
+  Geo<RY, NW, NI, 1> geo;
+  if (!geo.init(g, map, b)) return;
+  Marcher<RY, NW, NI, 1, FS, DL> fa;  // adjoint state psi^{m+1}
+  Marcher<RY, NW, NI, 1, FS, DL> fw;  // forward state w^m
+  fa.prime(cur, g, geo.z0, geo.off, geo.in, geo.hoff, geo.hin);
+  fw.prime(wm, g, geo.z0, geo.off, geo.in, geo.hoff, geo.hin);
+  float gxv[NI], gyv[RY];
+#pragma unroll
+  for (int i = 0; i < NI; ++i) gxv[i] = geo.xs[i] < g.nx ? g.gx[geo.xs[i]] : 0.0f;
+#pragma unroll
+  for (int j = 0; j < RY; ++j) gyv[j] = geo.yv[j] < g.ny ? g.gy[geo.yv[j]] : 0.0f;
+  ColCursor cc[NP];
+#pragma unroll
+  for (int j = 0; j < RY; ++j)
+#pragma unroll
+    for (int i = 0; i < NI; ++i)
+      cc[j * NI + i].init(rec, geo.yv[j] * g.nx + geo.xs[i], geo.z0, geo.in[j * NI + i]);
+  const float c0 = W0 * (g.cx + g.cy + g.cz);
+  const float *res_row = res_tm + (int64_t)(m - 1) * rec.nrec;
+  const int iexp = ILLUM ? il.out_exp2 - 2 * il.sc->e : 0;  // (2^e w)^2 -> 2^out_exp2 w^2
+  float pv[NP], kv[NP], mv[NP], gv[NP];
+#pragma unroll
+  for (int p = 0; p < NP; ++p) {
+    pv[p] = ld_stream(prev, g, geo.z0, geo.off[p], geo.in[p]);
+    kv[p] = ld_stream(g.k, g, geo.z0, geo.off[p], geo.in[p]);
+    mv[p] = VD ? ld_stream(g.m2, g, geo.z0, geo.off[p], geo.in[p]) : 0.0f;
+    gv[p] = ld_stream(grad, g, geo.z0, geo.off[p], geo.in[p]);
+  }
+  for (int z = geo.z0; z < geo.z1; ++z) {
+    float(*sa)[T::LX] = sm[0][z & 1];
+    float(*sw)[T::LX] = sm[1][z & 1];
+    fa.stage(sa, geo.wave, geo.lane, geo.hslot);
+    fw.stage(sw, geo.wave, geo.lane, geo.hslot);
+    fa.fetch(cur, g, z, geo.off, geo.in, geo.hoff, geo.hin);
+    fw.fetch(wm, g, z, geo.off, geo.in, geo.hoff, geo.hin);
+    const bool more = z + 1 < geo.z1;
+    float pn[NP], kn[NP], mn[NP], gn[NP];
+#pragma unroll
+    for (int p = 0; p < NP; ++p) {
+      pn[p] = ld_stream(prev, g, z + 1, geo.off[p], geo.in[p] && more);
+      kn[p] = ld_stream(g.k, g, z + 1, geo.off[p], geo.in[p] && more);
+      mn[p] = VD ? ld_stream(g.m2, g, z + 1, geo.off[p], geo.in[p] && more) : 0.0f;
+      gn[p] = ld_stream(grad, g, z + 1, geo.off[p], geo.in[p] && more);
+    }
+    __syncthreads();
+    const float gzv = g.gz[z];
+    const int64_t zoff = (int64_t)z * g.plane;
+    static_for<RY>([&](auto Jc) {
+      constexpr int J = decltype(Jc)::value;
+      static_for<NI>([&](auto Ic) {
+        constexpr int I = decltype(Ic)::value;
+        constexpr int P = J * NI + I;
+        float ax, ay, az, wx, wy, wz;
+        fa.template diffs<J, I>(sa, geo.wave, geo.lane, ax, ay, az);
+        fw.template diffs<J, I>(sw, geo.wave, geo.lane, wx, wy, wz);
+        const float ca = fa.q[P][4], cw = fw.q[P][4];
+        const float lap_a = c0 * ca + g.cx * ax + g.cy * ay + g.cz * az;
+        const float lap_w = c0 * cw + g.cx * wx + g.cy * wy + g.cz * wz;
+        float acc = VD ? 2.0f * ca + kv[P] * (lap_a - mv[P] * ca) : 2.0f * ca + kv[P] * lap_a;
+        if (cc[P].ez == z) {  // receiver residuals injected at this node
+          float sum = 0.0f;
+          for (int r = rec.ent_rp[cc[P].e]; r < rec.ent_rp[cc[P].e + 1]; ++r)
+            sum += res_row[rec.perm[r]];
+          acc += sum;
+          cc[P].advance(rec);
+        }
+        const float G = gxv[I] * gyv[J] * gzv;
+        const int64_t p = zoff + geo.off[P];
+        if (geo.in[P]) {
+          const bool live = !FS || z > g.zs;  // at and above a free surface psi and w stay zero
+          st_stream(out, p, live ? G * (acc - G * pv[P]) : 0.0f);
+          st_stream(grad, p, live ? gv[P] + ca * (VD ? lap_w - mv[P] * cw : lap_w) : gv[P]);
+          if (ILLUM) {
+            const int ix = geo.xs[I] - il.border, iy = geo.yv[J] - il.border,
+                      iz = z - il.border;
+            if (ix >= 0 && ix < il.mnx && iy >= 0 && iy < il.mny && iz >= 0 && iz < il.mnz)
+              il.p[((int64_t)iz * il.mny + iy) * il.mnx + ix] += ldexpf(cw * cw, iexp);
+          }
+        }
+      });
+    });
+    fa.shift();
+    fw.shift();
+#pragma unroll
+    for (int p = 0; p < NP; ++p) {
+      pv[p] = pn[p];
+      kv[p] = kn[p];
+      mv[p] = mn[p];
+      gv[p] = gn[p];
+    }
+  }
+}
+
+// The single-shot kernel keeps its own copy of the tile body: sharing the
+// device function with the batched kernel cost two VGPR spills in the plane
+// loop (1238 against 1220 us per step at 576^3).
 template <int RY, int NW, int NI, int DL, bool VD, bool ILLUM, bool FS>
 __global__ void __launch_bounds__(WAVE * NW)
     k_adjoint(StepGrid g, const float *__restrict__ cur, const float *prev, float *out,
@@ -500,6 +610,50 @@ __global__ void __launch_bounds__(WAVE * NW)
       gv[p] = gn[p];
     }
   }
+}
+
+// Buffer k of a batched gradient's forward pool: W1, W2, then the stored
+// checkpoint volumes.
+__device__ __forceinline__ float *pool_buffer(const GradWindow &d, int k) {
+  return k == 0 ? d.W1 : (k == 1 ? d.W2 : d.store + (int64_t)(k - 2) * d.vol);
+}
+
+// One forward step of every window of a batched gradient: block b belongs to
+// the window whose [fblock_begin, fblock_end) contains it; the step reads pool
+// buffers cur_k (w^n) and prev_k (w^{n-1}) and writes out_k, recording the
+// receivers when `record` is set.
+template <int RY, int NW, int NI, bool VD, bool FS>
+__global__ void __launch_bounds__(WAVE * NW)
+    k_forward_pool(const GradWindow *__restrict__ wins, int nwin, int n, int cur_k, int prev_k,
+                   int out_k, int record) {
+  using T = Tile<RY, NW, NI>;
+  __shared__ float sm[2][T::LY][T::LX];
+  const int b = blockIdx.x;
+  int w = 0;
+  while (w + 1 < nwin && b >= wins[w + 1].fblock_begin) ++w;
+  const GradWindow &d = wins[w];
+  if (b >= d.fblock_end) return;
+  const RecTable none{};
+  forward_tile<RY, NW, NI, VD, FS>(sm, d.g, pool_buffer(d, cur_k), pool_buffer(d, prev_k),
+                                   pool_buffer(d, out_k), d.src, n, record ? d.rec : none,
+                                   d.rec_scale, record ? d.seis_tm : nullptr, d.fmap,
+                                   b - d.fblock_begin);
+}
+
+// One adjoint step (with imaging) of every window: psi^{m+1} is P1 (parity 0)
+// or P2 (parity 1) and psi^m overwrites the other; w^m is pool buffer wm_k.
+template <int RY, int NW, int NI, int DL, bool VD, bool ILLUM, bool FS>
+__global__ void __launch_bounds__(WAVE * NW)
+    k_adjoint_multi(const GradWindow *__restrict__ wins, int nwin, int m, int parity, int wm_k) {
+  const int b = blockIdx.x;
+  int w = 0;
+  while (w + 1 < nwin && b >= wins[w + 1].ablock_begin) ++w;
+  const GradWindow &d = wins[w];
+  if (b >= d.ablock_end) return;
+  float *a1 = parity ? d.P2 : d.P1, *a2 = parity ? d.P1 : d.P2;
+  adjoint_tile<RY, NW, NI, DL, VD, ILLUM, FS>(d.g, a1, a2, a2, d.rec, d.res_tm, m,
+                                              pool_buffer(d, wm_k), d.gimg, d.il, d.amap,
+                                              b - d.ablock_begin);
 }
 
 int env_int(const char *name, int dflt) {
@@ -704,7 +858,101 @@ hipError_t adj_dispatch(const Tuning &tu, const StepGrid &g, const float *cur, c
 #undef WFD_ADJ
 }
 
+template <int V, bool VD, bool FS>
+hipError_t fwd_pool_launch(const GradWindow *wins, int nwin, int nblocks, int n, int ck, int pk,
+                           int ok, int record, hipStream_t stream) {
+  using S = FwdShape<V>;
+  hipLaunchKernelGGL((k_forward_pool<S::RY, S::NW, S::NI, VD, FS>), dim3(nblocks),
+                     dim3(FwdTile<V>::NTHREADS), 0, stream, wins, nwin, n, ck, pk, ok, record);
+  return hipGetLastError();
+}
+
+template <int V, bool VD, bool ILLUM, bool FS>
+hipError_t adj_multi_launch(const GradWindow *wins, int nwin, int nblocks, int m, int parity,
+                            int wk, hipStream_t stream) {
+  using S = AdjShape<V>;
+  hipLaunchKernelGGL((k_adjoint_multi<S::RY, S::NW, S::NI, S::DL, VD, ILLUM, FS>), dim3(nblocks),
+                     dim3(WAVE * S::NW), 0, stream, wins, nwin, m, parity, wk);
+  return hipGetLastError();
+}
+
+template <int V>
+hipError_t adj_multi_dispatch(const GradWindow *wins, int nwin, int nblocks, int m, int parity,
+                              int wk, bool vd, bool illum, bool fs, hipStream_t stream) {
+#define WFD_AM(VD_, IL_)                                                                     \
+  return fs ? adj_multi_launch<V, VD_, IL_, true>(wins, nwin, nblocks, m, parity, wk, stream) \
+            : adj_multi_launch<V, VD_, IL_, false>(wins, nwin, nblocks, m, parity, wk, stream)
+  if (vd) {
+    if (illum) WFD_AM(true, true);
+    WFD_AM(true, false);
+  }
+  if (illum) WFD_AM(false, true);
+  WFD_AM(false, false);
+#undef WFD_AM
+}
+
+template <int V>
+int adj_map(const StepGrid &g, const Tuning &tu, bool illum, TileMap *map) {
+  using S = AdjShape<V>;
+  using T = Tile<S::RY, S::NW, S::NI>;
+  const bool vd = g.m2 != nullptr, fs = g.zs != kNoSurface;
+  int per_cu;
+#define WFD_PC(VD_, IL_, FS_) \
+  blocks_per_cu(k_adjoint<S::RY, S::NW, S::NI, S::DL, VD_, IL_, FS_>, T::NTHREADS)
+  if (vd)
+    per_cu = illum ? (fs ? WFD_PC(true, true, true) : WFD_PC(true, true, false))
+                   : (fs ? WFD_PC(true, false, true) : WFD_PC(true, false, false));
+  else
+    per_cu = illum ? (fs ? WFD_PC(false, true, true) : WFD_PC(false, true, false))
+                   : (fs ? WFD_PC(false, false, true) : WFD_PC(false, false, false));
+#undef WFD_PC
+  *map = make_map(g, T::TX, T::TY, per_cu, 0, tu.adj_rounds, kAdjHalo);
+  return map->nblocks;
+}
+
 }  // namespace
+
+int adjoint_tile_map(const StepGrid &g, const Tuning &tu, bool illum, TileMap *map) {
+  switch (tu.adj_variant) {
+    case 1: return adj_map<1>(g, tu, illum, map);
+    case 2: return adj_map<2>(g, tu, illum, map);
+    case 3: return adj_map<3>(g, tu, illum, map);
+    default: return adj_map<0>(g, tu, illum, map);
+  }
+}
+
+hipError_t launch_forward_pool(const GradWindow *wins, int nwin, int nblocks, int n, int cur_k,
+                               int prev_k, int out_k, int record, int variant, bool vd, bool fs,
+                               hipStream_t stream) {
+#define WFD_FP(V)                                                                              \
+  return vd ? (fs ? fwd_pool_launch<V, true, true>(wins, nwin, nblocks, n, cur_k, prev_k, out_k, \
+                                                   record, stream)                             \
+                  : fwd_pool_launch<V, true, false>(wins, nwin, nblocks, n, cur_k, prev_k,     \
+                                                    out_k, record, stream))                    \
+            : (fs ? fwd_pool_launch<V, false, true>(wins, nwin, nblocks, n, cur_k, prev_k,     \
+                                                    out_k, record, stream)                     \
+                  : fwd_pool_launch<V, false, false>(wins, nwin, nblocks, n, cur_k, prev_k,    \
+                                                     out_k, record, stream))
+  switch (variant) {
+    case 1: WFD_FP(1);
+    case 2: WFD_FP(2);
+    case 3: WFD_FP(3);
+    case 4: WFD_FP(4);
+    default: WFD_FP(0);
+  }
+#undef WFD_FP
+}
+
+hipError_t launch_adjoint_multi(const GradWindow *wins, int nwin, int nblocks, int m, int parity,
+                                int wm_k, int adj_variant, bool vd, bool illum, bool fs,
+                                hipStream_t stream) {
+  switch (adj_variant) {
+    case 1: return adj_multi_dispatch<1>(wins, nwin, nblocks, m, parity, wm_k, vd, illum, fs, stream);
+    case 2: return adj_multi_dispatch<2>(wins, nwin, nblocks, m, parity, wm_k, vd, illum, fs, stream);
+    case 3: return adj_multi_dispatch<3>(wins, nwin, nblocks, m, parity, wm_k, vd, illum, fs, stream);
+    default: return adj_multi_dispatch<0>(wins, nwin, nblocks, m, parity, wm_k, vd, illum, fs, stream);
+  }
+}
 
 hipError_t launch_forward_step(const StepGrid &g, const float *cur, const float *prev, float *out,
                                const Source &src, int n, const RecTable *rec,

@@ -206,7 +206,7 @@ def test_autotune_picks_shapes_and_keeps_results():
     gbase = gbase.clone()
     t, fus, aus = P.autotune(steps=5)
     say(f"  picked {t}: forward {fus:.1f} us/step, adjoint {aus:.1f} us/step")
-    assert t[0] in range(4) and t[2] in range(3)
+    assert t[0] in range(5) and t[2] in range(4)
     assert t[1] in (0, 2, 3, 4, 6, 8) and t[3] in (0, 2, 3, 4, 6, 8)
     assert fus > 0 and aus > 0
     assert P.tuning() == t
@@ -297,3 +297,92 @@ def test_tile_shapes_bitwise_identical_with_free_surface(variant, adj_variant):
     assert float(J1.item()) == J0 and J0 > 0
     assert torch.equal(s1, s0)
     assert torch.equal(g1, g0)
+
+
+# ---------------------------------------------------------------------------
+# batched gradients
+# ---------------------------------------------------------------------------
+def _gradient_windows(torch):
+    """c3_small's 4 windows with observed data from a true model (three
+    +/-8 % blobs on a 3 % faster background), each window's data from its own
+    forward run on the true window."""
+    import copy
+    w, shots = _windows("c3_small")
+    wt = copy.copy(w)
+    wt.vel = (seisgen.blob_anomalies(w.vel, seed=31, n_blobs=3, amp=0.08, sigma_cells=(3.0, 6.0),
+                                     centre_lo=(15, 15, 12), centre_hi=(80, 65, 40))
+              * np.float32(1.03)).astype(np.float32)
+    true = [seisgen.shot_window(wt, i) for i in range(len(shots))]
+    wav = torch.from_numpy(shots[0].wavelet).cuda()
+    dobs = []
+    for s, t in zip(shots, true):
+        P = propagator(t)
+        dobs.append(P.forward(wav, s.sources[0], s.receivers).clone())
+    torch.cuda.synchronize()
+    return w, shots, true, wav, dobs
+
+
+def test_gradient_batch_equals_per_shot_and_oracle():
+    torch = gpu_or_skip()
+    from paper_2502_12350_amd import GradientBatch
+    w, shots, true, wav, dobs = _gradient_windows(torch)
+    say(f"[gradient batch] c3_small {len(shots)} windows {[s.padded_shape for s in shots]} "
+        f"nt {w.nt}, 3 stored pairs")
+    recs = [s.receivers for s in shots]
+    recs[1] = np.zeros((0, 3))          # a shot without receivers
+    dob = list(dobs)
+    dob[1] = None
+    props = [propagator(s) for s in shots]
+    b = GradientBatch(props, wav, [s.sources[0] for s in shots], recs, dob, 3, illum=True)
+    J, grads = b.run()
+    torch.cuda.synchronize()
+    J = J.cpu().numpy()
+    grads = [g.cpu().numpy() for g in grads]
+    ills = [i.cpu().numpy() for i in b.illum]
+    for i, (s, P) in enumerate(zip(shots, props)):
+        il = torch.zeros((s.nz, s.ny, s.nx), dtype=torch.float32, device="cuda")
+        if i == 1:
+            assert J[1] == 0.0 and not grads[1].any()
+            continue
+        Ji, gi = P.gradient(wav, s.sources[0], recs[i], dobs[i], ckpt=("revolve", 3), illum=il)
+        torch.cuda.synchronize()
+        assert float(Ji.item()) == J[i], f"shot {i}"
+        assert np.array_equal(gi.cpu().numpy(), grads[i]), f"shot {i}"
+        assert np.array_equal(il.cpu().numpy(), ills[i]), f"shot {i}"
+    s = shots[0]
+    ref = oracle.gradient(oracle_grid(s), s.vel, s.rho, s.wavelet, s.sources[0], s.receivers,
+                          dobs[0].cpu().numpy(), illumination=True)
+    eJ = abs(J[0] - ref.misfit) / ref.misfit
+    eg = rel_l2(grads[0], ref.grad)
+    say(f"  shot 0 vs oracle: misfit {eJ:.2e}, gradient rel-L2 {eg:.2e}")
+    assert eJ <= SEIS_TOL and eg <= 1e-3 and rel_l2(ills[0], ref.illum) <= SEIS_TOL
+    b.close()
+
+
+def test_gradient_batch_graph_replays_match_eager():
+    torch = gpu_or_skip()
+    from paper_2502_12350_amd import GradientBatch
+    w, shots, true, wav, dobs = _gradient_windows(torch)
+    say("[gradient batch graph] c3_small")
+    stream = torch.cuda.Stream()
+    props = [propagator(s) for s in shots]
+    with torch.cuda.stream(stream):
+        b = GradientBatch(props, wav, [s.sources[0] for s in shots], [s.receivers for s in shots],
+                          dobs, 2, stream=stream)
+        J0, g0 = b.run(use_graph=False)
+        J0, g0 = J0.clone(), [g.clone() for g in g0]
+    torch.cuda.synchronize()
+    for rep in range(3):
+        with torch.cuda.stream(stream):
+            b.misfit.zero_()
+            for g in b.grad:
+                g.fill_(0.0)
+            J, g = b.run(use_graph=True)
+        torch.cuda.synchronize()
+        assert torch.equal(J, J0), f"replay {rep}"
+        assert all(torch.equal(a, c) for a, c in zip(g, g0)), f"replay {rep}"
+        # the program's own eager work between replays
+        x = props[0].forward(wav, shots[0].sources[0], shots[0].receivers)
+        torch.cuda.synchronize()
+        assert bool(torch.isfinite(x).all())
+    b.close()
