@@ -216,9 +216,9 @@ def test_autotune_picks_shapes_and_keeps_results():
     assert torch.equal(s, base)
     assert torch.equal(g, gbase)
     with pytest.raises(WfdError):
-        P.set_tuning(4, 0)
+        P.set_tuning(5, 0)
     with pytest.raises(WfdError):
-        P.set_tuning(0, 0, 3, 0)
+        P.set_tuning(0, 0, 4, 0)
     with pytest.raises(WfdError):
         P.set_tuning(0, 65)
     with pytest.raises(WfdError):
