@@ -204,6 +204,35 @@ def _quadratic_step(J_at, v, d, J0, gd, a1, bounds):
     return best[1] if best[0] < J0 else None
 
 
+def _span_step(J_at, v, d1, d2, J0, s1, s2, a1, b1, bounds):
+    """Step in the plane spanned by d1 (the plain direction) and d2 (the
+    network's): the quadratic J(a, b) ~ J0 + s1 a + s2 b + 1/2 [a b] H [a b]'
+    fixed by the exact slopes and three trials (a1, 0), (0, b1), (a1, b1),
+    minimized (within 4 trial lengths per axis) and evaluated; returns the
+    best evaluated step vector, or None if no trial lowers J."""
+    tried = []
+
+    def trial(x, y):
+        step = x * a1 * d1 + y * b1 * d2
+        tried.append((J_at(_project(v + step, bounds)), x, y))
+        return tried[-1][0]
+
+    J10, J01, J11 = trial(1.0, 0.0), trial(0.0, 1.0), trial(1.0, 1.0)
+    S1, S2 = s1 * a1, s2 * b1                  # slopes per trial length
+    A = 2.0 * (J10 - J0 - S1)
+    C = 2.0 * (J01 - J0 - S2)
+    B = J11 - J10 - J01 + J0
+    det = A * C - B * B
+    if A > 0 and C > 0 and det > 0:
+        x = (-C * S1 + B * S2) / det
+        y = (B * S1 - A * S2) / det
+        x, y = min(max(x, -1.0), 4.0), min(max(y, -1.0), 4.0)
+        if min(abs(x - px) + abs(y - py) for _, px, py in tried) > 0.05:
+            trial(x, y)
+    Jb, x, y = min(tried)
+    return (x * a1 * d1 + y * b1 * d2) if Jb < J0 else None
+
+
 def _project(v, bounds):
     """Clamp to the velocity bounds: None, or (lower, upper) where either side
     may be None (the paper's L-BFGS-b bound types: unbounded, lower only,
@@ -250,7 +279,9 @@ def fwi(prop: Propagator, grid: GridSpec, v0, rho, shots: Shots, *, n_iter: int 
     "lbfgs": L-BFGS-B with that preconditioner in B0 = theta / P; "cnn": steepest
     descent along the learned preconditioner's direction (`precond`, a
     precond.Preconditioner), falling back to the illumination-compensated
-    gradient when the network's direction does not descend.
+    gradient when the network's direction does not descend; "cnn_span": a
+    step in the plane of both directions, from a two-dimensional quadratic
+    fit of three trial misfits and the exact slopes.
 
     Returns (final velocity, FwiTrace).  GPU-seconds are wall time of the
     synchronised GPU work (the device runs nothing else meanwhile), including
@@ -344,6 +375,10 @@ def fwi(prop: Propagator, grid: GridSpec, v0, rho, shots: Shots, *, n_iter: int 
         elif method == "cnn":
             d, used = timed(precond.direction, g, illum, eps_illum)
             alpha0 = first_step(d)
+        elif method == "cnn_span":
+            d2, used = timed(precond.direction, g, illum, eps_illum)
+            d = -P * g
+            alpha0 = first_step(d)
         else:
             d = -P * g
             alpha0 = first_step(d)
@@ -381,6 +416,21 @@ def fwi(prop: Propagator, grid: GridSpec, v0, rho, shots: Shots, *, n_iter: int 
                 if state_file is not None:
                     _save_state(state_file, it + 1, v, g, illum, J, S, Y, dv_prev, trace)
                 continue
+        elif method == "cnn_span" and used:
+            step = _span_step(J_at, v, d, d2, J, gd, _dot(g, d2), alpha0, first_step(d2),
+                              bounds)
+            if step is None:  # no decrease in the plane: the plain direction alone
+                alpha = _quadratic_step(J_at, v, d, J, gd, first_step(d, warm=False), bounds)
+                used = False
+            else:
+                d, alpha = step, 1.0
+            if alpha is None:
+                trace.record(clock[0], J)
+                if state_file is not None:
+                    _save_state(state_file, it + 1, v, g, illum, J, S, Y, dv_prev, trace)
+                continue
+            trace.n_network += int(used)
+            dv_prev = alpha * float(d.abs().max())
         else:
             alpha = _quadratic_step(J_at, v, d, J, gd, alpha0, bounds)
             if alpha is None and dv_prev is not None:  # warm start failed: default step

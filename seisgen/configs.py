@@ -31,6 +31,9 @@ c3        400 x 400 x 256 model from the c2 generator (seed 2503), 32-cell
           surface node of the window (depth index 2) (batched multi-shot).
 c3_small  the same recipe on 96 x 80 x 48 with 4 shots (2 x 2), sides from
           integers(24, 49), 8-cell sponge, 250 steps (element-wise parity).
+c3_narrow the same recipe with narrow apertures: 288 x 192 x 64, 24 shots
+          (6 x 4), sides from integers(32, 65), 8-cell sponge, 500 steps
+          (windows too small to fill the device on their own).
 c4        200 x 200 x 160 smooth layered background + six +/-10 % blobs,
           20-cell sponge, 1200 steps, 8 shots, 2500 receivers (FWI gradient).
 c4_fd     32^3 layered model, 8-cell sponge, 300 steps, one shot, 64
@@ -283,6 +286,8 @@ WORKLOADS: Dict[str, Callable[[], Workload]] = {
     "c3": _c3,
     "c3_small": lambda: _c3(nx=96, ny=80, nz=48, border=8, nt=250, shots_xy=(2, 2),
                             side=(24, 49), name="c3_small"),
+    "c3_narrow": lambda: _c3(nx=288, ny=192, nz=64, border=8, nt=500, shots_xy=(6, 4),
+                             side=(32, 65), name="c3_narrow"),
     "c4": _c4,
     "c4_start": lambda: _c4("start"),
     "c4_fd": _c4_fd,

@@ -1,5 +1,7 @@
-"""What the trained preconditioner gains over the method without it, on a
-model outside its training set (the training recipe with seed 9000)."""
+"""What the trained preconditioner gains over the method without it, on
+models outside its training set (the training recipe with seeds 9000+):
+direction quality, model error, and the headline comparison, GPU-seconds to
+equal final misfit."""
 
 import numpy as np
 import pytest
@@ -65,3 +67,31 @@ def test_fwi_with_the_network_moves_the_model_closer_to_the_truth():
             f"model error {res[method][1] / err0:.6f} of the start, network steps {tr.n_network}")
     assert res["cnn"][1] < res["sd"][1] < err0
     assert res["cnn"][0][-1] < res["cnn"][0][0]
+
+
+def test_span_step_reaches_the_plain_final_misfit_in_fewer_gpu_seconds():
+    """The headline comparison on an unseen model: FWI misfit cut per GPU-s at
+    equal final misfit.  The step in the plane of the plain and the network
+    directions must reach the misfit the plain method ends with after four
+    iterations in fewer GPU-seconds, and end at a lower misfit."""
+    torch = gpu_or_skip()
+    from paper_2502_12350_amd.fwi import fwi
+    from paper_2502_12350_amd.precond import Preconditioner, TRAINED
+    w, g, P, shots = _case(torch)
+    say("[precond] 4 FWI iterations, plane step vs plain, GPU-s to equal misfit")
+    net = Preconditioner.load(TRAINED)
+    v0 = torch.from_numpy(w.vel).cuda()
+    tr = {}
+    for method in ("sd", "cnn_span"):
+        _, tr[method] = fwi(P, g, v0, None, shots, n_iter=4, method=method,
+                            bounds=(1500.0, 4500.0), zero_top_planes=10, precond=net)
+        say(f"  {method}: misfit {tr[method].misfit[0]:.4e} -> {tr[method].misfit[-1]:.4e} in "
+            f"{tr[method].gpu_seconds[-1]:.2f} GPU-s ({tr[method].n_misfits} forward misfits, "
+            f"{tr[method].n_network} plane steps)")
+    sd, span = tr["sd"], tr["cnn_span"]
+    target = sd.misfit[-1] / sd.misfit[0]
+    t_sd, t_span = sd.time_to_reach(target), span.time_to_reach(target)
+    say(f"  GPU-s to the plain method's final misfit: plain {t_sd:.2f}, plane step {t_span}")
+    assert t_span is not None and t_span < t_sd
+    assert span.misfit[-1] < sd.misfit[-1]
+    assert span.n_network > 0
