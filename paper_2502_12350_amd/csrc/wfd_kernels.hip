@@ -1,14 +1,49 @@
 // HIP kernels for gfx950 (MI355X) around the step kernels (wfd_step.hip):
 // model preparation (Eq. 1 coefficients, in FP64 where it matters), per-shot
-// source / receiver scales with the field's power-of-two exponent, the misfit with a deterministic FP64 reduction
-// (Alg. 3, SeismicData::Misfit), seismogram transposes and the gradient
-// finish (chain rule to dJ/dv with the sponge fold).
+// source / receiver scales with the field's power-of-two exponent, the misfit
+// with a deterministic FP64 reduction (Alg. 3, SeismicData::Misfit),
+// seismogram transposes and the gradient finish (chain rule to dJ/dv with the
+// sponge fold).
+//
+// Block reductions run as a butterfly of cross-lane shuffles inside each
+// 64-lane wavefront (every lane ends with the same value, since a + b and
+// b + a round alike), then over the four wavefront results in a fixed order:
+// the result does not depend on scheduling.
 #include "wfd_internal.h"
 
 namespace wfd {
 namespace {
 
 __device__ __forceinline__ int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
+
+constexpr int kBlock = 256;                 // threads of every reducing block
+constexpr int kWaves = kBlock / 64;
+
+template <class T, class Op>
+__device__ __forceinline__ T wave_reduce(T v, Op op) {
+  for (int o = 32; o > 0; o >>= 1) v = op(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
+// Reduction over a 256-thread block, returned to every thread; t is the
+// thread's linear index in the block.
+template <class T, class Op>
+__device__ __forceinline__ T block_reduce(T v, Op op, int t) {
+  __shared__ T part[kWaves];
+  v = wave_reduce(v, op);
+  if ((t & 63) == 0) part[t >> 6] = v;
+  __syncthreads();
+  T r = part[0];
+  for (int w = 1; w < kWaves; ++w) r = op(r, part[w]);
+  return r;
+}
+
+struct MaxOp {
+  __device__ float operator()(float a, float b) const { return fmaxf(a, b); }
+};
+struct SumOp {
+  __device__ double operator()(double a, double b) const { return a + b; }
+};
 
 // k = dt^2 v^2 over the padded grid (v edge-replicated); per-block max of v.
 __global__ void __launch_bounds__(256)
@@ -29,14 +64,8 @@ __global__ void __launch_bounds__(256)
     k[(int64_t)z * pitch * ny + (int64_t)y * pitch + x] = (float)(dt * dt * v * v);
     vmax = fmaxf(vmax, (float)v);
   }
-  __shared__ float red[256];
-  red[threadIdx.x] = vmax;
-  __syncthreads();
-  for (int s = 128; s > 0; s >>= 1) {
-    if ((int)threadIdx.x < s) red[threadIdx.x] = fmaxf(red[threadIdx.x], red[threadIdx.x + s]);
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+  const float r = block_reduce(vmax, MaxOp(), threadIdx.x);
+  if (threadIdx.x == 0) part[blockIdx.x] = r;
 }
 
 // sqrt(rho) at model node (x, y, z), edge-replicated beyond the model; with a
@@ -81,14 +110,8 @@ __global__ void __launch_bounds__(256)
     if (mx >= 0 && mx < mnx && my >= 0 && my < mny && mz >= 0 && mz < mnz)
       sqrt_rho[((int64_t)mz * mny + my) * mnx + mx] = (float)s;
   }
-  __shared__ float red[256];
-  red[threadIdx.x] = mmax;
-  __syncthreads();
-  for (int s = 128; s > 0; s >>= 1) {
-    if ((int)threadIdx.x < s) red[threadIdx.x] = fmaxf(red[threadIdx.x], red[threadIdx.x + s]);
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+  const float r = block_reduce(mmax, MaxOp(), threadIdx.x);
+  if (threadIdx.x == 0) part[blockIdx.x] = r;
 }
 
 // Field exponent e of a source term of size x = sigma max|f|: x 2^e in [1, 2),
@@ -108,18 +131,12 @@ __global__ void __launch_bounds__(256)
                  int nrec, ShotScale *__restrict__ sc, float *__restrict__ rec_scale,
                  float *__restrict__ rec_adj) {
   (void)src_idx;
-  __shared__ float red[256];
   float fm = 0.0f;
-  for (int n = threadIdx.x; n < nt; n += 256) fm = fmaxf(fm, fabsf(wavelet[n]));
-  red[threadIdx.x] = fm;
-  __syncthreads();
-  for (int s = 128; s > 0; s >>= 1) {
-    if ((int)threadIdx.x < s) red[threadIdx.x] = fmaxf(red[threadIdx.x], red[threadIdx.x + s]);
-    __syncthreads();
-  }
+  for (int n = threadIdx.x; n < nt; n += kBlock) fm = fmaxf(fm, fabsf(wavelet[n]));
+  fm = block_reduce(fm, MaxOp(), threadIdx.x);
   const double s_src = sqrt_rho ? (double)sqrt_rho[src_model_idx] : 1.0;
   const double sigma = dt2_over_h3 / s_src;
-  const int e = field_exponent(sigma * (double)red[0]);
+  const int e = field_exponent(sigma * (double)fm);
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i == 0) {
     sc->sigma = (float)ldexp(sigma, e);
@@ -165,7 +182,6 @@ __global__ void __launch_bounds__(256)
                float *__restrict__ res_tm, double *__restrict__ partial) {
   const int e = sc->e;
   __shared__ float tile[TT][TT + 1];
-  __shared__ double red[256];
   const int r0 = blockIdx.y * TT, n0 = blockIdx.x * TT;
   const int tx = threadIdx.x, ty = threadIdx.y;  // 32 x 8
   for (int j = ty; j < TT; j += 8) {
@@ -183,27 +199,16 @@ __global__ void __launch_bounds__(256)
     }
   }
   const int t = ty * TT + tx;
-  red[t] = acc;
-  __syncthreads();
-  for (int s = 128; s > 0; s >>= 1) {
-    if (t < s) red[t] += red[t + s];
-    __syncthreads();
-  }
-  if (t == 0) partial[(int64_t)blockIdx.y * gridDim.x + blockIdx.x] = red[0];
+  acc = block_reduce(acc, SumOp(), t);
+  if (t == 0) partial[(int64_t)blockIdx.y * gridDim.x + blockIdx.x] = acc;
 }
 
 __global__ void __launch_bounds__(256)
     k_sum_partials(const double *__restrict__ partial, int n, double *misfit) {
-  __shared__ double red[256];
   double acc = 0.0;
-  for (int i = threadIdx.x; i < n; i += 256) acc += partial[i];
-  red[threadIdx.x] = acc;
-  __syncthreads();
-  for (int s = 128; s > 0; s >>= 1) {
-    if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) misfit[0] += red[0];
+  for (int i = threadIdx.x; i < n; i += kBlock) acc += partial[i];
+  acc = block_reduce(acc, SumOp(), threadIdx.x);
+  if (threadIdx.x == 0) misfit[0] += acc;
 }
 
 __global__ void __launch_bounds__(256)
