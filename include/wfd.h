@@ -445,8 +445,9 @@ wfd_status wfd_cnn_pack_weights(const float *w_dev, int32_t cin, int32_t cout, i
  * cin' = cout and cout' = cin.  (cin, cout) in {(2,16), (16,16), (16,1),
  * (1,16)}.  Written as BF16 (rounded to nearest even) and/or FP32
  * channels-last; in, packed and outputs 16-byte aligned, a 16-channel mask
- * 8-byte aligned.  WFD_E_ARG for another layer shape, an empty volume, a
- * misaligned or missing buffer, or a residual with more than one output. */
+ * 8-byte aligned.  WFD_E_ARG for another layer shape, an empty volume, an
+ * x-y plane of more than 2^24 voxels, a misaligned or missing buffer, or a
+ * residual with more than one output or outside 1 to 16 channels. */
 wfd_status wfd_cnn_conv(const uint16_t *in_dev, int32_t nx, int32_t ny, int32_t nz, int32_t cin,
                         int32_t cout, const uint16_t *packed_dev, const float *bias_or_null,
                         int32_t relu, const uint16_t *mask_or_null,

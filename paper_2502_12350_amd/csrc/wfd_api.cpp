@@ -1954,12 +1954,14 @@ wfd_status wfd_cnn_conv(const uint16_t *in, int32_t nx, int32_t ny, int32_t nz, 
   if (!shape) return fail(WFD_E_ARG, "no convolution %d -> %d channels", cin, cout);
   if (!cnn_volume_ok(nx, ny, nz))
     return fail(WFD_E_ARG, "volume %d x %d x %d empty or too large", nx, ny, nz);
+  if ((int64_t)nx * ny > (int64_t(1) << 24))
+    return fail(WFD_E_ARG, "an x-y plane of %d x %d voxels exceeds 2^24", nx, ny);
   if (!in || !apk) return fail(WFD_E_ARG, "NULL input or weights");
   if (mask && cout == 16 && (uintptr_t)mask % 8)
     return fail(WFD_E_ARG, "a 16-channel mask must be 8-byte aligned");
   if (!out_bf16 && !out_f32) return fail(WFD_E_ARG, "no output");
-  if (residual && (cout != 1 || residual_channels < 1))
-    return fail(WFD_E_ARG, "a residual needs a single-output convolution and >= 1 channel");
+  if (residual && (cout != 1 || residual_channels < 1 || residual_channels > 16))
+    return fail(WFD_E_ARG, "a residual needs a single-output convolution and 1 to 16 channels");
   if ((uintptr_t)in % 16 || (uintptr_t)apk % 16 || (uintptr_t)out_bf16 % 16 ||
       (uintptr_t)out_f32 % 16)
     return fail(WFD_E_ARG, "buffers must be 16-byte aligned");

@@ -29,6 +29,7 @@
 #include <stdint.h>
 
 #include <algorithm>
+#include <type_traits>
 
 #include "wfd_internal.h"
 
@@ -39,6 +40,7 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 typedef uint16_t u16x8 __attribute__((ext_vector_type(8)));
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
 
 __device__ __forceinline__ uint16_t to_bf16(float f) {
   uint32_t u = __float_as_uint(f);
@@ -61,14 +63,59 @@ constexpr int kpad(int cin) { return (27 * cin + 31) / 32 * 32; }
 // row as four 16 x 16 tiles with the packed weights held in registers.  With
 // one or two input channels (k_conv) all 27 taps of an output voxel fit in one
 // or two K chunks: output plane z reads planes z - 1 .. z + 1 from a four-slot
-// ring (plane p in slot p & 3) while plane z + 2 is fetched, into registers
-// before the matrix-core work and into its slot after it, so one barrier per
-// plane suffices (the slot written held plane z - 2, read only before the
-// previous barrier).  With 16 input channels, k_conv16 below.
+// ring (plane p in slot p & 3); plane z + 2 was fetched into registers during
+// iteration z - 1 and goes into its slot after the matrix-core work, so one
+// barrier per plane suffices (the slot written held plane z - 2, read only
+// before the previous barrier), and each load has a whole iteration of other
+// work before it is waited for.  With 16 input channels, k_conv16 below.
+//
+// The march issues little besides its loads, LDS reads and matrix-core
+// products: global memory is addressed through raw buffer resources, one per
+// plane, and an access at an offset past a resource's size reads zero (a
+// store is dropped).  Halo voxels outside the volume and output voxels past
+// its edge get an offset beyond every plane (kFarVox) once, before the march,
+// so the march has no per-lane bounds branches; every per-lane address is
+// likewise computed once, and the fragments of taps past the last one read a
+// zeroed LDS pad.  Offsets are 32-bit: a plane holds at most 2^24 voxels (the
+// host checks).
 constexpr int CM_TY = 4, CM_ZC = 16, CM_THR = 256;
 constexpr int CM_LX = 66, CM_LY = CM_TY + 2, CM_PLANE = CM_LX * CM_LY, CM_SLOTS = 4;
 // CIN = 16: a plane is CM_PLANE * 2 sixteen-byte items, at most CM_PF per thread
 constexpr int CM_PF = (CM_PLANE * 2 + CM_THR - 1) / CM_THR;
+// CIN = 1 or 2: a plane is CM_PLANE voxels, at most CM_PFS per thread
+constexpr int CM_PFS = (CM_PLANE + CM_THR - 1) / CM_THR;
+constexpr uint32_t kFarVox = 1u << 25;  // voxel index of "outside": every offset from it misses
+
+// Calls f(integral_constant<int, 0>), ..., f(integral_constant<int, N - 1>).
+template <int N, class F>
+__device__ __forceinline__ void static_for(F &&f) {
+  if constexpr (N > 0) {
+    static_for<N - 1>(f);
+    f(std::integral_constant<int, N - 1>{});
+  }
+}
+
+typedef __amdgpu_buffer_rsrc_t Rsrc;
+
+// Raw buffer resource over `bytes` bytes from p (stride 0, 32-bit data format).
+__device__ __forceinline__ Rsrc buf(const void *p, uint32_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), (short)0, (int)bytes,
+                                           0x00020000);
+}
+
+// Plane gz of a channels-last BF16 volume with c channels and pv voxels per
+// plane; an empty resource for a plane outside [0, nz).
+__device__ __forceinline__ Rsrc plane_buf(const uint16_t *v, int64_t pv, int c, int nz, int gz) {
+  const bool ok = gz >= 0 && gz < nz;
+  return buf(v + (ok ? (int64_t)gz * pv * c : 0), ok ? (uint32_t)(pv * c * 2) : 0u);
+}
+
+// Two floats -> two BF16 (round to nearest even) in one dword, low first.
+__device__ __forceinline__ uint32_t pack_bf16(float lo, float hi) {
+  typedef float f32x2 __attribute__((ext_vector_type(2)));
+  typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+  return __builtin_bit_cast(uint32_t, __builtin_convertvector((f32x2){lo, hi}, bf16x2));
+}
 
 // Block b runs on XCD b mod 8, and each XCD has its own L2: tiles are
 // numbered so that XCD k gets one contiguous range of them, and neighbouring
@@ -82,205 +129,264 @@ inline int cm_tiles(int nx, int ny, int nz) {
   return ((nx + 63) / 64) * ((ny + CM_TY - 1) / CM_TY) * ((nz + CM_ZC - 1) / CM_ZC);
 }
 
-// CIN = 16: fetch plane gz into registers, then store it into its slot.
-__device__ __forceinline__ void cm_fetch16(u32x4 *pf, const uint16_t *__restrict__ in, int nx,
-                                           int ny, int nz, int x0, int y0, int gz) {
-#pragma unroll
-  for (int i = 0; i < CM_PF; ++i) {
-    const int q = threadIdx.x + i * CM_THR;
-    const int v = q >> 1, half = q & 1;
-    const int lx = v % CM_LX, ly = v / CM_LX;
-    const int gx = x0 - 1 + lx, gy = y0 - 1 + ly;
-    u32x4 d = {0u, 0u, 0u, 0u};
-    if (q < CM_PLANE * 2 && gx >= 0 && gx < nx && gy >= 0 && gy < ny && gz >= 0 && gz < nz)
-      d = *reinterpret_cast<const u32x4 *>(in + (((int64_t)gz * ny + gy) * nx + gx) * 16 +
-                                           8 * half);
-    pf[i] = d;
-  }
-}
-__device__ __forceinline__ void cm_store16(uint16_t *lds, int slot, const u32x4 *pf) {
-#pragma unroll
-  for (int i = 0; i < CM_PF; ++i) {
-    const int q = threadIdx.x + i * CM_THR;
-    if (q < CM_PLANE * 2)
-      *reinterpret_cast<u32x4 *>(lds + (slot * CM_PLANE + (q >> 1)) * 16 + 8 * (q & 1)) = pf[i];
-  }
+// Byte offset within an input plane of the halo voxel v of the tile at
+// (x0, y0) (v = 66 ly + lx), times `bytes` per voxel; far outside the volume.
+__device__ __forceinline__ uint32_t halo_offset(int v, int nx, int ny, int x0, int y0,
+                                                uint32_t bytes) {
+  const int lx = v % CM_LX, ly = v / CM_LX;
+  const int gx = x0 - 1 + lx, gy = y0 - 1 + ly;
+  const bool ok = v < CM_PLANE && gx >= 0 && gx < nx && gy >= 0 && gy < ny;
+  return (ok ? (uint32_t)(gy * nx + gx) : kFarVox) * bytes;
 }
 
-// CIN = 1 or 2: fetch plane gz into registers (one voxel's channels per item),
-// then store it into its slot.
-constexpr int CM_PFS = (CM_PLANE + CM_THR - 1) / CM_THR;
-template <int CIN>
-__device__ __forceinline__ void cm_fetch_small(uint32_t *pf, const uint16_t *__restrict__ in,
-                                               int nx, int ny, int nz, int x0, int y0, int gz) {
-#pragma unroll
-  for (int i = 0; i < CM_PFS; ++i) {
-    const int v = threadIdx.x + i * CM_THR;
-    const int lx = v % CM_LX, ly = v / CM_LX;
-    const int gx = x0 - 1 + lx, gy = y0 - 1 + ly;
-    uint32_t d = 0u;
-    if (v < CM_PLANE && gx >= 0 && gx < nx && gy >= 0 && gy < ny && gz >= 0 && gz < nz) {
-      const int64_t g = ((int64_t)gz * ny + gy) * nx + gx;
-      d = CIN == 2 ? *reinterpret_cast<const uint32_t *>(in + g * 2) : (uint32_t)in[g];
-    }
-    pf[i] = d;
-  }
-}
-template <int CIN>
-__device__ __forceinline__ void cm_store_small(uint16_t *lds, int slot, const uint32_t *pf) {
-#pragma unroll
-  for (int i = 0; i < CM_PFS; ++i) {
-    const int v = threadIdx.x + i * CM_THR;
-    if (v >= CM_PLANE) continue;
-    if (CIN == 2)
-      *reinterpret_cast<uint32_t *>(lds + (slot * CM_PLANE + v) * 2) = pf[i];
-    else
-      lds[slot * CM_PLANE + v] = (uint16_t)pf[i];
-  }
-}
-
-// B fragment of chunk c (one or two input channels) for output voxel lx of
-// row ly and lane group g; sl[d] is the slot of input plane z - 1 + d.
-template <int CIN>
-__device__ __forceinline__ bf16x8 cm_gather(const uint16_t *lds, int c, int lx, int ly,
-                                            const int *sl, int g) {
-  if (CIN == 2) {  // elements (2u, 2u + 1) are both channels of tap 4 (c, g) + u
-    u32x4 d;
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int t = 16 * c + 4 * g + u;
-      uint32_t val = 0u;
-      if (t < 27) {
-        const int dz = t / 9, dy = (t / 3) % 3, dx = t % 3;
-        val = *reinterpret_cast<const uint32_t *>(
-            lds + (sl[dz] * CM_PLANE + (ly + dy) * CM_LX + lx + dx) * 2);
-      }
-      d[u] = val;
-    }
-    return __builtin_bit_cast(bf16x8, d);
-  } else {
-    u16x8 d;
-#pragma unroll
-    for (int e = 0; e < 8; ++e) {
-      const int k = 32 * c + 8 * g + e;
-      const int t = k / CIN, ci = k % CIN;
-      uint16_t val = 0;
-      if (t < 27) {
-        const int dz = t / 9, dy = (t / 3) % 3, dx = t % 3;
-        val = lds[(sl[dz] * CM_PLANE + (ly + dy) * CM_LX + lx + dx) * CIN + ci];
-      }
-      d[e] = val;
-    }
-    return __builtin_bit_cast(bf16x8, d);
-  }
-}
-
-// Epilogue of one output row of 4 x 16 voxels: lane holds D[co = 4 g + e][voxel
-// j] of each tile.  Bias, relu, the mask and (single output channel only) the
-// residual, then BF16 and/or FP32 stores.
+// Output voxel indices within a plane of this lane's four tiles (x0 + 16 tl +
+// j, row gy); kFarVox past the volume, and (single output channel) for lanes
+// outside group 0, which hold no output.
 template <int COUT>
-__device__ __forceinline__ void cm_epilogue(const f32x4 *acc, int nx, int ny, int z, int x0,
-                                            int gy, int j, int g, const float *__restrict__ bias,
-                                            int relu, const uint16_t *__restrict__ mask,
-                                            const uint16_t *__restrict__ res, int res_c,
-                                            uint16_t *__restrict__ out_bf,
-                                            float *__restrict__ out_f) {
-  if (gy >= ny) return;
+__device__ __forceinline__ void out_voxels(uint32_t *vo, int nx, int ny, int x0, int gy, int j,
+                                           int g) {
 #pragma unroll
   for (int tl = 0; tl < 4; ++tl) {
     const int gx = x0 + 16 * tl + j;
-    if (gx >= nx) continue;
-    const int64_t vox = ((int64_t)z * ny + gy) * nx + gx;
-    uint16_t mk[4] = {1, 1, 1, 1};  // positive bits unless a mask is given
-    if (mask) {
-      if (COUT == 16) {  // the lane's four channels 4g .. 4g + 3 in one load
-        const uint2 m2 = *reinterpret_cast<const uint2 *>(mask + vox * 16 + 4 * g);
-        mk[0] = (uint16_t)m2.x, mk[1] = (uint16_t)(m2.x >> 16);
-        mk[2] = (uint16_t)m2.y, mk[3] = (uint16_t)(m2.y >> 16);
-      } else if (g == 0) {
-        mk[0] = mask[vox * COUT];
-      }
-    }
+    const bool ok = gx < nx && gy < ny && (COUT == 16 || g == 0);
+    vo[tl] = ok ? (uint32_t)(gy * nx + gx) : kFarVox;
+  }
+}
+
+// Per-voxel inputs of the epilogue of one output row: COUT = 16: the mask of
+// the lane's channels 4 g .. 4 g + 3 per tile; COUT = 1: the mask (m[tl].x)
+// and the residual.  Loaded early (epi_load) so that the march does not wait
+// on them at the epilogue.
+struct EpiIn {
+  u32x2 m[4];
+  float r[4];
+};
+
+template <int COUT>
+__device__ __forceinline__ void epi_load(EpiIn &ei, int z, int64_t pv, const uint32_t *vo, int g,
+                                         const uint16_t *__restrict__ mask,
+                                         const uint16_t *__restrict__ res, int res_c) {
+  const int64_t zo = (int64_t)z * pv;
+  const uint32_t n = (uint32_t)pv;
+  if (mask) {
+    const Rsrc rm = buf(mask + zo * COUT, n * COUT * 2);
+#pragma unroll
+    for (int tl = 0; tl < 4; ++tl)
+      ei.m[tl] = COUT == 16 ? __builtin_amdgcn_raw_buffer_load_b64(rm, vo[tl] * 32u + 8u * (uint32_t)g, 0, 0)
+                            : u32x2{(uint32_t)__builtin_amdgcn_raw_buffer_load_b16(rm, vo[tl] * 2u, 0, 0), 0u};
+  }
+  if (COUT == 1 && res) {
+    const Rsrc rr = buf(res + zo * res_c, n * (uint32_t)res_c * 2);
+#pragma unroll
+    for (int tl = 0; tl < 4; ++tl)
+      ei.r[tl] = from_bf16(__builtin_amdgcn_raw_buffer_load_b16(rr, vo[tl] * (uint32_t)res_c * 2u, 0, 0));
+  }
+}
+
+// Epilogue of one output row of 4 x 16 voxels in plane z: lane holds D[co =
+// 4 g + e][voxel j] of each tile (single output channel: co = 0 in element 0
+// of group 0).  Bias (bco: the lane's channels), relu, the mask and (single
+// output channel) the residual from ei, then BF16 and/or FP32 stores.
+template <int COUT>
+__device__ __forceinline__ void cm_epilogue(const f32x4 *acc, int z, int64_t pv,
+                                            const uint32_t *vo, const float *bco, int g,
+                                            int relu, bool mask, bool res, const EpiIn &ei,
+                                            uint16_t *__restrict__ out_bf,
+                                            float *__restrict__ out_f) {
+  const int64_t zo = (int64_t)z * pv;
+  const uint32_t n = (uint32_t)pv;
+  const Rsrc rb = buf(out_bf ? out_bf + zo * COUT : nullptr, out_bf ? n * COUT * 2 : 0u);
+  const Rsrc rf = buf(out_f ? out_f + zo * COUT : nullptr, out_f ? n * COUT * 4 : 0u);
+#pragma unroll
+  for (int tl = 0; tl < 4; ++tl) {
     float v[4];
 #pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      const int co = 4 * g + e;
-      float s = acc[tl][e];
-      if (bias && co < COUT) s += bias[co];
-      if (relu) s = fmaxf(s, 0.0f);
-      if (mask && co < COUT && !bf16_pos(mk[e])) s = 0.0f;
-      v[e] = s;
+    for (int e = 0; e < 4; ++e) v[e] = acc[tl][e] + bco[e];
+    if (relu) {
+#pragma unroll
+      for (int e = 0; e < 4; ++e) v[e] = fmaxf(v[e], 0.0f);
     }
     if (COUT == 16) {
-      if (out_bf) {
-        const uint32_t lo = (uint32_t)to_bf16(v[0]) | ((uint32_t)to_bf16(v[1]) << 16);
-        const uint32_t hi = (uint32_t)to_bf16(v[2]) | ((uint32_t)to_bf16(v[3]) << 16);
-        *reinterpret_cast<uint2 *>(out_bf + vox * 16 + 4 * g) = make_uint2(lo, hi);
+      const uint32_t ob = vo[tl] * 32u + 8u * (uint32_t)g;  // channels 4g .. 4g + 3, BF16
+      if (mask) {
+        const u32x2 m = ei.m[tl];
+        v[0] = bf16_pos((uint16_t)m.x) ? v[0] : 0.0f;
+        v[1] = bf16_pos((uint16_t)(m.x >> 16)) ? v[1] : 0.0f;
+        v[2] = bf16_pos((uint16_t)m.y) ? v[2] : 0.0f;
+        v[3] = bf16_pos((uint16_t)(m.y >> 16)) ? v[3] : 0.0f;
       }
+      if (out_bf)
+        __builtin_amdgcn_raw_buffer_store_b64((u32x2){pack_bf16(v[0], v[1]), pack_bf16(v[2], v[3])},
+                                              rb, ob, 0, 0);
       if (out_f)
-        *reinterpret_cast<float4 *>(out_f + vox * 16 + 4 * g) =
-            make_float4(v[0], v[1], v[2], v[3]);
-    } else if (g == 0) {  // single output channel: co = 0 is element 0 of group 0
-      if (res) v[0] += from_bf16(res[vox * res_c]);
-      if (out_bf) out_bf[vox] = to_bf16(v[0]);
-      if (out_f) out_f[vox] = v[0];
+        __builtin_amdgcn_raw_buffer_store_b128(
+            (u32x4){__float_as_uint(v[0]), __float_as_uint(v[1]), __float_as_uint(v[2]),
+                    __float_as_uint(v[3])},
+            rf, vo[tl] * 64u + 16u * (uint32_t)g, 0, 0);
+    } else {
+      const uint32_t o = vo[tl];
+      if (mask) v[0] = bf16_pos((uint16_t)ei.m[tl].x) ? v[0] : 0.0f;
+      if (res) v[0] += ei.r[tl];
+      if (out_bf) __builtin_amdgcn_raw_buffer_store_b16((uint16_t)pack_bf16(v[0], 0.0f), rb, o * 2u, 0, 0);
+      if (out_f) __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v[0]), rf, o * 4u, 0, 0);
     }
   }
 }
 
+// Bias of the lane's output channels (4 g + e; single output channel: 0).
+template <int COUT>
+__device__ __forceinline__ void lane_bias(float *bco, const float *__restrict__ bias, int g) {
+#pragma unroll
+  for (int e = 0; e < 4; ++e) bco[e] = bias ? bias[COUT == 16 ? 4 * g + e : 0] : 0.0f;
+}
+
+// CIN = 1 or 2: a ring slot holds one halo plane, CM_PLANE voxels of CIN
+// BF16 channels; the zeroed pad after the four slots serves taps past 26
+// (offsets up to 3 tiles of 16 voxels on).
+template <int CIN>
+struct SmallRing {
+  static constexpr uint32_t SLOT = CM_PLANE * CIN * 2;
+  static constexpr uint32_t PAD = CM_SLOTS * SLOT;
+  static constexpr uint32_t PAD_BYTES = 3 * 16 * CIN * 2 + 16;
+  static constexpr uint32_t BYTES = PAD + PAD_BYTES;
+};
+
 template <int CIN, int COUT>
-__global__ void __launch_bounds__(CM_THR, 4)  // 4 waves per SIMD fit without spills; 5 spill
+__global__ void __launch_bounds__(CM_THR, 4)  // 4 waves per SIMD
     k_conv(const uint16_t *__restrict__ in, int nx, int ny, int nz,
            const uint16_t *__restrict__ apk, const float *__restrict__ bias, int relu,
            const uint16_t *__restrict__ mask, const uint16_t *__restrict__ res, int res_c,
            uint16_t *__restrict__ out_bf, float *__restrict__ out_f) {
   static_assert(CIN == 1 || CIN == 2, "16 input channels: k_conv16");
+  using RG = SmallRing<CIN>;
   constexpr int K = kpad(CIN), NC = K / 32;
-  __shared__ __attribute__((aligned(16))) uint16_t lds[CM_SLOTS * CM_PLANE * CIN + 8];
+  constexpr int NE = CIN == 2 ? 4 : 8;  // LDS reads per fragment: one per tap
+  __shared__ __attribute__((aligned(16))) char lds[(RG::BYTES + 15) / 16 * 16];
   const int tx = (nx + 63) / 64, ty = (ny + CM_TY - 1) / CM_TY;
   const int tile = xcd_tile(blockIdx.x, gridDim.x);
   const int x0 = (tile % tx) * 64, y0 = ((tile / tx) % ty) * CM_TY;
   const int zs = (tile / (tx * ty)) * CM_ZC, ze = min(zs + CM_ZC, nz);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int j = lane & 15, g = lane >> 4;
+  const int64_t pv = (int64_t)nx * ny;
   // weights: A fragment of every chunk (row co = j, k = 32 c + 8 g + e)
   bf16x8 a[NC];
 #pragma unroll
   for (int c = 0; c < NC; ++c)
     a[c] = __builtin_bit_cast(
         bf16x8, *reinterpret_cast<const u32x4 *>(apk + (size_t)j * K + 32 * c + 8 * g));
-  // prologue: planes zs - 1 .. zs + 1
-  for (int p = zs - 1; p <= zs + 1; ++p) {
-    uint32_t pf[CM_PFS];
-    cm_fetch_small<CIN>(pf, in, nx, ny, nz, x0, y0, p);
-    cm_store_small<CIN>(lds, p & 3, pf);
-  }
-  __syncthreads();
-  const int ly = wave, gy = y0 + ly;  // this wave's output row
-#pragma unroll 1
-  for (int z = zs; z < ze; ++z) {
-    const bool more = z + 1 < ze;  // plane z + 2 is needed for output plane z + 1
-    uint32_t pfs[CM_PFS];
-    if (more) cm_fetch_small<CIN>(pfs, in, nx, ny, nz, x0, y0, z + 2);
-    const int sl[3] = {(z - 1) & 3, z & 3, (z + 1) & 3};
-    f32x4 acc[4];
+  // (loaded before the prologue, whose stores wait for them too: the march
+  // then never waits on a load older than its own)
+  float bco[4];
+  lane_bias<COUT>(bco, bias, g);
+  for (uint32_t i = threadIdx.x * 4; i < RG::PAD_BYTES; i += CM_THR * 4)
+    *reinterpret_cast<uint32_t *>(lds + RG::PAD + i) = 0u;
+  uint32_t fo[CM_PFS];
 #pragma unroll
-    for (int tl = 0; tl < 4; ++tl) acc[tl] = f32x4{0.f, 0.f, 0.f, 0.f};
+  for (int i = 0; i < CM_PFS; ++i)
+    fo[i] = halo_offset(threadIdx.x + i * CM_THR, nx, ny, x0, y0, CIN * 2);
+  auto fetch = [&](uint32_t *pf, int gz) {
+    const Rsrc r = plane_buf(in, pv, CIN, nz, gz);
+#pragma unroll
+    for (int i = 0; i < CM_PFS; ++i)
+      pf[i] = CIN == 2 ? __builtin_amdgcn_raw_buffer_load_b32(r, fo[i], 0, 0)
+                       : (uint32_t)__builtin_amdgcn_raw_buffer_load_b16(r, fo[i], 0, 0);
+  };
+  auto store = [&](int gz, const uint32_t *pf) {
+    char *s = lds + (gz & 3) * RG::SLOT;
+#pragma unroll
+    for (int i = 0; i < CM_PFS; ++i) {
+      const int v = threadIdx.x + i * CM_THR;
+      if (i + 1 < CM_PFS || v < CM_PLANE) {
+        if (CIN == 2)
+          *reinterpret_cast<uint32_t *>(s + v * 4) = pf[i];
+        else
+          *reinterpret_cast<uint16_t *>(s + v * 2) = (uint16_t)pf[i];
+      }
+    }
+  };
+  for (int p = zs - 1; p <= zs + 1; ++p) {  // prologue: planes zs - 1 .. zs + 1
+    uint32_t pf[CM_PFS];
+    fetch(pf, p);
+    store(p, pf);
+  }
+  // planes and epilogue inputs are loaded an iteration before their use, into
+  // register sets A and B that alternate (the loop is unrolled twice, so that
+  // no register copy waits on a load in flight)
+  uint32_t pfA[CM_PFS], pfB[CM_PFS];
+  EpiIn eA, eB;
+  fetch(pfA, zs + 2);
+  const int ly = wave, gy = y0 + ly;  // this wave's output row
+  // The LDS read of tap element (c, e) of this lane: plane z - 1 + dz[c][e]
+  // at byte offset to[c][e] (tile 0; tile tl is 16 tl voxels on), or the pad
+  // (dz = 3) past the last tap.  CIN = 2: element e is the channel pair of tap
+  // 16 c + 4 g + e; CIN = 1: the channel of tap 32 c + 8 g + e.
+  int dz[NC][NE];
+  uint32_t to[NC][NE];
+#pragma unroll
+  for (int c = 0; c < NC; ++c)
+#pragma unroll
+    for (int e = 0; e < NE; ++e) {
+      const int t = CIN == 2 ? 16 * c + 4 * g + e : 32 * c + 8 * g + e;
+      const int kz = t / 9, ky = (t / 3) % 3, kx = t % 3;
+      dz[c][e] = t < 27 ? kz : 3;
+      to[c][e] = t < 27 ? (uint32_t)(((ly + ky) * CM_LX + j + kx) * CIN * 2) : 0u;
+    }
+  uint32_t vo[4];
+  out_voxels<COUT>(vo, nx, ny, x0, gy, j, g);
+  epi_load<COUT>(eA, zs, pv, vo, g, mask, res, res_c);
+  __syncthreads();
+  // output plane z from planes z - 1 .. z + 1; cur holds plane z + 2 and ec
+  // the epilogue inputs of z, nxt and en receive plane z + 3 and those of z + 1
+  auto step = [&](int z, uint32_t *cur, uint32_t *nxt, const EpiIn &ec, EpiIn &en) {
+    const bool more = z + 1 < ze;  // plane z + 2 is needed for output plane z + 1
+    if (z + 2 < ze) fetch(nxt, z + 3);
+    if (more) epi_load<COUT>(en, z + 1, pv, vo, g, mask, res, res_c);
+    const uint32_t sb0 = ((z - 1) & 3) * RG::SLOT, sb1 = (z & 3) * RG::SLOT,
+                   sb2 = ((z + 1) & 3) * RG::SLOT;
+    f32x4 acc[4];
     // chunk-major: the four tiles' fragments of one chunk are in flight together
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
+      uint32_t ad[NE];
+#pragma unroll
+      for (int e = 0; e < NE; ++e) {
+        const int d = dz[c][e];
+        ad[e] = to[c][e] + (d == 0 ? sb0 : d == 1 ? sb1 : d == 2 ? sb2 : RG::PAD);
+      }
       bf16x8 b[4];
 #pragma unroll
-      for (int tl = 0; tl < 4; ++tl) b[tl] = cm_gather<CIN>(lds, c, 16 * tl + j, ly, sl, g);
+      for (int tl = 0; tl < 4; ++tl) {
+        if (CIN == 2) {
+          u32x4 d;
+#pragma unroll
+          for (int e = 0; e < 4; ++e)
+            d[e] = *reinterpret_cast<const uint32_t *>(lds + ad[e] + 64 * tl);
+          b[tl] = __builtin_bit_cast(bf16x8, d);
+        } else {
+          u16x8 d;
+#pragma unroll
+          for (int e = 0; e < 8; ++e)
+            d[e] = *reinterpret_cast<const uint16_t *>(lds + ad[e] + 32 * tl);
+          b[tl] = __builtin_bit_cast(bf16x8, d);
+        }
+      }
 #pragma unroll
       for (int tl = 0; tl < 4; ++tl)
-        acc[tl] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[c], b[tl], acc[tl], 0, 0, 0);
+        acc[tl] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+            a[c], b[tl], c == 0 ? f32x4{0.f, 0.f, 0.f, 0.f} : acc[tl], 0, 0, 0);
     }
-    cm_epilogue<COUT>(acc, nx, ny, z, x0, gy, j, g, bias, relu, mask, res, res_c, out_bf, out_f);
-    if (more) cm_store_small<CIN>(lds, (z + 2) & 3, pfs);
+    cm_epilogue<COUT>(acc, z, pv, vo, bco, g, relu, mask, res, ec, out_bf, out_f);
+    if (more) store(z + 2, cur);
     __syncthreads();
+  };
+#pragma unroll 1
+  for (int z = zs; z < ze; z += 2) {
+    step(z, pfA, pfB, eA, eB);
+    if (z + 1 < ze) step(z + 1, pfB, pfA, eB, eA);
   }
 }
+
 // Convolution with 16 input channels, input-plane major.  An input plane p
 // feeds output planes p + 1, p and p - 1 through the taps kz = 0, 1, 2, so
 // the K dimension is split as k = 144 kz + k' with k' = 16 (3 ky + kx) + ci
@@ -288,13 +394,20 @@ __global__ void __launch_bounds__(CM_THR, 4)  // 4 waves per SIMD fit without sp
 // from LDS once and used by the three kz slices of the weights, and the
 // matrix-core work per output plane is 15 instead of 14 products while the
 // LDS fragment reads drop from 14 to 5.  With 16 output channels the three
-// kz products go to three rotating accumulators (output planes p + 1, p,
-// p - 1); with one output channel the rows of A are the three kz slices of
-// the single weight row, one product per chunk leaves the three partial sums
-// in rows 0..2, and two running sums per voxel complete the output.  Output
-// plane p - 1 is complete after input plane p.  Input planes go through a
-// two-slot LDS ring (the next plane is fetched into registers during the
-// matrix-core work and stored after it, one barrier per plane).
+// kz products go to three accumulators whose roles (output planes p + 1, p,
+// p - 1) rotate with p: the plane loop is unrolled three times so that the
+// rotation is a renaming, and the accumulator of output p + 1 starts from
+// its first product.  With one output channel the rows of A are the three kz
+// slices of the single weight row, one product per chunk leaves the three
+// partial sums in rows 0..2, and two running sums per voxel complete the
+// output.  Output plane p - 1 is complete after input plane p.  Input planes
+// go through a two-slot LDS ring (the next plane is fetched into registers
+// during the matrix-core work and stored after it, one barrier per plane);
+// each slot is followed by a zeroed pad that the fragments of k' >= 144 read.
+constexpr uint32_t C16_PLANE = CM_PLANE * 32;           // bytes of a halo plane
+constexpr uint32_t C16_PAD = 3 * 16 * 32 + 16;          // three tiles on, one item
+constexpr uint32_t C16_SLOT = C16_PLANE + C16_PAD;
+
 template <int COUT>
 __global__ void __launch_bounds__(CM_THR, COUT == 16 ? 3 : 1)
     k_conv16(const uint16_t *__restrict__ in, int nx, int ny, int nz,
@@ -303,18 +416,18 @@ __global__ void __launch_bounds__(CM_THR, COUT == 16 ? 3 : 1)
              uint16_t *__restrict__ out_bf, float *__restrict__ out_f) {
   constexpr int K = kpad(16), NC = 5, KP = 144;  // K' = 9 taps x 16 channels
   constexpr int NA = COUT == 16 ? 3 : 1;         // A fragments per chunk
-  __shared__ __attribute__((aligned(16))) uint16_t lds[2 * CM_PLANE * 16 + 8];
+  __shared__ __attribute__((aligned(16))) char lds[2 * C16_SLOT];
   const int tx = (nx + 63) / 64, ty = (ny + CM_TY - 1) / CM_TY;
   const int tile = xcd_tile(blockIdx.x, gridDim.x);
   const int x0 = (tile % tx) * 64, y0 = ((tile / tx) % ty) * CM_TY;
   const int zs = (tile / (tx * ty)) * CM_ZC, ze = min(zs + CM_ZC, nz);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int j = lane & 15, g = lane >> 4;
+  const int64_t pv = (int64_t)nx * ny;
   // A fragments: lane (i + 16 g) holds k' = 32 c + 8 g .. + 7 of row i.
   // COUT = 16: fragment (kz, c), row i = co, kept in LDS (read once per chunk,
-  // a conflict-free 16-byte read per lane), so that the kernel fits 128
-  // registers and 4 waves per SIMD hide the plane loads' latency.
-  // COUT = 1: a[0][c] in registers, row i = kz (rows 3..15 zero).
+  // a conflict-free 16-byte read per lane) to leave registers for the three
+  // accumulators.  COUT = 1: a[0][c] in registers, row i = kz (rows 3..15 zero).
   __shared__ __attribute__((aligned(16))) u32x4 alds[COUT == 16 ? NA * NC * 64 : 1];
   bf16x8 a[COUT == 16 ? 1 : NA][NC];
   if (COUT == 16) {
@@ -334,14 +447,51 @@ __global__ void __launch_bounds__(CM_THR, COUT == 16 ? 3 : 1)
       a[0][c] = __builtin_bit_cast(bf16x8, d);
     }
   }
+  float bco[4];  // before the prologue, whose stores wait for it too
+  lane_bias<COUT>(bco, bias, g);
+  for (uint32_t i = threadIdx.x * 16; i < 2 * C16_PAD; i += CM_THR * 16) {
+    const uint32_t s = i / C16_PAD, o = i % C16_PAD;
+    *reinterpret_cast<u32x4 *>(lds + s * C16_SLOT + C16_PLANE + o) = u32x4{0u, 0u, 0u, 0u};
+  }
+  // this thread's items (16-byte halves of halo voxels) of a plane
+  uint32_t fo[CM_PF];
+#pragma unroll
+  for (int i = 0; i < CM_PF; ++i) {
+    const int q = threadIdx.x + i * CM_THR;
+    fo[i] = halo_offset(q >> 1, nx, ny, x0, y0, 32) + 16u * (q & 1);
+  }
+  auto fetch = [&](u32x4 *pf, int gz) {
+    const Rsrc r = plane_buf(in, pv, 16, nz, gz);
+#pragma unroll
+    for (int i = 0; i < CM_PF; ++i) pf[i] = __builtin_amdgcn_raw_buffer_load_b128(r, fo[i], 0, 0);
+  };
+  auto store = [&](int gz, const u32x4 *pf) {
+    char *s = lds + (gz & 1) * C16_SLOT;
+#pragma unroll
+    for (int i = 0; i < CM_PF; ++i) {
+      const int q = threadIdx.x + i * CM_THR;
+      if (i + 1 < CM_PF || q < CM_PLANE * 2) *reinterpret_cast<u32x4 *>(s + q * 16) = pf[i];
+    }
+  };
   {  // prologue: input plane zs - 1
     u32x4 pf[CM_PF];
-    cm_fetch16(pf, in, nx, ny, nz, x0, y0, zs - 1);
-    cm_store16(lds, (zs - 1) & 1, pf);
+    fetch(pf, zs - 1);
+    store(zs - 1, pf);
   }
-  __syncthreads();
   const int ly = wave, gy = y0 + ly;  // this wave's output row
-  // COUT = 16: acc[0] -> output p + 1, acc[1] -> p, acc[2] -> p - 1 (per tile)
+  // B fragment of chunk c: taps t = 2 c + (g >> 1) (ky = t / 3, kx = t % 3),
+  // channels 8 (g & 1) .. + 7, at byte bo[c] of a slot (tile 0; tile tl is
+  // 16 voxels on); t = 9 (the zero half of chunk 4) reads the pad.
+  uint32_t bo[NC];
+#pragma unroll
+  for (int c = 0; c < NC; ++c) {
+    const int t = 2 * c + (g >> 1);
+    bo[c] = t < 9 ? (uint32_t)(((ly + t / 3) * CM_LX + j + t % 3) * 32 + 16 * (g & 1)) : C16_PLANE;
+  }
+  uint32_t vo[4];
+  out_voxels<COUT>(vo, nx, ny, x0, gy, j, g);
+  __syncthreads();
+  // COUT = 16: acc[s] accumulates output plane o with (o - zs + 1) mod 3 = s
   // COUT = 1: s1 = partial of output p, s2 = partial of output p - 1
   f32x4 acc[3][4];
   float s1[4], s2[4];
@@ -352,73 +502,67 @@ __global__ void __launch_bounds__(CM_THR, COUT == 16 ? 3 : 1)
     for (int q = 0; q < 3; ++q) acc[q][tl] = f32x4{0.f, 0.f, 0.f, 0.f};
   }
 #pragma unroll 1
-  for (int p = zs - 1; p <= ze; ++p) {
-    const bool more = p + 1 <= ze;
-    u32x4 pf[CM_PF];
-    if (more) cm_fetch16(pf, in, nx, ny, nz, x0, y0, p + 1);
-    const uint16_t *pl = lds + (p & 1) * CM_PLANE * 16;
-    // every input plane feeds three accumulators; those of output planes
-    // outside [zs, ze) (at the first two and last two input planes) are never
-    // written out, and branch-free products schedule better than skipping them
-    const bool to_prev = p - 1 >= zs;
-    f32x4 d[4];
+  for (int p0 = zs - 1; p0 <= ze; p0 += 3) {
+    static_for<3>([&](auto Rc) {
+      constexpr int R = decltype(Rc)::value;  // (p - zs + 1) mod 3
+      constexpr int SN = (R + 1) % 3, SC = R, SP = (R + 2) % 3;  // outputs p + 1, p, p - 1
+      const int p = p0 + R;
+      if (p > ze) return;
+      const bool more = p + 1 <= ze;
+      u32x4 pf[CM_PF];
+      if (more) fetch(pf, p + 1);
+      EpiIn ei;
+      if (p - 1 >= zs) epi_load<COUT>(ei, p - 1, pv, vo, g, mask, res, res_c);
+      const char *pl = lds + (p & 1) * C16_SLOT;
+      // every input plane feeds three accumulators; those of output planes
+      // outside [zs, ze) (at the first two and last two input planes) are
+      // never written out, and branch-free products schedule better than
+      // skipping them
+      f32x4 d[4];
 #pragma unroll
-    for (int tl = 0; tl < 4; ++tl) d[tl] = f32x4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-    for (int c = 0; c < NC; ++c) {
-      const int t = 2 * c + (g >> 1);  // tap ky * 3 + kx of this lane's k'
-      bf16x8 b[4];
-#pragma unroll
-      for (int tl = 0; tl < 4; ++tl) {
-        u32x4 v = {0u, 0u, 0u, 0u};
-        if (t < 9) {
-          const int vox = (ly + t / 3) * CM_LX + 16 * tl + j + t % 3;
-          v = *reinterpret_cast<const u32x4 *>(pl + vox * 16 + 8 * (g & 1));
-        }
-        b[tl] = __builtin_bit_cast(bf16x8, v);
-      }
-      if (COUT == 16) {
-        const bf16x8 a0 = __builtin_bit_cast(bf16x8, alds[(0 * NC + c) * 64 + lane]);
-        const bf16x8 a1 = __builtin_bit_cast(bf16x8, alds[(1 * NC + c) * 64 + lane]);
-        const bf16x8 a2 = __builtin_bit_cast(bf16x8, alds[(2 * NC + c) * 64 + lane]);
-#pragma unroll
-        for (int tl = 0; tl < 4; ++tl) {
-          acc[0][tl] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, b[tl], acc[0][tl], 0, 0, 0);
-          acc[1][tl] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, b[tl], acc[1][tl], 0, 0, 0);
-          acc[2][tl] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a2, b[tl], acc[2][tl], 0, 0, 0);
-        }
-      } else {
+      for (int c = 0; c < NC; ++c) {
+        bf16x8 b[4];
 #pragma unroll
         for (int tl = 0; tl < 4; ++tl)
-          d[tl] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0][c], b[tl], d[tl], 0, 0, 0);
-      }
-    }
-    if (to_prev) {  // output plane p - 1 is complete
-      if (COUT == 16) {
-        cm_epilogue<COUT>(acc[2], nx, ny, p - 1, x0, gy, j, g, bias, relu, mask, res, res_c,
-                          out_bf, out_f);
-      } else {  // lanes of group 0 hold (P0, P1, P2) of voxel j in elements 0..2
-        f32x4 o[4];
+          b[tl] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u32x4 *>(pl + bo[c] + 512 * tl));
+        if (COUT == 16) {
+          const bf16x8 a0 = __builtin_bit_cast(bf16x8, alds[(0 * NC + c) * 64 + lane]);
+          const bf16x8 a1 = __builtin_bit_cast(bf16x8, alds[(1 * NC + c) * 64 + lane]);
+          const bf16x8 a2 = __builtin_bit_cast(bf16x8, alds[(2 * NC + c) * 64 + lane]);
 #pragma unroll
-        for (int tl = 0; tl < 4; ++tl) o[tl] = f32x4{s2[tl] + d[tl][2], 0.f, 0.f, 0.f};
-        cm_epilogue<COUT>(o, nx, ny, p - 1, x0, gy, j, g, bias, relu, mask, res, res_c, out_bf,
-                          out_f);
-      }
-    }
-    // rotate: output p becomes p - 1 for the next plane, p + 1 becomes p
+          for (int tl = 0; tl < 4; ++tl) {
+            acc[SN][tl] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                a0, b[tl], c == 0 ? f32x4{0.f, 0.f, 0.f, 0.f} : acc[SN][tl], 0, 0, 0);
+            acc[SC][tl] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, b[tl], acc[SC][tl], 0, 0, 0);
+            acc[SP][tl] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a2, b[tl], acc[SP][tl], 0, 0, 0);
+          }
+        } else {
 #pragma unroll
-    for (int tl = 0; tl < 4; ++tl) {
-      if (COUT == 16) {
-        acc[2][tl] = acc[1][tl];
-        acc[1][tl] = acc[0][tl];
-        acc[0][tl] = f32x4{0.f, 0.f, 0.f, 0.f};
-      } else {
-        s2[tl] = s1[tl] + d[tl][1];
-        s1[tl] = d[tl][0];
+          for (int tl = 0; tl < 4; ++tl)
+            d[tl] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                a[0][c], b[tl], c == 0 ? f32x4{0.f, 0.f, 0.f, 0.f} : d[tl], 0, 0, 0);
+        }
       }
-    }
-    if (more) cm_store16(lds, (p + 1) & 1, pf);
-    __syncthreads();
+      if (p - 1 >= zs) {  // output plane p - 1 is complete
+        if (COUT == 16) {
+          cm_epilogue<COUT>(acc[SP], p - 1, pv, vo, bco, g, relu, mask, res, ei, out_bf, out_f);
+        } else {  // lanes of group 0 hold (P0, P1, P2) of voxel j in elements 0..2
+          f32x4 o[4];
+#pragma unroll
+          for (int tl = 0; tl < 4; ++tl) o[tl] = f32x4{s2[tl] + d[tl][2], 0.f, 0.f, 0.f};
+          cm_epilogue<COUT>(o, p - 1, pv, vo, bco, g, relu, mask, res, ei, out_bf, out_f);
+        }
+      }
+      if (COUT == 1) {
+#pragma unroll
+        for (int tl = 0; tl < 4; ++tl) {
+          s2[tl] = s1[tl] + d[tl][1];
+          s1[tl] = d[tl][0];
+        }
+      }
+      if (more) store(p + 1, pf);
+      __syncthreads();
+    });
   }
 }
 

@@ -176,6 +176,11 @@ def test_cnn_packed_sizes_and_workspace():
     assert L.wfd_cnn_wgrad(256, 256, 8, 8, 8, 16, 16, 256, 256, 256, 16, None) == -4   # work
     assert L.wfd_cnn_conv(256, 8, 8, 8, 16, 16, 256, None, 0, 260, None, 0, 256, None,
                           None) == -1                                     # mask alignment
+    # 32-bit plane offsets: an x-y plane holds at most 2^24 voxels
+    assert L.wfd_cnn_conv(256, 4097, 4096, 1, 16, 16, 256, None, 0, None, None, 0, 256, None,
+                          None) == -1
+    assert L.wfd_cnn_conv(256, 8, 8, 8, 16, 1, 256, None, 0, None, 256, 17, 256, None,
+                          None) == -1                                     # residual channels
 
 
 def test_smoothing_and_resampling_host_paths():
