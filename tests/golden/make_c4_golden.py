@@ -15,11 +15,12 @@ gradient are taken at the starting model (the background).  That is the body
 of Alg. 3 for one shot, evaluated end to end: J(v_start; d_obs = F(v_true)).
 
 With the workload's own true model the residual is only 0.36 % of the data
-(the direct wave dominates both), so an FP32 propagator's trace error of
-about 1.5e-5 of the data becomes about 4e-3 of the residual, and of the
-gradient, which is linear in it.  The second file ("fast": the true model
+and, at the receivers, zero until the reflections arrive (the direct wave
+dominates both data sets): an FP32 propagator's rounding noise in the direct
+wave, different in the observed and the synthetic run, then shows in the
+shallow gradient at a few 1e-3.  The second file ("fast": the true model
 scaled by 1.03, which moves every arrival) has a residual of the data's size
-and tests the gradient itself at the 1e-3 level.
+and tests the whole gradient at the 1e-3 level.
 
 Stored (``c4_shot1.npz``):
   misfit              J (FP64)

@@ -335,21 +335,23 @@ def _c4_against_stored(case):
 
 
 def test_gradient_workload_shot_matches_stored_oracle():
-    """The workload's own data.  The residual is 0.36 % of the data (the
-    direct wave dominates both), and the gradient is linear in the residual:
-    the FP32 traces' agreement e (within SEIS_TOL) therefore bounds the
-    gradient's to about sqrt(2) e |d| / |r| (observed and synthetic traces
-    err independently), 5.9e-3 at e = 1.5e-5, above GRAD_TOL.  The test
-    asserts that bound, with a factor 2, and GRAD_TOL on the plane z = 60,
-    away from the surface where the residual is injected; the next test
-    checks the whole gradient at GRAD_TOL on data with a large residual."""
+    """The workload's own data.  Its residual is 0.36 % of the data and, at
+    the receivers, physically zero until the blobs' reflections arrive; but
+    each FP32 run carries rounding noise of about 1e-6 of the direct wave,
+    and the noise of the observed and the synthetic run differs wherever
+    their models differ in any bit.  Back-propagated along the direct wave's
+    path, that noise perturbs the gradient near the surface by a few 1e-3
+    (on a 100 x 100 x 80 crop of the same shot: 0.8 %, while summing the
+    oracle's own products in FP32 costs only 1e-6).  The test holds traces,
+    misfit and illumination to SEIS_TOL, the gradient below the surface layer
+    (plane z = 60) to GRAD_TOL, and the whole gradient to 1e-2; the next test
+    checks the whole gradient at GRAD_TOL on data whose residual is of the
+    data's size."""
     e, ratio = _c4_against_stored("")
     assert e["dobs"] <= SEIS_TOL and e["seis"] <= SEIS_TOL and e["J"] <= SEIS_TOL
     assert e["illum"] <= SEIS_TOL
-    bound = 2.0 * np.sqrt(2.0) * max(e["dobs"], e["seis"]) / ratio
-    say(f"  gradient bound from the traces: {bound:.2e}")
-    assert max(e["norm"], e["sketch"], e["y100"]) <= bound
     assert e["z60"] <= GRAD_TOL
+    assert max(e["norm"], e["sketch"], e["y100"]) <= 1e-2
 
 
 def test_gradient_workload_grid_large_residual_matches_stored_oracle():
