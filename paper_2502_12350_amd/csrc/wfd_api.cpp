@@ -1446,15 +1446,17 @@ wfd_status wfd_batch_create(wfd_batch **out, int32_t nshot, wfd_ctx *const *ctxs
       b->d_wins[1] = w.wins + kMaxBatch;
     }
     // Each window keeps the tile map of its own launch (z chunks sized for the
-    // whole device); one launch then has a single tail instead of one per
-    // shot.  Measured on 24 windows of 173-300 cells: sizing the chunks for a
-    // 1/nshot share of the device instead makes full-depth columns, whose
-    // last round leaves the device idle longer.
+    // whole device, at least 16 planes deep when several shots share the
+    // launch, 4 for a single shot); one launch then has a single tail instead
+    // of one per shot.  Measured on 24 windows of 173-300 cells: sizing the
+    // chunks for a 1/nshot share of the device instead makes full-depth
+    // columns, whose last round leaves the device idle longer.
     wfd::Tuning tu = c->tuning;
     tu.variant = b->variant;  // one tile shape per launch
     wfd::WindowStep d{};
     d.g = step_grid(c);
-    const int nb = wfd::forward_tile_map(d.g, tu, &d.map);
+    const int nb = wfd::forward_tile_map(
+        d.g, tu, nshot == 1 ? wfd::kSingleMinZc : wfd::kBatchMinZc, &d.map);
     d.src = wfd::Source{src_idx, &w.scale->sigma, wavelet};
     d.rec = rec_table(w, nrec[i]);
     d.rec_scale = w.rec_scale;
@@ -1646,8 +1648,9 @@ wfd_status wfd_gbatch_create(wfd_gbatch **out, int32_t nshot, wfd_ctx *const *ct
     tu.adj_variant = b->adj_variant;
     wfd::GradWindow &d = h[(size_t)i];
     d.g = step_grid(c);
-    const int nf = wfd::forward_tile_map(d.g, tu, &d.fmap);
-    const int na = wfd::adjoint_tile_map(d.g, tu, illum, &d.amap);
+    const int min_zc = nshot == 1 ? wfd::kSingleMinZc : wfd::kBatchMinZc;
+    const int nf = wfd::forward_tile_map(d.g, tu, min_zc, &d.fmap);
+    const int na = wfd::adjoint_tile_map(d.g, tu, illum, min_zc, &d.amap);
     d.src = wfd::Source{src_idx, &w.scale->sigma, wavelet};
     d.rec = rec_table(w, nrec[i]);
     d.rec_scale = w.rec_scale;

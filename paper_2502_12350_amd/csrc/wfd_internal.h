@@ -135,8 +135,13 @@ hipError_t launch_forward_step(const StepGrid &g, const float *cur, const float 
                                const float *rec_scale, float *seis_tm, const Tuning &tu,
                                hipStream_t stream);
 
-// Blocks of one forward launch over g with tuning tu (and its tile map).
-int forward_tile_map(const StepGrid &g, const Tuning &tu, TileMap *map);
+// z chunks at least this deep: single launches, and batches of several shots
+// (whose windows fill the device together).
+constexpr int kSingleMinZc = 4, kBatchMinZc = 16;
+
+// Blocks of one window's share of a batched forward launch over g with tuning
+// tu, z chunks at least min_zc planes deep (and its tile map).
+int forward_tile_map(const StepGrid &g, const Tuning &tu, int min_zc, TileMap *map);
 
 // One step of every window in wins[0..nwin) (device array), nblocks blocks.
 // fs: some window has a free surface (selects the kernels with image loads).
@@ -149,8 +154,9 @@ hipError_t launch_adjoint_step(const Tuning &tu, const StepGrid &g, const float 
                                const float *wm, float *grad, const IllumOut &illum,
                                hipStream_t stream);
 
-// Blocks of one adjoint launch over g with tuning tu (and its tile map).
-int adjoint_tile_map(const StepGrid &g, const Tuning &tu, bool illum, TileMap *map);
+// Blocks of one window's share of a batched adjoint launch over g with
+// tuning tu, z chunks at least min_zc planes deep (and its tile map).
+int adjoint_tile_map(const StepGrid &g, const Tuning &tu, bool illum, int min_zc, TileMap *map);
 
 // Batched gradient: one forward step of every window (pool buffers cur_k,
 // prev_k -> out_k; receivers recorded when record != 0), and one adjoint step

@@ -694,7 +694,14 @@ int blocks_per_cu(K kernel, int threads) {
 // the 8-plane z halo of the stencil fields.  Fitted to step times measured at
 // 576^3 (forward 64x16 and adjoint 64x8 tiles, 2 to 19 chunks): time / cost
 // was constant to within 3 per cent, with a last round of few blocks taking
-// about half a full one.
+// about half a full one.  Chunks are at least min_zc planes deep.  A single
+// launch takes min_zc = 4: a grid too small to fill the device even then
+// (R <= 1) gets the shortest marches, since its step time is the latency of
+// one block's march (80^3 forward: 21 us per step with 16-plane chunks, 11 us
+// with 4-plane ones; 2 planes gave 11.2).  The windows of a batch of several
+// shots take 16: together they fill the device, and 4-plane chunks of small
+// windows only added halo re-reads (24 windows of 50-69 cells: gradients
+// 0.182 s against 0.162 s).
 constexpr double kTailFloor = 0.47;
 
 double launch_cost(double R, int zc, double halo) {
@@ -704,13 +711,13 @@ double launch_cost(double R, int zc, double halo) {
 }
 
 TileMap make_map(const StepGrid &g, int tx, int ty, int per_cu, int nch_override, int rounds,
-                 double halo) {
+                 double halo, int min_zc) {
   TileMap m;
   m.tiles_x = (g.nx + tx - 1) / tx;
   m.tiles_y = (g.ny + ty - 1) / ty;
   const int64_t tiles = (int64_t)m.tiles_x * m.tiles_y;
   const int64_t slots = (int64_t)per_cu * device_cus();
-  const int max_nch = std::max(1, (g.nz + 15) / 16);
+  const int max_nch = std::max(1, (g.nz + min_zc - 1) / min_zc);
   int nch = nch_override;
   if (nch <= 0 && rounds > 0) nch = (int)((rounds * slots + tiles / 2) / tiles);
   if (nch <= 0) {
@@ -807,7 +814,7 @@ hipError_t fwd_launch(const StepGrid &g, const float *cur, const float *prev, fl
   using S = FwdShape<V>;
   static const int nch_env = env_int("WFD_ZCHUNKS_FWD", 0);  // 0 = automatic
   const TileMap map = make_map(g, FwdTile<V>::TX, FwdTile<V>::TY, fwd_per_cu<V, VD, FS>(),
-                               nch_env, tu.rounds, kFwdHalo);
+                               nch_env, tu.rounds, kFwdHalo, kSingleMinZc);
   hipLaunchKernelGGL((k_forward<S::RY, S::NW, S::NI, VD, FS>), dim3(map.nblocks),
                      dim3(FwdTile<V>::NTHREADS), 0, stream, g, cur, prev, out, src, n, rec,
                      rec_scale, seis_tm, map);
@@ -832,7 +839,8 @@ hipError_t adj_launch(const Tuning &tu, const StepGrid &g, const float *cur, con
   static const int per_cu =
       blocks_per_cu(k_adjoint<S::RY, S::NW, S::NI, S::DL, VD, ILLUM, FS>, T::NTHREADS);
   static const int nch = env_int("WFD_ZCHUNKS_ADJ", 0);  // 0 = automatic
-  const TileMap map = make_map(g, T::TX, T::TY, per_cu, nch, tu.adj_rounds, kAdjHalo);
+  const TileMap map =
+      make_map(g, T::TX, T::TY, per_cu, nch, tu.adj_rounds, kAdjHalo, kSingleMinZc);
   hipLaunchKernelGGL((k_adjoint<S::RY, S::NW, S::NI, S::DL, VD, ILLUM, FS>), dim3(map.nblocks),
                      dim3(T::NTHREADS), 0, stream, g, cur, prev, out, rec, res_tm, m, wm, grad,
                      illum, map);
@@ -892,7 +900,7 @@ hipError_t adj_multi_dispatch(const GradWindow *wins, int nwin, int nblocks, int
 }
 
 template <int V>
-int adj_map(const StepGrid &g, const Tuning &tu, bool illum, TileMap *map) {
+int adj_map(const StepGrid &g, const Tuning &tu, bool illum, int min_zc, TileMap *map) {
   using S = AdjShape<V>;
   using T = Tile<S::RY, S::NW, S::NI>;
   const bool vd = g.m2 != nullptr, fs = g.zs != kNoSurface;
@@ -906,18 +914,18 @@ int adj_map(const StepGrid &g, const Tuning &tu, bool illum, TileMap *map) {
     per_cu = illum ? (fs ? WFD_PC(false, true, true) : WFD_PC(false, true, false))
                    : (fs ? WFD_PC(false, false, true) : WFD_PC(false, false, false));
 #undef WFD_PC
-  *map = make_map(g, T::TX, T::TY, per_cu, 0, tu.adj_rounds, kAdjHalo);
+  *map = make_map(g, T::TX, T::TY, per_cu, 0, tu.adj_rounds, kAdjHalo, min_zc);
   return map->nblocks;
 }
 
 }  // namespace
 
-int adjoint_tile_map(const StepGrid &g, const Tuning &tu, bool illum, TileMap *map) {
+int adjoint_tile_map(const StepGrid &g, const Tuning &tu, bool illum, int min_zc, TileMap *map) {
   switch (tu.adj_variant) {
-    case 1: return adj_map<1>(g, tu, illum, map);
-    case 2: return adj_map<2>(g, tu, illum, map);
-    case 3: return adj_map<3>(g, tu, illum, map);
-    default: return adj_map<0>(g, tu, illum, map);
+    case 1: return adj_map<1>(g, tu, illum, min_zc, map);
+    case 2: return adj_map<2>(g, tu, illum, min_zc, map);
+    case 3: return adj_map<3>(g, tu, illum, min_zc, map);
+    default: return adj_map<0>(g, tu, illum, min_zc, map);
   }
 }
 
@@ -977,7 +985,7 @@ hipError_t launch_forward_step(const StepGrid &g, const float *cur, const float 
 #undef WFD_FWD1
 }
 
-int forward_tile_map(const StepGrid &g, const Tuning &tu, TileMap *map) {
+int forward_tile_map(const StepGrid &g, const Tuning &tu, int min_zc, TileMap *map) {
   const bool vd = g.m2 != nullptr, fs = g.zs != kNoSurface;
   int tx = 64, ty = 16, per_cu = 4;
 #define WFD_PCU(V)                                                                 \
@@ -993,7 +1001,7 @@ int forward_tile_map(const StepGrid &g, const Tuning &tu, TileMap *map) {
     default: WFD_PCU(0); break;
   }
 #undef WFD_PCU
-  *map = make_map(g, tx, ty, per_cu, 0, tu.rounds, kFwdHalo);
+  *map = make_map(g, tx, ty, per_cu, 0, tu.rounds, kFwdHalo, min_zc);
   return map->nblocks;
 }
 
