@@ -207,8 +207,9 @@ wfd_status wfd_misfit_workspace_bytes(const wfd_ctx *ctx, int32_t nrec, size_t *
 /* Misfit and velocity gradient of one shot (Alg. 3 body for one shot).
  * With the CPML boundary WFD_CKPT_FULL keeps the layer's correction of every
  * step (on the shell of points the layer reaches) for the imaging condition;
- * WFD_CKPT_REVOLVE keeps six memory-variable volumes with each checkpoint
- * (a checkpoint then costs 8 volumes, not 2) and recomputes a visited step's
+ * WFD_CKPT_REVOLVE keeps the six memory variables with each checkpoint
+ * (stored near the layer only: 4 W / N of a volume per axis, W = B + 8 for
+ * a layer of B cells on an axis of N padded cells) and recomputes a visited step's
  * correction; WFD_CKPT_HOST returns WFD_E_ARG.  The steps:
  * forward sweep with recording and wavefield saving, res = d - d_obs,
  * J = 1/2 sum res^2, discrete adjoint sweep (exact transpose of the forward

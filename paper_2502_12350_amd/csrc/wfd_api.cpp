@@ -80,6 +80,7 @@ struct wfd_ctx {
   bool cpml = false;         // CPML layer instead of the sponge
   wfd::CpmlTables cpml_tab{};
   wfd::Shell shell{};        // the points the layer's terms reach
+  int64_t cpml_len[3] = {1, 1, 1};  // floats of a compact memory variable per axis
 
   // host staging of the receiver tables (kept alive until the upload ends)
   std::vector<char> stage;
@@ -351,6 +352,13 @@ struct Work {
   size_t bytes;
 };
 
+// Floats of CPML memory variable i (psi or zeta, mu or nu, of axis i % 3) and
+// of a set of all six.
+int64_t mem_len(const wfd_ctx *c, int i) { return c->cpml_len[i % 3]; }
+int64_t mem_set_len(const wfd_ctx *c) {
+  return 2 * (c->cpml_len[0] + c->cpml_len[1] + c->cpml_len[2]);
+}
+
 int64_t snapshots_for(const wfd_ctx *c, const wfd_ckpt *ck) {
   if (ck->mode == WFD_CKPT_FULL) return c->grid.nt;
   if (ck->mode == WFD_CKPT_HOST) return 0;
@@ -358,8 +366,10 @@ int64_t snapshots_for(const wfd_ctx *c, const wfd_ckpt *ck) {
   size_t free_b = 0, total_b = 0;
   if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) return 0;
   const double frac = (ck->mem_fraction > 0 && ck->mem_fraction <= 1.0) ? ck->mem_fraction : 0.8;
-  // a checkpoint holds a leapfrog pair, and with CPML six memory variables
-  const double pair = (c->cpml ? 8.0 : 2.0) * (double)c->vol * sizeof(float);
+  // a checkpoint holds a leapfrog pair, and with CPML a set of six memory
+  // variables on the layer
+  const double pair =
+      (2.0 * (double)c->vol + (c->cpml ? (double)mem_set_len(c) : 0.0)) * sizeof(float);
   int64_t s = (int64_t)(frac * (double)free_b / pair);
   return std::max<int64_t>(1, std::min<int64_t>(s, c->grid.nt));
 }
@@ -436,12 +446,12 @@ Work work_layout(const wfd_ctx *c, int nrec, WorkKind kind, const wfd_ckpt *ck, 
   }
   if (c->cpml) {
     const size_t S = (size_t)c->shell.start[c->shell.nbox];
-    for (int i = 0; i < 6; ++i) w.mem[i] = cv.take<float>((size_t)c->vol);
+    for (int i = 0; i < 6; ++i) w.mem[i] = cv.take<float>((size_t)mem_len(c, i));
     if (kind == WorkKind::Gradient && ck && ck->mode == WFD_CKPT_FULL)
       w.cstore = cv.take<float>((size_t)c->grid.nt * S);
     if (kind == WorkKind::Gradient && ck && ck->mode == WFD_CKPT_REVOLVE) {
-      for (int i = 0; i < 6; ++i) w.amem[i] = cv.take<float>((size_t)c->vol);
-      w.smem = cv.take<float>((size_t)nsnap * 6 * (size_t)c->vol);
+      for (int i = 0; i < 6; ++i) w.amem[i] = cv.take<float>((size_t)mem_len(c, i));
+      w.smem = cv.take<float>((size_t)nsnap * (size_t)mem_set_len(c));
       w.lastc = cv.take<float>(std::max<size_t>(S, 1));
       w.visitc = cv.take<float>(std::max<size_t>(S, 1));
     }
@@ -779,7 +789,16 @@ wfd_status wfd_set_model(wfd_ctx *c, const wfd_grid *grid, const float *vel,
     HIP_TRY(hipStreamSynchronize(c->stream));
     c->cpml_tab = wfd::CpmlTables{L.cpml[0], L.cpml[1], L.cpml[2], L.cpml[3], L.cpml[4],
                                   L.cpml[5], (float)(1.0 / grid->dx), (float)(1.0 / grid->dy),
-                                  (float)(1.0 / grid->dz)};
+                                  (float)(1.0 / grid->dz),
+                                  {wfd::cpml_slab_half(c->Nx, grid->border),
+                                   wfd::cpml_slab_half(c->Ny, grid->border),
+                                   wfd::cpml_slab_half(c->Nz, grid->border)},
+                                  {wfd::cpml_slab_len(c->Nx, grid->border),
+                                   wfd::cpml_slab_len(c->Ny, grid->border),
+                                   wfd::cpml_slab_len(c->Nz, grid->border)}};
+    for (int d = 0; d < 3; ++d)
+      c->cpml_len[d] = std::max<int64_t>(
+          1, wfd::cpml_mem_len(d, c->Nx, c->Ny, c->Nz, grid->border));
     c->shell = make_shell(*grid, c->Nx, c->Ny, c->Nz);
     for (int b = 0; b < c->shell.nbox; ++b)
       if (c->shell.start[b + 1] - c->shell.start[b] >= (int64_t(1) << 31))
@@ -885,8 +904,8 @@ wfd_status forward_core(wfd_ctx *c, const float *wavelet, const double src_xyz[3
   const wfd::RecTable rt = rec_table(w, nrec);
   const wfd::Source src{src_idx, &w.scale->sigma, wavelet};
   if (c->cpml)
-    for (float *m : w.mem)
-      if ((s = zero(c, m, c->vol)) != WFD_OK) return s;
+    for (int i = 0; i < 6; ++i)
+      if ((s = zero(c, w.mem[i], mem_len(c, i))) != WFD_OK) return s;
   float *cur = w.W1, *prev = w.W2;
   for (int n = 0; n < c->grid.nt; ++n) {
     {
@@ -988,7 +1007,8 @@ wfd_status wfd_gradient_ex(wfd_ctx *c, const float *wavelet, const double src_xy
   } else {
     // derived count: as many pairs as the given workspace holds
     const size_t base = work_layout(c, nrec, WorkKind::Gradient, ck, 0, nullptr).bytes;
-    const size_t pair = align_up((size_t)c->vol * sizeof(float)) * (c->cpml ? 8 : 2);
+    const size_t pair = align_up((size_t)c->vol * sizeof(float)) * 2 +
+                        (c->cpml ? (size_t)mem_set_len(c) * sizeof(float) : 0);
     nsnap = work_bytes > base ? (int64_t)((work_bytes - base) / pair) : 0;
     nsnap = std::min<int64_t>(nsnap, c->grid.nt);
     if (nsnap < 1) return fail(WFD_E_NOMEM, "workspace holds no checkpoint pair");
@@ -1081,14 +1101,14 @@ wfd_status wfd_gradient_ex(wfd_ctx *c, const float *wavelet, const double src_xy
       return w.store + (size_t)(m - 1) * (size_t)c->vol;
     };
     if (c->cpml)
-      for (float *m : w.mem)
-        if ((s = zero(c, m, c->vol)) != WFD_OK) return s;
+      for (int i = 0; i < 6; ++i)
+        if ((s = zero(c, w.mem[i], mem_len(c, i))) != WFD_OK) return s;
     for (int n = 0; n < nt; ++n)
       if ((s = fwd(S(n), S(n - 1), S(n + 1), n, true)) != WFD_OK) return s;
     if ((s = residual()) != WFD_OK) return s;
     if (c->cpml)  // the adjoint's mu and nu start at zero
-      for (float *m : w.mem)
-        if ((s = zero(c, m, c->vol)) != WFD_OK) return s;
+      for (int i = 0; i < 6; ++i)
+        if ((s = zero(c, w.mem[i], mem_len(c, i))) != WFD_OK) return s;
     for (int m = nt; m >= 1; --m)
       if ((s = adjoint(m, S(m))) != WFD_OK) return s;
   } else if (ck->mode == WFD_CKPT_HOST) {
@@ -1168,18 +1188,22 @@ wfd_status wfd_gradient_ex(wfd_ctx *c, const float *wavelet, const double src_xy
     // w.mem while m is the working state and copied to and from slot sets.
     auto slot_mem = [&](size_t slot) {
       std::array<float *, 6> m;
-      for (int i = 0; i < 6; ++i) m[i] = w.smem + (slot * 6 + (size_t)i) * (size_t)c->vol;
+      float *p = w.smem + slot * (size_t)mem_set_len(c);
+      for (int i = 0; i < 6; ++i) {
+        m[i] = p;
+        p += mem_len(c, i);
+      }
       return m;
     };
     auto copy_mem = [&](float *const *dst, float *const *src) -> wfd_status {
       for (int i = 0; i < 6; ++i)
-        HIP_TRY(hipMemcpyAsync(dst[i], src[i], (size_t)c->vol * sizeof(float),
+        HIP_TRY(hipMemcpyAsync(dst[i], src[i], (size_t)mem_len(c, i) * sizeof(float),
                                hipMemcpyDeviceToDevice, c->stream));
       return WFD_OK;
     };
     if (c->cpml)
-      for (float *m : w.amem)
-        if ((s = zero(c, m, c->vol)) != WFD_OK) return s;
+      for (int i = 0; i < 6; ++i)
+        if ((s = zero(c, w.amem[i], mem_len(c, i))) != WFD_OK) return s;
     for (size_t i = 0; i + 3 <= plan.size(); i += 3) {
       const int op = plan[i], a = plan[i + 1], b = plan[i + 2];
       if (op == wfd::kAdvance) {
@@ -1191,8 +1215,8 @@ wfd_status wfd_gradient_ex(wfd_ctx *c, const float *wavelet, const double src_xy
             if ((s = zero(c, buf[cur], c->vol)) != WFD_OK) return s;
             if ((s = zero(c, buf[prev], c->vol)) != WFD_OK) return s;
             if (c->cpml)
-              for (float *m : w.mem)
-                if ((s = zero(c, m, c->vol)) != WFD_OK) return s;
+              for (int i = 0; i < 6; ++i)
+                if ((s = zero(c, w.mem[i], mem_len(c, i))) != WFD_OK) return s;
           } else {
             Slot *sl = slot_of(a);
             if (!sl) return fail(WFD_E_STATE, "checkpoint plan: state %d not stored", a);

@@ -20,6 +20,16 @@
 // of planes; where the box is within reach of a z layer each thread keeps
 // nine-plane queues along z, and x and y neighbours come through the caches.
 // The point-wise nu update runs one thread per shell point.
+//
+// A memory variable of axis d is nonzero only on that axis' layer, the B
+// border cells at each end of the padded axis, and is stored as two slabs of
+// W = B + 8 cells, [0, W) and [N - W, N) (the whole axis when they would
+// meet): x as [Nz][Ny][2W], y as [Nz][2W][Nx], z as [2W][Ny][Nx].  A point
+// within reach of the layer (4 cells) reads the variable at most 4 cells
+// further, so every read lands in the point's own slab and a line of the
+// variable is addressed like a line of a full volume.  Psi and zeta (or mu
+// and nu) of an axis take 4 W / N of a volume rather than two volumes, and
+// every checkpoint of the gradient's forward sweep holds a set of six.
 #include <hip/hip_runtime.h>
 
 #include <stdint.h>
@@ -42,6 +52,31 @@ __device__ __forceinline__ float d2c(int j) {
 
 __device__ __forceinline__ int64_t lin(const StepGrid &g, int x, int y, int z) {
   return (int64_t)z * g.plane + (int64_t)y * g.pitch + x;
+}
+
+// Compact memory variables (above): stored index of cell i on an axis of n
+// cells with slab width `half` and stored length `len`, whether it is stored,
+// and the element of (x, y, z) in the x, y or z variable.
+__device__ __forceinline__ int cidx(int i, int half, int len, int n) {
+  return i < half ? i : i - (n - len);
+}
+__device__ __forceinline__ bool stored(int i, int half, int len, int n) {
+  return i < half || i >= n - (len - half);
+}
+__device__ __forceinline__ int64_t mem_x(const StepGrid &g, const CpmlTables &t, int x, int y,
+                                         int z) {
+  return ((int64_t)z * g.ny + y) * t.len[0] + cidx(x, t.half[0], t.len[0], g.nx);
+}
+__device__ __forceinline__ int64_t mem_y(const StepGrid &g, const CpmlTables &t, int x, int y,
+                                         int z) {
+  return ((int64_t)z * t.len[1] + cidx(y, t.half[1], t.len[1], g.ny)) * g.nx + x;
+}
+__device__ __forceinline__ int64_t mem_z(const StepGrid &g, const CpmlTables &t, int x, int y,
+                                         int z) {
+  return ((int64_t)cidx(z, t.half[2], t.len[2], g.nz) * g.ny + y) * g.nx + x;
+}
+__device__ __forceinline__ bool stored_z(const StepGrid &g, const CpmlTables &t, int z) {
+  return z >= 0 && z < g.nz && stored(z, t.half[2], t.len[2], g.nz);
 }
 
 // Shell point q -> (x, y, z).  Offsets inside a box fit 32 bits (the host
@@ -197,12 +232,20 @@ __global__ void __launch_bounds__(kThreads)
   if (zq) qw.prime(wz, c.z0);
   for (int z = c.z0; z < c.z1; ++z) {
     const int64_t p = (int64_t)z * g.plane + c.pxy;
-    if (ax != 0.0f) px[p] = bx * px[p] + ax * (first_diff(Line{w, nullptr, p, 1, c.x, g.nx}) * t.ihx);
-    if (ay != 0.0f)
-      py[p] = by * py[p] + ay * (first_diff(Line{w, nullptr, p, g.pitch, c.y, g.ny}) * t.ihy);
+    if (ax != 0.0f) {
+      float &v = px[mem_x(g, t, c.x, c.y, z)];
+      v = bx * v + ax * (first_diff(Line{w, nullptr, p, 1, c.x, g.nx}) * t.ihx);
+    }
+    if (ay != 0.0f) {
+      float &v = py[mem_y(g, t, c.x, c.y, z)];
+      v = by * v + ay * (first_diff(Line{w, nullptr, p, g.pitch, c.y, g.ny}) * t.ihy);
+    }
     if (zq) {
       const float az = t.az[z];
-      if (az != 0.0f) pz[p] = t.bz[z] * pz[p] + az * (qw.d1() * t.ihz);
+      if (az != 0.0f) {
+        float &v = pz[mem_z(g, t, c.x, c.y, z)];
+        v = t.bz[z] * v + az * (qw.d1() * t.ihz);
+      }
       qw.advance(wz, z);
     }
   }
@@ -219,7 +262,7 @@ __global__ void __launch_bounds__(kThreads)
   const bool nx = near(sh, 0, c.x), ny = near(sh, 1, c.y);
   const float ax = t.ax[c.x], bx = t.bx[c.x], ay = t.ay[c.y], by = t.by[c.y];
   auto wz = [&](int zz) { return zval(w, g, c.pxy, zz, true); };
-  auto pzz = [&](int zz) { return zval(pz, g, c.pxy, zz, false); };
+  auto pzz = [&](int zz) { return stored_z(g, t, zz) ? pz[mem_z(g, t, c.x, c.y, zz)] : 0.0f; };
   ZWin qw, qp;
   if (zq) {
     qw.prime(wz, c.z0);
@@ -229,23 +272,25 @@ __global__ void __launch_bounds__(kThreads)
     const int64_t p = (int64_t)z * g.plane + c.pxy;
     float C = 0.0f;
     if (nx) {
-      const float d1p = first_diff(Line{px, nullptr, p, 1, c.x, g.nx}) * t.ihx;
+      const int64_t q = mem_x(g, t, c.x, c.y, z);
+      const float d1p = first_diff(Line{px, nullptr, q, 1, c.x, g.nx}) * t.ihx;
       C += d1p;
       if (ax != 0.0f) {
         const float v =
-            bx * zx[p] + ax * (second_diff(Line{w, nullptr, p, 1, c.x, g.nx}) * g.cx + d1p);
-        zx[p] = v;
+            bx * zx[q] + ax * (second_diff(Line{w, nullptr, p, 1, c.x, g.nx}) * g.cx + d1p);
+        zx[q] = v;
         C += v;
       }
     }
     if (ny) {
-      const float d1p = first_diff(Line{py, nullptr, p, g.pitch, c.y, g.ny}) * t.ihy;
+      const int64_t q = mem_y(g, t, c.x, c.y, z);
+      const float d1p = first_diff(Line{py, nullptr, q, g.nx, c.y, g.ny}) * t.ihy;
       C += d1p;
       if (ay != 0.0f) {
-        const float v = by * zy[p] +
+        const float v = by * zy[q] +
                         ay * (second_diff(Line{w, nullptr, p, g.pitch, c.y, g.ny}) *
                                   g.cy + d1p);
-        zy[p] = v;
+        zy[q] = v;
         C += v;
       }
     }
@@ -255,8 +300,9 @@ __global__ void __launch_bounds__(kThreads)
         C += d1p;
         const float az = t.az[z];
         if (az != 0.0f) {
-          const float v = t.bz[z] * zz_[p] + az * (qw.d2() * g.cz + d1p);
-          zz_[p] = v;
+          float &zv = zz_[mem_z(g, t, c.x, c.y, z)];
+          const float v = t.bz[z] * zv + az * (qw.d2() * g.cz + d1p);
+          zv = v;
           C += v;
         }
       }
@@ -276,11 +322,19 @@ __global__ void __launch_bounds__(kThreads)
        q += (int64_t)gridDim.x * blockDim.x) {
     int x, y, z;
     decode(sh, q, x, y, z);
-    const int64_t p = lin(g, x, y, z);
-    const float f = phi1[p];
-    if (t.ax[x] != 0.0f) nx_[p] = f + t.bx[x] * nx_[p];
-    if (t.ay[y] != 0.0f) ny_[p] = f + t.by[y] * ny_[p];
-    if (t.az[z] != 0.0f) nz_[p] = f + t.bz[z] * nz_[p];
+    const float f = phi1[lin(g, x, y, z)];
+    if (t.ax[x] != 0.0f) {
+      float &v = nx_[mem_x(g, t, x, y, z)];
+      v = f + t.bx[x] * v;
+    }
+    if (t.ay[y] != 0.0f) {
+      float &v = ny_[mem_y(g, t, x, y, z)];
+      v = f + t.by[y] * v;
+    }
+    if (t.az[z] != 0.0f) {
+      float &v = nz_[mem_z(g, t, x, y, z)];
+      v = f + t.bz[z] * v;
+    }
   }
 }
 
@@ -294,27 +348,32 @@ __global__ void __launch_bounds__(kThreads)
   const float ax = t.ax[c.x], bx = t.bx[c.x], ay = t.ay[c.y], by = t.by[c.y];
   // D1 of (a nu + phi1); along z from a queue of a_z nu_z + phi1
   auto fz = [&](int zz) {
-    return (zz >= 0 && zz < g.nz) ? t.az[zz] * nz_[(int64_t)zz * g.plane + c.pxy] +
-                                        phi1[(int64_t)zz * g.plane + c.pxy]
-                                  : 0.0f;
+    if (zz < 0 || zz >= g.nz) return 0.0f;
+    const float f = phi1[(int64_t)zz * g.plane + c.pxy];
+    return stored_z(g, t, zz) ? t.az[zz] * nz_[mem_z(g, t, c.x, c.y, zz)] + f : f;
   };
   ZWin qf;
   if (zq) qf.prime(fz, c.z0);
   for (int z = c.z0; z < c.z1; ++z) {
     const int64_t p = (int64_t)z * g.plane + c.pxy;
     if (ax != 0.0f) {
-      const float d = first_diff(Line{nx_, t.ax, p, 1, c.x, g.nx}) +
+      const int64_t q = mem_x(g, t, c.x, c.y, z);
+      const float d = first_diff(Line{nx_, t.ax, q, 1, c.x, g.nx}) +
                       first_diff(Line{phi1, nullptr, p, 1, c.x, g.nx});
-      mx[p] = bx * mx[p] - d * t.ihx;
+      mx[q] = bx * mx[q] - d * t.ihx;
     }
     if (ay != 0.0f) {
-      const float d = first_diff(Line{ny_, t.ay, p, g.pitch, c.y, g.ny}) +
+      const int64_t q = mem_y(g, t, c.x, c.y, z);
+      const float d = first_diff(Line{ny_, t.ay, q, g.nx, c.y, g.ny}) +
                       first_diff(Line{phi1, nullptr, p, g.pitch, c.y, g.ny});
-      my[p] = by * my[p] - d * t.ihy;
+      my[q] = by * my[q] - d * t.ihy;
     }
     if (zq) {
       const float az = t.az[z];
-      if (az != 0.0f) mz[p] = t.bz[z] * mz[p] - qf.d1() * t.ihz;
+      if (az != 0.0f) {
+        float &v = mz[mem_z(g, t, c.x, c.y, z)];
+        v = t.bz[z] * v - qf.d1() * t.ihz;
+      }
       qf.advance(fz, z);
     }
   }
@@ -338,10 +397,10 @@ __global__ void __launch_bounds__(kThreads)
       z2 = 2 * g.zs - zz;
       sgn = -1.0f;
     }
-    return (z2 >= 0 && z2 < g.nz) ? sgn * t.az[z2] * nz_[(int64_t)z2 * g.plane + c.pxy] : 0.0f;
+    return stored_z(g, t, z2) ? sgn * t.az[z2] * nz_[mem_z(g, t, c.x, c.y, z2)] : 0.0f;
   };
   auto muz = [&](int zz) {
-    return (zz >= 0 && zz < g.nz) ? t.az[zz] * mz[(int64_t)zz * g.plane + c.pxy] : 0.0f;
+    return stored_z(g, t, zz) ? t.az[zz] * mz[mem_z(g, t, c.x, c.y, zz)] : 0.0f;
   };
   ZWin qn, qm;
   if (zq) {
@@ -351,12 +410,16 @@ __global__ void __launch_bounds__(kThreads)
   for (int z = c.z0; z < c.z1; ++z) {
     const int64_t p = (int64_t)z * g.plane + c.pxy;
     float corr = 0.0f;
-    if (nx)
-      corr += second_diff(Line{nx_, t.ax, p, 1, c.x, g.nx}) * g.cx -
-              first_diff(Line{mx, t.ax, p, 1, c.x, g.nx}) * t.ihx;
-    if (ny)
-      corr += second_diff(Line{ny_, t.ay, p, g.pitch, c.y, g.ny}) * g.cy -
-              first_diff(Line{my, t.ay, p, g.pitch, c.y, g.ny}) * t.ihy;
+    if (nx) {
+      const int64_t q = mem_x(g, t, c.x, c.y, z);
+      corr += second_diff(Line{nx_, t.ax, q, 1, c.x, g.nx}) * g.cx -
+              first_diff(Line{mx, t.ax, q, 1, c.x, g.nx}) * t.ihx;
+    }
+    if (ny) {
+      const int64_t q = mem_y(g, t, c.x, c.y, z);
+      corr += second_diff(Line{ny_, t.ay, q, g.nx, c.y, g.ny}) * g.cy -
+              first_diff(Line{my, t.ay, q, g.nx, c.y, g.ny}) * t.ihy;
+    }
     if (zq) {
       if (near(sh, 2, z)) corr += qn.d2() * g.cz - qm.d1() * t.ihz;
       qn.advance(nuz, z);

@@ -262,7 +262,23 @@ constexpr int kStencilRadius = 4;  // reach of the eighth-order differences
 struct CpmlTables {
   const float *ax, *bx, *ay, *by, *az, *bz;
   float ihx, ihy, ihz;  // 1 / h per axis
+  // Compact memory variables (layout in wfd_cpml.hip): per axis x, y, z the
+  // slab width W (cells [0, W) and [N - W, N) are stored) and the stored
+  // length L of the axis (2 W, or N when the two slabs would meet).
+  int half[3], len[3];
 };
+// Stored slab width of an axis of N padded cells with a layer of B cells: the
+// layer plus the 8 cells that points within reach of it (4) see through their
+// own reach (4), so every memory-variable read of the layer kernels lands in
+// the slab; the whole axis when the two slabs would meet.
+inline int cpml_slab_half(int N, int B) { return 2 * (B + 8) >= N ? N : B + 8; }
+inline int cpml_slab_len(int N, int B) { return 2 * (B + 8) >= N ? N : 2 * (B + 8); }
+// Floats of one compact memory variable of axis d (0, 1, 2 = x, y, z).
+inline int64_t cpml_mem_len(int d, int Nx, int Ny, int Nz, int B) {
+  return d == 0   ? (int64_t)Nz * Ny * cpml_slab_len(Nx, B)
+         : d == 1 ? (int64_t)Nz * cpml_slab_len(Ny, B) * Nx
+                  : (int64_t)cpml_slab_len(Nz, B) * Ny * Nx;
+}
 // The points the layer's terms reach: the padded grid minus the inner box
 // more than 4 cells from every layer, as up to 6 boxes [lo, hi) in (z, y, x).
 // Point q of the shell lies in the box b with start[b] <= q < start[b + 1],
