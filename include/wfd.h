@@ -464,7 +464,8 @@ wfd_status wfd_cnn_wgrad_workspace_bytes(int32_t nx, int32_t ny, int32_t nz, siz
  *   db[co] = sum_p dz[p][co]                                     (if non-NULL)
  * BF16 products, FP32 sums in a fixed order (deterministic).  in and (for
  * 16 output channels) dz 16-byte aligned; work (device, caller-owned) at
- * least wfd_cnn_wgrad_workspace_bytes, else WFD_E_NOMEM. */
+ * least wfd_cnn_wgrad_workspace_bytes, else WFD_E_NOMEM.  An x-y plane holds
+ * at most 2^24 voxels (WFD_E_ARG otherwise). */
 wfd_status wfd_cnn_wgrad(const uint16_t *in_dev, const uint16_t *dz_dev, int32_t nx, int32_t ny,
                          int32_t nz, int32_t cin, int32_t cout, float *dw_dev,
                          float *db_dev_or_null, void *work_dev, size_t work_bytes, void *stream);

@@ -2013,6 +2013,8 @@ wfd_status wfd_cnn_wgrad(const uint16_t *in, const uint16_t *dz, int32_t nx, int
   if (!layer) return fail(WFD_E_ARG, "no network layer %d -> %d", cin, cout);
   if (!cnn_volume_ok(nx, ny, nz))
     return fail(WFD_E_ARG, "volume %d x %d x %d empty or too large", nx, ny, nz);
+  if ((int64_t)nx * ny > (int64_t(1) << 24))
+    return fail(WFD_E_ARG, "an x-y plane of %d x %d voxels exceeds 2^24", nx, ny);
   if (!in || !dz || !dw || !work) return fail(WFD_E_ARG, "NULL argument");
   if ((uintptr_t)in % 16) return fail(WFD_E_ARG, "input must be 16-byte aligned");
   if (cout == 16 && (uintptr_t)dz % 16)

@@ -600,56 +600,65 @@ __device__ __forceinline__ uint32_t wg_hi(uint32_t a, uint32_t b) {
 
 // Input plane gz (66 x 6 voxels from (x0 - 1, y0 - 1)) in pairs of voxels
 // (lx = 2p, 2p + 1): item = (row, channel half, pair).  Fetched into
-// registers, then stored as one dword per channel.
+// registers, then stored as one dword per channel.  init() computes, once per
+// tile, each item's byte offsets in a plane (kFarVox-based past the volume,
+// so that the buffer loads read zero) and its LDS position.
 template <int CIN>
 struct WgIn {
   static constexpr int HALVES = CIN == 16 ? 2 : 1;
   static constexpr int ITEMS = WG_LY * HALVES * 33;
   static constexpr int PER = (ITEMS + WG_THR - 1) / WG_THR;
   static constexpr int SLOT = WG_LY * CIN * WG_RX;  // elements per slot
-  u32x4 a[PER], b[PER];
-  __device__ __forceinline__ void fetch(const uint16_t *__restrict__ in, int nx, int ny, int nz,
-                                        int x0, int y0, int gz) {
+  static constexpr uint32_t VB = CIN * 2;           // bytes per voxel
+  struct Data {
+    u32x4 a[PER], b[PER];
+  };
+  uint32_t oa[PER], ob[PER];  // byte offsets of voxels xa and xa + 1
+  int ld[PER];                // dword offset in a slot, -1 past the items
+  __device__ __forceinline__ void init(int nx, int ny, int x0, int y0) {
 #pragma unroll
     for (int i = 0; i < PER; ++i) {
       const int q = threadIdx.x + i * WG_THR;
       const int pr = q % 33, h = (q / 33) % HALVES, ly = q / (33 * HALVES);
       const int gy = y0 - 1 + ly, xa = x0 - 1 + 2 * pr;
-      const bool row = q < ITEMS && gy >= 0 && gy < ny && gz >= 0 && gz < nz;
-      const int64_t base = ((int64_t)gz * ny + gy) * nx;
-      u32x4 va = {0u, 0u, 0u, 0u}, vb = {0u, 0u, 0u, 0u};
-      if (CIN == 16) {
-        if (row && xa >= 0 && xa < nx)
-          va = *reinterpret_cast<const u32x4 *>(in + (base + xa) * 16 + 8 * h);
-        if (row && xa + 1 < nx)
-          vb = *reinterpret_cast<const u32x4 *>(in + (base + xa + 1) * 16 + 8 * h);
-      } else if (CIN == 2) {  // one dword per voxel
-        if (row && xa >= 0 && xa < nx) va[0] = *reinterpret_cast<const uint32_t *>(in + (base + xa) * 2);
-        if (row && xa + 1 < nx) vb[0] = *reinterpret_cast<const uint32_t *>(in + (base + xa + 1) * 2);
-      } else {  // CIN = 1: one element per voxel
-        if (row && xa >= 0 && xa < nx) va[0] = in[base + xa];
-        if (row && xa + 1 < nx) vb[0] = in[base + xa + 1];
-      }
-      a[i] = va;
-      b[i] = vb;
+      const bool row = q < ITEMS && gy >= 0 && gy < ny;
+      const uint32_t hb = CIN == 16 ? 16u * h : 0u;
+      oa[i] = (row && xa >= 0 && xa < nx ? (uint32_t)(gy * nx + xa) : kFarVox) * VB + hb;
+      ob[i] = (row && xa + 1 < nx ? (uint32_t)(gy * nx + xa + 1) : kFarVox) * VB + hb;
+      ld[i] = q < ITEMS ? ((ly * CIN + 8 * h) * WG_RX) / 2 + pr : -1;
     }
   }
-  __device__ __forceinline__ void store(uint32_t *lds, int slot) const {
+  __device__ __forceinline__ void fetch(Data &d, const uint16_t *__restrict__ in, int64_t pv,
+                                        int nz, int gz) const {
+    const Rsrc r = plane_buf(in, pv, CIN, nz, gz);
 #pragma unroll
     for (int i = 0; i < PER; ++i) {
-      const int q = threadIdx.x + i * WG_THR;
-      if (q >= ITEMS) continue;
-      const int pr = q % 33, h = (q / 33) % HALVES, ly = q / (33 * HALVES);
-      uint32_t *d = lds + (slot * SLOT + (ly * CIN + 8 * h) * WG_RX) / 2 + pr;
+      if (CIN == 16) {
+        d.a[i] = __builtin_amdgcn_raw_buffer_load_b128(r, oa[i], 0, 0);
+        d.b[i] = __builtin_amdgcn_raw_buffer_load_b128(r, ob[i], 0, 0);
+      } else if (CIN == 2) {  // one dword per voxel
+        d.a[i] = u32x4{__builtin_amdgcn_raw_buffer_load_b32(r, oa[i], 0, 0), 0u, 0u, 0u};
+        d.b[i] = u32x4{__builtin_amdgcn_raw_buffer_load_b32(r, ob[i], 0, 0), 0u, 0u, 0u};
+      } else {  // CIN = 1: one element per voxel
+        d.a[i] = u32x4{(uint32_t)__builtin_amdgcn_raw_buffer_load_b16(r, oa[i], 0, 0), 0u, 0u, 0u};
+        d.b[i] = u32x4{(uint32_t)__builtin_amdgcn_raw_buffer_load_b16(r, ob[i], 0, 0), 0u, 0u, 0u};
+      }
+    }
+  }
+  __device__ __forceinline__ void store(uint32_t *lds, int slot, const Data &dd) const {
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+      if (i + 1 == PER && ld[i] < 0) continue;
+      uint32_t *d = lds + slot * (SLOT / 2) + ld[i];
       if (CIN == 16) {
 #pragma unroll
         for (int w = 0; w < 4; ++w) {
-          d[(2 * w) * (WG_RX / 2)] = wg_lo(a[i][w], b[i][w]);
-          d[(2 * w + 1) * (WG_RX / 2)] = wg_hi(a[i][w], b[i][w]);
+          d[(2 * w) * (WG_RX / 2)] = wg_lo(dd.a[i][w], dd.b[i][w]);
+          d[(2 * w + 1) * (WG_RX / 2)] = wg_hi(dd.a[i][w], dd.b[i][w]);
         }
       } else {
-        d[0] = wg_lo(a[i][0], b[i][0]);
-        if (CIN == 2) d[WG_RX / 2] = wg_hi(a[i][0], b[i][0]);
+        d[0] = wg_lo(dd.a[i][0], dd.b[i][0]);
+        if (CIN == 2) d[WG_RX / 2] = wg_hi(dd.a[i][0], dd.b[i][0]);
       }
     }
   }
@@ -662,44 +671,52 @@ struct WgDz {
   static constexpr int ITEMS = WG_TY * HALVES * 32;
   static constexpr int PER = (ITEMS + WG_THR - 1) / WG_THR;
   static constexpr int SLOT = WG_TY * COUT * WG_RX;
-  u32x4 a[PER], b[PER];
-  __device__ __forceinline__ void fetch(const uint16_t *__restrict__ dz, int nx, int ny, int x0,
-                                        int y0, int gz) {
+  static constexpr uint32_t VB = COUT * 2;
+  struct Data {
+    u32x4 a[PER], b[PER];
+  };
+  uint32_t oa[PER], ob[PER];
+  int ld[PER];
+  __device__ __forceinline__ void init(int nx, int ny, int x0, int y0) {
 #pragma unroll
     for (int i = 0; i < PER; ++i) {
       const int q = threadIdx.x + i * WG_THR;
       const int pr = q % 32, h = (q / 32) % HALVES, r = q / (32 * HALVES);
       const int gy = y0 + r, xa = x0 + 2 * pr;
       const bool row = q < ITEMS && gy < ny;
-      const int64_t base = ((int64_t)gz * ny + gy) * nx;
-      u32x4 va = {0u, 0u, 0u, 0u}, vb = {0u, 0u, 0u, 0u};
-      if (COUT == 16) {
-        if (row && xa < nx) va = *reinterpret_cast<const u32x4 *>(dz + (base + xa) * 16 + 8 * h);
-        if (row && xa + 1 < nx)
-          vb = *reinterpret_cast<const u32x4 *>(dz + (base + xa + 1) * 16 + 8 * h);
-      } else {  // COUT = 1: one element per voxel
-        if (row && xa < nx) va[0] = dz[base + xa];
-        if (row && xa + 1 < nx) vb[0] = dz[base + xa + 1];
-      }
-      a[i] = va;
-      b[i] = vb;
+      const uint32_t hb = COUT == 16 ? 16u * h : 0u;
+      oa[i] = (row && xa < nx ? (uint32_t)(gy * nx + xa) : kFarVox) * VB + hb;
+      ob[i] = (row && xa + 1 < nx ? (uint32_t)(gy * nx + xa + 1) : kFarVox) * VB + hb;
+      ld[i] = q < ITEMS ? ((r * COUT + 8 * h) * WG_RX) / 2 + pr : -1;
     }
   }
-  __device__ __forceinline__ void store(uint32_t *lds, int slot) const {
+  __device__ __forceinline__ void fetch(Data &d, const uint16_t *__restrict__ dz, int64_t pv,
+                                        int nz, int gz) const {
+    const Rsrc r = plane_buf(dz, pv, COUT, nz, gz);
 #pragma unroll
     for (int i = 0; i < PER; ++i) {
-      const int q = threadIdx.x + i * WG_THR;
-      if (q >= ITEMS) continue;
-      const int pr = q % 32, h = (q / 32) % HALVES, r = q / (32 * HALVES);
-      uint32_t *d = lds + (slot * SLOT + (r * COUT + 8 * h) * WG_RX) / 2 + pr;
+      if (COUT == 16) {
+        d.a[i] = __builtin_amdgcn_raw_buffer_load_b128(r, oa[i], 0, 0);
+        d.b[i] = __builtin_amdgcn_raw_buffer_load_b128(r, ob[i], 0, 0);
+      } else {  // COUT = 1: one element per voxel
+        d.a[i] = u32x4{(uint32_t)__builtin_amdgcn_raw_buffer_load_b16(r, oa[i], 0, 0), 0u, 0u, 0u};
+        d.b[i] = u32x4{(uint32_t)__builtin_amdgcn_raw_buffer_load_b16(r, ob[i], 0, 0), 0u, 0u, 0u};
+      }
+    }
+  }
+  __device__ __forceinline__ void store(uint32_t *lds, int slot, const Data &dd) const {
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+      if (i + 1 == PER && ld[i] < 0) continue;
+      uint32_t *d = lds + slot * (SLOT / 2) + ld[i];
       if (COUT == 16) {
 #pragma unroll
         for (int w = 0; w < 4; ++w) {
-          d[(2 * w) * (WG_RX / 2)] = wg_lo(a[i][w], b[i][w]);
-          d[(2 * w + 1) * (WG_RX / 2)] = wg_hi(a[i][w], b[i][w]);
+          d[(2 * w) * (WG_RX / 2)] = wg_lo(dd.a[i][w], dd.b[i][w]);
+          d[(2 * w + 1) * (WG_RX / 2)] = wg_hi(dd.a[i][w], dd.b[i][w]);
         }
       } else {
-        d[0] = wg_lo(a[i][0], b[i][0]);
+        d[0] = wg_lo(dd.a[i][0], dd.b[i][0]);
       }
     }
   }
@@ -718,6 +735,7 @@ __global__ void __launch_bounds__(WG_THR)
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int j = lane & 15, g = lane >> 4;
   const int tx = (nx + 63) / 64, ty = (ny + WG_TY - 1) / WG_TY;
+  const int64_t pv = (int64_t)nx * ny;
   f32x4 acc[27];
 #pragma unroll
   for (int t = 0; t < 27; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
@@ -727,26 +745,30 @@ __global__ void __launch_bounds__(WG_THR)
   for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
     const int x0 = (tile % tx) * 64, y0 = ((tile / tx) % ty) * WG_TY;
     const int zs = (tile / (tx * ty)) * WG_ZC, ze = min(zs + WG_ZC, nz);
+    In fin;
+    Dz fdz;
+    fin.init(nx, ny, x0, y0);
+    fdz.init(nx, ny, x0, y0);
     {  // prologue: input planes zs - 1 .. zs + 1 and dz plane zs
-      In pin;
+      typename In::Data d;
       for (int p = zs - 1; p <= zs + 1; ++p) {
-        pin.fetch(in, nx, ny, nz, x0, y0, p);
-        pin.store(lin, p & 3);
+        fin.fetch(d, in, pv, nz, p);
+        fin.store(lin, p & 3, d);
       }
-      Dz pdz;
-      pdz.fetch(dz, nx, ny, x0, y0, zs);
-      pdz.store(ldz, zs & 1);
+      typename Dz::Data e;
+      fdz.fetch(e, dz, pv, nz, zs);
+      fdz.store(ldz, zs & 1, e);
     }
     __syncthreads();
     const bool row_live = y0 + wave < ny;
 #pragma unroll 1
     for (int z = zs; z < ze; ++z) {
       const bool more = z + 1 < ze;
-      In nin;
-      Dz ndz;
+      typename In::Data nin;
+      typename Dz::Data ndz;
       if (more) {
-        nin.fetch(in, nx, ny, nz, x0, y0, z + 2);
-        ndz.fetch(dz, nx, ny, x0, y0, z + 1);
+        fin.fetch(nin, in, pv, nz, z + 2);
+        fdz.fetch(ndz, dz, pv, nz, z + 1);
       }
       if (row_live) {
 #pragma unroll
@@ -790,8 +812,8 @@ __global__ void __launch_bounds__(WG_THR)
         }
       }
       if (more) {
-        nin.store(lin, (z + 2) & 3);
-        ndz.store(ldz, (z + 1) & 1);
+        fin.store(lin, (z + 2) & 3, nin);
+        fdz.store(ldz, (z + 1) & 1, ndz);
       }
       __syncthreads();
     }
@@ -853,6 +875,7 @@ __global__ void __launch_bounds__(WG_THR)
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int j = lane & 15, g = lane >> 4;
   const int tx = (nx + 63) / 64, ty = (ny + WG_TY - 1) / WG_TY;
+  const int64_t pv = (int64_t)nx * ny;
   // the lane's tap and channel in each shifted fragment
   int tk[NQ], ch[NQ];
 #pragma unroll
@@ -869,26 +892,30 @@ __global__ void __launch_bounds__(WG_THR)
   for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
     const int x0 = (tile % tx) * 64, y0 = ((tile / tx) % ty) * WG_TY;
     const int zs = (tile / (tx * ty)) * WG_ZC, ze = min(zs + WG_ZC, nz);
+    Ring fr;
+    Flat ff;
+    fr.init(nx, ny, x0, y0);
+    ff.init(nx, ny, x0, y0);
     {  // prologue: ring planes zs - 1 .. zs + 1 and flat plane zs
-      Ring pr;
+      typename Ring::Data d;
       for (int p = zs - 1; p <= zs + 1; ++p) {
-        pr.fetch(ring_src, nx, ny, nz, x0, y0, p);
-        pr.store(lring, p & 3);
+        fr.fetch(d, ring_src, pv, nz, p);
+        fr.store(lring, p & 3, d);
       }
-      Flat pf;
-      pf.fetch(flat_src, nx, ny, x0, y0, zs);
-      pf.store(lflat, zs & 1);
+      typename Flat::Data e;
+      ff.fetch(e, flat_src, pv, nz, zs);
+      ff.store(lflat, zs & 1, e);
     }
     __syncthreads();
     const bool row_live = y0 + wave < ny;
 #pragma unroll 1
     for (int z = zs; z < ze; ++z) {
       const bool more = z + 1 < ze;
-      Ring nr;
-      Flat nf;
+      typename Ring::Data nr;
+      typename Flat::Data nf;
       if (more) {
-        nr.fetch(ring_src, nx, ny, nz, x0, y0, z + 2);
-        nf.fetch(flat_src, nx, ny, x0, y0, z + 1);
+        fr.fetch(nr, ring_src, pv, nz, z + 2);
+        ff.fetch(nf, flat_src, pv, nz, z + 1);
       }
       if (row_live) {
 #pragma unroll
@@ -922,8 +949,8 @@ __global__ void __launch_bounds__(WG_THR)
         }
       }
       if (more) {
-        nr.store(lring, (z + 2) & 3);
-        nf.store(lflat, (z + 1) & 1);
+        fr.store(lring, (z + 2) & 3, nr);
+        ff.store(lflat, (z + 1) & 1, nf);
       }
       __syncthreads();
     }

@@ -181,6 +181,8 @@ def test_cnn_packed_sizes_and_workspace():
                           None) == -1
     assert L.wfd_cnn_conv(256, 8, 8, 8, 16, 1, 256, None, 0, None, 256, 17, 256, None,
                           None) == -1                                     # residual channels
+    assert L.wfd_cnn_wgrad(256, 256, 4097, 4096, 1, 16, 16, 256, 256, 256, big,
+                           None) == -1                                    # plane > 2^24
 
 
 def test_smoothing_and_resampling_host_paths():
