@@ -132,10 +132,10 @@ inline int cm_tiles(int nx, int ny, int nz) {
 // Byte offset within an input plane of the halo voxel v of the tile at
 // (x0, y0) (v = 66 ly + lx), times `bytes` per voxel; far outside the volume.
 __device__ __forceinline__ uint32_t halo_offset(int v, int nx, int ny, int x0, int y0,
-                                                uint32_t bytes) {
+                                                uint32_t bytes, int nvox = CM_PLANE) {
   const int lx = v % CM_LX, ly = v / CM_LX;
   const int gx = x0 - 1 + lx, gy = y0 - 1 + ly;
-  const bool ok = v < CM_PLANE && gx >= 0 && gx < nx && gy >= 0 && gy < ny;
+  const bool ok = v < nvox && gx >= 0 && gx < nx && gy >= 0 && gy < ny;
   return (ok ? (uint32_t)(gy * nx + gx) : kFarVox) * bytes;
 }
 
@@ -240,19 +240,29 @@ __device__ __forceinline__ void lane_bias(float *bco, const float *__restrict__ 
   for (int e = 0; e < 4; ++e) bco[e] = bias ? bias[COUT == 16 ? 4 * g + e : 0] : 0.0f;
 }
 
-// CIN = 1 or 2: a ring slot holds one halo plane, CM_PLANE voxels of CIN
-// BF16 channels; the zeroed pad after the four slots serves taps past 26
-// (offsets up to 3 tiles of 16 voxels on).
+// CIN = 1 or 2 (k_conv): a block owns a 64 x 8 output tile, each wavefront
+// two consecutive rows, so that every plane load and barrier is shared by
+// twice the matrix-core work (these marches wait on load latency, not on
+// bandwidth).  A ring slot holds one halo plane, 66 x 10 voxels of CIN BF16
+// channels; the zeroed pad after the four slots serves taps past 26 (offsets
+// up to one row and 3 tiles of 16 voxels on).
+constexpr int KC_RW = 2, KC_TY = 4 * KC_RW, KC_LY = KC_TY + 2, KC_PLANE = CM_LX * KC_LY;
+constexpr int KC_PFS = (KC_PLANE + CM_THR - 1) / CM_THR;
 template <int CIN>
 struct SmallRing {
-  static constexpr uint32_t SLOT = CM_PLANE * CIN * 2;
+  static constexpr uint32_t ROW = CM_LX * CIN * 2;  // bytes of a halo row
+  static constexpr uint32_t SLOT = KC_PLANE * CIN * 2;
   static constexpr uint32_t PAD = CM_SLOTS * SLOT;
-  static constexpr uint32_t PAD_BYTES = 3 * 16 * CIN * 2 + 16;
+  static constexpr uint32_t PAD_BYTES = ROW + 3 * 16 * CIN * 2 + 16;
   static constexpr uint32_t BYTES = PAD + PAD_BYTES;
 };
 
+inline int kc_tiles(int nx, int ny, int nz) {
+  return ((nx + 63) / 64) * ((ny + KC_TY - 1) / KC_TY) * ((nz + CM_ZC - 1) / CM_ZC);
+}
+
 template <int CIN, int COUT>
-__global__ void __launch_bounds__(CM_THR, 4)  // 4 waves per SIMD
+__global__ void __launch_bounds__(CM_THR, 3)
     k_conv(const uint16_t *__restrict__ in, int nx, int ny, int nz,
            const uint16_t *__restrict__ apk, const float *__restrict__ bias, int relu,
            const uint16_t *__restrict__ mask, const uint16_t *__restrict__ res, int res_c,
@@ -262,9 +272,9 @@ __global__ void __launch_bounds__(CM_THR, 4)  // 4 waves per SIMD
   constexpr int K = kpad(CIN), NC = K / 32;
   constexpr int NE = CIN == 2 ? 4 : 8;  // LDS reads per fragment: one per tap
   __shared__ __attribute__((aligned(16))) char lds[(RG::BYTES + 15) / 16 * 16];
-  const int tx = (nx + 63) / 64, ty = (ny + CM_TY - 1) / CM_TY;
+  const int tx = (nx + 63) / 64, ty = (ny + KC_TY - 1) / KC_TY;
   const int tile = xcd_tile(blockIdx.x, gridDim.x);
-  const int x0 = (tile % tx) * 64, y0 = ((tile / tx) % ty) * CM_TY;
+  const int x0 = (tile % tx) * 64, y0 = ((tile / tx) % ty) * KC_TY;
   const int zs = (tile / (tx * ty)) * CM_ZC, ze = min(zs + CM_ZC, nz);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int j = lane & 15, g = lane >> 4;
@@ -281,23 +291,23 @@ __global__ void __launch_bounds__(CM_THR, 4)  // 4 waves per SIMD
   lane_bias<COUT>(bco, bias, g);
   for (uint32_t i = threadIdx.x * 4; i < RG::PAD_BYTES; i += CM_THR * 4)
     *reinterpret_cast<uint32_t *>(lds + RG::PAD + i) = 0u;
-  uint32_t fo[CM_PFS];
+  uint32_t fo[KC_PFS];
 #pragma unroll
-  for (int i = 0; i < CM_PFS; ++i)
-    fo[i] = halo_offset(threadIdx.x + i * CM_THR, nx, ny, x0, y0, CIN * 2);
+  for (int i = 0; i < KC_PFS; ++i)
+    fo[i] = halo_offset(threadIdx.x + i * CM_THR, nx, ny, x0, y0, CIN * 2, KC_PLANE);
   auto fetch = [&](uint32_t *pf, int gz) {
     const Rsrc r = plane_buf(in, pv, CIN, nz, gz);
 #pragma unroll
-    for (int i = 0; i < CM_PFS; ++i)
+    for (int i = 0; i < KC_PFS; ++i)
       pf[i] = CIN == 2 ? __builtin_amdgcn_raw_buffer_load_b32(r, fo[i], 0, 0)
                        : (uint32_t)__builtin_amdgcn_raw_buffer_load_b16(r, fo[i], 0, 0);
   };
   auto store = [&](int gz, const uint32_t *pf) {
     char *s = lds + (gz & 3) * RG::SLOT;
 #pragma unroll
-    for (int i = 0; i < CM_PFS; ++i) {
+    for (int i = 0; i < KC_PFS; ++i) {
       const int v = threadIdx.x + i * CM_THR;
-      if (i + 1 < CM_PFS || v < CM_PLANE) {
+      if (i + 1 < KC_PFS || v < KC_PLANE) {
         if (CIN == 2)
           *reinterpret_cast<uint32_t *>(s + v * 4) = pf[i];
         else
@@ -306,21 +316,21 @@ __global__ void __launch_bounds__(CM_THR, 4)  // 4 waves per SIMD
     }
   };
   for (int p = zs - 1; p <= zs + 1; ++p) {  // prologue: planes zs - 1 .. zs + 1
-    uint32_t pf[CM_PFS];
+    uint32_t pf[KC_PFS];
     fetch(pf, p);
     store(p, pf);
   }
-  // planes and epilogue inputs are loaded an iteration before their use, into
-  // register sets A and B that alternate (the loop is unrolled twice, so that
-  // no register copy waits on a load in flight)
-  uint32_t pfA[CM_PFS], pfB[CM_PFS];
-  EpiIn eA, eB;
+  // planes are loaded an iteration before their use, into register sets A and
+  // B that alternate (the loop is unrolled twice, so that no register copy
+  // waits on a load in flight)
+  uint32_t pfA[KC_PFS], pfB[KC_PFS];
   fetch(pfA, zs + 2);
-  const int ly = wave, gy = y0 + ly;  // this wave's output row
-  // The LDS read of tap element (c, e) of this lane: plane z - 1 + dz[c][e]
-  // at byte offset to[c][e] (tile 0; tile tl is 16 tl voxels on), or the pad
-  // (dz = 3) past the last tap.  CIN = 2: element e is the channel pair of tap
-  // 16 c + 4 g + e; CIN = 1: the channel of tap 32 c + 8 g + e.
+  const int ly = KC_RW * wave;  // this wave's first output row in the tile
+  // The LDS read of tap element (c, e) of this lane for the first row: plane
+  // z - 1 + dz[c][e] at byte offset to[c][e] (tile 0; tile tl is 16 tl voxels
+  // on, the second row one halo row on), or the pad (dz = 3) past the last
+  // tap.  CIN = 2: element e is the channel pair of tap 16 c + 4 g + e;
+  // CIN = 1: the channel of tap 32 c + 8 g + e.
   int dz[NC][NE];
   uint32_t to[NC][NE];
 #pragma unroll
@@ -332,20 +342,22 @@ __global__ void __launch_bounds__(CM_THR, 4)  // 4 waves per SIMD
       dz[c][e] = t < 27 ? kz : 3;
       to[c][e] = t < 27 ? (uint32_t)(((ly + ky) * CM_LX + j + kx) * CIN * 2) : 0u;
     }
-  uint32_t vo[4];
-  out_voxels<COUT>(vo, nx, ny, x0, gy, j, g);
-  epi_load<COUT>(eA, zs, pv, vo, g, mask, res, res_c);
+  uint32_t vo[KC_RW][4];
+#pragma unroll
+  for (int r = 0; r < KC_RW; ++r) out_voxels<COUT>(vo[r], nx, ny, x0, y0 + ly + r, j, g);
   __syncthreads();
-  // output plane z from planes z - 1 .. z + 1; cur holds plane z + 2 and ec
-  // the epilogue inputs of z, nxt and en receive plane z + 3 and those of z + 1
-  auto step = [&](int z, uint32_t *cur, uint32_t *nxt, const EpiIn &ec, EpiIn &en) {
+  // output plane z from planes z - 1 .. z + 1; cur holds plane z + 2, nxt
+  // receives plane z + 3
+  auto step = [&](int z, uint32_t *cur, uint32_t *nxt) {
     const bool more = z + 1 < ze;  // plane z + 2 is needed for output plane z + 1
     if (z + 2 < ze) fetch(nxt, z + 3);
-    if (more) epi_load<COUT>(en, z + 1, pv, vo, g, mask, res, res_c);
+    EpiIn ei[KC_RW];
+#pragma unroll
+    for (int r = 0; r < KC_RW; ++r) epi_load<COUT>(ei[r], z, pv, vo[r], g, mask, res, res_c);
     const uint32_t sb0 = ((z - 1) & 3) * RG::SLOT, sb1 = (z & 3) * RG::SLOT,
                    sb2 = ((z + 1) & 3) * RG::SLOT;
-    f32x4 acc[4];
-    // chunk-major: the four tiles' fragments of one chunk are in flight together
+    f32x4 acc[KC_RW][4];
+    // chunk-major: the tiles' fragments of one chunk are in flight together
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
       uint32_t ad[NE];
@@ -354,36 +366,41 @@ __global__ void __launch_bounds__(CM_THR, 4)  // 4 waves per SIMD
         const int d = dz[c][e];
         ad[e] = to[c][e] + (d == 0 ? sb0 : d == 1 ? sb1 : d == 2 ? sb2 : RG::PAD);
       }
-      bf16x8 b[4];
 #pragma unroll
-      for (int tl = 0; tl < 4; ++tl) {
-        if (CIN == 2) {
-          u32x4 d;
+      for (int r = 0; r < KC_RW; ++r) {
+        bf16x8 b[4];
 #pragma unroll
-          for (int e = 0; e < 4; ++e)
-            d[e] = *reinterpret_cast<const uint32_t *>(lds + ad[e] + 64 * tl);
-          b[tl] = __builtin_bit_cast(bf16x8, d);
-        } else {
-          u16x8 d;
+        for (int tl = 0; tl < 4; ++tl) {
+          if (CIN == 2) {
+            u32x4 d;
 #pragma unroll
-          for (int e = 0; e < 8; ++e)
-            d[e] = *reinterpret_cast<const uint16_t *>(lds + ad[e] + 32 * tl);
-          b[tl] = __builtin_bit_cast(bf16x8, d);
+            for (int e = 0; e < 4; ++e)
+              d[e] = *reinterpret_cast<const uint32_t *>(lds + ad[e] + r * RG::ROW + 64 * tl);
+            b[tl] = __builtin_bit_cast(bf16x8, d);
+          } else {
+            u16x8 d;
+#pragma unroll
+            for (int e = 0; e < 8; ++e)
+              d[e] = *reinterpret_cast<const uint16_t *>(lds + ad[e] + r * RG::ROW + 32 * tl);
+            b[tl] = __builtin_bit_cast(bf16x8, d);
+          }
         }
-      }
 #pragma unroll
-      for (int tl = 0; tl < 4; ++tl)
-        acc[tl] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
-            a[c], b[tl], c == 0 ? f32x4{0.f, 0.f, 0.f, 0.f} : acc[tl], 0, 0, 0);
+        for (int tl = 0; tl < 4; ++tl)
+          acc[r][tl] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+              a[c], b[tl], c == 0 ? f32x4{0.f, 0.f, 0.f, 0.f} : acc[r][tl], 0, 0, 0);
+      }
     }
-    cm_epilogue<COUT>(acc, z, pv, vo, bco, g, relu, mask, res, ec, out_bf, out_f);
+#pragma unroll
+    for (int r = 0; r < KC_RW; ++r)
+      cm_epilogue<COUT>(acc[r], z, pv, vo[r], bco, g, relu, mask, res, ei[r], out_bf, out_f);
     if (more) store(z + 2, cur);
     __syncthreads();
   };
 #pragma unroll 1
   for (int z = zs; z < ze; z += 2) {
-    step(z, pfA, pfB, eA, eB);
-    if (z + 1 < ze) step(z + 1, pfB, pfA, eB, eA);
+    step(z, pfA, pfB);
+    if (z + 1 < ze) step(z + 1, pfB, pfA);
   }
 }
 
@@ -1135,10 +1152,10 @@ hipError_t launch_conv(int cin, int cout, const uint16_t *in, int nx, int ny, in
                        const uint16_t *apk, const float *bias, int relu, const uint16_t *mask,
                        const uint16_t *res, int res_c, uint16_t *out_bf, float *out_f,
                        hipStream_t stream) {
-  const dim3 grid(cm_tiles(nx, ny, nz)), block(CM_THR);
+  const dim3 grid(cm_tiles(nx, ny, nz)), grid_kc(kc_tiles(nx, ny, nz)), block(CM_THR);
 #define WFD_CONV(CI, CO)                                                                      \
-  hipLaunchKernelGGL((k_conv<CI, CO>), grid, block, 0, stream, in, nx, ny, nz, apk, bias, relu, \
-                     mask, res, res_c, out_bf, out_f)
+  hipLaunchKernelGGL((k_conv<CI, CO>), grid_kc, block, 0, stream, in, nx, ny, nz, apk, bias,   \
+                     relu, mask, res, res_c, out_bf, out_f)
 #define WFD_CONV16(CO)                                                                        \
   hipLaunchKernelGGL((k_conv16<CO>), grid, block, 0, stream, in, nx, ny, nz, apk, bias, relu,  \
                      mask, res, res_c, out_bf, out_f)
