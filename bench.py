@@ -721,7 +721,7 @@ def cnn_kernel_bench(n: int = 256, reps: int = 20):
     print(json.dumps(res), flush=True)
 
 
-def precond_fwi_bench(n_iter: int):
+def precond_fwi_bench(n_iter: int, methods=("sd", "cnn", "cnn_span")):
     """FWI with the learned preconditioner against the plain method: the
     256^3 recipe of the training models (seed 5999, never trained on), 20-cell
     sponge, 1600 steps, 8 shots, 4096 receivers, constant density; start =
@@ -754,7 +754,7 @@ def precond_fwi_bench(n_iter: int):
     vt_d = torch.from_numpy(vt).to(dev)
     err0 = float(torch.linalg.vector_norm((v0 - vt_d).double()))
     runs = {}
-    for method in ("sd", "cnn", "cnn_span"):
+    for method in methods:
         print(f"[bench-precond] {method}", file=sys.stderr, flush=True)
         errs = [1.0]
 
@@ -775,10 +775,10 @@ def precond_fwi_bench(n_iter: int):
             "model_error_rel": float(np.linalg.norm(v.cpu().numpy() - vt) /
                                      np.linalg.norm(w.vel - vt)),
             "_trace": tr}
-    sd, cnn, span = runs["sd"], runs["cnn"], runs["cnn_span"]
+    sd, cnn, span = runs["sd"], runs.get("cnn"), runs["cnn_span"]
     target = sd["misfit"][-1]  # equal final misfit: the plain method's
     t_sd = sd["_trace"].time_to_reach(target / sd["misfit"][0])
-    t_cnn = cnn["_trace"].time_to_reach(target / cnn["misfit"][0])
+    t_cnn = cnn["_trace"].time_to_reach(target / cnn["misfit"][0]) if cnn else None
     t_span = span["_trace"].time_to_reach(target / span["misfit"][0])
 
     def t_err(r, e):  # GPU-seconds until the model error is at most e
@@ -788,7 +788,8 @@ def precond_fwi_bench(n_iter: int):
         return None
 
     e_target = sd["model_error_rel_per_iteration"][-1]
-    te_sd, te_cnn, te_span = t_err(sd, e_target), t_err(cnn, e_target), t_err(span, e_target)
+    te_sd, te_span = t_err(sd, e_target), t_err(span, e_target)
+    te_cnn = t_err(cnn, e_target) if cnn else None
     for r in runs.values():
         r.pop("_trace")
     out = {"metric": "FWI misfit cut per GPU-s: learned preconditioner vs illumination-compensated "
@@ -952,6 +953,8 @@ def main():
                     help="per-window gradients of narrow windows: batched vs per-shot")
     ap.add_argument("--kernels", action="store_true",
                     help="per-kernel table: forward/adjoint CD and VD at 576^3, cache-resident sizes")
+    ap.add_argument("--precond-methods", default="sd,cnn,cnn_span",
+                    help="--precond-fwi: methods to run (sd and cnn_span are required)")
     ap.add_argument("--precond-fwi", type=int, default=0, metavar="ITERS",
                     help="run FWI with the learned preconditioner against the plain method")
     ap.add_argument("--cnn", type=int, default=0, metavar="N",
@@ -985,7 +988,7 @@ def main():
         cnn_kernel_bench(args.cnn)
         return
     if args.precond_fwi:
-        precond_fwi_bench(args.precond_fwi)
+        precond_fwi_bench(args.precond_fwi, tuple(args.precond_methods.split(",")))
         return
     if args.kernels:
         kernel_table_bench()
