@@ -421,29 +421,51 @@ __global__ void __launch_bounds__(CM_THR, 3)
 // go through a two-slot LDS ring (the next plane is fetched into registers
 // during the matrix-core work and stored after it, one barrier per plane);
 // each slot is followed by a zeroed pad that the fragments of k' >= 144 read.
-constexpr uint32_t C16_PLANE = CM_PLANE * 32;           // bytes of a halo plane
-constexpr uint32_t C16_PAD = 3 * 16 * 32 + 16;          // three tiles on, one item
-constexpr uint32_t C16_SLOT = C16_PLANE + C16_PAD;
+//
+// RW output rows per wavefront: a block owns a 64 x 4 RW tile and every
+// plane load, LDS weight-fragment read and barrier serves RW rows of
+// products.
+template <int RW>
+struct C16 {
+  static constexpr int TY = 4 * RW, LY = TY + 2, VOX = CM_LX * LY;  // halo plane
+  static constexpr int ITEMS = VOX * 2;                             // 16-byte halves
+  static constexpr int PF = (ITEMS + CM_THR - 1) / CM_THR;
+  static constexpr uint32_t ROW = CM_LX * 32;                       // bytes of a halo row
+  static constexpr uint32_t PLANE = VOX * 32;
+  // zeroed pad read by the fragments of k' >= 144: up to RW - 1 rows and
+  // three tiles on, one item
+  static constexpr uint32_t PAD = (RW - 1) * ROW + 3 * 16 * 32 + 16;
+  static constexpr uint32_t SLOT = PLANE + PAD;
+};
+constexpr int C16_RW16 = 2;  // rows per wavefront with 16 output channels
+template <int COUT>
+constexpr int c16_rw() { return COUT == 16 ? C16_RW16 : 1; }
+
+inline int c16_tiles(int rw, int nx, int ny, int nz) {
+  return ((nx + 63) / 64) * ((ny + 4 * rw - 1) / (4 * rw)) * ((nz + CM_ZC - 1) / CM_ZC);
+}
 
 template <int COUT>
-__global__ void __launch_bounds__(CM_THR, COUT == 16 ? 3 : 1)
+__global__ void __launch_bounds__(CM_THR, COUT == 16 ? 2 : 1)
     k_conv16(const uint16_t *__restrict__ in, int nx, int ny, int nz,
              const uint16_t *__restrict__ apk, const float *__restrict__ bias, int relu,
              const uint16_t *__restrict__ mask, const uint16_t *__restrict__ res, int res_c,
              uint16_t *__restrict__ out_bf, float *__restrict__ out_f) {
+  constexpr int RW = c16_rw<COUT>();
+  using G = C16<RW>;
   constexpr int K = kpad(16), NC = 5, KP = 144;  // K' = 9 taps x 16 channels
   constexpr int NA = COUT == 16 ? 3 : 1;         // A fragments per chunk
-  __shared__ __attribute__((aligned(16))) char lds[2 * C16_SLOT];
-  const int tx = (nx + 63) / 64, ty = (ny + CM_TY - 1) / CM_TY;
+  __shared__ __attribute__((aligned(16))) char lds[2 * G::SLOT];
+  const int tx = (nx + 63) / 64, ty = (ny + G::TY - 1) / G::TY;
   const int tile = xcd_tile(blockIdx.x, gridDim.x);
-  const int x0 = (tile % tx) * 64, y0 = ((tile / tx) % ty) * CM_TY;
+  const int x0 = (tile % tx) * 64, y0 = ((tile / tx) % ty) * G::TY;
   const int zs = (tile / (tx * ty)) * CM_ZC, ze = min(zs + CM_ZC, nz);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int j = lane & 15, g = lane >> 4;
   const int64_t pv = (int64_t)nx * ny;
   // A fragments: lane (i + 16 g) holds k' = 32 c + 8 g .. + 7 of row i.
   // COUT = 16: fragment (kz, c), row i = co, kept in LDS (read once per chunk,
-  // a conflict-free 16-byte read per lane) to leave registers for the three
+  // a conflict-free 16-byte read per lane) to leave registers for the
   // accumulators.  COUT = 1: a[0][c] in registers, row i = kz (rows 3..15 zero).
   __shared__ __attribute__((aligned(16))) u32x4 alds[COUT == 16 ? NA * NC * 64 : 1];
   bf16x8 a[COUT == 16 ? 1 : NA][NC];
@@ -466,58 +488,63 @@ __global__ void __launch_bounds__(CM_THR, COUT == 16 ? 3 : 1)
   }
   float bco[4];  // before the prologue, whose stores wait for it too
   lane_bias<COUT>(bco, bias, g);
-  for (uint32_t i = threadIdx.x * 16; i < 2 * C16_PAD; i += CM_THR * 16) {
-    const uint32_t s = i / C16_PAD, o = i % C16_PAD;
-    *reinterpret_cast<u32x4 *>(lds + s * C16_SLOT + C16_PLANE + o) = u32x4{0u, 0u, 0u, 0u};
+  for (uint32_t i = threadIdx.x * 16; i < 2 * G::PAD; i += CM_THR * 16) {
+    const uint32_t s = i / G::PAD, o = i % G::PAD;
+    *reinterpret_cast<u32x4 *>(lds + s * G::SLOT + G::PLANE + o) = u32x4{0u, 0u, 0u, 0u};
   }
   // this thread's items (16-byte halves of halo voxels) of a plane
-  uint32_t fo[CM_PF];
+  uint32_t fo[G::PF];
 #pragma unroll
-  for (int i = 0; i < CM_PF; ++i) {
+  for (int i = 0; i < G::PF; ++i) {
     const int q = threadIdx.x + i * CM_THR;
-    fo[i] = halo_offset(q >> 1, nx, ny, x0, y0, 32) + 16u * (q & 1);
+    fo[i] = halo_offset(q >> 1, nx, ny, x0, y0, 32, G::VOX) + 16u * (q & 1);
   }
   auto fetch = [&](u32x4 *pf, int gz) {
     const Rsrc r = plane_buf(in, pv, 16, nz, gz);
 #pragma unroll
-    for (int i = 0; i < CM_PF; ++i) pf[i] = __builtin_amdgcn_raw_buffer_load_b128(r, fo[i], 0, 0);
+    for (int i = 0; i < G::PF; ++i) pf[i] = __builtin_amdgcn_raw_buffer_load_b128(r, fo[i], 0, 0);
   };
   auto store = [&](int gz, const u32x4 *pf) {
-    char *s = lds + (gz & 1) * C16_SLOT;
+    char *s = lds + (gz & 1) * G::SLOT;
 #pragma unroll
-    for (int i = 0; i < CM_PF; ++i) {
+    for (int i = 0; i < G::PF; ++i) {
       const int q = threadIdx.x + i * CM_THR;
-      if (i + 1 < CM_PF || q < CM_PLANE * 2) *reinterpret_cast<u32x4 *>(s + q * 16) = pf[i];
+      if (i + 1 < G::PF || q < G::ITEMS) *reinterpret_cast<u32x4 *>(s + q * 16) = pf[i];
     }
   };
   {  // prologue: input plane zs - 1
-    u32x4 pf[CM_PF];
+    u32x4 pf[G::PF];
     fetch(pf, zs - 1);
     store(zs - 1, pf);
   }
-  const int ly = wave, gy = y0 + ly;  // this wave's output row
-  // B fragment of chunk c: taps t = 2 c + (g >> 1) (ky = t / 3, kx = t % 3),
-  // channels 8 (g & 1) .. + 7, at byte bo[c] of a slot (tile 0; tile tl is
-  // 16 voxels on); t = 9 (the zero half of chunk 4) reads the pad.
+  const int ly = RW * wave;  // this wave's first output row in the tile
+  // B fragment of chunk c for the first row: taps t = 2 c + (g >> 1) (ky =
+  // t / 3, kx = t % 3), channels 8 (g & 1) .. + 7, at byte bo[c] of a slot
+  // (tile 0; tile tl is 16 voxels on, row r one halo row on); t = 9 (the zero
+  // half of chunk 4) reads the pad.
   uint32_t bo[NC];
 #pragma unroll
   for (int c = 0; c < NC; ++c) {
     const int t = 2 * c + (g >> 1);
-    bo[c] = t < 9 ? (uint32_t)(((ly + t / 3) * CM_LX + j + t % 3) * 32 + 16 * (g & 1)) : C16_PLANE;
+    bo[c] = t < 9 ? (uint32_t)(((ly + t / 3) * CM_LX + j + t % 3) * 32 + 16 * (g & 1)) : G::PLANE;
   }
-  uint32_t vo[4];
-  out_voxels<COUT>(vo, nx, ny, x0, gy, j, g);
+  uint32_t vo[RW][4];
+#pragma unroll
+  for (int r = 0; r < RW; ++r) out_voxels<COUT>(vo[r], nx, ny, x0, y0 + ly + r, j, g);
   __syncthreads();
-  // COUT = 16: acc[s] accumulates output plane o with (o - zs + 1) mod 3 = s
-  // COUT = 1: s1 = partial of output p, s2 = partial of output p - 1
-  f32x4 acc[3][4];
-  float s1[4], s2[4];
+  // COUT = 16: acc[r][s] accumulates output plane o of row r with
+  // (o - zs + 1) mod 3 = s.  COUT = 1: s1 = partial of output p, s2 = partial
+  // of output p - 1.
+  f32x4 acc[RW][3][4];
+  float s1[RW][4], s2[RW][4];
 #pragma unroll
-  for (int tl = 0; tl < 4; ++tl) {
-    s1[tl] = s2[tl] = 0.0f;
+  for (int r = 0; r < RW; ++r)
 #pragma unroll
-    for (int q = 0; q < 3; ++q) acc[q][tl] = f32x4{0.f, 0.f, 0.f, 0.f};
-  }
+    for (int tl = 0; tl < 4; ++tl) {
+      s1[r][tl] = s2[r][tl] = 0.0f;
+#pragma unroll
+      for (int q = 0; q < 3; ++q) acc[r][q][tl] = f32x4{0.f, 0.f, 0.f, 0.f};
+    }
 #pragma unroll 1
   for (int p0 = zs - 1; p0 <= ze; p0 += 3) {
     static_for<3>([&](auto Rc) {
@@ -526,56 +553,75 @@ __global__ void __launch_bounds__(CM_THR, COUT == 16 ? 3 : 1)
       const int p = p0 + R;
       if (p > ze) return;
       const bool more = p + 1 <= ze;
-      u32x4 pf[CM_PF];
+      u32x4 pf[G::PF];
       if (more) fetch(pf, p + 1);
-      EpiIn ei;
-      if (p - 1 >= zs) epi_load<COUT>(ei, p - 1, pv, vo, g, mask, res, res_c);
-      const char *pl = lds + (p & 1) * C16_SLOT;
+      EpiIn ei[RW];
+      if (p - 1 >= zs) {
+#pragma unroll
+        for (int r = 0; r < RW; ++r) epi_load<COUT>(ei[r], p - 1, pv, vo[r], g, mask, res, res_c);
+      }
+      const char *pl = lds + (p & 1) * G::SLOT;
       // every input plane feeds three accumulators; those of output planes
       // outside [zs, ze) (at the first two and last two input planes) are
       // never written out, and branch-free products schedule better than
       // skipping them
-      f32x4 d[4];
+      f32x4 d[RW][4];
 #pragma unroll
       for (int c = 0; c < NC; ++c) {
-        bf16x8 b[4];
-#pragma unroll
-        for (int tl = 0; tl < 4; ++tl)
-          b[tl] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u32x4 *>(pl + bo[c] + 512 * tl));
+        bf16x8 a0, a1, a2;
         if (COUT == 16) {
-          const bf16x8 a0 = __builtin_bit_cast(bf16x8, alds[(0 * NC + c) * 64 + lane]);
-          const bf16x8 a1 = __builtin_bit_cast(bf16x8, alds[(1 * NC + c) * 64 + lane]);
-          const bf16x8 a2 = __builtin_bit_cast(bf16x8, alds[(2 * NC + c) * 64 + lane]);
+          a0 = __builtin_bit_cast(bf16x8, alds[(0 * NC + c) * 64 + lane]);
+          a1 = __builtin_bit_cast(bf16x8, alds[(1 * NC + c) * 64 + lane]);
+          a2 = __builtin_bit_cast(bf16x8, alds[(2 * NC + c) * 64 + lane]);
+        }
 #pragma unroll
-          for (int tl = 0; tl < 4; ++tl) {
-            acc[SN][tl] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
-                a0, b[tl], c == 0 ? f32x4{0.f, 0.f, 0.f, 0.f} : acc[SN][tl], 0, 0, 0);
-            acc[SC][tl] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, b[tl], acc[SC][tl], 0, 0, 0);
-            acc[SP][tl] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a2, b[tl], acc[SP][tl], 0, 0, 0);
-          }
-        } else {
+        for (int r = 0; r < RW; ++r) {
+          bf16x8 b[4];
 #pragma unroll
           for (int tl = 0; tl < 4; ++tl)
-            d[tl] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
-                a[0][c], b[tl], c == 0 ? f32x4{0.f, 0.f, 0.f, 0.f} : d[tl], 0, 0, 0);
+            b[tl] = __builtin_bit_cast(
+                bf16x8, *reinterpret_cast<const u32x4 *>(pl + bo[c] + r * G::ROW + 512 * tl));
+          if (COUT == 16) {
+#pragma unroll
+            for (int tl = 0; tl < 4; ++tl) {
+              acc[r][SN][tl] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                  a0, b[tl], c == 0 ? f32x4{0.f, 0.f, 0.f, 0.f} : acc[r][SN][tl], 0, 0, 0);
+              acc[r][SC][tl] =
+                  __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, b[tl], acc[r][SC][tl], 0, 0, 0);
+              acc[r][SP][tl] =
+                  __builtin_amdgcn_mfma_f32_16x16x32_bf16(a2, b[tl], acc[r][SP][tl], 0, 0, 0);
+            }
+          } else {
+#pragma unroll
+            for (int tl = 0; tl < 4; ++tl)
+              d[r][tl] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                  a[0][c], b[tl], c == 0 ? f32x4{0.f, 0.f, 0.f, 0.f} : d[r][tl], 0, 0, 0);
+          }
         }
       }
       if (p - 1 >= zs) {  // output plane p - 1 is complete
-        if (COUT == 16) {
-          cm_epilogue<COUT>(acc[SP], p - 1, pv, vo, bco, g, relu, mask, res, ei, out_bf, out_f);
-        } else {  // lanes of group 0 hold (P0, P1, P2) of voxel j in elements 0..2
-          f32x4 o[4];
 #pragma unroll
-          for (int tl = 0; tl < 4; ++tl) o[tl] = f32x4{s2[tl] + d[tl][2], 0.f, 0.f, 0.f};
-          cm_epilogue<COUT>(o, p - 1, pv, vo, bco, g, relu, mask, res, ei, out_bf, out_f);
+        for (int r = 0; r < RW; ++r) {
+          if (COUT == 16) {
+            cm_epilogue<COUT>(acc[r][SP], p - 1, pv, vo[r], bco, g, relu, mask, res, ei[r],
+                              out_bf, out_f);
+          } else {  // lanes of group 0 hold (P0, P1, P2) of voxel j in elements 0..2
+            f32x4 o[4];
+#pragma unroll
+            for (int tl = 0; tl < 4; ++tl) o[tl] = f32x4{s2[r][tl] + d[r][tl][2], 0.f, 0.f, 0.f};
+            cm_epilogue<COUT>(o, p - 1, pv, vo[r], bco, g, relu, mask, res, ei[r], out_bf,
+                              out_f);
+          }
         }
       }
       if (COUT == 1) {
 #pragma unroll
-        for (int tl = 0; tl < 4; ++tl) {
-          s2[tl] = s1[tl] + d[tl][1];
-          s1[tl] = d[tl][0];
-        }
+        for (int r = 0; r < RW; ++r)
+#pragma unroll
+          for (int tl = 0; tl < 4; ++tl) {
+            s2[r][tl] = s1[r][tl] + d[r][tl][1];
+            s1[r][tl] = d[r][tl][0];
+          }
       }
       if (more) store(p + 1, pf);
       __syncthreads();
@@ -1156,9 +1202,9 @@ hipError_t launch_conv(int cin, int cout, const uint16_t *in, int nx, int ny, in
 #define WFD_CONV(CI, CO)                                                                      \
   hipLaunchKernelGGL((k_conv<CI, CO>), grid_kc, block, 0, stream, in, nx, ny, nz, apk, bias,   \
                      relu, mask, res, res_c, out_bf, out_f)
-#define WFD_CONV16(CO)                                                                        \
-  hipLaunchKernelGGL((k_conv16<CO>), grid, block, 0, stream, in, nx, ny, nz, apk, bias, relu,  \
-                     mask, res, res_c, out_bf, out_f)
+#define WFD_CONV16(CO)                                                                         \
+  hipLaunchKernelGGL((k_conv16<CO>), dim3(c16_tiles(c16_rw<CO>(), nx, ny, nz)), block, 0,      \
+                     stream, in, nx, ny, nz, apk, bias, relu, mask, res, res_c, out_bf, out_f)
   if (cin == 16 && cout == 16) WFD_CONV16(16);
   else if (cin == 2 && cout == 16) WFD_CONV(2, 16);
   else if (cin == 1 && cout == 16) WFD_CONV(1, 16);
