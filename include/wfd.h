@@ -28,7 +28,9 @@
  *   - the border is added outside the model on all six faces (with a free
  *     surface the top one holds zeros and absorbs nothing); the padded grid
  *     is Nd = nd + 2 border, with the model's edge values replicated into
- *     the border.
+ *     the border; each Nd is at most 2^24 and a pitched x-y plane (Nx
+ *     rounded up to a multiple of 64, times Ny) holds fewer than 2^30 points
+ *     (WFD_E_ARG otherwise).
  *
  * Ownership and ordering
  *   - the caller owns every device buffer (model buffer, workspace, inputs,

@@ -202,7 +202,9 @@ wfd_status check_grid(const wfd_grid *g) {
     return fail(WFD_E_ARG, "cpml_vmax must be finite and >= 0");
   const int64_t Nx = (int64_t)g->nx + 2 * g->border, Ny = (int64_t)g->ny + 2 * g->border,
                 Nz = (int64_t)g->nz + 2 * g->border;
-  if (Nx > (1 << 24) || Ny > (1 << 24) || Nz > (1 << 24) || Nx * Ny > (int64_t(1) << 30))
+  // the step kernels address a pitched x-y plane with 32-bit byte offsets
+  if (Nx > (1 << 24) || Ny > (1 << 24) || Nz > (1 << 24) ||
+      (Nx + 63) / 64 * 64 * Ny >= (int64_t(1) << 30))
     return fail(WFD_E_ARG, "padded grid too large");
   return WFD_OK;
 }
