@@ -157,26 +157,36 @@ __device__ __forceinline__ void out_voxels(uint32_t *vo, int nx, int ny, int x0,
 // the lane's channels 4 g .. 4 g + 3 per tile; COUT = 1: the mask (m[tl].x)
 // and the residual.  Loaded early (epi_load) so that the march does not wait
 // on them at the epilogue.
+//
+// BF (branch-free; the 16 -> 16 convolution): loads and stores go through
+// resources that are empty for an absent option or an unwanted plane (ok
+// false) instead of being skipped by a branch.  The compiler can then count
+// the accesses in flight exactly instead of waiting for all of them; that
+// took the 16 -> 16 convolution at 256^3 from 330 to 294 us, but made the
+// one- and two-channel marches and the 16 -> 1 layer slower (148 -> 175 and
+// 176 -> 222 us), which keep the branches.
 struct EpiIn {
   u32x2 m[4];
   float r[4];
 };
 
-template <int COUT>
-__device__ __forceinline__ void epi_load(EpiIn &ei, int z, int64_t pv, const uint32_t *vo, int g,
+template <int COUT, bool BF = false>
+__device__ __forceinline__ void epi_load(EpiIn &ei, int z, bool ok, int64_t pv,
+                                         const uint32_t *vo, int g,
                                          const uint16_t *__restrict__ mask,
                                          const uint16_t *__restrict__ res, int res_c) {
   const int64_t zo = (int64_t)z * pv;
   const uint32_t n = (uint32_t)pv;
-  if (mask) {
-    const Rsrc rm = buf(mask + zo * COUT, n * COUT * 2);
+  const bool has_m = ok && mask, has_r = ok && res;
+  if (BF || has_m) {
+    const Rsrc rm = buf(has_m ? mask + zo * COUT : nullptr, has_m ? n * COUT * 2 : 0u);
 #pragma unroll
     for (int tl = 0; tl < 4; ++tl)
       ei.m[tl] = COUT == 16 ? __builtin_amdgcn_raw_buffer_load_b64(rm, vo[tl] * 32u + 8u * (uint32_t)g, 0, 0)
                             : u32x2{(uint32_t)__builtin_amdgcn_raw_buffer_load_b16(rm, vo[tl] * 2u, 0, 0), 0u};
   }
-  if (COUT == 1 && res) {
-    const Rsrc rr = buf(res + zo * res_c, n * (uint32_t)res_c * 2);
+  if (COUT == 1 && (BF || has_r)) {
+    const Rsrc rr = buf(has_r ? res + zo * res_c : nullptr, has_r ? n * (uint32_t)res_c * 2 : 0u);
 #pragma unroll
     for (int tl = 0; tl < 4; ++tl)
       ei.r[tl] = from_bf16(__builtin_amdgcn_raw_buffer_load_b16(rr, vo[tl] * (uint32_t)res_c * 2u, 0, 0));
@@ -187,16 +197,17 @@ __device__ __forceinline__ void epi_load(EpiIn &ei, int z, int64_t pv, const uin
 // 4 g + e][voxel j] of each tile (single output channel: co = 0 in element 0
 // of group 0).  Bias (bco: the lane's channels), relu, the mask and (single
 // output channel) the residual from ei, then BF16 and/or FP32 stores.
-template <int COUT>
-__device__ __forceinline__ void cm_epilogue(const f32x4 *acc, int z, int64_t pv,
+template <int COUT, bool BF = false>
+__device__ __forceinline__ void cm_epilogue(const f32x4 *acc, int z, bool ok, int64_t pv,
                                             const uint32_t *vo, const float *bco, int g,
                                             int relu, bool mask, bool res, const EpiIn &ei,
                                             uint16_t *__restrict__ out_bf,
                                             float *__restrict__ out_f) {
   const int64_t zo = (int64_t)z * pv;
   const uint32_t n = (uint32_t)pv;
-  const Rsrc rb = buf(out_bf ? out_bf + zo * COUT : nullptr, out_bf ? n * COUT * 2 : 0u);
-  const Rsrc rf = buf(out_f ? out_f + zo * COUT : nullptr, out_f ? n * COUT * 4 : 0u);
+  const bool has_bf = ok && out_bf, has_f = ok && out_f;
+  const Rsrc rb = buf(has_bf ? out_bf + zo * COUT : nullptr, has_bf ? n * COUT * 2 : 0u);
+  const Rsrc rf = buf(has_f ? out_f + zo * COUT : nullptr, has_f ? n * COUT * 4 : 0u);
 #pragma unroll
   for (int tl = 0; tl < 4; ++tl) {
     float v[4];
@@ -215,10 +226,10 @@ __device__ __forceinline__ void cm_epilogue(const f32x4 *acc, int z, int64_t pv,
         v[2] = bf16_pos((uint16_t)m.y) ? v[2] : 0.0f;
         v[3] = bf16_pos((uint16_t)(m.y >> 16)) ? v[3] : 0.0f;
       }
-      if (out_bf)
+      if (BF || has_bf)
         __builtin_amdgcn_raw_buffer_store_b64((u32x2){pack_bf16(v[0], v[1]), pack_bf16(v[2], v[3])},
                                               rb, ob, 0, 0);
-      if (out_f)
+      if (BF || has_f)
         __builtin_amdgcn_raw_buffer_store_b128(
             (u32x4){__float_as_uint(v[0]), __float_as_uint(v[1]), __float_as_uint(v[2]),
                     __float_as_uint(v[3])},
@@ -227,8 +238,9 @@ __device__ __forceinline__ void cm_epilogue(const f32x4 *acc, int z, int64_t pv,
       const uint32_t o = vo[tl];
       if (mask) v[0] = bf16_pos((uint16_t)ei.m[tl].x) ? v[0] : 0.0f;
       if (res) v[0] += ei.r[tl];
-      if (out_bf) __builtin_amdgcn_raw_buffer_store_b16((uint16_t)pack_bf16(v[0], 0.0f), rb, o * 2u, 0, 0);
-      if (out_f) __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v[0]), rf, o * 4u, 0, 0);
+      if (BF || has_bf)
+        __builtin_amdgcn_raw_buffer_store_b16((uint16_t)pack_bf16(v[0], 0.0f), rb, o * 2u, 0, 0);
+      if (BF || has_f) __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v[0]), rf, o * 4u, 0, 0);
     }
   }
 }
@@ -353,7 +365,8 @@ __global__ void __launch_bounds__(CM_THR, 3)
     if (z + 2 < ze) fetch(nxt, z + 3);
     EpiIn ei[KC_RW];
 #pragma unroll
-    for (int r = 0; r < KC_RW; ++r) epi_load<COUT>(ei[r], z, pv, vo[r], g, mask, res, res_c);
+    for (int r = 0; r < KC_RW; ++r)
+      epi_load<COUT>(ei[r], z, true, pv, vo[r], g, mask, res, res_c);
     const uint32_t sb0 = ((z - 1) & 3) * RG::SLOT, sb1 = (z & 3) * RG::SLOT,
                    sb2 = ((z + 1) & 3) * RG::SLOT;
     f32x4 acc[KC_RW][4];
@@ -393,7 +406,8 @@ __global__ void __launch_bounds__(CM_THR, 3)
     }
 #pragma unroll
     for (int r = 0; r < KC_RW; ++r)
-      cm_epilogue<COUT>(acc[r], z, pv, vo[r], bco, g, relu, mask, res, ei[r], out_bf, out_f);
+      cm_epilogue<COUT>(acc[r], z, true, pv, vo[r], bco, g, relu, mask, res, ei[r], out_bf,
+                        out_f);
     if (more) store(z + 2, cur);
     __syncthreads();
   };
@@ -499,8 +513,8 @@ __global__ void __launch_bounds__(CM_THR, COUT == 16 ? 2 : 1)
     const int q = threadIdx.x + i * CM_THR;
     fo[i] = halo_offset(q >> 1, nx, ny, x0, y0, 32, G::VOX) + 16u * (q & 1);
   }
-  auto fetch = [&](u32x4 *pf, int gz) {
-    const Rsrc r = plane_buf(in, pv, 16, nz, gz);
+  auto fetch = [&](u32x4 *pf, int gz, bool ok) {  // ok false: zeros, no traffic
+    const Rsrc r = plane_buf(in, pv, 16, ok ? nz : 0, gz);
 #pragma unroll
     for (int i = 0; i < G::PF; ++i) pf[i] = __builtin_amdgcn_raw_buffer_load_b128(r, fo[i], 0, 0);
   };
@@ -514,7 +528,7 @@ __global__ void __launch_bounds__(CM_THR, COUT == 16 ? 2 : 1)
   };
   {  // prologue: input plane zs - 1
     u32x4 pf[G::PF];
-    fetch(pf, zs - 1);
+    fetch(pf, zs - 1, true);
     store(zs - 1, pf);
   }
   const int ly = RW * wave;  // this wave's first output row in the tile
@@ -545,87 +559,111 @@ __global__ void __launch_bounds__(CM_THR, COUT == 16 ? 2 : 1)
 #pragma unroll
       for (int q = 0; q < 3; ++q) acc[r][q][tl] = f32x4{0.f, 0.f, 0.f, 0.f};
     }
-#pragma unroll 1
-  for (int p0 = zs - 1; p0 <= ze; p0 += 3) {
-    static_for<3>([&](auto Rc) {
-      constexpr int R = decltype(Rc)::value;  // (p - zs + 1) mod 3
-      constexpr int SN = (R + 1) % 3, SC = R, SP = (R + 2) % 3;  // outputs p + 1, p, p - 1
-      const int p = p0 + R;
-      if (p > ze) return;
-      const bool more = p + 1 <= ze;
-      u32x4 pf[G::PF];
-      if (more) fetch(pf, p + 1);
-      EpiIn ei[RW];
-      if (p - 1 >= zs) {
+  // Input plane p (p = zs - 1 .. ze); R = (p - zs + 1) mod 3 fixes the
+  // accumulators' roles.  BF (16 output channels, see EpiIn): no memory
+  // access is skipped by a branch, the epilogue's loads go first, and the
+  // loop below runs whole groups of three planes.
+  constexpr bool BF = COUT == 16;
+  auto sub = [&](auto Rc, int p) {
+    constexpr int R = decltype(Rc)::value;
+    constexpr int SN = (R + 1) % 3, SC = R, SP = (R + 2) % 3;  // outputs p + 1, p, p - 1
+    const bool more = p + 1 <= ze;
+    const bool done = p - 1 >= zs;  // output plane p - 1 is complete after this plane
+    u32x4 pf[G::PF];
+    if (!BF && more) fetch(pf, p + 1, true);
+    EpiIn ei[RW];
+    if (BF || done) {
 #pragma unroll
-        for (int r = 0; r < RW; ++r) epi_load<COUT>(ei[r], p - 1, pv, vo[r], g, mask, res, res_c);
+      for (int r = 0; r < RW; ++r)
+        epi_load<COUT, BF>(ei[r], p - 1, done, pv, vo[r], g, mask, res, res_c);
+    }
+    if (BF) fetch(pf, p + 1, more);
+    const char *pl = lds + (p & 1) * G::SLOT;
+    // every input plane feeds three accumulators; those of output planes
+    // outside [zs, ze) (at the first two and last two input planes) are
+    // never written out, and branch-free products schedule better than
+    // skipping them
+    f32x4 d[RW][4];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      bf16x8 a0, a1, a2;
+      if (COUT == 16) {
+        a0 = __builtin_bit_cast(bf16x8, alds[(0 * NC + c) * 64 + lane]);
+        a1 = __builtin_bit_cast(bf16x8, alds[(1 * NC + c) * 64 + lane]);
+        a2 = __builtin_bit_cast(bf16x8, alds[(2 * NC + c) * 64 + lane]);
       }
-      const char *pl = lds + (p & 1) * G::SLOT;
-      // every input plane feeds three accumulators; those of output planes
-      // outside [zs, ze) (at the first two and last two input planes) are
-      // never written out, and branch-free products schedule better than
-      // skipping them
-      f32x4 d[RW][4];
 #pragma unroll
-      for (int c = 0; c < NC; ++c) {
-        bf16x8 a0, a1, a2;
+      for (int r = 0; r < RW; ++r) {
+        bf16x8 b[4];
+#pragma unroll
+        for (int tl = 0; tl < 4; ++tl)
+          b[tl] = __builtin_bit_cast(
+              bf16x8, *reinterpret_cast<const u32x4 *>(pl + bo[c] + r * G::ROW + 512 * tl));
         if (COUT == 16) {
-          a0 = __builtin_bit_cast(bf16x8, alds[(0 * NC + c) * 64 + lane]);
-          a1 = __builtin_bit_cast(bf16x8, alds[(1 * NC + c) * 64 + lane]);
-          a2 = __builtin_bit_cast(bf16x8, alds[(2 * NC + c) * 64 + lane]);
-        }
-#pragma unroll
-        for (int r = 0; r < RW; ++r) {
-          bf16x8 b[4];
-#pragma unroll
-          for (int tl = 0; tl < 4; ++tl)
-            b[tl] = __builtin_bit_cast(
-                bf16x8, *reinterpret_cast<const u32x4 *>(pl + bo[c] + r * G::ROW + 512 * tl));
-          if (COUT == 16) {
-#pragma unroll
-            for (int tl = 0; tl < 4; ++tl) {
-              acc[r][SN][tl] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
-                  a0, b[tl], c == 0 ? f32x4{0.f, 0.f, 0.f, 0.f} : acc[r][SN][tl], 0, 0, 0);
-              acc[r][SC][tl] =
-                  __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, b[tl], acc[r][SC][tl], 0, 0, 0);
-              acc[r][SP][tl] =
-                  __builtin_amdgcn_mfma_f32_16x16x32_bf16(a2, b[tl], acc[r][SP][tl], 0, 0, 0);
-            }
-          } else {
-#pragma unroll
-            for (int tl = 0; tl < 4; ++tl)
-              d[r][tl] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
-                  a[0][c], b[tl], c == 0 ? f32x4{0.f, 0.f, 0.f, 0.f} : d[r][tl], 0, 0, 0);
-          }
-        }
-      }
-      if (p - 1 >= zs) {  // output plane p - 1 is complete
-#pragma unroll
-        for (int r = 0; r < RW; ++r) {
-          if (COUT == 16) {
-            cm_epilogue<COUT>(acc[r][SP], p - 1, pv, vo[r], bco, g, relu, mask, res, ei[r],
-                              out_bf, out_f);
-          } else {  // lanes of group 0 hold (P0, P1, P2) of voxel j in elements 0..2
-            f32x4 o[4];
-#pragma unroll
-            for (int tl = 0; tl < 4; ++tl) o[tl] = f32x4{s2[r][tl] + d[r][tl][2], 0.f, 0.f, 0.f};
-            cm_epilogue<COUT>(o, p - 1, pv, vo[r], bco, g, relu, mask, res, ei[r], out_bf,
-                              out_f);
-          }
-        }
-      }
-      if (COUT == 1) {
-#pragma unroll
-        for (int r = 0; r < RW; ++r)
 #pragma unroll
           for (int tl = 0; tl < 4; ++tl) {
-            s2[r][tl] = s1[r][tl] + d[r][tl][1];
-            s1[r][tl] = d[r][tl][0];
+            acc[r][SN][tl] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                a0, b[tl], c == 0 ? f32x4{0.f, 0.f, 0.f, 0.f} : acc[r][SN][tl], 0, 0, 0);
+            acc[r][SC][tl] =
+                __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, b[tl], acc[r][SC][tl], 0, 0, 0);
+            acc[r][SP][tl] =
+                __builtin_amdgcn_mfma_f32_16x16x32_bf16(a2, b[tl], acc[r][SP][tl], 0, 0, 0);
           }
+        } else {
+#pragma unroll
+          for (int tl = 0; tl < 4; ++tl)
+            d[r][tl] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                a[0][c], b[tl], c == 0 ? f32x4{0.f, 0.f, 0.f, 0.f} : d[r][tl], 0, 0, 0);
+        }
       }
-      if (more) store(p + 1, pf);
-      __syncthreads();
-    });
+    }
+    if (BF || done) {  // output plane p - 1 (BF: its stores are dropped unless done)
+#pragma unroll
+      for (int r = 0; r < RW; ++r) {
+        if (COUT == 16) {
+          cm_epilogue<COUT, BF>(acc[r][SP], p - 1, done, pv, vo[r], bco, g, relu, mask, res,
+                                ei[r], out_bf, out_f);
+        } else {  // lanes of group 0 hold (P0, P1, P2) of voxel j in elements 0..2
+          f32x4 o[4];
+#pragma unroll
+          for (int tl = 0; tl < 4; ++tl) o[tl] = f32x4{s2[r][tl] + d[r][tl][2], 0.f, 0.f, 0.f};
+          cm_epilogue<COUT, BF>(o, p - 1, done, pv, vo[r], bco, g, relu, mask, res, ei[r],
+                                out_bf, out_f);
+        }
+      }
+    }
+    if (COUT == 1) {
+#pragma unroll
+      for (int r = 0; r < RW; ++r)
+#pragma unroll
+        for (int tl = 0; tl < 4; ++tl) {
+          s2[r][tl] = s1[r][tl] + d[r][tl][1];
+          s1[r][tl] = d[r][tl][0];
+        }
+    }
+    if (more) store(p + 1, pf);
+    __syncthreads();
+  };
+  using I0 = std::integral_constant<int, 0>;
+  using I1 = std::integral_constant<int, 1>;
+  using I2 = std::integral_constant<int, 2>;
+  int p0 = zs - 1;
+  if (BF) {  // whole groups in the loop, the last one or two planes after it
+#pragma unroll 1
+    for (; p0 + 2 <= ze; p0 += 3) {
+      sub(I0{}, p0);
+      sub(I1{}, p0 + 1);
+      sub(I2{}, p0 + 2);
+    }
+    if (p0 <= ze) sub(I0{}, p0);
+    if (p0 + 1 <= ze) sub(I1{}, p0 + 1);
+  } else {
+#pragma unroll 1
+    for (; p0 <= ze; p0 += 3) {
+      sub(I0{}, p0);
+      if (p0 + 1 <= ze) sub(I1{}, p0 + 1);
+      if (p0 + 2 <= ze) sub(I2{}, p0 + 2);
+    }
   }
 }
 
