@@ -51,6 +51,15 @@ def test_error_paths_report_status_and_message():
     assert e.value.name == "WFD_E_ARG"
 
 
+def test_pitched_plane_limit():
+    # the step kernels address a pitched x-y plane (x rounded up to 64) with
+    # 32-bit byte offsets: below 2^30 points it is accepted, at or above refused
+    api.model_bytes(api.GridSpec(16384, 65535, 1, 10, 10, 10, border=0), False)
+    with pytest.raises(_lib.WfdError) as e:  # 16385 x 65300 < 2^30, pitched 16448 x 65300 is not
+        api.model_bytes(api.GridSpec(16385, 65300, 1, 10, 10, 10, border=0), False)
+    assert e.value.name == "WFD_E_ARG" and "too large" in str(e.value)
+
+
 def test_model_bytes_scales_with_density_option():
     g = api.GridSpec(30, 20, 10, 10, 10, 10, border=4)
     cd = api.model_bytes(g, False)
