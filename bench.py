@@ -178,6 +178,9 @@ def _probe_lib():
     L.bench_stream_probe.restype = C.c_int
     L.bench_stream_probe.argtypes = [C.c_int, C.c_int, C.c_int, C.c_void_p, C.c_int64, C.c_int,
                                      C.c_void_p]
+    L.bench_march_probe.restype = C.c_int
+    L.bench_march_probe.argtypes = [C.c_int, C.c_int, C.c_void_p, C.c_int, C.c_int, C.c_int,
+                                    C.c_int, C.c_void_p]
     return L
 
 
@@ -215,8 +218,29 @@ def stream_probe(reps: int = 10):
                 if best is None or gbs > best[0]:
                     best = (gbs, nt, blocks)
         rows[f"r{r}w{w}"] = {"GBps": round(best[0], 0), "nontemporal": best[1], "blocks": best[2]}
+    # the step kernels' own pattern: 64-wide column tiles marching z chunks of
+    # 192 planes (3 chunks at 576^3, as the cost model picks for both kernels)
+    march = {}
+    for r, w, tile in ((4, 1, "64x16"), (6, 2, "64x32")):
+        def run_m():
+            rc = L.bench_march_probe(r, w, buf.data_ptr(), 576, 576, 576, 192, st)
+            if rc != 0:
+                raise RuntimeError(f"bench_march_probe failed with HIP error {rc}")
+        for _ in range(2):
+            run_m()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(reps):
+            run_m()
+        e1.record()
+        torch.cuda.synchronize()
+        gbs = (r + w) * 4.0 * n / (e0.elapsed_time(e1) / reps * 1e-3) / 1e9
+        print(f"[stream-probe] tile march R{r}W{w} {tile} tiles, 192-plane chunks: {gbs:.0f} GB/s",
+              file=sys.stderr, flush=True)
+        march[f"r{r}w{w}"] = {"GBps": round(gbs, 0), "tile": tile, "z_chunk": 192}
     print(json.dumps({"metric": "streaming probe bandwidth", "unit": "GB/s", "n_floats_per_array": n,
-                      "best": rows}), flush=True)
+                      "best": rows, "tile_march": march}), flush=True)
 
 
 def fwi_bench(n_iter: int):
