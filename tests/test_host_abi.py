@@ -253,3 +253,23 @@ def test_library_holds_no_measurement_probe():
     not part of the library."""
     from paper_2502_12350_amd import _lib
     assert not hasattr(_lib.lib(), "wfd_stream_probe")
+
+
+def test_bench_one_gpu_only_and_probe_argument_checks():
+    """bench.py refuses more than one GPU before touching one, and the
+    bench-side probe entry points reject bad arguments before any launch."""
+    import os
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode != 0 and "one GPU only" in (r.stdout + r.stderr)
+    sys.path.insert(0, root)
+    import bench
+    L = bench._probe_lib()
+    assert L.bench_march_probe(4, 1, None, 576, 576, 576, 192, None) != 0   # no buffer
+    assert L.bench_march_probe(4, 1, 256, 0, 576, 576, 192, None) != 0      # empty grid
+    assert L.bench_stream_probe(4, 1, 1, None, 1024, 256, None) != 0        # no buffer
+    assert L.bench_stream_probe(4, 1, 1, 256, 1023, 256, None) != 0         # n % 4 != 0
+
