@@ -316,6 +316,37 @@ def fwi_bench(n_iter: int):
     print(json.dumps(out), flush=True)
 
 
+def cpml_forward_bench(steps: int):
+    """The 576^3 variable-density forward with the CPML layer for a few steps
+    (the workload the layer kernels' trace and counters in profiles/ come
+    from): ms per step and the layer kernels' share."""
+    import time
+    import torch
+    import seisgen
+    from paper_2502_12350_amd import GridSpec, Propagator, K_FORWARD, K_OTHER
+    dev = torch.device("cuda", 0)
+    c2 = seisgen.workload("c2")
+    gs = GridSpec(**{**c2.grid_kwargs(), "nt": steps}, cpml=True, fpeak=10.0)
+    R = Propagator(0)
+    R.set_model(gs, torch.from_numpy(c2.vel).to(dev), torch.from_numpy(c2.rho).to(dev))
+    wv = torch.from_numpy(c2.wavelet[:steps]).to(dev)
+    R.forward(wv, c2.sources[0], c2.receivers)  # warm-up
+    torch.cuda.synchronize()
+    R.set_profiling(True)
+    t0 = time.perf_counter()
+    R.forward(wv, c2.sources[0], c2.receivers)
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) * 1e3 / steps
+    nf, msf = R.kernel_stats(K_FORWARD)
+    no, mso = R.kernel_stats(K_OTHER)
+    R.set_profiling(False)
+    print(json.dumps({"metric": "CPML forward step", "unit": "ms", "higher_is_better": False,
+                      "n_gpus": 1, "dtype": "f32", "data": "synthetic", "steps": steps,
+                      "config": {"workload": "576^3 padded VD (c2 model), 32-cell CPML layer"},
+                      "ms_per_step": round(wall, 3), "step_kernel_us": round(1e3 * msf / nf, 1),
+                      "layer_kernels_us_per_step": round(1e3 * mso / steps, 1)}), flush=True)
+
+
 def options_bench():
     """Cost of the paper's boundary and storage options.  (1) One gradient shot
     of the 200x200x160 + 20 workload (1200 steps, 2500 receivers) with the
@@ -971,6 +1002,8 @@ def main():
                     help="run the FWI benchmark with this many iterations per method instead")
     ap.add_argument("--options", action="store_true",
                     help="cost of wavefield storage modes and of the CPML layer")
+    ap.add_argument("--cpml-forward", type=int, default=0, metavar="STEPS",
+                    help="the 576^3 forward with the CPML layer (profiling workload)")
     ap.add_argument("--batch-fwi", type=int, default=0, metavar="ITERS",
                     help="windowed FWI: batched vs per-shot gradients and trial misfits")
     ap.add_argument("--batch-gradient", action="store_true",
@@ -1025,6 +1058,9 @@ def main():
         return
     if args.options:
         options_bench()
+        return
+    if args.cpml_forward:
+        cpml_forward_bench(args.cpml_forward)
         return
 
     import numpy as np
